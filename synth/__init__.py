@@ -1,0 +1,97 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark.
+
+This module holds only input generation: gauge links, Gaussian sources,
+random starting vectors and SU(3) gauge transformations.  It contains none of
+the arithmetic of the method itself (no Dirac operator, no projector, no
+solver), so that the CPU oracle and the HIP path can both draw from it without
+sharing any computation.
+
+Canonical layouts (the contract between generator, oracle and library):
+
+* gauge   ``U[t][z][y][x][mu][a][b]``  complex128, ``mu`` = x, y, z, t
+* odd half-field ``psi[rhs][s][cb][spin][colour]`` complex128 with
+  ``cb = lex >> 1`` and ``lex = x + X*(y + Y*(z + Z*t))`` (X even)
+
+Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "gell_mann",
+    "gauge_field",
+    "su3_field",
+    "gaussian_half_field",
+    "half_field_shape",
+    "rng",
+]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def gell_mann() -> np.ndarray:
+    """The eight Gell-Mann matrices, shape (8, 3, 3)."""
+    l = np.zeros((8, 3, 3), dtype=np.complex128)
+    l[0, 0, 1] = l[0, 1, 0] = 1
+    l[1, 0, 1] = -1j
+    l[1, 1, 0] = 1j
+    l[2, 0, 0] = 1
+    l[2, 1, 1] = -1
+    l[3, 0, 2] = l[3, 2, 0] = 1
+    l[4, 0, 2] = -1j
+    l[4, 2, 0] = 1j
+    l[5, 1, 2] = l[5, 2, 1] = 1
+    l[6, 1, 2] = -1j
+    l[6, 2, 1] = 1j
+    l[7, 0, 0] = l[7, 1, 1] = 1 / np.sqrt(3)
+    l[7, 2, 2] = -2 / np.sqrt(3)
+    return l
+
+
+def _exp_i_eps_h(omega: np.ndarray, eps: float) -> np.ndarray:
+    """exp(i*eps*H) with H = sum_a omega_a lambda_a / 2 (traceless Hermitian),
+    through the eigendecomposition of H so the result is unitary to rounding."""
+    h = np.einsum("...a,aij->...ij", omega, gell_mann()) * 0.5
+    w, v = np.linalg.eigh(h)
+    ph = np.exp(1j * eps * w)
+    return np.einsum("...ij,...j,...kj->...ik", v, ph, v.conj())
+
+
+def gauge_field(dims, eps: float, seed: int) -> np.ndarray:
+    """Seeded SU(3) links U = exp(i eps H), H Gaussian traceless Hermitian.
+
+    ``dims`` = (X, Y, Z, T).  Returns complex128 of shape (T, Z, Y, X, 4, 3, 3).
+    The eight Gaussian coefficients of each link are drawn in canonical order
+    ``standard_normal((T, Z, Y, X, 4, 8))``.
+    """
+    X, Y, Z, T = dims
+    om = rng(seed).standard_normal((T, Z, Y, X, 4, 8))
+    return np.ascontiguousarray(_exp_i_eps_h(om, eps))
+
+
+def su3_field(dims, seed: int, eps: float = 3.0) -> np.ndarray:
+    """One random SU(3) matrix per site, shape (T, Z, Y, X, 3, 3)."""
+    X, Y, Z, T = dims
+    om = rng(seed).standard_normal((T, Z, Y, X, 8))
+    return np.ascontiguousarray(_exp_i_eps_h(om, eps))
+
+
+def half_field_shape(dims, Ls: int, nrhs: int | None = None):
+    X, Y, Z, T = dims
+    vh = X * Y * Z * T // 2
+    s = (Ls, vh, 4, 3)
+    return s if nrhs is None else (nrhs,) + s
+
+
+def gaussian_half_field(dims, Ls: int, seed: int, nrhs: int | None = None) -> np.ndarray:
+    """Complex Gaussian odd half-field(s), real and imaginary parts N(0, 1),
+    drawn in canonical layout order (real part block first, then imaginary)."""
+    shape = half_field_shape(dims, Ls, nrhs)
+    g = rng(seed)
+    re = g.standard_normal(shape)
+    im = g.standard_normal(shape)
+    return re + 1j * im
