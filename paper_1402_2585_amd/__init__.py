@@ -1,0 +1,16 @@
+"""MI355X-native hot path of hierarchically deflated CG (arXiv:1402.2585).
+
+The compute lives in the HIP library libhdcg.so (built in-tree by
+``paper_1402_2585_amd.build``); this package is its ctypes binding plus
+small helpers that allocate device buffers with PyTorch.  Importing the
+package fails loudly if the library has not been built: there is no CPU
+fallback.
+"""
+from ._lib import (  # noqa: F401
+    DWF_BF16, DWF_C64, DWF_C128, DWF_F16, DWF_NOT_CONVERGED, DWF_OK, HdcgError, cg_solve,
+    dwf_cg_update, dwf_convert, dwf_create, dwf_destroy, dwf_dot, dwf_export, dwf_field_bytes,
+    dwf_import, dwf_last_error, dwf_norm2, dwf_xpay, load, mpc_apply, mpc_dag_mpc_apply,
+)
+from .fields import FineOperator  # noqa: F401
+
+load()

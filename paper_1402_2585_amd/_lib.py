@@ -1,0 +1,181 @@
+"""ctypes binding of libhdcg.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: it checks that tensors live on the GPU and are
+contiguous, passes their device addresses and torch's current stream, and
+turns status codes into exceptions.  All compute runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdcg.so")
+
+DWF_OK, DWF_NOT_CONVERGED = 0, 1
+DWF_C128, DWF_C64, DWF_BF16, DWF_F16 = 0, 1, 2, 3
+
+_ERRORS = {
+    -1: "DWF_ERR_ARG", -2: "DWF_ERR_GEOMETRY", -3: "DWF_ERR_HIP",
+    -4: "DWF_ERR_OOM", -5: "DWF_ERR_STATE", -6: "DWF_ERR_NUMERIC",
+}
+
+
+class HdcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("true_residual", C.c_double), ("seconds", C.c_double), ("matmuls", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1402_2585_amd.build.build() first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "dwf_create": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, vp, dp, vp]),
+        "dwf_destroy": (i, [vp]),
+        "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
+        "dwf_import": (i, [vp, vp, vp, i, i, vp]),
+        "dwf_export": (i, [vp, vp, vp, i, i, vp]),
+        "dwf_convert": (i, [vp, vp, i, vp, i, i, vp]),
+        "mpc_apply": (i, [vp, vp, vp, i, i, i, vp]),
+        "mpc_dag_mpc_apply": (i, [vp, vp, vp, i, i, vp]),
+        "dwf_norm2": (i, [vp, dp, vp, i, i, vp]),
+        "dwf_dot": (i, [vp, dp, vp, vp, i, i, vp]),
+        "dwf_cg_update": (i, [vp, vp, vp, vp, vp, dp, dp, i, i, vp]),
+        "dwf_xpay": (i, [vp, vp, vp, dp, i, i, vp]),
+        "cg_solve": (i, [vp, vp, vp, i, d, i, C.POINTER(SolveStats), vp]),
+        "dwf_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------- marshalling --
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(rc, allow_soft=False):
+    if rc < 0 or (rc > 0 and not allow_soft):
+        raise HdcgError(rc, load().dwf_last_error().decode())
+    return rc
+
+
+def _dbl(values, n):
+    arr = (C.c_double * n)(*[float(v) for v in np.broadcast_to(np.asarray(values, float), (n,))])
+    return arr
+
+
+# ------------------------------------------------------------ entry points --
+def dwf_create(gauge, dims, Ls, M5, mass, bc=(1, 1, 1, -1), stream=None):
+    h = C.c_void_p()
+    d = (C.c_int * 4)(*[int(x) for x in dims])
+    ph = _dbl([v for z in bc for v in (complex(z).real, complex(z).imag)], 8)
+    _check(load().dwf_create(C.byref(h), C.byref(d), int(Ls), float(M5), float(mass), _ptr(gauge), ph,
+                             _stream(stream)))
+    return h
+
+
+def dwf_destroy(op):
+    _check(load().dwf_destroy(op))
+
+
+def dwf_field_bytes(op, prec, nrhs=1):
+    n = C.c_size_t()
+    _check(load().dwf_field_bytes(op, int(prec), int(nrhs), C.byref(n)))
+    return n.value
+
+
+def dwf_import(op, native, canonical, prec, nrhs=1, stream=None):
+    _check(load().dwf_import(op, _ptr(native), _ptr(canonical), int(prec), int(nrhs), _stream(stream)))
+
+
+def dwf_export(op, canonical, native, prec, nrhs=1, stream=None):
+    _check(load().dwf_export(op, _ptr(canonical), _ptr(native), int(prec), int(nrhs), _stream(stream)))
+
+
+def dwf_convert(op, dst, dst_prec, src, src_prec, nrhs=1, stream=None):
+    _check(load().dwf_convert(op, _ptr(dst), int(dst_prec), _ptr(src), int(src_prec), int(nrhs),
+                              _stream(stream)))
+
+
+def mpc_apply(op, out, inp, prec, dagger=0, nrhs=1, stream=None):
+    _check(load().mpc_apply(op, _ptr(out), _ptr(inp), int(prec), int(dagger), int(nrhs), _stream(stream)))
+
+
+def mpc_dag_mpc_apply(op, out, inp, prec, nrhs=1, stream=None):
+    _check(load().mpc_dag_mpc_apply(op, _ptr(out), _ptr(inp), int(prec), int(nrhs), _stream(stream)))
+
+
+def dwf_norm2(op, x, prec, nrhs=1, stream=None):
+    out = (C.c_double * nrhs)()
+    _check(load().dwf_norm2(op, out, _ptr(x), int(prec), int(nrhs), _stream(stream)))
+    return np.array(out[:])
+
+
+def dwf_dot(op, a, b, prec, nrhs=1, stream=None):
+    out = (C.c_double * (2 * nrhs))()
+    _check(load().dwf_dot(op, out, _ptr(a), _ptr(b), int(prec), int(nrhs), _stream(stream)))
+    v = np.array(out[:])
+    return v[0::2] + 1j * v[1::2]
+
+
+def dwf_cg_update(op, x, r, p, w, alpha, prec, nrhs=1, stream=None):
+    rr = (C.c_double * nrhs)()
+    _check(load().dwf_cg_update(op, _ptr(x), _ptr(r), _ptr(p), _ptr(w), _dbl(alpha, nrhs), rr,
+                                int(prec), int(nrhs), _stream(stream)))
+    return np.array(rr[:])
+
+
+def dwf_xpay(op, p, r, beta, prec, nrhs=1, stream=None):
+    _check(load().dwf_xpay(op, _ptr(p), _ptr(r), _dbl(beta, nrhs), int(prec), int(nrhs), _stream(stream)))
+
+
+def cg_solve(op, x, b, nrhs=1, tol=1e-8, maxiter=100000, stream=None):
+    st = SolveStats()
+    rc = _check(load().cg_solve(op, _ptr(x), _ptr(b), int(nrhs), float(tol), int(maxiter), C.byref(st),
+                                _stream(stream)), allow_soft=True)
+    return rc, st.as_dict()
+
+
+def dwf_last_error():
+    return load().dwf_last_error().decode()

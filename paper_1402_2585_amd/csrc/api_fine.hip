@@ -1,0 +1,427 @@
+// C ABI: fine operator, BLAS-1 and the plain FP64 CG comparator.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fine_op.h"
+
+namespace hdk {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int import_gauge(dwf_op* op, const void* gauge_c128, hipStream_t stream);
+template <typename R>
+int launch_layout(dwf_op* op, void* dst, const void* src, int nrhs, bool to_native,
+                  hipStream_t stream);
+
+static int check_op(dwf_op* op) {
+  if (!op) return fail(DWF_ERR_ARG, "null operator handle");
+  return DWF_OK;
+}
+static int check_prec(int prec) {
+  if (prec != DWF_C128 && prec != DWF_C64)
+    return fail(DWF_ERR_ARG, "precision must be DWF_C128 or DWF_C64 for fine fields");
+  return DWF_OK;
+}
+static int check_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 64) return fail(DWF_ERR_ARG, "nrhs must be in 1..64");
+  return DWF_OK;
+}
+
+// ------------------------------------------------------------- CG solver ---
+// Plain CG on H x = b in FP64 with device-resident scalars.  The host reads
+// |r|^2 through a pinned ring with a lag of kLag iterations, so the GPU queue
+// never drains while the host checks convergence; the few iterations queued
+// past convergence only reduce the residual further.
+static int cg_one(dwf_op* op, c128* x, const c128* b, double tol, int maxiter, int* iters,
+                  int* restarts, double* true_res, double* matmuls, hipStream_t stream) {
+  constexpr int kLag = 2, kRing = 8;
+  const size_t n = op->field_elems(1);
+  HDCG_TRY(ensure_reducer(op));
+  for (int i = 0; i < 3; ++i) HDCG_TRY(op->cgw[i].ensure(n * sizeof(c128)));
+  c128* r = op->cgw[0].as<c128>();
+  c128* p = op->cgw[1].as<c128>();
+  c128* w = op->cgw[2].as<c128>();
+  // device scalar slots (in the reducer's result buffer, after slot 128)
+  double* sc = op->red.results.as<double>() + 128;
+  double* rr_slot[2] = {sc + 0, sc + 1};
+  double* pap = sc + 2;
+  double* bb = sc + 3;
+  double* hp = op->pinned;  // [kRing + 4]
+  hipEvent_t ev[kRing];
+  for (int i = 0; i < kRing; ++i) HDCG_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  int status = DWF_OK;
+  int it = 0, rs = 0;
+  double mm = 0.0;
+  double bnorm2 = 0.0, tr = 0.0;
+  auto cleanup = [&]() {
+    for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(ev[i]);
+  };
+#define CG_TRY(expr)          \
+  do {                        \
+    int s_ = (expr);          \
+    if (s_ < 0) {             \
+      cleanup();              \
+      return s_;              \
+    }                         \
+  } while (0)
+#define CG_HIP(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      cleanup();                                                                 \
+      return fail(DWF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                            \
+  } while (0)
+
+  CG_TRY(launch_norm2<double>(op, b, 1, bb, stream));
+  CG_HIP(hipMemcpyAsync(hp + kRing, bb, sizeof(double), hipMemcpyDeviceToHost, stream));
+  CG_HIP(hipStreamSynchronize(stream));
+  bnorm2 = hp[kRing];
+  if (!std::isfinite(bnorm2)) {
+    cleanup();
+    return fail(DWF_ERR_NUMERIC, "source norm is not finite");
+  }
+  if (bnorm2 == 0.0) {
+    CG_HIP(hipMemsetAsync(x, 0, n * sizeof(c128), stream));
+    CG_HIP(hipStreamSynchronize(stream));
+    *iters = 0;
+    *restarts = 0;
+    *true_res = 0.0;
+    *matmuls = 0.0;
+    cleanup();
+    return DWF_OK;
+  }
+  const double stop = tol * tol * bnorm2;
+  for (;;) {
+    // r = b - H x (FP64 true residual), p = r
+    CG_TRY(launch_mpcdagmpc<double>(op, w, x, 1, stream, nullptr));
+    mm += 1;
+    CG_HIP(hipMemcpyAsync(r, b, n * sizeof(c128), hipMemcpyDeviceToDevice, stream));
+    CG_TRY(launch_axpby<double>(op, r, w, -1.0, 1.0, n, stream));
+    CG_TRY(launch_norm2<double>(op, r, 1, rr_slot[0], stream));
+    CG_HIP(hipMemcpyAsync(hp + kRing, rr_slot[0], sizeof(double), hipMemcpyDeviceToHost, stream));
+    CG_HIP(hipStreamSynchronize(stream));
+    const double rr0 = hp[kRing];
+    if (!std::isfinite(rr0)) {
+      cleanup();
+      return fail(DWF_ERR_NUMERIC, "residual is not finite");
+    }
+    tr = std::sqrt(rr0 / bnorm2);
+    if (rr0 <= stop || it >= maxiter) break;
+    if (it > 0) ++rs;
+    CG_HIP(hipMemcpyAsync(p, r, n * sizeof(c128), hipMemcpyDeviceToDevice, stream));
+    int k = 0;  // iterations in this cycle
+    int checked = 0;
+    bool done = false;
+    while (!done) {
+      if (it + k < maxiter) {
+        double* cur = rr_slot[k & 1];
+        double* nxt = rr_slot[(k + 1) & 1];
+        // w = H p with pap = <p, H p> = |M_pc p|^2 fused into stage 2
+        CG_TRY(launch_mpcdagmpc<double>(op, w, p, 1, stream, pap));
+        CG_TRY(launch_cg_update<double>(op, x, r, p, w, cur, pap, nullptr, nxt, 1, stream));
+        CG_TRY(launch_xpay<double>(op, p, r, nxt, cur, nullptr, 1, stream));
+        CG_HIP(hipMemcpyAsync(hp + (k % kRing), nxt, sizeof(double), hipMemcpyDeviceToHost, stream));
+        CG_HIP(hipEventRecord(ev[k % kRing], stream));
+        ++k;
+      }
+      // check iteration `checked` once it is kLag behind (or everything queued)
+      const bool drain = (it + k >= maxiter);
+      while (checked < k && (k - checked > kLag || drain)) {
+        CG_HIP(hipEventSynchronize(ev[checked % kRing]));
+        const double rrv = hp[checked % kRing];
+        ++checked;
+        if (!std::isfinite(rrv)) {
+          cleanup();
+          return fail(DWF_ERR_NUMERIC, "CG residual became non-finite");
+        }
+        if (rrv <= stop) {
+          done = true;
+          break;
+        }
+      }
+      if (drain && checked == k) done = true;
+    }
+    // iterations queued past the converged one have run too
+    CG_HIP(hipStreamSynchronize(stream));
+    it += k;
+    mm += k;
+  }
+  *iters = it;
+  *restarts = rs;
+  *true_res = tr;
+  *matmuls = mm;
+  cleanup();
+  return (tr <= tol) ? DWF_OK : DWF_NOT_CONVERGED;
+#undef CG_TRY
+#undef CG_HIP
+}
+
+}  // namespace hdk
+
+using namespace hdk;
+
+extern "C" {
+
+const char* dwf_last_error(void) { return g_last_error.c_str(); }
+
+int dwf_create(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass,
+               const void* gauge_c128, const double bc_phase[8], void* stream) {
+  if (!out || !dims || !gauge_c128) return fail(DWF_ERR_ARG, "null argument to dwf_create");
+  *out = nullptr;
+  for (int mu = 0; mu < 4; ++mu)
+    if (dims[mu] < 2 || (dims[mu] & 1)) return fail(DWF_ERR_GEOMETRY, "lattice extents must be even and >= 2");
+  if (Ls < 1 || Ls > 64) return fail(DWF_ERR_GEOMETRY, "Ls must be in 1..64");
+  const double d = 5.0 - M5;
+  if (!(std::fabs(d) > 1.0)) return fail(DWF_ERR_ARG, "need |5 - M5| > 1 for the M_5^-1 recurrence");
+  dwf_op* op = new (std::nothrow) dwf_op();
+  if (!op) return fail(DWF_ERR_OOM, "host allocation failed");
+  op->g.X = dims[0];
+  op->g.Y = dims[1];
+  op->g.Z = dims[2];
+  op->g.T = dims[3];
+  op->g.Xh = dims[0] / 2;
+  op->g.Ls = Ls;
+  const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V / 2 > (size_t)0x7fffffff / 12) {
+    delete op;
+    return fail(DWF_ERR_GEOMETRY, "lattice too large");
+  }
+  op->g.Vh = (int)(V / 2);
+  op->M5 = M5;
+  op->mass = mass;
+  const double defbc[8] = {1, 0, 1, 0, 1, 0, -1, 0};
+  std::memcpy(op->bc, bc_phase ? bc_phase : defbc, sizeof(op->bc));
+  op->f5.d = d;
+  op->f5.mass = mass;
+  // closed form of M_5^-1: (M+^-1)_{ss'} = pw[(s-s') mod Ls] * (s >= s' ? 1 : -m)
+  const double den = 1.0 + mass * std::pow(d, -Ls);
+  for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(d, -1 - n) / den : 0.0;
+  (void)hipGetDevice(&op->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = DWF_OK;
+  do {
+    rc = op->pw128.ensure(64 * sizeof(double));
+    if (rc) break;
+    rc = op->pw64.ensure(64 * sizeof(float));
+    if (rc) break;
+    float pwf[64];
+    for (int n = 0; n < 64; ++n) pwf[n] = (float)op->f5.pw[n];
+    if (hipMemcpy(op->pw128.ptr, op->f5.pw, 64 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(op->pw64.ptr, pwf, 64 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(DWF_ERR_HIP, "copy of the M_5^-1 table failed");
+      break;
+    }
+    if (hipHostMalloc((void**)&op->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      op->pinned = nullptr;
+      rc = fail(DWF_ERR_HIP, "pinned host allocation failed");
+      break;
+    }
+    rc = ensure_reducer(op);
+    if (rc) break;
+    rc = import_gauge(op, gauge_c128, st);
+    if (rc) break;
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(DWF_ERR_HIP, "gauge import failed");
+      break;
+    }
+  } while (0);
+  if (rc != DWF_OK) {
+    dwf_destroy(op);
+    return rc;
+  }
+  *out = op;
+  return DWF_OK;
+}
+
+int dwf_destroy(dwf_op_t op) {
+  if (!op) return DWF_OK;
+  (void)hipDeviceSynchronize();
+  op->gauge128.release();
+  op->gauge64.release();
+  op->pw128.release();
+  op->pw64.release();
+  for (auto& a : op->tmp)
+    for (auto& b : a) b.release();
+  for (auto& b : op->cgw) b.release();
+  op->red.partials.release();
+  op->red.counters.release();
+  op->red.results.release();
+  if (op->pinned) (void)hipHostFree(op->pinned);
+  delete op;
+  return DWF_OK;
+}
+
+int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  if (!bytes || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_field_bytes");
+  *bytes = op->field_elems(nrhs) * cbytes(prec);
+  return DWF_OK;
+}
+
+int dwf_import(dwf_op_t op, void* native, const void* canonical, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  if (!native || !canonical || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_import");
+  auto st = static_cast<hipStream_t>(stream);
+  return prec == DWF_C128 ? launch_layout<double>(op, native, canonical, nrhs, true, st)
+                          : launch_layout<float>(op, native, canonical, nrhs, true, st);
+}
+
+int dwf_export(dwf_op_t op, void* canonical, const void* native, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  if (!native || !canonical || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_export");
+  auto st = static_cast<hipStream_t>(stream);
+  return prec == DWF_C128 ? launch_layout<double>(op, canonical, native, nrhs, false, st)
+                          : launch_layout<float>(op, canonical, native, nrhs, false, st);
+}
+
+int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_prec, int nrhs,
+                void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(dst_prec));
+  HDCG_TRY(check_prec(src_prec));
+  if (!dst || !src || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_convert");
+  auto st = static_cast<hipStream_t>(stream);
+  const size_t n = op->field_elems(nrhs);
+  if (dst_prec == src_prec) {
+    HDCG_HIP(hipMemcpyAsync(dst, src, n * cbytes(src_prec), hipMemcpyDeviceToDevice, st));
+    return DWF_OK;
+  }
+  if (dst_prec == DWF_C64)
+    return launch_convert<float, double>(static_cast<c64*>(dst), static_cast<const c128*>(src), n, st);
+  return launch_convert<double, float>(static_cast<c128*>(dst), static_cast<const c64*>(src), n, st);
+}
+
+int mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int dagger, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!out || !in || out == in) return fail(DWF_ERR_ARG, "mpc_apply needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128)
+    return launch_mpc<double>(op, static_cast<c128*>(out), static_cast<const c128*>(in), dagger != 0, nrhs, st, nullptr);
+  return launch_mpc<float>(op, static_cast<c64*>(out), static_cast<const c64*>(in), dagger != 0, nrhs, st, nullptr);
+}
+
+int mpc_dag_mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!out || !in || out == in) return fail(DWF_ERR_ARG, "mpc_dag_mpc_apply needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128)
+    return launch_mpcdagmpc<double>(op, static_cast<c128*>(out), static_cast<const c128*>(in), nrhs, st, nullptr);
+  return launch_mpcdagmpc<float>(op, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, st, nullptr);
+}
+
+static int fetch(dwf_op* op, double* host, const double* dev, int n, hipStream_t st) {
+  HDCG_HIP(hipMemcpyAsync(op->pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  std::memcpy(host, op->pinned, n * sizeof(double));
+  return DWF_OK;
+}
+
+int dwf_norm2(dwf_op_t op, double* out_host, const void* x, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!out_host || !x) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  double* res = op->red.results.as<double>();
+  if (prec == DWF_C128)
+    HDCG_TRY(launch_norm2<double>(op, static_cast<const c128*>(x), nrhs, res, st));
+  else
+    HDCG_TRY(launch_norm2<float>(op, static_cast<const c64*>(x), nrhs, res, st));
+  return fetch(op, out_host, res, nrhs, st);
+}
+
+int dwf_dot(dwf_op_t op, double* out_host, const void* a, const void* b, int prec, int nrhs,
+            void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!out_host || !a || !b) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  double* res = op->red.results.as<double>();
+  if (prec == DWF_C128)
+    HDCG_TRY(launch_dot<double>(op, static_cast<const c128*>(a), static_cast<const c128*>(b), nrhs, res, st));
+  else
+    HDCG_TRY(launch_dot<float>(op, static_cast<const c64*>(a), static_cast<const c64*>(b), nrhs, res, st));
+  return fetch(op, out_host, res, 2 * nrhs, st);
+}
+
+int dwf_cg_update(dwf_op_t op, void* x, void* r, const void* p, const void* w,
+                  const double* alpha_host, double* rr_host, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!x || !r || !p || !w || !alpha_host || !rr_host) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  double* res = op->red.results.as<double>();
+  double* dal = res + 192;
+  HDCG_HIP(hipMemcpyAsync(dal, alpha_host, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  if (prec == DWF_C128)
+    HDCG_TRY(launch_cg_update<double>(op, static_cast<c128*>(x), static_cast<c128*>(r),
+                                      static_cast<const c128*>(p), static_cast<const c128*>(w),
+                                      nullptr, nullptr, dal, res, nrhs, st));
+  else
+    HDCG_TRY(launch_cg_update<float>(op, static_cast<c64*>(x), static_cast<c64*>(r),
+                                     static_cast<const c64*>(p), static_cast<const c64*>(w),
+                                     nullptr, nullptr, dal, res, nrhs, st));
+  return fetch(op, rr_host, res, nrhs, st);
+}
+
+int dwf_xpay(dwf_op_t op, void* p, const void* r, const double* beta_host, int prec, int nrhs,
+             void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!p || !r || !beta_host) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  double* dbeta = op->red.results.as<double>() + 192;
+  HDCG_HIP(hipMemcpyAsync(dbeta, beta_host, nrhs * sizeof(double), hipMemcpyHostToDevice, st));
+  if (prec == DWF_C128)
+    return launch_xpay<double>(op, static_cast<c128*>(p), static_cast<const c128*>(r), nullptr, nullptr, dbeta, nrhs, st);
+  return launch_xpay<float>(op, static_cast<c64*>(p), static_cast<const c64*>(r), nullptr, nullptr, dbeta, nrhs, st);
+}
+
+int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxiter,
+             struct dwf_solve_stats* st, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!x || !b || !(tol > 0) || maxiter < 0) return fail(DWF_ERR_ARG, "bad arguments to cg_solve");
+  auto s = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  dwf_solve_stats acc{};
+  acc.converged = 1;
+  int worst = DWF_OK;
+  const size_t n = op->field_elems(1);
+  for (int i = 0; i < nrhs; ++i) {
+    int it = 0, rs = 0;
+    double tr = 0, mm = 0;
+    int rc = cg_one(op, static_cast<c128*>(x) + i * n, static_cast<const c128*>(b) + i * n, tol,
+                    maxiter, &it, &rs, &tr, &mm, s);
+    if (rc < 0) return rc;
+    if (rc == DWF_NOT_CONVERGED) {
+      worst = DWF_NOT_CONVERGED;
+      acc.converged = 0;
+    }
+    acc.iterations += it;
+    acc.restarts += rs;
+    acc.matmuls += mm;
+    if (tr > acc.true_residual) acc.true_residual = tr;
+  }
+  acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = acc;
+  if (worst == DWF_NOT_CONVERGED) set_error("cg_solve: maxiter reached before tol");
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// Internal runtime pieces shared by the library's translation units:
+// complex arithmetic, error reporting, device buffers, reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hdcg.h"
+
+namespace hdk {
+
+// ---------------------------------------------------------------- errors ---
+void set_error(const std::string& msg);
+
+struct Status {
+  int code = DWF_OK;
+  Status() = default;
+  Status(int c) : code(c) {}
+  bool ok() const { return code == DWF_OK; }
+};
+
+#define HDCG_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::hdk::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+      return DWF_ERR_HIP;                                                     \
+    }                                                                         \
+  } while (0)
+
+#define HDCG_TRY(expr)                 \
+  do {                                 \
+    int s_ = (expr);                   \
+    if (s_ < 0) return s_;             \
+  } while (0)
+
+inline int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+// --------------------------------------------------------------- complex ---
+template <typename R>
+struct alignas(2 * sizeof(R)) cplx {
+  R re, im;
+};
+using c128 = cplx<double>;
+using c64 = cplx<float>;
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> cmk(R a, R b) {
+  cplx<R> c;
+  c.re = a;
+  c.im = b;
+  return c;
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) {
+  return cmk(a.re + b.re, a.im + b.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) {
+  return cmk(a.re - b.re, a.im - b.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(cplx<R> a, cplx<R> b) {
+  return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> operator*(R s, cplx<R> a) {
+  return cmk(s * a.re, s * a.im);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> conj(cplx<R> a) {
+  return cmk(a.re, -a.im);
+}
+// i*a and -i*a
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> timesI(cplx<R> a) {
+  return cmk(-a.im, a.re);
+}
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> timesMinusI(cplx<R> a) {
+  return cmk(a.im, -a.re);
+}
+// a += b*c ; a += conj(b)*c
+template <typename R>
+__host__ __device__ __forceinline__ void cmac(cplx<R>& a, cplx<R> b, cplx<R> c) {
+  a.re += b.re * c.re - b.im * c.im;
+  a.im += b.re * c.im + b.im * c.re;
+}
+template <typename R>
+__host__ __device__ __forceinline__ void cjmac(cplx<R>& a, cplx<R> b, cplx<R> c) {
+  a.re += b.re * c.re + b.im * c.im;
+  a.im += b.re * c.im - b.im * c.re;
+}
+
+template <typename R>
+inline int prec_of();
+template <>
+inline int prec_of<double>() {
+  return DWF_C128;
+}
+template <>
+inline int prec_of<float>() {
+  return DWF_C64;
+}
+inline size_t cbytes(int prec) { return prec == DWF_C128 ? 16 : 8; }
+
+// --------------------------------------------------------------- buffers ---
+// Grow-only device buffer owned by a handle.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t want) {
+    if (want <= bytes) return DWF_OK;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return fail(DWF_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+    return DWF_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+};
+
+// ------------------------------------------------------------ reductions ---
+// Deterministic two-stage reductions: every workgroup writes one partial per
+// output, the last workgroup to finish (ticket counter) sums the partials in
+// a fixed order and resets the counter.
+constexpr int kMaxPartials = 1 << 16;  // partial slots per reduced quantity
+constexpr int kRedThreads = 256;
+
+struct Reducer {
+  DevBuf partials;  // double [nq][kMaxPartials]
+  DevBuf counters;  // unsigned [64]
+  DevBuf results;   // double [nq]
+  int ensure(int nq);
+};
+
+// Sum of a double across the workgroup; valid in thread 0.  blockDim.x must
+// be a multiple of 64 and at most 1024.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_sum(double (&v)[NQ], double* lds /* NQ*16 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[q * 16 + wave] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += lds[q * 16 + w];
+      v[q] = s;
+    }
+  }
+}
+
+// Finish a reduction: thread 0 of every workgroup has its partials in v.
+// partials layout [NQ][nslots]; the last workgroup writes result[q].
+// Returns true in the workgroup that finalised (all threads).
+template <int NQ>
+__device__ __forceinline__ bool finish_reduction(const double (&v)[NQ], double* partials,
+                                                 int nslots, int slot, unsigned* counter,
+                                                 double* result, int nblocks) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) partials[q * nslots + slot] = v[q];
+    __threadfence();
+    unsigned t = atomicAdd(counter, 1u);
+    last = (t == (unsigned)nblocks - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  // fixed-order sum by the last workgroup, one quantity per wave lane range
+  for (int q = 0; q < NQ; ++q) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x)
+      s += __hip_atomic_load(&partials[q * nslots + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ double red[16];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += red[w];
+      result[q] = t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
+  return true;
+}
+
+// Map blockIdx.x so that each of the 8 XCDs (workgroups are dispatched to
+// XCDs round-robin) receives one contiguous range of tiles: neighbouring
+// tiles then share that XCD's L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = bid & 7, k = bid >> 3;
+  const int base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return base + k;
+}
+
+}  // namespace hdk

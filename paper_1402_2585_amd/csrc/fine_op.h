@@ -1,0 +1,90 @@
+// The fine domain-wall operator: handle state and host-side launchers.
+//
+// Native half-field layout (private): field[rhs][cb][c][s] with
+// c = spin*3 + colour (12 components) and s innermost, complex.  One 4D
+// site's whole fifth-dimension column is contiguous (12*Ls complex), so a
+// workgroup owning a few sites and all their s reads and writes long
+// contiguous runs, reuses each gauge link Ls times, and can apply the dense-
+// in-s inverse M_5^-1 from LDS.
+//
+// Native gauge layout (private): gauge[parity][cb][dir][3][3] for the sites
+// of each parity; dir 0..3 = U_mu(x) (times zeta_mu when x_mu = L_mu - 1),
+// dir 4..7 = U_mu(x - mu)^+ (times conj(zeta_mu) when x_mu = 0).  Each hop
+// stage reads the eight links of its output site contiguously.
+#pragma once
+
+#include "common.h"
+
+namespace hdk {
+
+struct Geom {
+  int X, Y, Z, T;  // 4D extents
+  int Xh;          // X / 2
+  int Ls;
+  int Vh;          // sites per checkerboard
+};
+
+struct FifthDim {
+  double d;       // 5 - M5
+  double mass;
+  double pw[64];  // pw[n] = d^(-1-n) / (1 + m d^(-Ls)) (closed form of M_5^-1)
+};
+
+struct dwf_op_impl;
+
+}  // namespace hdk
+
+struct dwf_op {
+  hdk::Geom g;
+  double M5, mass;
+  double bc[8];
+  hdk::FifthDim f5;
+  hdk::DevBuf gauge128, gauge64;  // [2][Vh][8][9]
+  hdk::DevBuf pw128, pw64;        // closed-form table on the device
+  hdk::DevBuf tmp[2][3];          // [prec][t_e, chi, s_e] work fields
+  hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
+  hdk::Reducer red;
+  hdk::DevBuf host_pinned_dummy;
+  double* pinned = nullptr;        // host pinned scalars
+  int device = 0;
+  size_t site_elems() const { return (size_t)12 * g.Ls; }
+  size_t field_elems(int nrhs) const { return (size_t)nrhs * g.Vh * 12 * g.Ls; }
+};
+
+namespace hdk {
+
+// Launch helpers (all asynchronous on `stream`).
+template <typename R>
+int launch_mpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, bool dagger, int nrhs,
+               hipStream_t stream, double* norm_result /*nullable: |M_pc in|^2 per rhs*/);
+template <typename R>
+int launch_mpcdagmpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, int nrhs, hipStream_t stream,
+                     double* pap_result /*nullable: <in, H in> = |M_pc in|^2 per rhs*/);
+
+// BLAS-1 (FP64 accumulation); results are device doubles, one per rhs.
+template <typename R>
+int launch_norm2(dwf_op* op, const cplx<R>* x, int nrhs, double* result, hipStream_t stream);
+template <typename R>
+int launch_dot(dwf_op* op, const cplx<R>* a, const cplx<R>* b, int nrhs, double* result /*2*nrhs*/,
+               hipStream_t stream);
+// x += alpha p ; r -= alpha w ; |r|^2 -> rr.  alpha = num[i]/den[i] (device)
+// or alpha_host if num == nullptr.
+template <typename R>
+int launch_cg_update(dwf_op* op, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w,
+                     const double* num, const double* den, const double* alpha_host, double* rr,
+                     int nrhs, hipStream_t stream);
+// p = r + beta p, beta = num/den (device) or beta_host.
+template <typename R>
+int launch_xpay(dwf_op* op, cplx<R>* p, const cplx<R>* r, const double* num, const double* den,
+                const double* beta_host, int nrhs, hipStream_t stream);
+// y = a*x + b*y (generic real coefficients on host)
+template <typename R>
+int launch_axpby(dwf_op* op, cplx<R>* y, const cplx<R>* x, double a, double b, size_t n,
+                 hipStream_t stream);
+template <typename Rd, typename Rs>
+int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t stream);
+
+int ensure_tmp(dwf_op* op, int prec, int nrhs);
+int ensure_reducer(dwf_op* op);
+
+}  // namespace hdk

@@ -1,0 +1,650 @@
+// Fine domain-wall operator kernels for gfx950.
+//
+// One hop stage = one launch.  A workgroup owns `spw` consecutive output
+// sites of one checkerboard and all Ls slices of each (thread = (site, s)),
+// so every gauge link is loaded once per workgroup wave and broadcast to the
+// Ls threads that use it, and the neighbour spinors of a site column are
+// contiguous runs of Ls complex numbers per component.
+//
+// Epilogues (the fifth-dimension factors of M_pc, Sec. IV):
+//   EPI_INV  out = M_5^-1 (Dh in)          or M_5^-+ (Dh^+ in)   [dense in s]
+//   EPI_SUB  out = M_5 c - 1/4 (Dh in)      or M_5^+ c - 1/4 (Dh^+ in)
+// EPI_INV stages the hop result in LDS and solves the Ls x Ls system per
+// (site, component) with the O(Ls) recurrence of the closed-form inverse.
+#include "fine_op.h"
+
+namespace hdk {
+
+enum { EPI_INV = 0, EPI_SUB = 1 };
+
+// ------------------------------------------------------------ coordinates --
+struct Site {
+  int x, y, z, t, xh, rest;
+};
+
+__device__ __forceinline__ Site site_coords(int v, int parity, const Geom& g) {
+  Site c;
+  c.xh = v % g.Xh;
+  c.rest = v / g.Xh;
+  c.y = c.rest % g.Y;
+  int zt = c.rest / g.Y;
+  c.z = zt % g.Z;
+  c.t = zt / g.Z;
+  c.x = 2 * c.xh + ((c.y + c.z + c.t + parity) & 1);
+  return c;
+}
+
+// ------------------------------------------------------------ gauge import -
+__global__ void gauge_import_kernel(const c128* __restrict__ U, c128* __restrict__ G128,
+                                    c64* __restrict__ G64, Geom g, double4 bcxy, double4 bczt) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // (parity, cb)
+  if (idx >= 2 * g.Vh) return;
+  const int p = idx / g.Vh, v = idx % g.Vh;
+  const Site c = site_coords(v, p, g);
+  const int L[4] = {g.X, g.Y, g.Z, g.T};
+  const int xc[4] = {c.x, c.y, c.z, c.t};
+  const double zr[4] = {bcxy.x, bcxy.z, bczt.x, bczt.z};
+  const double zi[4] = {bcxy.y, bcxy.w, bczt.y, bczt.w};
+  const size_t lex = c.x + (size_t)g.X * (c.y + (size_t)g.Y * (c.z + (size_t)g.Z * c.t));
+  c128* out128 = G128 + (size_t)idx * 72;
+  c64* out64 = G64 + (size_t)idx * 72;
+  for (int mu = 0; mu < 4; ++mu) {
+    // forward link U_mu(x), phase when the hop x -> x+mu wraps
+    const c128 zf = (xc[mu] == L[mu] - 1) ? cmk(zr[mu], zi[mu]) : cmk(1.0, 0.0);
+    const c128* u = U + (lex * 4 + mu) * 9;
+    for (int e = 0; e < 9; ++e) {
+      c128 w = zf * u[e];
+      out128[mu * 9 + e] = w;
+      out64[mu * 9 + e] = cmk((float)w.re, (float)w.im);
+    }
+    // backward link U_mu(x-mu)^+, conj phase when the hop x -> x-mu wraps
+    int xm[4] = {c.x, c.y, c.z, c.t};
+    xm[mu] = (xm[mu] == 0) ? L[mu] - 1 : xm[mu] - 1;
+    const size_t lexm = xm[0] + (size_t)g.X * (xm[1] + (size_t)g.Y * (xm[2] + (size_t)g.Z * xm[3]));
+    const c128 zb = (xc[mu] == 0) ? cmk(zr[mu], -zi[mu]) : cmk(1.0, 0.0);
+    const c128* ub = U + (lexm * 4 + mu) * 9;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        c128 w = zb * conj(ub[b * 3 + a]);
+        out128[(4 + mu) * 9 + a * 3 + b] = w;
+        out64[(4 + mu) * 9 + a * 3 + b] = cmk((float)w.re, (float)w.im);
+      }
+  }
+}
+
+// ----------------------------------------------------------- field layout --
+// canonical [rhs][s][cb][c]  <->  native [rhs][cb][c][s]
+template <typename R, bool TO_NATIVE>
+__global__ void field_layout_kernel(cplx<R>* __restrict__ dst, const cplx<R>* __restrict__ src,
+                                    int Ls, int Vh, size_t total) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  // idx enumerates the native layout
+  const int s = idx % Ls;
+  const int c = (idx / Ls) % 12;
+  const size_t cb = (idx / ((size_t)Ls * 12)) % Vh;
+  const size_t rhs = idx / ((size_t)Ls * 12 * Vh);
+  const size_t can = ((rhs * Ls + s) * Vh + cb) * 12 + c;
+  if (TO_NATIVE)
+    dst[idx] = src[can];
+  else
+    dst[can] = src[idx];
+}
+
+template <typename Rd, typename Rs>
+__global__ void convert_kernel(cplx<Rd>* __restrict__ dst, const cplx<Rs>* __restrict__ src,
+                               size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    cplx<Rs> v = src[i];
+    dst[i] = cmk((Rd)v.re, (Rd)v.im);
+  }
+}
+
+// ------------------------------------------------------------- hop stage --
+// Spin structure in the chiral basis: gamma_mu = [[0, A_mu], [A_mu^+, 0]]
+// with A_x = -i sigma_x, A_y = -i sigma_y, A_z = -i sigma_z, A_t = 1.
+// (1 + sg*gamma_mu) psi = (h ; sg A^+ h) with h = u + sg A l, where u, l are
+// the upper and lower spin pairs of psi: the hop moves 6 complex numbers
+// through the SU(3) link instead of 12.
+template <typename R, int MU>
+__device__ __forceinline__ void apply_A(const cplx<R> l0, const cplx<R> l1, cplx<R>& a0,
+                                        cplx<R>& a1) {
+  if (MU == 0) {  // A_x l = (-i l1, -i l0)
+    a0 = timesMinusI(l1);
+    a1 = timesMinusI(l0);
+  } else if (MU == 1) {  // A_y l = (-l1, l0)
+    a0 = cmk(-l1.re, -l1.im);
+    a1 = l0;
+  } else if (MU == 2) {  // A_z l = (-i l0, i l1)
+    a0 = timesMinusI(l0);
+    a1 = timesI(l1);
+  } else {  // A_t l = l
+    a0 = l0;
+    a1 = l1;
+  }
+}
+template <typename R, int MU>
+__device__ __forceinline__ void apply_Adag(const cplx<R> h0, const cplx<R> h1, cplx<R>& a0,
+                                           cplx<R>& a1) {
+  if (MU == 0) {  // A_x^+ h = (i h1, i h0)
+    a0 = timesI(h1);
+    a1 = timesI(h0);
+  } else if (MU == 1) {  // A_y^+ h = (h1, -h0)
+    a0 = h1;
+    a1 = cmk(-h0.re, -h0.im);
+  } else if (MU == 2) {  // A_z^+ h = (i h0, -i h1)
+    a0 = timesI(h0);
+    a1 = timesMinusI(h1);
+  } else {
+    a0 = h0;
+    a1 = h1;
+  }
+}
+
+// acc += (1 + SG*gamma_mu) W psi, psi read at `p` (stride Ls between
+// components), W = 3x3 link at `w`.
+template <typename R, int MU, int SG>
+__device__ __forceinline__ void hop_term(cplx<R> (&acc)[12], const cplx<R>* __restrict__ p,
+                                         const cplx<R>* __restrict__ w, int Ls) {
+  cplx<R> h[2][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx<R> u0 = p[(0 * 3 + c) * Ls];
+    const cplx<R> u1 = p[(1 * 3 + c) * Ls];
+    const cplx<R> l0 = p[(2 * 3 + c) * Ls];
+    const cplx<R> l1 = p[(3 * 3 + c) * Ls];
+    cplx<R> a0, a1;
+    apply_A<R, MU>(l0, l1, a0, a1);
+    if (SG > 0) {
+      h[0][c] = u0 + a0;
+      h[1][c] = u1 + a1;
+    } else {
+      h[0][c] = u0 - a0;
+      h[1][c] = u1 - a1;
+    }
+  }
+  cplx<R> Wh[2][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<R> w0 = w[a * 3 + 0], w1 = w[a * 3 + 1], w2 = w[a * 3 + 2];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      cplx<R> t = w0 * h[sp][0];
+      cmac(t, w1, h[sp][1]);
+      cmac(t, w2, h[sp][2]);
+      Wh[sp][a] = t;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    acc[0 * 3 + a] = acc[0 * 3 + a] + Wh[0][a];
+    acc[1 * 3 + a] = acc[1 * 3 + a] + Wh[1][a];
+    cplx<R> b0, b1;
+    apply_Adag<R, MU>(Wh[0][a], Wh[1][a], b0, b1);
+    if (SG > 0) {
+      acc[2 * 3 + a] = acc[2 * 3 + a] + b0;
+      acc[3 * 3 + a] = acc[3 * 3 + a] + b1;
+    } else {
+      acc[2 * 3 + a] = acc[2 * 3 + a] - b0;
+      acc[3 * 3 + a] = acc[3 * 3 + a] - b1;
+    }
+  }
+}
+
+struct HopArgs {
+  Geom g;
+  int out_parity;
+  int spw;            // sites per workgroup
+  size_t field;       // complex elements per rhs
+  double d, mass;     // fifth dimension
+  double* partials;   // EPI_SUB norm: [rhs][kMaxPartials] (nullable)
+  unsigned* counters; // [rhs]
+  double* result;     // [rhs]
+};
+
+template <typename R, bool DAG, int EPI>
+__global__ void __launch_bounds__(256)
+hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
+           const cplx<R>* __restrict__ center, const cplx<R>* __restrict__ gauge,
+           const R* __restrict__ pw, HopArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Geom& g = A.g;
+  const int Ls = g.Ls;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int rhs = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int vloc = tid / Ls, s = tid - vloc * Ls;
+  const int v = wg * A.spw + vloc;
+  const bool active = (vloc < A.spw) && (v < g.Vh);
+
+  in += rhs * A.field;
+  out += rhs * A.field;
+
+  cplx<R> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = cmk((R)0, (R)0);
+
+  // forward terms (1 - g) U(x) psi(x+mu) [non-dagger]; dagger flips signs
+  constexpr int SF = DAG ? 1 : -1;
+  if (active) {
+    const Site c = site_coords(v, A.out_parity, g);
+    const size_t col = (size_t)12 * Ls;
+    const cplx<R>* G = gauge + (size_t)v * 72;
+    const int rowyzt = c.rest * g.Xh;
+    // x direction
+    {
+      const int xp = (c.x + 1 == g.X) ? 0 : c.x + 1;
+      const int xm = (c.x == 0) ? g.X - 1 : c.x - 1;
+      hop_term<R, 0, SF>(acc, in + (size_t)((xp >> 1) + rowyzt) * col + s, G + 0 * 9, Ls);
+      hop_term<R, 0, -SF>(acc, in + (size_t)((xm >> 1) + rowyzt) * col + s, G + 4 * 9, Ls);
+    }
+    // y direction
+    {
+      const int zt = c.rest / g.Y;
+      const int yp = (c.y + 1 == g.Y) ? 0 : c.y + 1;
+      const int ym = (c.y == 0) ? g.Y - 1 : c.y - 1;
+      hop_term<R, 1, SF>(acc, in + (size_t)(c.xh + g.Xh * (yp + g.Y * zt)) * col + s, G + 1 * 9, Ls);
+      hop_term<R, 1, -SF>(acc, in + (size_t)(c.xh + g.Xh * (ym + g.Y * zt)) * col + s, G + 5 * 9, Ls);
+    }
+    // z direction
+    {
+      const int zp = (c.z + 1 == g.Z) ? 0 : c.z + 1;
+      const int zm = (c.z == 0) ? g.Z - 1 : c.z - 1;
+      const size_t b = (size_t)c.xh + (size_t)g.Xh * c.y;
+      const size_t sy = (size_t)g.Xh * g.Y;
+      hop_term<R, 2, SF>(acc, in + (b + sy * (zp + (size_t)g.Z * c.t)) * col + s, G + 2 * 9, Ls);
+      hop_term<R, 2, -SF>(acc, in + (b + sy * (zm + (size_t)g.Z * c.t)) * col + s, G + 6 * 9, Ls);
+    }
+    // t direction
+    {
+      const int tp = (c.t + 1 == g.T) ? 0 : c.t + 1;
+      const int tm = (c.t == 0) ? g.T - 1 : c.t - 1;
+      const size_t b = (size_t)c.xh + (size_t)g.Xh * (c.y + (size_t)g.Y * c.z);
+      const size_t sz = (size_t)g.Xh * g.Y * g.Z;
+      hop_term<R, 3, SF>(acc, in + (b + sz * tp) * col + s, G + 3 * 9, Ls);
+      hop_term<R, 3, -SF>(acc, in + (b + sz * tm) * col + s, G + 7 * 9, Ls);
+    }
+  }
+
+  if (EPI == EPI_INV) {
+    // ---- M_5^-1 (or its adjoint) across s, through LDS --------------------
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][12][Ls+1]
+    const int ld = Ls + 1;
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) buf[(vloc * 12 + c) * ld + s] = acc[c];
+    }
+    __syncthreads();
+    const R invd = (R)(1.0 / A.d);
+    const R m = (R)A.mass;
+    for (int q = tid; q < A.spw * 12; q += blockDim.x) {
+      const int vl = q / 12, c = q - vl * 12;
+      if (wg * A.spw + vl >= g.Vh) continue;
+      cplx<R>* row = buf + (vl * 12 + c) * ld;
+      // P+ (c < 6) takes M+^-1 (lower-triangular recurrence), P- takes M-^-1;
+      // the adjoint swaps the two.
+      const bool lower = ((c < 6) != DAG);
+      if (lower) {
+        cplx<R> tsum = cmk((R)0, (R)0);
+        for (int sp = 1; sp < Ls; ++sp) tsum = tsum + pw[Ls - sp] * row[sp];
+        cplx<R> y = pw[0] * row[0] - m * tsum;
+        row[0] = y;
+        for (int sp = 1; sp < Ls; ++sp) {
+          y = invd * (row[sp] + y);
+          row[sp] = y;
+        }
+      } else {
+        cplx<R> tsum = cmk((R)0, (R)0);
+        for (int t = 1; t < Ls; ++t) tsum = tsum + pw[Ls - t] * row[Ls - 1 - t];
+        cplx<R> y = pw[0] * row[Ls - 1] - m * tsum;
+        row[Ls - 1] = y;
+        for (int sp = Ls - 2; sp >= 0; --sp) {
+          y = invd * (row[sp] + y);
+          row[sp] = y;
+        }
+      }
+    }
+    __syncthreads();
+    if (active) {
+      cplx<R>* o = out + (size_t)v * 12 * Ls + s;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) o[c * Ls] = buf[(vloc * 12 + c) * ld + s];
+    }
+  } else {
+    // ---- M_5 c - 1/4 hop (or M_5^+ c - 1/4 hop^+) --------------------------
+    double nrm = 0.0;
+    if (active) {
+      const cplx<R>* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
+      cplx<R>* o = out + (size_t)v * 12 * Ls + s;
+      const R d = (R)A.d, m = (R)A.mass, q = (R)0.25;
+      // M_5: P+ couples to s-1 (mass term from Ls-1 at s = 0), P- to s+1
+      // (mass term from 0 at s = Ls-1); the adjoint swaps the directions.
+      const int s_dn = (s > 0) ? s - 1 : Ls - 1;
+      const R f_dn = (s > 0) ? (R)-1 : m;
+      const int s_up = (s < Ls - 1) ? s + 1 : 0;
+      const R f_up = (s < Ls - 1) ? (R)-1 : m;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cplx<R>* cc = cen + c * Ls;
+        const bool from_below = ((c < 6) != DAG);
+        const int sn = from_below ? s_dn : s_up;
+        const R fn = from_below ? f_dn : f_up;
+        const cplx<R> r = d * cc[s] + fn * cc[sn] - q * acc[c];
+        o[c * Ls] = r;
+        nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+      }
+    }
+    if (A.partials) {
+      double vv[1] = {nrm};
+      __shared__ double red[16];
+      block_sum<1>(vv, red);
+      finish_reduction<1>(vv, A.partials + (size_t)rhs * kMaxPartials, 0, wg, A.counters + rhs,
+                          A.result + rhs, gridDim.x);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ BLAS ---
+template <typename R>
+__device__ __forceinline__ double cnorm(cplx<R> a) {
+  return (double)a.re * a.re + (double)a.im * a.im;
+}
+
+struct RedArgs {
+  size_t n;  // complex elements per rhs
+  double* partials;
+  unsigned* counters;
+  double* result;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) norm2_kernel(const cplx<R>* __restrict__ x, RedArgs A) {
+  const int rhs = blockIdx.y;
+  x += rhs * A.n;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+       i += (size_t)gridDim.x * blockDim.x)
+    acc += cnorm(x[i]);
+  double v[1] = {acc};
+  __shared__ double red[16];
+  block_sum<1>(v, red);
+  finish_reduction<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x,
+                      A.counters + rhs, A.result + rhs, gridDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+dot_kernel(const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ b, RedArgs A) {
+  const int rhs = blockIdx.y;
+  a += rhs * A.n;
+  b += rhs * A.n;
+  double re = 0.0, im = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const cplx<R> x = a[i], y = b[i];
+    re += (double)x.re * y.re + (double)x.im * y.im;  // conj(a) b
+    im += (double)x.re * y.im - (double)x.im * y.re;
+  }
+  double v[2] = {re, im};
+  __shared__ double red[32];
+  block_sum<2>(v, red);
+  // partial layout [rhs][2][kMaxPartials/2]
+  finish_reduction<2>(v, A.partials + (size_t)rhs * kMaxPartials, kMaxPartials / 2, blockIdx.x,
+                      A.counters + rhs, A.result + 2 * rhs, gridDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+cg_update_kernel(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+                 const cplx<R>* __restrict__ w, const double* num, const double* den,
+                 const double* alpha_host, RedArgs A) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * A.n;
+  const double al = num ? num[rhs] / den[rhs] : alpha_host[rhs];
+  const R a = (R)al;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const cplx<R> pi = p[off + i], wi = w[off + i];
+    cplx<R> xi = x[off + i], ri = r[off + i];
+    xi = xi + a * pi;
+    ri = ri - a * wi;
+    x[off + i] = xi;
+    r[off + i] = ri;
+    acc += cnorm(ri);
+  }
+  double v[1] = {acc};
+  __shared__ double red[16];
+  block_sum<1>(v, red);
+  finish_reduction<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x,
+                      A.counters + rhs, A.result + rhs, gridDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+xpay_kernel(cplx<R>* __restrict__ p, const cplx<R>* __restrict__ r, const double* num,
+            const double* den, const double* beta_host, size_t n) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * n;
+  const R b = (R)(num ? num[rhs] / den[rhs] : beta_host[rhs]);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[off + i] = r[off + i] + b * p[off + i];
+}
+
+template <typename R>
+__global__ void axpby_kernel(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, R a, R b,
+                             size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// ============================================================= launchers ===
+static inline int red_blocks(size_t n) {
+  size_t b = (n + 256 * 8 - 1) / (256 * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+int ensure_reducer(dwf_op* op) {
+  HDCG_TRY(op->red.partials.ensure(sizeof(double) * (size_t)kMaxPartials * 64));
+  if (op->red.counters.bytes == 0) {
+    HDCG_TRY(op->red.counters.ensure(sizeof(unsigned) * 64));
+    HDCG_HIP(hipMemset(op->red.counters.ptr, 0, sizeof(unsigned) * 64));
+  }
+  HDCG_TRY(op->red.results.ensure(sizeof(double) * 256));
+  return DWF_OK;
+}
+
+int ensure_tmp(dwf_op* op, int prec, int nrhs) {
+  const size_t bytes = op->field_elems(nrhs) * cbytes(prec);
+  const int pi = prec == DWF_C128 ? 0 : 1;
+  for (int i = 0; i < 3; ++i) HDCG_TRY(op->tmp[pi][i].ensure(bytes));
+  return DWF_OK;
+}
+
+template <typename R>
+static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>* center,
+                      bool dagger, int epi, int out_parity, int nrhs, hipStream_t stream,
+                      double* norm_result) {
+  const Geom& g = op->g;
+  HopArgs A;
+  A.g = g;
+  A.out_parity = out_parity;
+  A.spw = g.Ls >= 256 ? 1 : 256 / g.Ls;
+  A.field = (size_t)g.Vh * 12 * g.Ls;
+  A.d = op->f5.d;
+  A.mass = op->f5.mass;
+  A.partials = nullptr;
+  A.counters = nullptr;
+  A.result = nullptr;
+  const int threads = ((A.spw * g.Ls + 63) / 64) * 64;
+  const int nwg = (g.Vh + A.spw - 1) / A.spw;
+  if (norm_result) {
+    if (nwg > kMaxPartials || nrhs > 64) return fail(DWF_ERR_ARG, "lattice too large for fused norm");
+    A.partials = op->red.partials.as<double>();
+    A.counters = op->red.counters.as<unsigned>();
+    A.result = norm_result;
+  }
+  const bool dbl = sizeof(R) == 8;
+  const cplx<R>* G = reinterpret_cast<const cplx<R>*>(dbl ? op->gauge128.ptr : op->gauge64.ptr) +
+                     (size_t)out_parity * g.Vh * 72;
+  const R* pw = reinterpret_cast<const R*>(dbl ? op->pw128.ptr : op->pw64.ptr);
+  dim3 grid(nwg, nrhs), block(threads);
+  const size_t lds = epi == EPI_INV ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  if (epi == EPI_INV) {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV>), grid, block, lds, stream, out, in, center, G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV>), grid, block, lds, stream, out, in, center, G, pw, A);
+  } else {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB>), grid, block, lds, stream, out, in, center, G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB>), grid, block, lds, stream, out, in, center, G, pw, A);
+  }
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_mpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, bool dagger, int nrhs,
+               hipStream_t stream, double* norm_result) {
+  const int prec = prec_of<R>();
+  HDCG_TRY(ensure_tmp(op, prec, nrhs));
+  cplx<R>* te = op->tmp[prec == DWF_C128 ? 0 : 1][0].as<cplx<R>>();
+  // stage 1: t_e = M_5^-1 Dh_eo in    (adjoint: M_5^-+ Dh^+_eo in)
+  HDCG_TRY(hop_launch<R>(op, te, in, nullptr, dagger, EPI_INV, 0, nrhs, stream, nullptr));
+  // stage 2: out = M_5 in - 1/4 Dh_oe t_e  (adjoint: M_5^+ in - 1/4 Dh^+_oe t_e)
+  HDCG_TRY(hop_launch<R>(op, out, te, in, dagger, EPI_SUB, 1, nrhs, stream, norm_result));
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_mpcdagmpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, int nrhs, hipStream_t stream,
+                     double* pap_result) {
+  const int prec = prec_of<R>();
+  HDCG_TRY(ensure_tmp(op, prec, nrhs));
+  cplx<R>* chi = op->tmp[prec == DWF_C128 ? 0 : 1][1].as<cplx<R>>();
+  HDCG_TRY(launch_mpc<R>(op, chi, in, false, nrhs, stream, pap_result));
+  HDCG_TRY(launch_mpc<R>(op, out, chi, true, nrhs, stream, nullptr));
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_norm2(dwf_op* op, const cplx<R>* x, int nrhs, double* result, hipStream_t stream) {
+  RedArgs A{op->field_elems(1), op->red.partials.as<double>(), op->red.counters.as<unsigned>(),
+            result};
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  dim3 grid(red_blocks(A.n), nrhs);
+  hipLaunchKernelGGL((norm2_kernel<R>), grid, dim3(256), 0, stream, x, A);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_dot(dwf_op* op, const cplx<R>* a, const cplx<R>* b, int nrhs, double* result,
+               hipStream_t stream) {
+  RedArgs A{op->field_elems(1), op->red.partials.as<double>(), op->red.counters.as<unsigned>(),
+            result};
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  dim3 grid(red_blocks(A.n), nrhs);
+  hipLaunchKernelGGL((dot_kernel<R>), grid, dim3(256), 0, stream, a, b, A);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_cg_update(dwf_op* op, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w,
+                     const double* num, const double* den, const double* alpha_host, double* rr,
+                     int nrhs, hipStream_t stream) {
+  RedArgs A{op->field_elems(1), op->red.partials.as<double>(), op->red.counters.as<unsigned>(), rr};
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  dim3 grid(red_blocks(A.n), nrhs);
+  hipLaunchKernelGGL((cg_update_kernel<R>), grid, dim3(256), 0, stream, x, r, p, w, num, den,
+                     alpha_host, A);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_xpay(dwf_op* op, cplx<R>* p, const cplx<R>* r, const double* num, const double* den,
+                const double* beta_host, int nrhs, hipStream_t stream) {
+  const size_t n = op->field_elems(1);
+  dim3 grid(red_blocks(n), nrhs);
+  hipLaunchKernelGGL((xpay_kernel<R>), grid, dim3(256), 0, stream, p, r, num, den, beta_host, n);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_axpby(dwf_op*, cplx<R>* y, const cplx<R>* x, double a, double b, size_t n,
+                 hipStream_t stream) {
+  hipLaunchKernelGGL((axpby_kernel<R>), dim3(red_blocks(n)), dim3(256), 0, stream, y, x, (R)a,
+                     (R)b, n);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename Rd, typename Rs>
+int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t stream) {
+  hipLaunchKernelGGL((convert_kernel<Rd, Rs>), dim3(red_blocks(n)), dim3(256), 0, stream, dst, src, n);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+#define INST(R)                                                                                 \
+  template int launch_mpc<R>(dwf_op*, cplx<R>*, const cplx<R>*, bool, int, hipStream_t, double*); \
+  template int launch_mpcdagmpc<R>(dwf_op*, cplx<R>*, const cplx<R>*, int, hipStream_t, double*); \
+  template int launch_norm2<R>(dwf_op*, const cplx<R>*, int, double*, hipStream_t);             \
+  template int launch_dot<R>(dwf_op*, const cplx<R>*, const cplx<R>*, int, double*, hipStream_t); \
+  template int launch_cg_update<R>(dwf_op*, cplx<R>*, cplx<R>*, const cplx<R>*, const cplx<R>*, \
+                                   const double*, const double*, const double*, double*, int,  \
+                                   hipStream_t);                                                \
+  template int launch_xpay<R>(dwf_op*, cplx<R>*, const cplx<R>*, const double*, const double*,  \
+                              const double*, int, hipStream_t);                                 \
+  template int launch_axpby<R>(dwf_op*, cplx<R>*, const cplx<R>*, double, double, size_t,      \
+                               hipStream_t);
+INST(double)
+INST(float)
+template int launch_convert<double, float>(cplx<double>*, const cplx<float>*, size_t, hipStream_t);
+template int launch_convert<float, double>(cplx<float>*, const cplx<double>*, size_t, hipStream_t);
+
+// ------------------------------------------------------------ host setup ---
+int import_gauge(dwf_op* op, const void* gauge_c128, hipStream_t stream) {
+  const Geom& g = op->g;
+  HDCG_TRY(op->gauge128.ensure(sizeof(c128) * 2 * (size_t)g.Vh * 72));
+  HDCG_TRY(op->gauge64.ensure(sizeof(c64) * 2 * (size_t)g.Vh * 72));
+  double4 bcxy = make_double4(op->bc[0], op->bc[1], op->bc[2], op->bc[3]);
+  double4 bczt = make_double4(op->bc[4], op->bc[5], op->bc[6], op->bc[7]);
+  const int n = 2 * g.Vh;
+  hipLaunchKernelGGL(gauge_import_kernel, dim3((n + 127) / 128), dim3(128), 0, stream,
+                     static_cast<const c128*>(gauge_c128), op->gauge128.as<c128>(),
+                     op->gauge64.as<c64>(), g, bcxy, bczt);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int launch_layout(dwf_op* op, void* dst, const void* src, int nrhs, bool to_native,
+                  hipStream_t stream) {
+  const size_t total = op->field_elems(nrhs);
+  const int blocks = (int)((total + 255) / 256);
+  if (to_native)
+    hipLaunchKernelGGL((field_layout_kernel<R, true>), dim3(blocks), dim3(256), 0, stream,
+                       static_cast<cplx<R>*>(dst), static_cast<const cplx<R>*>(src), op->g.Ls,
+                       op->g.Vh, total);
+  else
+    hipLaunchKernelGGL((field_layout_kernel<R, false>), dim3(blocks), dim3(256), 0, stream,
+                       static_cast<cplx<R>*>(dst), static_cast<const cplx<R>*>(src), op->g.Ls,
+                       op->g.Vh, total);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+template int launch_layout<double>(dwf_op*, void*, const void*, int, bool, hipStream_t);
+template int launch_layout<float>(dwf_op*, void*, const void*, int, bool, hipStream_t);
+
+}  // namespace hdk

@@ -1,0 +1,71 @@
+"""Device-buffer helpers around an operator handle (allocation with PyTorch,
+layout conversion through the library)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib as L
+
+_DT = {L.DWF_C128: "complex128", L.DWF_C64: "complex64"}
+
+
+class FineOperator:
+    """Owns one dwf_op handle; fields are torch tensors in the native layout."""
+
+    def __init__(self, gauge, dims, Ls, M5, mass, bc=(1, 1, 1, -1)):
+        import torch
+
+        self.torch = torch
+        g = gauge if isinstance(gauge, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(gauge))
+        g = g.to(device="cuda", dtype=torch.complex128).contiguous()
+        self.dims, self.Ls, self.M5, self.mass, self.bc = tuple(dims), int(Ls), float(M5), float(mass), bc
+        self.h = L.dwf_create(g, dims, Ls, M5, mass, bc)
+        torch.cuda.synchronize()
+        X, Y, Z, T = dims
+        self.Vh = X * Y * Z * T // 2
+        self.canonical_shape = (self.Ls, self.Vh, 4, 3)
+
+    def close(self):
+        if self.h is not None:
+            L.dwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dtype(self, prec):
+        return getattr(self.torch, _DT[prec])
+
+    def new_field(self, prec=L.DWF_C128, nrhs=1, zero=False):
+        n = L.dwf_field_bytes(self.h, prec, nrhs) // (16 if prec == L.DWF_C128 else 8)
+        f = self.torch.zeros if zero else self.torch.empty
+        return f(n, dtype=self.dtype(prec), device="cuda")
+
+    def to_native(self, canonical, prec=L.DWF_C128):
+        """canonical: numpy or torch array (nrhs, Ls, Vh, 4, 3) or (Ls, Vh, 4, 3)."""
+        t = canonical if isinstance(canonical, self.torch.Tensor) else self.torch.from_numpy(
+            np.ascontiguousarray(canonical))
+        t = t.to(device="cuda", dtype=self.dtype(prec)).contiguous()
+        nrhs = t.numel() // (self.Vh * self.Ls * 12)
+        out = self.new_field(prec, nrhs)
+        L.dwf_import(self.h, out, t, prec, nrhs)
+        return out
+
+    def to_canonical(self, native, prec=L.DWF_C128, nrhs=None):
+        nrhs = nrhs or native.numel() // (self.Vh * self.Ls * 12)
+        out = self.torch.empty((nrhs,) + self.canonical_shape, dtype=self.dtype(prec), device="cuda")
+        L.dwf_export(self.h, out, native, prec, nrhs)
+        return out if nrhs > 1 else out[0]
+
+    def mpc(self, x, prec=L.DWF_C128, dagger=0, nrhs=1, out=None):
+        out = self.new_field(prec, nrhs) if out is None else out
+        L.mpc_apply(self.h, out, x, prec, dagger, nrhs)
+        return out
+
+    def H(self, x, prec=L.DWF_C128, nrhs=1, out=None):
+        out = self.new_field(prec, nrhs) if out is None else out
+        L.mpc_dag_mpc_apply(self.h, out, x, prec, nrhs)
+        return out

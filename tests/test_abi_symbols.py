@@ -1,0 +1,46 @@
+"""The C-ABI library loads on the CPU host and exports every function that
+include/hdcg.h declares (no compute call is made without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("dwf_create", "mpc_dag_mpc_apply", "cg_solve", "dwf_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1402_2585_amd._lib import LIB_PATH
+
+    lib = ctypes.CDLL(LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_errors_without_device_calls():
+    """Argument validation happens before any device work."""
+    import paper_1402_2585_amd as hd
+
+    lib = hd.load()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int * 4)(4, 4, 5, 4)  # odd extent
+    rc = lib.dwf_create(ctypes.byref(h), ctypes.byref(dims), 8, 1.8, 0.01, ctypes.c_void_p(1), None, None)
+    assert rc == -2 and b"even" in lib.dwf_last_error()
+    dims = (ctypes.c_int * 4)(4, 4, 4, 4)
+    rc = lib.dwf_create(ctypes.byref(h), ctypes.byref(dims), 0, 1.8, 0.01, ctypes.c_void_p(1), None, None)
+    assert rc == -2
+    assert lib.mpc_apply(None, None, None, 0, 0, 1, None) == -1

@@ -1,0 +1,207 @@
+"""GPU parity of the fine operator, BLAS-1 and FP64 CG against the oracle.
+
+Tolerances: FP64 applications 1e-12 relative (max-norm); complex64
+applications 5e-6 (a sum of ~100 terms of O(1) magnitude in float32,
+eps 6e-8); integer layouts bit-exact; CG true residual <= 1e-8."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.cg import cg
+from oracle.dwf import DWF
+from oracle import geometry as geo
+from tests.gpu_util import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1402_2585_amd as hd  # noqa: E402
+
+CASES = {
+    "cfg1-4^4xLs8": ((4, 4, 4, 4), 8, 0.5, (1, 1, 1, -1), 0.01),
+    "ragged-6x4x4x8xLs5": ((6, 4, 4, 8), 5, 0.8, (1, 1, 1, -1), 0.1),
+    "phases-8x4x6x4xLs3": ((8, 4, 6, 4), 3, 0.9, (1, np.exp(0.3j), -1, np.exp(-0.7j)), 0.05),
+    "ls1-4x4x4x6": ((4, 4, 4, 6), 1, 0.7, (1, 1, 1, -1), 0.02),
+    "ls12-4x4x6x4": ((4, 4, 6, 4), 12, 0.6, (1, 1, 1, -1), 0.003),
+}
+
+
+def _make(name, seed=1):
+    dims, Ls, eps, bc, mass = CASES[name]
+    U = synth.gauge_field(dims, eps, 100 + seed)
+    return dims, Ls, U, bc, mass, hd.FineOperator(U, dims, Ls, 1.8, mass, bc), DWF(U, dims, Ls, 1.8, mass, bc)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_layout_roundtrip_bit_exact(name):
+    banner(f"layout {name}")
+    dims, Ls, U, bc, mass, op, ref = _make(name)
+    for prec, dt in ((hd.DWF_C128, np.complex128), (hd.DWF_C64, np.complex64)):
+        b = synth.gaussian_half_field(dims, Ls, 7, nrhs=2).astype(dt)
+        back = op.to_canonical(op.to_native(b, prec), prec, nrhs=2).cpu().numpy()
+        assert np.array_equal(back, b)
+    op.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mpc_and_H_c128(name):
+    banner(f"mpc/H c128 {name}")
+    dims, Ls, U, bc, mass, op, ref = _make(name)
+    b = synth.gaussian_half_field(dims, Ls, 11)
+    nb = op.to_native(b)
+    for dag in (0, 1):
+        got = op.to_canonical(op.mpc(nb, dagger=dag)).cpu().numpy()
+        want = ref.mpc_dag(b) if dag else ref.mpc(b)
+        assert rel_err(got, want) < 1e-12, (dag, rel_err(got, want))
+    got = op.to_canonical(op.H(nb)).cpu().numpy()
+    assert rel_err(got, ref.H(b)) < 1e-12
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["cfg1-4^4xLs8", "ragged-6x4x4x8xLs5", "phases-8x4x6x4xLs3"])
+def test_H_c64(name):
+    banner(f"H c64 {name}")
+    dims, Ls, U, bc, mass, op, ref = _make(name)
+    b = synth.gaussian_half_field(dims, Ls, 12)
+    nb = op.to_native(b, hd.DWF_C64)
+    got = op.to_canonical(op.H(nb, hd.DWF_C64), hd.DWF_C64).cpu().numpy()
+    err = rel_err(got, ref.H(b))
+    print(f"c64 rel err {err:.2e}", flush=True)
+    assert err < 5e-6
+    op.close()
+
+
+def test_multi_rhs_matches_single():
+    banner("H c128 nrhs=3")
+    dims, Ls, U, bc, mass, op, ref = _make("ragged-6x4x4x8xLs5")
+    b = synth.gaussian_half_field(dims, Ls, 13, nrhs=3)
+    nb = op.to_native(b)
+    got = op.to_canonical(op.H(nb, nrhs=3), nrhs=3).cpu().numpy()
+    for r in range(3):
+        assert rel_err(got[r], ref.H(b[r])) < 1e-12
+    op.close()
+
+
+def test_free_field_plane_wave_through_gpu():
+    banner("free-field plane wave 4^4xLs8")
+    from tests.test_oracle_dwf import _free_field_K, _plane_wave
+
+    dims, Ls, M5, m = (4, 4, 4, 4), 8, 1.8, 0.01
+    U = np.broadcast_to(np.eye(3), (4, 4, 4, 4, 4, 3, 3)).copy()
+    op = hd.FineOperator(U, dims, Ls, M5, m)
+    p = [np.pi / 2, np.pi, 0.0, 3 * np.pi / 4]
+    K = _free_field_K(p, Ls, M5, m)
+    lam, W = np.linalg.eigh(K.conj().T @ K)
+    for i in (0, len(lam) - 1):
+        psi = _plane_wave(dims, Ls, p, W[:, i], np.array([0.2, 0.7j, -0.4]))
+        got = op.to_canonical(op.H(op.to_native(psi))).cpu().numpy()
+        assert rel_err(got, lam[i] * psi) < 1e-12
+    op.close()
+
+
+def test_gauge_covariance_through_gpu():
+    banner("gauge covariance 4x4x6x4xLs4")
+    dims, Ls = (4, 4, 6, 4), 4
+    U = synth.gauge_field(dims, 0.9, 5)
+    g = synth.su3_field(dims, 77)
+    U2 = U.copy()
+    for mu in range(4):
+        gs = np.roll(g, -1, axis=3 - mu)
+        U2[..., mu, :, :] = g @ U[..., mu, :, :] @ gs.conj().swapaxes(-1, -2)
+    op, op2 = hd.FineOperator(U, dims, Ls, 1.8, 0.01), hd.FineOperator(U2, dims, Ls, 1.8, 0.01)
+    go = g.reshape(-1, 3, 3)[geo.parity_sites(dims, 1)]
+    psi = synth.gaussian_half_field(dims, Ls, 3)
+    gpsi = np.matmul(psi, go.swapaxes(-1, -2))
+    lhs = op2.to_canonical(op2.H(op2.to_native(gpsi))).cpu().numpy()
+    rhs = np.matmul(op.to_canonical(op.H(op.to_native(psi))).cpu().numpy(), go.swapaxes(-1, -2))
+    assert rel_err(lhs, rhs) < 1e-12
+    op.close()
+    op2.close()
+
+
+@pytest.mark.parametrize("prec", [hd.DWF_C128, hd.DWF_C64])
+def test_blas_against_numpy(prec):
+    banner(f"blas prec={prec}")
+    dims, Ls, U, bc, mass, op, ref = _make("ragged-6x4x4x8xLs5")
+    dt = np.complex128 if prec == hd.DWF_C128 else np.complex64
+    tol = 1e-13 if prec == hd.DWF_C128 else 1e-6
+    f = [synth.gaussian_half_field(dims, Ls, 20 + i, nrhs=2).astype(dt) for i in range(4)]
+    x, r, p, w = [op.to_native(a, prec) for a in f]
+    n2 = hd.dwf_norm2(op.h, x, prec, 2)
+    want = np.array([np.vdot(f[0][i], f[0][i]).real for i in range(2)])
+    assert np.abs(n2 - want).max() <= 1e-13 * want.max()
+    n2b = hd.dwf_norm2(op.h, x, prec, 2)
+    assert np.array_equal(n2, n2b)  # deterministic reduction
+    d = hd.dwf_dot(op.h, x, r, prec, 2)
+    wd = np.array([np.vdot(f[0][i].astype(complex), f[1][i].astype(complex)) for i in range(2)])
+    assert np.abs(d - wd).max() <= 1e-12 * np.abs(wd).max() + 1e-9
+    alpha = [0.3, -1.7]
+    rr = hd.dwf_cg_update(op.h, x, r, p, w, alpha, prec, 2)
+    xs = op.to_canonical(x, prec, 2).cpu().numpy()
+    rs = op.to_canonical(r, prec, 2).cpu().numpy()
+    for i in range(2):
+        ex = f[0][i].astype(complex) + alpha[i] * f[2][i]
+        er = f[1][i].astype(complex) - alpha[i] * f[3][i]
+        assert rel_err(xs[i], ex) < tol and rel_err(rs[i], er) < tol
+        assert abs(rr[i] - np.vdot(rs[i].astype(complex), rs[i].astype(complex)).real) < 1e-12 * rr[i]
+    beta = [0.25, 2.0]
+    hd.dwf_xpay(op.h, p, r, beta, prec, 2)
+    ps = op.to_canonical(p, prec, 2).cpu().numpy()
+    for i in range(2):
+        assert rel_err(ps[i], rs[i].astype(complex) + beta[i] * f[2][i]) < tol
+    op.close()
+
+
+def test_cg_solve_config1_against_oracle():
+    banner("cg_solve fp64 config 1 (4^4 x Ls8, m=0.01, eps=0.5)")
+    dims, Ls, M5, mass = (4, 4, 4, 4), 8, 1.8, 0.01
+    U = synth.gauge_field(dims, 0.5, 1001)
+    b = synth.gaussian_half_field(dims, Ls, 1100)
+    op = hd.FineOperator(U, dims, Ls, M5, mass)
+    ref = DWF(U, dims, Ls, M5, mass)
+    nb = op.to_native(b)
+    x = op.new_field(zero=True)
+    rc, st = hd.cg_solve(op.h, x, nb, 1, 1e-8, 5000)
+    assert rc == 0 and st["converged"] == 1
+    xc = op.to_canonical(x).cpu().numpy()
+    r = b - ref.H(xc)
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+    xr, it, _ = cg(ref.H, b, tol=1e-8)
+    print(f"gpu its {st['iterations']} oracle its {it}", flush=True)
+    # the host checks convergence two iterations behind the GPU, so up to two
+    # extra iterations can run
+    assert it - 2 <= st["iterations"] <= it + 4
+    assert np.sqrt(np.vdot(xc - xr, xc - xr).real / np.vdot(xr, xr).real) < 1e-5
+    op.close()
+
+
+def test_cg_solve_zero_source_and_maxiter():
+    banner("cg_solve edge cases")
+    dims, Ls = (4, 4, 4, 4), 4
+    op = hd.FineOperator(synth.gauge_field(dims, 0.5, 3), dims, Ls, 1.8, 0.01)
+    x = op.new_field(zero=True)
+    z = op.new_field(zero=True)
+    rc, st = hd.cg_solve(op.h, x, z, 1, 1e-8, 100)
+    assert rc == 0 and st["iterations"] == 0
+    b = op.to_native(synth.gaussian_half_field(dims, Ls, 4))
+    rc, st = hd.cg_solve(op.h, x, b, 1, 1e-8, 3)
+    assert rc == hd.DWF_NOT_CONVERGED and st["converged"] == 0
+    op.close()
+
+
+def test_config2_full_size_H():
+    """Config 2 (16^4 x Ls16, eps 0.7) at full size in the launch shape the
+    benchmark times: c128 to 1e-12, c64 to 5e-6."""
+    banner("H config 2 full size 16^4xLs16")
+    dims, Ls, M5, mass = (16, 16, 16, 16), 16, 1.8, 0.01
+    U = synth.gauge_field(dims, 0.7, 2001)
+    b = synth.gaussian_half_field(dims, Ls, 2100)
+    op = hd.FineOperator(U, dims, Ls, M5, mass)
+    want = DWF(U, dims, Ls, M5, mass).H(b)
+    got = op.to_canonical(op.H(op.to_native(b))).cpu().numpy()
+    assert rel_err(got, want) < 1e-12
+    got64 = op.to_canonical(op.H(op.to_native(b, hd.DWF_C64), hd.DWF_C64), hd.DWF_C64).cpu().numpy()
+    assert rel_err(got64, want) < 5e-6
+    op.close()
