@@ -48,6 +48,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    # standalone profiling driver linked against the library
+    prof = os.path.join(HERE, "hdcg_prof")
+    cmd = [HIPCC, *FLAGS, "-o", prof, os.path.join(CSRC, "tools", "hdcg_prof.cpp"), f"-L{HERE}", "-lhdcg",
+           "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hdcg_prof build failed:\n{r.stderr}")
     if verbose:
         print("built", OUT)
     return OUT

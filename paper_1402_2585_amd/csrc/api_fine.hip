@@ -1,6 +1,8 @@
 // C ABI: fine operator, BLAS-1 and the plain FP64 CG comparator.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -202,6 +204,15 @@ int dwf_create(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass,
   const double den = 1.0 + mass * std::pow(d, -Ls);
   for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(d, -1 - n) / den : 0.0;
   (void)hipGetDevice(&op->device);
+  // hop launch shape: HDCG_HOP_TILE="bx,by,bz,bt,remap" overrides the default
+  if (const char* e = std::getenv("HDCG_HOP_TILE")) {
+    int b[6] = {0, 0, 0, 0, 1, 0};
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3], &b[4], &b[5]) >= 4) {
+      for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
+      op->tune.remap = b[4];
+      op->tune.lds_kb = b[5] < 0 ? 0 : (b[5] > 150 ? 150 : b[5]);
+    }
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = DWF_OK;
   do {

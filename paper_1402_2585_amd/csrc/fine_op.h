@@ -44,6 +44,11 @@ struct dwf_op {
   hdk::DevBuf tmp[2][3];          // [prec][t_e, chi, s_e] work fields
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
   hdk::Reducer red;
+  struct {
+    int block[4] = {0, 0, 0, 0};  // hop workgroup site block (x/2, y, z, t); 0 = linear
+    int remap = 1;                // XCD-contiguous workgroup order
+    int lds_kb = 0;               // minimum LDS per workgroup (caps occupancy)
+  } tune;
   hdk::DevBuf host_pinned_dummy;
   double* pinned = nullptr;        // host pinned scalars
   int device = 0;

@@ -196,6 +196,9 @@ struct HopArgs {
   Geom g;
   int out_parity;
   int spw;            // sites per workgroup
+  int bx, by, bz, bt; // 4D site block per workgroup in (x/2, y, z, t); bx = 0: linear cb order
+  int nbx, nby, nbz;  // block-grid extents
+  int remap;          // XCD-contiguous workgroup order
   size_t field;       // complex elements per rhs
   double d, mass;     // fifth dimension
   double* partials;   // EPI_SUB norm: [rhs][kMaxPartials] (nullable)
@@ -211,11 +214,28 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Geom& g = A.g;
   const int Ls = g.Ls;
-  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int wg = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
   const int vloc = tid / Ls, s = tid - vloc * Ls;
-  const int v = wg * A.spw + vloc;
+  int v;
+  if (A.bx > 0) {
+    // workgroup = one bx*by*bz*bt block of sites in (x/2, y, z, t)
+    int q = wg;
+    const int gx = q % A.nbx; q /= A.nbx;
+    const int gy = q % A.nby; q /= A.nby;
+    const int gz = q % A.nbz;
+    const int gt = q / A.nbz;
+    int r = vloc;
+    const int lx = r % A.bx; r /= A.bx;
+    const int ly = r % A.by; r /= A.by;
+    const int lz = r % A.bz;
+    const int lt = r / A.bz;
+    const int xh = gx * A.bx + lx, yy = gy * A.by + ly, zz = gz * A.bz + lz, tt = gt * A.bt + lt;
+    v = xh + g.Xh * (yy + g.Y * (zz + g.Z * tt));
+  } else {
+    v = wg * A.spw + vloc;
+  }
   const bool active = (vloc < A.spw) && (v < g.Vh);
 
   in += rhs * A.field;
@@ -280,7 +300,7 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
     const R m = (R)A.mass;
     for (int q = tid; q < A.spw * 12; q += blockDim.x) {
       const int vl = q / 12, c = q - vl * 12;
-      if (wg * A.spw + vl >= g.Vh) continue;
+      if (A.bx == 0 && wg * A.spw + vl >= g.Vh) continue;
       cplx<R>* row = buf + (vl * 12 + c) * ld;
       // P+ (c < 6) takes M+^-1 (lower-triangular recurrence), P- takes M-^-1;
       // the adjoint swaps the two.
@@ -474,7 +494,27 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   HopArgs A;
   A.g = g;
   A.out_parity = out_parity;
+  // at most 256 threads, and the M_5^-1 staging buffer within 64 KiB of LDS
   A.spw = g.Ls >= 256 ? 1 : 256 / g.Ls;
+  while (A.spw > 1 && (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(c128) > 65536) A.spw >>= 1;
+  A.bx = A.by = A.bz = A.bt = 0;
+  A.nbx = A.nby = A.nbz = 1;
+  A.remap = op->tune.remap;
+  {
+    const int* b = op->tune.block;
+    if (b[0] > 0 && b[0] * b[1] * b[2] * b[3] * g.Ls <= 256 &&
+        (size_t)b[0] * b[1] * b[2] * b[3] * 12 * (g.Ls + 1) * sizeof(c128) <= 65536 && g.Xh % b[0] == 0 && g.Y % b[1] == 0 &&
+        g.Z % b[2] == 0 && g.T % b[3] == 0) {
+      A.bx = b[0];
+      A.by = b[1];
+      A.bz = b[2];
+      A.bt = b[3];
+      A.spw = b[0] * b[1] * b[2] * b[3];
+      A.nbx = g.Xh / b[0];
+      A.nby = g.Y / b[1];
+      A.nbz = g.Z / b[2];
+    }
+  }
   A.field = (size_t)g.Vh * 12 * g.Ls;
   A.d = op->f5.d;
   A.mass = op->f5.mass;
@@ -494,7 +534,9 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
                      (size_t)out_parity * g.Vh * 72;
   const R* pw = reinterpret_cast<const R*>(dbl ? op->pw128.ptr : op->pw64.ptr);
   dim3 grid(nwg, nrhs), block(threads);
-  const size_t lds = epi == EPI_INV ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  size_t lds = epi == EPI_INV ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  // optional LDS request that caps the resident workgroups per CU
+  if ((size_t)op->tune.lds_kb * 1024 > lds) lds = (size_t)op->tune.lds_kb * 1024;
   if (epi == EPI_INV) {
     if (dagger)
       hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV>), grid, block, lds, stream, out, in, center, G, pw, A);

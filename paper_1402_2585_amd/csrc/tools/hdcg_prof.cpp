@@ -1,0 +1,130 @@
+// Standalone profiling driver for rocprofv3 (no Python, no torch): applies
+// M_pc^+ M_pc through the C ABI on a unit-link lattice (memory traffic does
+// not depend on the link values), or runs a plain copy kernel of known size
+// to calibrate the FETCH_SIZE / WRITE_SIZE counters.
+//
+//   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64> <reps> [nrhs]
+//   hdcg_prof copy <MiB> <reps>
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../../include/hdcg.h"
+
+#define CHECK(x)                                                              \
+  do {                                                                        \
+    hipError_t e = (x);                                                       \
+    if (e != hipSuccess) {                                                    \
+      std::fprintf(stderr, "%s: %s\n", #x, hipGetErrorString(e));             \
+      return 1;                                                               \
+    }                                                                         \
+  } while (0)
+#define ACHECK(x)                                                             \
+  do {                                                                        \
+    int r = (x);                                                              \
+    if (r < 0) {                                                              \
+      std::fprintf(stderr, "%s -> %d: %s\n", #x, r, dwf_last_error());        \
+      return 1;                                                               \
+    }                                                                         \
+  } while (0)
+
+__global__ void copy_kernel(const double4* __restrict__ x, double4* __restrict__ y, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+int main(int argc, char** argv) {
+  if (argc < 2) return 2;
+  if (!std::strcmp(argv[1], "copy")) {
+    const size_t mib = argc > 2 ? std::atol(argv[2]) : 1024;
+    const int reps = argc > 3 ? std::atoi(argv[3]) : 3;
+    const size_t n = mib * 1024 * 1024 / sizeof(double4);
+    double4 *x, *y;
+    CHECK(hipMalloc(&x, n * sizeof(double4)));
+    CHECK(hipMalloc(&y, n * sizeof(double4)));
+    CHECK(hipMemset(x, 0, n * sizeof(double4)));
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, 0, x, y, n);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    std::printf("copy %zu MiB x %d (bytes per launch read %zu write %zu)\n", mib, reps, n * 32, n * 32);
+    return 0;
+  }
+  if (!std::strcmp(argv[1], "sweep")) {
+    // hdcg_prof sweep X Y Z T Ls prec reps tile1 tile2 ...   (tile = "bx,by,bz,bt,remap")
+    int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
+    const int Ls = std::atoi(argv[6]);
+    const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : DWF_C128;
+    const int reps = std::atoi(argv[8]);
+    const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+    std::vector<double> U(V * 4 * 9 * 2, 0.0);
+    for (size_t l = 0; l < V * 4; ++l)
+      for (int a = 0; a < 3; ++a) U[(l * 9 + a * 4) * 2] = 1.0;
+    void* dU;
+    CHECK(hipMalloc(&dU, U.size() * sizeof(double)));
+    CHECK(hipMemcpy(dU, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    for (int a = 9; a < argc; ++a) {
+      setenv("HDCG_HOP_TILE", argv[a], 1);
+      dwf_op_t op;
+      ACHECK(dwf_create(&op, dims, Ls, 1.8, 0.01, dU, nullptr, nullptr));
+      size_t bytes = 0;
+      ACHECK(dwf_field_bytes(op, prec, 1, &bytes));
+      void *x, *y;
+      CHECK(hipMalloc(&x, bytes));
+      CHECK(hipMalloc(&y, bytes));
+      CHECK(hipMemset(x, 0, bytes));
+      for (int r = 0; r < 3; ++r) ACHECK(mpc_dag_mpc_apply(op, y, x, prec, 1, nullptr));
+      CHECK(hipEventRecord(e0, nullptr));
+      for (int r = 0; r < reps; ++r) ACHECK(mpc_dag_mpc_apply(op, (r & 1) ? x : y, (r & 1) ? y : x, prec, 1, nullptr));
+      CHECK(hipEventRecord(e1, nullptr));
+      CHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      CHECK(hipEventElapsedTime(&ms, e0, e1));
+      const double half = (double)V / 2 * Ls * 12, cb = prec == DWF_C64 ? 8 : 16;
+      const double by = (10 * half + 4.0 * V * 36) * cb;
+      std::printf("tile %-14s %s %dx%dx%dx%d Ls=%d  %.4f ms/H  %.1f GB/s\n", argv[a], argv[7], dims[0], dims[1],
+                  dims[2], dims[3], Ls, ms / reps, by / (ms / reps * 1e-3) / 1e9);
+      std::fflush(stdout);
+      CHECK(hipFree(x));
+      CHECK(hipFree(y));
+      ACHECK(dwf_destroy(op));
+    }
+    return 0;
+  }
+  if (argc < 9) return 2;
+  int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
+  const int Ls = std::atoi(argv[6]);
+  const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : DWF_C128;
+  const int reps = std::atoi(argv[8]);
+  const int nrhs = argc > 9 ? std::atoi(argv[9]) : 1;
+  const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
+  std::vector<double> U(V * 4 * 9 * 2, 0.0);
+  for (size_t l = 0; l < V * 4; ++l)
+    for (int a = 0; a < 3; ++a) U[(l * 9 + a * 4) * 2] = 1.0;
+  void* dU;
+  CHECK(hipMalloc(&dU, U.size() * sizeof(double)));
+  CHECK(hipMemcpy(dU, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
+  dwf_op_t op;
+  ACHECK(dwf_create(&op, dims, Ls, 1.8, 0.01, dU, nullptr, nullptr));
+  size_t bytes = 0;
+  ACHECK(dwf_field_bytes(op, prec, nrhs, &bytes));
+  void *x, *y;
+  CHECK(hipMalloc(&x, bytes));
+  CHECK(hipMalloc(&y, bytes));
+  std::vector<unsigned char> h(bytes);
+  for (size_t i = 0; i < bytes; ++i) h[i] = (unsigned char)((i * 2654435761u) >> 24) & 0x3f;
+  CHECK(hipMemcpy(x, h.data(), bytes, hipMemcpyHostToDevice));
+  for (int r = 0; r < reps; ++r) {
+    ACHECK(mpc_dag_mpc_apply(op, y, x, prec, nrhs, nullptr));
+    ACHECK(mpc_dag_mpc_apply(op, x, y, prec, nrhs, nullptr));
+  }
+  CHECK(hipDeviceSynchronize());
+  ACHECK(dwf_destroy(op));
+  std::printf("H %s %dx%dx%dx%d Ls=%d nrhs=%d x %d\n", argv[7], dims[0], dims[1], dims[2], dims[3], Ls, nrhs, 2 * reps);
+  return 0;
+}

@@ -1,0 +1,72 @@
+"""Workload driver for profiler runs (rocprofv3 --kernel-trace / --pmc).
+
+  python3 -m paper_1402_2585_amd.prof_driver --what H --prec c128 --reps 5
+  python3 -m paper_1402_2585_amd.prof_driver --what copy --mib 1024 --reps 5
+
+`H` applies M_pc^+ M_pc to a seeded source on the 16^4 x Ls16 workload (or
+--dims/--Ls); `copy` runs a plain device-to-device copy kernel of known size,
+which calibrates the FETCH_SIZE / WRITE_SIZE counters (bytes reported per
+byte actually moved).
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--what", choices=["H", "copy"], default="H")
+    ap.add_argument("--prec", choices=["c128", "c64"], default="c128")
+    ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 16])
+    ap.add_argument("--Ls", type=int, default=16)
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--mib", type=int, default=1024)
+    a = ap.parse_args()
+
+    import torch
+
+    if a.what == "copy":
+        n = a.mib * 1024 * 1024 // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(a.reps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"copy {a.mib} MiB x {a.reps}", flush=True)
+        return
+
+    import synth
+
+    dims = tuple(a.dims)
+    dt = torch.complex128 if a.prec == "c128" else torch.complex64
+    # every torch operation happens before the library launches its first kernel
+    U = torch.from_numpy(synth.gauge_field(dims, 0.7, 2001)).to("cuda")
+    b = torch.from_numpy(synth.gaussian_half_field(dims, a.Ls, 2100, nrhs=a.nrhs)).to(dtype=dt).to("cuda")
+    torch.cuda.synchronize()
+    print("inputs on device", flush=True)
+
+    import paper_1402_2585_amd as hd
+
+    prec = hd.DWF_C128 if a.prec == "c128" else hd.DWF_C64
+    h = hd.dwf_create(U, dims, a.Ls, 1.8, 0.01)
+    nbytes = hd.dwf_field_bytes(h, prec, a.nrhs)
+    x = torch.empty(nbytes // b.element_size(), dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    hd.dwf_import(h, x, b, prec, a.nrhs)
+    print("operator created", flush=True)
+    for _ in range(a.reps):
+        hd.mpc_dag_mpc_apply(h, y, x, prec, a.nrhs)
+        hd.mpc_dag_mpc_apply(h, x, y, prec, a.nrhs)
+    hd.dwf_norm2(h, x, prec, a.nrhs)  # synchronises the stream
+    hd.dwf_destroy(h)
+    print(f"H {a.prec} dims={dims} Ls={a.Ls} nrhs={a.nrhs} x {2 * a.reps}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

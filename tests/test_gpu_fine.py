@@ -130,7 +130,7 @@ def test_blas_against_numpy(prec):
     f = [synth.gaussian_half_field(dims, Ls, 20 + i, nrhs=2).astype(dt) for i in range(4)]
     x, r, p, w = [op.to_native(a, prec) for a in f]
     n2 = hd.dwf_norm2(op.h, x, prec, 2)
-    want = np.array([np.vdot(f[0][i], f[0][i]).real for i in range(2)])
+    want = np.array([np.vdot(f[0][i].astype(complex), f[0][i].astype(complex)).real for i in range(2)])
     assert np.abs(n2 - want).max() <= 1e-13 * want.max()
     n2b = hd.dwf_norm2(op.h, x, prec, 2)
     assert np.array_equal(n2, n2b)  # deterministic reduction
