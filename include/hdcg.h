@@ -132,6 +132,103 @@ struct dwf_solve_stats {
 int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxiter,
              struct dwf_solve_stats* st, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Hierarchically deflated CG: blocked subspace (Sec. II), little Dirac
+ * operator (Sec. V.A.1), the A-DEF2 solver (Sec. IV.E, Table "algos").     */
+
+struct hdcg_params {
+  int n_ii;           /* inverse-iteration steps on the starting vectors (0: use as given) */
+  double lambda_ii;   /* shift of the inverse iteration: (H + lambda_ii)^-1 */
+  double tol_ii;      /* relative residual of each inverse-iteration solve (complex64 CG) */
+  int maxiter_ii;     /* iteration cap of each inverse-iteration solve */
+  int n_irs;          /* M_IRS: CG iterations on H + lambda_irs (Sec. IV.C), default 7 */
+  double lambda_irs;  /* M_IRS infra-red shift, default 1.0 */
+  double coarse_tol;  /* relative residual of the coarse CG inside Q, default 0.04 */
+  int coarse_maxiter; /* coarse CG iteration cap */
+  int flexible;       /* 1: flexible search-direction update (default), 0: standard PCG */
+  double inner_tol;   /* relative residual of each complex64 A-DEF2 inner solve, default 1e-5 */
+  int inner_maxiter;  /* inner iteration cap */
+  int outer_maxiter;  /* FP64 defect-correction restarts cap */
+  int build_batch;    /* probe vectors per H application batch in the coarse build */
+};
+
+struct hdcg_stats {
+  int outer_iterations;  /* FP64 defect-correction restarts */
+  int inner_iterations;  /* A-DEF2 iterations summed over restarts */
+  int coarse_solves;     /* applications of Q */
+  int coarse_iterations; /* coarse CG iterations summed */
+  int converged;         /* 1 if |b - H x| / |b| <= tol for every RHS */
+  int pad;
+  double true_residual;  /* max over RHS of the FP64 relative residual */
+  double seconds;        /* solve wall time (setup excluded) */
+  double setup_seconds;  /* wall time of hdcg_setup */
+  double matmuls_fp64;   /* applications of H in complex128 (per RHS summed) */
+  double matmuls_fp32;   /* applications of H in complex64 (per RHS summed) */
+};
+
+/* Fill *p with the defaults above. */
+void hdcg_default_params(struct hdcg_params* p);
+
+/* Build the two-level solver for operator `op` (Sec. II, Sec. V.A):
+ * block = {Bx, By, Bz, Bt} (each even, >= 4, dividing the lattice, with at
+ * least 3 blocks in every direction so the coarse stencil has 81 distinct
+ * points); blocks span all of s.  vectors_c128: device, nvec canonical
+ * complex128 half-fields Phi[k][s][cb][spin][colour] (the random starting
+ * vectors; the caller draws them).  The library applies p->n_ii steps of
+ * inverse iteration (complex64 CG, each vector renormalised), orthonormalises
+ * the blocked vectors block by block (Cholesky-QR applied twice in FP64:
+ * the unique QR with positive diagonal, as Gram-Schmidt gives), and computes
+ * A^{ab}_{jk} = <phi^a_j|H|phi^b_k> in FP64 with 81 phased probes per vector
+ * (the Fourier trick of Sec. V.A.1, momenta p_mu = 2 pi n m_mu / Lc_mu,
+ * m_mu = round(Lc_mu / 3)).  The handle owns the subspace, the operator and
+ * all workspaces until hdcg_destroy.  Synchronises `stream`.
+ * Errors: DWF_ERR_GEOMETRY (block shape), DWF_ERR_NUMERIC (dependent
+ * vectors on a block), DWF_ERR_OOM. */
+int hdcg_setup(hdcg_t* h, dwf_op_t op, const int block[4], int nvec, const void* vectors_c128,
+               const struct hdcg_params* p, void* stream);
+int hdcg_destroy(hdcg_t h);
+/* Coarse grid extents, number of coarse sites and of vectors (host outputs, nullable). */
+int hdcg_dims(hdcg_t h, int coarse_dims[4], int* ncoarse, int* nvec);
+
+/* c[rhs][a][k] = <phi^a_k, psi_rhs> (project, P^+) and psi = sum phi^a_k
+ * c[a][k] (promote, P), Sec. II.  Fine fields native, coarse vectors
+ * canonical, both in precision prec (C128 or C64); asynchronous. */
+int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int nrhs, void* stream);
+int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream);
+
+/* out[rhs][a][j] = sum_l sum_k A[a][l][j][k] in[rhs][a + delta_l][k]:
+ * the 81-point block stencil of the little Dirac operator (Sec. V.A);
+ * prec C128 or C64; asynchronous; out != in. */
+int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream);
+
+/* CG on A x = b (A Hermitian positive definite, Sec. V.B) from x = 0 to
+ * |r| <= tol |b| for every RHS; *iters receives the iteration count.
+ * Synchronises; DWF_NOT_CONVERGED at maxiter. */
+int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
+                      int* iters, void* stream);
+
+/* out = M_IRS in: exactly n_irs complex64 CG iterations on H + lambda_irs
+ * from zero (Sec. IV.C); native complex64 fields; asynchronous. */
+int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream);
+
+/* Copies for parity checks: the little Dirac operator in the canonical layout
+ * A[a][l][j][k] (device, Nc*81*nvec*nvec complex128), the orthonormalised
+ * subspace Phi[k][s][cb][spin][colour] (device complex128), and the block map
+ * (host int arrays of V/2 entries indexed by cb: block index, rank in block). */
+int hdcg_export_coarse(hdcg_t h, void* A_c128, void* stream);
+int hdcg_export_subspace(hdcg_t h, void* phi_c128, void* stream);
+int hdcg_export_block_map(hdcg_t h, int* block_of_site, int* index_in_block);
+
+/* Solve H x = b for nrhs right-hand sides to |b - H x| / |b| <= tol (FP64
+ * true residual).  Outer loop: FP64 defect correction r = b - H x; inner:
+ * complex64 generalised PCG with the A-DEF2 choices V_start = Q r,
+ * M_1 = P_R M_IRS + Q (applied as z - Q (H z - r), z = M_IRS r), flexible
+ * search directions (alpha = (p, r)/(p, w), beta = -(w, y)/(p, w)), to
+ * p->inner_tol.  x, b: native complex128.  Synchronises; fills *stats
+ * (nullable); DWF_NOT_CONVERGED after outer_maxiter restarts. */
+int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
+               struct hdcg_stats* stats, void* stream);
+
 const char* dwf_last_error(void);
 
 #ifdef __cplusplus

@@ -38,6 +38,24 @@ class SolveStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class HdcgParams(C.Structure):
+    _fields_ = [("n_ii", C.c_int), ("lambda_ii", C.c_double), ("tol_ii", C.c_double),
+                ("maxiter_ii", C.c_int), ("n_irs", C.c_int), ("lambda_irs", C.c_double),
+                ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("flexible", C.c_int),
+                ("inner_tol", C.c_double), ("inner_maxiter", C.c_int), ("outer_maxiter", C.c_int),
+                ("build_batch", C.c_int)]
+
+
+class HdcgStats(C.Structure):
+    _fields_ = [("outer_iterations", C.c_int), ("inner_iterations", C.c_int),
+                ("coarse_solves", C.c_int), ("coarse_iterations", C.c_int), ("converged", C.c_int),
+                ("pad", C.c_int), ("true_residual", C.c_double), ("seconds", C.c_double),
+                ("setup_seconds", C.c_double), ("matmuls_fp64", C.c_double), ("matmuls_fp32", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 _lib = None
 
 
@@ -66,6 +84,19 @@ def load():
         "dwf_xpay": (i, [vp, vp, vp, dp, i, i, vp]),
         "cg_solve": (i, [vp, vp, vp, i, d, i, C.POINTER(SolveStats), vp]),
         "dwf_last_error": (C.c_char_p, []),
+        "hdcg_default_params": (None, [C.POINTER(HdcgParams)]),
+        "hdcg_setup": (i, [C.POINTER(vp), vp, C.POINTER(C.c_int * 4), i, vp, C.POINTER(HdcgParams), vp]),
+        "hdcg_destroy": (i, [vp]),
+        "hdcg_dims": (i, [vp, C.POINTER(C.c_int * 4), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "hdcg_project": (i, [vp, vp, vp, i, i, vp]),
+        "hdcg_promote": (i, [vp, vp, vp, i, i, vp]),
+        "coarse_apply": (i, [vp, vp, vp, i, i, vp]),
+        "hdcg_coarse_solve": (i, [vp, vp, vp, i, i, d, i, C.POINTER(C.c_int), vp]),
+        "hdcg_mirs": (i, [vp, vp, vp, i, vp]),
+        "hdcg_export_coarse": (i, [vp, vp, vp]),
+        "hdcg_export_subspace": (i, [vp, vp, vp]),
+        "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "hdcg_solve": (i, [vp, vp, vp, i, d, C.POINTER(HdcgStats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -179,3 +210,78 @@ def cg_solve(op, x, b, nrhs=1, tol=1e-8, maxiter=100000, stream=None):
 
 def dwf_last_error():
     return load().dwf_last_error().decode()
+
+
+# ------------------------------------------------------------------- HDCG --
+def hdcg_default_params(**overrides):
+    p = HdcgParams()
+    load().hdcg_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def hdcg_setup(op, block, nvec, vectors, params=None, stream=None):
+    h = C.c_void_p()
+    b = (C.c_int * 4)(*[int(x) for x in block])
+    p = params if params is not None else hdcg_default_params()
+    _check(load().hdcg_setup(C.byref(h), op, C.byref(b), int(nvec), _ptr(vectors), C.byref(p), _stream(stream)))
+    return h
+
+
+def hdcg_destroy(h):
+    _check(load().hdcg_destroy(h))
+
+
+def hdcg_dims(h):
+    c = (C.c_int * 4)()
+    nc, nv = C.c_int(), C.c_int()
+    _check(load().hdcg_dims(h, C.byref(c), C.byref(nc), C.byref(nv)))
+    return tuple(c[:]), nc.value, nv.value
+
+
+def hdcg_project(h, coarse_out, fine_in, prec, nrhs=1, stream=None):
+    _check(load().hdcg_project(h, _ptr(coarse_out), _ptr(fine_in), int(prec), int(nrhs), _stream(stream)))
+
+
+def hdcg_promote(h, fine_out, coarse_in, prec, nrhs=1, stream=None):
+    _check(load().hdcg_promote(h, _ptr(fine_out), _ptr(coarse_in), int(prec), int(nrhs), _stream(stream)))
+
+
+def coarse_apply(h, out, inp, prec, nrhs=1, stream=None):
+    _check(load().coarse_apply(h, _ptr(out), _ptr(inp), int(prec), int(nrhs), _stream(stream)))
+
+
+def hdcg_coarse_solve(h, x, b, prec, nrhs=1, tol=1e-8, maxiter=10000, stream=None):
+    it = C.c_int()
+    rc = _check(load().hdcg_coarse_solve(h, _ptr(x), _ptr(b), int(prec), int(nrhs), float(tol), int(maxiter),
+                                         C.byref(it), _stream(stream)), allow_soft=True)
+    return rc, it.value
+
+
+def hdcg_mirs(h, out, inp, nrhs=1, stream=None):
+    _check(load().hdcg_mirs(h, _ptr(out), _ptr(inp), int(nrhs), _stream(stream)))
+
+
+def hdcg_export_coarse(h, out, stream=None):
+    _check(load().hdcg_export_coarse(h, _ptr(out), _stream(stream)))
+
+
+def hdcg_export_subspace(h, out, stream=None):
+    _check(load().hdcg_export_subspace(h, _ptr(out), _stream(stream)))
+
+
+def hdcg_export_block_map(h, vh):
+    a = (C.c_int * vh)()
+    j = (C.c_int * vh)()
+    _check(load().hdcg_export_block_map(h, a, j))
+    return np.array(a[:]), np.array(j[:])
+
+
+def hdcg_solve(h, x, b, nrhs=1, tol=1e-8, stream=None):
+    st = HdcgStats()
+    rc = _check(load().hdcg_solve(h, _ptr(x), _ptr(b), int(nrhs), float(tol), C.byref(st), _stream(stream)),
+                allow_soft=True)
+    return rc, st.as_dict()

@@ -1,0 +1,249 @@
+// BLAS-1 kernels with device-resident coefficients and FP64 reductions.
+#include "blas.h"
+
+namespace hdk {
+
+namespace {
+
+constexpr int kT = 256;
+
+inline int nblocks(size_t n) {
+  size_t b = (n + kT * 8 - 1) / (kT * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+template <typename R>
+__device__ __forceinline__ double nrm(cplx<R> a) {
+  return (double)a.re * a.re + (double)a.im * a.im;
+}
+
+__device__ __forceinline__ void coef(const double* num, bool cnum, const double* den,
+                                     const double* den2, double lam, int rhs, double& re,
+                                     double& im, int dstr) {
+  double d = den[rhs * dstr];
+  if (den2) d += lam * den2[rhs];
+  if (d == 0.0) {
+    re = im = 0.0;
+    return;
+  }
+  if (cnum) {
+    re = num[2 * rhs] / d;
+    im = num[2 * rhs + 1] / d;
+  } else {
+    re = num[rhs] / d;
+    im = 0.0;
+  }
+}
+
+template <int NQ>
+__device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, double* res) {
+  __shared__ double lds[NQ * 16];
+  block_sum<NQ>(v, lds);
+  finish_reduction<NQ>(v, red.partials + (size_t)rhs * kMaxPartials, kMaxPartials / NQ,
+                       blockIdx.x, red.counters + rhs, res + NQ * rhs, gridDim.x);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kT) k_norm2(const cplx<R>* __restrict__ x, size_t n, Red red,
+                                              double* res) {
+  const int rhs = blockIdx.y;
+  x += rhs * n;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+    acc += nrm(x[i]);
+  double v[1] = {acc};
+  reduce_out<1>(v, red, rhs, res);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kT) k_dot(const cplx<R>* __restrict__ a,
+                                            const cplx<R>* __restrict__ b, size_t n, Red red,
+                                            double* res) {
+  const int rhs = blockIdx.y;
+  a += rhs * n;
+  b += rhs * n;
+  double re = 0.0, im = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+    const cplx<R> x = a[i], y = b[i];
+    re += (double)x.re * y.re + (double)x.im * y.im;
+    im += (double)x.re * y.im - (double)x.im * y.re;
+  }
+  double v[2] = {re, im};
+  reduce_out<2>(v, red, rhs, res);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kT)
+k_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+         const cplx<R>* __restrict__ w, size_t n, const double* num, bool cnum, const double* den,
+         const double* den2, double lam, Red red, double* rr, int dstr) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * n;
+  double are, aim;
+  coef(num, cnum, den, den2, lam, rhs, are, aim, dstr);
+  const cplx<R> a = cmk((R)are, (R)aim);
+  const R l = (R)lam;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+    const cplx<R> pi = p[off + i];
+    cplx<R> wi = w[off + i];
+    if (den2) wi = wi + l * pi;
+    x[off + i] = x[off + i] + a * pi;
+    const cplx<R> ri = r[off + i] - a * wi;
+    r[off + i] = ri;
+    acc += nrm(ri);
+  }
+  if (rr) {
+    double v[1] = {acc};
+    reduce_out<1>(v, red, rhs, rr);
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kT)
+k_xpay(cplx<R>* __restrict__ p, const cplx<R>* __restrict__ y, size_t n, const double* num,
+       bool cnum, const double* den, double sign, Red red, double* pp, int dstr) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * n;
+  double bre, bim;
+  coef(num, cnum, den, nullptr, 0.0, rhs, bre, bim, dstr);
+  const cplx<R> b = cmk((R)(sign * bre), (R)(sign * bim));
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+    const cplx<R> v = y[off + i] + b * p[off + i];
+    p[off + i] = v;
+    acc += nrm(v);
+  }
+  if (pp) {
+    double v[1] = {acc};
+    reduce_out<1>(v, red, rhs, pp);
+  }
+}
+
+template <typename R>
+__global__ void k_axpby(cplx<R>* __restrict__ y, const cplx<R>* __restrict__ x, R a, R b,
+                        size_t total) {
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT)
+    y[i] = a * x[i] + b * y[i];
+}
+
+template <typename Ry, typename Rx>
+__global__ void k_axpy_mixed(cplx<Ry>* __restrict__ y, const cplx<Rx>* __restrict__ x,
+                             const double* s, size_t n, bool sqrt_s) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * n;
+  const Ry f = s ? (Ry)(sqrt_s ? sqrt(s[rhs]) : s[rhs]) : (Ry)1;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+    const cplx<Rx> v = x[off + i];
+    y[off + i] = y[off + i] + f * cmk((Ry)v.re, (Ry)v.im);
+  }
+}
+
+template <typename Ry, typename Rx>
+__global__ void k_scale_copy(cplx<Ry>* __restrict__ y, const cplx<Rx>* __restrict__ x,
+                             const double* v, bool invsqrt, size_t n) {
+  const int rhs = blockIdx.y;
+  const size_t off = rhs * n;
+  double s = v ? v[rhs] : 1.0;
+  if (invsqrt) s = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+    const cplx<Rx> a = x[off + i];
+    y[off + i] = cmk((Ry)(s * a.re), (Ry)(s * a.im));
+  }
+}
+
+template <typename R>
+__global__ void k_zero(cplx<R>* __restrict__ y, size_t total) {
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT)
+    y[i] = cmk((R)0, (R)0);
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK() HDCG_HIP(hipGetLastError())
+
+template <typename R>
+int b_norm2(Red red, const cplx<R>* x, size_t n, int nrhs, double* res, hipStream_t st) {
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_norm2<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, n, red, res);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename R>
+int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, double* res,
+          hipStream_t st) {
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_dot<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, a, b, n, red, res);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename R>
+int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w, size_t n,
+             int nrhs, const double* num, bool cnum, const double* den, const double* den2,
+             double lam, double* rr, hipStream_t st, int dstr) {
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_update<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
+                     cnum, den, den2, lam, red, rr, dstr);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename R>
+int b_xpay(Red red, cplx<R>* p, const cplx<R>* y, size_t n, int nrhs, const double* num, bool cnum,
+           const double* den, double sign, double* pp, hipStream_t st, int dstr) {
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_xpay<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, p, y, n, num, cnum, den,
+                     sign, red, pp, dstr);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename R>
+int b_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, size_t total, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpby<R>), dim3(nblocks(total)), dim3(kT), 0, st, y, x, (R)a, (R)b, total);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename Ry, typename Rx>
+int b_axpy_mixed(cplx<Ry>* y, const cplx<Rx>* x, const double* s, size_t n, int nrhs,
+                 hipStream_t st, bool sqrt_s) {
+  hipLaunchKernelGGL((k_axpy_mixed<Ry, Rx>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, y, x, s, n, sqrt_s);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename Ry, typename Rx>
+int b_scale_copy(cplx<Ry>* y, const cplx<Rx>* x, const double* v, bool invsqrt, size_t n, int nrhs,
+                 hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_copy<Ry, Rx>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, y, x, v,
+                     invsqrt, n);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+template <typename R>
+int b_zero(cplx<R>* y, size_t total, hipStream_t st) {
+  hipLaunchKernelGGL((k_zero<R>), dim3(nblocks(total)), dim3(kT), 0, st, y, total);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+
+#define INST(R)                                                                                   \
+  template int b_norm2<R>(Red, const cplx<R>*, size_t, int, double*, hipStream_t);               \
+  template int b_dot<R>(Red, const cplx<R>*, const cplx<R>*, size_t, int, double*, hipStream_t); \
+  template int b_update<R>(Red, cplx<R>*, cplx<R>*, const cplx<R>*, const cplx<R>*, size_t, int, \
+                           const double*, bool, const double*, const double*, double, double*,   \
+                           hipStream_t, int);                                                     \
+  template int b_xpay<R>(Red, cplx<R>*, const cplx<R>*, size_t, int, const double*, bool,        \
+                         const double*, double, double*, hipStream_t, int);                       \
+  template int b_axpby<R>(cplx<R>*, const cplx<R>*, double, double, size_t, hipStream_t);        \
+  template int b_zero<R>(cplx<R>*, size_t, hipStream_t);
+INST(double)
+INST(float)
+template int b_axpy_mixed<double, float>(cplx<double>*, const cplx<float>*, const double*, size_t, int, hipStream_t, bool);
+template int b_axpy_mixed<double, double>(cplx<double>*, const cplx<double>*, const double*, size_t, int, hipStream_t, bool);
+template int b_axpy_mixed<float, float>(cplx<float>*, const cplx<float>*, const double*, size_t, int, hipStream_t, bool);
+template int b_scale_copy<float, double>(cplx<float>*, const cplx<double>*, const double*, bool, size_t, int, hipStream_t);
+template int b_scale_copy<double, float>(cplx<double>*, const cplx<float>*, const double*, bool, size_t, int, hipStream_t);
+template int b_scale_copy<double, double>(cplx<double>*, const cplx<double>*, const double*, bool, size_t, int, hipStream_t);
+template int b_scale_copy<float, float>(cplx<float>*, const cplx<float>*, const double*, bool, size_t, int, hipStream_t);
+
+}  // namespace hdk

@@ -22,18 +22,18 @@ struct Status {
   bool ok() const { return code == DWF_OK; }
 };
 
-#define HDCG_HIP(call)                                                        \
-  do {                                                                        \
-    hipError_t e_ = (call);                                                   \
-    if (e_ != hipSuccess) {                                                   \
-      ::hdk::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
-      return DWF_ERR_HIP;                                                     \
-    }                                                                         \
+#define HDCG_HIP(...)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (__VA_ARGS__);                                               \
+    if (e_ != hipSuccess) {                                                      \
+      ::hdk::set_error(std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_)); \
+      return DWF_ERR_HIP;                                                        \
+    }                                                                            \
   } while (0)
 
-#define HDCG_TRY(expr)                 \
+#define HDCG_TRY(...)                  \
   do {                                 \
-    int s_ = (expr);                   \
+    int s_ = (__VA_ARGS__);            \
     if (s_ < 0) return s_;             \
   } while (0)
 

@@ -1,0 +1,82 @@
+// HDCG handle: blocked subspace, little Dirac operator and solver state.
+//
+// Blocks are 4D (B_mu sites, every B_mu even and >= 4) and span all of s
+// (Sec. V.A).  Odd site j of block a (j = rank by checkerboard index) has
+// the native fine-field column site_of[a][j]; a block vector is stored as
+// phi[a][k][j][c][s] (block-major: the Nvec vectors of one block are one
+// contiguous (Nvec x n_b) panel, n_b = nsb * 12 * Ls).
+//
+// Coarse vectors: c[rhs][a][k].  Little Dirac operator: A128 is the
+// canonical A[a][l][j][k] (complex128); AT64 is the complex64 copy stored
+// transposed per stencil point, AT[a][l][k][j], so the mat-vec reads it with
+// consecutive threads on consecutive j.
+#pragma once
+
+#include "blas.h"
+#include "fine_op.h"
+
+constexpr int kStencil = 81;
+
+struct hdcg {
+  dwf_op* op = nullptr;
+  int B[4] = {0, 0, 0, 0};
+  int C[4] = {0, 0, 0, 0};
+  int Nc = 0, nsb = 0, nvec = 0;
+  size_t nb = 0;  // complex per block vector
+  hdk::DevBuf site_of;        // int [Nc][nsb]
+  hdk::DevBuf nbr;            // int [Nc][81]
+  hdk::DevBuf phi128, phi64;  // [Nc][nvec][nb]
+  hdk::DevBuf A128;           // [Nc][81][nvec][nvec]
+  hdk::DevBuf AT64;           // [Nc][81][nvec][nvec] transposed per l
+  hdk::DevBuf AT128;          // same layout in complex128 (parity / FP64 use)
+  hdk::DevBuf gram, rinv;     // [Nc][nvec][nvec] c128 Cholesky-QR work
+  hdk::DevBuf flag;           // int error flag
+  hdk::DevBuf cw[6];          // coarse work vectors (c64/c128)
+  hdk::DevBuf fw64[8];        // fine c64 work fields
+  hdk::DevBuf fw128[3];       // fine c128 work fields
+  hdk::DevBuf scal;           // device scalars
+  hdk::DevBuf probe_c;        // coarse probe vectors for the build
+  double* pinned = nullptr;   // host pinned scalars
+  struct {
+    int n_ii = 0;
+    double lambda_ii = 0.0, tol_ii = 1e-4;
+    int maxiter_ii = 500;
+    int n_irs = 7;
+    double lambda_irs = 1.0;
+    double coarse_tol = 0.04;
+    int coarse_maxiter = 2000;
+    int flexible = 1;
+    double inner_tol = 1e-5;
+    int inner_maxiter = 500;
+    int outer_maxiter = 50;
+    int build_batch = 8;
+  } prm;
+  double setup_seconds = 0.0;
+  long long setup_matmuls = 0;
+};
+
+namespace hdk {
+
+// kernels (hdcg_kernels.hip)
+int blk_build_maps(hdcg* h, hipStream_t st);
+template <typename R>
+int blk_phi_layout(hdcg* h, cplx<R>* phi_native, const cplx<double>* canonical, bool to_native,
+                   int kcount, hipStream_t st);
+// out[r*sr + a*sa + k*sk] (+ph[a] factor) = sum_i conj(P[a][k][i]) * Q(r, a, i)
+// Q from a native fine field set (fine != nullptr, nr fields, field stride fstride) or a
+// block-major panel (blockq: [a][nr][nb]).
+template <typename R>
+int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride,
+            const cplx<R>* blockq, int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk,
+            const cplx<double>* phase, hipStream_t st);
+// fine_out[r] = (base ? base[r] : 0) + sign * sum_k P[a][k][i] c[r][a][k]
+template <typename R>
+int blk_promote(hdcg* h, const cplx<R>* P, const cplx<R>* c, int nr, cplx<R>* fine_out,
+                const cplx<R>* base, double sign, size_t fstride, hipStream_t st);
+int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
+template <typename R>
+int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);
+int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_t st);
+int crs_transpose(hdcg* h, hipStream_t st);  // A128 -> AT128, AT64
+
+}  // namespace hdk

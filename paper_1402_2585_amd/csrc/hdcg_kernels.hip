@@ -1,0 +1,470 @@
+// Kernels of the blocked subspace and the little Dirac operator:
+//   block map (integer index tables), subspace layout, batched block inner
+//   products (project, Gram matrices), promote, Cholesky-QR
+//   orthonormalisation, the per-dimension inverse of the 81-point phase
+//   matrix, and the complex64/complex128 coarse block-stencil mat-vec.
+#include "hdcg_impl.h"
+
+namespace hdk {
+
+namespace {
+
+constexpr int kT = 256;
+
+__global__ void k_blockmap(int* __restrict__ site_of, Geom g, int4 B, int4 C, int nsb, int total) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int a = idx / nsb, j = idx - (idx / nsb) * nsb;
+  int r = a;
+  const int cx = r % C.x;
+  r /= C.x;
+  const int cy = r % C.y;
+  r /= C.y;
+  const int cz = r % C.z;
+  const int ct = r / C.z;
+  // odd site j of the block: one of the local lexicographic pair (2j, 2j+1)
+  int L = 2 * j;
+  const int lx0 = L % B.x;
+  L /= B.x;
+  const int ly = L % B.y;
+  L /= B.y;
+  const int lz = L % B.z;
+  const int lt = L / B.z;
+  const int x0 = cx * B.x + lx0, y = cy * B.y + ly, z = cz * B.z + lz, t = ct * B.w + lt;
+  const int x = x0 + ((x0 + y + z + t + 1) & 1);
+  const long lex = x + (long)g.X * (y + (long)g.Y * (z + (long)g.Z * t));
+  site_of[idx] = (int)(lex >> 1);
+}
+
+__global__ void k_nbr(int* __restrict__ nbr, int4 C, int Nc) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Nc * kStencil) return;
+  const int a = idx / kStencil, l = idx % kStencil;
+  const int Cd[4] = {C.x, C.y, C.z, C.w};
+  int c[4];
+  int r = a;
+  for (int mu = 0; mu < 4; ++mu) {
+    c[mu] = r % Cd[mu];
+    r /= Cd[mu];
+  }
+  int q = l;
+  for (int mu = 0; mu < 4; ++mu) {
+    const int d = q % 3 - 1;
+    q /= 3;
+    c[mu] = (c[mu] + d + Cd[mu]) % Cd[mu];
+  }
+  nbr[idx] = c[0] + C.x * (c[1] + C.y * (c[2] + C.z * c[3]));
+}
+
+template <typename R>
+__global__ void k_phi_layout(cplx<R>* __restrict__ phi, const cplx<double>* __restrict__ can,
+                             const int* __restrict__ site_of, int nsb, int Ls, int Vh, int nvec,
+                             size_t nb, size_t total, bool to_native) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const size_t panel = (size_t)nvec * nb;
+  const size_t a = e / panel, rem = e - a * panel;
+  const size_t k = rem / nb, i = rem - k * nb;
+  const int col = 12 * Ls;
+  const int j = (int)(i / col), q = (int)(i - (size_t)j * col);
+  const int c = q / Ls, s = q - (q / Ls) * Ls;
+  const size_t cb = (size_t)site_of[a * nsb + j];
+  const size_t ci = ((k * Ls + s) * (size_t)Vh + cb) * 12 + c;
+  if (to_native) {
+    const cplx<double> v = can[ci];
+    phi[e] = cmk((R)v.re, (R)v.im);
+  } else {
+    const cplx<R> v = phi[e];
+    const_cast<cplx<double>*>(can)[ci] = cmk((double)v.re, (double)v.im);
+  }
+}
+
+// out[r*sr + a*sa + k*sk] = ph[a] * sum_i conj(P[a][k][i]) Q(r, a, i)
+template <typename R, bool FINE>
+__global__ void __launch_bounds__(kT)
+k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
+         const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
+         cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk,
+         const cplx<double>* __restrict__ phase) {
+  __shared__ cplx<R> Ps[16][33];
+  __shared__ cplx<R> Qs[32][17];
+  const int a = blockIdx.x, k0 = blockIdx.y * 16, r0 = blockIdx.z * 16;
+  const int t = threadIdx.x, tk = t >> 4, tr = t & 15;
+  cplx<R> acc = cmk((R)0, (R)0);
+  const cplx<R>* Pa = P + (size_t)a * nvec * nb;
+  for (size_t i0 = 0; i0 < nb; i0 += 32) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = t + h * kT;
+      const int kk = e >> 5, ii = e & 31;
+      const int k = k0 + kk;
+      cplx<R> v = cmk((R)0, (R)0);
+      if (k < nvec) v = conj(Pa[(size_t)k * nb + i0 + ii]);
+      Ps[kk][ii] = v;
+      const int rr = e >> 5;  // 0..15
+      const int r = r0 + rr;
+      cplx<R> q = cmk((R)0, (R)0);
+      if (r < nr) {
+        const size_t i = i0 + ii;
+        if (FINE) {
+          const int j = (int)(i / col), qq = (int)(i - (size_t)j * col);
+          q = Q[r * fstride + (size_t)site_of[(size_t)a * nsb + j] * col + qq];
+        } else {
+          q = Q[((size_t)a * nr + r) * nb + i];
+        }
+      }
+      Qs[ii][rr] = q;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int ii = 0; ii < 32; ++ii) cmac(acc, Ps[tk][ii], Qs[ii][tr]);
+    __syncthreads();
+  }
+  const int k = k0 + tk, r = r0 + tr;
+  if (k < nvec && r < nr) {
+    if (phase) {
+      const cplx<double> ph = phase[a];
+      acc = cmk((R)(ph.re * acc.re - ph.im * acc.im), (R)(ph.re * acc.im + ph.im * acc.re));
+    }
+    out[r * sr + a * sa + k * sk] = acc;
+  }
+}
+
+// fine_out[r][site(a, i)] = base + sign * sum_k P[a][k][i] c[r][a][k]
+template <typename R, int NR>
+__global__ void __launch_bounds__(kT)
+k_promote(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int Nc, int nvec,
+          size_t nb, int nsb, int col, const int* __restrict__ site_of, cplx<R>* __restrict__ out,
+          const cplx<R>* __restrict__ base, R sign, size_t fstride) {
+  __shared__ cplx<R> cs[NR * 64];
+  const int a = blockIdx.y;
+  const size_t i = (size_t)blockIdx.x * kT + threadIdx.x;
+  for (int e = threadIdx.x; e < nr * nvec; e += kT)
+    cs[e] = c[((size_t)(e / nvec) * Nc + a) * nvec + e % nvec];
+  __syncthreads();
+  if (i >= nb) return;
+  cplx<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
+  const cplx<R>* Pa = P + (size_t)a * nvec * nb + i;
+  for (int k = 0; k < nvec; ++k) {
+    const cplx<R> pv = Pa[(size_t)k * nb];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) cmac(acc[r], pv, cs[r * nvec + k]);
+  }
+  const int j = (int)(i / col), q = (int)(i - (size_t)j * col);
+  const size_t addr = (size_t)site_of[(size_t)a * nsb + j] * col + q;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r < nr) {
+      cplx<R> o = sign * acc[r];
+      if (base) o = base[r * fstride + addr] + o;
+      out[r * fstride + addr] = o;
+    }
+  }
+}
+
+// Cholesky G = R^+ R (R upper, positive diagonal) of one block's Gram
+// matrix, then X = R^-1; one workgroup per block, thread m owns column m.
+__global__ void __launch_bounds__(64)
+k_chol_inv(const c128* __restrict__ G, c128* __restrict__ X, int nvec, int* flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* S = reinterpret_cast<c128*>(smem);  // [nvec][nvec], upper triangle used
+  const int a = blockIdx.x, m = threadIdx.x;
+  const size_t off = (size_t)a * nvec * nvec;
+  for (int e = m; e < nvec * nvec; e += blockDim.x) S[e] = G[off + e];
+  __syncthreads();
+  for (int k = 0; k < nvec; ++k) {
+    if (m == 0) {
+      const double d = S[k * nvec + k].re;
+      if (!(d > 0.0)) {
+        atomicExch(flag, 1);
+        S[k * nvec + k] = cmk(1.0, 0.0);
+      } else {
+        S[k * nvec + k] = cmk(sqrt(d), 0.0);
+      }
+    }
+    __syncthreads();
+    const double rkk = S[k * nvec + k].re;
+    if (m > k && m < nvec) S[k * nvec + m] = (1.0 / rkk) * S[k * nvec + m];
+    __syncthreads();
+    if (m > k && m < nvec) {
+      const c128 rkm = S[k * nvec + m];
+      for (int i = k + 1; i <= m; ++i) {
+        const c128 rki = S[k * nvec + i];
+        c128 v = S[i * nvec + m];
+        v.re -= rki.re * rkm.re + rki.im * rkm.im;  // conj(R[k][i]) R[k][m]
+        v.im -= rki.re * rkm.im - rki.im * rkm.re;
+        S[i * nvec + m] = v;
+      }
+    }
+    __syncthreads();
+  }
+  // column m of X = R^-1 by back substitution
+  if (m < nvec) {
+    c128* Xa = X + off;
+    for (int i = m + 1; i < nvec; ++i) Xa[i * nvec + m] = cmk(0.0, 0.0);
+    c128 xm = cmk(1.0 / S[m * nvec + m].re, 0.0);
+    Xa[m * nvec + m] = xm;
+    for (int i = m - 1; i >= 0; --i) {
+      c128 s = cmk(0.0, 0.0);
+      for (int j = i + 1; j <= m; ++j) cmac(s, S[i * nvec + j], Xa[j * nvec + m]);
+      Xa[i * nvec + m] = (-1.0 / S[i * nvec + i].re) * s;
+    }
+  }
+}
+
+// phi[a][k][i] <- sum_{j <= k} phi[a][j][i] X[j][k]
+__global__ void __launch_bounds__(kT)
+k_gs_apply(c128* __restrict__ phi, const c128* __restrict__ X, int nvec, size_t nb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  c128* S = reinterpret_cast<c128*>(smem);  // [nvec][32]
+  const int a = blockIdx.y;
+  const size_t i0 = (size_t)blockIdx.x * 32;
+  const int ii = threadIdx.x & 31, kg = threadIdx.x >> 5;
+  c128* Pa = phi + (size_t)a * nvec * nb;
+  const c128* Xa = X + (size_t)a * nvec * nvec;
+  for (int e = threadIdx.x; e < nvec * 32; e += kT) {
+    const int j = e >> 5, q = e & 31;
+    S[j * 32 + q] = (i0 + q < nb) ? Pa[(size_t)j * nb + i0 + q] : cmk(0.0, 0.0);
+  }
+  __syncthreads();
+  c128 res[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = kg + 8 * u;
+    c128 acc = cmk(0.0, 0.0);
+    if (k < nvec)
+      for (int j = 0; j <= k; ++j) cmac(acc, S[j * 32 + ii], Xa[j * nvec + k]);
+    res[u] = acc;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int k = kg + 8 * u;
+    if (k < nvec && i0 + ii < nb) Pa[(size_t)k * nb + i0 + ii] = res[u];
+  }
+}
+
+__global__ void k_idft_dim(c128* __restrict__ Y, int nvec2, int Nc, int mu, c128 f00, c128 f01,
+                           c128 f02, c128 f10, c128 f11, c128 f12, c128 f20, c128 f21, c128 f22) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)Nc * 27 * nvec2;
+  if (idx >= total) return;
+  const int jk = (int)(idx % nvec2);
+  const int o = (int)((idx / nvec2) % 27);
+  const size_t a = idx / ((size_t)nvec2 * 27);
+  int d[4];
+  int q = o;
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) {
+      d[nu] = 0;
+      continue;
+    }
+    d[nu] = q % 3;
+    q /= 3;
+  }
+  int stride = 1;
+  for (int nu = 0; nu < mu; ++nu) stride *= 3;
+  const int l0 = d[0] + 3 * (d[1] + 3 * (d[2] + 3 * d[3]));
+  c128* base = Y + (a * kStencil) * nvec2 + jk;
+  const c128 y0 = base[(size_t)(l0)*nvec2];
+  const c128 y1 = base[(size_t)(l0 + stride) * nvec2];
+  const c128 y2 = base[(size_t)(l0 + 2 * stride) * nvec2];
+  c128 r0 = f00 * y0, r1 = f10 * y0, r2 = f20 * y0;
+  cmac(r0, f01, y1);
+  cmac(r0, f02, y2);
+  cmac(r1, f11, y1);
+  cmac(r1, f12, y2);
+  cmac(r2, f21, y1);
+  cmac(r2, f22, y2);
+  base[(size_t)(l0)*nvec2] = r0;
+  base[(size_t)(l0 + stride) * nvec2] = r1;
+  base[(size_t)(l0 + 2 * stride) * nvec2] = r2;
+}
+
+__global__ void k_transpose(const c128* __restrict__ A, c128* __restrict__ AT128,
+                            c64* __restrict__ AT64, int nvec, size_t total) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const size_t n2 = (size_t)nvec * nvec;
+  const size_t al = e / n2;
+  const int jk = (int)(e - al * n2);
+  const int j = jk / nvec, k = jk - j * nvec;
+  const c128 v = A[e];
+  const size_t o = al * n2 + (size_t)k * nvec + j;
+  AT128[o] = v;
+  AT64[o] = cmk((float)v.re, (float)v.im);
+}
+
+// (A c)[r][a][j] = sum_l sum_k A[a][l][j][k] c[r][nbr(a,l)][k], with AT[a][l][k][j].
+template <typename R, int NR>
+__global__ void __launch_bounds__(kT)
+k_capply(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr, const cplx<R>* __restrict__ in,
+         cplx<R>* __restrict__ out, int Nc, int nvec, int nr) {
+  __shared__ cplx<R> red[kT * NR];
+  const int a = blockIdx.x, r0 = blockIdx.y * NR;
+  const int parts = kT / nvec;
+  const int j = threadIdx.x % nvec, part = threadIdx.x / nvec;
+  cplx<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
+  if (part < parts) {
+    const cplx<R>* Aa = AT + (size_t)a * kStencil * nvec * nvec + j;
+    const int* nb = nbr + (size_t)a * kStencil;
+    for (int q = part; q < kStencil * nvec; q += parts) {
+      const int l = q / nvec, k = q - (q / nvec) * nvec;
+      const cplx<R> Av = Aa[(size_t)q * nvec];
+      const size_t vo = (size_t)nb[l] * nvec + k;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r0 + r < nr) cmac(acc[r], Av, in[(size_t)(r0 + r) * Nc * nvec + vo]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r * kT + threadIdx.x] = acc[r];
+  __syncthreads();
+  if (threadIdx.x < nvec) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r0 + r >= nr) continue;
+      cplx<R> s = cmk((R)0, (R)0);
+      for (int p = 0; p < parts; ++p) s = s + red[r * kT + p * nvec + threadIdx.x];
+      out[((size_t)(r0 + r) * Nc + a) * nvec + threadIdx.x] = s;
+    }
+  }
+}
+
+}  // namespace
+
+// ================================================================= host ===
+int blk_build_maps(hdcg* h, hipStream_t st) {
+  const Geom& g = h->op->g;
+  HDCG_TRY(h->site_of.ensure(sizeof(int) * (size_t)h->Nc * h->nsb));
+  HDCG_TRY(h->nbr.ensure(sizeof(int) * (size_t)h->Nc * kStencil));
+  const int total = h->Nc * h->nsb;
+  hipLaunchKernelGGL(k_blockmap, dim3((total + 255) / 256), dim3(256), 0, st, h->site_of.as<int>(), g,
+                     make_int4(h->B[0], h->B[1], h->B[2], h->B[3]),
+                     make_int4(h->C[0], h->C[1], h->C[2], h->C[3]), h->nsb, total);
+  HDCG_HIP(hipGetLastError());
+  const int tn = h->Nc * kStencil;
+  hipLaunchKernelGGL(k_nbr, dim3((tn + 255) / 256), dim3(256), 0, st, h->nbr.as<int>(),
+                     make_int4(h->C[0], h->C[1], h->C[2], h->C[3]), h->Nc);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int blk_phi_layout(hdcg* h, cplx<R>* phi, const cplx<double>* can, bool to_native, int,
+                   hipStream_t st) {
+  const size_t total = (size_t)h->Nc * h->nvec * h->nb;
+  hipLaunchKernelGGL((k_phi_layout<R>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, phi,
+                     can, h->site_of.as<int>(), h->nsb, h->op->g.Ls, h->op->g.Vh, h->nvec, h->nb,
+                     total, to_native);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
+            int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
+            hipStream_t st) {
+  dim3 grid(h->Nc, (h->nvec + 15) / 16, (nr + 15) / 16);
+  const int col = 12 * h->op->g.Ls;
+  if (fine)
+    hipLaunchKernelGGL((k_blkdot<R, true>), grid, dim3(kT), 0, st, P, fine, fstride,
+                       h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
+  else
+    hipLaunchKernelGGL((k_blkdot<R, false>), grid, dim3(kT), 0, st, P, blockq, (size_t)0,
+                       h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int blk_promote(hdcg* h, const cplx<R>* P, const cplx<R>* c, int nr, cplx<R>* out,
+                const cplx<R>* base, double sign, size_t fstride, hipStream_t st) {
+  if (nr < 1 || h->nvec > 64) return fail(DWF_ERR_ARG, "promote: bad nr / nvec");
+  const int col = 12 * h->op->g.Ls;
+  for (int r0 = 0; r0 < nr; r0 += 16) {
+    const int n = nr - r0 < 16 ? nr - r0 : 16;
+    dim3 grid((unsigned)((h->nb + kT - 1) / kT), h->Nc);
+    const cplx<R>* cc = c + (size_t)r0 * h->Nc * h->nvec;
+    cplx<R>* o = out + (size_t)r0 * fstride;
+    const cplx<R>* b = base ? base + (size_t)r0 * fstride : nullptr;
+    if (n <= 1)
+      hipLaunchKernelGGL((k_promote<R, 1>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+    else if (n <= 4)
+      hipLaunchKernelGGL((k_promote<R, 4>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+    else
+      hipLaunchKernelGGL((k_promote<R, 16>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+    HDCG_HIP(hipGetLastError());
+  }
+  return DWF_OK;
+}
+
+int blk_cholqr_step(hdcg* h, hipStream_t st) {
+  const int n = h->nvec;
+  const size_t n2 = (size_t)n * n;
+  HDCG_TRY(h->gram.ensure(sizeof(c128) * h->Nc * n2));
+  HDCG_TRY(h->rinv.ensure(sizeof(c128) * h->Nc * n2));
+  c128* phi = h->phi128.as<c128>();
+  // G[a][k'][k] = <phi_k', phi_k> on block a
+  HDCG_TRY(blk_dot<double>(h, phi, nullptr, 0, phi, n, h->gram.as<c128>(), 1, n2, n, nullptr, st));
+  hipLaunchKernelGGL(k_chol_inv, dim3(h->Nc), dim3(64), n2 * sizeof(c128), st, h->gram.as<c128>(),
+                     h->rinv.as<c128>(), n, h->flag.as<int>());
+  HDCG_HIP(hipGetLastError());
+  dim3 grid((unsigned)((h->nb + 31) / 32), h->Nc);
+  hipLaunchKernelGGL(k_gs_apply, grid, dim3(kT), (size_t)n * 32 * sizeof(c128), st, phi,
+                     h->rinv.as<c128>(), n, h->nb);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <typename R>
+int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st) {
+  if (h->nvec > kT) return fail(DWF_ERR_ARG, "nvec too large for the coarse mat-vec");
+  constexpr int NR = sizeof(R) == 8 ? 2 : 4;
+  dim3 grid(h->Nc, (nr + NR - 1) / NR);
+  hipLaunchKernelGGL((k_capply<R, NR>), grid, dim3(kT), 0, st, AT, h->nbr.as<int>(), in, out, h->Nc,
+                     h->nvec, nr);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+int crs_idft(hdcg* h, c128* Y, const c128 finv[4][9], hipStream_t st) {
+  const size_t total = (size_t)h->Nc * 27 * h->nvec * h->nvec;
+  for (int mu = 0; mu < 4; ++mu) {
+    const c128* f = finv[mu];
+    hipLaunchKernelGGL(k_idft_dim, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, Y,
+                       h->nvec * h->nvec, h->Nc, mu, f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7],
+                       f[8]);
+    HDCG_HIP(hipGetLastError());
+  }
+  return DWF_OK;
+}
+
+int crs_transpose(hdcg* h, hipStream_t st) {
+  const size_t total = (size_t)h->Nc * kStencil * h->nvec * h->nvec;
+  HDCG_TRY(h->AT128.ensure(total * sizeof(c128)));
+  HDCG_TRY(h->AT64.ensure(total * sizeof(c64)));
+  hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     h->A128.as<c128>(), h->AT128.as<c128>(), h->AT64.as<c64>(), h->nvec, total);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+#define INST(R)                                                                                    \
+  template int blk_phi_layout<R>(hdcg*, cplx<R>*, const cplx<double>*, bool, int, hipStream_t);   \
+  template int blk_dot<R>(hdcg*, const cplx<R>*, const cplx<R>*, size_t, const cplx<R>*, int,     \
+                          cplx<R>*, size_t, size_t, size_t, const cplx<double>*, hipStream_t);     \
+  template int blk_promote<R>(hdcg*, const cplx<R>*, const cplx<R>*, int, cplx<R>*,              \
+                              const cplx<R>*, double, size_t, hipStream_t);                       \
+  template int crs_apply<R>(hdcg*, const cplx<R>*, const cplx<R>*, cplx<R>*, int, hipStream_t);
+INST(double)
+INST(float)
+
+}  // namespace hdk

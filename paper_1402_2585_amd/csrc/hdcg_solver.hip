@@ -1,0 +1,721 @@
+// HDCG setup and solve: subspace (inverse iteration + block Cholesky-QR),
+// little Dirac operator by the Fourier trick, coarse CG, Q, M_IRS, the
+// flexible A-DEF2 inner solver (complex64) and the FP64 defect-correction
+// outer loop; plus the C ABI of these steps.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hdcg_impl.h"
+
+using hdk::c128;
+using hdk::c64;
+using hdk::cplx;
+
+namespace hdk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+Red red_of(dwf_op* op) { return Red{op->red.partials.as<double>(), op->red.counters.as<unsigned>()}; }
+
+// device scalar slots, 128 doubles each (room for 64 right-hand sides x 2)
+enum {
+  S_RR0, S_RR1, S_PAP, S_PP,                       // fine CG
+  S_CRR0, S_CRR1, S_CPAP,                           // coarse CG
+  S_ARR, S_APR, S_AWY, S_ARY0, S_ARY1, S_AINIT, S_APW,  // A-DEF2 (own slots: M_IRS runs inside)
+  S_ORR, S_OBB,                                     // outer loop
+  S_NSLOT
+};
+inline double* slot(hdcg* h, int s) { return h->scal.as<double>() + 128 * s; }
+
+inline size_t fine_elems(hdcg* h) { return h->op->field_elems(1); }
+
+// Host reads of device residual norms through a pinned ring: iteration k is
+// inspected once `lag` later iterations are queued, so the GPU never idles.
+struct LagRing {
+  static constexpr int kRing = 8;
+  hipEvent_t ev[kRing];
+  double* host = nullptr;  // [kRing][64]
+  int nr = 1, queued = 0, checked = 0;
+  bool ok = false;
+  int init(double* pinned, int n) {
+    host = pinned;
+    nr = n;
+    for (int i = 0; i < kRing; ++i)
+      if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess)
+        return fail(DWF_ERR_HIP, "event creation failed");
+    ok = true;
+    return DWF_OK;
+  }
+  ~LagRing() {
+    if (ok)
+      for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(ev[i]);
+  }
+  int push(const double* dev, hipStream_t st) {
+    const int s = queued % kRing;
+    HDCG_HIP(hipMemcpyAsync(host + 64 * s, dev, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HDCG_HIP(hipEventRecord(ev[s], st));
+    ++queued;
+    return DWF_OK;
+  }
+  // wait for the oldest unchecked iteration; *vals points at its nr values
+  int pop(const double** vals) {
+    const int s = checked % kRing;
+    HDCG_HIP(hipEventSynchronize(ev[s]));
+    *vals = host + 64 * s;
+    ++checked;
+    return DWF_OK;
+  }
+};
+
+__global__ void k_probe(c128* __restrict__ c, const c128* __restrict__ z, int k0, int nbt, int Nc,
+                        int nvec) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)nbt * Nc * nvec;
+  if (e >= total) return;
+  const int k = (int)(e % nvec);
+  const size_t ra = e / nvec;
+  const int a = (int)(ra % Nc);
+  const int r = (int)(ra / Nc);
+  c[e] = (k == k0 + r) ? z[a] : cmk(0.0, 0.0);
+}
+
+int ensure_fine64(hdcg* h, int idx, int nr) {
+  return h->fw64[idx].ensure(fine_elems(h) * nr * sizeof(c64));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- fine CG --
+// CG on (H + lam) in complex64 from x = 0.  fixed > 0: exactly `fixed`
+// iterations with no host interaction (M_IRS); otherwise until
+// |r| <= tol |b| for every right-hand side or maxiter.
+int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double tol, int maxiter,
+            int* iters, hipStream_t st) {
+  dwf_op* op = h->op;
+  const size_t n = fine_elems(h);
+  for (int i = 8; i <= 10; ++i) HDCG_TRY(ensure_fine64(h, i, nr));
+  c64* r = h->fw64[8].as<c64>();
+  c64* p = h->fw64[9].as<c64>();
+  c64* w = h->fw64[10].as<c64>();
+  const Red red = red_of(op);
+  double* rr[2] = {slot(h, S_RR0), slot(h, S_RR1)};
+  double* pap = slot(h, S_PAP);
+  double* pp = slot(h, S_PP);
+  HDCG_TRY(b_zero<float>(x, n * nr, st));
+  HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  HDCG_HIP(hipMemcpyAsync(p, b, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  HDCG_TRY(b_norm2<float>(red, r, n, nr, rr[0], st));
+  if (lam != 0.0) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<double> bb(nr, 0.0);
+  LagRing ring;
+  if (fixed <= 0) {
+    HDCG_TRY(ring.init(h->pinned, nr));
+    HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 8, rr[0], nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HDCG_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nr; ++i) bb[i] = h->pinned[64 * 8 + i];
+  }
+  const int limit = fixed > 0 ? fixed : maxiter;
+  int k = 0;
+  bool done = false;
+  while (!done && k < limit) {
+    double* cur = rr[k & 1];
+    double* nxt = rr[(k + 1) & 1];
+    HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pap));
+    HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, cur, false, pap, lam != 0.0 ? pp : nullptr, lam,
+                             nxt, st));
+    HDCG_TRY(b_xpay<float>(red, p, r, n, nr, nxt, false, cur, 1.0, lam != 0.0 ? pp : nullptr, st));
+    ++k;
+    if (fixed > 0) continue;
+    HDCG_TRY(ring.push(nxt, st));
+    while (ring.checked < ring.queued && (ring.queued - ring.checked > 2 || k >= limit)) {
+      const double* v;
+      HDCG_TRY(ring.pop(&v));
+      bool conv = true;
+      for (int i = 0; i < nr; ++i) {
+        if (!std::isfinite(v[i])) return fail(DWF_ERR_NUMERIC, "fine CG residual not finite");
+        if (v[i] > tol * tol * bb[i]) conv = false;
+      }
+      if (conv) {
+        done = true;
+        break;
+      }
+    }
+  }
+  if (iters) *iters = k;
+  return DWF_OK;
+}
+
+// -------------------------------------------------------------- coarse CG --
+template <typename R>
+int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
+              int maxiter, int* iters, hipStream_t st) {
+  const size_t n = (size_t)h->Nc * h->nvec;
+  for (int i = 0; i < 3; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
+  cplx<R>* r = h->cw[0].as<cplx<R>>();
+  cplx<R>* p = h->cw[1].as<cplx<R>>();
+  cplx<R>* w = h->cw[2].as<cplx<R>>();
+  const Red red = red_of(h->op);
+  double* rr[2] = {slot(h, S_CRR0), slot(h, S_CRR1)};
+  double* pap = slot(h, S_CPAP);
+  HDCG_TRY(b_zero<R>(x, n * nr, st));
+  HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  HDCG_HIP(hipMemcpyAsync(p, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  HDCG_TRY(b_norm2<R>(red, r, n, nr, rr[0], st));
+  HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 9, rr[0], nr * sizeof(double), hipMemcpyDeviceToHost, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  std::vector<double> bb(h->pinned + 64 * 9, h->pinned + 64 * 9 + nr);
+  bool any = false;
+  for (double v : bb) any = any || v > 0.0;
+  int k = 0;
+  if (any) {
+    LagRing ring;
+    HDCG_TRY(ring.init(h->pinned, nr));
+    bool done = false;
+    while (!done && k < maxiter) {
+      double* cur = rr[k & 1];
+      double* nxt = rr[(k + 1) & 1];
+      HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
+      HDCG_TRY(b_dot<R>(red, p, w, n, nr, pap, st));
+      HDCG_TRY(b_update<R>(red, x, r, p, w, n, nr, cur, false, pap, nullptr, 0.0, nxt, st, 2));
+      HDCG_TRY(b_xpay<R>(red, p, r, n, nr, nxt, false, cur, 1.0, nullptr, st));
+      ++k;
+      HDCG_TRY(ring.push(nxt, st));
+      while (ring.checked < ring.queued && (ring.queued - ring.checked > 2 || k >= maxiter)) {
+        const double* v;
+        HDCG_TRY(ring.pop(&v));
+        bool conv = true;
+        for (int i = 0; i < nr; ++i) {
+          if (!std::isfinite(v[i])) return fail(DWF_ERR_NUMERIC, "coarse CG residual not finite");
+          if (v[i] > tol * tol * bb[i]) conv = false;
+        }
+        if (conv) {
+          done = true;
+          break;
+        }
+      }
+    }
+  }
+  if (iters) *iters = k;
+  return DWF_OK;
+}
+
+// Q v = P A^-1 P^+ v (complex64): out = base + sign * Q in
+static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, double sign,
+                   int* citers, hipStream_t st) {
+  const size_t n = (size_t)h->Nc * h->nvec;
+  HDCG_TRY(h->cw[3].ensure(n * nr * sizeof(c128)));
+  HDCG_TRY(h->cw[4].ensure(n * nr * sizeof(c128)));
+  c64* cb = h->cw[3].as<c64>();
+  c64* cx = h->cw[4].as<c64>();
+  HDCG_TRY(blk_dot<float>(h, h->phi64.as<c64>(), in, fine_elems(h), nullptr, nr, cb, n, h->nvec, 1,
+                          nullptr, st));
+  int it = 0;
+  HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter,
+                            &it, st));
+  if (citers) *citers += it;
+  HDCG_TRY(blk_promote<float>(h, h->phi64.as<c64>(), cx, nr, out, base, sign, fine_elems(h), st));
+  return DWF_OK;
+}
+
+struct InnerStats {
+  int iterations = 0, coarse_solves = 0, coarse_iterations = 0;
+  double matmuls32 = 0;
+};
+
+// y = M_1 r = P_R M_IRS r + Q r = z - Q (H z - r), z = M_IRS r
+static int precondition(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, hipStream_t st) {
+  const size_t n = fine_elems(h);
+  c64* z = h->fw64[4].as<c64>();
+  c64* t = h->fw64[6].as<c64>();
+  int it = 0;
+  HDCG_TRY(fine_cg(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, 0.0, 0, &it, st));
+  is->matmuls32 += it * nr;
+  HDCG_TRY(launch_mpcdagmpc<float>(h->op, t, z, nr, st, nullptr));
+  is->matmuls32 += nr;
+  HDCG_TRY(b_axpby<float>(t, r, -1.0, 1.0, n * nr, st));  // t = H z - r
+  HDCG_TRY(apply_Q(h, y, t, nr, z, -1.0, &is->coarse_iterations, st));
+  is->coarse_solves += 1;
+  return DWF_OK;
+}
+
+// Inner solve H e = rin in complex64 by the generalised PCG with the A-DEF2
+// choices (V_start = Q rin, M_1 = P_R M_IRS + Q), flexible or standard
+// search-direction update, to |r| <= tol |rin| or maxiter.
+static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxiter, InnerStats* is,
+                 hipStream_t st) {
+  dwf_op* op = h->op;
+  const size_t n = fine_elems(h);
+  for (int i = 1; i <= 6; ++i) HDCG_TRY(ensure_fine64(h, i, nr));
+  c64* r = h->fw64[1].as<c64>();
+  c64* p = h->fw64[2].as<c64>();
+  c64* w = h->fw64[3].as<c64>();
+  c64* y = h->fw64[5].as<c64>();
+  const Red red = red_of(op);
+  double* rr = slot(h, S_ARR);
+  double* pr = slot(h, S_APR);
+  double* wy = slot(h, S_AWY);
+  double* ry[2] = {slot(h, S_ARY0), slot(h, S_ARY1)};
+  double* pw = slot(h, S_APW);
+  double* init = slot(h, S_AINIT);
+  const bool flex = h->prm.flexible != 0;
+  HDCG_TRY(b_norm2<float>(red, rin, n, nr, init, st));
+  HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 10, init, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+  // x0 = Q rin ; r0 = rin - H x0
+  HDCG_TRY(apply_Q(h, x, rin, nr, nullptr, 1.0, &is->coarse_iterations, st));
+  is->coarse_solves += 1;
+  HDCG_TRY(launch_mpcdagmpc<float>(op, w, x, nr, st, nullptr));
+  is->matmuls32 += nr;
+  HDCG_HIP(hipMemcpyAsync(r, rin, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  HDCG_TRY(b_axpby<float>(r, w, -1.0, 1.0, n * nr, st));
+  HDCG_TRY(precondition(h, y, r, nr, is, st));
+  HDCG_HIP(hipMemcpyAsync(p, y, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+  if (!flex) HDCG_TRY(b_dot<float>(red, r, y, n, nr, ry[0], st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  std::vector<double> r0(h->pinned + 64 * 10, h->pinned + 64 * 10 + nr);
+  int k = 0;
+  while (k < maxiter) {
+    // w = H p, (p, w) = |M_pc p|^2 fused into the operator
+    HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pw));
+    is->matmuls32 += nr;
+    if (flex) {
+      HDCG_TRY(b_dot<float>(red, p, r, n, nr, pr, st));  // alpha = (p, r) / (p, w)
+      HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, pr, true, pw, nullptr, 0.0, rr, st));
+    } else {
+      HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, ry[k & 1], true, pw, nullptr, 0.0, rr, st));
+    }
+    ++k;
+    HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 11, rr, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HDCG_HIP(hipStreamSynchronize(st));
+    bool conv = true;
+    for (int i = 0; i < nr; ++i) {
+      const double v = h->pinned[64 * 11 + i];
+      if (!std::isfinite(v)) return fail(DWF_ERR_NUMERIC, "A-DEF2 residual not finite");
+      if (v > tol * tol * r0[i]) conv = false;
+    }
+    if (conv) break;
+    HDCG_TRY(precondition(h, y, r, nr, is, st));
+    if (flex) {
+      HDCG_TRY(b_dot<float>(red, w, y, n, nr, wy, st));  // beta = -(w, y) / (p, w)
+      HDCG_TRY(b_xpay<float>(red, p, y, n, nr, wy, true, pw, -1.0, nullptr, st));
+    } else {
+      // beta = (r', y') / (r, y)
+      HDCG_TRY(b_dot<float>(red, r, y, n, nr, ry[(k) & 1], st));
+      HDCG_TRY(b_xpay<float>(red, p, y, n, nr, ry[k & 1], true, ry[(k + 1) & 1], 1.0, nullptr, st, 2));
+    }
+  }
+  is->iterations += k;
+  return DWF_OK;
+}
+
+}  // namespace hdk
+
+using namespace hdk;
+
+// ====================================================================== ABI
+extern "C" {
+
+void hdcg_default_params(struct hdcg_params* p) {
+  if (!p) return;
+  p->n_ii = 0;
+  p->lambda_ii = 0.0;
+  p->tol_ii = 1e-4;
+  p->maxiter_ii = 500;
+  p->n_irs = 7;
+  p->lambda_irs = 1.0;
+  p->coarse_tol = 0.04;
+  p->coarse_maxiter = 2000;
+  p->flexible = 1;
+  p->inner_tol = 1e-5;
+  p->inner_maxiter = 500;
+  p->outer_maxiter = 50;
+  p->build_batch = 8;
+}
+
+int hdcg_destroy(hdcg_t h) {
+  if (!h) return DWF_OK;
+  (void)hipDeviceSynchronize();
+  h->site_of.release();
+  h->nbr.release();
+  h->phi128.release();
+  h->phi64.release();
+  h->A128.release();
+  h->AT64.release();
+  h->AT128.release();
+  h->gram.release();
+  h->rinv.release();
+  h->flag.release();
+  for (auto& b : h->cw) b.release();
+  for (auto& b : h->fw64) b.release();
+  for (auto& b : h->fw128) b.release();
+  h->scal.release();
+  h->probe_c.release();
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return DWF_OK;
+}
+
+static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
+  dwf_op* op = h->op;
+  const Geom& g = op->g;
+  const size_t fe = op->field_elems(1);
+  const int nv = h->nvec;
+  HDCG_TRY(ensure_reducer(op));
+  HDCG_TRY(h->scal.ensure(sizeof(double) * 128 * S_NSLOT));
+  HDCG_TRY(h->flag.ensure(sizeof(int) * 4));
+  HDCG_HIP(hipMemsetAsync(h->flag.ptr, 0, sizeof(int) * 4, st));
+  HDCG_TRY(blk_build_maps(h, st));
+
+  // ---- subspace: inverse iteration on the given starting vectors ---------
+  DevBuf work;  // canonical c128 copy of the vectors
+  HDCG_TRY(work.ensure(fe * nv * sizeof(c128)));
+  HDCG_HIP(hipMemcpyAsync(work.ptr, vectors, fe * nv * sizeof(c128), hipMemcpyDeviceToDevice, st));
+  if (h->prm.n_ii > 0) {
+    HDCG_TRY(h->fw128[0].ensure(fe * sizeof(c128)));
+    HDCG_TRY(ensure_fine64(h, 0, 1));
+    HDCG_TRY(ensure_fine64(h, 1, 1));
+    c128* v128 = h->fw128[0].as<c128>();
+    c64* v = h->fw64[0].as<c64>();
+    c64* xv = h->fw64[1].as<c64>();
+    double* nrm = slot(h, S_ORR);
+    for (int k = 0; k < nv; ++k) {
+      c128* can = work.as<c128>() + (size_t)k * fe;
+      HDCG_TRY(dwf_import(op, v128, can, DWF_C128, 1, st));
+      HDCG_TRY(launch_convert<float, double>(v, v128, fe, st));
+      for (int s = 0; s < h->prm.n_ii; ++s) {
+        int it = 0;
+        HDCG_TRY(fine_cg(h, xv, v, 1, h->prm.lambda_ii, 0, h->prm.tol_ii, h->prm.maxiter_ii, &it, st));
+        h->setup_matmuls += it;
+        HDCG_TRY(b_norm2<float>(red_of(op), xv, fe, 1, nrm, st));
+        HDCG_TRY(b_scale_copy<float, float>(v, xv, nrm, true, fe, 1, st));  // normalise
+      }
+      HDCG_TRY(launch_convert<double, float>(v128, v, fe, st));
+      HDCG_TRY(dwf_export(op, can, v128, DWF_C128, 1, st));
+    }
+  }
+  HDCG_TRY(h->phi128.ensure(fe * nv * sizeof(c128)));
+  HDCG_TRY(blk_phi_layout<double>(h, h->phi128.as<c128>(), work.as<c128>(), true, nv, st));
+  work.release();
+
+  // ---- block orthonormalisation: Cholesky-QR, twice (FP64) -------------
+  HDCG_TRY(blk_cholqr_step(h, st));
+  HDCG_TRY(blk_cholqr_step(h, st));
+  int flag = 0;
+  HDCG_HIP(hipMemcpyAsync(&flag, h->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  if (flag) return fail(DWF_ERR_NUMERIC, "block Gram matrix not positive definite (subspace vectors dependent on a block)");
+  HDCG_TRY(h->phi64.ensure(fe * nv * sizeof(c64)));
+  HDCG_TRY(launch_convert<float, double>(h->phi64.as<c64>(), h->phi128.as<c128>(), fe * nv, st));
+
+  // ---- little Dirac operator by the Fourier trick (Sec. V.A.1) ---------
+  const size_t n2 = (size_t)nv * nv;
+  HDCG_TRY(h->A128.ensure((size_t)h->Nc * kStencil * n2 * sizeof(c128)));
+  const int NB = std::max(1, std::min(h->prm.build_batch, std::min(nv, 16)));
+  HDCG_TRY(h->fw128[1].ensure(fe * NB * sizeof(c128)));
+  HDCG_TRY(h->fw128[2].ensure(fe * NB * sizeof(c128)));
+  HDCG_TRY(h->probe_c.ensure((size_t)NB * h->Nc * nv * sizeof(c128)));
+  DevBuf zbuf;
+  HDCG_TRY(zbuf.ensure(sizeof(c128) * 2 * h->Nc));
+  double m[4];
+  for (int mu = 0; mu < 4; ++mu) m[mu] = std::max(1.0, std::round(h->C[mu] / 3.0));
+  std::vector<c128> z(2 * h->Nc);
+  for (int s = 0; s < kStencil; ++s) {
+    double p[4];
+    (void)kPi;
+    int q = s;
+    for (int mu = 0; mu < 4; ++mu) {
+      p[mu] = 2.0 * kPi * (q % 3 - 1) * m[mu] / h->C[mu];
+      q /= 3;
+    }
+    for (int a = 0; a < h->Nc; ++a) {
+      int r = a;
+      double ph = 0.0;
+      for (int mu = 0; mu < 4; ++mu) {
+        ph += p[mu] * (r % h->C[mu]);
+        r /= h->C[mu];
+      }
+      z[a] = cmk(std::cos(ph), std::sin(ph));            // z^s_a = exp(i p.x^a)
+      z[h->Nc + a] = cmk(std::cos(ph), -std::sin(ph));   // its conjugate
+    }
+    HDCG_HIP(hipMemcpyAsync(zbuf.ptr, z.data(), sizeof(c128) * 2 * h->Nc, hipMemcpyHostToDevice, st));
+    for (int k0 = 0; k0 < nv; k0 += NB) {
+      const int nbt = std::min(NB, nv - k0);
+      const size_t tot = (size_t)nbt * h->Nc * nv;
+      hipLaunchKernelGGL(k_probe, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                         h->probe_c.as<c128>(), zbuf.as<c128>(), k0, nbt, h->Nc, nv);
+      HDCG_HIP(hipGetLastError());
+      // phi~_k(p^s) = sum_b z^s_b phi^b_k, then H, then <phi^b_k'| . > e^{-ip.x^b}
+      HDCG_TRY(blk_promote<double>(h, h->phi128.as<c128>(), h->probe_c.as<c128>(), nbt,
+                                   h->fw128[1].as<c128>(), nullptr, 1.0, fe, st));
+      HDCG_TRY(launch_mpcdagmpc<double>(op, h->fw128[2].as<c128>(), h->fw128[1].as<c128>(), nbt, st, nullptr));
+      h->setup_matmuls += nbt;
+      HDCG_TRY(blk_dot<double>(h, h->phi128.as<c128>(), h->fw128[2].as<c128>(), fe, nullptr, nbt,
+                               h->A128.as<c128>() + (size_t)s * n2 + k0, 1, (size_t)kStencil * n2, nv,
+                               zbuf.as<c128>() + h->Nc, st));
+    }
+    HDCG_HIP(hipStreamSynchronize(st));  // z is rewritten next
+  }
+  // invert M_sl = prod_mu exp(i p^s_mu delta^l_mu) one dimension at a time
+  c128 finv[4][9];
+  for (int mu = 0; mu < 4; ++mu) {
+    std::complex<double> F[3][3], I[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) F[a][b] = std::polar(1.0, 2.0 * kPi * m[mu] / h->C[mu] * (a - 1) * (b - 1));
+    const std::complex<double> det = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                                     F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                                     F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+    if (std::abs(det) < 1e-10) return fail(DWF_ERR_GEOMETRY, "phase matrix singular (coarse extent < 3?)");
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const int a1 = (b + 1) % 3, a2 = (b + 2) % 3, b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+        I[a][b] = (F[a1][b1] * F[a2][b2] - F[a1][b2] * F[a2][b1]) / det;  // adjugate / det
+      }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) finv[mu][a * 3 + b] = cmk(I[a][b].real(), I[a][b].imag());
+  }
+  HDCG_TRY(crs_idft(h, h->A128.as<c128>(), finv, st));
+  HDCG_TRY(crs_transpose(h, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  h->fw128[1].release();
+  h->fw128[2].release();
+  h->probe_c.release();
+  return DWF_OK;
+}
+
+int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const void* vectors_c128,
+               const struct hdcg_params* p, void* stream) {
+  if (!out || !op || !block || !vectors_c128) return fail(DWF_ERR_ARG, "null argument to hdcg_setup");
+  *out = nullptr;
+  if (nvec < 1 || nvec > 64) return fail(DWF_ERR_ARG, "nvec must be in 1..64");
+  const int L[4] = {op->g.X, op->g.Y, op->g.Z, op->g.T};
+  for (int mu = 0; mu < 4; ++mu) {
+    if (block[mu] < 4 || (block[mu] & 1) || L[mu] % block[mu])
+      return fail(DWF_ERR_GEOMETRY, "blocks must be even, >= 4 and divide the lattice");
+    if (L[mu] / block[mu] < 3) return fail(DWF_ERR_GEOMETRY, "coarse extent must be >= 3 in every direction");
+  }
+  hdcg* h = new (std::nothrow) hdcg();
+  if (!h) return fail(DWF_ERR_OOM, "host allocation failed");
+  h->op = op;
+  h->Nc = 1;
+  int bvol = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    h->B[mu] = block[mu];
+    h->C[mu] = L[mu] / block[mu];
+    h->Nc *= h->C[mu];
+    bvol *= block[mu];
+  }
+  h->nsb = bvol / 2;
+  h->nvec = nvec;
+  h->nb = (size_t)h->nsb * 12 * op->g.Ls;
+  if (p) {
+    h->prm.n_ii = p->n_ii;
+    h->prm.lambda_ii = p->lambda_ii;
+    h->prm.tol_ii = p->tol_ii;
+    h->prm.maxiter_ii = p->maxiter_ii;
+    h->prm.n_irs = p->n_irs;
+    h->prm.lambda_irs = p->lambda_irs;
+    h->prm.coarse_tol = p->coarse_tol;
+    h->prm.coarse_maxiter = p->coarse_maxiter;
+    h->prm.flexible = p->flexible;
+    h->prm.inner_tol = p->inner_tol;
+    h->prm.inner_maxiter = p->inner_maxiter;
+    h->prm.outer_maxiter = p->outer_maxiter;
+    h->prm.build_batch = p->build_batch;
+  }
+  if (hipHostMalloc((void**)&h->pinned, 64 * 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    h->pinned = nullptr;
+    hdcg_destroy(h);
+    return fail(DWF_ERR_HIP, "pinned allocation failed");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = setup_impl(h, vectors_c128, static_cast<hipStream_t>(stream));
+  if (rc < 0) {
+    hdcg_destroy(h);
+    return rc;
+  }
+  h->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return DWF_OK;
+}
+
+int hdcg_dims(hdcg_t h, int coarse_dims[4], int* ncoarse, int* nvec) {
+  if (!h) return fail(DWF_ERR_ARG, "null handle");
+  if (coarse_dims)
+    for (int mu = 0; mu < 4; ++mu) coarse_dims[mu] = h->C[mu];
+  if (ncoarse) *ncoarse = h->Nc;
+  if (nvec) *nvec = h->nvec;
+  return DWF_OK;
+}
+
+int hdcg_export_block_map(hdcg_t h, int* block_of_site, int* index_in_block) {
+  if (!h || !block_of_site || !index_in_block) return fail(DWF_ERR_ARG, "null argument");
+  std::vector<int> so((size_t)h->Nc * h->nsb);
+  HDCG_HIP(hipMemcpy(so.data(), h->site_of.ptr, so.size() * sizeof(int), hipMemcpyDeviceToHost));
+  for (int a = 0; a < h->Nc; ++a)
+    for (int j = 0; j < h->nsb; ++j) {
+      const int cb = so[(size_t)a * h->nsb + j];
+      if (cb < 0 || cb >= h->op->g.Vh) return fail(DWF_ERR_STATE, "block map out of range");
+      block_of_site[cb] = a;
+      index_in_block[cb] = j;
+    }
+  return DWF_OK;
+}
+
+int hdcg_export_subspace(hdcg_t h, void* phi_c128, void* stream) {
+  if (!h || !phi_c128) return fail(DWF_ERR_ARG, "null argument");
+  return blk_phi_layout<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(phi_c128), false, h->nvec,
+                                static_cast<hipStream_t>(stream));
+}
+
+int hdcg_export_coarse(hdcg_t h, void* A_c128, void* stream) {
+  if (!h || !A_c128) return fail(DWF_ERR_ARG, "null argument");
+  HDCG_HIP(hipMemcpyAsync(A_c128, h->A128.ptr, (size_t)h->Nc * kStencil * h->nvec * h->nvec * sizeof(c128),
+                          hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return DWF_OK;
+}
+
+static int check_h(hdcg* h, int prec, int nrhs) {
+  if (!h) return fail(DWF_ERR_ARG, "null hdcg handle");
+  if (prec != DWF_C128 && prec != DWF_C64) return fail(DWF_ERR_ARG, "precision must be DWF_C128 or DWF_C64");
+  if (nrhs < 1 || nrhs > 64) return fail(DWF_ERR_ARG, "nrhs must be in 1..64");
+  return DWF_OK;
+}
+
+int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!coarse_out || !fine_in) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)h->Nc * h->nvec, fe = h->op->field_elems(1);
+  if (prec == DWF_C128)
+    return blk_dot<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(fine_in), fe, nullptr, nrhs,
+                           static_cast<c128*>(coarse_out), n, h->nvec, 1, nullptr, st);
+  return blk_dot<float>(h, h->phi64.as<c64>(), static_cast<const c64*>(fine_in), fe, nullptr, nrhs,
+                        static_cast<c64*>(coarse_out), n, h->nvec, 1, nullptr, st);
+}
+
+int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!coarse_in || !fine_out) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  const size_t fe = h->op->field_elems(1);
+  if (prec == DWF_C128)
+    return blk_promote<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(coarse_in), nrhs,
+                               static_cast<c128*>(fine_out), nullptr, 1.0, fe, st);
+  return blk_promote<float>(h, h->phi64.as<c64>(), static_cast<const c64*>(coarse_in), nrhs,
+                            static_cast<c64*>(fine_out), nullptr, 1.0, fe, st);
+}
+
+int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!out || !in || out == in) return fail(DWF_ERR_ARG, "coarse_apply needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128)
+    return crs_apply<double>(h, h->AT128.as<c128>(), static_cast<const c128*>(in), static_cast<c128*>(out), nrhs, st);
+  return crs_apply<float>(h, h->AT64.as<c64>(), static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
+}
+
+int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
+                      int* iters, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!x || !b || !(tol > 0)) return fail(DWF_ERR_ARG, "bad arguments to hdcg_coarse_solve");
+  auto st = static_cast<hipStream_t>(stream);
+  int it = 0;
+  if (prec == DWF_C128)
+    HDCG_TRY(coarse_cg<double>(h, h->AT128.as<c128>(), static_cast<c128*>(x), static_cast<const c128*>(b), nrhs,
+                               tol, maxiter, &it, st));
+  else
+    HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), static_cast<c64*>(x), static_cast<const c64*>(b), nrhs, tol,
+                              maxiter, &it, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  if (iters) *iters = it;
+  return it >= maxiter ? DWF_NOT_CONVERGED : DWF_OK;
+}
+
+int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, DWF_C64, nrhs));
+  if (!out || !in || out == in) return fail(DWF_ERR_ARG, "hdcg_mirs needs distinct in/out buffers");
+  return fine_cg(h, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, h->prm.lambda_irs, h->prm.n_irs,
+                 0.0, 0, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol, struct hdcg_stats* stats,
+               void* stream) {
+  HDCG_TRY(check_h(h, DWF_C128, nrhs));
+  if (!x_c128 || !b_c128 || !(tol > 0)) return fail(DWF_ERR_ARG, "bad arguments to hdcg_solve");
+  auto st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  dwf_op* op = h->op;
+  const size_t fe = op->field_elems(1);
+  c128* x = static_cast<c128*>(x_c128);
+  const c128* b = static_cast<const c128*>(b_c128);
+  HDCG_TRY(h->fw128[0].ensure(fe * nrhs * sizeof(c128)));
+  HDCG_TRY(h->fw128[1].ensure(fe * nrhs * sizeof(c128)));
+  HDCG_TRY(ensure_fine64(h, 0, nrhs));
+  HDCG_TRY(ensure_fine64(h, 7, nrhs));
+  c128* r = h->fw128[0].as<c128>();
+  c128* w = h->fw128[1].as<c128>();
+  c64* r64 = h->fw64[7].as<c64>();
+  c64* e64 = h->fw64[0].as<c64>();
+  const Red red = red_of(op);
+  double* orr = slot(h, S_ORR);
+  double* obb = slot(h, S_OBB);
+  HDCG_TRY(b_norm2<double>(red, b, fe, nrhs, obb, st));
+  HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 12, obb, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  HDCG_TRY(b_zero<double>(x, fe * nrhs, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  std::vector<double> bb(h->pinned + 64 * 12, h->pinned + 64 * 12 + nrhs);
+  InnerStats is;
+  int outer = 0;
+  double mm64 = 0, rel = 0;
+  int status = DWF_OK;
+  for (;;) {
+    // r = b - H x in FP64
+    HDCG_HIP(hipMemcpyAsync(r, b, fe * nrhs * sizeof(c128), hipMemcpyDeviceToDevice, st));
+    if (outer > 0) {
+      HDCG_TRY(launch_mpcdagmpc<double>(op, w, x, nrhs, st, nullptr));
+      mm64 += nrhs;
+      HDCG_TRY(b_axpby<double>(r, w, -1.0, 1.0, fe * nrhs, st));
+    }
+    HDCG_TRY(b_norm2<double>(red, r, fe, nrhs, orr, st));
+    HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 13, orr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    HDCG_HIP(hipStreamSynchronize(st));
+    rel = 0;
+    for (int i = 0; i < nrhs; ++i) {
+      const double v = h->pinned[64 * 13 + i];
+      if (!std::isfinite(v)) return fail(DWF_ERR_NUMERIC, "outer residual not finite");
+      rel = std::max(rel, bb[i] > 0 ? std::sqrt(v / bb[i]) : 0.0);
+    }
+    if (rel <= tol) break;
+    if (outer >= h->prm.outer_maxiter) {
+      status = DWF_NOT_CONVERGED;
+      break;
+    }
+    // inner complex64 solve on the normalised residual, x += |r| e
+    HDCG_TRY(b_scale_copy<float, double>(r64, r, orr, true, fe, nrhs, st));
+    HDCG_TRY(adef2(h, e64, r64, nrhs, h->prm.inner_tol, h->prm.inner_maxiter, &is, st));
+    HDCG_TRY(b_axpy_mixed<double, float>(x, e64, orr, fe, nrhs, st, true));
+    ++outer;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->outer_iterations = outer;
+    stats->inner_iterations = is.iterations;
+    stats->coarse_solves = is.coarse_solves;
+    stats->coarse_iterations = is.coarse_iterations;
+    stats->converged = status == DWF_OK;
+    stats->true_residual = rel;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->setup_seconds = h->setup_seconds;
+    stats->matmuls_fp64 = mm64;
+    stats->matmuls_fp32 = is.matmuls32;
+  }
+  if (status == DWF_NOT_CONVERGED) set_error("hdcg_solve: outer iteration limit reached");
+  return status;
+}
+
+}  // extern "C"

@@ -69,3 +69,42 @@ class FineOperator:
         out = self.new_field(prec, nrhs) if out is None else out
         L.mpc_dag_mpc_apply(self.h, out, x, prec, nrhs)
         return out
+
+
+class HDCG:
+    """Owns one hdcg handle built on a FineOperator."""
+
+    def __init__(self, op: FineOperator, block, vectors, params=None, **overrides):
+        torch = op.torch
+        self.op = op
+        v = vectors if isinstance(vectors, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(vectors))
+        v = v.to(device="cuda", dtype=torch.complex128).contiguous()
+        self.nvec = v.shape[0]
+        p = params if params is not None else L.hdcg_default_params(**overrides)
+        self.h = L.hdcg_setup(op.h, block, self.nvec, v, p)
+        self.coarse_dims, self.Nc, _ = L.hdcg_dims(self.h)
+
+    def close(self):
+        if self.h is not None:
+            L.hdcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_coarse(self, prec=L.DWF_C128, nrhs=1, zero=True):
+        f = self.op.torch.zeros if zero else self.op.torch.empty
+        return f((nrhs, self.Nc, self.nvec), dtype=self.op.dtype(prec), device="cuda")
+
+    def coarse_matrix(self):
+        A = self.op.torch.empty((self.Nc, 81, self.nvec, self.nvec), dtype=self.op.torch.complex128, device="cuda")
+        L.hdcg_export_coarse(self.h, A)
+        return A
+
+    def subspace(self):
+        P = self.op.torch.empty((self.nvec,) + self.op.canonical_shape, dtype=self.op.torch.complex128, device="cuda")
+        L.hdcg_export_subspace(self.h, P)
+        return P

@@ -1,0 +1,195 @@
+"""GPU parity of the HDCG rows against the oracle.
+
+Every reference value is computed by the oracle from the same seeded inputs
+(the oracle builds its own subspace orthonormalisation and its own coarse
+operator by brute force); nothing flows from the GPU into the oracle.
+
+Tolerances: FP64 results 1e-12 relative (max-norm over the array); complex64
+results 2e-5 (sums of ~10^4 terms in float32, eps 6e-8, against O(1) data);
+integer maps bit-exact; solves to their stated residual.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import blocks as oblk
+from oracle import coarse as ocrs
+from oracle import hdcg as ohdcg
+from oracle.cg import cg
+from oracle.dwf import DWF
+from tests.gpu_util import banner, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1402_2585_amd as hd  # noqa: E402
+
+GEOMS = {
+    # name: dims, Ls, block, nvec, eps, mass
+    "12^4xLs2-b4-n2": ((12, 12, 12, 12), 2, (4, 4, 4, 4), 2, 0.5, 0.01),
+    "12x12x18x12xLs2-b4x4x6x4-n3": ((12, 12, 18, 12), 2, (4, 4, 6, 4), 3, 0.6, 0.05),
+}
+
+
+def _setup(name, n_ii=0):
+    dims, Ls, block, nvec, eps, mass = GEOMS[name]
+    U = synth.gauge_field(dims, eps, 300)
+    raw = synth.gaussian_half_field(dims, Ls, 301, nrhs=nvec)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass)
+    h = hd.HDCG(op, block, raw, n_ii=n_ii)
+    ref = DWF(U, dims, Ls, 1.8, mass)
+    return dims, Ls, block, nvec, raw, op, h, ref
+
+
+@pytest.fixture(scope="module", params=list(GEOMS))
+def two_level(request):
+    name = request.param
+    banner(f"hdcg setup {name}")
+    dims, Ls, block, nvec, raw, op, h, ref = _setup(name)
+    _, _, sob = oblk.block_map(dims, block)
+    phi = oblk.orthonormalise(raw, sob)
+    C = oblk.coarse_dims(dims, block)
+    A = ocrs.build_brute(ref, phi, sob, C)
+    yield dict(name=name, dims=dims, Ls=Ls, block=block, nvec=nvec, op=op, h=h, ref=ref, sob=sob, phi=phi,
+               C=C, A=A)
+    h.close()
+    op.close()
+
+
+def test_block_map_bit_exact(two_level):
+    t = two_level
+    banner(f"block map {t['name']}")
+    a, idx, _ = oblk.block_map(t["dims"], t["block"])
+    ga, gi = hd.hdcg_export_block_map(t["h"].h, len(a))
+    assert np.array_equal(ga, a) and np.array_equal(gi, idx)
+
+
+def test_gram_schmidt_subspace(two_level):
+    t = two_level
+    banner(f"subspace {t['name']}")
+    got = t["h"].subspace().cpu().numpy()
+    assert rel_err(got, t["phi"]) < 1e-12
+
+
+def test_project_promote(two_level):
+    t = two_level
+    banner(f"project/promote {t['name']}")
+    op, h, phi, sob = t["op"], t["h"], t["phi"], t["sob"]
+    psi = synth.gaussian_half_field(t["dims"], t["Ls"], 310, nrhs=2)
+    c = synth.rng(311).standard_normal((2, h.Nc, h.nvec)) + 1j * synth.rng(312).standard_normal((2, h.Nc, h.nvec))
+    want_c = oblk.project(phi, sob, psi)
+    want_p = oblk.promote(phi, sob, c)
+    for prec, tol in ((hd.DWF_C128, 1e-12), (hd.DWF_C64, 2e-5)):
+        out = h.new_coarse(prec, 2)
+        hd.hdcg_project(h.h, out, op.to_native(psi, prec), prec, 2)
+        assert rel_err(out.cpu().numpy(), want_c) < tol
+        fine = op.new_field(prec, 2)
+        hd.hdcg_promote(h.h, fine, torch.from_numpy(c).to("cuda", op.dtype(prec)), prec, 2)
+        assert rel_err(op.to_canonical(fine, prec, 2).cpu().numpy(), want_p) < tol
+
+
+def test_coarse_operator_fourier_vs_oracle_brute_force(two_level):
+    t = two_level
+    banner(f"coarse A {t['name']}")
+    got = t["h"].coarse_matrix().cpu().numpy()
+    err = rel_err(got, t["A"])
+    print(f"A rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_coarse_apply(two_level):
+    t = two_level
+    banner(f"coarse apply {t['name']}")
+    h = t["h"]
+    c = synth.rng(320).standard_normal((3, h.Nc, h.nvec)) + 1j * synth.rng(321).standard_normal((3, h.Nc, h.nvec))
+    want = ocrs.apply(t["A"], c, t["C"])
+    for prec, tol in ((hd.DWF_C128, 1e-12), (hd.DWF_C64, 2e-5)):
+        inp = torch.from_numpy(c).to("cuda", t["op"].dtype(prec)).contiguous()
+        out = h.new_coarse(prec, 3)
+        hd.coarse_apply(h.h, out, inp, prec, 3)
+        assert rel_err(out.cpu().numpy(), want) < tol
+
+
+def test_coarse_solve(two_level):
+    t = two_level
+    banner(f"coarse solve {t['name']}")
+    h = t["h"]
+    b = synth.rng(330).standard_normal((1, h.Nc, h.nvec)) + 1j * synth.rng(331).standard_normal((1, h.Nc, h.nvec))
+    D = ocrs.to_dense(t["A"], t["C"])
+    xw = np.linalg.solve(D, b.ravel())
+    x = h.new_coarse(hd.DWF_C128, 1)
+    rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to("cuda"), hd.DWF_C128, 1, 1e-12, 5000)
+    assert rc == 0 and it > 0
+    cond = np.linalg.cond(D)
+    assert rel_err(x.cpu().numpy().ravel(), xw) < 10 * cond * 1e-12
+    # complex64 coarse CG to the solver's working tolerance 0.04
+    x64 = h.new_coarse(hd.DWF_C64, 1)
+    rc, it = hd.hdcg_coarse_solve(h.h, x64, torch.from_numpy(b).to("cuda", torch.complex64), hd.DWF_C64, 1, 0.04, 5000)
+    r = b.ravel() - D @ x64.cpu().numpy().ravel().astype(complex)
+    assert np.linalg.norm(r) <= 0.041 * np.linalg.norm(b)
+
+
+def test_mirs(two_level):
+    t = two_level
+    banner(f"M_IRS {t['name']}")
+    op, h = t["op"], t["h"]
+    r = synth.gaussian_half_field(t["dims"], t["Ls"], 340)
+    want = ohdcg.m_irs(t["ref"], r, 7, 1.0)
+    out = op.new_field(hd.DWF_C64)
+    hd.hdcg_mirs(h.h, out, op.to_native(r, hd.DWF_C64))
+    err = rel_err(op.to_canonical(out, hd.DWF_C64).cpu().numpy(), want)
+    print(f"M_IRS c64 rel err {err:.2e}", flush=True)
+    assert err < 2e-5
+
+
+def test_hdcg_solve_small(two_level):
+    t = two_level
+    banner(f"hdcg_solve {t['name']}")
+    op, h, ref = t["op"], t["h"], t["ref"]
+    b = synth.gaussian_half_field(t["dims"], t["Ls"], 350)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    print(st, flush=True)
+    assert rc == 0 and st["converged"] == 1
+    xc = op.to_canonical(x).cpu().numpy()
+    r = b - ref.H(xc)
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+
+
+def test_hdcg_inverse_iteration_and_multi_rhs():
+    """Setup with two inverse-iteration steps, then two right-hand sides at once."""
+    name = "12^4xLs2-b4-n2"
+    banner(f"hdcg n_ii=2 nrhs=2 {name}")
+    dims, Ls, block, nvec, raw, op, h, ref = _setup(name, n_ii=2)
+    b = synth.gaussian_half_field(dims, Ls, 360, nrhs=2)
+    x = op.new_field(nrhs=2)
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 2, 1e-8)
+    assert rc == 0
+    xc = op.to_canonical(x, nrhs=2).cpu().numpy()
+    for i in range(2):
+        r = b[i] - ref.H(xc[i])
+        assert np.sqrt(np.vdot(r, r).real / np.vdot(b[i], b[i]).real) <= 1e-8
+    # orthonormal blocks after inverse iteration
+    P = h.subspace().cpu().numpy()
+    _, _, sob = oblk.block_map(dims, block)
+    Pb = oblk.to_blocks(P, sob)
+    for a in (0, 40):
+        G = Pb[:, a, :].conj() @ Pb[:, a, :].T
+        assert np.abs(G - np.eye(nvec)).max() < 1e-12
+    h.close()
+    op.close()
+
+
+def test_setup_rejects_bad_blocks():
+    banner("setup geometry errors")
+    dims, Ls = (8, 8, 8, 8), 2
+    op = hd.FineOperator(synth.gauge_field(dims, 0.5, 1), dims, Ls, 1.8, 0.01)
+    v = synth.gaussian_half_field(dims, Ls, 2, nrhs=1)
+    with pytest.raises(hd.HdcgError) as e:
+        hd.HDCG(op, (4, 4, 4, 4), v)  # coarse extent 2 < 3
+    assert e.value.code == -2
+    with pytest.raises(hd.HdcgError):
+        hd.HDCG(op, (2, 4, 4, 4), v)
+    op.close()
