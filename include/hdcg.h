@@ -150,6 +150,8 @@ struct hdcg_params {
   int inner_maxiter;  /* inner iteration cap */
   int outer_maxiter;  /* FP64 defect-correction restarts cap */
   int build_batch;    /* probe vectors per H application batch in the coarse build */
+  int coarse_prec;    /* storage of A inside Q: DWF_C64 (VALU, default), DWF_BF16 or DWF_F16
+                         (MFMA with FP32 accumulation, per-matrix scales; nvec % 4 == 0) */
 };
 
 struct hdcg_stats {
@@ -198,11 +200,15 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
 
 /* out[rhs][a][j] = sum_l sum_k A[a][l][j][k] in[rhs][a + delta_l][k]:
  * the 81-point block stencil of the little Dirac operator (Sec. V.A);
- * prec C128 or C64; asynchronous; out != in. */
+ * prec C128 or C64 (VALU, vectors in that precision), or BF16 / F16: the
+ * matrix stored in 16 bits with one scale per stencil matrix A[a][l], the
+ * complex64 vectors rounded to 16 bits, products accumulated in FP32 on MFMA
+ * (vectors in/out complex64).  Asynchronous; out != in. */
 int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream);
 
 /* CG on A x = b (A Hermitian positive definite, Sec. V.B) from x = 0 to
- * |r| <= tol |b| for every RHS; *iters receives the iteration count.
+ * |r| <= tol |b| for every RHS, with the mat-vec of coarse_apply in precision
+ * prec (BF16 / F16 use complex64 vectors); *iters receives the iteration count.
  * Synchronises; DWF_NOT_CONVERGED at maxiter. */
 int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
                       int* iters, void* stream);

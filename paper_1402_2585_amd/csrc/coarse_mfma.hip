@@ -1,0 +1,278 @@
+// Little Dirac operator mat-vec on MFMA with 16-bit matrix storage
+// (bf16 or fp16) and FP32 accumulation.
+//
+// For one coarse site a the 81-point stencil is one real GEMM
+//   out[j][n] = sum_kappa Ahat[j][kappa] B[kappa][n]
+// with kappa = (part, l, k) over K = 2 * 81 * Nvec:
+//   Ahat[j][(0,l,k)] = Re A[a][l][j][k] / s_al,  Ahat[j][(1,l,k)] = Im A[a][l][j][k] / s_al
+//   B[(0,l,k)][r]          = rho_al Re c_r[a+dl][k],   B[(1,l,k)][r]          = -rho_al Im c_r[a+dl][k]
+//   B[(0,l,k)][nrhs + r]   = rho_al Im c_r[a+dl][k],   B[(1,l,k)][nrhs + r]   =  rho_al Re c_r[a+dl][k]
+// so that columns r and nrhs + r give Re and Im of (A c_r)[a][j] / smax_a.
+// s_al is the largest |Re|, |Im| entry of the matrix A[a][l] (per-matrix
+// scale), smax_a = max_l s_al and rho_al = s_al / smax_a <= 1, which keeps
+// both operands within the fp16 range.
+//
+// Ahat is stored in MFMA fragment order [a][kstep][mtile][lane][4] so that a
+// wave reads 512 contiguous bytes per fragment.  One workgroup (4 waves) per
+// coarse site; the waves split the K steps and reduce through LDS.
+#include "hdcg_impl.h"
+
+namespace hdk {
+
+namespace {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ unsigned short f2h(float f) {
+  _Float16 h = (_Float16)f;
+  return __builtin_bit_cast(unsigned short, h);
+}
+
+template <bool BF16>
+__device__ __forceinline__ unsigned short to16(float f) {
+  return BF16 ? f2bf(f) : f2h(f);
+}
+
+// per-matrix scales: s[a][l] = max |Re|, |Im| over A[a][l]
+__global__ void k_scales(const c128* __restrict__ A, float* __restrict__ s, int nvec2) {
+  const int al = blockIdx.x;
+  const c128* M = A + (size_t)al * nvec2;
+  float m = 0.f;
+  for (int e = threadIdx.x; e < nvec2; e += blockDim.x) {
+    const c128 v = M[e];
+    m = fmaxf(m, fmaxf(fabsf((float)v.re), fabsf((float)v.im)));
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s[al] = red[0];
+}
+
+// rho[a][l] = s_al / smax_a (in place), smax[a]
+__global__ void k_rho(float* __restrict__ s, float* __restrict__ smax, int Nc) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= Nc) return;
+  float m = 0.f;
+  for (int l = 0; l < kStencil; ++l) m = fmaxf(m, s[a * kStencil + l]);
+  smax[a] = m;
+  for (int l = 0; l < kStencil; ++l) {
+    const float v = s[a * kStencil + l];
+    s[a * kStencil + l] = m > 0.f ? v / m : 0.f;
+  }
+}
+
+template <bool BF16>
+__global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho,
+                       const float* __restrict__ smax, unsigned short* __restrict__ F, int Nc,
+                       int nvec, int mtiles, int ksteps) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one (a, s, mt, lane)
+  const size_t total = (size_t)Nc * ksteps * mtiles * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int mt = (int)((e / 64) % mtiles);
+  const size_t as = e / (64 * (size_t)mtiles);
+  const int s = (int)(as % ksteps);
+  const int a = (int)(as / ksteps);
+  const int m = mt * 16 + (lane & 15);
+  const int ktot = 2 * kStencil * nvec;
+  unsigned short v4[4];
+  for (int i = 0; i < 4; ++i) {
+    const int kap = 16 * s + 4 * (lane >> 4) + i;
+    float v = 0.f;
+    if (m < nvec && kap < ktot) {
+      const int part = kap / (kStencil * nvec);
+      const int rem = kap - part * kStencil * nvec;
+      const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
+      const float sal = rho[a * kStencil + l] * smax[a];
+      const c128 x = A[(((size_t)a * kStencil + l) * nvec + m) * nvec + k];
+      v = sal > 0.f ? (float)((part == 0 ? x.re : x.im) / sal) : 0.f;
+    }
+    v4[i] = to16<BF16>(v);
+  }
+  unsigned short* o = F + e * 4;
+  for (int i = 0; i < 4; ++i) o[i] = v4[i];
+}
+
+template <bool BF16, int MT, int NT>
+__global__ void __launch_bounds__(256)
+k_capply_mfma(const unsigned short* __restrict__ F, const float* __restrict__ rho,
+              const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
+              c64* __restrict__ out, int Nc, int nvec, int nrhs, int ksteps) {
+  __shared__ f32x4 red[4][MT * NT][64];
+  const int a = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ktot = 2 * kStencil * nvec;
+  const int kn = kStencil * nvec;
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const unsigned short* Fa = F + (size_t)a * ksteps * MT * 64 * 4;
+  const int* nb = nbr + (size_t)a * kStencil;
+  const float* rh = rho + (size_t)a * kStencil;
+  for (int s = wave; s < ksteps; s += 4) {
+    s16x4 af[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      af[mt] = *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * MT + mt) * 64 + lane) * 4);
+    const int k0 = 16 * s + 4 * (lane >> 4);
+    s16x4 bf[NT];
+    if (k0 < ktot) {
+      const int part = k0 / kn;
+      const int rem = k0 - part * kn;
+      const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
+      const float r = rh[l];
+      const size_t vo = (size_t)nb[l] * nvec + k;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int g = nt * 16 + (lane & 15);
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (g < 2 * nrhs) {
+          const bool imcol = g >= nrhs;
+          const int rr = imcol ? g - nrhs : g;
+          const c64* c = in + (size_t)rr * Nc * nvec + vo;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const c64 x = c[i];
+            // columns r:        part 0 -> Re c, part 1 -> -Im c
+            // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
+            v[i] = imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im);
+            v[i] *= r;
+          }
+        }
+        s16x4 b;
+        b.x = (short)to16<BF16>(v[0]);
+        b.y = (short)to16<BF16>(v[1]);
+        b.z = (short)to16<BF16>(v[2]);
+        b.w = (short)to16<BF16>(v[3]);
+        bf[nt] = b;
+      }
+    } else {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bf[nt] = s16x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        if (BF16)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
+        else
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[mt]),
+                                                              __builtin_bit_cast(h16x4, bf[nt]),
+                                                              acc[mt][nt], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) red[wave][mt * NT + nt][lane] = acc[mt][nt];
+  __syncthreads();
+  if (wave != 0) return;
+  const float sm = smax[a];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      f32x4 v = red[0][mt * NT + nt][lane];
+      for (int w = 1; w < 4; ++w) v += red[w][mt * NT + nt][lane];
+      // lane holds D[m = 4 (lane / 16) + i][n = lane % 16]
+      const int g = nt * 16 + (lane & 15);
+      if (g >= 2 * nrhs) continue;
+      const bool imcol = g >= nrhs;
+      const int rr = imcol ? g - nrhs : g;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = mt * 16 + 4 * (lane >> 4) + i;
+        if (m >= nvec) continue;
+        float* o = reinterpret_cast<float*>(out + ((size_t)rr * Nc + a) * nvec + m);
+        o[imcol ? 1 : 0] = sm * v[i];
+      }
+    }
+}
+
+template <bool BF16, int MT>
+int launch_mt(hdcg* h, const unsigned short* F, const c64* in, c64* out, int nr, int ksteps,
+              hipStream_t st) {
+  const float* rho = h->mf_rho.as<float>();
+  const float* smax = h->mf_smax.as<float>();
+  for (int r0 = 0; r0 < nr; r0 += 16) {
+    const int n = nr - r0 < 16 ? nr - r0 : 16;
+    const c64* i0 = in + (size_t)r0 * h->Nc * h->nvec;
+    c64* o0 = out + (size_t)r0 * h->Nc * h->nvec;
+    if (2 * n <= 16)
+      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 1>), dim3(h->Nc), dim3(256), 0, st, F, rho, smax,
+                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps);
+    else
+      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2>), dim3(h->Nc), dim3(256), 0, st, F, rho, smax,
+                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps);
+    HDCG_HIP(hipGetLastError());
+  }
+  return DWF_OK;
+}
+
+}  // namespace
+
+int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
+  const int nv = h->nvec;
+  if (nv % 4 != 0 || nv > 64)
+    return fail(DWF_ERR_ARG, "16-bit coarse storage needs nvec a multiple of 4 and <= 64");
+  const int mtiles = (nv + 15) / 16;
+  const int ksteps = (2 * kStencil * nv + 15) / 16;
+  if (h->mf_smax.bytes == 0) {
+    HDCG_TRY(h->mf_rho.ensure(sizeof(float) * h->Nc * kStencil));
+    HDCG_TRY(h->mf_smax.ensure(sizeof(float) * h->Nc));
+    hipLaunchKernelGGL(k_scales, dim3(h->Nc * kStencil), dim3(256), 0, st, h->A128.as<c128>(),
+                       h->mf_rho.as<float>(), nv * nv);
+    HDCG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rho, dim3((h->Nc + 127) / 128), dim3(128), 0, st, h->mf_rho.as<float>(),
+                       h->mf_smax.as<float>(), h->Nc);
+    HDCG_HIP(hipGetLastError());
+  }
+  DevBuf& F = prec == DWF_BF16 ? h->mf_bf16 : h->mf_f16;
+  const size_t total = (size_t)h->Nc * ksteps * mtiles * 64;
+  HDCG_TRY(F.ensure(total * 4 * sizeof(unsigned short)));
+  if (prec == DWF_BF16)
+    hipLaunchKernelGGL((k_frag<true>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
+                       F.as<unsigned short>(), h->Nc, nv, mtiles, ksteps);
+  else
+    hipLaunchKernelGGL((k_frag<false>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
+                       F.as<unsigned short>(), h->Nc, nv, mtiles, ksteps);
+  HDCG_HIP(hipGetLastError());
+  if (prec == DWF_BF16)
+    h->mf_have_bf16 = 1;
+  else
+    h->mf_have_f16 = 1;
+  return DWF_OK;
+}
+
+int crs_apply_mfma(hdcg* h, int prec, const c64* in, c64* out, int nr, hipStream_t st) {
+  if ((prec == DWF_BF16 && !h->mf_have_bf16) || (prec == DWF_F16 && !h->mf_have_f16))
+    HDCG_TRY(crs_build_mfma(h, prec, st));
+  const int mtiles = (h->nvec + 15) / 16;
+  const int ksteps = (2 * kStencil * h->nvec + 15) / 16;
+  const unsigned short* F = (prec == DWF_BF16 ? h->mf_bf16 : h->mf_f16).as<unsigned short>();
+  const bool bf = prec == DWF_BF16;
+  switch (mtiles) {
+    case 1: return bf ? launch_mt<true, 1>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 1>(h, F, in, out, nr, ksteps, st);
+    case 2: return bf ? launch_mt<true, 2>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 2>(h, F, in, out, nr, ksteps, st);
+    case 3: return bf ? launch_mt<true, 3>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 3>(h, F, in, out, nr, ksteps, st);
+    default: return bf ? launch_mt<true, 4>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 4>(h, F, in, out, nr, ksteps, st);
+  }
+}
+
+}  // namespace hdk

@@ -32,10 +32,13 @@ struct hdcg {
   hdk::DevBuf gram, rinv;     // [Nc][nvec][nvec] c128 Cholesky-QR work
   hdk::DevBuf flag;           // int error flag
   hdk::DevBuf cw[6];          // coarse work vectors (c64/c128)
-  hdk::DevBuf fw64[8];        // fine c64 work fields
+  hdk::DevBuf fw64[12];       // fine c64 work fields: 0-7 solver, 8-10 fine CG
   hdk::DevBuf fw128[3];       // fine c128 work fields
   hdk::DevBuf scal;           // device scalars
   hdk::DevBuf probe_c;        // coarse probe vectors for the build
+  hdk::DevBuf mf_rho, mf_smax;      // per-matrix scales of the 16-bit coarse storage
+  hdk::DevBuf mf_bf16, mf_f16;      // MFMA fragment-ordered 16-bit coarse matrices
+  int mf_have_bf16 = 0, mf_have_f16 = 0;
   double* pinned = nullptr;   // host pinned scalars
   struct {
     int n_ii = 0;
@@ -50,6 +53,7 @@ struct hdcg {
     int inner_maxiter = 500;
     int outer_maxiter = 50;
     int build_batch = 8;
+    int coarse_prec = DWF_C64;  // storage of A inside Q: C64 (VALU), BF16 / F16 (MFMA)
   } prm;
   double setup_seconds = 0.0;
   long long setup_matmuls = 0;
@@ -78,5 +82,7 @@ template <typename R>
 int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);
 int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_t st);
 int crs_transpose(hdcg* h, hipStream_t st);  // A128 -> AT128, AT64
+int crs_build_mfma(hdcg* h, int prec, hipStream_t st);
+int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
 
 }  // namespace hdk

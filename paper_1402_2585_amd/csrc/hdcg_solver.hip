@@ -154,7 +154,7 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
 // -------------------------------------------------------------- coarse CG --
 template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
-              int maxiter, int* iters, hipStream_t st) {
+              int maxiter, int* iters, hipStream_t st, int mprec = -1) {
   const size_t n = (size_t)h->Nc * h->nvec;
   for (int i = 0; i < 3; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
   cplx<R>* r = h->cw[0].as<cplx<R>>();
@@ -180,7 +180,14 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
     while (!done && k < maxiter) {
       double* cur = rr[k & 1];
       double* nxt = rr[(k + 1) & 1];
-      HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
+      if constexpr (sizeof(R) == 4) {
+        if (mprec == DWF_BF16 || mprec == DWF_F16)
+          HDCG_TRY(crs_apply_mfma(h, mprec, p, w, nr, st));
+        else
+          HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
+      } else {
+        HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
+      }
       HDCG_TRY(b_dot<R>(red, p, w, n, nr, pap, st));
       HDCG_TRY(b_update<R>(red, x, r, p, w, n, nr, cur, false, pap, nullptr, 0.0, nxt, st, 2));
       HDCG_TRY(b_xpay<R>(red, p, r, n, nr, nxt, false, cur, 1.0, nullptr, st));
@@ -217,7 +224,7 @@ static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, do
                           nullptr, st));
   int it = 0;
   HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter,
-                            &it, st));
+                            &it, st, h->prm.coarse_prec));
   if (citers) *citers += it;
   HDCG_TRY(blk_promote<float>(h, h->phi64.as<c64>(), cx, nr, out, base, sign, fine_elems(h), st));
   return DWF_OK;
@@ -335,6 +342,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->inner_maxiter = 500;
   p->outer_maxiter = 50;
   p->build_batch = 8;
+  p->coarse_prec = DWF_C64;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -355,6 +363,10 @@ int hdcg_destroy(hdcg_t h) {
   for (auto& b : h->fw128) b.release();
   h->scal.release();
   h->probe_c.release();
+  h->mf_rho.release();
+  h->mf_smax.release();
+  h->mf_bf16.release();
+  h->mf_f16.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return DWF_OK;
@@ -480,6 +492,8 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   }
   HDCG_TRY(crs_idft(h, h->A128.as<c128>(), finv, st));
   HDCG_TRY(crs_transpose(h, st));
+  if (h->prm.coarse_prec == DWF_BF16 || h->prm.coarse_prec == DWF_F16)
+    HDCG_TRY(crs_build_mfma(h, h->prm.coarse_prec, st));
   HDCG_HIP(hipStreamSynchronize(st));
   h->fw128[1].release();
   h->fw128[2].release();
@@ -526,6 +540,11 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.inner_maxiter = p->inner_maxiter;
     h->prm.outer_maxiter = p->outer_maxiter;
     h->prm.build_batch = p->build_batch;
+    h->prm.coarse_prec = p->coarse_prec;
+    if (h->prm.coarse_prec != DWF_C64 && h->prm.coarse_prec != DWF_BF16 && h->prm.coarse_prec != DWF_F16) {
+      delete h;
+      return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");
+    }
   }
   if (hipHostMalloc((void**)&h->pinned, 64 * 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     h->pinned = nullptr;
@@ -611,9 +630,11 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
 }
 
 int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream) {
-  HDCG_TRY(check_h(h, prec, nrhs));
+  const bool m16 = prec == DWF_BF16 || prec == DWF_F16;
+  HDCG_TRY(check_h(h, m16 ? DWF_C64 : prec, nrhs));
   if (!out || !in || out == in) return fail(DWF_ERR_ARG, "coarse_apply needs distinct in/out buffers");
   auto st = static_cast<hipStream_t>(stream);
+  if (m16) return crs_apply_mfma(h, prec, static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
   if (prec == DWF_C128)
     return crs_apply<double>(h, h->AT128.as<c128>(), static_cast<const c128*>(in), static_cast<c128*>(out), nrhs, st);
   return crs_apply<float>(h, h->AT64.as<c64>(), static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
@@ -621,7 +642,8 @@ int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* 
 
 int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
                       int* iters, void* stream) {
-  HDCG_TRY(check_h(h, prec, nrhs));
+  const bool m16 = prec == DWF_BF16 || prec == DWF_F16;
+  HDCG_TRY(check_h(h, m16 ? DWF_C64 : prec, nrhs));
   if (!x || !b || !(tol > 0)) return fail(DWF_ERR_ARG, "bad arguments to hdcg_coarse_solve");
   auto st = static_cast<hipStream_t>(stream);
   int it = 0;
@@ -630,7 +652,7 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
                                tol, maxiter, &it, st));
   else
     HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), static_cast<c64*>(x), static_cast<const c64*>(b), nrhs, tol,
-                              maxiter, &it, st));
+                              maxiter, &it, st, m16 ? prec : -1));
   HDCG_HIP(hipStreamSynchronize(st));
   if (iters) *iters = it;
   return it >= maxiter ? DWF_NOT_CONVERGED : DWF_OK;
@@ -695,9 +717,12 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
       status = DWF_NOT_CONVERGED;
       break;
     }
-    // inner complex64 solve on the normalised residual, x += |r| e
+    // inner complex64 solve on the normalised residual, x += |r| e; the inner
+    // target is only as tight as the remaining reduction needs (never below
+    // the complex64 floor inner_tol)
     HDCG_TRY(b_scale_copy<float, double>(r64, r, orr, true, fe, nrhs, st));
-    HDCG_TRY(adef2(h, e64, r64, nrhs, h->prm.inner_tol, h->prm.inner_maxiter, &is, st));
+    const double itol = std::max(h->prm.inner_tol, 0.5 * tol / rel);
+    HDCG_TRY(adef2(h, e64, r64, nrhs, itol, h->prm.inner_maxiter, &is, st));
     HDCG_TRY(b_axpy_mixed<double, float>(x, e64, orr, fe, nrhs, st, true));
     ++outer;
   }

@@ -6,7 +6,10 @@ operator by brute force); nothing flows from the GPU into the oracle.
 
 Tolerances: FP64 results 1e-12 relative (max-norm over the array); complex64
 results 2e-5 (sums of ~10^4 terms in float32, eps 6e-8, against O(1) data);
-integer maps bit-exact; solves to their stated residual.
+16-bit coarse storage: bf16 1e-2 and fp16 2e-3 (operands rounded to 8 and 11
+significant bits, relative rounding 2^-9 and 2^-12 per operand, products summed
+in FP32 over K = 2*81*Nvec terms); integer maps bit-exact; solves to their
+stated residual.
 """
 import numpy as np
 import pytest
@@ -28,7 +31,7 @@ import paper_1402_2585_amd as hd  # noqa: E402
 
 GEOMS = {
     # name: dims, Ls, block, nvec, eps, mass
-    "12^4xLs2-b4-n2": ((12, 12, 12, 12), 2, (4, 4, 4, 4), 2, 0.5, 0.01),
+    "12^4xLs2-b4-n4": ((12, 12, 12, 12), 2, (4, 4, 4, 4), 4, 0.5, 0.01),
     "12x12x18x12xLs2-b4x4x6x4-n3": ((12, 12, 18, 12), 2, (4, 4, 6, 4), 3, 0.6, 0.05),
 }
 
@@ -112,6 +115,24 @@ def test_coarse_apply(two_level):
         assert rel_err(out.cpu().numpy(), want) < tol
 
 
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_coarse_apply_mfma_16bit(two_level, nrhs):
+    t = two_level
+    h = t["h"]
+    if h.nvec % 4:
+        pytest.skip("16-bit coarse storage needs nvec % 4 == 0")
+    banner(f"coarse apply MFMA {t['name']} nrhs={nrhs}")
+    c = synth.rng(325).standard_normal((nrhs, h.Nc, h.nvec)) + 1j * synth.rng(326).standard_normal((nrhs, h.Nc, h.nvec))
+    want = ocrs.apply(t["A"], c, t["C"])
+    inp = torch.from_numpy(c).to("cuda", torch.complex64).contiguous()
+    for prec, tol in ((hd.DWF_BF16, 1e-2), (hd.DWF_F16, 2e-3)):
+        out = h.new_coarse(hd.DWF_C64, nrhs)
+        hd.coarse_apply(h.h, out, inp, prec, nrhs)
+        err = rel_err(out.cpu().numpy(), want)
+        print(f"prec {prec} rel err {err:.2e}", flush=True)
+        assert err < tol
+
+
 def test_coarse_solve(two_level):
     t = two_level
     banner(f"coarse solve {t['name']}")
@@ -158,9 +179,30 @@ def test_hdcg_solve_small(two_level):
     assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
 
 
+@pytest.mark.parametrize("cprec", [hd.DWF_BF16, hd.DWF_F16])
+def test_hdcg_solve_16bit_coarse(cprec):
+    name = "12^4xLs2-b4-n4"
+    banner(f"hdcg_solve coarse_prec={cprec} {name}")
+    dims, Ls, block, nvec, eps, mass = GEOMS[name]
+    U = synth.gauge_field(dims, eps, 300)
+    raw = synth.gaussian_half_field(dims, Ls, 301, nrhs=nvec)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass)
+    h = hd.HDCG(op, block, raw, coarse_prec=cprec)
+    ref = DWF(U, dims, Ls, 1.8, mass)
+    b = synth.gaussian_half_field(dims, Ls, 355)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    assert rc == 0
+    xc = op.to_canonical(x).cpu().numpy()
+    r = b - ref.H(xc)
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+    h.close()
+    op.close()
+
+
 def test_hdcg_inverse_iteration_and_multi_rhs():
     """Setup with two inverse-iteration steps, then two right-hand sides at once."""
-    name = "12^4xLs2-b4-n2"
+    name = "12^4xLs2-b4-n4"
     banner(f"hdcg n_ii=2 nrhs=2 {name}")
     dims, Ls, block, nvec, raw, op, h, ref = _setup(name, n_ii=2)
     b = synth.gaussian_half_field(dims, Ls, 360, nrhs=2)
