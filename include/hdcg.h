@@ -152,6 +152,7 @@ struct hdcg_params {
   int build_batch;    /* probe vectors per H application batch in the coarse build */
   int coarse_prec;    /* storage of A inside Q: DWF_C64 (VALU, default), DWF_BF16 or DWF_F16
                          (MFMA with FP32 accumulation, per-matrix scales; nvec % 4 == 0) */
+  int verbose;        /* 1: hdcg_setup prints stage progress to stderr */
 };
 
 struct hdcg_stats {

@@ -43,7 +43,7 @@ class HdcgParams(C.Structure):
                 ("maxiter_ii", C.c_int), ("n_irs", C.c_int), ("lambda_irs", C.c_double),
                 ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("flexible", C.c_int),
                 ("inner_tol", C.c_double), ("inner_maxiter", C.c_int), ("outer_maxiter", C.c_int),
-                ("build_batch", C.c_int), ("coarse_prec", C.c_int)]
+                ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int)]
 
 
 class HdcgStats(C.Structure):

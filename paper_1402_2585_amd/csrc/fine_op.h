@@ -90,6 +90,7 @@ template <typename Rd, typename Rs>
 int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t stream);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
+void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)
 int ensure_reducer(dwf_op* op);
 
 }  // namespace hdk

@@ -479,6 +479,11 @@ int ensure_reducer(dwf_op* op) {
   return DWF_OK;
 }
 
+void release_tmp(dwf_op* op) {
+  for (auto& a : op->tmp)
+    for (auto& b : a) b.release();
+}
+
 int ensure_tmp(dwf_op* op, int prec, int nrhs) {
   const size_t bytes = op->field_elems(nrhs) * cbytes(prec);
   const int pi = prec == DWF_C128 ? 0 : 1;

@@ -54,6 +54,7 @@ struct hdcg {
     int outer_maxiter = 50;
     int build_batch = 8;
     int coarse_prec = DWF_C64;  // storage of A inside Q: C64 (VALU), BF16 / F16 (MFMA)
+    int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;
   long long setup_matmuls = 0;
@@ -81,7 +82,7 @@ int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
 template <typename R>
 int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);
 int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_t st);
-int crs_transpose(hdcg* h, hipStream_t st);  // A128 -> AT128, AT64
+int crs_transpose(hdcg* h, bool fp64, hipStream_t st);  // A128 -> AT128 (fp64) or AT64
 int crs_build_mfma(hdcg* h, int prec, hipStream_t st);
 int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
 

@@ -134,8 +134,8 @@ k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fs
 template <typename R, int NR>
 __global__ void __launch_bounds__(kT)
 k_promote(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int Nc, int nvec,
-          size_t nb, int nsb, int col, const int* __restrict__ site_of, cplx<R>* __restrict__ out,
-          const cplx<R>* __restrict__ base, R sign, size_t fstride) {
+          size_t nb, int nsb, int col, const int* __restrict__ site_of, cplx<R>* out,
+          const cplx<R>* base, R sign, size_t fstride) {  // out may alias base (in place)
   __shared__ cplx<R> cs[NR * 64];
   const int a = blockIdx.y;
   const size_t i = (size_t)blockIdx.x * kT + threadIdx.x;
@@ -293,8 +293,8 @@ __global__ void k_transpose(const c128* __restrict__ A, c128* __restrict__ AT128
   const int j = jk / nvec, k = jk - j * nvec;
   const c128 v = A[e];
   const size_t o = al * n2 + (size_t)k * nvec + j;
-  AT128[o] = v;
-  AT64[o] = cmk((float)v.re, (float)v.im);
+  if (AT128) AT128[o] = v;
+  if (AT64) AT64[o] = cmk((float)v.re, (float)v.im);
 }
 
 // (A c)[r][a][j] = sum_l sum_k A[a][l][j][k] c[r][nbr(a,l)][k], with AT[a][l][k][j].
@@ -447,12 +447,15 @@ int crs_idft(hdcg* h, c128* Y, const c128 finv[4][9], hipStream_t st) {
   return DWF_OK;
 }
 
-int crs_transpose(hdcg* h, hipStream_t st) {
+int crs_transpose(hdcg* h, bool fp64, hipStream_t st) {
   const size_t total = (size_t)h->Nc * kStencil * h->nvec * h->nvec;
-  HDCG_TRY(h->AT128.ensure(total * sizeof(c128)));
-  HDCG_TRY(h->AT64.ensure(total * sizeof(c64)));
+  if (fp64)
+    HDCG_TRY(h->AT128.ensure(total * sizeof(c128)));
+  else
+    HDCG_TRY(h->AT64.ensure(total * sizeof(c64)));
   hipLaunchKernelGGL(k_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     h->A128.as<c128>(), h->AT128.as<c128>(), h->AT64.as<c64>(), h->nvec, total);
+                     h->A128.as<c128>(), fp64 ? h->AT128.as<c128>() : nullptr,
+                     fp64 ? nullptr : h->AT64.as<c64>(), h->nvec, total);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -235,10 +236,11 @@ struct InnerStats {
   double matmuls32 = 0;
 };
 
-// y = M_1 r = P_R M_IRS r + Q r = z - Q (H z - r), z = M_IRS r
+// y = M_1 r = P_R M_IRS r + Q r = z - Q (H z - r), z = M_IRS r.  z is
+// computed in y's storage and the correction subtracted in place.
 static int precondition(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, hipStream_t st) {
   const size_t n = fine_elems(h);
-  c64* z = h->fw64[4].as<c64>();
+  c64* z = y;
   c64* t = h->fw64[6].as<c64>();
   int it = 0;
   HDCG_TRY(fine_cg(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, 0.0, 0, &it, st));
@@ -258,7 +260,7 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
                  hipStream_t st) {
   dwf_op* op = h->op;
   const size_t n = fine_elems(h);
-  for (int i = 1; i <= 6; ++i) HDCG_TRY(ensure_fine64(h, i, nr));
+  for (int i : {1, 2, 3, 5, 6}) HDCG_TRY(ensure_fine64(h, i, nr));
   c64* r = h->fw64[1].as<c64>();
   c64* p = h->fw64[2].as<c64>();
   c64* w = h->fw64[3].as<c64>();
@@ -343,6 +345,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->outer_maxiter = 50;
   p->build_batch = 8;
   p->coarse_prec = DWF_C64;
+  p->verbose = 0;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -388,26 +391,38 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   HDCG_TRY(work.ensure(fe * nv * sizeof(c128)));
   HDCG_HIP(hipMemcpyAsync(work.ptr, vectors, fe * nv * sizeof(c128), hipMemcpyDeviceToDevice, st));
   if (h->prm.n_ii > 0) {
-    HDCG_TRY(h->fw128[0].ensure(fe * sizeof(c128)));
-    HDCG_TRY(ensure_fine64(h, 0, 1));
-    HDCG_TRY(ensure_fine64(h, 1, 1));
+    const int G = std::min(nv, 8);
+    HDCG_TRY(h->fw128[0].ensure(fe * G * sizeof(c128)));
+    HDCG_TRY(ensure_fine64(h, 0, G));
+    HDCG_TRY(ensure_fine64(h, 1, G));
     c128* v128 = h->fw128[0].as<c128>();
     c64* v = h->fw64[0].as<c64>();
     c64* xv = h->fw64[1].as<c64>();
     double* nrm = slot(h, S_ORR);
-    for (int k = 0; k < nv; ++k) {
-      c128* can = work.as<c128>() + (size_t)k * fe;
-      HDCG_TRY(dwf_import(op, v128, can, DWF_C128, 1, st));
-      HDCG_TRY(launch_convert<float, double>(v, v128, fe, st));
+    // groups of vectors share one multi-RHS CG (all of a group iterate until
+    // every member reaches tol_ii)
+    for (int k0 = 0; k0 < nv; k0 += G) {
+      const int g = std::min(G, nv - k0);
+      c128* can = work.as<c128>() + (size_t)k0 * fe;
+      HDCG_TRY(dwf_import(op, v128, can, DWF_C128, g, st));
+      HDCG_TRY(launch_convert<float, double>(v, v128, fe * g, st));
+      int its = 0;
       for (int s = 0; s < h->prm.n_ii; ++s) {
         int it = 0;
-        HDCG_TRY(fine_cg(h, xv, v, 1, h->prm.lambda_ii, 0, h->prm.tol_ii, h->prm.maxiter_ii, &it, st));
-        h->setup_matmuls += it;
-        HDCG_TRY(b_norm2<float>(red_of(op), xv, fe, 1, nrm, st));
-        HDCG_TRY(b_scale_copy<float, float>(v, xv, nrm, true, fe, 1, st));  // normalise
+        HDCG_TRY(fine_cg(h, xv, v, g, h->prm.lambda_ii, 0, h->prm.tol_ii, h->prm.maxiter_ii, &it, st));
+        h->setup_matmuls += (long long)it * g;
+        its += it;
+        HDCG_TRY(b_norm2<float>(red_of(op), xv, fe, g, nrm, st));
+        HDCG_TRY(b_scale_copy<float, float>(v, xv, nrm, true, fe, g, st));  // normalise
       }
-      HDCG_TRY(launch_convert<double, float>(v128, v, fe, st));
-      HDCG_TRY(dwf_export(op, can, v128, DWF_C128, 1, st));
+      HDCG_TRY(launch_convert<double, float>(v128, v, fe * g, st));
+      HDCG_TRY(dwf_export(op, can, v128, DWF_C128, g, st));
+      if (h->prm.verbose) {
+        HDCG_HIP(hipStreamSynchronize(st));
+        std::fprintf(stderr, "[hdcg_setup] inverse iteration: vectors %d-%d done, %d CG iterations\n", k0,
+                     k0 + g - 1, its);
+        std::fflush(stderr);
+      }
     }
   }
   HDCG_TRY(h->phi128.ensure(fe * nv * sizeof(c128)));
@@ -471,6 +486,10 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
                                zbuf.as<c128>() + h->Nc, st));
     }
     HDCG_HIP(hipStreamSynchronize(st));  // z is rewritten next
+    if (h->prm.verbose && (s % 9 == 8)) {
+      std::fprintf(stderr, "[hdcg_setup] coarse operator: %d of 81 momenta done\n", s + 1);
+      std::fflush(stderr);
+    }
   }
   // invert M_sl = prod_mu exp(i p^s_mu delta^l_mu) one dimension at a time
   c128 finv[4][9];
@@ -491,13 +510,15 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
       for (int b = 0; b < 3; ++b) finv[mu][a * 3 + b] = cmk(I[a][b].real(), I[a][b].imag());
   }
   HDCG_TRY(crs_idft(h, h->A128.as<c128>(), finv, st));
-  HDCG_TRY(crs_transpose(h, st));
+  HDCG_TRY(crs_transpose(h, false, st));
   if (h->prm.coarse_prec == DWF_BF16 || h->prm.coarse_prec == DWF_F16)
     HDCG_TRY(crs_build_mfma(h, h->prm.coarse_prec, st));
   HDCG_HIP(hipStreamSynchronize(st));
-  h->fw128[1].release();
-  h->fw128[2].release();
+  // setup-only work memory goes back before the solve allocates its own
+  for (int i = 0; i < 3; ++i) h->fw128[i].release();
+  for (int i : {0, 1, 8, 9, 10}) h->fw64[i].release();
   h->probe_c.release();
+  release_tmp(op);
   return DWF_OK;
 }
 
@@ -541,6 +562,7 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.outer_maxiter = p->outer_maxiter;
     h->prm.build_batch = p->build_batch;
     h->prm.coarse_prec = p->coarse_prec;
+    h->prm.verbose = p->verbose;
     if (h->prm.coarse_prec != DWF_C64 && h->prm.coarse_prec != DWF_BF16 && h->prm.coarse_prec != DWF_F16) {
       delete h;
       return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");
@@ -629,14 +651,21 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
                             static_cast<c64*>(fine_out), nullptr, 1.0, fe, st);
 }
 
+static int ensure_at128(hdcg* h, hipStream_t st) {
+  if (h->AT128.bytes == 0) HDCG_TRY(crs_transpose(h, true, st));
+  return DWF_OK;
+}
+
 int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream) {
   const bool m16 = prec == DWF_BF16 || prec == DWF_F16;
   HDCG_TRY(check_h(h, m16 ? DWF_C64 : prec, nrhs));
   if (!out || !in || out == in) return fail(DWF_ERR_ARG, "coarse_apply needs distinct in/out buffers");
   auto st = static_cast<hipStream_t>(stream);
   if (m16) return crs_apply_mfma(h, prec, static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
-  if (prec == DWF_C128)
+  if (prec == DWF_C128) {
+    HDCG_TRY(ensure_at128(h, st));
     return crs_apply<double>(h, h->AT128.as<c128>(), static_cast<const c128*>(in), static_cast<c128*>(out), nrhs, st);
+  }
   return crs_apply<float>(h, h->AT64.as<c64>(), static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
 }
 
@@ -648,9 +677,11 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
   auto st = static_cast<hipStream_t>(stream);
   int it = 0;
   if (prec == DWF_C128)
+  {
+    HDCG_TRY(ensure_at128(h, st));
     HDCG_TRY(coarse_cg<double>(h, h->AT128.as<c128>(), static_cast<c128*>(x), static_cast<const c128*>(b), nrhs,
                                tol, maxiter, &it, st));
-  else
+  } else
     HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), static_cast<c64*>(x), static_cast<const c64*>(b), nrhs, tol,
                               maxiter, &it, st, m16 ? prec : -1));
   HDCG_HIP(hipStreamSynchronize(st));
@@ -665,18 +696,14 @@ int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
                  0.0, 0, nullptr, static_cast<hipStream_t>(stream));
 }
 
-int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol, struct hdcg_stats* stats,
-               void* stream) {
-  HDCG_TRY(check_h(h, DWF_C128, nrhs));
-  if (!x_c128 || !b_c128 || !(tol > 0)) return fail(DWF_ERR_ARG, "bad arguments to hdcg_solve");
-  auto st = static_cast<hipStream_t>(stream);
-  const auto t0 = std::chrono::steady_clock::now();
+// FP64 defect correction for one group of right-hand sides solved together.
+static int solve_group(hdcg* h, c128* x, const c128* b, int nrhs, double tol, InnerStats* is,
+                       int* outer_out, double* mm64_out, double* rel_out, hipStream_t st) {
   dwf_op* op = h->op;
   const size_t fe = op->field_elems(1);
-  c128* x = static_cast<c128*>(x_c128);
-  const c128* b = static_cast<const c128*>(b_c128);
+  constexpr int kOuterChunk = 4;  // FP64 residual computed a few right-hand sides at a time
   HDCG_TRY(h->fw128[0].ensure(fe * nrhs * sizeof(c128)));
-  HDCG_TRY(h->fw128[1].ensure(fe * nrhs * sizeof(c128)));
+  HDCG_TRY(h->fw128[1].ensure(fe * std::min(nrhs, kOuterChunk) * sizeof(c128)));
   HDCG_TRY(ensure_fine64(h, 0, nrhs));
   HDCG_TRY(ensure_fine64(h, 7, nrhs));
   c128* r = h->fw128[0].as<c128>();
@@ -691,7 +718,6 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
   HDCG_TRY(b_zero<double>(x, fe * nrhs, st));
   HDCG_HIP(hipStreamSynchronize(st));
   std::vector<double> bb(h->pinned + 64 * 12, h->pinned + 64 * 12 + nrhs);
-  InnerStats is;
   int outer = 0;
   double mm64 = 0, rel = 0;
   int status = DWF_OK;
@@ -699,9 +725,12 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
     // r = b - H x in FP64
     HDCG_HIP(hipMemcpyAsync(r, b, fe * nrhs * sizeof(c128), hipMemcpyDeviceToDevice, st));
     if (outer > 0) {
-      HDCG_TRY(launch_mpcdagmpc<double>(op, w, x, nrhs, st, nullptr));
+      for (int r0 = 0; r0 < nrhs; r0 += kOuterChunk) {
+        const int nc = std::min(kOuterChunk, nrhs - r0);
+        HDCG_TRY(launch_mpcdagmpc<double>(op, w, x + (size_t)r0 * fe, nc, st, nullptr));
+        HDCG_TRY(b_axpby<double>(r + (size_t)r0 * fe, w, -1.0, 1.0, fe * nc, st));
+      }
       mm64 += nrhs;
-      HDCG_TRY(b_axpby<double>(r, w, -1.0, 1.0, fe * nrhs, st));
     }
     HDCG_TRY(b_norm2<double>(red, r, fe, nrhs, orr, st));
     HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 13, orr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -722,9 +751,40 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
     // the complex64 floor inner_tol)
     HDCG_TRY(b_scale_copy<float, double>(r64, r, orr, true, fe, nrhs, st));
     const double itol = std::max(h->prm.inner_tol, 0.5 * tol / rel);
-    HDCG_TRY(adef2(h, e64, r64, nrhs, itol, h->prm.inner_maxiter, &is, st));
+    HDCG_TRY(adef2(h, e64, r64, nrhs, itol, h->prm.inner_maxiter, is, st));
     HDCG_TRY(b_axpy_mixed<double, float>(x, e64, orr, fe, nrhs, st, true));
     ++outer;
+  }
+  *outer_out = outer;
+  *mm64_out += mm64;
+  *rel_out = rel;
+  return status;
+}
+
+int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol, struct hdcg_stats* stats,
+               void* stream) {
+  HDCG_TRY(check_h(h, DWF_C128, nrhs));
+  if (!x_c128 || !b_c128 || !(tol > 0)) return fail(DWF_ERR_ARG, "bad arguments to hdcg_solve");
+  auto st = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t fe = h->op->field_elems(1);
+  // right-hand sides are solved together in groups of at most kGroup: they
+  // share every coarse solve, and the work memory stays bounded
+  constexpr int kGroup = 8;
+  InnerStats is;
+  int outer = 0, status = DWF_OK;
+  double mm64 = 0, rel = 0;
+  for (int g0 = 0; g0 < nrhs; g0 += kGroup) {
+    const int ng = std::min(kGroup, nrhs - g0);
+    int o = 0;
+    double rg = 0;
+    const int rc = solve_group(h, static_cast<c128*>(x_c128) + (size_t)g0 * fe,
+                               static_cast<const c128*>(b_c128) + (size_t)g0 * fe, ng, tol, &is, &o, &mm64,
+                               &rg, st);
+    if (rc < 0) return rc;
+    if (rc == DWF_NOT_CONVERGED) status = DWF_NOT_CONVERGED;
+    outer = std::max(outer, o);
+    rel = std::max(rel, rg);
   }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
