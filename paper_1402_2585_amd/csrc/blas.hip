@@ -38,11 +38,31 @@ __device__ __forceinline__ void coef(const double* num, bool cnum, const double*
 }
 
 template <int NQ>
-__device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, double* res) {
+__device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, double*) {
   __shared__ double lds[NQ * 16];
   block_sum<NQ>(v, lds);
-  finish_reduction<NQ>(v, red.partials + (size_t)rhs * kMaxPartials, kMaxPartials / NQ,
-                       blockIdx.x, red.counters + rhs, res + NQ * rhs, gridDim.x);
+  store_partial<NQ>(v, red.partials + (size_t)rhs * kMaxPartials, kMaxPartials / NQ, blockIdx.x);
+}
+
+template <int NQ>
+__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nslots,
+                                                  int nblocks, double* __restrict__ res) {
+  const int rhs = blockIdx.x;
+  const double* p = partials + (size_t)rhs * kMaxPartials;
+  __shared__ double lds[16];
+  for (int q = 0; q < NQ; ++q) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += p[q * nslots + i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
+      res[NQ * rhs + q] = t;
+    }
+    __syncthreads();
+  }
 }
 
 template <typename R>
@@ -164,12 +184,23 @@ __global__ void k_zero(cplx<R>* __restrict__ y, size_t total) {
 
 #define LAUNCH_CHECK() HDCG_HIP(hipGetLastError())
 
+int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int nrhs, double* res,
+                    hipStream_t st) {
+  if (nblocks > kMaxPartials / nq) return fail(DWF_ERR_ARG, "too many partial sums");
+  if (nq == 1)
+    hipLaunchKernelGGL((k_finalize<1>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, res);
+  else
+    hipLaunchKernelGGL((k_finalize<2>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, res);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+
 template <typename R>
 int b_norm2(Red red, const cplx<R>* x, size_t n, int nrhs, double* res, hipStream_t st) {
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
   hipLaunchKernelGGL((k_norm2<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, n, red, res);
   LAUNCH_CHECK();
-  return DWF_OK;
+  return launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, res, st);
 }
 template <typename R>
 int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, double* res,
@@ -177,7 +208,7 @@ int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, doubl
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
   hipLaunchKernelGGL((k_dot<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, a, b, n, red, res);
   LAUNCH_CHECK();
-  return DWF_OK;
+  return launch_finalize(2, red.partials, kMaxPartials / 2, nblocks(n), nrhs, res, st);
 }
 template <typename R>
 int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w, size_t n,
@@ -187,7 +218,7 @@ int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w
   hipLaunchKernelGGL((k_update<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
                      cnum, den, den2, lam, red, rr, dstr);
   LAUNCH_CHECK();
-  return DWF_OK;
+  return rr ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, rr, st) : DWF_OK;
 }
 template <typename R>
 int b_xpay(Red red, cplx<R>* p, const cplx<R>* y, size_t n, int nrhs, const double* num, bool cnum,
@@ -196,7 +227,7 @@ int b_xpay(Red red, cplx<R>* p, const cplx<R>* y, size_t n, int nrhs, const doub
   hipLaunchKernelGGL((k_xpay<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, p, y, n, num, cnum, den,
                      sign, red, pp, dstr);
   LAUNCH_CHECK();
-  return DWF_OK;
+  return pp ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, pp, st) : DWF_OK;
 }
 template <typename R>
 int b_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, size_t total, hipStream_t st) {

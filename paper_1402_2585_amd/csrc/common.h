@@ -181,43 +181,22 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ], double* lds /* NQ*16 
   }
 }
 
-// Finish a reduction: thread 0 of every workgroup has its partials in v.
-// partials layout [NQ][nslots]; the last workgroup writes result[q].
-// Returns true in the workgroup that finalised (all threads).
+// Thread 0 of every workgroup stores its partial sums: partials[q * nslots +
+// slot].  A separate finalize launch (launch_finalize) then sums the
+// partials of each right-hand side in a fixed order, so results are
+// deterministic and no workgroup waits on a fence or an atomic.
 template <int NQ>
-__device__ __forceinline__ bool finish_reduction(const double (&v)[NQ], double* partials,
-                                                 int nslots, int slot, unsigned* counter,
-                                                 double* result, int nblocks) {
-  __shared__ bool last;
+__device__ __forceinline__ void store_partial(const double (&v)[NQ], double* partials, int nslots,
+                                              int slot) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) partials[q * nslots + slot] = v[q];
-    __threadfence();
-    unsigned t = atomicAdd(counter, 1u);
-    last = (t == (unsigned)nblocks - 1);
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  // fixed-order sum by the last workgroup, one quantity per wave lane range
-  for (int q = 0; q < NQ; ++q) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x)
-      s += __hip_atomic_load(&partials[q * nslots + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __shared__ double red[16];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += red[w];
-      result[q] = t;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
-  return true;
 }
+
+// res[nq * rhs + q] = sum_{i < nblocks} partials[rhs * kMaxPartials + q * nslots + i]
+int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int nrhs, double* res,
+                    hipStream_t st);
 
 // Map blockIdx.x so that each of the 8 XCDs (workgroups are dispatched to
 // XCDs round-robin) receives one contiguous range of tiles: neighbouring

@@ -359,8 +359,7 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
       double vv[1] = {nrm};
       __shared__ double red[16];
       block_sum<1>(vv, red);
-      finish_reduction<1>(vv, A.partials + (size_t)rhs * kMaxPartials, 0, wg, A.counters + rhs,
-                          A.result + rhs, gridDim.x);
+      store_partial<1>(vv, A.partials + (size_t)rhs * kMaxPartials, 0, wg);
     }
   }
 }
@@ -389,8 +388,7 @@ __global__ void __launch_bounds__(256) norm2_kernel(const cplx<R>* __restrict__ 
   double v[1] = {acc};
   __shared__ double red[16];
   block_sum<1>(v, red);
-  finish_reduction<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x,
-                      A.counters + rhs, A.result + rhs, gridDim.x);
+  store_partial<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x);
 }
 
 template <typename R>
@@ -410,8 +408,7 @@ dot_kernel(const cplx<R>* __restrict__ a, const cplx<R>* __restrict__ b, RedArgs
   __shared__ double red[32];
   block_sum<2>(v, red);
   // partial layout [rhs][2][kMaxPartials/2]
-  finish_reduction<2>(v, A.partials + (size_t)rhs * kMaxPartials, kMaxPartials / 2, blockIdx.x,
-                      A.counters + rhs, A.result + 2 * rhs, gridDim.x);
+  store_partial<2>(v, A.partials + (size_t)rhs * kMaxPartials, kMaxPartials / 2, blockIdx.x);
 }
 
 template <typename R>
@@ -437,8 +434,7 @@ cg_update_kernel(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>
   double v[1] = {acc};
   __shared__ double red[16];
   block_sum<1>(v, red);
-  finish_reduction<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x,
-                      A.counters + rhs, A.result + rhs, gridDim.x);
+  store_partial<1>(v, A.partials + (size_t)rhs * kMaxPartials, 0, blockIdx.x);
 }
 
 template <typename R>
@@ -554,6 +550,7 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
       hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB>), grid, block, lds, stream, out, in, center, G, pw, A);
   }
   HDCG_HIP(hipGetLastError());
+  if (norm_result) return launch_finalize(1, A.partials, 0, nwg, nrhs, norm_result, stream);
   return DWF_OK;
 }
 
@@ -589,7 +586,7 @@ int launch_norm2(dwf_op* op, const cplx<R>* x, int nrhs, double* result, hipStre
   dim3 grid(red_blocks(A.n), nrhs);
   hipLaunchKernelGGL((norm2_kernel<R>), grid, dim3(256), 0, stream, x, A);
   HDCG_HIP(hipGetLastError());
-  return DWF_OK;
+  return launch_finalize(1, A.partials, kMaxPartials, grid.x, nrhs, result, stream);
 }
 
 template <typename R>
@@ -601,7 +598,7 @@ int launch_dot(dwf_op* op, const cplx<R>* a, const cplx<R>* b, int nrhs, double*
   dim3 grid(red_blocks(A.n), nrhs);
   hipLaunchKernelGGL((dot_kernel<R>), grid, dim3(256), 0, stream, a, b, A);
   HDCG_HIP(hipGetLastError());
-  return DWF_OK;
+  return launch_finalize(2, A.partials, kMaxPartials / 2, grid.x, nrhs, result, stream);
 }
 
 template <typename R>
@@ -614,7 +611,7 @@ int launch_cg_update(dwf_op* op, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const
   hipLaunchKernelGGL((cg_update_kernel<R>), grid, dim3(256), 0, stream, x, r, p, w, num, den,
                      alpha_host, A);
   HDCG_HIP(hipGetLastError());
-  return DWF_OK;
+  return launch_finalize(1, A.partials, kMaxPartials, grid.x, nrhs, rr, stream);
 }
 
 template <typename R>

@@ -130,6 +130,52 @@ k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fs
   }
 }
 
+// Few right-hand sides: one workgroup per (vector k, block a) streams the
+// row P[a][k][:] once, lanes running over the 12 Ls contiguous components of
+// each site column; out[r*sr + a*sa + k*sk] = sum_i conj(P[a][k][i]) Q_r(site(a, i)).
+template <typename R, int NR>
+__global__ void __launch_bounds__(256)
+k_project_small(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
+                const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
+                cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk) {
+  const int k = blockIdx.x, a = blockIdx.y;
+  const cplx<R>* Pk = P + ((size_t)a * nvec + k) * nb;
+  const int* so = site_of + (size_t)a * nsb;
+  cplx<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
+  for (int j = 0; j < nsb; ++j) {
+    const size_t base = (size_t)so[j] * col;
+    const cplx<R>* Pj = Pk + (size_t)j * col;
+    for (int q = threadIdx.x; q < col; q += blockDim.x) {
+      const cplx<R> pv = conj(Pj[q]);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nr) cmac(acc[r], pv, Q[r * fstride + base + q]);
+    }
+  }
+  __shared__ double red[2 * NR][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double re = wave_sum((double)acc[r].re), im = wave_sum((double)acc[r].im);
+    if (lane == 0) {
+      red[2 * r][wave] = re;
+      red[2 * r + 1][wave] = im;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nr && threadIdx.x < NR) {
+    const int r = threadIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      re += red[2 * r][w];
+      im += red[2 * r + 1][w];
+    }
+    out[r * sr + a * sa + k * sk] = cmk((R)re, (R)im);
+  }
+}
+
 // fine_out[r][site(a, i)] = base + sign * sum_k P[a][k][i] c[r][a][k]
 template <typename R, int NR>
 __global__ void __launch_bounds__(kT)
@@ -369,8 +415,21 @@ template <typename R>
 int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
             int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
             hipStream_t st) {
-  dim3 grid(h->Nc, (h->nvec + 15) / 16, (nr + 15) / 16);
   const int col = 12 * h->op->g.Ls;
+  if (fine && !phase && nr <= 4) {
+    // streaming kernel: P read once, few accumulators per lane
+    const int threads = ((std::min(col, 256) + 63) / 64) * 64;
+    dim3 g2(h->nvec, h->Nc);
+    if (nr == 1)
+      hipLaunchKernelGGL((k_project_small<R, 1>), g2, dim3(threads), 0, st, P, fine, fstride,
+                         h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
+    else
+      hipLaunchKernelGGL((k_project_small<R, 4>), g2, dim3(threads), 0, st, P, fine, fstride,
+                         h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
+    HDCG_HIP(hipGetLastError());
+    return DWF_OK;
+  }
+  dim3 grid(h->Nc, (h->nvec + 15) / 16, (nr + 15) / 16);
   if (fine)
     hipLaunchKernelGGL((k_blkdot<R, true>), grid, dim3(kT), 0, st, P, fine, fstride,
                        h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
