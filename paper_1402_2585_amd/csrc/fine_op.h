@@ -48,6 +48,8 @@ struct dwf_op {
     int block[4] = {0, 0, 0, 0};  // hop workgroup site block (x/2, y, z, t); 0 = linear
     int remap = 1;                // XCD-contiguous workgroup order
     int lds_kb = 0;               // minimum LDS per workgroup (caps occupancy)
+    int nt = 0;                   // non-temporal output stores (1) / gauge loads (2)
+    int morton = 0;               // Morton order of the site blocks
   } tune;
   hdk::DevBuf host_pinned_dummy;
   double* pinned = nullptr;        // host pinned scalars

@@ -142,11 +142,27 @@ __device__ __forceinline__ void apply_Adag(const cplx<R> h0, const cplx<R> h1, c
   }
 }
 
+template <typename R>
+__device__ __forceinline__ void store_field(cplx<R>* p, cplx<R> v, bool nt) {
+  if (nt) {
+    __builtin_nontemporal_store(v.re, &p->re);
+    __builtin_nontemporal_store(v.im, &p->im);
+  } else {
+    *p = v;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> load_link(const cplx<R>* p, bool nt) {
+  if (nt) return cmk(__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im));
+  return *p;
+}
+
 // acc += (1 + SG*gamma_mu) W psi, psi read at `p` (stride Ls between
 // components), W = 3x3 link at `w`.
 template <typename R, int MU, int SG>
 __device__ __forceinline__ void hop_term(cplx<R> (&acc)[12], const cplx<R>* __restrict__ p,
-                                         const cplx<R>* __restrict__ w, int Ls) {
+                                         const cplx<R>* __restrict__ w, int Ls, bool ntg) {
   cplx<R> h[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -167,7 +183,8 @@ __device__ __forceinline__ void hop_term(cplx<R> (&acc)[12], const cplx<R>* __re
   cplx<R> Wh[2][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cplx<R> w0 = w[a * 3 + 0], w1 = w[a * 3 + 1], w2 = w[a * 3 + 2];
+    const cplx<R> w0 = load_link(w + a * 3 + 0, ntg), w1 = load_link(w + a * 3 + 1, ntg),
+                  w2 = load_link(w + a * 3 + 2, ntg);
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
       cplx<R> t = w0 * h[sp][0];
@@ -199,6 +216,9 @@ struct HopArgs {
   int bx, by, bz, bt; // 4D site block per workgroup in (x/2, y, z, t); bx = 0: linear cb order
   int nbx, nby, nbz;  // block-grid extents
   int remap;          // XCD-contiguous workgroup order
+  int nt;             // bit 0: non-temporal output stores; bit 1: non-temporal gauge loads
+  int morton;         // Morton (bit-interleaved) order of the block grid (power-of-two grids)
+  int nbt;            // block-grid extent in t
   size_t field;       // complex elements per rhs
   double d, mass;     // fifth dimension
   double* partials;   // EPI_SUB norm: [rhs][kMaxPartials] (nullable)
@@ -221,11 +241,24 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
   int v;
   if (A.bx > 0) {
     // workgroup = one bx*by*bz*bt block of sites in (x/2, y, z, t)
-    int q = wg;
-    const int gx = q % A.nbx; q /= A.nbx;
-    const int gy = q % A.nby; q /= A.nby;
-    const int gz = q % A.nbz;
-    const int gt = q / A.nbz;
+    int gx, gy, gz, gt;
+    if (A.morton) {
+      // de-interleave the bits of wg over the four block-grid dimensions
+      gx = gy = gz = gt = 0;
+      int bit = 0, px = 0, py = 0, pz = 0, pt = 0;
+      while ((1 << px) < A.nbx || (1 << py) < A.nby || (1 << pz) < A.nbz || (1 << pt) < A.nbt) {
+        if ((1 << px) < A.nbx) gx |= ((wg >> bit++) & 1) << px++;
+        if ((1 << py) < A.nby) gy |= ((wg >> bit++) & 1) << py++;
+        if ((1 << pz) < A.nbz) gz |= ((wg >> bit++) & 1) << pz++;
+        if ((1 << pt) < A.nbt) gt |= ((wg >> bit++) & 1) << pt++;
+      }
+    } else {
+      int q = wg;
+      gx = q % A.nbx; q /= A.nbx;
+      gy = q % A.nby; q /= A.nby;
+      gz = q % A.nbz;
+      gt = q / A.nbz;
+    }
     int r = vloc;
     const int lx = r % A.bx; r /= A.bx;
     const int ly = r % A.by; r /= A.by;
@@ -247,6 +280,7 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
 
   // forward terms (1 - g) U(x) psi(x+mu) [non-dagger]; dagger flips signs
   constexpr int SF = DAG ? 1 : -1;
+  const bool ntg = (A.nt & 2) != 0;
   if (active) {
     const Site c = site_coords(v, A.out_parity, g);
     const size_t col = (size_t)12 * Ls;
@@ -256,16 +290,16 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
     {
       const int xp = (c.x + 1 == g.X) ? 0 : c.x + 1;
       const int xm = (c.x == 0) ? g.X - 1 : c.x - 1;
-      hop_term<R, 0, SF>(acc, in + (size_t)((xp >> 1) + rowyzt) * col + s, G + 0 * 9, Ls);
-      hop_term<R, 0, -SF>(acc, in + (size_t)((xm >> 1) + rowyzt) * col + s, G + 4 * 9, Ls);
+      hop_term<R, 0, SF>(acc, in + (size_t)((xp >> 1) + rowyzt) * col + s, G + 0 * 9, Ls, ntg);
+      hop_term<R, 0, -SF>(acc, in + (size_t)((xm >> 1) + rowyzt) * col + s, G + 4 * 9, Ls, ntg);
     }
     // y direction
     {
       const int zt = c.rest / g.Y;
       const int yp = (c.y + 1 == g.Y) ? 0 : c.y + 1;
       const int ym = (c.y == 0) ? g.Y - 1 : c.y - 1;
-      hop_term<R, 1, SF>(acc, in + (size_t)(c.xh + g.Xh * (yp + g.Y * zt)) * col + s, G + 1 * 9, Ls);
-      hop_term<R, 1, -SF>(acc, in + (size_t)(c.xh + g.Xh * (ym + g.Y * zt)) * col + s, G + 5 * 9, Ls);
+      hop_term<R, 1, SF>(acc, in + (size_t)(c.xh + g.Xh * (yp + g.Y * zt)) * col + s, G + 1 * 9, Ls, ntg);
+      hop_term<R, 1, -SF>(acc, in + (size_t)(c.xh + g.Xh * (ym + g.Y * zt)) * col + s, G + 5 * 9, Ls, ntg);
     }
     // z direction
     {
@@ -273,8 +307,8 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
       const int zm = (c.z == 0) ? g.Z - 1 : c.z - 1;
       const size_t b = (size_t)c.xh + (size_t)g.Xh * c.y;
       const size_t sy = (size_t)g.Xh * g.Y;
-      hop_term<R, 2, SF>(acc, in + (b + sy * (zp + (size_t)g.Z * c.t)) * col + s, G + 2 * 9, Ls);
-      hop_term<R, 2, -SF>(acc, in + (b + sy * (zm + (size_t)g.Z * c.t)) * col + s, G + 6 * 9, Ls);
+      hop_term<R, 2, SF>(acc, in + (b + sy * (zp + (size_t)g.Z * c.t)) * col + s, G + 2 * 9, Ls, ntg);
+      hop_term<R, 2, -SF>(acc, in + (b + sy * (zm + (size_t)g.Z * c.t)) * col + s, G + 6 * 9, Ls, ntg);
     }
     // t direction
     {
@@ -282,8 +316,8 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
       const int tm = (c.t == 0) ? g.T - 1 : c.t - 1;
       const size_t b = (size_t)c.xh + (size_t)g.Xh * (c.y + (size_t)g.Y * c.z);
       const size_t sz = (size_t)g.Xh * g.Y * g.Z;
-      hop_term<R, 3, SF>(acc, in + (b + sz * tp) * col + s, G + 3 * 9, Ls);
-      hop_term<R, 3, -SF>(acc, in + (b + sz * tm) * col + s, G + 7 * 9, Ls);
+      hop_term<R, 3, SF>(acc, in + (b + sz * tp) * col + s, G + 3 * 9, Ls, ntg);
+      hop_term<R, 3, -SF>(acc, in + (b + sz * tm) * col + s, G + 7 * 9, Ls, ntg);
     }
   }
 
@@ -329,7 +363,7 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
     if (active) {
       cplx<R>* o = out + (size_t)v * 12 * Ls + s;
 #pragma unroll
-      for (int c = 0; c < 12; ++c) o[c * Ls] = buf[(vloc * 12 + c) * ld + s];
+      for (int c = 0; c < 12; ++c) store_field(o + c * Ls, buf[(vloc * 12 + c) * ld + s], A.nt & 1);
     }
   } else {
     // ---- M_5 c - 1/4 hop (or M_5^+ c - 1/4 hop^+) --------------------------
@@ -351,7 +385,7 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
         const int sn = from_below ? s_dn : s_up;
         const R fn = from_below ? f_dn : f_up;
         const cplx<R> r = d * cc[s] + fn * cc[sn] - q * acc[c];
-        o[c * Ls] = r;
+        store_field(o + c * Ls, r, A.nt & 1);
         nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
       }
     }
@@ -501,6 +535,9 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   A.bx = A.by = A.bz = A.bt = 0;
   A.nbx = A.nby = A.nbz = 1;
   A.remap = op->tune.remap;
+  A.nt = op->tune.nt;
+  A.morton = 0;
+  A.nbt = 1;
   {
     const int* b = op->tune.block;
     if (b[0] > 0 && b[0] * b[1] * b[2] * b[3] * g.Ls <= 256 &&
@@ -514,6 +551,9 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
       A.nbx = g.Xh / b[0];
       A.nby = g.Y / b[1];
       A.nbz = g.Z / b[2];
+      A.nbt = g.T / b[3];
+      auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+      A.morton = op->tune.morton && pow2(A.nbx) && pow2(A.nby) && pow2(A.nbz) && pow2(A.nbt);
     }
   }
   A.field = (size_t)g.Vh * 12 * g.Ls;
