@@ -204,15 +204,18 @@ int dwf_create(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass,
   const double den = 1.0 + mass * std::pow(d, -Ls);
   for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(d, -1 - n) / den : 0.0;
   (void)hipGetDevice(&op->device);
-  // hop launch shape: HDCG_HOP_TILE="bx,by,bz,bt,remap" overrides the default
+  // hop launch shape: HDCG_HOP_TILE="bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]"
+  // overrides the default (bx = 0: consecutive sites)
   if (const char* e = std::getenv("HDCG_HOP_TILE")) {
-    int b[8] = {0, 0, 0, 0, 1, 0, 0, 0};
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3], &b[4], &b[5], &b[6], &b[7]) >= 4) {
+    int b[9] = {0, 0, 0, 0, op->tune.remap, op->tune.lds_kb, op->tune.nt, op->tune.morton, op->tune.phases};
+    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3], &b[4], &b[5], &b[6], &b[7],
+                    &b[8]) >= 4) {
       for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
       op->tune.remap = b[4];
       op->tune.lds_kb = b[5] < 0 ? 0 : (b[5] > 150 ? 150 : b[5]);
-      op->tune.nt = b[6] & 3;
+      op->tune.nt = b[6] & 1;
       op->tune.morton = b[7] != 0;
+      op->tune.phases = b[8] == 2 ? 2 : 4;
     }
   }
   hipStream_t st = static_cast<hipStream_t>(stream);

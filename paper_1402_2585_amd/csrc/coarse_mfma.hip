@@ -12,9 +12,13 @@
 // scale), smax_a = max_l s_al and rho_al = s_al / smax_a <= 1, which keeps
 // both operands within the fp16 range.
 //
-// Ahat is stored in MFMA fragment order [a][kstep][mtile][lane][4] so that a
-// wave reads 512 contiguous bytes per fragment.  One workgroup (4 waves) per
-// coarse site; the waves split the K steps and reduce through LDS.
+// Ahat is stored per coarse site and K step as [row m < nvec][kgroup 0..3][4]
+// (the 16 K values of one step and row are contiguous), so the A fragment of
+// an M tile is one contiguous run that a wave reads with 8-byte lanes, and no
+// bytes are stored or read for the rows that pad nvec to a multiple of 16.
+// One workgroup (NW waves) per coarse site; each wave takes U consecutive K
+// steps at a time, with all their loads issued before the MFMAs, and the
+// waves reduce through LDS.
 #include "hdcg_impl.h"
 
 namespace hdk {
@@ -75,22 +79,21 @@ __global__ void k_rho(float* __restrict__ s, float* __restrict__ smax, int Nc) {
 template <bool BF16>
 __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho,
                        const float* __restrict__ smax, unsigned short* __restrict__ F, int Nc,
-                       int nvec, int mtiles, int ksteps) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one (a, s, mt, lane)
-  const size_t total = (size_t)Nc * ksteps * mtiles * 64;
+                       int nvec, int ksteps) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one (a, s, m, kg)
+  const size_t total = (size_t)Nc * ksteps * nvec * 4;
   if (e >= total) return;
-  const int lane = (int)(e % 64);
-  const int mt = (int)((e / 64) % mtiles);
-  const size_t as = e / (64 * (size_t)mtiles);
+  const int kg = (int)(e % 4);
+  const int m = (int)((e / 4) % nvec);
+  const size_t as = e / (4 * (size_t)nvec);
   const int s = (int)(as % ksteps);
   const int a = (int)(as / ksteps);
-  const int m = mt * 16 + (lane & 15);
   const int ktot = 2 * kStencil * nvec;
   unsigned short v4[4];
   for (int i = 0; i < 4; ++i) {
-    const int kap = 16 * s + 4 * (lane >> 4) + i;
+    const int kap = 16 * s + 4 * kg + i;
     float v = 0.f;
-    if (m < nvec && kap < ktot) {
+    if (kap < ktot) {
       const int part = kap / (kStencil * nvec);
       const int rem = kap - part * kStencil * nvec;
       const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
@@ -104,103 +107,127 @@ __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho
   for (int i = 0; i < 4; ++i) o[i] = v4[i];
 }
 
-template <bool BF16, int MT, int NT>
-__global__ void __launch_bounds__(256)
+template <bool BF16, int MT, int NT, int NW, int U>
+__global__ void __launch_bounds__(NW * 64)
 k_capply_mfma(const unsigned short* __restrict__ F, const float* __restrict__ rho,
               const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
               c64* __restrict__ out, int Nc, int nvec, int nrhs, int ksteps) {
-  __shared__ f32x4 red[4][MT * NT][64];
+  __shared__ f32x4 red[NW][MT * NT][64];
   const int a = blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ktot = 2 * kStencil * nvec;
   const int kn = kStencil * nvec;
+  const int r16 = lane & 15, kg = lane >> 4;
   f32x4 acc[MT][NT];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const unsigned short* Fa = F + (size_t)a * ksteps * MT * 64 * 4;
+  const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
   const int* nb = nbr + (size_t)a * kStencil;
   const float* rh = rho + (size_t)a * kStencil;
-  for (int s = wave; s < ksteps; s += 4) {
-    s16x4 af[MT];
+  for (int s0 = wave * U; s0 < ksteps; s0 += NW * U) {
+    s16x4 af[U][MT];
+    s16x4 bf[U][NT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      af[mt] = *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * MT + mt) * 64 + lane) * 4);
-    const int k0 = 16 * s + 4 * (lane >> 4);
-    s16x4 bf[NT];
-    if (k0 < ktot) {
-      const int part = k0 / kn;
-      const int rem = k0 - part * kn;
-      const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
-      const float r = rh[l];
-      const size_t vo = (size_t)nb[l] * nvec + k;
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 + u;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int g = nt * 16 + (lane & 15);
-        float v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (g < 2 * nrhs) {
-          const bool imcol = g >= nrhs;
-          const int rr = imcol ? g - nrhs : g;
-          const c64* c = in + (size_t)rr * Nc * nvec + vo;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const c64 x = c[i];
-            // columns r:        part 0 -> Re c, part 1 -> -Im c
-            // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
-            v[i] = imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im);
-            v[i] *= r;
-          }
-        }
-        s16x4 b;
-        b.x = (short)to16<BF16>(v[0]);
-        b.y = (short)to16<BF16>(v[1]);
-        b.z = (short)to16<BF16>(v[2]);
-        b.w = (short)to16<BF16>(v[3]);
-        bf[nt] = b;
+      for (int mt = 0; mt < MT; ++mt) {
+        const int m = mt * 16 + r16;
+        af[u][mt] = (s < ksteps && m < nvec)
+                        ? *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * nvec + m) * 4 + kg) * 4)
+                        : s16x4{0, 0, 0, 0};
       }
-    } else {
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bf[nt] = s16x4{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int u = 0; u < U; ++u) {
+      const int k0 = 16 * (s0 + u) + 4 * kg;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        if (BF16)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[mt], bf[nt], acc[mt][nt], 0, 0, 0);
-        else
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[mt]),
-                                                              __builtin_bit_cast(h16x4, bf[nt]),
-                                                              acc[mt][nt], 0, 0, 0);
+      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = s16x4{0, 0, 0, 0};
+      if (s0 + u < ksteps && k0 < ktot) {
+        const int part = k0 / kn;
+        const int rem = k0 - part * kn;
+        const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
+        const float r = rh[l];
+        const size_t vo = (size_t)nb[l] * nvec + k;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int g = nt * 16 + r16;
+          if (g < 2 * nrhs) {
+            const bool imcol = g >= nrhs;
+            const int rr = imcol ? g - nrhs : g;
+            const c64* c = in + (size_t)rr * Nc * nvec + vo;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const c64 x = c[i];
+              // columns r:        part 0 -> Re c, part 1 -> -Im c
+              // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
+              v[i] = r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im));
+            }
+            s16x4 b;
+            b.x = (short)to16<BF16>(v[0]);
+            b.y = (short)to16<BF16>(v[1]);
+            b.z = (short)to16<BF16>(v[2]);
+            b.w = (short)to16<BF16>(v[3]);
+            bf[u][nt] = b;
+          }
+        }
       }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          if (BF16)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u][mt], bf[u][nt], acc[mt][nt], 0, 0, 0);
+          else
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[u][mt]),
+                                                                __builtin_bit_cast(h16x4, bf[u][nt]),
+                                                                acc[mt][nt], 0, 0, 0);
+        }
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) red[wave][mt * NT + nt][lane] = acc[mt][nt];
   __syncthreads();
-  if (wave != 0) return;
   const float sm = smax[a];
+  for (int q = threadIdx.x; q < MT * NT * 64; q += NW * 64) {
+    const int tile = q >> 6, ln = q & 63;
+    const int mt = tile / NT, nt = tile - mt * NT;
+    f32x4 v = red[0][tile][ln];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int w = 1; w < NW; ++w) v += red[w][tile][ln];
+    // lane ln holds D[m = 4 (ln / 16) + i][n = ln % 16]
+    const int g = nt * 16 + (ln & 15);
+    if (g >= 2 * nrhs) continue;
+    const bool imcol = g >= nrhs;
+    const int rr = imcol ? g - nrhs : g;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      f32x4 v = red[0][mt * NT + nt][lane];
-      for (int w = 1; w < 4; ++w) v += red[w][mt * NT + nt][lane];
-      // lane holds D[m = 4 (lane / 16) + i][n = lane % 16]
-      const int g = nt * 16 + (lane & 15);
-      if (g >= 2 * nrhs) continue;
-      const bool imcol = g >= nrhs;
-      const int rr = imcol ? g - nrhs : g;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = mt * 16 + 4 * (lane >> 4) + i;
-        if (m >= nvec) continue;
-        float* o = reinterpret_cast<float*>(out + ((size_t)rr * Nc + a) * nvec + m);
-        o[imcol ? 1 : 0] = sm * v[i];
-      }
+    for (int i = 0; i < 4; ++i) {
+      const int m = mt * 16 + 4 * (ln >> 4) + i;
+      if (m >= nvec) continue;
+      float* o = reinterpret_cast<float*>(out + ((size_t)rr * Nc + a) * nvec + m);
+      o[imcol ? 1 : 0] = sm * v[i];
     }
+  }
+}
+
+// 8 waves per workgroup while their LDS reduction buffers fit in 48 KiB
+template <bool BF16, int MT, int NT>
+void launch_tile(const unsigned short* F, const float* rho, const float* smax, const int* nbr,
+                 const c64* in, c64* out, int Nc, int nvec, int n, int ksteps, hipStream_t st) {
+  constexpr int U = 4;
+  if constexpr (MT * NT <= 6)
+    hipLaunchKernelGGL((k_capply_mfma<BF16, MT, NT, 8, U>), dim3(Nc), dim3(8 * 64), 0, st, F, rho, smax,
+                       nbr, in, out, Nc, nvec, n, ksteps);
+  else
+    hipLaunchKernelGGL((k_capply_mfma<BF16, MT, NT, 4, U>), dim3(Nc), dim3(4 * 64), 0, st, F, rho, smax,
+                       nbr, in, out, Nc, nvec, n, ksteps);
 }
 
 template <bool BF16, int MT>
@@ -213,11 +240,9 @@ int launch_mt(hdcg* h, const unsigned short* F, const c64* in, c64* out, int nr,
     const c64* i0 = in + (size_t)r0 * h->Nc * h->nvec;
     c64* o0 = out + (size_t)r0 * h->Nc * h->nvec;
     if (2 * n <= 16)
-      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 1>), dim3(h->Nc), dim3(256), 0, st, F, rho, smax,
-                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps);
+      launch_tile<BF16, MT, 1>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);
     else
-      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2>), dim3(h->Nc), dim3(256), 0, st, F, rho, smax,
-                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps);
+      launch_tile<BF16, MT, 2>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);
     HDCG_HIP(hipGetLastError());
   }
   return DWF_OK;
@@ -229,7 +254,6 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
   const int nv = h->nvec;
   if (nv % 4 != 0 || nv > 64)
     return fail(DWF_ERR_ARG, "16-bit coarse storage needs nvec a multiple of 4 and <= 64");
-  const int mtiles = (nv + 15) / 16;
   const int ksteps = (2 * kStencil * nv + 15) / 16;
   if (h->mf_smax.bytes == 0) {
     HDCG_TRY(h->mf_rho.ensure(sizeof(float) * h->Nc * kStencil));
@@ -242,16 +266,16 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
     HDCG_HIP(hipGetLastError());
   }
   DevBuf& F = prec == DWF_BF16 ? h->mf_bf16 : h->mf_f16;
-  const size_t total = (size_t)h->Nc * ksteps * mtiles * 64;
+  const size_t total = (size_t)h->Nc * ksteps * nv * 4;  // (a, s, m, kg), 4 values each
   HDCG_TRY(F.ensure(total * 4 * sizeof(unsigned short)));
   if (prec == DWF_BF16)
     hipLaunchKernelGGL((k_frag<true>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
-                       F.as<unsigned short>(), h->Nc, nv, mtiles, ksteps);
+                       F.as<unsigned short>(), h->Nc, nv, ksteps);
   else
     hipLaunchKernelGGL((k_frag<false>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
-                       F.as<unsigned short>(), h->Nc, nv, mtiles, ksteps);
+                       F.as<unsigned short>(), h->Nc, nv, ksteps);
   HDCG_HIP(hipGetLastError());
   if (prec == DWF_BF16)
     h->mf_have_bf16 = 1;

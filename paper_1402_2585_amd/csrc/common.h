@@ -86,16 +86,20 @@ template <typename R>
 __host__ __device__ __forceinline__ cplx<R> timesMinusI(cplx<R> a) {
   return cmk(a.im, -a.re);
 }
-// a += b*c ; a += conj(b)*c
+// a += b*c ; a += conj(b)*c, as four chained fused multiply-adds each
 template <typename R>
 __host__ __device__ __forceinline__ void cmac(cplx<R>& a, cplx<R> b, cplx<R> c) {
-  a.re += b.re * c.re - b.im * c.im;
-  a.im += b.re * c.im + b.im * c.re;
+  a.re = fma(b.re, c.re, a.re);
+  a.re = fma(-b.im, c.im, a.re);
+  a.im = fma(b.re, c.im, a.im);
+  a.im = fma(b.im, c.re, a.im);
 }
 template <typename R>
 __host__ __device__ __forceinline__ void cjmac(cplx<R>& a, cplx<R> b, cplx<R> c) {
-  a.re += b.re * c.re + b.im * c.im;
-  a.im += b.re * c.im - b.im * c.re;
+  a.re = fma(b.re, c.re, a.re);
+  a.re = fma(b.im, c.im, a.re);
+  a.im = fma(b.re, c.im, a.im);
+  a.im = fma(-b.im, c.re, a.im);
 }
 
 template <typename R>

@@ -45,11 +45,13 @@ struct dwf_op {
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
   hdk::Reducer red;
   struct {
-    int block[4] = {0, 0, 0, 0};  // hop workgroup site block (x/2, y, z, t); 0 = linear
+    // hop launch shape (measured best on MI355X at 16^4 and 24^3x48, Ls = 16)
+    int block[4] = {2, 2, 1, 1};  // workgroup site block in (x/2, y, z, t), powers of two; 0 = linear
     int remap = 1;                // XCD-contiguous workgroup order
     int lds_kb = 0;               // minimum LDS per workgroup (caps occupancy)
-    int nt = 0;                   // non-temporal output stores (1) / gauge loads (2)
-    int morton = 0;               // Morton order of the site blocks
+    int nt = 1;                   // non-temporal output stores
+    int morton = 1;               // Morton order of the site blocks (power-of-two block grids)
+    int phases = 4;               // neighbour-load phases per stage (2 or 4)
   } tune;
   hdk::DevBuf host_pinned_dummy;
   double* pinned = nullptr;        // host pinned scalars

@@ -1,16 +1,22 @@
 // Fine domain-wall operator kernels for gfx950.
 //
-// One hop stage = one launch.  A workgroup owns `spw` consecutive output
-// sites of one checkerboard and all Ls slices of each (thread = (site, s)),
-// so every gauge link is loaded once per workgroup wave and broadcast to the
-// Ls threads that use it, and the neighbour spinors of a site column are
-// contiguous runs of Ls complex numbers per component.
+// One hop stage = one launch.  A workgroup owns `spw` output sites of one
+// checkerboard (a small 4D block of sites, or consecutive sites) and all Ls
+// slices of each (thread = (site, s)).  The Ls threads of a site copy its
+// eight links into LDS once, the neighbour spinors of a site column are
+// contiguous runs of Ls complex numbers per component, and each thread
+// issues the loads of several neighbour spinors before any arithmetic, so
+// many bytes are in flight per wave and few sites need to be resident per
+// CU: the neighbour columns a CU touches then stay in its XCD's L2 between
+// their consumers.
 //
 // Epilogues (the fifth-dimension factors of M_pc, Sec. IV):
 //   EPI_INV  out = M_5^-1 (Dh in)          or M_5^-+ (Dh^+ in)   [dense in s]
 //   EPI_SUB  out = M_5 c - 1/4 (Dh in)      or M_5^+ c - 1/4 (Dh^+ in)
 // EPI_INV stages the hop result in LDS and solves the Ls x Ls system per
 // (site, component) with the O(Ls) recurrence of the closed-form inverse.
+#include <algorithm>
+
 #include "fine_op.h"
 
 namespace hdk {
@@ -19,7 +25,9 @@ enum { EPI_INV = 0, EPI_SUB = 1 };
 
 // ------------------------------------------------------------ coordinates --
 struct Site {
-  int x, y, z, t, xh, rest;
+  int x, y, z, t, xh;
+  int rest;  // y + Y (z + Z t)
+  int zt;    // z + Z t
 };
 
 __device__ __forceinline__ Site site_coords(int v, int parity, const Geom& g) {
@@ -27,9 +35,9 @@ __device__ __forceinline__ Site site_coords(int v, int parity, const Geom& g) {
   c.xh = v % g.Xh;
   c.rest = v / g.Xh;
   c.y = c.rest % g.Y;
-  int zt = c.rest / g.Y;
-  c.z = zt % g.Z;
-  c.t = zt / g.Z;
+  c.zt = c.rest / g.Y;
+  c.z = c.zt % g.Z;
+  c.t = c.zt / g.Z;
   c.x = 2 * c.xh + ((c.y + c.z + c.t + parity) & 1);
   return c;
 }
@@ -152,39 +160,15 @@ __device__ __forceinline__ void store_field(cplx<R>* p, cplx<R> v, bool nt) {
   }
 }
 
-template <typename R>
-__device__ __forceinline__ cplx<R> load_link(const cplx<R>* p, bool nt) {
-  if (nt) return cmk(__builtin_nontemporal_load(&p->re), __builtin_nontemporal_load(&p->im));
-  return *p;
-}
-
-// acc += (1 + SG*gamma_mu) W psi, psi read at `p` (stride Ls between
-// components), W = 3x3 link at `w`.
+// acc += (1 + SG*gamma_mu) W psi from the projected half-spinor
+// h = u + SG A l (two spin pairs of 3 colours), W = 3x3 link at `w`.
 template <typename R, int MU, int SG>
-__device__ __forceinline__ void hop_term(cplx<R> (&acc)[12], const cplx<R>* __restrict__ p,
-                                         const cplx<R>* __restrict__ w, int Ls, bool ntg) {
-  cplx<R> h[2][3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const cplx<R> u0 = p[(0 * 3 + c) * Ls];
-    const cplx<R> u1 = p[(1 * 3 + c) * Ls];
-    const cplx<R> l0 = p[(2 * 3 + c) * Ls];
-    const cplx<R> l1 = p[(3 * 3 + c) * Ls];
-    cplx<R> a0, a1;
-    apply_A<R, MU>(l0, l1, a0, a1);
-    if (SG > 0) {
-      h[0][c] = u0 + a0;
-      h[1][c] = u1 + a1;
-    } else {
-      h[0][c] = u0 - a0;
-      h[1][c] = u1 - a1;
-    }
-  }
+__device__ __forceinline__ void link_mul_add(cplx<R> (&acc)[12], const cplx<R> (&h)[2][3],
+                                             const cplx<R>* __restrict__ w) {
   cplx<R> Wh[2][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const cplx<R> w0 = load_link(w + a * 3 + 0, ntg), w1 = load_link(w + a * 3 + 1, ntg),
-                  w2 = load_link(w + a * 3 + 2, ntg);
+    const cplx<R> w0 = w[a * 3 + 0], w1 = w[a * 3 + 1], w2 = w[a * 3 + 2];
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
       cplx<R> t = w0 * h[sp][0];
@@ -209,14 +193,41 @@ __device__ __forceinline__ void hop_term(cplx<R> (&acc)[12], const cplx<R>* __re
   }
 }
 
+// Spin projection h = u + SG A_mu l of the components c0 (u0 u1 l0 l1 for
+// colour c).
+template <typename R, int MU, int SG>
+__device__ __forceinline__ void project(cplx<R> (&h)[2][3], int c, cplx<R> u0, cplx<R> u1,
+                                        cplx<R> l0, cplx<R> l1) {
+  cplx<R> a0, a1;
+  apply_A<R, MU>(l0, l1, a0, a1);
+  if (SG > 0) {
+    h[0][c] = u0 + a0;
+    h[1][c] = u1 + a1;
+  } else {
+    h[0][c] = u0 - a0;
+    h[1][c] = u1 - a1;
+  }
+}
+
+// acc += (1 + SG*gamma_mu) W psi for a spinor psi already in registers.
+template <typename R, int MU, int SG>
+__device__ __forceinline__ void hop_term_vals(cplx<R> (&acc)[12], const cplx<R> (&psi)[12],
+                                              const cplx<R>* __restrict__ w) {
+  cplx<R> h[2][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) project<R, MU, SG>(h, c, psi[c], psi[3 + c], psi[6 + c], psi[9 + c]);
+  link_mul_add<R, MU, SG>(acc, h, w);
+}
+
 struct HopArgs {
   Geom g;
   int out_parity;
   int spw;            // sites per workgroup
-  int bx, by, bz, bt; // 4D site block per workgroup in (x/2, y, z, t); bx = 0: linear cb order
+  int bx, by, bz, bt; // 4D site block per workgroup in (x/2, y, z, t), powers of two; bx = 0: linear cb order
+  int lbx, lby, lbz;  // log2 of bx, by, bz
   int nbx, nby, nbz;  // block-grid extents
   int remap;          // XCD-contiguous workgroup order
-  int nt;             // bit 0: non-temporal output stores; bit 1: non-temporal gauge loads
+  int nt;             // non-temporal output stores
   int morton;         // Morton (bit-interleaved) order of the block grid (power-of-two grids)
   int nbt;            // block-grid extent in t
   size_t field;       // complex elements per rhs
@@ -226,101 +237,66 @@ struct HopArgs {
   double* result;     // [rhs]
 };
 
-template <typename R, bool DAG, int EPI>
-__global__ void __launch_bounds__(256)
-hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
-           const cplx<R>* __restrict__ center, const cplx<R>* __restrict__ gauge,
-           const R* __restrict__ pw, HopArgs A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const Geom& g = A.g;
-  const int Ls = g.Ls;
-  const int wg = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int rhs = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int vloc = tid / Ls, s = tid - vloc * Ls;
-  int v;
-  if (A.bx > 0) {
-    // workgroup = one bx*by*bz*bt block of sites in (x/2, y, z, t)
-    int gx, gy, gz, gt;
-    if (A.morton) {
-      // de-interleave the bits of wg over the four block-grid dimensions
-      gx = gy = gz = gt = 0;
-      int bit = 0, px = 0, py = 0, pz = 0, pt = 0;
-      while ((1 << px) < A.nbx || (1 << py) < A.nby || (1 << pz) < A.nbz || (1 << pt) < A.nbt) {
-        if ((1 << px) < A.nbx) gx |= ((wg >> bit++) & 1) << px++;
-        if ((1 << py) < A.nby) gy |= ((wg >> bit++) & 1) << py++;
-        if ((1 << pz) < A.nbz) gz |= ((wg >> bit++) & 1) << pz++;
-        if ((1 << pt) < A.nbt) gt |= ((wg >> bit++) & 1) << pt++;
-      }
-    } else {
-      int q = wg;
-      gx = q % A.nbx; q /= A.nbx;
-      gy = q % A.nby; q /= A.nby;
-      gz = q % A.nbz;
-      gt = q / A.nbz;
+// Block coordinates of workgroup wg in the block grid (lexicographic or
+// Morton order); uniform across the workgroup.
+__device__ __forceinline__ void hop_block(const HopArgs& A, int wg, int& gx, int& gy, int& gz, int& gt) {
+  if (A.morton) {
+    // de-interleave the bits of wg over the four block-grid dimensions
+    gx = gy = gz = gt = 0;
+    int bit = 0, px = 0, py = 0, pz = 0, pt = 0;
+    while ((1 << px) < A.nbx || (1 << py) < A.nby || (1 << pz) < A.nbz || (1 << pt) < A.nbt) {
+      if ((1 << px) < A.nbx) gx |= ((wg >> bit++) & 1) << px++;
+      if ((1 << py) < A.nby) gy |= ((wg >> bit++) & 1) << py++;
+      if ((1 << pz) < A.nbz) gz |= ((wg >> bit++) & 1) << pz++;
+      if ((1 << pt) < A.nbt) gt |= ((wg >> bit++) & 1) << pt++;
     }
-    int r = vloc;
-    const int lx = r % A.bx; r /= A.bx;
-    const int ly = r % A.by; r /= A.by;
-    const int lz = r % A.bz;
-    const int lt = r / A.bz;
-    const int xh = gx * A.bx + lx, yy = gy * A.by + ly, zz = gz * A.bz + lz, tt = gt * A.bt + lt;
-    v = xh + g.Xh * (yy + g.Y * (zz + g.Z * tt));
   } else {
-    v = wg * A.spw + vloc;
+    int q = wg;
+    gx = q % A.nbx; q /= A.nbx;
+    gy = q % A.nby; q /= A.nby;
+    gz = q % A.nbz;
+    gt = q / A.nbz;
   }
-  const bool active = (vloc < A.spw) && (v < g.Vh);
+}
 
-  in += rhs * A.field;
-  out += rhs * A.field;
-
-  cplx<R> acc[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = cmk((R)0, (R)0);
-
-  // forward terms (1 - g) U(x) psi(x+mu) [non-dagger]; dagger flips signs
-  constexpr int SF = DAG ? 1 : -1;
-  const bool ntg = (A.nt & 2) != 0;
-  if (active) {
-    const Site c = site_coords(v, A.out_parity, g);
-    const size_t col = (size_t)12 * Ls;
-    const cplx<R>* G = gauge + (size_t)v * 72;
-    const int rowyzt = c.rest * g.Xh;
-    // x direction
-    {
-      const int xp = (c.x + 1 == g.X) ? 0 : c.x + 1;
-      const int xm = (c.x == 0) ? g.X - 1 : c.x - 1;
-      hop_term<R, 0, SF>(acc, in + (size_t)((xp >> 1) + rowyzt) * col + s, G + 0 * 9, Ls, ntg);
-      hop_term<R, 0, -SF>(acc, in + (size_t)((xm >> 1) + rowyzt) * col + s, G + 4 * 9, Ls, ntg);
-    }
-    // y direction
-    {
-      const int zt = c.rest / g.Y;
-      const int yp = (c.y + 1 == g.Y) ? 0 : c.y + 1;
-      const int ym = (c.y == 0) ? g.Y - 1 : c.y - 1;
-      hop_term<R, 1, SF>(acc, in + (size_t)(c.xh + g.Xh * (yp + g.Y * zt)) * col + s, G + 1 * 9, Ls, ntg);
-      hop_term<R, 1, -SF>(acc, in + (size_t)(c.xh + g.Xh * (ym + g.Y * zt)) * col + s, G + 5 * 9, Ls, ntg);
-    }
-    // z direction
-    {
-      const int zp = (c.z + 1 == g.Z) ? 0 : c.z + 1;
-      const int zm = (c.z == 0) ? g.Z - 1 : c.z - 1;
-      const size_t b = (size_t)c.xh + (size_t)g.Xh * c.y;
-      const size_t sy = (size_t)g.Xh * g.Y;
-      hop_term<R, 2, SF>(acc, in + (b + sy * (zp + (size_t)g.Z * c.t)) * col + s, G + 2 * 9, Ls, ntg);
-      hop_term<R, 2, -SF>(acc, in + (b + sy * (zm + (size_t)g.Z * c.t)) * col + s, G + 6 * 9, Ls, ntg);
-    }
-    // t direction
-    {
-      const int tp = (c.t + 1 == g.T) ? 0 : c.t + 1;
-      const int tm = (c.t == 0) ? g.T - 1 : c.t - 1;
-      const size_t b = (size_t)c.xh + (size_t)g.Xh * (c.y + (size_t)g.Y * c.z);
-      const size_t sz = (size_t)g.Xh * g.Y * g.Z;
-      hop_term<R, 3, SF>(acc, in + (b + sz * tp) * col + s, G + 3 * 9, Ls, ntg);
-      hop_term<R, 3, -SF>(acc, in + (b + sz * tm) * col + s, G + 7 * 9, Ls, ntg);
-    }
+// Coordinates and checkerboard index of the vloc-th output site of
+// workgroup wg: either `spw` consecutive sites, or one bx*by*bz*bt block of
+// the (x/2, y, z, t) grid, the blocks taken in lexicographic or Morton
+// (bit-interleaved) order.  The index may exceed Vh - 1 only in the linear
+// order's last workgroup (then the coordinates are not meaningful).
+__device__ __forceinline__ int hop_site(const HopArgs& A, int wg, int vloc, Site& c) {
+  const Geom& g = A.g;
+  if (A.bx <= 0) {
+    const int v = wg * A.spw + vloc;
+    c = site_coords(v, A.out_parity, g);
+    return v;
   }
+  int gx, gy, gz, gt;
+  hop_block(A, wg, gx, gy, gz, gt);
+  c.xh = gx * A.bx + (vloc & (A.bx - 1));
+  c.y = gy * A.by + ((vloc >> A.lbx) & (A.by - 1));
+  c.z = gz * A.bz + ((vloc >> (A.lbx + A.lby)) & (A.bz - 1));
+  c.t = gt * A.bt + (vloc >> (A.lbx + A.lby + A.lbz));
+  c.zt = c.z + g.Z * c.t;
+  c.rest = c.y + g.Y * c.zt;
+  c.x = 2 * c.xh + ((c.y + c.z + c.t + A.out_parity) & 1);
+  return c.xh + g.Xh * c.rest;
+}
 
+// Fifth-dimension epilogue of a hop stage: acc holds (Dh in) or (Dh^+ in)
+// at (site v, slice s).  EPI_INV stages acc in LDS (`smem_raw`, spw*12*(Ls+1)
+// complex) and applies M_5^-1 (or M_5^-+); EPI_SUB forms M_5 c - acc/4 (or
+// M_5^+ c - acc/4) and, when A.partials is set, stores this workgroup's part
+// of its squared norm.  Every thread of the workgroup must call it.
+template <typename R, bool DAG, int EPI, int LS = 0>
+__device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool active, int vloc, int s,
+                                             int v, int wg, int rhs, cplx<R>* __restrict__ out,
+                                             const cplx<R>* __restrict__ center,
+                                             const R* __restrict__ pw, const HopArgs& A,
+                                             unsigned char* smem_raw) {
+  const Geom& g = A.g;
+  const int Ls = LS > 0 ? LS : g.Ls;
+  const int tid = threadIdx.x;
   if (EPI == EPI_INV) {
     // ---- M_5^-1 (or its adjoint) across s, through LDS --------------------
     cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][12][Ls+1]
@@ -396,6 +372,127 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
       store_partial<1>(vv, A.partials + (size_t)rhs * kMaxPartials, 0, wg);
     }
   }
+}
+
+// ---------------------------------------------------------- hop kernel --
+constexpr int kLinkLd = 73;  // LDS row of one site's 72 link entries (odd: no bank aliasing)
+
+// Checkerboard indices of the eight neighbours of site c, in the order
+// x+, x-, y+, y-, z+, z-, t+, t-.
+__device__ __forceinline__ void hop_neighbours(const Geom& g, const Site& c, int (&nb)[8]) {
+  const int rowyzt = c.rest * g.Xh;
+  const int xp = (c.x + 1 == g.X) ? 0 : c.x + 1;
+  const int xm = (c.x == 0) ? g.X - 1 : c.x - 1;
+  nb[0] = (xp >> 1) + rowyzt;
+  nb[1] = (xm >> 1) + rowyzt;
+  const int yp = (c.y + 1 == g.Y) ? 0 : c.y + 1;
+  const int ym = (c.y == 0) ? g.Y - 1 : c.y - 1;
+  nb[2] = c.xh + g.Xh * (yp + g.Y * c.zt);
+  nb[3] = c.xh + g.Xh * (ym + g.Y * c.zt);
+  const int zp = (c.z + 1 == g.Z) ? 0 : c.z + 1;
+  const int zm = (c.z == 0) ? g.Z - 1 : c.z - 1;
+  const int bz = c.xh + g.Xh * c.y, sy = g.Xh * g.Y;
+  nb[4] = bz + sy * (zp + g.Z * c.t);
+  nb[5] = bz + sy * (zm + g.Z * c.t);
+  const int tp = (c.t + 1 == g.T) ? 0 : c.t + 1;
+  const int tm = (c.t == 0) ? g.T - 1 : c.t - 1;
+  const int bt = c.xh + g.Xh * (c.y + g.Y * c.z), sz = g.Xh * g.Y * g.Z;
+  nb[6] = bt + sz * tp;
+  nb[7] = bt + sz * tm;
+}
+
+// Direction D of hop_neighbours: mu = D/2, forward (even D, link mu) or
+// backward (odd D, link 4 + mu); SF is the sign of gamma_mu on forward hops.
+template <typename R, int D, int SF>
+__device__ __forceinline__ void dir_term(cplx<R> (&acc)[12], const cplx<R> (&psi)[12],
+                                         const cplx<R>* links) {
+  constexpr int MU = D / 2;
+  constexpr int SG = (D & 1) ? -SF : SF;
+  hop_term_vals<R, MU, SG>(acc, psi, links + ((D & 1) ? 4 + MU : MU) * 9);
+}
+
+template <typename R, int D0, int N>
+__device__ __forceinline__ void load_dirs(cplx<R> (&psi)[N][12], const cplx<R>* __restrict__ in,
+                                          const int (&nb)[8], size_t col, int s, int Ls) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const cplx<R>* p = in + (size_t)nb[D0 + k] * col + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[k][c] = p[c * Ls];
+  }
+}
+
+template <typename R, int D0, int N, int SF>
+__device__ __forceinline__ void apply_dirs(cplx<R> (&acc)[12], const cplx<R> (&psi)[N][12],
+                                           const cplx<R>* links) {
+  dir_term<R, D0 + 0, SF>(acc, psi[0], links);
+  if (N > 1) dir_term<R, D0 + 1, SF>(acc, psi[N > 1 ? 1 : 0], links);
+  if (N > 2) dir_term<R, D0 + 2, SF>(acc, psi[N > 2 ? 2 : 0], links);
+  if (N > 3) dir_term<R, D0 + 3, SF>(acc, psi[N > 3 ? 3 : 0], links);
+  if (N > 4) dir_term<R, (D0 + 4) & 7, SF>(acc, psi[N > 4 ? 4 : 0], links);
+  if (N > 5) dir_term<R, (D0 + 5) & 7, SF>(acc, psi[N > 5 ? 5 : 0], links);
+  if (N > 6) dir_term<R, (D0 + 6) & 7, SF>(acc, psi[N > 6 ? 6 : 0], links);
+  if (N > 7) dir_term<R, (D0 + 7) & 7, SF>(acc, psi[N > 7 ? 7 : 0], links);
+}
+
+// NPH = number of load phases (2: four directions in flight at a time; 4:
+// two).  LS > 0 fixes Ls at compile time.  Dynamic LDS:
+// max(spw * kLinkLd, spw * 12 * (Ls + 1)) complex.
+template <typename R, bool DAG, int EPI, int NPH, int LS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
+               const cplx<R>* __restrict__ center, const cplx<R>* __restrict__ gauge,
+               const R* __restrict__ pw, HopArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const Geom& g = A.g;
+  const int Ls = LS > 0 ? LS : g.Ls;  // compile-time when LS > 0: immediate load offsets
+  const int wg = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int vloc = tid / Ls, s = tid - vloc * Ls;
+  Site c;
+  const int v = hop_site(A, wg, vloc, c);
+  const bool active = (vloc < A.spw) && (v < g.Vh);
+
+  in += rhs * A.field;
+  out += rhs * A.field;
+
+  cplx<R>* links = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][kLinkLd]
+  if (active) {
+    const cplx<R>* G = gauge + (size_t)v * 72;
+    for (int e = s; e < 72; e += Ls) links[vloc * kLinkLd + e] = G[e];
+  }
+
+  constexpr int ND = 8 / NPH;
+  constexpr int SF = DAG ? 1 : -1;
+  const size_t col = (size_t)12 * Ls;
+  int nb[8];
+  cplx<R> psi[ND][12];
+  if (active) {
+    hop_neighbours(g, c, nb);
+    load_dirs<R, 0, ND>(psi, in, nb, col, s, Ls);
+  }
+  __syncthreads();  // links in LDS
+
+  cplx<R> acc[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = cmk((R)0, (R)0);
+  if (active) {
+    const cplx<R>* L = links + vloc * kLinkLd;
+    apply_dirs<R, 0, ND, SF>(acc, psi, L);
+    if (NPH >= 2) {
+      load_dirs<R, ND % 8, ND>(psi, in, nb, col, s, Ls);
+      apply_dirs<R, ND % 8, ND, SF>(acc, psi, L);
+    }
+    if (NPH == 4) {
+      load_dirs<R, 4, ND>(psi, in, nb, col, s, Ls);
+      apply_dirs<R, 4, ND, SF>(acc, psi, L);
+      load_dirs<R, 6, ND>(psi, in, nb, col, s, Ls);
+      apply_dirs<R, 6, ND, SF>(acc, psi, L);
+    }
+  }
+  if (EPI == EPI_INV) __syncthreads();  // the M_5^-1 buffer reuses the link rows
+  hop_epilogue<R, DAG, EPI, LS>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
 }
 
 // ------------------------------------------------------------------ BLAS ---
@@ -521,6 +618,23 @@ int ensure_tmp(dwf_op* op, int prec, int nrhs) {
   return DWF_OK;
 }
 
+template <typename R, int NPH, int LS>
+static void launch_hop(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                       cplx<R>* out, const cplx<R>* in, const cplx<R>* center, const cplx<R>* G,
+                       const R* pw, const HopArgs& A) {
+  if (epi == EPI_INV) {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+  } else {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+  }
+}
+
 template <typename R>
 static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>* center,
                       bool dagger, int epi, int out_parity, int nrhs, hipStream_t stream,
@@ -529,10 +643,10 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   HopArgs A;
   A.g = g;
   A.out_parity = out_parity;
-  // at most 256 threads, and the M_5^-1 staging buffer within 64 KiB of LDS
-  A.spw = g.Ls >= 256 ? 1 : 256 / g.Ls;
-  while (A.spw > 1 && (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(c128) > 65536) A.spw >>= 1;
+  // linear order: one wave's worth of threads per workgroup (at least one site)
+  A.spw = g.Ls >= 64 ? 1 : 64 / g.Ls;
   A.bx = A.by = A.bz = A.bt = 0;
+  A.lbx = A.lby = A.lbz = 0;
   A.nbx = A.nby = A.nbz = 1;
   A.remap = op->tune.remap;
   A.nt = op->tune.nt;
@@ -540,7 +654,8 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   A.nbt = 1;
   {
     const int* b = op->tune.block;
-    if (b[0] > 0 && b[0] * b[1] * b[2] * b[3] * g.Ls <= 256 &&
+    auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+    if (b[0] > 0 && pow2(b[0]) && pow2(b[1]) && pow2(b[2]) && pow2(b[3]) && b[0] * b[1] * b[2] * b[3] * g.Ls <= 256 &&
         (size_t)b[0] * b[1] * b[2] * b[3] * 12 * (g.Ls + 1) * sizeof(c128) <= 65536 && g.Xh % b[0] == 0 && g.Y % b[1] == 0 &&
         g.Z % b[2] == 0 && g.T % b[3] == 0) {
       A.bx = b[0];
@@ -552,7 +667,9 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
       A.nby = g.Y / b[1];
       A.nbz = g.Z / b[2];
       A.nbt = g.T / b[3];
-      auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+      A.lbx = __builtin_ctz(b[0]);
+      A.lby = __builtin_ctz(b[1]);
+      A.lbz = __builtin_ctz(b[2]);
       A.morton = op->tune.morton && pow2(A.nbx) && pow2(A.nby) && pow2(A.nbz) && pow2(A.nbt);
     }
   }
@@ -576,18 +693,21 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   const R* pw = reinterpret_cast<const R*>(dbl ? op->pw128.ptr : op->pw64.ptr);
   dim3 grid(nwg, nrhs), block(threads);
   size_t lds = epi == EPI_INV ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  lds = std::max(lds, (size_t)A.spw * kLinkLd * sizeof(cplx<R>));
   // optional LDS request that caps the resident workgroups per CU
   if ((size_t)op->tune.lds_kb * 1024 > lds) lds = (size_t)op->tune.lds_kb * 1024;
-  if (epi == EPI_INV) {
-    if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV>), grid, block, lds, stream, out, in, center, G, pw, A);
+  // directions whose neighbour loads are in flight together: 8 / phases
+  const bool two = op->tune.phases == 4;
+  if (g.Ls == 16) {
+    if (two)
+      launch_hop<R, 4, 16>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV>), grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 2, 16>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   } else {
-    if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB>), grid, block, lds, stream, out, in, center, G, pw, A);
+    if (two)
+      launch_hop<R, 4, 0>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB>), grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 2, 0>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   }
   HDCG_HIP(hipGetLastError());
   if (norm_result) return launch_finalize(1, A.partials, 0, nwg, nrhs, norm_result, stream);
