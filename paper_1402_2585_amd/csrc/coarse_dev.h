@@ -1,0 +1,244 @@
+// Device code of the little Dirac operator mat-vec, shared by the
+// standalone mat-vec kernels and the persistent coarse CG kernel.
+//
+// (A c)[r][a][j] = sum_l sum_k A[a][l][j][k] c[r][nbr(a,l)][k]   (Sec. V.A)
+//
+// Both forms take one coarse site a per 512-thread workgroup (8 waves).
+#pragma once
+
+#include "hdcg_impl.h"
+
+namespace hdk {
+
+constexpr int kCT = 512;  // threads per coarse-site workgroup
+
+// Loads and stores of complex64 values that other workgroups of a running
+// persistent kernel write or read: relaxed device-scope atomics, coherent
+// across the XCDs' L2 caches without whole-cache write-back or invalidation.
+__device__ __forceinline__ c64 ld_coherent(const c64* p) {
+  const unsigned long long v =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_bit_cast(c64, v);
+}
+__device__ __forceinline__ void st_coherent(c64* p, c64 v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------- complex64/128 VALU --
+// AT[a][l][k][j] (transposed per stencil point).  Thread (part, j) sums the
+// columns q = (l, k) = part, part + parts, ... of row j, U columns at a time
+// with all their loads issued before the multiply-adds (the operator is read
+// once per mat-vec, so many loads must be in flight per wave).  Writes
+// out[r][a][j] for r0 <= r < min(r0 + NR, nr).  `red` is kCT * NR complex
+// of LDS.  With STAGED (one right-hand side) `in` is instead the site's
+// operand already gathered into LDS: in[l * nvec + k] = c[nbr(a,l)][k].
+// Every thread of the workgroup must call it.
+template <typename R, int NR, int U, bool STAGED = false>
+__device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr,
+                                            const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
+                                            int a, int Nc, int nvec, int nr, int r0, cplx<R>* red) {
+  static_assert(!STAGED || NR == 1, "a staged operand holds one right-hand side");
+  const int parts = kCT / nvec;
+  const int j = threadIdx.x % nvec, part = threadIdx.x / nvec;
+  const int K = kStencil * nvec;
+  cplx<R> acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
+  if (part < parts) {
+    const cplx<R>* Aa = AT + (size_t)a * K * nvec + j;
+    const int* nb = nbr + (size_t)a * kStencil;
+    for (int q0 = part; q0 < K; q0 += parts * U) {
+      cplx<R> Av[U], xv[U][NR];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * parts;
+        Av[u] = cmk((R)0, (R)0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) xv[u][r] = cmk((R)0, (R)0);
+        if (q < K) {
+          Av[u] = Aa[(size_t)q * nvec];
+          if constexpr (STAGED) {
+            xv[u][0] = in[q];
+          } else {
+            const int l = q / nvec, k = q - l * nvec;
+            const size_t vo = (size_t)nb[l] * nvec + k;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+              if (r0 + r < nr) xv[u][r] = in[(size_t)(r0 + r) * Nc * nvec + vo];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cmac(acc[r], Av[u], xv[u][r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[r * kCT + threadIdx.x] = acc[r];
+  __syncthreads();
+  if (threadIdx.x < nvec) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r0 + r >= nr) continue;
+      cplx<R> s = cmk((R)0, (R)0);
+      for (int p = 0; p < parts; ++p) s = s + red[r * kCT + p * nvec + threadIdx.x];
+      out[((size_t)(r0 + r) * Nc + a) * nvec + threadIdx.x] = s;
+    }
+  }
+  __syncthreads();  // `red` may be reused by the caller
+}
+
+// ------------------------------------------------------ 16-bit MFMA form --
+// For one coarse site the 81-point stencil is one real GEMM
+//   out[j][n] = sum_kappa Ahat[j][kappa] B[kappa][n]
+// with kappa = (part, l, k) over K = 2 * 81 * Nvec:
+//   Ahat[j][(0,l,k)] = Re A[a][l][j][k] / s_al,  Ahat[j][(1,l,k)] = Im A[a][l][j][k] / s_al
+//   B[(0,l,k)][r]          = rho_al Re c_r[a+dl][k],   B[(1,l,k)][r]          = -rho_al Im c_r[a+dl][k]
+//   B[(0,l,k)][nrhs + r]   = rho_al Im c_r[a+dl][k],   B[(1,l,k)][nrhs + r]   =  rho_al Re c_r[a+dl][k]
+// so that columns r and nrhs + r give Re and Im of (A c_r)[a][j] / smax_a.
+// s_al is the largest |Re|, |Im| entry of the matrix A[a][l] (per-matrix
+// scale), smax_a = max_l s_al and rho_al = s_al / smax_a <= 1, which keeps
+// both operands within the fp16 range.
+//
+// Ahat is stored per coarse site and K step as [row m < nvec][kgroup 0..3][4]
+// (the 16 K values of one step and row are contiguous), so the A fragment of
+// an M tile is one contiguous run that a wave reads with 8-byte lanes, and no
+// bytes are stored or read for the rows that pad nvec to a multiple of 16.
+// The NW waves take U consecutive K steps at a time, with all their loads
+// issued before the MFMAs, and reduce through LDS.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ unsigned short f2h(float f) {
+  _Float16 h = (_Float16)f;
+  return __builtin_bit_cast(unsigned short, h);
+}
+template <bool BF16>
+__device__ __forceinline__ unsigned short to16(float f) {
+  return BF16 ? f2bf(f) : f2h(f);
+}
+
+// `red` is NW * MT * NT * 64 f32x4 of LDS.  Writes out[r][a][:] for the
+// nrhs right-hand sides of `in` (at most 16 when NT = 2, 8 when NT = 1).
+// With STAGED (one right-hand side) `in` is the site's operand gathered
+// into LDS: in[l * nvec + k] = c[nbr(a,l)][k].  Every thread of the
+// workgroup (NW * 64 threads) must call it.
+template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false>
+__device__ __forceinline__ void capply_site_mfma(const unsigned short* __restrict__ F,
+                                                 const float* __restrict__ rho,
+                                                 const float* __restrict__ smax, const int* __restrict__ nbr,
+                                                 const c64* __restrict__ in, c64* __restrict__ out, int a,
+                                                 int Nc, int nvec, int nrhs, int ksteps, f32x4* red) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ktot = 2 * kStencil * nvec;
+  const int kn = kStencil * nvec;
+  const int r16 = lane & 15, kg = lane >> 4;
+  f32x4 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
+  const int* nb = nbr + (size_t)a * kStencil;
+  const float* rh = rho + (size_t)a * kStencil;
+  for (int s0 = wave * U; s0 < ksteps; s0 += NW * U) {
+    s16x4 af[U][MT];
+    s16x4 bf[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 + u;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int m = mt * 16 + r16;
+        af[u][mt] = (s < ksteps && m < nvec)
+                        ? *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * nvec + m) * 4 + kg) * 4)
+                        : s16x4{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k0 = 16 * (s0 + u) + 4 * kg;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = s16x4{0, 0, 0, 0};
+      if (s0 + u < ksteps && k0 < ktot) {
+        const int part = k0 / kn;
+        const int rem = k0 - part * kn;
+        const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
+        const float r = rh[l];
+        const size_t vo = (size_t)nb[l] * nvec + k;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int g = nt * 16 + r16;
+          if (g < 2 * nrhs) {
+            const bool imcol = g >= nrhs;
+            const int rr = imcol ? g - nrhs : g;
+            const size_t co = (size_t)rr * Nc * nvec + vo;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const c64 x = STAGED ? in[rem + i] : in[co + i];
+              // columns r:        part 0 -> Re c, part 1 -> -Im c
+              // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
+              v[i] = r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im));
+            }
+            s16x4 b;
+            b.x = (short)to16<BF16>(v[0]);
+            b.y = (short)to16<BF16>(v[1]);
+            b.z = (short)to16<BF16>(v[2]);
+            b.w = (short)to16<BF16>(v[3]);
+            bf[u][nt] = b;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          if (BF16)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u][mt], bf[u][nt], acc[mt][nt], 0, 0, 0);
+          else
+            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[u][mt]),
+                                                                __builtin_bit_cast(h16x4, bf[u][nt]),
+                                                                acc[mt][nt], 0, 0, 0);
+        }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) red[(wave * MT * NT + mt * NT + nt) * 64 + lane] = acc[mt][nt];
+  __syncthreads();
+  const float sm = smax[a];
+  for (int q = threadIdx.x; q < MT * NT * 64; q += NW * 64) {
+    const int tile = q >> 6, ln = q & 63;
+    const int mt = tile / NT, nt = tile - mt * NT;
+    f32x4 v = red[tile * 64 + ln];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[(w * MT * NT + tile) * 64 + ln];
+    // lane ln holds D[m = 4 (ln / 16) + i][n = ln % 16]
+    const int g = nt * 16 + (ln & 15);
+    if (g >= 2 * nrhs) continue;
+    const bool imcol = g >= nrhs;
+    const int rr = imcol ? g - nrhs : g;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mt * 16 + 4 * (ln >> 4) + i;
+      if (m >= nvec) continue;
+      float* o = reinterpret_cast<float*>(out + ((size_t)rr * Nc + a) * nvec + m);
+      o[imcol ? 1 : 0] = sm * v[i];
+    }
+  }
+  __syncthreads();  // `red` may be reused by the caller
+}
+
+}  // namespace hdk

@@ -1,48 +1,12 @@
-// Little Dirac operator mat-vec on MFMA with 16-bit matrix storage
-// (bf16 or fp16) and FP32 accumulation.
-//
-// For one coarse site a the 81-point stencil is one real GEMM
-//   out[j][n] = sum_kappa Ahat[j][kappa] B[kappa][n]
-// with kappa = (part, l, k) over K = 2 * 81 * Nvec:
-//   Ahat[j][(0,l,k)] = Re A[a][l][j][k] / s_al,  Ahat[j][(1,l,k)] = Im A[a][l][j][k] / s_al
-//   B[(0,l,k)][r]          = rho_al Re c_r[a+dl][k],   B[(1,l,k)][r]          = -rho_al Im c_r[a+dl][k]
-//   B[(0,l,k)][nrhs + r]   = rho_al Im c_r[a+dl][k],   B[(1,l,k)][nrhs + r]   =  rho_al Re c_r[a+dl][k]
-// so that columns r and nrhs + r give Re and Im of (A c_r)[a][j] / smax_a.
-// s_al is the largest |Re|, |Im| entry of the matrix A[a][l] (per-matrix
-// scale), smax_a = max_l s_al and rho_al = s_al / smax_a <= 1, which keeps
-// both operands within the fp16 range.
-//
-// Ahat is stored per coarse site and K step as [row m < nvec][kgroup 0..3][4]
-// (the 16 K values of one step and row are contiguous), so the A fragment of
-// an M tile is one contiguous run that a wave reads with 8-byte lanes, and no
-// bytes are stored or read for the rows that pad nvec to a multiple of 16.
-// One workgroup (NW waves) per coarse site; each wave takes U consecutive K
-// steps at a time, with all their loads issued before the MFMAs, and the
-// waves reduce through LDS.
-#include "hdcg_impl.h"
+// Little Dirac operator mat-vec on MFMA with 16-bit matrix storage (bf16
+// or fp16) and FP32 accumulation: per-matrix scales, fragment-ordered
+// storage and the standalone mat-vec launch.  The per-site GEMM itself
+// (operand layout, scaling) is capply_site_mfma in coarse_dev.h.
+#include "coarse_dev.h"
 
 namespace hdk {
 
 namespace {
-
-typedef short s16x4 __attribute__((ext_vector_type(4)));
-typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ unsigned short f2h(float f) {
-  _Float16 h = (_Float16)f;
-  return __builtin_bit_cast(unsigned short, h);
-}
-
-template <bool BF16>
-__device__ __forceinline__ unsigned short to16(float f) {
-  return BF16 ? f2bf(f) : f2h(f);
-}
 
 // per-matrix scales: s[a][l] = max |Re|, |Im| over A[a][l]
 __global__ void k_scales(const c128* __restrict__ A, float* __restrict__ s, int nvec2) {
@@ -112,109 +76,27 @@ __global__ void __launch_bounds__(NW * 64)
 k_capply_mfma(const unsigned short* __restrict__ F, const float* __restrict__ rho,
               const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
               c64* __restrict__ out, int Nc, int nvec, int nrhs, int ksteps) {
-  __shared__ f32x4 red[NW][MT * NT][64];
+  __shared__ f32x4 red[NW * MT * NT * 64];
+  capply_site_mfma<BF16, MT, NT, NW, U>(F, rho, smax, nbr, in, out, blockIdx.x, Nc, nvec, nrhs, ksteps, red);
+}
+
+// One right-hand side: the site's operand at its 81 neighbours is gathered
+// into LDS first (one coalesced pass).
+template <bool BF16, int MT>
+__global__ void __launch_bounds__(8 * 64)
+k_capply_mfma_staged(const unsigned short* __restrict__ F, const float* __restrict__ rho,
+                     const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
+                     c64* __restrict__ out, int Nc, int nvec, int ksteps) {
+  __shared__ f32x4 red[8 * MT * 64];
+  __shared__ c64 xin[kStencil * 64];
   const int a = blockIdx.x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ktot = 2 * kStencil * nvec;
-  const int kn = kStencil * nvec;
-  const int r16 = lane & 15, kg = lane >> 4;
-  f32x4 acc[MT][NT];
-#pragma unroll
-  for (int i = 0; i < MT; ++i)
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
   const int* nb = nbr + (size_t)a * kStencil;
-  const float* rh = rho + (size_t)a * kStencil;
-  for (int s0 = wave * U; s0 < ksteps; s0 += NW * U) {
-    s16x4 af[U][MT];
-    s16x4 bf[U][NT];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int s = s0 + u;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int m = mt * 16 + r16;
-        af[u][mt] = (s < ksteps && m < nvec)
-                        ? *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * nvec + m) * 4 + kg) * 4)
-                        : s16x4{0, 0, 0, 0};
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k0 = 16 * (s0 + u) + 4 * kg;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = s16x4{0, 0, 0, 0};
-      if (s0 + u < ksteps && k0 < ktot) {
-        const int part = k0 / kn;
-        const int rem = k0 - part * kn;
-        const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
-        const float r = rh[l];
-        const size_t vo = (size_t)nb[l] * nvec + k;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int g = nt * 16 + r16;
-          if (g < 2 * nrhs) {
-            const bool imcol = g >= nrhs;
-            const int rr = imcol ? g - nrhs : g;
-            const c64* c = in + (size_t)rr * Nc * nvec + vo;
-            float v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const c64 x = c[i];
-              // columns r:        part 0 -> Re c, part 1 -> -Im c
-              // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
-              v[i] = r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im));
-            }
-            s16x4 b;
-            b.x = (short)to16<BF16>(v[0]);
-            b.y = (short)to16<BF16>(v[1]);
-            b.z = (short)to16<BF16>(v[2]);
-            b.w = (short)to16<BF16>(v[3]);
-            bf[u][nt] = b;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          if (BF16)
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u][mt], bf[u][nt], acc[mt][nt], 0, 0, 0);
-          else
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[u][mt]),
-                                                                __builtin_bit_cast(h16x4, bf[u][nt]),
-                                                                acc[mt][nt], 0, 0, 0);
-        }
+  for (int e = threadIdx.x; e < kStencil * nvec; e += 8 * 64) {
+    const int l = e / nvec;
+    xin[e] = in[(size_t)nb[l] * nvec + (e - l * nvec)];
   }
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) red[wave][mt * NT + nt][lane] = acc[mt][nt];
   __syncthreads();
-  const float sm = smax[a];
-  for (int q = threadIdx.x; q < MT * NT * 64; q += NW * 64) {
-    const int tile = q >> 6, ln = q & 63;
-    const int mt = tile / NT, nt = tile - mt * NT;
-    f32x4 v = red[0][tile][ln];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) v += red[w][tile][ln];
-    // lane ln holds D[m = 4 (ln / 16) + i][n = ln % 16]
-    const int g = nt * 16 + (ln & 15);
-    if (g >= 2 * nrhs) continue;
-    const bool imcol = g >= nrhs;
-    const int rr = imcol ? g - nrhs : g;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = mt * 16 + 4 * (ln >> 4) + i;
-      if (m >= nvec) continue;
-      float* o = reinterpret_cast<float*>(out + ((size_t)rr * Nc + a) * nvec + m);
-      o[imcol ? 1 : 0] = sm * v[i];
-    }
-  }
+  capply_site_mfma<BF16, MT, 1, 8, 4, true>(F, rho, smax, nbr, xin, out, a, Nc, nvec, 1, ksteps, red);
 }
 
 // 8 waves per workgroup while their LDS reduction buffers fit in 48 KiB
@@ -239,7 +121,10 @@ int launch_mt(hdcg* h, const unsigned short* F, const c64* in, c64* out, int nr,
     const int n = nr - r0 < 16 ? nr - r0 : 16;
     const c64* i0 = in + (size_t)r0 * h->Nc * h->nvec;
     c64* o0 = out + (size_t)r0 * h->Nc * h->nvec;
-    if (2 * n <= 16)
+    if (n == 1)
+      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho, smax,
+                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, ksteps);
+    else if (2 * n <= 16)
       launch_tile<BF16, MT, 1>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);
     else
       launch_tile<BF16, MT, 2>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);

@@ -39,7 +39,10 @@ struct hdcg {
   hdk::DevBuf mf_rho, mf_smax;      // per-matrix scales of the 16-bit coarse storage
   hdk::DevBuf mf_bf16, mf_f16;      // MFMA fragment-ordered 16-bit coarse matrices
   int mf_have_bf16 = 0, mf_have_f16 = 0;
-  double* pinned = nullptr;   // host pinned scalars
+  hdk::DevBuf pcg_part;             // persistent coarse CG: per-workgroup partial sums
+  hdk::DevBuf pcg_state;            // persistent coarse CG: grid barrier, status, iterations
+  int persistent_coarse = 1;        // run the coarse CG as one persistent kernel when it applies
+  double* pinned = nullptr;   // host pinned scalars [16][64]
   struct {
     int n_ii = 0;
     double lambda_ii = 0.0, tol_ii = 1e-4;
@@ -85,5 +88,11 @@ int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_
 int crs_transpose(hdcg* h, bool fp64, hipStream_t st);  // A128 -> AT128 (fp64) or AT64
 int crs_build_mfma(hdcg* h, int prec, hipStream_t st);
 int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
+
+// coarse CG from x = 0 on the complex64 (mprec = DWF_C64) or 16-bit MFMA
+// operator as one persistent kernel (coarse_cg.hip); *done = 0 when that form
+// does not apply (more than 8 right-hand sides, unsuited nvec).
+int coarse_cg_persistent(hdcg* h, int mprec, cplx<float>* x, const cplx<float>* b, int nr, double tol,
+                         int maxiter, int* iters, int* done, hipStream_t st);
 
 }  // namespace hdk

@@ -3,7 +3,7 @@
 //   products (project, Gram matrices), promote, Cholesky-QR
 //   orthonormalisation, the per-dimension inverse of the 81-point phase
 //   matrix, and the complex64/complex128 coarse block-stencil mat-vec.
-#include "hdcg_impl.h"
+#include "coarse_dev.h"
 
 namespace hdk {
 
@@ -144,14 +144,29 @@ k_project_small(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, si
   cplx<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
-  for (int j = 0; j < nsb; ++j) {
-    const size_t base = (size_t)so[j] * col;
-    const cplx<R>* Pj = Pk + (size_t)j * col;
-    for (int q = threadIdx.x; q < col; q += blockDim.x) {
-      const cplx<R> pv = conj(Pj[q]);
+  // U sites at a time, their loads issued before the multiply-adds
+  constexpr int U = 8;
+  for (int q = threadIdx.x; q < col; q += blockDim.x) {
+    for (int j0 = 0; j0 < nsb; j0 += U) {
+      cplx<R> pv[U], qv[U][NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r < nr) cmac(acc[r], pv, Q[r * fstride + base + q]);
+      for (int u = 0; u < U; ++u) {
+        pv[u] = cmk((R)0, (R)0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) qv[u][r] = cmk((R)0, (R)0);
+        const int j = j0 + u;
+        if (j < nsb) {
+          pv[u] = Pk[(size_t)j * col + q];
+          const size_t base = (size_t)so[j] * col + q;
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (r < nr) qv[u][r] = Q[r * fstride + base];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cjmac(acc[r], pv[u], qv[u][r]);
     }
   }
   __shared__ double red[2 * NR][4];
@@ -193,11 +208,17 @@ k_promote(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ c, int nr, 
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
   const cplx<R>* Pa = P + (size_t)a * nvec * nb + i;
-  for (int k = 0; k < nvec; ++k) {
-    const cplx<R> pv = Pa[(size_t)k * nb];
+  // U subspace vectors at a time, their loads issued before the multiply-adds
+  constexpr int U = 8;
+  for (int k0 = 0; k0 < nvec; k0 += U) {
+    cplx<R> pv[U];
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if (r < nr) cmac(acc[r], pv, cs[r * nvec + k]);
+    for (int u = 0; u < U; ++u) pv[u] = (k0 + u < nvec) ? Pa[(size_t)(k0 + u) * nb] : cmk((R)0, (R)0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r < nr && k0 + u < nvec) cmac(acc[r], pv[u], cs[r * nvec + k0 + u]);
   }
   const int j = (int)(i / col), q = (int)(i - (size_t)j * col);
   const size_t addr = (size_t)site_of[(size_t)a * nsb + j] * col + q;
@@ -344,41 +365,32 @@ __global__ void k_transpose(const c128* __restrict__ A, c128* __restrict__ AT128
 }
 
 // (A c)[r][a][j] = sum_l sum_k A[a][l][j][k] c[r][nbr(a,l)][k], with AT[a][l][k][j].
-template <typename R, int NR>
-__global__ void __launch_bounds__(kT)
+template <typename R, int NR, int U>
+__global__ void __launch_bounds__(kCT)
 k_capply(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr, const cplx<R>* __restrict__ in,
          cplx<R>* __restrict__ out, int Nc, int nvec, int nr) {
-  __shared__ cplx<R> red[kT * NR];
-  const int a = blockIdx.x, r0 = blockIdx.y * NR;
-  const int parts = kT / nvec;
-  const int j = threadIdx.x % nvec, part = threadIdx.x / nvec;
-  cplx<R> acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
-  if (part < parts) {
-    const cplx<R>* Aa = AT + (size_t)a * kStencil * nvec * nvec + j;
-    const int* nb = nbr + (size_t)a * kStencil;
-    for (int q = part; q < kStencil * nvec; q += parts) {
-      const int l = q / nvec, k = q - (q / nvec) * nvec;
-      const cplx<R> Av = Aa[(size_t)q * nvec];
-      const size_t vo = (size_t)nb[l] * nvec + k;
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (r0 + r < nr) cmac(acc[r], Av, in[(size_t)(r0 + r) * Nc * nvec + vo]);
-    }
+  __shared__ cplx<R> red[kCT * NR];
+  capply_site<R, NR, U>(AT, nbr, in, out, blockIdx.x, Nc, nvec, nr, blockIdx.y * NR, red);
+}
+
+// One right-hand side in complex64: the site's operand at its 81 neighbours
+// is first gathered into LDS (one coalesced pass), so the column loop reads
+// only the operator from memory.
+constexpr int kStageNvec = 64;
+template <int U>
+__global__ void __launch_bounds__(kCT)
+k_capply_staged(const c64* __restrict__ AT, const int* __restrict__ nbr, const c64* __restrict__ in,
+                c64* __restrict__ out, int Nc, int nvec) {
+  __shared__ c64 red[kCT];
+  __shared__ c64 xin[kStencil * kStageNvec];
+  const int a = blockIdx.x;
+  const int* nb = nbr + (size_t)a * kStencil;
+  for (int e = threadIdx.x; e < kStencil * nvec; e += kCT) {
+    const int l = e / nvec;
+    xin[e] = in[(size_t)nb[l] * nvec + (e - l * nvec)];
   }
-#pragma unroll
-  for (int r = 0; r < NR; ++r) red[r * kT + threadIdx.x] = acc[r];
   __syncthreads();
-  if (threadIdx.x < nvec) {
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (r0 + r >= nr) continue;
-      cplx<R> s = cmk((R)0, (R)0);
-      for (int p = 0; p < parts; ++p) s = s + red[r * kT + p * nvec + threadIdx.x];
-      out[((size_t)(r0 + r) * Nc + a) * nvec + threadIdx.x] = s;
-    }
-  }
+  capply_site<float, 1, U, true>(AT, nbr, xin, out, a, Nc, nvec, 1, 0, red);
 }
 
 }  // namespace
@@ -485,11 +497,23 @@ int blk_cholqr_step(hdcg* h, hipStream_t st) {
 
 template <typename R>
 int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st) {
-  if (h->nvec > kT) return fail(DWF_ERR_ARG, "nvec too large for the coarse mat-vec");
-  constexpr int NR = sizeof(R) == 8 ? 2 : 4;
-  dim3 grid(h->Nc, (nr + NR - 1) / NR);
-  hipLaunchKernelGGL((k_capply<R, NR>), grid, dim3(kT), 0, st, AT, h->nbr.as<int>(), in, out, h->Nc,
-                     h->nvec, nr);
+  if (h->nvec > kCT) return fail(DWF_ERR_ARG, "nvec too large for the coarse mat-vec");
+  if (nr == 1) {
+    if constexpr (sizeof(R) == 4) {
+      if (h->nvec <= kStageNvec) {
+        hipLaunchKernelGGL((k_capply_staged<16>), dim3(h->Nc), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in, out,
+                           h->Nc, h->nvec);
+        HDCG_HIP(hipGetLastError());
+        return DWF_OK;
+      }
+    }
+    hipLaunchKernelGGL((k_capply<R, 1, 16>), dim3(h->Nc, 1), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in, out,
+                       h->Nc, h->nvec, nr);
+  } else {
+    constexpr int NR = sizeof(R) == 8 ? 2 : 4;
+    hipLaunchKernelGGL((k_capply<R, NR, 8>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st, AT,
+                       h->nbr.as<int>(), in, out, h->Nc, h->nvec, nr);
+  }
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }

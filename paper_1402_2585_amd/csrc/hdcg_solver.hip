@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -156,6 +157,14 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
 template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
               int maxiter, int* iters, hipStream_t st, int mprec = -1) {
+  if constexpr (sizeof(R) == 4) {
+    if (h->persistent_coarse) {
+      int done = 0;
+      HDCG_TRY(coarse_cg_persistent(h, mprec == DWF_BF16 || mprec == DWF_F16 ? mprec : DWF_C64, x, b, nr, tol,
+                                    maxiter, iters, &done, st));
+      if (done) return DWF_OK;
+    }
+  }
   const size_t n = (size_t)h->Nc * h->nvec;
   for (int i = 0; i < 3; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
   cplx<R>* r = h->cw[0].as<cplx<R>>();
@@ -370,6 +379,8 @@ int hdcg_destroy(hdcg_t h) {
   h->mf_smax.release();
   h->mf_bf16.release();
   h->mf_f16.release();
+  h->pcg_part.release();
+  h->pcg_state.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return DWF_OK;
@@ -563,6 +574,10 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.build_batch = p->build_batch;
     h->prm.coarse_prec = p->coarse_prec;
     h->prm.verbose = p->verbose;
+  }
+  // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
+  if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
+  {
     if (h->prm.coarse_prec != DWF_C64 && h->prm.coarse_prec != DWF_BF16 && h->prm.coarse_prec != DWF_F16) {
       delete h;
       return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");

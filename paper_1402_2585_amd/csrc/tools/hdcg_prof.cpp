@@ -4,7 +4,7 @@
 // to calibrate the FETCH_SIZE / WRITE_SIZE counters.
 //
 //   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64> <reps> [nrhs]
-//   hdcg_prof copy <MiB> <reps>
+//   hdcg_prof copy|read <MiB> <reps> [grid]
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -36,20 +36,50 @@ __global__ void copy_kernel(const double4* __restrict__ x, double4* __restrict__
     y[i] = x[i];
 }
 
+// streaming read: one partial sum per thread (n / (grid * block) loads each)
+__global__ void read_kernel(const double4* __restrict__ x, double* __restrict__ y, size_t n) {
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double4 v = x[i];
+    s += v.x + v.y + v.z + v.w;
+  }
+  y[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 int main(int argc, char** argv) {
   if (argc < 2) return 2;
-  if (!std::strcmp(argv[1], "copy")) {
+  if (!std::strcmp(argv[1], "copy") || !std::strcmp(argv[1], "read")) {
+    // hdcg_prof copy|read <MiB> <reps> [grid]: plain copy (or streaming read) of MiB
+    const bool rd = !std::strcmp(argv[1], "read");
     const size_t mib = argc > 2 ? std::atol(argv[2]) : 1024;
     const int reps = argc > 3 ? std::atoi(argv[3]) : 3;
+    const int grid = argc > 4 ? std::atoi(argv[4]) : 4096;
     const size_t n = mib * 1024 * 1024 / sizeof(double4);
     double4 *x, *y;
+    double* part;
     CHECK(hipMalloc(&x, n * sizeof(double4)));
     CHECK(hipMalloc(&y, n * sizeof(double4)));
+    CHECK(hipMalloc(&part, (size_t)grid * 256 * sizeof(double)));
     CHECK(hipMemset(x, 0, n * sizeof(double4)));
-    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(copy_kernel, dim3(4096), dim3(256), 0, 0, x, y, n);
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r) {
+      if (rd)
+        hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, x, part, n);
+      else
+        hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, x, y, n);
+    }
+    CHECK(hipEventRecord(e1, 0));
     CHECK(hipGetLastError());
     CHECK(hipDeviceSynchronize());
-    std::printf("copy %zu MiB x %d (bytes per launch read %zu write %zu)\n", mib, reps, n * 32, n * 32);
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    const double bytes = (double)n * 32 * (rd ? 1 : 2);
+    std::printf("%s %zu MiB x %d grid %d (bytes per launch read %zu write %zu)  %.4f ms/launch  %.1f GB/s\n",
+                rd ? "read" : "copy", mib, reps, grid, n * 32, rd ? (size_t)0 : n * 32, ms / reps,
+                bytes / (ms / reps * 1e-3) / 1e9);
     return 0;
   }
   if (!std::strcmp(argv[1], "sweep")) {

@@ -152,6 +152,35 @@ def test_coarse_solve(two_level):
     assert np.linalg.norm(r) <= 0.041 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("persistent", [True, False])
+def test_coarse_solve_c64_persistent_and_stepwise(two_level, persistent, monkeypatch):
+    """complex64 coarse CG for 1, 3 and 9 right-hand sides, as one persistent
+    kernel (up to 8 right-hand sides) and as one launch per step; every
+    solution checked against the oracle's dense coarse operator."""
+    t = two_level
+    banner(f"coarse solve c64 persistent={persistent} {t['name']}")
+    if persistent:
+        h, own = t["h"], False
+    else:
+        monkeypatch.setenv("HDCG_COARSE_PERSISTENT", "0")
+        raw = synth.gaussian_half_field(t["dims"], t["Ls"], 301, nrhs=t["nvec"])
+        h, own = hd.HDCG(t["op"], t["block"], raw), True
+    D = ocrs.to_dense(t["A"], t["C"])
+    for nr in (1, 3, 9):
+        g = synth.rng(340 + nr)
+        b = g.standard_normal((nr, h.Nc, h.nvec)) + 1j * g.standard_normal((nr, h.Nc, h.nvec))
+        x = h.new_coarse(hd.DWF_C64, nr)
+        rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to("cuda", torch.complex64), hd.DWF_C64, nr,
+                                      1e-4, 5000)
+        assert rc == 0 and it > 0
+        xs = x.cpu().numpy().astype(complex).reshape(nr, -1)
+        for r in range(nr):
+            res = b[r].ravel() - D @ xs[r]
+            assert np.linalg.norm(res) <= 3e-4 * np.linalg.norm(b[r]), (nr, r, np.linalg.norm(res) / np.linalg.norm(b[r]))
+    if own:
+        h.close()
+
+
 def test_mirs(two_level):
     t = two_level
     banner(f"M_IRS {t['name']}")
