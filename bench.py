@@ -104,9 +104,10 @@ def cpu_baseline(dims, Ls, eps, mass, n_apps=3):
 
 def hdcg_vs_cg(hd, torch, tol=1e-8):
     """The metric's second half on the 16^3x32 x Ls16, m=0.003 workload: plain
-    FP64 CG and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps, complex64
-    coarse operator and inner solver, FP64 defect correction) from the same
-    seeded source, each to a 1e-8 FP64 true residual, on this GPU."""
+    FP64 CG and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps each to
+    1e-3, complex64 coarse operator and inner solver, FP64 defect correction)
+    from the same seeded source, each to a 1e-8 FP64 true residual, on this
+    GPU."""
     import numpy as np
 
     import synth
@@ -125,7 +126,7 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     V = np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k)) for k in range(w.nvec)])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = hd.HDCG(op, w.block, V, n_ii=3, tol_ii=1e-4, maxiter_ii=500)
+    h = hd.HDCG(op, w.block, V, n_ii=3, tol_ii=1e-3, maxiter_ii=500)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     x2 = op.new_field(zero=True)
@@ -142,7 +143,8 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     h.close()
     op.close()
     return {
-        "workload": "16^3x32 x Ls16, M5=1.8, m=0.003, eps=0.7, Nvec=24, 4^4 blocks (coarse 4^3x8)",
+        "workload": "16^3x32 x Ls16, M5=1.8, m=0.003, eps=0.7, Nvec=24, 4^4 blocks (coarse 4^3x8), "
+                    "inverse iteration 3 steps to 1e-3",
         "cg_fp64": {"seconds": round(t_cg, 4), "iterations": st_cg["iterations"], "matmuls": st_cg["matmuls"],
                     "true_residual": st_cg["true_residual"], "status": rc_cg},
         "hdcg": {"seconds": round(t_h, 4), "setup_seconds": round(t_setup, 3),

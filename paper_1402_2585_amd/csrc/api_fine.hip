@@ -265,6 +265,7 @@ int dwf_destroy(dwf_op_t op) {
     for (auto& b : a) b.release();
   for (auto& b : op->cgw) b.release();
   op->red.partials.release();
+  op->hop_part.release();
   op->red.counters.release();
   op->red.results.release();
   if (op->pinned) (void)hipHostFree(op->pinned);

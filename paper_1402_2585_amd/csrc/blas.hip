@@ -46,9 +46,9 @@ __device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, do
 
 template <int NQ>
 __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nslots,
-                                                  int nblocks, double* __restrict__ res) {
+                                                  int nblocks, size_t rstride, double* __restrict__ res) {
   const int rhs = blockIdx.x;
-  const double* p = partials + (size_t)rhs * kMaxPartials;
+  const double* p = partials + (size_t)rhs * rstride;
   __shared__ double lds[16];
   for (int q = 0; q < NQ; ++q) {
     double s = 0.0;
@@ -185,12 +185,12 @@ __global__ void k_zero(cplx<R>* __restrict__ y, size_t total) {
 #define LAUNCH_CHECK() HDCG_HIP(hipGetLastError())
 
 int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int nrhs, double* res,
-                    hipStream_t st) {
-  if (nblocks > kMaxPartials / nq) return fail(DWF_ERR_ARG, "too many partial sums");
+                    hipStream_t st, size_t rstride) {
+  if (nblocks > nslots || (size_t)nq * nslots > rstride) return fail(DWF_ERR_ARG, "too many partial sums");
   if (nq == 1)
-    hipLaunchKernelGGL((k_finalize<1>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, res);
+    hipLaunchKernelGGL((k_finalize<1>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, rstride, res);
   else
-    hipLaunchKernelGGL((k_finalize<2>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, res);
+    hipLaunchKernelGGL((k_finalize<2>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, rstride, res);
   LAUNCH_CHECK();
   return DWF_OK;
 }

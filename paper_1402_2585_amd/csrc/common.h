@@ -198,9 +198,9 @@ __device__ __forceinline__ void store_partial(const double (&v)[NQ], double* par
   }
 }
 
-// res[nq * rhs + q] = sum_{i < nblocks} partials[rhs * kMaxPartials + q * nslots + i]
+// res[nq * rhs + q] = sum_{i < nblocks} partials[rhs * rstride + q * nslots + i]
 int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int nrhs, double* res,
-                    hipStream_t st);
+                    hipStream_t st, size_t rstride = kMaxPartials);
 
 // Map blockIdx.x so that each of the 8 XCDs (workgroups are dispatched to
 // XCDs round-robin) receives one contiguous range of tiles: neighbouring

@@ -44,6 +44,7 @@ struct dwf_op {
   hdk::DevBuf tmp[2][3];          // [prec][t_e, chi, s_e] work fields
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
   hdk::Reducer red;
+  hdk::DevBuf hop_part;           // fused-norm partials of the hop stage: [rhs][workgroups]
   struct {
     // hop launch shape (measured best on MI355X at 16^4 and 24^3x48, Ls = 16)
     int block[4] = {2, 2, 1, 1};  // workgroup site block in (x/2, y, z, t), powers of two; 0 = linear

@@ -232,7 +232,8 @@ struct HopArgs {
   int nbt;            // block-grid extent in t
   size_t field;       // complex elements per rhs
   double d, mass;     // fifth dimension
-  double* partials;   // EPI_SUB norm: [rhs][kMaxPartials] (nullable)
+  double* partials;   // EPI_SUB norm: [rhs][pstride] per-workgroup partials (nullable)
+  size_t pstride;     // = number of workgroups
   unsigned* counters; // [rhs]
   double* result;     // [rhs]
 };
@@ -369,7 +370,7 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
       double vv[1] = {nrm};
       __shared__ double red[16];
       block_sum<1>(vv, red);
-      store_partial<1>(vv, A.partials + (size_t)rhs * kMaxPartials, 0, wg);
+      store_partial<1>(vv, A.partials + (size_t)rhs * A.pstride, 0, wg);
     }
   }
 }
@@ -681,9 +682,11 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   A.result = nullptr;
   const int threads = ((A.spw * g.Ls + 63) / 64) * 64;
   const int nwg = (g.Vh + A.spw - 1) / A.spw;
+  A.pstride = (size_t)nwg;
   if (norm_result) {
-    if (nwg > kMaxPartials || nrhs > 64) return fail(DWF_ERR_ARG, "lattice too large for fused norm");
-    A.partials = op->red.partials.as<double>();
+    if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+    HDCG_TRY(op->hop_part.ensure(sizeof(double) * (size_t)nwg * nrhs));
+    A.partials = op->hop_part.as<double>();
     A.counters = op->red.counters.as<unsigned>();
     A.result = norm_result;
   }
@@ -710,7 +713,7 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
       launch_hop<R, 2, 0>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   }
   HDCG_HIP(hipGetLastError());
-  if (norm_result) return launch_finalize(1, A.partials, 0, nwg, nrhs, norm_result, stream);
+  if (norm_result) return launch_finalize(1, A.partials, nwg, nwg, nrhs, norm_result, stream, A.pstride);
   return DWF_OK;
 }
 

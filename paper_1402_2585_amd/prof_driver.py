@@ -2,11 +2,14 @@
 
   python3 -m paper_1402_2585_amd.prof_driver --what H --prec c128 --reps 5
   python3 -m paper_1402_2585_amd.prof_driver --what copy --mib 1024 --reps 5
+  python3 -m paper_1402_2585_amd.prof_driver --what hdcg --workload 3 --coarse c64
 
 `H` applies M_pc^+ M_pc to a seeded source on the 16^4 x Ls16 workload (or
 --dims/--Ls); `copy` runs a plain device-to-device copy kernel of known size,
 which calibrates the FETCH_SIZE / WRITE_SIZE counters (bytes reported per
-byte actually moved).
+byte actually moved); `hdcg` sets up HDCG on a numbered synthetic workload
+(inverse iteration with the given steps / tolerance / cap) and runs one
+solve to a 1e-8 FP64 true residual, printing the solver statistics.
 """
 from __future__ import annotations
 
@@ -20,7 +23,12 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["H", "copy"], default="H")
+    ap.add_argument("--what", choices=["H", "copy", "hdcg"], default="H")
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
+    ap.add_argument("--n_ii", type=int, default=3)
+    ap.add_argument("--tol_ii", type=float, default=1e-3)
+    ap.add_argument("--maxiter_ii", type=int, default=500)
     ap.add_argument("--prec", choices=["c128", "c64"], default="c128")
     ap.add_argument("--dims", type=int, nargs=4, default=[16, 16, 16, 16])
     ap.add_argument("--Ls", type=int, default=16)
@@ -42,6 +50,10 @@ def main():
         return
 
     import synth
+
+    if a.what == "hdcg":
+        run_hdcg(a, torch, synth)
+        return
 
     dims = tuple(a.dims)
     dt = torch.complex128 if a.prec == "c128" else torch.complex64
@@ -66,6 +78,35 @@ def main():
     hd.dwf_norm2(h, x, prec, a.nrhs)  # synchronises the stream
     hd.dwf_destroy(h)
     print(f"H {a.prec} dims={dims} Ls={a.Ls} nrhs={a.nrhs} x {2 * a.reps}", flush=True)
+
+
+def run_hdcg(a, torch, synth):
+    import numpy as np
+
+    from synth.configs import WORKLOADS
+
+    w = WORKLOADS[a.workload]
+    # every torch operation on the inputs happens before the library's first launch
+    U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
+    V = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k))
+                                   for k in range(w.nvec)])).to("cuda")
+    bsrc = torch.from_numpy(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(0))).to("cuda")
+    torch.cuda.synchronize()
+    print("inputs on device", flush=True)
+
+    import paper_1402_2585_amd as hd
+
+    cprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16, "f16": hd.DWF_F16}[a.coarse]
+    op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
+    b = op.to_native(bsrc)
+    h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
+                verbose=1)
+    print("setup done", flush=True)
+    x = op.new_field(zero=True)
+    rc, st = hd.hdcg_solve(h.h, x, b, 1, 1e-8)
+    print(f"hdcg workload {a.workload} coarse {a.coarse}: status {rc} {st}", flush=True)
+    h.close()
+    op.close()
 
 
 if __name__ == "__main__":

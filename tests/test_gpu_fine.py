@@ -177,6 +177,24 @@ def test_cg_solve_config1_against_oracle():
     op.close()
 
 
+def test_cg_solve_more_hop_workgroups_than_reduction_slots():
+    """24^3 x 48 gives 82944 hop workgroups (4 sites each), more than the
+    65536 slots of the BLAS reductions: the fused |M_pc p|^2 of the CG must
+    still be summed over all of them."""
+    banner("cg_solve fp64 24^3x48 x Ls2 (fused norm over 82944 workgroups)")
+    dims, Ls, M5, mass = (24, 24, 24, 48), 2, 1.8, 0.2
+    U = synth.gauge_field(dims, 0.5, 1201)
+    b = synth.gaussian_half_field(dims, Ls, 1202)
+    op = hd.FineOperator(U, dims, Ls, M5, mass)
+    x = op.new_field(zero=True)
+    rc, st = hd.cg_solve(op.h, x, op.to_native(b), 1, 1e-8, 2000)
+    assert rc == 0 and st["converged"] == 1
+    xc = op.to_canonical(x).cpu().numpy()
+    op.close()
+    r = b - DWF(U, dims, Ls, M5, mass).H(xc)
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+
+
 def test_cg_solve_zero_source_and_maxiter():
     banner("cg_solve edge cases")
     dims, Ls = (4, 4, 4, 4), 4
