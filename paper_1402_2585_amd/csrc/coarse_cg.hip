@@ -175,7 +175,7 @@ __device__ __forceinline__ void sum_partials(double* part, int buf, int nr, int 
 // 2: fp16 MFMA (MT M tiles).
 constexpr int kMaxNvec = 64;
 template <int MODE, int MT>
-__global__ void __launch_bounds__(kCT) k_coarse_cg(PcgArgs A) {
+__global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_cg(PcgArgs A) {
   constexpr int kRedBytes = MODE == 0 ? kCT * (int)sizeof(c64) : 8 * MT * 64 * (int)sizeof(f32x4);
   __shared__ __align__(16) unsigned char red_raw[kRedBytes];
   __shared__ c64 s_in[kStencil * kMaxNvec];  // the site's operand at its neighbours
@@ -254,9 +254,9 @@ __global__ void __launch_bounds__(kCT) k_coarse_cg(PcgArgs A) {
         __syncthreads();
       }
       if constexpr (MODE == 0) {
-        capply_site<float, 1, 16, true>(A.AT, A.nbr, s_in, A.w, a, Nc, nvec, 1, 0, reinterpret_cast<c64*>(red_raw));
+        capply_site<float, 1, 12, true>(A.AT, A.nbr, s_in, A.w, a, Nc, nvec, 1, 0, reinterpret_cast<c64*>(red_raw));
       } else {
-        capply_site_mfma<MODE == 1, MT, 1, 8, 4, true>(A.F, A.rho, A.smax, A.nbr, s_in, A.w, a, Nc, nvec, 1,
+        capply_site_mfma<MODE == 1, MT, 1, 8, (MT >= 3 ? 3 : 4), true>(A.F, A.rho, A.smax, A.nbr, s_in, A.w, a, Nc, nvec, 1,
                                                        A.ksteps, reinterpret_cast<f32x4*>(red_raw));
       }
       for (int e = tid; e < ne; e += kCT) {
