@@ -60,7 +60,10 @@ def traffic_from_profiles(prec_tag):
     return None if v is None else v.get("bytes_per_launch")
 
 
-def time_H(op, hd, prec, steps, warmup, nrhs=1):
+def time_H(op, hd, prec, steps, warmup, nrhs=1, reps=1):
+    """Median over `reps` repetitions of `steps` ping-pong applications of H,
+    each timed with HIP events on torch's current stream (where the library
+    launches); returns ms per application."""
     import torch
 
     x = op.new_field(prec, nrhs)
@@ -71,16 +74,56 @@ def time_H(op, hd, prec, steps, warmup, nrhs=1):
         hd.mpc_dag_mpc_apply(op.h, y, x, prec, nrhs)
         hd.mpc_dag_mpc_apply(op.h, x, y, prec, nrhs)
     torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        a, b = x, y
+        for _ in range(steps):
+            hd.mpc_dag_mpc_apply(op.h, b, a, prec, nrhs)  # ping-pong
+            a, b = b, a
+        e1.record(s)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    return sorted(times)[len(times) // 2]
+
+
+def copy_bandwidth(torch, mib=2048, reps=10):
+    """Device-to-device copy of `mib` MiB (read + write bytes per second): the
+    measured second denominator of the roofline."""
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    a, b = x, y
-    for _ in range(steps):
-        hd.mpc_dag_mpc_apply(op.h, b, a, prec, nrhs)  # ping-pong
-        a, b = b, a
-    e1.record(s)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps  # ms per application
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def mall_busting(hd, torch, steps=10):
+    """H at 32^3 x 64 x Ls16, whose fields (1.6 GB per complex64 half-field)
+    do not fit the 256 MB Infinity Cache: GB/s in complex128 and complex64."""
+    import synth
+
+    dims, Ls = (32, 32, 32, 64), 16
+    U = synth.gauge_field(dims, 0.7, 2201)
+    op = hd.FineOperator(U, dims, Ls, 1.8, 0.01)
+    out = {"workload": "mpcdagmpc 32^3x64 x Ls16, 1 RHS"}
+    for name, prec, cb in (("c128", hd.DWF_C128, 16), ("c64", hd.DWF_C64, 8)):
+        ms = time_H(op, hd, prec, steps, 2, reps=3)
+        out[name] = {"gbs": round(algorithmic_bytes_H(dims, Ls, 1, cb) / (ms * 1e-3) / 1e9, 1),
+                     "ms_per_application": round(ms, 4)}
+    op.close()
+    return out
 
 
 def cpu_baseline(dims, Ls, eps, mass, n_apps=3):
@@ -104,7 +147,8 @@ def cpu_baseline(dims, Ls, eps, mass, n_apps=3):
 
 def hdcg_vs_cg(hd, torch, tol=1e-8):
     """The metric's second half on the 16^3x32 x Ls16, m=0.003 workload: plain
-    FP64 CG and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps each to
+    FP64 CG, mixed-precision CG (complex64 CG inside FP64 defect correction)
+    and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps each to
     1e-3, complex64 coarse operator and inner solver, FP64 defect correction)
     from the same seeded source, each to a 1e-8 FP64 true residual, on this
     GPU."""
@@ -123,6 +167,13 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     rc_cg, st_cg = hd.cg_solve(op.h, x, b, 1, tol, 50000)
     torch.cuda.synchronize()
     t_cg = time.perf_counter() - t0
+    xm = op.new_field(zero=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc_m, st_m = hd.cg_solve_mixed(op.h, xm, b, 1, tol, 1e-5, 50000)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    del xm
     V = np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k)) for k in range(w.nvec)])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,11 +198,15 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
                     "inverse iteration 3 steps to 1e-3",
         "cg_fp64": {"seconds": round(t_cg, 4), "iterations": st_cg["iterations"], "matmuls": st_cg["matmuls"],
                     "true_residual": st_cg["true_residual"], "status": rc_cg},
+        "cg_mixed": {"seconds": round(t_mixed, 4), "iterations_c64": st_m["iterations"],
+                     "corrections_fp64": st_m["restarts"], "matmuls": st_m["matmuls"],
+                     "true_residual": st_m["true_residual"], "status": rc_m},
         "hdcg": {"seconds": round(t_h, 4), "setup_seconds": round(t_setup, 3),
                  "outer": st_h["outer_iterations"], "inner": st_h["inner_iterations"],
                  "coarse_iterations": st_h["coarse_iterations"], "matmuls_fp64": st_h["matmuls_fp64"],
                  "matmuls_fp32": st_h["matmuls_fp32"], "true_residual": rel, "status": rc_h},
         "speedup_solve": round(t_cg / t_h, 3),
+        "speedup_solve_vs_mixed_cg": round(t_mixed / t_h, 3),
         "break_even_rhs": (round(t_setup / (t_cg - t_h), 1) if t_cg > t_h else None),
     }
 
@@ -163,6 +218,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-hdcg", action="store_true", help="skip HDCG vs CG at 16^3x32xLs16")
+    ap.add_argument("--no-extra", action="store_true", help="skip the copy bandwidth and the 32^3x64 H")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -187,6 +243,9 @@ def main():
     ms128 = time_H(op, hd, hd.DWF_C128, args.steps, args.warmup)
     wall = time.perf_counter() - t0
     ms64 = time_H(op, hd, hd.DWF_C64, args.steps, args.warmup)
+    # outside the timed region: the median of 5 further repetitions
+    med128 = time_H(op, hd, hd.DWF_C128, args.steps, 0, reps=5)
+    med64 = time_H(op, hd, hd.DWF_C64, args.steps, 0, reps=5)
     gbs128 = by128 / (ms128 * 1e-3) / 1e9
     gbs64 = by64 / (ms64 * 1e-3) / 1e9
 
@@ -220,7 +279,15 @@ def main():
             "avg_launch_ms": round(ms128 / 4, 5),
         },
         "timed_wall_s": round(wall, 3),
+        "median_of_5": {"c128_ms_per_application": round(med128, 5), "c64_ms_per_application": round(med64, 5),
+                        "c128_gbs": round(by128 / (med128 * 1e-3) / 1e9, 1),
+                        "c64_gbs": round(by64 / (med64 * 1e-3) / 1e9, 1)},
     }
+    if not args.no_extra:
+        cb = copy_bandwidth(torch)
+        out["roofline"]["copy_gbs_measured"] = round(cb, 1)
+        out["roofline"]["frac_of_copy"] = round(gbs128 / cb, 4)
+        out["mall_busting"] = mall_busting(hd, torch)
     if not args.no_hdcg:
         out["hdcg_vs_cg"] = hdcg_vs_cg(hd, torch)
     if not args.no_cpu:

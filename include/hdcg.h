@@ -132,6 +132,18 @@ struct dwf_solve_stats {
 int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxiter,
              struct dwf_solve_stats* st, void* stream);
 
+/* Mixed-precision CG on H x = b (the "CGNE (mixed)" comparator of Table
+ * "wallclock", Sec. VI.B): FP64 defect correction -- r = b - H x in
+ * complex128, then a complex64 CG from zero on H e = r to the relative
+ * residual max(inner_tol, tol / (2 |r|/|b|)), then x += e in complex128 --
+ * until |b - H x|/|b| <= tol.  x: native c128, in = initial guess, out =
+ * solution; b: native c128.  st->iterations counts complex64 CG iterations,
+ * st->restarts the corrections, st->matmuls every H (both precisions).
+ * Synchronises; returns DWF_NOT_CONVERGED once maxiter complex64 iterations
+ * have run without reaching tol; DWF_ERR_ARG unless 0 < inner_tol < 1. */
+int cg_solve_mixed(dwf_op_t op, void* x, const void* b, int nrhs, double tol, double inner_tol, int maxiter,
+                   struct dwf_solve_stats* st, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Hierarchically deflated CG: blocked subspace (Sec. II), little Dirac
  * operator (Sec. V.A.1), the A-DEF2 solver (Sec. IV.E, Table "algos").     */

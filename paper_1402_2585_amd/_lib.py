@@ -83,6 +83,7 @@ def load():
         "dwf_cg_update": (i, [vp, vp, vp, vp, vp, dp, dp, i, i, vp]),
         "dwf_xpay": (i, [vp, vp, vp, dp, i, i, vp]),
         "cg_solve": (i, [vp, vp, vp, i, d, i, C.POINTER(SolveStats), vp]),
+        "cg_solve_mixed": (i, [vp, vp, vp, i, d, d, i, C.POINTER(SolveStats), vp]),
         "dwf_last_error": (C.c_char_p, []),
         "hdcg_default_params": (None, [C.POINTER(HdcgParams)]),
         "hdcg_setup": (i, [C.POINTER(vp), vp, C.POINTER(C.c_int * 4), i, vp, C.POINTER(HdcgParams), vp]),
@@ -205,6 +206,13 @@ def cg_solve(op, x, b, nrhs=1, tol=1e-8, maxiter=100000, stream=None):
     st = SolveStats()
     rc = _check(load().cg_solve(op, _ptr(x), _ptr(b), int(nrhs), float(tol), int(maxiter), C.byref(st),
                                 _stream(stream)), allow_soft=True)
+    return rc, st.as_dict()
+
+
+def cg_solve_mixed(op, x, b, nrhs=1, tol=1e-8, inner_tol=1e-5, maxiter=100000, stream=None):
+    st = SolveStats()
+    rc = _check(load().cg_solve_mixed(op, _ptr(x), _ptr(b), int(nrhs), float(tol), float(inner_tol), int(maxiter),
+                                      C.byref(st), _stream(stream)), allow_soft=True)
     return rc, st.as_dict()
 
 

@@ -1,6 +1,7 @@
 """Build libhdcg.so in-tree for gfx950 with hipcc.
 
-Usage: python -m paper_1402_2585_amd.build   (or build() from Python)
+Usage: python paper_1402_2585_amd/build.py   (or build() from Python; run by path,
+since importing the package loads the library built before)
 
 Every HIP source under csrc/ is compiled in parallel to an object file, then
 linked into paper_1402_2585_amd/libhdcg.so.  Packed-FP32 instruction

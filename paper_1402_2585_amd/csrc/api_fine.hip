@@ -1,4 +1,5 @@
 // C ABI: fine operator, BLAS-1 and the plain FP64 CG comparator.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -163,6 +164,131 @@ static int cg_one(dwf_op* op, c128* x, const c128* b, double tol, int maxiter, i
 #undef CG_HIP
 }
 
+// ------------------------------------------------ mixed-precision CG ---
+// complex64 CG from e = 0 on H e = f until the recursive residual has
+// |r| <= rtol |f| (lag-2 host checks through the pinned ring, as cg_one) or
+// maxiter iterations have run.
+static int cg_inner64(dwf_op* op, c64* e, const c64* f, double rtol, int maxiter, int* iters,
+                      hipStream_t stream) {
+  constexpr int kLag = 2, kRing = 8;
+  const size_t n = op->field_elems(1);
+  for (int i = 0; i < 3; ++i) HDCG_TRY(op->mgw[i].ensure(n * sizeof(c64)));
+  c64* r = op->mgw[0].as<c64>();
+  c64* p = op->mgw[1].as<c64>();
+  c64* w = op->mgw[2].as<c64>();
+  double* sc = op->red.results.as<double>() + 128;
+  double* rr_slot[2] = {sc + 8, sc + 9};
+  double* pap = sc + 10;
+  double* hp = op->pinned;
+  HDCG_HIP(hipMemsetAsync(e, 0, n * sizeof(c64), stream));
+  HDCG_HIP(hipMemcpyAsync(r, f, n * sizeof(c64), hipMemcpyDeviceToDevice, stream));
+  HDCG_HIP(hipMemcpyAsync(p, f, n * sizeof(c64), hipMemcpyDeviceToDevice, stream));
+  HDCG_TRY(launch_norm2<float>(op, r, 1, rr_slot[0], stream));
+  HDCG_HIP(hipMemcpyAsync(hp + kRing, rr_slot[0], sizeof(double), hipMemcpyDeviceToHost, stream));
+  HDCG_HIP(hipStreamSynchronize(stream));
+  const double ff = hp[kRing];
+  *iters = 0;
+  if (!(ff > 0.0)) return std::isfinite(ff) ? DWF_OK : fail(DWF_ERR_NUMERIC, "inner source not finite");
+  const double stop = rtol * rtol * ff;
+  hipEvent_t ev[kRing];
+  for (int i = 0; i < kRing; ++i) HDCG_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  int k = 0, checked = 0, rc = DWF_OK;
+  bool done = false;
+  while (!done && rc == DWF_OK) {
+    if (k < maxiter) {
+      double* cur = rr_slot[k & 1];
+      double* nxt = rr_slot[(k + 1) & 1];
+      rc = launch_mpcdagmpc<float>(op, w, p, 1, stream, pap);
+      if (rc == DWF_OK) rc = launch_cg_update<float>(op, e, r, p, w, cur, pap, nullptr, nxt, 1, stream);
+      if (rc == DWF_OK) rc = launch_xpay<float>(op, p, r, nxt, cur, nullptr, 1, stream);
+      if (rc == DWF_OK && hipMemcpyAsync(hp + (k % kRing), nxt, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        rc = fail(DWF_ERR_HIP, "copy of the residual norm failed");
+      if (rc == DWF_OK && hipEventRecord(ev[k % kRing], stream) != hipSuccess) rc = fail(DWF_ERR_HIP, "event record failed");
+      ++k;
+    }
+    const bool drain = k >= maxiter;
+    while (rc == DWF_OK && checked < k && (k - checked > kLag || drain)) {
+      if (hipEventSynchronize(ev[checked % kRing]) != hipSuccess) {
+        rc = fail(DWF_ERR_HIP, "event synchronisation failed");
+        break;
+      }
+      const double rrv = hp[checked % kRing];
+      ++checked;
+      if (!std::isfinite(rrv)) {
+        rc = fail(DWF_ERR_NUMERIC, "inner CG residual became non-finite");
+        break;
+      }
+      if (rrv <= stop) {
+        done = true;
+        break;
+      }
+    }
+    if (drain && checked == k) done = true;
+  }
+  if (rc == DWF_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(DWF_ERR_HIP, "stream synchronisation failed");
+  for (int i = 0; i < kRing; ++i) (void)hipEventDestroy(ev[i]);
+  *iters = k;
+  return rc;
+}
+
+// Mixed-precision CG: FP64 defect correction (true residual r = b - H x in
+// complex128) around the complex64 CG of cg_inner64, whose relative target
+// is max(inner_tol, tol / (2 rel)) for the current FP64 residual rel.
+static int cg_mixed_one(dwf_op* op, c128* x, const c128* b, double tol, double inner_tol, int maxiter,
+                        int* iters, int* restarts, double* true_res, double* matmuls, hipStream_t stream) {
+  const size_t n = op->field_elems(1);
+  HDCG_TRY(ensure_reducer(op));
+  for (int i = 0; i < 2; ++i) HDCG_TRY(op->cgw[i].ensure(n * sizeof(c128)));
+  HDCG_TRY(op->mgw[3].ensure(n * sizeof(c64)));
+  HDCG_TRY(op->mgw[4].ensure(n * sizeof(c64)));
+  c128* r = op->cgw[0].as<c128>();
+  c128* t = op->cgw[1].as<c128>();
+  c64* f = op->mgw[3].as<c64>();
+  c64* e = op->mgw[4].as<c64>();
+  double* sc = op->red.results.as<double>() + 128;
+  double* hp = op->pinned;
+  HDCG_TRY(launch_norm2<double>(op, b, 1, sc + 12, stream));
+  HDCG_HIP(hipMemcpyAsync(hp + 8, sc + 12, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HDCG_HIP(hipStreamSynchronize(stream));
+  const double bb = hp[8];
+  *iters = 0;
+  *restarts = 0;
+  *true_res = 0.0;
+  *matmuls = 0.0;
+  if (!std::isfinite(bb)) return fail(DWF_ERR_NUMERIC, "source norm is not finite");
+  if (bb == 0.0) {
+    HDCG_HIP(hipMemsetAsync(x, 0, n * sizeof(c128), stream));
+    HDCG_HIP(hipStreamSynchronize(stream));
+    return DWF_OK;
+  }
+  int it = 0;
+  for (;;) {
+    // r = b - H x in FP64
+    HDCG_TRY(launch_mpcdagmpc<double>(op, t, x, 1, stream, nullptr));
+    *matmuls += 1;
+    HDCG_HIP(hipMemcpyAsync(r, b, n * sizeof(c128), hipMemcpyDeviceToDevice, stream));
+    HDCG_TRY(launch_axpby<double>(op, r, t, -1.0, 1.0, n, stream));
+    HDCG_TRY(launch_norm2<double>(op, r, 1, sc + 12, stream));
+    HDCG_HIP(hipMemcpyAsync(hp + 8, sc + 12, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HDCG_HIP(hipStreamSynchronize(stream));
+    if (!std::isfinite(hp[8])) return fail(DWF_ERR_NUMERIC, "residual is not finite");
+    const double rel = std::sqrt(hp[8] / bb);
+    *true_res = rel;
+    if (rel <= tol || it >= maxiter) break;
+    // H e = r in complex64, then x += e in FP64
+    HDCG_TRY(launch_convert<float, double>(f, r, n, stream));
+    int k = 0;
+    HDCG_TRY(cg_inner64(op, e, f, std::max(inner_tol, 0.5 * tol / rel), maxiter - it, &k, stream));
+    it += k;
+    *matmuls += k;
+    ++*restarts;
+    HDCG_TRY(launch_convert<double, float>(t, e, n, stream));
+    HDCG_TRY(launch_axpby<double>(op, x, t, 1.0, 1.0, n, stream));
+  }
+  *iters = it;
+  return *true_res <= tol ? DWF_OK : DWF_NOT_CONVERGED;
+}
+
 }  // namespace hdk
 
 using namespace hdk;
@@ -266,6 +392,7 @@ int dwf_destroy(dwf_op_t op) {
   for (auto& b : op->cgw) b.release();
   op->red.partials.release();
   op->hop_part.release();
+  for (auto& m : op->mgw) m.release();
   op->red.counters.release();
   op->red.results.release();
   if (op->pinned) (void)hipHostFree(op->pinned);
@@ -438,6 +565,39 @@ int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxi
   acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (st) *st = acc;
   if (worst == DWF_NOT_CONVERGED) set_error("cg_solve: maxiter reached before tol");
+  return worst;
+}
+
+int cg_solve_mixed(dwf_op_t op, void* x, const void* b, int nrhs, double tol, double inner_tol, int maxiter,
+                   struct dwf_solve_stats* st, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!x || !b || !(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1) || maxiter < 0)
+    return fail(DWF_ERR_ARG, "bad arguments to cg_solve_mixed");
+  auto s = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  dwf_solve_stats acc{};
+  acc.converged = 1;
+  int worst = DWF_OK;
+  const size_t n = op->field_elems(1);
+  for (int i = 0; i < nrhs; ++i) {
+    int it = 0, rs = 0;
+    double tr = 0, mm = 0;
+    int rc = cg_mixed_one(op, static_cast<c128*>(x) + i * n, static_cast<const c128*>(b) + i * n, tol, inner_tol,
+                          maxiter, &it, &rs, &tr, &mm, s);
+    if (rc < 0) return rc;
+    if (rc == DWF_NOT_CONVERGED) {
+      worst = DWF_NOT_CONVERGED;
+      acc.converged = 0;
+    }
+    acc.iterations += it;
+    acc.restarts += rs;
+    acc.matmuls += mm;
+    if (tr > acc.true_residual) acc.true_residual = tr;
+  }
+  acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = acc;
+  if (worst == DWF_NOT_CONVERGED) set_error("cg_solve_mixed: maxiter reached before tol");
   return worst;
 }
 

@@ -43,6 +43,7 @@ struct dwf_op {
   hdk::DevBuf pw128, pw64;        // closed-form table on the device
   hdk::DevBuf tmp[2][3];          // [prec][t_e, chi, s_e] work fields
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
+  hdk::DevBuf mgw[5];             // mixed-precision CG work fields (c64): r, p, w, source, correction
   hdk::Reducer red;
   hdk::DevBuf hop_part;           // fused-norm partials of the hop stage: [rhs][workgroups]
   struct {

@@ -9,7 +9,10 @@
 which calibrates the FETCH_SIZE / WRITE_SIZE counters (bytes reported per
 byte actually moved); `hdcg` sets up HDCG on a numbered synthetic workload
 (inverse iteration with the given steps / tolerance / cap) and runs one
-solve to a 1e-8 FP64 true residual, printing the solver statistics.
+solve to a 1e-8 FP64 true residual, printing the solver statistics;
+`lanczos` estimates the extreme eigenvalues of H on a numbered workload (the
+conditioning that sets the plain-CG iteration count) from --steps Lanczos
+steps with full reorthogonalisation, H applied by the library in FP64.
 """
 from __future__ import annotations
 
@@ -23,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["H", "copy", "hdcg"], default="H")
+    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos"], default="H")
+    ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
     ap.add_argument("--n_ii", type=int, default=3)
@@ -53,6 +57,9 @@ def main():
 
     if a.what == "hdcg":
         run_hdcg(a, torch, synth)
+        return
+    if a.what == "lanczos":
+        run_lanczos(a, torch, synth)
         return
 
     dims = tuple(a.dims)
@@ -106,6 +113,44 @@ def run_hdcg(a, torch, synth):
     rc, st = hd.hdcg_solve(h.h, x, b, 1, 1e-8)
     print(f"hdcg workload {a.workload} coarse {a.coarse}: status {rc} {st}", flush=True)
     h.close()
+    op.close()
+
+
+def run_lanczos(a, torch, synth):
+    import numpy as np
+
+    from synth.configs import WORKLOADS
+
+    w = WORKLOADS[a.workload]
+    U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
+    b = torch.from_numpy(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(0))).to("cuda")
+    torch.cuda.synchronize()
+
+    import paper_1402_2585_amd as hd
+
+    op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
+    v = op.to_native(b)
+    v /= torch.linalg.vector_norm(v)
+    Q = [v.clone()]
+    alpha, beta = [], []
+    for j in range(a.steps):
+        wv = op.H(Q[-1])
+        al = torch.vdot(Q[-1], wv).real
+        wv -= al * Q[-1]
+        if j > 0:
+            wv -= beta[-1] * Q[-2]
+        for q in Q:  # full reorthogonalisation
+            wv -= torch.vdot(q, wv) * q
+        be = torch.linalg.vector_norm(wv)
+        alpha.append(float(al))
+        beta.append(float(be))
+        Q.append(wv / be)
+        if len(Q) > 2 and j % 20 == 19:
+            print(f"lanczos step {j + 1}", flush=True)
+    T = np.diag(alpha) + np.diag(beta[:-1], 1) + np.diag(beta[:-1], -1)
+    ev = np.linalg.eigvalsh(T)
+    print(f"lanczos workload {a.workload} {w.dims} Ls={w.Ls} m={w.mass}: steps {a.steps} "
+          f"lambda_min {ev[0]:.6e} lambda_max {ev[-1]:.6e} ratio {ev[-1] / ev[0]:.1f}", flush=True)
     op.close()
 
 

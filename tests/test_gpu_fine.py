@@ -177,6 +177,28 @@ def test_cg_solve_config1_against_oracle():
     op.close()
 
 
+@pytest.mark.parametrize("inner_tol", [1e-5, 1e-2])
+def test_cg_solve_mixed_against_oracle(inner_tol):
+    banner(f"cg_solve_mixed config 1 inner_tol={inner_tol}")
+    dims, Ls, M5, mass = (4, 4, 4, 4), 8, 1.8, 0.01
+    U = synth.gauge_field(dims, 0.5, 1001)
+    b = synth.gaussian_half_field(dims, Ls, 1100, nrhs=2)
+    op = hd.FineOperator(U, dims, Ls, M5, mass)
+    ref = DWF(U, dims, Ls, M5, mass)
+    x = op.new_field(nrhs=2, zero=True)
+    rc, st = hd.cg_solve_mixed(op.h, x, op.to_native(b), 2, 1e-10, inner_tol, 5000)
+    assert rc == 0 and st["converged"] == 1 and st["restarts"] >= 1
+    xc = op.to_canonical(x, nrhs=2).cpu().numpy()
+    for r in range(2):
+        res = b[r] - ref.H(xc[r])
+        assert np.sqrt(np.vdot(res, res).real / np.vdot(b[r], b[r]).real) <= 1e-10
+    # zero source
+    z = op.new_field(zero=True)
+    rc, st = hd.cg_solve_mixed(op.h, op.new_field(), z, 1, 1e-8)
+    assert rc == 0 and st["iterations"] == 0
+    op.close()
+
+
 def test_cg_solve_more_hop_workgroups_than_reduction_slots():
     """24^3 x 48 gives 82944 hop workgroups (4 sites each), more than the
     65536 slots of the BLAS reductions: the fused |M_pc p|^2 of the CG must
