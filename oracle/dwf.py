@@ -19,6 +19,19 @@ reverse hop).
 Deliberately plain: full 4x4 spin matrices (no spin projection), full-lattice
 arrays with np.roll for neighbours, dense Ls x Ls matrices for the fifth
 dimension, np.linalg.inv for M_5^-1.
+
+Mobius (Cayley-form) kernel, which the paper names (abstract, Sec. I) but
+does not write out; the reading follows the standard form of the cited
+literature, with b = 1, c = 0 giving Shamir:
+
+  (D psi)_s = (b D_W + 1) psi_s + (c D_W - 1) (P- psi_{s+1} + P+ psi_{s-1}),
+  D_W = (4 - M5) - Dh/2, and -m in place of 1 for the wall couplings.
+
+With K = P- S+ + P+ S- (the two chiral shifts, -m at the wrap) this is
+D = (alpha + beta K) - (1/2) Dh (b + c K), alpha = b (4 - M5) + 1,
+beta = c (4 - M5) - 1.  Hence M_ee = M_oo = M_5 := alpha + beta K,
+M_eo = -(1/2) Dh_eo C_5, M_oe = -(1/2) Dh_oe C_5 with C_5 := b + c K applied
+before the hop, and M_pc = M_5 - (1/4) Dh_oe C_5 M_5^-1 Dh_eo C_5.
 """
 from __future__ import annotations
 
@@ -97,6 +110,27 @@ def m5_matrices(Ls, M5, mass):
     return Mp, Mm
 
 
+def mobius_matrices(Ls, M5, mass, b, c):
+    """Dense Ls x Ls matrices (P+ half, P- half) of M_5 = alpha + beta K and
+    C_5 = b + c K for the Mobius kernel; K is S- (s-1) on P+ and S+ (s+1) on
+    P-, each with -m on its wrapped entry."""
+    Kp = np.zeros((Ls, Ls))
+    Km = np.zeros((Ls, Ls))
+    for s in range(Ls):
+        if s > 0:
+            Kp[s, s - 1] = 1.0
+        else:
+            Kp[0, Ls - 1] = -mass
+        if s < Ls - 1:
+            Km[s, s + 1] = 1.0
+        else:
+            Km[Ls - 1, 0] = -mass
+    alpha = b * (4.0 - M5) + 1.0
+    beta = c * (4.0 - M5) - 1.0
+    one = np.eye(Ls)
+    return (alpha * one + beta * Kp, alpha * one + beta * Km), (b * one + c * Kp, b * one + c * Km)
+
+
 def apply_5d(Mp, Mm, half):
     """Apply Mp (x) P+ + Mm (x) P- to a half-field (..., Ls, Vh, 4, 3)."""
     Pp, Pm = chiral_projectors()
@@ -110,16 +144,22 @@ def apply_5d(Mp, Mm, half):
 
 
 class DWF:
-    """Shamir domain-wall operator on the odd checkerboard."""
+    """Domain-wall operator on the odd checkerboard: Shamir, or Mobius when
+    (b, c) is given other than (1, 0)."""
 
-    def __init__(self, U, dims, Ls, M5, mass, bc=(1, 1, 1, -1)):
+    def __init__(self, U, dims, Ls, M5, mass, bc=(1, 1, 1, -1), b=1.0, c=0.0):
         self.U = np.asarray(U, dtype=np.complex128)
         self.dims = tuple(dims)
         self.Ls = int(Ls)
         self.M5 = float(M5)
         self.mass = float(mass)
         self.bc = tuple(complex(z) for z in bc)
-        self.Mp, self.Mm = m5_matrices(self.Ls, self.M5, self.mass)
+        self.b, self.c = float(b), float(c)
+        self.mobius = (self.b, self.c) != (1.0, 0.0)
+        if self.mobius:
+            (self.Mp, self.Mm), (self.Cp, self.Cm) = mobius_matrices(self.Ls, self.M5, self.mass, self.b, self.c)
+        else:
+            self.Mp, self.Mm = m5_matrices(self.Ls, self.M5, self.mass)
         self.Mpi = np.linalg.inv(self.Mp)
         self.Mmi = np.linalg.inv(self.Mm)
 
@@ -135,6 +175,12 @@ class DWF:
 
     def m5_inv_dag(self, h):
         return apply_5d(self.Mpi.T, self.Mmi.T, h)
+
+    def c5(self, h):
+        return apply_5d(self.Cp, self.Cm, h) if self.mobius else h
+
+    def c5_dag(self, h):
+        return apply_5d(self.Cp.T, self.Cm.T, h) if self.mobius else h
 
     # checkerboard hops -----------------------------------------------------
     def _tables(self, out_parity):
@@ -179,15 +225,16 @@ class DWF:
 
     # preconditioned operator ------------------------------------------------
     def mpc(self, h):
-        """M_pc = M_5 - (1/4) Dh_oe M_5^-1 Dh_eo on odd half-fields."""
-        t = self.m5_inv(self.dh_eo(h))
-        return self.m5(h) - 0.25 * self.dh_oe(t)
+        """M_pc = M_5 - (1/4) Dh_oe C_5 M_5^-1 Dh_eo C_5 on odd half-fields
+        (C_5 = 1 for Shamir)."""
+        t = self.m5_inv(self.dh_eo(self.c5(h)))
+        return self.m5(h) - 0.25 * self.dh_oe(self.c5(t))
 
     def mpc_dag(self, h):
-        """M_pc^dagger = M_5^+ - (1/4) (Dh_eo)^+ (M_5^-1)^+ (Dh_oe)^+, with
-        (Dh_oe)^+ = (Dh^+)_eo and (Dh_eo)^+ = (Dh^+)_oe."""
-        t = self.m5_inv_dag(self.dh_eo(h, dagger=True))
-        return self.m5_dag(h) - 0.25 * self.dh_oe(t, dagger=True)
+        """M_pc^dagger = M_5^+ - (1/4) C_5^+ (Dh_eo)^+ (M_5^-1)^+ C_5^+ (Dh_oe)^+,
+        with (Dh_oe)^+ = (Dh^+)_eo and (Dh_eo)^+ = (Dh^+)_oe."""
+        t = self.m5_inv_dag(self.c5_dag(self.dh_eo(h, dagger=True)))
+        return self.m5_dag(h) - 0.25 * self.c5_dag(self.dh_oe(t, dagger=True))
 
     def H(self, h):
         """The Hermitian red-black operator M_pc^dagger M_pc."""
