@@ -284,6 +284,14 @@ def main():
                         "c64_gbs": round(by64 / (med64 * 1e-3) / 1e9, 1)},
     }
     if not args.no_extra:
+        # the Mobius kernel (b5 = 1.5, c5 = 0.5) on the same workload
+        opm = hd.FineOperator(U, dims, Ls, 1.8, mass, b5=1.5, c5=0.5)
+        msm = time_H(opm, hd, hd.DWF_C128, args.steps, 2)
+        msm64 = time_H(opm, hd, hd.DWF_C64, args.steps, 2)
+        opm.close()
+        out["mobius"] = {"b5": 1.5, "c5": 0.5,
+                         "c128": {"gbs": round(by128 / (msm * 1e-3) / 1e9, 1), "ms_per_application": round(msm, 5)},
+                         "c64": {"gbs": round(by64 / (msm64 * 1e-3) / 1e9, 1), "ms_per_application": round(msm64, 5)}}
         cb = copy_bandwidth(torch)
         out["roofline"]["copy_gbs_measured"] = round(cb, 1)
         out["roofline"]["frac_of_copy"] = round(gbs128 / cb, 4)

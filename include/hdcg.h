@@ -80,6 +80,19 @@ typedef struct hdcg* hdcg_t;
  * Errors: DWF_ERR_GEOMETRY for odd or non-positive extents or Ls out of range. */
 int dwf_create(dwf_op_t* op, const int dims[4], int Ls, double M5, double mass,
                const void* gauge_c128, const double bc_phase[8], void* stream);
+
+/* The same with the Mobius (Cayley-form) kernel the paper treats alongside
+ * Shamir's (abstract, Sec. I; written out in the literature it cites):
+ *   (D psi)_s = (b5 D_W + 1) psi_s + (c5 D_W - 1)(P- psi_{s+1} + P+ psi_{s-1}),
+ *   D_W = (4 - M5) - Dh/2, -mass in place of 1 at the wall couplings,
+ * so that with K = P- S_+ + P+ S_- (the chiral shifts in s):
+ *   M_5 = alpha + beta K, alpha = b5 (4 - M5) + 1, beta = c5 (4 - M5) - 1;
+ *   C_5 = b5 + c5 K;  M_pc = M_5 - 1/4 Dh_oe C_5 M_5^-1 Dh_eo C_5;  H = M_pc^+ M_pc.
+ * b5 = 1, c5 = 0 is Shamir (dwf_create).  Every other entry point works on
+ * either kernel.  Errors as dwf_create, and DWF_ERR_ARG unless
+ * |beta| < |alpha| (the M_5^-1 recurrence). */
+int dwf_create_mobius(dwf_op_t* op, const int dims[4], int Ls, double M5, double mass, double b5, double c5,
+                      const void* gauge_c128, const double bc_phase[8], void* stream);
 int dwf_destroy(dwf_op_t op);
 
 /* Bytes of one native half-field buffer holding nrhs right-hand sides. */

@@ -71,6 +71,7 @@ def load():
     dp = C.POINTER(C.c_double)
     sig = {
         "dwf_create": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, vp, dp, vp]),
+        "dwf_create_mobius": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, d, d, vp, dp, vp]),
         "dwf_destroy": (i, [vp]),
         "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
         "dwf_import": (i, [vp, vp, vp, i, i, vp]),
@@ -144,6 +145,15 @@ def dwf_create(gauge, dims, Ls, M5, mass, bc=(1, 1, 1, -1), stream=None):
     ph = _dbl([v for z in bc for v in (complex(z).real, complex(z).imag)], 8)
     _check(load().dwf_create(C.byref(h), C.byref(d), int(Ls), float(M5), float(mass), _ptr(gauge), ph,
                              _stream(stream)))
+    return h
+
+
+def dwf_create_mobius(gauge, dims, Ls, M5, mass, b5, c5, bc=(1, 1, 1, -1), stream=None):
+    h = C.c_void_p()
+    d = (C.c_int * 4)(*[int(x) for x in dims])
+    ph = _dbl([v for z in bc for v in (complex(z).real, complex(z).imag)], 8)
+    _check(load().dwf_create_mobius(C.byref(h), C.byref(d), int(Ls), float(M5), float(mass), float(b5), float(c5),
+                                    _ptr(gauge), ph, _stream(stream)))
     return h
 
 

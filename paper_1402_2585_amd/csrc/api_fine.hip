@@ -299,13 +299,21 @@ const char* dwf_last_error(void) { return g_last_error.c_str(); }
 
 int dwf_create(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass,
                const void* gauge_c128, const double bc_phase[8], void* stream) {
+  return dwf_create_mobius(out, dims, Ls, M5, mass, 1.0, 0.0, gauge_c128, bc_phase, stream);
+}
+
+int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass, double b5, double c5,
+                      const void* gauge_c128, const double bc_phase[8], void* stream) {
   if (!out || !dims || !gauge_c128) return fail(DWF_ERR_ARG, "null argument to dwf_create");
   *out = nullptr;
   for (int mu = 0; mu < 4; ++mu)
     if (dims[mu] < 2 || (dims[mu] & 1)) return fail(DWF_ERR_GEOMETRY, "lattice extents must be even and >= 2");
   if (Ls < 1 || Ls > 64) return fail(DWF_ERR_GEOMETRY, "Ls must be in 1..64");
-  const double d = 5.0 - M5;
-  if (!(std::fabs(d) > 1.0)) return fail(DWF_ERR_ARG, "need |5 - M5| > 1 for the M_5^-1 recurrence");
+  // M_5 = alpha + beta K; the M_5^-1 recurrence needs |beta / alpha| < 1
+  // (Shamir: |5 - M5| > 1)
+  const double alpha = b5 * (4.0 - M5) + 1.0, beta = c5 * (4.0 - M5) - 1.0;
+  if (!std::isfinite(alpha) || !std::isfinite(beta) || !(std::fabs(beta) < std::fabs(alpha)))
+    return fail(DWF_ERR_ARG, "need |c5 (4 - M5) - 1| < |b5 (4 - M5) + 1| for the M_5^-1 recurrence");
   dwf_op* op = new (std::nothrow) dwf_op();
   if (!op) return fail(DWF_ERR_OOM, "host allocation failed");
   op->g.X = dims[0];
@@ -324,11 +332,18 @@ int dwf_create(dwf_op_t* out, const int dims[4], int Ls, double M5, double mass,
   op->mass = mass;
   const double defbc[8] = {1, 0, 1, 0, 1, 0, -1, 0};
   std::memcpy(op->bc, bc_phase ? bc_phase : defbc, sizeof(op->bc));
-  op->f5.d = d;
+  op->f5.alpha = alpha;
+  op->f5.beta = beta;
+  op->f5.ia = 1.0 / alpha;
+  op->f5.kap = -beta / alpha;
+  op->f5.b5 = b5;
+  op->f5.c5 = c5;
+  op->f5.mobius = !(b5 == 1.0 && c5 == 0.0);
   op->f5.mass = mass;
   // closed form of M_5^-1: (M+^-1)_{ss'} = pw[(s-s') mod Ls] * (s >= s' ? 1 : -m)
-  const double den = 1.0 + mass * std::pow(d, -Ls);
-  for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(d, -1 - n) / den : 0.0;
+  const double kap = op->f5.kap;
+  const double den = alpha * (1.0 + mass * std::pow(kap, Ls));
+  for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(kap, n) / den : 0.0;
   (void)hipGetDevice(&op->device);
   // hop launch shape: HDCG_HOP_TILE="bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]"
   // overrides the default (bx = 0: consecutive sites)

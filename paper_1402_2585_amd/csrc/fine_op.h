@@ -24,10 +24,18 @@ struct Geom {
   int Vh;          // sites per checkerboard
 };
 
+// Fifth dimension of the domain-wall kernel.  Mobius (Cayley form) with
+// C_5 = b5 + c5 K and M_5 = alpha + beta K, K the chiral shift (P+ from s-1,
+// P- from s+1, -mass at the wrap); Shamir is b5 = 1, c5 = 0 (alpha = 5 - M5,
+// beta = -1).  M_5^-1 on P+: pw[(s - s') mod Ls] (s >= s' ? 1 : -mass) with
+// pw[n] = kap^n / (alpha (1 + mass kap^Ls)), kap = -beta / alpha, and the
+// recurrence y_s = ia x_s + kap y_{s-1}, ia = 1 / alpha.
 struct FifthDim {
-  double d;       // 5 - M5
+  double alpha, beta, ia, kap;
+  double b5, c5;
+  bool mobius;
   double mass;
-  double pw[64];  // pw[n] = d^(-1-n) / (1 + m d^(-Ls)) (closed form of M_5^-1)
+  double pw[64];
 };
 
 struct dwf_op_impl;

@@ -231,7 +231,9 @@ struct HopArgs {
   int morton;         // Morton (bit-interleaved) order of the block grid (power-of-two grids)
   int nbt;            // block-grid extent in t
   size_t field;       // complex elements per rhs
-  double d, mass;     // fifth dimension
+  // fifth dimension: M_5 = alpha + beta K, recurrence of M_5^-1 y_s = ia x_s + kap y_{s-1},
+  // Mobius C_5 = b5 + c5 K (K: P+ from s-1, P- from s+1, -mass at the wrap)
+  double alpha, beta, ia, kap, b5, c5, mass;
   double* partials;   // EPI_SUB norm: [rhs][pstride] per-workgroup partials (nullable)
   size_t pstride;     // = number of workgroups
   unsigned* counters; // [rhs]
@@ -284,12 +286,27 @@ __device__ __forceinline__ int hop_site(const HopArgs& A, int wg, int vloc, Site
   return c.xh + g.Xh * c.rest;
 }
 
+// row <- (b + c S) row in place along s, S taking s+1 (up) or s-1 (down),
+// with -m times the wrapped entry at the wall.
+template <typename R>
+__device__ __forceinline__ void bcs_row(cplx<R>* row, int Ls, R b, R c, R m, bool up) {
+  if (up) {
+    const cplx<R> first = row[0];
+    for (int t = 0; t < Ls - 1; ++t) row[t] = b * row[t] + c * row[t + 1];
+    row[Ls - 1] = b * row[Ls - 1] + (-m * c) * first;
+  } else {
+    const cplx<R> last = row[Ls - 1];
+    for (int t = Ls - 1; t > 0; --t) row[t] = b * row[t] + c * row[t - 1];
+    row[0] = b * row[0] + (-m * c) * last;
+  }
+}
+
 // Fifth-dimension epilogue of a hop stage: acc holds (Dh in) or (Dh^+ in)
 // at (site v, slice s).  EPI_INV stages acc in LDS (`smem_raw`, spw*12*(Ls+1)
 // complex) and applies M_5^-1 (or M_5^-+); EPI_SUB forms M_5 c - acc/4 (or
 // M_5^+ c - acc/4) and, when A.partials is set, stores this workgroup's part
 // of its squared norm.  Every thread of the workgroup must call it.
-template <typename R, bool DAG, int EPI, int LS = 0>
+template <typename R, bool DAG, int EPI, int LS = 0, bool MOB = false>
 __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool active, int vloc, int s,
                                              int v, int wg, int rhs, cplx<R>* __restrict__ out,
                                              const cplx<R>* __restrict__ center,
@@ -307,12 +324,15 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
       for (int c = 0; c < 12; ++c) buf[(vloc * 12 + c) * ld + s] = acc[c];
     }
     __syncthreads();
-    const R invd = (R)(1.0 / A.d);
+    const R ia = (R)A.ia, kap = (R)A.kap;
     const R m = (R)A.mass;
     for (int q = tid; q < A.spw * 12; q += blockDim.x) {
       const int vl = q / 12, c = q - vl * 12;
       if (A.bx == 0 && wg * A.spw + vl >= g.Vh) continue;
       cplx<R>* row = buf + (vl * 12 + c) * ld;
+      // Mobius, adjoint chain: C_5^+ = b5 + c5 K^+ on the hop result first
+      // (K^+ takes P+ from s+1 and P- from s-1)
+      if (MOB && DAG) bcs_row(row, Ls, (R)A.b5, (R)A.c5, m, c < 6);
       // P+ (c < 6) takes M+^-1 (lower-triangular recurrence), P- takes M-^-1;
       // the adjoint swaps the two.
       const bool lower = ((c < 6) != DAG);
@@ -322,7 +342,7 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
         cplx<R> y = pw[0] * row[0] - m * tsum;
         row[0] = y;
         for (int sp = 1; sp < Ls; ++sp) {
-          y = invd * (row[sp] + y);
+          y = ia * row[sp] + kap * y;
           row[sp] = y;
         }
       } else {
@@ -331,10 +351,12 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
         cplx<R> y = pw[0] * row[Ls - 1] - m * tsum;
         row[Ls - 1] = y;
         for (int sp = Ls - 2; sp >= 0; --sp) {
-          y = invd * (row[sp] + y);
+          y = ia * row[sp] + kap * y;
           row[sp] = y;
         }
       }
+      // Mobius: C_5 = b5 + c5 K after M_5^-1 (K takes P+ from s-1, P- from s+1)
+      if (MOB && !DAG) bcs_row(row, Ls, (R)A.b5, (R)A.c5, m, c >= 6);
     }
     __syncthreads();
     if (active) {
@@ -344,24 +366,48 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
     }
   } else {
     // ---- M_5 c - 1/4 hop (or M_5^+ c - 1/4 hop^+) --------------------------
+    cplx<R> hop[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) hop[c] = acc[c];
+    if (MOB && DAG) {
+      // adjoint chain: C_5^+ = b5 + c5 K^+ on the hop result, through LDS
+      // (K^+ takes P+ from s+1 and P- from s-1, -mass at the wrap)
+      cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][12][Ls+1]
+      const int ld = Ls + 1;
+      if (active) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) buf[(vloc * 12 + c) * ld + s] = acc[c];
+      }
+      __syncthreads();
+      if (active) {
+        const R b5 = (R)A.b5, c5 = (R)A.c5, m = (R)A.mass;
+        const int s_up = (s < Ls - 1) ? s + 1 : 0, s_dn = (s > 0) ? s - 1 : Ls - 1;
+        const R w_up = (s < Ls - 1) ? c5 : -m * c5, w_dn = (s > 0) ? c5 : -m * c5;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const cplx<R>* row = buf + (vloc * 12 + c) * ld;
+          hop[c] = b5 * row[s] + (c < 6 ? w_up * row[s_up] : w_dn * row[s_dn]);
+        }
+      }
+    }
     double nrm = 0.0;
     if (active) {
       const cplx<R>* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
       cplx<R>* o = out + (size_t)v * 12 * Ls + s;
-      const R d = (R)A.d, m = (R)A.mass, q = (R)0.25;
-      // M_5: P+ couples to s-1 (mass term from Ls-1 at s = 0), P- to s+1
-      // (mass term from 0 at s = Ls-1); the adjoint swaps the directions.
+      const R al = (R)A.alpha, be = (R)A.beta, m = (R)A.mass, q = (R)0.25;
+      // M_5 = alpha + beta K: P+ couples to s-1 (-mass times Ls-1 at s = 0),
+      // P- to s+1 (-mass times 0 at s = Ls-1); the adjoint swaps the directions.
       const int s_dn = (s > 0) ? s - 1 : Ls - 1;
-      const R f_dn = (s > 0) ? (R)-1 : m;
+      const R f_dn = (s > 0) ? be : -m * be;
       const int s_up = (s < Ls - 1) ? s + 1 : 0;
-      const R f_up = (s < Ls - 1) ? (R)-1 : m;
+      const R f_up = (s < Ls - 1) ? be : -m * be;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const cplx<R>* cc = cen + c * Ls;
         const bool from_below = ((c < 6) != DAG);
         const int sn = from_below ? s_dn : s_up;
         const R fn = from_below ? f_dn : f_up;
-        const cplx<R> r = d * cc[s] + fn * cc[sn] - q * acc[c];
+        const cplx<R> r = al * cc[s] + fn * cc[sn] - q * hop[c];
         store_field(o + c * Ls, r, A.nt & 1);
         nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
       }
@@ -423,6 +469,27 @@ __device__ __forceinline__ void load_dirs(cplx<R> (&psi)[N][12], const cplx<R>* 
   }
 }
 
+// load_dirs for the Mobius first stage: each neighbour spinor is read as
+// C_5 psi = b5 psi_s + c5 (K psi)_s (K: P+ from s-1, P- from s+1, -mass at the
+// wrap), the s +- 1 entries read from the same contiguous column.
+template <typename R, int D0, int N>
+__device__ __forceinline__ void load_dirs_c5(cplx<R> (&psi)[N][12], const cplx<R>* __restrict__ in,
+                                             const int (&nb)[8], size_t col, int s, int Ls, R b5, R c5,
+                                             R m) {
+  const int s_dn = (s > 0) ? s - 1 : Ls - 1, s_up = (s < Ls - 1) ? s + 1 : 0;
+  const R w_dn = (s > 0) ? c5 : -m * c5, w_up = (s < Ls - 1) ? c5 : -m * c5;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const cplx<R>* p = in + (size_t)nb[D0 + k] * col;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const cplx<R> x = p[c * Ls + s];
+      const cplx<R> y = c < 6 ? p[c * Ls + s_dn] : p[c * Ls + s_up];
+      psi[k][c] = b5 * x + (c < 6 ? w_dn : w_up) * y;
+    }
+  }
+}
+
 template <typename R, int D0, int N, int SF>
 __device__ __forceinline__ void apply_dirs(cplx<R> (&acc)[12], const cplx<R> (&psi)[N][12],
                                            const cplx<R>* links) {
@@ -439,7 +506,7 @@ __device__ __forceinline__ void apply_dirs(cplx<R> (&acc)[12], const cplx<R> (&p
 // NPH = number of load phases (2: four directions in flight at a time; 4:
 // two).  LS > 0 fixes Ls at compile time.  Dynamic LDS:
 // max(spw * kLinkLd, spw * 12 * (Ls + 1)) complex.
-template <typename R, bool DAG, int EPI, int NPH, int LS>
+template <typename R, bool DAG, int EPI, int NPH, int LS, bool MOB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
 hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
                const cplx<R>* __restrict__ center, const cplx<R>* __restrict__ gauge,
@@ -469,9 +536,14 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
   const size_t col = (size_t)12 * Ls;
   int nb[8];
   cplx<R> psi[ND][12];
+  // Mobius: the first stage of M_pc hops C_5 in (C_5 on the neighbours' columns)
+  constexpr bool C5IN = MOB && !DAG && EPI == EPI_INV;
   if (active) {
     hop_neighbours(g, c, nb);
-    load_dirs<R, 0, ND>(psi, in, nb, col, s, Ls);
+    if (C5IN)
+      load_dirs_c5<R, 0, ND>(psi, in, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
+    else
+      load_dirs<R, 0, ND>(psi, in, nb, col, s, Ls);
   }
   __syncthreads();  // links in LDS
 
@@ -481,19 +553,29 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
   if (active) {
     const cplx<R>* L = links + vloc * kLinkLd;
     apply_dirs<R, 0, ND, SF>(acc, psi, L);
+    const R b5 = (R)A.b5, c5 = (R)A.c5, mm = (R)A.mass;
     if (NPH >= 2) {
-      load_dirs<R, ND % 8, ND>(psi, in, nb, col, s, Ls);
+      if (C5IN)
+        load_dirs_c5<R, ND % 8, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+      else
+        load_dirs<R, ND % 8, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, ND % 8, ND, SF>(acc, psi, L);
     }
     if (NPH == 4) {
-      load_dirs<R, 4, ND>(psi, in, nb, col, s, Ls);
+      if (C5IN)
+        load_dirs_c5<R, 4, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+      else
+        load_dirs<R, 4, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, 4, ND, SF>(acc, psi, L);
-      load_dirs<R, 6, ND>(psi, in, nb, col, s, Ls);
+      if (C5IN)
+        load_dirs_c5<R, 6, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+      else
+        load_dirs<R, 6, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, 6, ND, SF>(acc, psi, L);
     }
   }
-  if (EPI == EPI_INV) __syncthreads();  // the M_5^-1 buffer reuses the link rows
-  hop_epilogue<R, DAG, EPI, LS>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
+  if (EPI == EPI_INV || (MOB && DAG)) __syncthreads();  // the epilogue's LDS buffer reuses the link rows
+  hop_epilogue<R, DAG, EPI, LS, MOB>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
 }
 
 // ------------------------------------------------------------------ BLAS ---
@@ -619,20 +701,20 @@ int ensure_tmp(dwf_op* op, int prec, int nrhs) {
   return DWF_OK;
 }
 
-template <typename R, int NPH, int LS>
+template <typename R, int NPH, int LS, bool MOB>
 static void launch_hop(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
                        cplx<R>* out, const cplx<R>* in, const cplx<R>* center, const cplx<R>* G,
                        const R* pw, const HopArgs& A) {
   if (epi == EPI_INV) {
     if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
   } else {
     if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
   }
 }
 
@@ -675,8 +757,14 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
     }
   }
   A.field = (size_t)g.Vh * 12 * g.Ls;
-  A.d = op->f5.d;
+  A.alpha = op->f5.alpha;
+  A.beta = op->f5.beta;
+  A.ia = op->f5.ia;
+  A.kap = op->f5.kap;
+  A.b5 = op->f5.b5;
+  A.c5 = op->f5.c5;
   A.mass = op->f5.mass;
+  const bool mob = op->f5.mobius;
   A.partials = nullptr;
   A.counters = nullptr;
   A.result = nullptr;
@@ -695,22 +783,28 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
                      (size_t)out_parity * g.Vh * 72;
   const R* pw = reinterpret_cast<const R*>(dbl ? op->pw128.ptr : op->pw64.ptr);
   dim3 grid(nwg, nrhs), block(threads);
-  size_t lds = epi == EPI_INV ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  size_t lds = (epi == EPI_INV || (mob && dagger)) ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
   lds = std::max(lds, (size_t)A.spw * kLinkLd * sizeof(cplx<R>));
   // optional LDS request that caps the resident workgroups per CU
   if ((size_t)op->tune.lds_kb * 1024 > lds) lds = (size_t)op->tune.lds_kb * 1024;
   // directions whose neighbour loads are in flight together: 8 / phases
-  const bool two = op->tune.phases == 4;
-  if (g.Ls == 16) {
-    if (two)
-      launch_hop<R, 4, 16>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+  // (the Mobius kernels are built for four phases only)
+  const bool two = op->tune.phases == 4 || mob;
+  if (mob) {
+    if (g.Ls == 16)
+      launch_hop<R, 4, 16, true>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      launch_hop<R, 2, 16>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 0, true>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+  } else if (g.Ls == 16) {
+    if (two)
+      launch_hop<R, 4, 16, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+    else
+      launch_hop<R, 2, 16, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   } else {
     if (two)
-      launch_hop<R, 4, 0>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 0, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      launch_hop<R, 2, 0>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 2, 0, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   }
   HDCG_HIP(hipGetLastError());
   if (norm_result) return launch_finalize(1, A.partials, nwg, nwg, nrhs, norm_result, stream, A.pstride);

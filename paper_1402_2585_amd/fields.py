@@ -12,14 +12,19 @@ _DT = {L.DWF_C128: "complex128", L.DWF_C64: "complex64"}
 class FineOperator:
     """Owns one dwf_op handle; fields are torch tensors in the native layout."""
 
-    def __init__(self, gauge, dims, Ls, M5, mass, bc=(1, 1, 1, -1)):
+    def __init__(self, gauge, dims, Ls, M5, mass, bc=(1, 1, 1, -1), b5=1.0, c5=0.0):
+        """Shamir kernel, or Mobius when (b5, c5) is not (1, 0)."""
         import torch
 
         self.torch = torch
         g = gauge if isinstance(gauge, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(gauge))
         g = g.to(device="cuda", dtype=torch.complex128).contiguous()
         self.dims, self.Ls, self.M5, self.mass, self.bc = tuple(dims), int(Ls), float(M5), float(mass), bc
-        self.h = L.dwf_create(g, dims, Ls, M5, mass, bc)
+        self.b5, self.c5 = float(b5), float(c5)
+        if (self.b5, self.c5) == (1.0, 0.0):
+            self.h = L.dwf_create(g, dims, Ls, M5, mass, bc)
+        else:
+            self.h = L.dwf_create_mobius(g, dims, Ls, M5, mass, b5, c5, bc)
         torch.cuda.synchronize()
         X, Y, Z, T = dims
         self.Vh = X * Y * Z * T // 2

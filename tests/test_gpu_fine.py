@@ -277,3 +277,53 @@ def test_hop_launch_shapes_ls16(shape, monkeypatch):
     got64 = op.to_canonical(op.H(op.to_native(b, hd.DWF_C64), hd.DWF_C64), hd.DWF_C64).cpu().numpy()
     assert rel_err(got64, want) < 5e-6
     op.close()
+
+
+# Mobius (Cayley-form) kernel: (b5, c5) other than Shamir's (1, 0)
+MOBIUS = {
+    "4^4xLs8-b1.5-c0.5": ((4, 4, 4, 4), 8, 1.5, 0.5, 0.02, (1, 1, 1, -1)),
+    "8x4x6x4xLs5-b2-c1-phases": ((8, 4, 6, 4), 5, 2.0, 1.0, 0.1, (1, np.exp(0.3j), -1, np.exp(-0.7j))),
+    "8x8x4x8xLs16-b1.5-c0.5": ((8, 8, 4, 8), 16, 1.5, 0.5, 0.01, (1, 1, 1, -1)),
+    "4x4x4x6xLs1-b1.2-c0.3": ((4, 4, 4, 6), 1, 1.2, 0.3, 0.05, (1, 1, 1, -1)),
+}
+
+
+@pytest.mark.parametrize("name", list(MOBIUS))
+def test_mobius_mpc_and_H(name):
+    banner(f"mobius {name}")
+    dims, Ls, b5, c5, mass, bc = MOBIUS[name]
+    U = synth.gauge_field(dims, 0.6, 160)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass, bc, b5=b5, c5=c5)
+    ref = DWF(U, dims, Ls, 1.8, mass, bc, b=b5, c=c5)
+    b = synth.gaussian_half_field(dims, Ls, 161)
+    nb = op.to_native(b)
+    for dag in (0, 1):
+        got = op.to_canonical(op.mpc(nb, dagger=dag)).cpu().numpy()
+        want = ref.mpc_dag(b) if dag else ref.mpc(b)
+        assert rel_err(got, want) < 1e-12, (dag, rel_err(got, want))
+    want = ref.H(b)
+    assert rel_err(op.to_canonical(op.H(nb)).cpu().numpy(), want) < 1e-12
+    got64 = op.to_canonical(op.H(op.to_native(b, hd.DWF_C64), hd.DWF_C64), hd.DWF_C64).cpu().numpy()
+    assert rel_err(got64, want) < 5e-6
+    op.close()
+
+
+def test_mobius_cg_solve_against_oracle():
+    banner("mobius cg_solve 4^4 x Ls8")
+    dims, Ls, b5, c5, mass = (4, 4, 4, 4), 8, 1.5, 0.5, 0.02
+    U = synth.gauge_field(dims, 0.5, 162)
+    b = synth.gaussian_half_field(dims, Ls, 163)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass, b5=b5, c5=c5)
+    x = op.new_field(zero=True)
+    rc, st = hd.cg_solve(op.h, x, op.to_native(b), 1, 1e-9, 5000)
+    assert rc == 0
+    r = b - DWF(U, dims, Ls, 1.8, mass, b=b5, c=c5).H(op.to_canonical(x).cpu().numpy())
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-9
+    op.close()
+
+
+def test_mobius_rejects_unstable_fifth_dimension():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.5, 164)
+    with pytest.raises(hd.HdcgError):
+        hd.FineOperator(U, dims, 8, 1.8, 0.01, b5=0.1, c5=2.0)  # |beta| > |alpha|

@@ -229,6 +229,32 @@ def test_hdcg_solve_16bit_coarse(cprec):
     op.close()
 
 
+def test_hdcg_solve_mobius():
+    """The whole two-level path on the Mobius kernel: subspace, Fourier-trick
+    coarse operator (checked against the oracle's brute force), solve."""
+    dims, Ls, block, nvec, eps, mass = (12, 12, 12, 12), 2, (4, 4, 4, 4), 4, 0.5, 0.01
+    b5, c5 = 1.5, 0.5
+    banner("hdcg mobius 12^4 x Ls2")
+    U = synth.gauge_field(dims, eps, 300)
+    raw = synth.gaussian_half_field(dims, Ls, 301, nrhs=nvec)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass, b5=b5, c5=c5)
+    h = hd.HDCG(op, block, raw)
+    ref = DWF(U, dims, Ls, 1.8, mass, b=b5, c=c5)
+    _, _, sob = oblk.block_map(dims, block)
+    phi = oblk.orthonormalise(raw, sob)
+    C = oblk.coarse_dims(dims, block)
+    A = ocrs.build_brute(ref, phi, sob, C)
+    assert rel_err(h.coarse_matrix().cpu().numpy(), A) < 1e-12
+    b = synth.gaussian_half_field(dims, Ls, 356)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    assert rc == 0
+    r = b - ref.H(op.to_canonical(x).cpu().numpy())
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+    h.close()
+    op.close()
+
+
 def test_hdcg_inverse_iteration_and_multi_rhs():
     """Setup with two inverse-iteration steps, then two right-hand sides at once."""
     name = "12^4xLs2-b4-n4"
