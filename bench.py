@@ -21,15 +21,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
-def algorithmic_bytes_H(dims, Ls, nrhs, cbytes):
+def algorithmic_bytes_H(dims, Ls, nrhs, cbytes, gbytes=None):
     """Bytes one application of M_pc^+ M_pc must move: four hop stages, each
     reading its input half-field and writing its output (8 transfers), two
     centre re-reads (the M_5 terms of stages 2 and 4), one full gauge read per
-    stage (V sites x 4 links x 9 complex, shared by all right-hand sides)."""
+    stage (V sites x 4 links x 9 complex, shared by all right-hand sides).
+    cbytes / gbytes: bytes per complex of the fields / the links (16-bit
+    fields keep complex64 links)."""
     X, Y, Z, T = dims
     V = X * Y * Z * T
     half = V // 2 * Ls * 12
-    return (10 * half * nrhs + 4 * V * 36) * cbytes
+    return 10 * half * nrhs * cbytes + 4 * V * 36 * (cbytes if gbytes is None else gbytes)
 
 
 def flops_H(dims, Ls, nrhs):
@@ -186,11 +188,24 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     rc_h, st_h = hd.hdcg_solve(h.h, x2, b, 1, tol)
     torch.cuda.synchronize()
     t_h = time.perf_counter() - t0
-    # independent FP64 true residual of the HDCG solution on the GPU operator
-    r = op.H(x2)
     bb = hd.dwf_norm2(op.h, b, hd.DWF_C128)[0]
-    hd.dwf_xpay(op.h, r, b, [-1.0], hd.DWF_C128)  # r = b - H x
-    rel = float(np.sqrt(hd.dwf_norm2(op.h, r, hd.DWF_C128)[0] / bb))
+
+    def true_residual(xs):
+        # independent FP64 true residual of a solution on the GPU operator
+        r = op.H(xs)
+        hd.dwf_xpay(op.h, r, b, [-1.0], hd.DWF_C128)  # r = b - H x
+        return float(np.sqrt(hd.dwf_norm2(op.h, r, hd.DWF_C128)[0] / bb))
+
+    rel = true_residual(x2)
+    # the same solve with M_IRS on 16-bit fields (Sec. VI.E, Table "sloppy")
+    h.set_params(irs_prec=hd.DWF_BF16)
+    x3 = op.new_field(zero=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc_b, st_b = hd.hdcg_solve(h.h, x3, b, 1, tol)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    rel_b = true_residual(x3)
     h.close()
     op.close()
     return {
@@ -205,6 +220,12 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
                  "outer": st_h["outer_iterations"], "inner": st_h["inner_iterations"],
                  "coarse_iterations": st_h["coarse_iterations"], "matmuls_fp64": st_h["matmuls_fp64"],
                  "matmuls_fp32": st_h["matmuls_fp32"], "true_residual": rel, "status": rc_h},
+        "hdcg_bf16_mirs": {"seconds": round(t_b, 4), "outer": st_b["outer_iterations"],
+                           "inner": st_b["inner_iterations"], "coarse_iterations": st_b["coarse_iterations"],
+                           "true_residual": rel_b, "status": rc_b,
+                           "speedup_vs_c64_mirs": round(t_h / t_b, 3),
+                           "speedup_solve_vs_cg": round(t_cg / t_b, 3),
+                           "speedup_solve_vs_mixed_cg": round(t_mixed / t_b, 3)},
         "speedup_solve": round(t_cg / t_h, 3),
         "speedup_solve_vs_mixed_cg": round(t_mixed / t_h, 3),
         "break_even_rhs": (round(t_setup / (t_cg - t_h), 1) if t_cg > t_h else None),
@@ -289,6 +310,12 @@ def main():
         msm = time_H(opm, hd, hd.DWF_C128, args.steps, 2)
         msm64 = time_H(opm, hd, hd.DWF_C64, args.steps, 2)
         opm.close()
+        # 16-bit fields (the M_IRS storage of irs_prec = DWF_BF16), complex64 links
+        ms16 = time_H(op, hd, hd.DWF_BF16, args.steps, 2)
+        by16 = algorithmic_bytes_H(dims, Ls, 1, 4, 8)
+        out["bf16"] = {"gbs": round(by16 / (ms16 * 1e-3) / 1e9, 1), "ms_per_application": round(ms16, 5),
+                       "speedup_vs_c64": round(ms64 / ms16, 3),
+                       "frac_of_hbm_peak": round(by16 / (ms16 * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
         out["mobius"] = {"b5": 1.5, "c5": 0.5,
                          "c128": {"gbs": round(by128 / (msm * 1e-3) / 1e9, 1), "ms_per_application": round(msm, 5)},
                          "c64": {"gbs": round(by64 / (msm64 * 1e-3) / 1e9, 1), "ms_per_application": round(msm64, 5)}}

@@ -64,6 +64,11 @@ enum {
   DWF_ERR_NUMERIC = -6   /* NaN/Inf or breakdown detected in a solver */
 };
 
+/* Storage of complex values: complex128, complex64, or pairs of 16-bit
+ * floats (bfloat16 / IEEE half; re then im, 4 bytes) whose arithmetic runs in
+ * FP32.  Fine fields take DWF_BF16 where a call says so (the 16-bit
+ * inner-solver data of Sec. VI.E, Table "sloppy", here as storage on one GPU); the coarse
+ * matrix takes DWF_BF16 and DWF_F16. */
 enum dwf_prec { DWF_C128 = 0, DWF_C64 = 1, DWF_BF16 = 2, DWF_F16 = 3 };
 
 typedef struct dwf_op* dwf_op_t;
@@ -95,7 +100,8 @@ int dwf_create_mobius(dwf_op_t* op, const int dims[4], int Ls, double M5, double
                       const void* gauge_c128, const double bc_phase[8], void* stream);
 int dwf_destroy(dwf_op_t op);
 
-/* Bytes of one native half-field buffer holding nrhs right-hand sides. */
+/* Bytes of one native half-field buffer holding nrhs right-hand sides
+ * (prec DWF_C128, DWF_C64 or DWF_BF16). */
 int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes);
 
 /* Canonical <-> native half-field layout (asynchronous).  prec = DWF_C128 or
@@ -103,20 +109,25 @@ int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes);
 int dwf_import(dwf_op_t op, void* native, const void* canonical, int prec, int nrhs, void* stream);
 int dwf_export(dwf_op_t op, void* canonical, const void* native, int prec, int nrhs, void* stream);
 
-/* Convert native fields between DWF_C128 and DWF_C64 (round to nearest). */
+/* Convert native fields between DWF_C128 and DWF_C64, or between DWF_C64 and
+ * DWF_BF16 (round to nearest even; no other pair).  Asynchronous. */
 int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_prec, int nrhs,
                 void* stream);
 
 /* out = M_pc in (dagger = 0) or M_pc^+ in (dagger = 1); native fields,
- * asynchronous.  out and in must not alias. */
+ * asynchronous.  out and in must not alias.  prec DWF_BF16: 16-bit fields in
+ * and out and for the two intermediate half-fields, FP32 arithmetic (gauge
+ * links complex64), every stored value rounded to nearest even. */
 int mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int dagger, int nrhs, void* stream);
 
-/* out = M_pc^+ M_pc in = H in; native fields, asynchronous; out != in. */
+/* out = M_pc^+ M_pc in = H in; native fields, asynchronous; out != in;
+ * prec as mpc_apply (DWF_BF16 also stores M_pc in in 16 bits). */
 int mpc_dag_mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int nrhs, void* stream);
 
 /* BLAS-1 with FP64 accumulation over native fields (the linear combinations
  * of the CG of Fig. "pcg").  Results go to HOST arrays of nrhs entries
- * (dot: nrhs (re, im) pairs); these calls synchronise `stream`. */
+ * (dot: nrhs (re, im) pairs); these calls synchronise `stream`.  dwf_norm2
+ * also takes DWF_BF16 fields; the others DWF_C128 and DWF_C64. */
 int dwf_norm2(dwf_op_t op, double* out_host, const void* x, int prec, int nrhs, void* stream);
 int dwf_dot(dwf_op_t op, double* out_host, const void* a, const void* b, int prec, int nrhs,
             void* stream);
@@ -178,6 +189,9 @@ struct hdcg_params {
   int coarse_prec;    /* storage of A inside Q: DWF_C64 (VALU, default), DWF_BF16 or DWF_F16
                          (MFMA with FP32 accumulation, per-matrix scales; nvec % 4 == 0) */
   int verbose;        /* 1: hdcg_setup prints stage progress to stderr */
+  int irs_prec;       /* storage of the M_IRS fields: DWF_C64 (default) or DWF_BF16 (16-bit
+                         fields, FP32 arithmetic, FP64 norms; the one-GPU form of the
+                         16-bit M_IRS communication of Sec. VI.E, Table "sloppy") */
 };
 
 struct hdcg_stats {
@@ -239,9 +253,19 @@ int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* 
 int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
                       int* iters, void* stream);
 
-/* out = M_IRS in: exactly n_irs complex64 CG iterations on H + lambda_irs
- * from zero (Sec. IV.C); native complex64 fields; asynchronous. */
+/* out = M_IRS in: exactly n_irs CG iterations on H + lambda_irs from zero
+ * (Sec. IV.C) with the work fields stored as p->irs_prec selects (complex64,
+ * or bfloat16 pairs rounded to nearest even after every kernel); in and out
+ * are native complex64 fields; asynchronous. */
 int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream);
+
+/* Replace the solve-phase parameters of a built handle (n_irs, lambda_irs,
+ * coarse_tol, coarse_maxiter, flexible, inner_tol, inner_maxiter,
+ * outer_maxiter, coarse_prec, irs_prec); the setup-phase fields of *p are
+ * ignored.  Builds the 16-bit copy of A when coarse_prec asks for one not yet
+ * built.  Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle
+ * is then unchanged). */
+int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream);
 
 /* Copies for parity checks: the little Dirac operator in the canonical layout
  * A[a][l][j][k] (device, Nc*81*nvec*nvec complex128), the orthonormalised

@@ -68,14 +68,16 @@ def m_irs(op, r, niter, lam):
 
 
 def gpcg(tl, b, method="adef2", n_irs=7, lam_irs=1.0, tol=1e-8, maxiter=1000,
-         flexible=True, x=None, callback=None):
-    """Generalised PCG (Tang et al.) for the A-DEF2 and BNN rows.
+         flexible=True, x=None, callback=None, m_irs_fn=None):
+    """Generalised PCG (Tang et al.) for the A-DEF2 and BNN rows.  m_irs_fn
+    replaces m_irs (same arguments), e.g. by its 16-bit storage form.
 
     Returns (x, iterations, recursive relative residual)."""
     H = tl.op.H
+    mirs = m_irs if m_irs_fn is None else m_irs_fn
 
     def M_irs(r):
-        return m_irs(tl.op, r, n_irs, lam_irs)
+        return mirs(tl.op, r, n_irs, lam_irs)
 
     if method == "adef2":
         def M1(r):

@@ -43,7 +43,8 @@ class HdcgParams(C.Structure):
                 ("maxiter_ii", C.c_int), ("n_irs", C.c_int), ("lambda_irs", C.c_double),
                 ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("flexible", C.c_int),
                 ("inner_tol", C.c_double), ("inner_maxiter", C.c_int), ("outer_maxiter", C.c_int),
-                ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int)]
+                ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int),
+                ("irs_prec", C.c_int)]
 
 
 class HdcgStats(C.Structure):
@@ -95,6 +96,7 @@ def load():
         "coarse_apply": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_coarse_solve": (i, [vp, vp, vp, i, i, d, i, C.POINTER(C.c_int), vp]),
         "hdcg_mirs": (i, [vp, vp, vp, i, vp]),
+        "hdcg_set_params": (i, [vp, C.POINTER(HdcgParams), vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -281,6 +283,10 @@ def hdcg_coarse_solve(h, x, b, prec, nrhs=1, tol=1e-8, maxiter=10000, stream=Non
 
 def hdcg_mirs(h, out, inp, nrhs=1, stream=None):
     _check(load().hdcg_mirs(h, _ptr(out), _ptr(inp), int(nrhs), _stream(stream)))
+
+
+def hdcg_set_params(h, params, stream=None):
+    _check(load().hdcg_set_params(h, C.byref(params), _stream(stream)))
 
 
 def hdcg_export_coarse(h, out, stream=None):

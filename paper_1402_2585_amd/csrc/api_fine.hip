@@ -29,6 +29,12 @@ static int check_prec(int prec) {
     return fail(DWF_ERR_ARG, "precision must be DWF_C128 or DWF_C64 for fine fields");
   return DWF_OK;
 }
+// the calls that also take 16-bit (bfloat16 pair) fields
+static int check_prec16(int prec) {
+  if (prec != DWF_C128 && prec != DWF_C64 && prec != DWF_BF16)
+    return fail(DWF_ERR_ARG, "precision must be DWF_C128, DWF_C64 or DWF_BF16 for fine fields");
+  return DWF_OK;
+}
 static int check_nrhs(int nrhs) {
   if (nrhs < 1 || nrhs > 64) return fail(DWF_ERR_ARG, "nrhs must be in 1..64");
   return DWF_OK;
@@ -276,13 +282,13 @@ static int cg_mixed_one(dwf_op* op, c128* x, const c128* b, double tol, double i
     *true_res = rel;
     if (rel <= tol || it >= maxiter) break;
     // H e = r in complex64, then x += e in FP64
-    HDCG_TRY(launch_convert<float, double>(f, r, n, stream));
+    HDCG_TRY(launch_convert(f, r, n, stream));
     int k = 0;
     HDCG_TRY(cg_inner64(op, e, f, std::max(inner_tol, 0.5 * tol / rel), maxiter - it, &k, stream));
     it += k;
     *matmuls += k;
     ++*restarts;
-    HDCG_TRY(launch_convert<double, float>(t, e, n, stream));
+    HDCG_TRY(launch_convert(t, e, n, stream));
     HDCG_TRY(launch_axpby<double>(op, x, t, 1.0, 1.0, n, stream));
   }
   *iters = it;
@@ -417,7 +423,7 @@ int dwf_destroy(dwf_op_t op) {
 
 int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes) {
   HDCG_TRY(check_op(op));
-  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_prec16(prec));
   if (!bytes || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_field_bytes");
   *bytes = op->field_elems(nrhs) * cbytes(prec);
   return DWF_OK;
@@ -444,39 +450,49 @@ int dwf_export(dwf_op_t op, void* canonical, const void* native, int prec, int n
 int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_prec, int nrhs,
                 void* stream) {
   HDCG_TRY(check_op(op));
-  HDCG_TRY(check_prec(dst_prec));
-  HDCG_TRY(check_prec(src_prec));
+  HDCG_TRY(check_prec16(dst_prec));
+  HDCG_TRY(check_prec16(src_prec));
   if (!dst || !src || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_convert");
+  if ((dst_prec == DWF_BF16 && src_prec == DWF_C128) || (dst_prec == DWF_C128 && src_prec == DWF_BF16))
+    return fail(DWF_ERR_ARG, "DWF_BF16 fields convert to and from DWF_C64 only");
   auto st = static_cast<hipStream_t>(stream);
   const size_t n = op->field_elems(nrhs);
   if (dst_prec == src_prec) {
     HDCG_HIP(hipMemcpyAsync(dst, src, n * cbytes(src_prec), hipMemcpyDeviceToDevice, st));
     return DWF_OK;
   }
+  if (dst_prec == DWF_BF16) return launch_convert(static_cast<bf16c*>(dst), static_cast<const c64*>(src), n, st);
+  if (src_prec == DWF_BF16) return launch_convert(static_cast<c64*>(dst), static_cast<const bf16c*>(src), n, st);
   if (dst_prec == DWF_C64)
-    return launch_convert<float, double>(static_cast<c64*>(dst), static_cast<const c128*>(src), n, st);
-  return launch_convert<double, float>(static_cast<c128*>(dst), static_cast<const c64*>(src), n, st);
+    return launch_convert(static_cast<c64*>(dst), static_cast<const c128*>(src), n, st);
+  return launch_convert(static_cast<c128*>(dst), static_cast<const c64*>(src), n, st);
 }
 
 int mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int dagger, int nrhs, void* stream) {
   HDCG_TRY(check_op(op));
-  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_prec16(prec));
   HDCG_TRY(check_nrhs(nrhs));
   if (!out || !in || out == in) return fail(DWF_ERR_ARG, "mpc_apply needs distinct in/out buffers");
   auto st = static_cast<hipStream_t>(stream);
   if (prec == DWF_C128)
     return launch_mpc<double>(op, static_cast<c128*>(out), static_cast<const c128*>(in), dagger != 0, nrhs, st, nullptr);
+  if (prec == DWF_BF16)
+    return launch_mpc<float, bf16c>(op, static_cast<bf16c*>(out), static_cast<const bf16c*>(in), dagger != 0, nrhs,
+                                    st, nullptr);
   return launch_mpc<float>(op, static_cast<c64*>(out), static_cast<const c64*>(in), dagger != 0, nrhs, st, nullptr);
 }
 
 int mpc_dag_mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int nrhs, void* stream) {
   HDCG_TRY(check_op(op));
-  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_prec16(prec));
   HDCG_TRY(check_nrhs(nrhs));
   if (!out || !in || out == in) return fail(DWF_ERR_ARG, "mpc_dag_mpc_apply needs distinct in/out buffers");
   auto st = static_cast<hipStream_t>(stream);
   if (prec == DWF_C128)
     return launch_mpcdagmpc<double>(op, static_cast<c128*>(out), static_cast<const c128*>(in), nrhs, st, nullptr);
+  if (prec == DWF_BF16)
+    return launch_mpcdagmpc<float, bf16c>(op, static_cast<bf16c*>(out), static_cast<const bf16c*>(in), nrhs, st,
+                                          nullptr);
   return launch_mpcdagmpc<float>(op, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, st, nullptr);
 }
 
@@ -489,13 +505,15 @@ static int fetch(dwf_op* op, double* host, const double* dev, int n, hipStream_t
 
 int dwf_norm2(dwf_op_t op, double* out_host, const void* x, int prec, int nrhs, void* stream) {
   HDCG_TRY(check_op(op));
-  HDCG_TRY(check_prec(prec));
+  HDCG_TRY(check_prec16(prec));
   HDCG_TRY(check_nrhs(nrhs));
   if (!out_host || !x) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   double* res = op->red.results.as<double>();
   if (prec == DWF_C128)
     HDCG_TRY(launch_norm2<double>(op, static_cast<const c128*>(x), nrhs, res, st));
+  else if (prec == DWF_BF16)
+    HDCG_TRY((launch_norm2<float, bf16c>(op, static_cast<const bf16c*>(x), nrhs, res, st)));
   else
     HDCG_TRY(launch_norm2<float>(op, static_cast<const c64*>(x), nrhs, res, st));
   return fetch(op, out_host, res, nrhs, st);

@@ -49,4 +49,15 @@ int b_scale_copy(cplx<Ry>* y, const cplx<Rx>* x, const double* v, bool invsqrt, 
 template <typename R>
 int b_zero(cplx<R>* y, size_t total, hipStream_t st);
 
+// The real-coefficient forms of the above on fields stored in 16 bits
+// (bf16c): FP32 arithmetic on each loaded value, results rounded to nearest
+// even on store, FP64 accumulation of the norms.
+int b_norm2(Red red, const bf16c* x, size_t n, int nrhs, double* res, hipStream_t st);
+int b_update(Red red, bf16c* x, bf16c* r, const bf16c* p, const bf16c* w, size_t n, int nrhs,
+             const double* num, const double* den, const double* den2, double lam, double* rr,
+             hipStream_t st);
+int b_xpay(Red red, bf16c* p, const bf16c* y, size_t n, int nrhs, const double* num,
+           const double* den, double* pp, hipStream_t st);
+int b_zero(bf16c* y, size_t total, hipStream_t st);
+
 }  // namespace hdk

@@ -65,28 +65,63 @@ __global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ par
   }
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kT) k_norm2(const cplx<R>* __restrict__ x, size_t n, Red red,
+// Fields are stored as T (cplx<R>, or bf16c with FP32 arithmetic).  The
+// streaming kernels move Vec<T>::V consecutive values per lane and operand
+// with one load or store: one complex for cplx<R>, four bf16c (16 bytes) for
+// the 16-bit storage, so a lane keeps as many bytes in flight as in complex64
+// or wider.  n must be a multiple of V (the launchers check).
+template <typename T>
+struct Vec {
+  static constexpr int V = 1;
+  using R = typename St<T>::R;
+  __device__ __forceinline__ static void ld(const T* p, size_t g, cplx<R> (&o)[1]) { o[0] = St<T>::ld(p + g); }
+  __device__ __forceinline__ static void st(T* p, size_t g, const cplx<R> (&v)[1]) { St<T>::st(p + g, v[0]); }
+};
+struct alignas(16) bf16c4 {
+  bf16c v[4];
+};
+template <>
+struct Vec<bf16c> {
+  static constexpr int V = 4;
+  __device__ __forceinline__ static void ld(const bf16c* p, size_t g, cplx<float> (&o)[4]) {
+    const bf16c4 q = reinterpret_cast<const bf16c4*>(p)[g];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = St<bf16c>::ld(&q.v[k]);
+  }
+  __device__ __forceinline__ static void st(bf16c* p, size_t g, const cplx<float> (&v)[4]) {
+    bf16c4 q;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) St<bf16c>::st(&q.v[k], v[k]);
+    reinterpret_cast<bf16c4*>(p)[g] = q;
+  }
+};
+template <typename T>
+__global__ void __launch_bounds__(kT) k_norm2(const T* __restrict__ x, size_t n, Red red,
                                               double* res) {
+  using R = typename St<T>::R;
   const int rhs = blockIdx.y;
   x += rhs * n;
+  constexpr int V = Vec<T>::V;
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
-    acc += nrm(x[i]);
+  for (size_t g = (size_t)blockIdx.x * kT + threadIdx.x; g < n / V; g += (size_t)gridDim.x * kT) {
+    cplx<R> v[V];
+    Vec<T>::ld(x, g, v);
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc += nrm(v[k]);
+  }
   double v[1] = {acc};
   reduce_out<1>(v, red, rhs, res);
 }
 
-template <typename R>
-__global__ void __launch_bounds__(kT) k_dot(const cplx<R>* __restrict__ a,
-                                            const cplx<R>* __restrict__ b, size_t n, Red red,
-                                            double* res) {
+template <typename T>
+__global__ void __launch_bounds__(kT) k_dot(const T* __restrict__ a, const T* __restrict__ b,
+                                            size_t n, Red red, double* res) {
   const int rhs = blockIdx.y;
   a += rhs * n;
   b += rhs * n;
   double re = 0.0, im = 0.0;
   for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-    const cplx<R> x = a[i], y = b[i];
+    const auto x = St<T>::ld(a + i), y = St<T>::ld(b + i);
     re += (double)x.re * y.re + (double)x.im * y.im;
     im += (double)x.re * y.im - (double)x.im * y.re;
   }
@@ -94,26 +129,39 @@ __global__ void __launch_bounds__(kT) k_dot(const cplx<R>* __restrict__ a,
   reduce_out<2>(v, red, rhs, res);
 }
 
-template <typename R>
+template <typename T>
 __global__ void __launch_bounds__(kT)
-k_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
-         const cplx<R>* __restrict__ w, size_t n, const double* num, bool cnum, const double* den,
-         const double* den2, double lam, Red red, double* rr, int dstr) {
+k_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ w,
+         size_t n, const double* num, bool cnum, const double* den, const double* den2, double lam,
+         Red red, double* rr, int dstr) {
+  using R = typename St<T>::R;
   const int rhs = blockIdx.y;
   const size_t off = rhs * n;
   double are, aim;
   coef(num, cnum, den, den2, lam, rhs, are, aim, dstr);
   const cplx<R> a = cmk((R)are, (R)aim);
   const R l = (R)lam;
+  constexpr int V = Vec<T>::V;
+  x += off;
+  r += off;
+  p += off;
+  w += off;
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-    const cplx<R> pi = p[off + i];
-    cplx<R> wi = w[off + i];
-    if (den2) wi = wi + l * pi;
-    x[off + i] = x[off + i] + a * pi;
-    const cplx<R> ri = r[off + i] - a * wi;
-    r[off + i] = ri;
-    acc += nrm(ri);
+  for (size_t g = (size_t)blockIdx.x * kT + threadIdx.x; g < n / V; g += (size_t)gridDim.x * kT) {
+    cplx<R> pv[V], wv[V], xv[V], rv[V];
+    Vec<T>::ld(p, g, pv);
+    Vec<T>::ld(w, g, wv);
+    Vec<T>::ld(x, g, xv);
+    Vec<T>::ld(r, g, rv);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (den2) wv[k] = wv[k] + l * pv[k];
+      xv[k] = xv[k] + a * pv[k];
+      rv[k] = rv[k] - a * wv[k];
+      acc += nrm(rv[k]);
+    }
+    Vec<T>::st(x, g, xv);
+    Vec<T>::st(r, g, rv);
   }
   if (rr) {
     double v[1] = {acc};
@@ -121,20 +169,30 @@ k_update(cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __rest
   }
 }
 
-template <typename R>
+template <typename T>
 __global__ void __launch_bounds__(kT)
-k_xpay(cplx<R>* __restrict__ p, const cplx<R>* __restrict__ y, size_t n, const double* num,
-       bool cnum, const double* den, double sign, Red red, double* pp, int dstr) {
+k_xpay(T* __restrict__ p, const T* __restrict__ y, size_t n, const double* num, bool cnum,
+       const double* den, double sign, Red red, double* pp, int dstr) {
+  using R = typename St<T>::R;
   const int rhs = blockIdx.y;
   const size_t off = rhs * n;
   double bre, bim;
   coef(num, cnum, den, nullptr, 0.0, rhs, bre, bim, dstr);
   const cplx<R> b = cmk((R)(sign * bre), (R)(sign * bim));
+  constexpr int V = Vec<T>::V;
+  p += off;
+  y += off;
   double acc = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-    const cplx<R> v = y[off + i] + b * p[off + i];
-    p[off + i] = v;
-    acc += nrm(v);
+  for (size_t g = (size_t)blockIdx.x * kT + threadIdx.x; g < n / V; g += (size_t)gridDim.x * kT) {
+    cplx<R> yv[V], pv[V];
+    Vec<T>::ld(y, g, yv);
+    Vec<T>::ld(p, g, pv);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      pv[k] = yv[k] + b * pv[k];
+      acc += nrm(pv[k]);
+    }
+    Vec<T>::st(p, g, pv);
   }
   if (pp) {
     double v[1] = {acc};
@@ -174,10 +232,15 @@ __global__ void k_scale_copy(cplx<Ry>* __restrict__ y, const cplx<Rx>* __restric
   }
 }
 
-template <typename R>
-__global__ void k_zero(cplx<R>* __restrict__ y, size_t total) {
-  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT)
-    y[i] = cmk((R)0, (R)0);
+template <typename T>
+__global__ void k_zero(T* __restrict__ y, size_t total) {
+  using R = typename St<T>::R;
+  constexpr int V = Vec<T>::V;
+  cplx<R> z[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) z[k] = cmk((R)0, (R)0);
+  for (size_t g = (size_t)blockIdx.x * kT + threadIdx.x; g < total / V; g += (size_t)gridDim.x * kT)
+    Vec<T>::st(y, g, z);
 }
 
 }  // namespace
@@ -195,40 +258,83 @@ int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int
   return DWF_OK;
 }
 
-template <typename R>
-int b_norm2(Red red, const cplx<R>* x, size_t n, int nrhs, double* res, hipStream_t st) {
+template <typename T>
+int norm2_t(Red red, const T* x, size_t n, int nrhs, double* res, hipStream_t st) {
+  if (n % Vec<T>::V) return fail(DWF_ERR_ARG, "16-bit fields need a multiple of 4 complex values");
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
-  hipLaunchKernelGGL((k_norm2<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, n, red, res);
+  hipLaunchKernelGGL((k_norm2<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, n, red, res);
   LAUNCH_CHECK();
   return launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, res, st);
+}
+template <typename T>
+int dot_t(Red red, const T* a, const T* b, size_t n, int nrhs, double* res, hipStream_t st) {
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_dot<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, a, b, n, red, res);
+  LAUNCH_CHECK();
+  return launch_finalize(2, red.partials, kMaxPartials / 2, nblocks(n), nrhs, res, st);
+}
+template <typename T>
+int update_t(Red red, T* x, T* r, const T* p, const T* w, size_t n, int nrhs, const double* num,
+             bool cnum, const double* den, const double* den2, double lam, double* rr,
+             hipStream_t st, int dstr) {
+  if (n % Vec<T>::V) return fail(DWF_ERR_ARG, "16-bit fields need a multiple of 4 complex values");
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_update<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
+                     cnum, den, den2, lam, red, rr, dstr);
+  LAUNCH_CHECK();
+  return rr ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, rr, st) : DWF_OK;
+}
+template <typename T>
+int xpay_t(Red red, T* p, const T* y, size_t n, int nrhs, const double* num, bool cnum,
+           const double* den, double sign, double* pp, hipStream_t st, int dstr) {
+  if (n % Vec<T>::V) return fail(DWF_ERR_ARG, "16-bit fields need a multiple of 4 complex values");
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL((k_xpay<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, p, y, n, num, cnum, den,
+                     sign, red, pp, dstr);
+  LAUNCH_CHECK();
+  return pp ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, pp, st) : DWF_OK;
+}
+template <typename T>
+int zero_t(T* y, size_t total, hipStream_t st) {
+  if (total % Vec<T>::V) return fail(DWF_ERR_ARG, "16-bit fields need a multiple of 4 complex values");
+  hipLaunchKernelGGL((k_zero<T>), dim3(nblocks(total)), dim3(kT), 0, st, y, total);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+
+template <typename R>
+int b_norm2(Red red, const cplx<R>* x, size_t n, int nrhs, double* res, hipStream_t st) {
+  return norm2_t(red, x, n, nrhs, res, st);
 }
 template <typename R>
 int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, double* res,
           hipStream_t st) {
-  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
-  hipLaunchKernelGGL((k_dot<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, a, b, n, red, res);
-  LAUNCH_CHECK();
-  return launch_finalize(2, red.partials, kMaxPartials / 2, nblocks(n), nrhs, res, st);
+  return dot_t(red, a, b, n, nrhs, res, st);
 }
 template <typename R>
 int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w, size_t n,
              int nrhs, const double* num, bool cnum, const double* den, const double* den2,
              double lam, double* rr, hipStream_t st, int dstr) {
-  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
-  hipLaunchKernelGGL((k_update<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
-                     cnum, den, den2, lam, red, rr, dstr);
-  LAUNCH_CHECK();
-  return rr ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, rr, st) : DWF_OK;
+  return update_t(red, x, r, p, w, n, nrhs, num, cnum, den, den2, lam, rr, st, dstr);
 }
 template <typename R>
 int b_xpay(Red red, cplx<R>* p, const cplx<R>* y, size_t n, int nrhs, const double* num, bool cnum,
            const double* den, double sign, double* pp, hipStream_t st, int dstr) {
-  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
-  hipLaunchKernelGGL((k_xpay<R>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, p, y, n, num, cnum, den,
-                     sign, red, pp, dstr);
-  LAUNCH_CHECK();
-  return pp ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, pp, st) : DWF_OK;
+  return xpay_t(red, p, y, n, nrhs, num, cnum, den, sign, pp, st, dstr);
 }
+int b_norm2(Red red, const bf16c* x, size_t n, int nrhs, double* res, hipStream_t st) {
+  return norm2_t(red, x, n, nrhs, res, st);
+}
+int b_update(Red red, bf16c* x, bf16c* r, const bf16c* p, const bf16c* w, size_t n, int nrhs,
+             const double* num, const double* den, const double* den2, double lam, double* rr,
+             hipStream_t st) {
+  return update_t(red, x, r, p, w, n, nrhs, num, false, den, den2, lam, rr, st, 1);
+}
+int b_xpay(Red red, bf16c* p, const bf16c* y, size_t n, int nrhs, const double* num,
+           const double* den, double* pp, hipStream_t st) {
+  return xpay_t(red, p, y, n, nrhs, num, false, den, 1.0, pp, st, 1);
+}
+int b_zero(bf16c* y, size_t total, hipStream_t st) { return zero_t(y, total, st); }
 template <typename R>
 int b_axpby(cplx<R>* y, const cplx<R>* x, double a, double b, size_t total, hipStream_t st) {
   hipLaunchKernelGGL((k_axpby<R>), dim3(nblocks(total)), dim3(kT), 0, st, y, x, (R)a, (R)b, total);
@@ -252,9 +358,7 @@ int b_scale_copy(cplx<Ry>* y, const cplx<Rx>* x, const double* v, bool invsqrt, 
 }
 template <typename R>
 int b_zero(cplx<R>* y, size_t total, hipStream_t st) {
-  hipLaunchKernelGGL((k_zero<R>), dim3(nblocks(total)), dim3(kT), 0, st, y, total);
-  LAUNCH_CHECK();
-  return DWF_OK;
+  return zero_t(y, total, st);
 }
 
 #define INST(R)                                                                                   \

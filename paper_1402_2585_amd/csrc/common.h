@@ -102,6 +102,59 @@ __host__ __device__ __forceinline__ void cjmac(cplx<R>& a, cplx<R> b, cplx<R> c)
   a.im = fma(-b.im, c.re, a.im);
 }
 
+// ------------------------------------------------------ field storage ---
+// A complex number stored as two bfloat16 values (re, im): 4 bytes, for
+// fields whose arithmetic runs in FP32 but whose storage may be 16-bit.
+struct alignas(4) bf16c {
+  unsigned short re, im;
+};
+
+__host__ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  unsigned u = (unsigned)h << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+// round to nearest even; a NaN may come out as an infinity (still
+// non-finite, which is all the solvers test for)
+__host__ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  unsigned u;
+  __builtin_memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+// Storage traits: St<T>::R is the arithmetic type of a field stored as T;
+// ld / st convert between the two.
+template <typename T>
+struct St;
+template <>
+struct St<cplx<double>> {
+  using R = double;
+  __device__ __forceinline__ static cplx<double> ld(const cplx<double>* p) { return *p; }
+  __device__ __forceinline__ static void st(cplx<double>* p, cplx<double> v) { *p = v; }
+};
+template <>
+struct St<cplx<float>> {
+  using R = float;
+  __device__ __forceinline__ static cplx<float> ld(const cplx<float>* p) { return *p; }
+  __device__ __forceinline__ static void st(cplx<float>* p, cplx<float> v) { *p = v; }
+};
+template <>
+struct St<bf16c> {
+  using R = float;
+  __device__ __forceinline__ static cplx<float> ld(const bf16c* p) {
+    const bf16c v = *p;
+    return cmk(bf16_to_f32(v.re), bf16_to_f32(v.im));
+  }
+  __device__ __forceinline__ static void st(bf16c* p, cplx<float> v) {
+    bf16c o;
+    o.re = f32_to_bf16(v.re);
+    o.im = f32_to_bf16(v.im);
+    *p = o;
+  }
+};
+
 template <typename R>
 inline int prec_of();
 template <>
@@ -112,7 +165,8 @@ template <>
 inline int prec_of<float>() {
   return DWF_C64;
 }
-inline size_t cbytes(int prec) { return prec == DWF_C128 ? 16 : 8; }
+// bytes per complex of a fine field in precision prec (DWF_BF16: 16-bit storage)
+inline size_t cbytes(int prec) { return prec == DWF_C128 ? 16 : (prec == DWF_BF16 ? 4 : 8); }
 
 // --------------------------------------------------------------- buffers ---
 // Grow-only device buffer owned by a handle.

@@ -49,7 +49,7 @@ struct dwf_op {
   hdk::FifthDim f5;
   hdk::DevBuf gauge128, gauge64;  // [2][Vh][8][9]
   hdk::DevBuf pw128, pw64;        // closed-form table on the device
-  hdk::DevBuf tmp[2][3];          // [prec][t_e, chi, s_e] work fields
+  hdk::DevBuf tmp[3][3];          // [c128, c64, bf16][t_e, chi, s_e] work fields
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
   hdk::DevBuf mgw[5];             // mixed-precision CG work fields (c64): r, p, w, source, correction
   hdk::Reducer red;
@@ -73,16 +73,17 @@ struct dwf_op {
 namespace hdk {
 
 // Launch helpers (all asynchronous on `stream`).
-template <typename R>
-int launch_mpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, bool dagger, int nrhs,
-               hipStream_t stream, double* norm_result /*nullable: |M_pc in|^2 per rhs*/);
-template <typename R>
-int launch_mpcdagmpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, int nrhs, hipStream_t stream,
+// Fields stored as T (cplx<R>, or bf16c with R = float), arithmetic in R.
+template <typename R, typename T = cplx<R>>
+int launch_mpc(dwf_op* op, T* out, const T* in, bool dagger, int nrhs, hipStream_t stream,
+               double* norm_result /*nullable: |M_pc in|^2 per rhs*/);
+template <typename R, typename T = cplx<R>>
+int launch_mpcdagmpc(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t stream,
                      double* pap_result /*nullable: <in, H in> = |M_pc in|^2 per rhs*/);
 
 // BLAS-1 (FP64 accumulation); results are device doubles, one per rhs.
-template <typename R>
-int launch_norm2(dwf_op* op, const cplx<R>* x, int nrhs, double* result, hipStream_t stream);
+template <typename R, typename T = cplx<R>>
+int launch_norm2(dwf_op* op, const T* x, int nrhs, double* result, hipStream_t stream);
 template <typename R>
 int launch_dot(dwf_op* op, const cplx<R>* a, const cplx<R>* b, int nrhs, double* result /*2*nrhs*/,
                hipStream_t stream);
@@ -100,8 +101,9 @@ int launch_xpay(dwf_op* op, cplx<R>* p, const cplx<R>* r, const double* num, con
 template <typename R>
 int launch_axpby(dwf_op* op, cplx<R>* y, const cplx<R>* x, double a, double b, size_t n,
                  hipStream_t stream);
-template <typename Rd, typename Rs>
-int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t stream);
+// dst = src between storage types (c128, c64, bf16c), rounded to nearest even
+template <typename Td, typename Ts>
+int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
 void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)

@@ -16,6 +16,7 @@
 // EPI_INV stages the hop result in LDS and solves the Ls x Ls system per
 // (site, component) with the O(Ls) recurrence of the closed-form inverse.
 #include <algorithm>
+#include <type_traits>
 
 #include "fine_op.h"
 
@@ -99,13 +100,14 @@ __global__ void field_layout_kernel(cplx<R>* __restrict__ dst, const cplx<R>* __
     dst[can] = src[idx];
 }
 
-template <typename Rd, typename Rs>
-__global__ void convert_kernel(cplx<Rd>* __restrict__ dst, const cplx<Rs>* __restrict__ src,
-                               size_t n) {
+// dst (stored as Td) = src (stored as Ts), rounded to nearest (even)
+template <typename Td, typename Ts>
+__global__ void convert_kernel(Td* __restrict__ dst, const Ts* __restrict__ src, size_t n) {
+  using Rd = typename St<Td>::R;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
-    cplx<Rs> v = src[i];
-    dst[i] = cmk((Rd)v.re, (Rd)v.im);
+    const auto v = St<Ts>::ld(src + i);
+    St<Td>::st(dst + i, cmk((Rd)v.re, (Rd)v.im));
   }
 }
 
@@ -158,6 +160,13 @@ __device__ __forceinline__ void store_field(cplx<R>* p, cplx<R> v, bool nt) {
   } else {
     *p = v;
   }
+}
+__device__ __forceinline__ void store_field(bf16c* p, cplx<float> v, bool nt) {
+  const unsigned w = (unsigned)f32_to_bf16(v.re) | ((unsigned)f32_to_bf16(v.im) << 16);
+  if (nt)
+    __builtin_nontemporal_store(w, reinterpret_cast<unsigned*>(p));
+  else
+    *reinterpret_cast<unsigned*>(p) = w;
 }
 
 // acc += (1 + SG*gamma_mu) W psi from the projected half-spinor
@@ -306,10 +315,10 @@ __device__ __forceinline__ void bcs_row(cplx<R>* row, int Ls, R b, R c, R m, boo
 // complex) and applies M_5^-1 (or M_5^-+); EPI_SUB forms M_5 c - acc/4 (or
 // M_5^+ c - acc/4) and, when A.partials is set, stores this workgroup's part
 // of its squared norm.  Every thread of the workgroup must call it.
-template <typename R, bool DAG, int EPI, int LS = 0, bool MOB = false>
+template <typename R, bool DAG, int EPI, int LS = 0, bool MOB = false, typename T = cplx<R>>
 __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool active, int vloc, int s,
-                                             int v, int wg, int rhs, cplx<R>* __restrict__ out,
-                                             const cplx<R>* __restrict__ center,
+                                             int v, int wg, int rhs, T* __restrict__ out,
+                                             const T* __restrict__ center,
                                              const R* __restrict__ pw, const HopArgs& A,
                                              unsigned char* smem_raw) {
   const Geom& g = A.g;
@@ -360,7 +369,7 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
     }
     __syncthreads();
     if (active) {
-      cplx<R>* o = out + (size_t)v * 12 * Ls + s;
+      T* o = out + (size_t)v * 12 * Ls + s;
 #pragma unroll
       for (int c = 0; c < 12; ++c) store_field(o + c * Ls, buf[(vloc * 12 + c) * ld + s], A.nt & 1);
     }
@@ -392,8 +401,8 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
     }
     double nrm = 0.0;
     if (active) {
-      const cplx<R>* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
-      cplx<R>* o = out + (size_t)v * 12 * Ls + s;
+      const T* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
+      T* o = out + (size_t)v * 12 * Ls + s;
       const R al = (R)A.alpha, be = (R)A.beta, m = (R)A.mass, q = (R)0.25;
       // M_5 = alpha + beta K: P+ couples to s-1 (-mass times Ls-1 at s = 0),
       // P- to s+1 (-mass times 0 at s = Ls-1); the adjoint swaps the directions.
@@ -403,11 +412,11 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
       const R f_up = (s < Ls - 1) ? be : -m * be;
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const cplx<R>* cc = cen + c * Ls;
+        const T* cc = cen + c * Ls;
         const bool from_below = ((c < 6) != DAG);
         const int sn = from_below ? s_dn : s_up;
         const R fn = from_below ? f_dn : f_up;
-        const cplx<R> r = al * cc[s] + fn * cc[sn] - q * hop[c];
+        const cplx<R> r = al * St<T>::ld(cc + s) + fn * St<T>::ld(cc + sn) - q * hop[c];
         store_field(o + c * Ls, r, A.nt & 1);
         nrm += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
       }
@@ -458,33 +467,33 @@ __device__ __forceinline__ void dir_term(cplx<R> (&acc)[12], const cplx<R> (&psi
   hop_term_vals<R, MU, SG>(acc, psi, links + ((D & 1) ? 4 + MU : MU) * 9);
 }
 
-template <typename R, int D0, int N>
-__device__ __forceinline__ void load_dirs(cplx<R> (&psi)[N][12], const cplx<R>* __restrict__ in,
+template <typename T, int D0, int N>
+__device__ __forceinline__ void load_dirs(cplx<typename St<T>::R> (&psi)[N][12], const T* __restrict__ in,
                                           const int (&nb)[8], size_t col, int s, int Ls) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const cplx<R>* p = in + (size_t)nb[D0 + k] * col + s;
+    const T* p = in + (size_t)nb[D0 + k] * col + s;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[k][c] = p[c * Ls];
+    for (int c = 0; c < 12; ++c) psi[k][c] = St<T>::ld(p + c * Ls);
   }
 }
 
 // load_dirs for the Mobius first stage: each neighbour spinor is read as
 // C_5 psi = b5 psi_s + c5 (K psi)_s (K: P+ from s-1, P- from s+1, -mass at the
 // wrap), the s +- 1 entries read from the same contiguous column.
-template <typename R, int D0, int N>
-__device__ __forceinline__ void load_dirs_c5(cplx<R> (&psi)[N][12], const cplx<R>* __restrict__ in,
+template <typename T, int D0, int N, typename R = typename St<T>::R>
+__device__ __forceinline__ void load_dirs_c5(cplx<R> (&psi)[N][12], const T* __restrict__ in,
                                              const int (&nb)[8], size_t col, int s, int Ls, R b5, R c5,
                                              R m) {
   const int s_dn = (s > 0) ? s - 1 : Ls - 1, s_up = (s < Ls - 1) ? s + 1 : 0;
   const R w_dn = (s > 0) ? c5 : -m * c5, w_up = (s < Ls - 1) ? c5 : -m * c5;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const cplx<R>* p = in + (size_t)nb[D0 + k] * col;
+    const T* p = in + (size_t)nb[D0 + k] * col;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const cplx<R> x = p[c * Ls + s];
-      const cplx<R> y = c < 6 ? p[c * Ls + s_dn] : p[c * Ls + s_up];
+      const cplx<R> x = St<T>::ld(p + c * Ls + s);
+      const cplx<R> y = St<T>::ld(c < 6 ? p + c * Ls + s_dn : p + c * Ls + s_up);
       psi[k][c] = b5 * x + (c < 6 ? w_dn : w_up) * y;
     }
   }
@@ -506,11 +515,10 @@ __device__ __forceinline__ void apply_dirs(cplx<R> (&acc)[12], const cplx<R> (&p
 // NPH = number of load phases (2: four directions in flight at a time; 4:
 // two).  LS > 0 fixes Ls at compile time.  Dynamic LDS:
 // max(spw * kLinkLd, spw * 12 * (Ls + 1)) complex.
-template <typename R, bool DAG, int EPI, int NPH, int LS, bool MOB>
+template <typename R, bool DAG, int EPI, int NPH, int LS, bool MOB, typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
-hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
-               const cplx<R>* __restrict__ center, const cplx<R>* __restrict__ gauge,
-               const R* __restrict__ pw, HopArgs A) {
+hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ center,
+           const cplx<R>* __restrict__ gauge, const R* __restrict__ pw, HopArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Geom& g = A.g;
   const int Ls = LS > 0 ? LS : g.Ls;  // compile-time when LS > 0: immediate load offsets
@@ -541,9 +549,9 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
   if (active) {
     hop_neighbours(g, c, nb);
     if (C5IN)
-      load_dirs_c5<R, 0, ND>(psi, in, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
+      load_dirs_c5<T, 0, ND>(psi, in, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
     else
-      load_dirs<R, 0, ND>(psi, in, nb, col, s, Ls);
+      load_dirs<T, 0, ND>(psi, in, nb, col, s, Ls);
   }
   __syncthreads();  // links in LDS
 
@@ -556,26 +564,26 @@ hop_kernel(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ in,
     const R b5 = (R)A.b5, c5 = (R)A.c5, mm = (R)A.mass;
     if (NPH >= 2) {
       if (C5IN)
-        load_dirs_c5<R, ND % 8, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+        load_dirs_c5<T, ND % 8, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
       else
-        load_dirs<R, ND % 8, ND>(psi, in, nb, col, s, Ls);
+        load_dirs<T, ND % 8, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, ND % 8, ND, SF>(acc, psi, L);
     }
     if (NPH == 4) {
       if (C5IN)
-        load_dirs_c5<R, 4, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+        load_dirs_c5<T, 4, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
       else
-        load_dirs<R, 4, ND>(psi, in, nb, col, s, Ls);
+        load_dirs<T, 4, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, 4, ND, SF>(acc, psi, L);
       if (C5IN)
-        load_dirs_c5<R, 6, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
+        load_dirs_c5<T, 6, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
       else
-        load_dirs<R, 6, ND>(psi, in, nb, col, s, Ls);
+        load_dirs<T, 6, ND>(psi, in, nb, col, s, Ls);
       apply_dirs<R, 6, ND, SF>(acc, psi, L);
     }
   }
   if (EPI == EPI_INV || (MOB && DAG)) __syncthreads();  // the epilogue's LDS buffer reuses the link rows
-  hop_epilogue<R, DAG, EPI, LS, MOB>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
+  hop_epilogue<R, DAG, EPI, LS, MOB, T>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
 }
 
 // ------------------------------------------------------------------ BLAS ---
@@ -591,14 +599,14 @@ struct RedArgs {
   double* result;
 };
 
-template <typename R>
-__global__ void __launch_bounds__(256) norm2_kernel(const cplx<R>* __restrict__ x, RedArgs A) {
+template <typename T>
+__global__ void __launch_bounds__(256) norm2_kernel(const T* __restrict__ x, RedArgs A) {
   const int rhs = blockIdx.y;
   x += rhs * A.n;
   double acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n;
        i += (size_t)gridDim.x * blockDim.x)
-    acc += cnorm(x[i]);
+    acc += cnorm(St<T>::ld(x + i));
   double v[1] = {acc};
   __shared__ double red[16];
   block_sum<1>(v, red);
@@ -694,32 +702,33 @@ void release_tmp(dwf_op* op) {
     for (auto& b : a) b.release();
 }
 
+static int tmp_index(int prec) { return prec == DWF_C128 ? 0 : (prec == DWF_BF16 ? 2 : 1); }
+
 int ensure_tmp(dwf_op* op, int prec, int nrhs) {
   const size_t bytes = op->field_elems(nrhs) * cbytes(prec);
-  const int pi = prec == DWF_C128 ? 0 : 1;
+  const int pi = tmp_index(prec);
   for (int i = 0; i < 3; ++i) HDCG_TRY(op->tmp[pi][i].ensure(bytes));
   return DWF_OK;
 }
 
-template <typename R, int NPH, int LS, bool MOB>
+template <typename R, int NPH, int LS, bool MOB, typename T>
 static void launch_hop(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
-                       cplx<R>* out, const cplx<R>* in, const cplx<R>* center, const cplx<R>* G,
-                       const R* pw, const HopArgs& A) {
+                       T* out, const T* in, const T* center, const cplx<R>* G, const R* pw, const HopArgs& A) {
   if (epi == EPI_INV) {
     if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
   } else {
     if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS, MOB>), grid, block, lds, stream, out, in, center, G, pw, A);
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
   }
 }
 
-template <typename R>
-static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>* center,
+template <typename R, typename T = cplx<R>>
+static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
                       bool dagger, int epi, int out_parity, int nrhs, hipStream_t stream,
                       double* norm_result) {
   const Geom& g = op->g;
@@ -792,56 +801,55 @@ static int hop_launch(dwf_op* op, cplx<R>* out, const cplx<R>* in, const cplx<R>
   const bool two = op->tune.phases == 4 || mob;
   if (mob) {
     if (g.Ls == 16)
-      launch_hop<R, 4, 16, true>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 16, true, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      launch_hop<R, 4, 0, true>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 0, true, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   } else if (g.Ls == 16) {
     if (two)
-      launch_hop<R, 4, 16, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 16, false, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      launch_hop<R, 2, 16, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 2, 16, false, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   } else {
     if (two)
-      launch_hop<R, 4, 0, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 4, 0, false, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
     else
-      launch_hop<R, 2, 0, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
+      launch_hop<R, 2, 0, false, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   }
   HDCG_HIP(hipGetLastError());
   if (norm_result) return launch_finalize(1, A.partials, nwg, nwg, nrhs, norm_result, stream, A.pstride);
   return DWF_OK;
 }
 
-template <typename R>
-int launch_mpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, bool dagger, int nrhs,
-               hipStream_t stream, double* norm_result) {
-  const int prec = prec_of<R>();
+template <typename R, typename T>
+int launch_mpc(dwf_op* op, T* out, const T* in, bool dagger, int nrhs, hipStream_t stream,
+               double* norm_result) {
+  const int prec = std::is_same<T, bf16c>::value ? DWF_BF16 : prec_of<R>();
   HDCG_TRY(ensure_tmp(op, prec, nrhs));
-  cplx<R>* te = op->tmp[prec == DWF_C128 ? 0 : 1][0].as<cplx<R>>();
+  T* te = op->tmp[tmp_index(prec)][0].as<T>();
   // stage 1: t_e = M_5^-1 Dh_eo in    (adjoint: M_5^-+ Dh^+_eo in)
-  HDCG_TRY(hop_launch<R>(op, te, in, nullptr, dagger, EPI_INV, 0, nrhs, stream, nullptr));
+  HDCG_TRY((hop_launch<R, T>(op, te, in, nullptr, dagger, EPI_INV, 0, nrhs, stream, nullptr)));
   // stage 2: out = M_5 in - 1/4 Dh_oe t_e  (adjoint: M_5^+ in - 1/4 Dh^+_oe t_e)
-  HDCG_TRY(hop_launch<R>(op, out, te, in, dagger, EPI_SUB, 1, nrhs, stream, norm_result));
+  HDCG_TRY((hop_launch<R, T>(op, out, te, in, dagger, EPI_SUB, 1, nrhs, stream, norm_result)));
   return DWF_OK;
 }
 
-template <typename R>
-int launch_mpcdagmpc(dwf_op* op, cplx<R>* out, const cplx<R>* in, int nrhs, hipStream_t stream,
-                     double* pap_result) {
-  const int prec = prec_of<R>();
+template <typename R, typename T>
+int launch_mpcdagmpc(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t stream, double* pap_result) {
+  const int prec = std::is_same<T, bf16c>::value ? DWF_BF16 : prec_of<R>();
   HDCG_TRY(ensure_tmp(op, prec, nrhs));
-  cplx<R>* chi = op->tmp[prec == DWF_C128 ? 0 : 1][1].as<cplx<R>>();
-  HDCG_TRY(launch_mpc<R>(op, chi, in, false, nrhs, stream, pap_result));
-  HDCG_TRY(launch_mpc<R>(op, out, chi, true, nrhs, stream, nullptr));
+  T* chi = op->tmp[tmp_index(prec)][1].as<T>();
+  HDCG_TRY((launch_mpc<R, T>(op, chi, in, false, nrhs, stream, pap_result)));
+  HDCG_TRY((launch_mpc<R, T>(op, out, chi, true, nrhs, stream, nullptr)));
   return DWF_OK;
 }
 
-template <typename R>
-int launch_norm2(dwf_op* op, const cplx<R>* x, int nrhs, double* result, hipStream_t stream) {
+template <typename R, typename T>
+int launch_norm2(dwf_op* op, const T* x, int nrhs, double* result, hipStream_t stream) {
   RedArgs A{op->field_elems(1), op->red.partials.as<double>(), op->red.counters.as<unsigned>(),
             result};
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
   dim3 grid(red_blocks(A.n), nrhs);
-  hipLaunchKernelGGL((norm2_kernel<R>), grid, dim3(256), 0, stream, x, A);
+  hipLaunchKernelGGL((norm2_kernel<T>), grid, dim3(256), 0, stream, x, A);
   HDCG_HIP(hipGetLastError());
   return launch_finalize(1, A.partials, kMaxPartials, grid.x, nrhs, result, stream);
 }
@@ -890,17 +898,17 @@ int launch_axpby(dwf_op*, cplx<R>* y, const cplx<R>* x, double a, double b, size
   return DWF_OK;
 }
 
-template <typename Rd, typename Rs>
-int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t stream) {
-  hipLaunchKernelGGL((convert_kernel<Rd, Rs>), dim3(red_blocks(n)), dim3(256), 0, stream, dst, src, n);
+template <typename Td, typename Ts>
+int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream) {
+  hipLaunchKernelGGL((convert_kernel<Td, Ts>), dim3(red_blocks(n)), dim3(256), 0, stream, dst, src, n);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }
 
 #define INST(R)                                                                                 \
-  template int launch_mpc<R>(dwf_op*, cplx<R>*, const cplx<R>*, bool, int, hipStream_t, double*); \
-  template int launch_mpcdagmpc<R>(dwf_op*, cplx<R>*, const cplx<R>*, int, hipStream_t, double*); \
-  template int launch_norm2<R>(dwf_op*, const cplx<R>*, int, double*, hipStream_t);             \
+  template int launch_mpc<R, cplx<R>>(dwf_op*, cplx<R>*, const cplx<R>*, bool, int, hipStream_t, double*); \
+  template int launch_mpcdagmpc<R, cplx<R>>(dwf_op*, cplx<R>*, const cplx<R>*, int, hipStream_t, double*); \
+  template int launch_norm2<R, cplx<R>>(dwf_op*, const cplx<R>*, int, double*, hipStream_t);    \
   template int launch_dot<R>(dwf_op*, const cplx<R>*, const cplx<R>*, int, double*, hipStream_t); \
   template int launch_cg_update<R>(dwf_op*, cplx<R>*, cplx<R>*, const cplx<R>*, const cplx<R>*, \
                                    const double*, const double*, const double*, double*, int,  \
@@ -911,8 +919,13 @@ int launch_convert(cplx<Rd>* dst, const cplx<Rs>* src, size_t n, hipStream_t str
                                hipStream_t);
 INST(double)
 INST(float)
-template int launch_convert<double, float>(cplx<double>*, const cplx<float>*, size_t, hipStream_t);
-template int launch_convert<float, double>(cplx<float>*, const cplx<double>*, size_t, hipStream_t);
+template int launch_mpc<float, bf16c>(dwf_op*, bf16c*, const bf16c*, bool, int, hipStream_t, double*);
+template int launch_mpcdagmpc<float, bf16c>(dwf_op*, bf16c*, const bf16c*, int, hipStream_t, double*);
+template int launch_norm2<float, bf16c>(dwf_op*, const bf16c*, int, double*, hipStream_t);
+template int launch_convert<c128, c64>(c128*, const c64*, size_t, hipStream_t);
+template int launch_convert<c64, c128>(c64*, const c128*, size_t, hipStream_t);
+template int launch_convert<bf16c, c64>(bf16c*, const c64*, size_t, hipStream_t);
+template int launch_convert<c64, bf16c>(c64*, const bf16c*, size_t, hipStream_t);
 
 // ------------------------------------------------------------ host setup ---
 int import_gauge(dwf_op* op, const void* gauge_c128, hipStream_t stream) {

@@ -34,6 +34,7 @@ struct hdcg {
   hdk::DevBuf cw[6];          // coarse work vectors (c64/c128)
   hdk::DevBuf fw64[12];       // fine c64 work fields: 0-7 solver, 8-10 fine CG
   hdk::DevBuf fw128[3];       // fine c128 work fields
+  hdk::DevBuf fw16[4];        // fine 16-bit work fields of M_IRS: x, r, p, w
   hdk::DevBuf scal;           // device scalars
   hdk::DevBuf probe_c;        // coarse probe vectors for the build
   hdk::DevBuf mf_rho, mf_smax;      // per-matrix scales of the 16-bit coarse storage
@@ -57,6 +58,7 @@ struct hdcg {
     int outer_maxiter = 50;
     int build_batch = 8;
     int coarse_prec = DWF_C64;  // storage of A inside Q: C64 (VALU), BF16 / F16 (MFMA)
+    int irs_prec = DWF_C64;     // storage of the M_IRS fields: C64 or BF16
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;

@@ -153,6 +153,45 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
   return DWF_OK;
 }
 
+// M_IRS with 16-bit fields: exactly `fixed` CG iterations on (H + lam) from
+// x = 0 with x, r, p, w stored as bf16c (FP32 arithmetic inside every kernel,
+// FP64 norms, H itself on 16-bit fields); b and x_out are complex64.
+int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixed, hipStream_t st) {
+  dwf_op* op = h->op;
+  const size_t n = fine_elems(h);
+  for (int i = 0; i < 4; ++i) HDCG_TRY(h->fw16[i].ensure(n * nr * sizeof(bf16c)));
+  bf16c* x = h->fw16[0].as<bf16c>();
+  bf16c* r = h->fw16[1].as<bf16c>();
+  bf16c* p = h->fw16[2].as<bf16c>();
+  bf16c* w = h->fw16[3].as<bf16c>();
+  const Red red = red_of(op);
+  double* rr[2] = {slot(h, S_RR0), slot(h, S_RR1)};
+  double* pap = slot(h, S_PAP);
+  double* pp = lam != 0.0 ? slot(h, S_PP) : nullptr;
+  HDCG_TRY(b_zero(x, n * nr, st));
+  HDCG_TRY(launch_convert(r, b, n * nr, st));
+  HDCG_HIP(hipMemcpyAsync(p, r, n * nr * sizeof(bf16c), hipMemcpyDeviceToDevice, st));
+  HDCG_TRY(b_norm2(red, r, n, nr, rr[0], st));
+  if (pp) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < fixed; ++k) {
+    double* cur = rr[k & 1];
+    double* nxt = rr[(k + 1) & 1];
+    HDCG_TRY((launch_mpcdagmpc<float, bf16c>(op, w, p, nr, st, pap)));
+    HDCG_TRY(b_update(red, x, r, p, w, n, nr, cur, pap, pp, lam, nxt, st));
+    HDCG_TRY(b_xpay(red, p, r, n, nr, nxt, cur, pp, st));
+  }
+  return launch_convert(x_out, x, n * nr, st);
+}
+
+// M_IRS in the storage precision the parameters select
+static int apply_mirs(hdcg* h, c64* z, const c64* r, int nr, int* it, hipStream_t st) {
+  if (h->prm.irs_prec == DWF_BF16) {
+    *it = h->prm.n_irs;
+    return fine_cg_bf16(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, st);
+  }
+  return fine_cg(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, 0.0, 0, it, st);
+}
+
 // -------------------------------------------------------------- coarse CG --
 template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
@@ -252,7 +291,7 @@ static int precondition(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, h
   c64* z = y;
   c64* t = h->fw64[6].as<c64>();
   int it = 0;
-  HDCG_TRY(fine_cg(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, 0.0, 0, &it, st));
+  HDCG_TRY(apply_mirs(h, z, r, nr, &it, st));
   is->matmuls32 += it * nr;
   HDCG_TRY(launch_mpcdagmpc<float>(h->op, t, z, nr, st, nullptr));
   is->matmuls32 += nr;
@@ -335,6 +374,14 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
 
 using namespace hdk;
 
+static int check_solve_params(int coarse_prec, int irs_prec) {
+  if (coarse_prec != DWF_C64 && coarse_prec != DWF_BF16 && coarse_prec != DWF_F16)
+    return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");
+  if (irs_prec != DWF_C64 && irs_prec != DWF_BF16)
+    return fail(DWF_ERR_ARG, "irs_prec must be DWF_C64 or DWF_BF16");
+  return DWF_OK;
+}
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -355,6 +402,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->build_batch = 8;
   p->coarse_prec = DWF_C64;
   p->verbose = 0;
+  p->irs_prec = DWF_C64;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -373,6 +421,7 @@ int hdcg_destroy(hdcg_t h) {
   for (auto& b : h->cw) b.release();
   for (auto& b : h->fw64) b.release();
   for (auto& b : h->fw128) b.release();
+  for (auto& b : h->fw16) b.release();
   h->scal.release();
   h->probe_c.release();
   h->mf_rho.release();
@@ -416,7 +465,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
       const int g = std::min(G, nv - k0);
       c128* can = work.as<c128>() + (size_t)k0 * fe;
       HDCG_TRY(dwf_import(op, v128, can, DWF_C128, g, st));
-      HDCG_TRY(launch_convert<float, double>(v, v128, fe * g, st));
+      HDCG_TRY(launch_convert(v, v128, fe * g, st));
       int its = 0;
       for (int s = 0; s < h->prm.n_ii; ++s) {
         int it = 0;
@@ -426,7 +475,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
         HDCG_TRY(b_norm2<float>(red_of(op), xv, fe, g, nrm, st));
         HDCG_TRY(b_scale_copy<float, float>(v, xv, nrm, true, fe, g, st));  // normalise
       }
-      HDCG_TRY(launch_convert<double, float>(v128, v, fe * g, st));
+      HDCG_TRY(launch_convert(v128, v, fe * g, st));
       HDCG_TRY(dwf_export(op, can, v128, DWF_C128, g, st));
       if (h->prm.verbose) {
         HDCG_HIP(hipStreamSynchronize(st));
@@ -448,7 +497,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   HDCG_HIP(hipStreamSynchronize(st));
   if (flag) return fail(DWF_ERR_NUMERIC, "block Gram matrix not positive definite (subspace vectors dependent on a block)");
   HDCG_TRY(h->phi64.ensure(fe * nv * sizeof(c64)));
-  HDCG_TRY(launch_convert<float, double>(h->phi64.as<c64>(), h->phi128.as<c128>(), fe * nv, st));
+  HDCG_TRY(launch_convert(h->phi64.as<c64>(), h->phi128.as<c128>(), fe * nv, st));
 
   // ---- little Dirac operator by the Fourier trick (Sec. V.A.1) ---------
   const size_t n2 = (size_t)nv * nv;
@@ -574,14 +623,13 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.build_batch = p->build_batch;
     h->prm.coarse_prec = p->coarse_prec;
     h->prm.verbose = p->verbose;
+    h->prm.irs_prec = p->irs_prec;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
-  {
-    if (h->prm.coarse_prec != DWF_C64 && h->prm.coarse_prec != DWF_BF16 && h->prm.coarse_prec != DWF_F16) {
-      delete h;
-      return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");
-    }
+  if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec); rc < 0) {
+    delete h;
+    return rc;
   }
   if (hipHostMalloc((void**)&h->pinned, 64 * 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     h->pinned = nullptr;
@@ -707,8 +755,32 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
 int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
   HDCG_TRY(check_h(h, DWF_C64, nrhs));
   if (!out || !in || out == in) return fail(DWF_ERR_ARG, "hdcg_mirs needs distinct in/out buffers");
-  return fine_cg(h, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, h->prm.lambda_irs, h->prm.n_irs,
-                 0.0, 0, nullptr, static_cast<hipStream_t>(stream));
+  int it = 0;
+  return apply_mirs(h, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, &it,
+                    static_cast<hipStream_t>(stream));
+}
+
+int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
+  if (!h || !p) return fail(DWF_ERR_ARG, "null argument to hdcg_set_params");
+  HDCG_TRY(check_solve_params(p->coarse_prec, p->irs_prec));
+  if (p->n_irs < 0 || p->coarse_maxiter < 1 || p->inner_maxiter < 1 || p->outer_maxiter < 1 ||
+      !(p->coarse_tol > 0.0) || !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
+    return fail(DWF_ERR_ARG, "hdcg_set_params: iteration caps must be positive, tolerances in (0, 1)");
+  auto st = static_cast<hipStream_t>(stream);
+  if (p->coarse_prec == DWF_BF16 && !h->mf_have_bf16) HDCG_TRY(crs_build_mfma(h, DWF_BF16, st));
+  if (p->coarse_prec == DWF_F16 && !h->mf_have_f16) HDCG_TRY(crs_build_mfma(h, DWF_F16, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  h->prm.n_irs = p->n_irs;
+  h->prm.lambda_irs = p->lambda_irs;
+  h->prm.coarse_tol = p->coarse_tol;
+  h->prm.coarse_maxiter = p->coarse_maxiter;
+  h->prm.flexible = p->flexible;
+  h->prm.inner_tol = p->inner_tol;
+  h->prm.inner_maxiter = p->inner_maxiter;
+  h->prm.outer_maxiter = p->outer_maxiter;
+  h->prm.coarse_prec = p->coarse_prec;
+  h->prm.irs_prec = p->irs_prec;
+  return DWF_OK;
 }
 
 // FP64 defect correction for one group of right-hand sides solved together.

@@ -6,7 +6,10 @@ import numpy as np
 
 from . import _lib as L
 
-_DT = {L.DWF_C128: "complex128", L.DWF_C64: "complex64"}
+# torch element type of a native field per precision; 16-bit fields are
+# bfloat16 tensors holding (re, im) pairs, two elements per complex value
+_DT = {L.DWF_C128: "complex128", L.DWF_C64: "complex64", L.DWF_BF16: "bfloat16"}
+_ELEM_BYTES = {L.DWF_C128: 16, L.DWF_C64: 8, L.DWF_BF16: 2}
 
 
 class FineOperator:
@@ -45,7 +48,7 @@ class FineOperator:
         return getattr(self.torch, _DT[prec])
 
     def new_field(self, prec=L.DWF_C128, nrhs=1, zero=False):
-        n = L.dwf_field_bytes(self.h, prec, nrhs) // (16 if prec == L.DWF_C128 else 8)
+        n = L.dwf_field_bytes(self.h, prec, nrhs) // _ELEM_BYTES[prec]
         f = self.torch.zeros if zero else self.torch.empty
         return f(n, dtype=self.dtype(prec), device="cuda")
 
@@ -64,6 +67,12 @@ class FineOperator:
         out = self.torch.empty((nrhs,) + self.canonical_shape, dtype=self.dtype(prec), device="cuda")
         L.dwf_export(self.h, out, native, prec, nrhs)
         return out if nrhs > 1 else out[0]
+
+    def convert(self, x, dst_prec, src_prec, nrhs=1):
+        """Native field x (src_prec) as a new native field in dst_prec."""
+        out = self.new_field(dst_prec, nrhs)
+        L.dwf_convert(self.h, out, dst_prec, x, src_prec, nrhs)
+        return out
 
     def mpc(self, x, prec=L.DWF_C128, dagger=0, nrhs=1, out=None):
         out = self.new_field(prec, nrhs) if out is None else out
@@ -86,8 +95,21 @@ class HDCG:
         v = v.to(device="cuda", dtype=torch.complex128).contiguous()
         self.nvec = v.shape[0]
         p = params if params is not None else L.hdcg_default_params(**overrides)
+        self.params = p
         self.h = L.hdcg_setup(op.h, block, self.nvec, v, p)
         self.coarse_dims, self.Nc, _ = L.hdcg_dims(self.h)
+
+    def set_params(self, **changes):
+        """Change solve-phase parameters (hdcg_set_params) of the built handle."""
+        p = L.HdcgParams()
+        for k, _ in p._fields_:
+            setattr(p, k, getattr(self.params, k))
+        for k, v in changes.items():
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        L.hdcg_set_params(self.h, p)
+        self.params = p
 
     def close(self):
         if self.h is not None:

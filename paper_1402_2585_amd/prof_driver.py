@@ -30,6 +30,7 @@ def main():
     ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
+    ap.add_argument("--irs", choices=["c64", "bf16"], default="c64", help="storage of the M_IRS fields")
     ap.add_argument("--n_ii", type=int, default=3)
     ap.add_argument("--tol_ii", type=float, default=1e-3)
     ap.add_argument("--maxiter_ii", type=int, default=500)
@@ -106,12 +107,13 @@ def run_hdcg(a, torch, synth):
     cprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16, "f16": hd.DWF_F16}[a.coarse]
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
     b = op.to_native(bsrc)
+    iprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.irs]
     h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
-                verbose=1)
+                irs_prec=iprec, verbose=1)
     print("setup done", flush=True)
     x = op.new_field(zero=True)
     rc, st = hd.hdcg_solve(h.h, x, b, 1, 1e-8)
-    print(f"hdcg workload {a.workload} coarse {a.coarse}: status {rc} {st}", flush=True)
+    print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs}: status {rc} {st}", flush=True)
     h.close()
     op.close()
 

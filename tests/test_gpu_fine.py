@@ -327,3 +327,108 @@ def test_mobius_rejects_unstable_fifth_dimension():
     U = synth.gauge_field(dims, 0.5, 164)
     with pytest.raises(hd.HdcgError):
         hd.FineOperator(U, dims, 8, 1.8, 0.01, b5=0.1, c5=2.0)  # |beta| > |alpha|
+
+
+# 16-bit (bfloat16) storage of fine fields: the form M_IRS takes with
+# irs_prec = DWF_BF16 (Sec. VI.E, Table "sloppy").  Against the oracle that
+# rounds the same stored fields, the only differences are rounding decisions
+# that FP32 (kernel) and FP64 (oracle) arithmetic take apart, each one unit in
+# the last bfloat16 place, so: norm-wise 2e-4 (vs ~2e-3 for one missing or
+# extra rounding: unit roundoff 2^-8 = 3.9e-3), and element-wise 2^-6 of the
+# value plus 2^-8 of the largest value.
+from oracle import precision as prc  # noqa: E402
+
+BF16_CASES = ["cfg1-4^4xLs8", "ragged-6x4x4x8xLs5", "phases-8x4x6x4xLs3", "ls12-4x4x6x4"]
+
+
+def _bf16_input(op, b):
+    """b rounded through complex64 and then the library's bfloat16 store."""
+    n64 = op.to_native(b, hd.DWF_C64)
+    nrhs = b.size // (op.Vh * op.Ls * 12)
+    return op.convert(n64, hd.DWF_BF16, hd.DWF_C64, nrhs), n64
+
+
+def _from_bf16(op, x16, nrhs=1):
+    return op.to_canonical(op.convert(x16, hd.DWF_C64, hd.DWF_BF16, nrhs), hd.DWF_C64, nrhs).cpu().numpy()
+
+
+def _check_bf16(got, want):
+    got = np.asarray(got, np.complex128)
+    nerr = np.sqrt(np.vdot(got - want, got - want).real / np.vdot(want, want).real)
+    d = np.abs(got - want)
+    bound = 2.0 ** -6 * np.abs(want) + 2.0 ** -8 * np.abs(want).max()
+    return nerr, bool(np.all(d <= bound))
+
+
+def test_bf16_convert_is_round_to_nearest_even():
+    banner("bf16 convert 6x4x4x8xLs5 nrhs=2")
+    dims, Ls, U, bc, mass, op, ref = _make("ragged-6x4x4x8xLs5")
+    b = synth.gaussian_half_field(dims, Ls, 17, nrhs=2).astype(np.complex64)
+    x16, _ = _bf16_input(op, b)
+    assert x16.dtype == torch.bfloat16 and x16.numel() == 2 * b.size
+    got = _from_bf16(op, x16, 2)
+    assert np.array_equal(got.astype(np.complex128), prc.round_bf16(b.astype(np.complex128)))
+    nrm = hd.dwf_norm2(op.h, x16, hd.DWF_BF16, 2)
+    want = [np.vdot(g, g).real for g in got.astype(np.complex128)]
+    assert np.allclose(nrm, want, rtol=1e-12, atol=0)
+    with pytest.raises(hd.HdcgError):
+        hd.dwf_convert(op.h, x16, hd.DWF_BF16, op.to_native(b[0]), hd.DWF_C128, 1)
+    op.close()
+
+
+@pytest.mark.parametrize("name", BF16_CASES)
+def test_bf16_mpc_and_H_against_rounding_oracle(name):
+    banner(f"mpc/H bf16 {name}")
+    dims, Ls, U, bc, mass, op, ref = _make(name)
+    b = synth.gaussian_half_field(dims, Ls, 18).astype(np.complex64)
+    x16, _ = _bf16_input(op, b)
+    xin = prc.round_bf16(b.astype(np.complex128))
+    for dag in (0, 1):
+        got = _from_bf16(op, op.mpc(x16, hd.DWF_BF16, dagger=dag))
+        want = prc.mpc_dag_bf16(ref, xin) if dag else prc.mpc_bf16(ref, xin)[0]
+        nerr, elem_ok = _check_bf16(got, want)
+        print(f"dagger={dag} norm-wise {nerr:.2e}", flush=True)
+        assert nerr < 2e-4 and elem_ok
+    got = _from_bf16(op, op.H(x16, hd.DWF_BF16))
+    nerr, elem_ok = _check_bf16(got, prc.H_bf16(ref, xin)[0])
+    print(f"H norm-wise {nerr:.2e}", flush=True)
+    assert nerr < 2e-4 and elem_ok
+    # and against the exact FP64 H: the error one rounding per stored field gives
+    exact = ref.H(xin)
+    e = np.sqrt(np.vdot(got - exact, got - exact).real / np.vdot(exact, exact).real)
+    assert 2.0 ** -8 / 10 < e < 4 * 2.0 ** -8
+    op.close()
+
+
+def test_bf16_mobius_H_within_rounding_bound():
+    banner("H bf16 mobius 8x8x4x8xLs16")
+    dims, Ls, b5, c5, mass, bc = MOBIUS["8x8x4x8xLs16-b1.5-c0.5"]
+    U = synth.gauge_field(dims, 0.6, 165)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass, bc, b5=b5, c5=c5)
+    ref = DWF(U, dims, Ls, 1.8, mass, bc, b=b5, c=c5)
+    b = synth.gaussian_half_field(dims, Ls, 166).astype(np.complex64)
+    x16, _ = _bf16_input(op, b)
+    xin = prc.round_bf16(b.astype(np.complex128))
+    got = _from_bf16(op, op.H(x16, hd.DWF_BF16))
+    exact = ref.H(xin)
+    e = np.sqrt(np.vdot(got - exact, got - exact).real / np.vdot(exact, exact).real)
+    print(f"mobius bf16 H norm-wise {e:.2e}", flush=True)
+    assert e < 4 * 2.0 ** -8
+    op.close()
+
+
+def test_bf16_full_size_H_config2():
+    """16^4 x Ls16 in the launch shape the benchmark times, against the
+    rounding oracle on every site."""
+    banner("H bf16 config 2 full size 16^4xLs16")
+    dims, Ls, M5, mass = (16, 16, 16, 16), 16, 1.8, 0.01
+    U = synth.gauge_field(dims, 0.7, 2001)
+    b = synth.gaussian_half_field(dims, Ls, 2100).astype(np.complex64)
+    op = hd.FineOperator(U, dims, Ls, M5, mass)
+    x16, _ = _bf16_input(op, b)
+    got = _from_bf16(op, op.H(x16, hd.DWF_BF16))
+    want = prc.H_bf16(DWF(U, dims, Ls, M5, mass), prc.round_bf16(b.astype(np.complex128)))[0]
+    nerr, elem_ok = _check_bf16(got, want)
+    print(f"config 2 bf16 H norm-wise {nerr:.2e}", flush=True)
+    assert nerr < 2e-4 and elem_ok
+    op.close()

@@ -194,6 +194,82 @@ def test_mirs(two_level):
     assert err < 2e-5
 
 
+def test_mirs_bf16_fields(two_level):
+    """M_IRS with 16-bit fields (irs_prec = DWF_BF16) against the oracle that
+    rounds the same fields.  One iteration: norm-wise 2e-4 (the kernel's FP32
+    coefficient moves a few rounding decisions by one bfloat16 unit).  Seven
+    iterations: such one-unit differences spread through H to every site
+    within a few iterations (rounding the oracle's values through float32
+    first already moves its own result by 2.3e-3 here), so the bar is the
+    rounding level itself, 2^-7 norm-wise; and against the FP64 M_IRS the
+    error lies between a tenth of the unit roundoff 2^-8 and 2e-2."""
+    from oracle import precision as prc
+
+    t = two_level
+    banner(f"M_IRS bf16 {t['name']}")
+    op, h = t["op"], t["h"]
+    r = synth.gaussian_half_field(t["dims"], t["Ls"], 341).astype(np.complex64)
+    r128 = r.astype(np.complex128)
+
+    def nrel(a, b):
+        return float(np.sqrt(np.vdot(a - b, a - b).real / np.vdot(b, b).real))
+
+    got = {}
+    try:
+        for n in (1, 7):
+            h.set_params(irs_prec=hd.DWF_BF16, n_irs=n)
+            out = op.new_field(hd.DWF_C64)
+            hd.hdcg_mirs(h.h, out, op.to_native(r, hd.DWF_C64))
+            got[n] = op.to_canonical(out, hd.DWF_C64).cpu().numpy().astype(np.complex128)
+    finally:
+        h.set_params(irs_prec=hd.DWF_C64, n_irs=7)
+    e1 = nrel(got[1], prc.m_irs_bf16(t["ref"], r128, 1, 1.0))
+    e7 = nrel(got[7], prc.m_irs_bf16(t["ref"], r128, 7, 1.0))
+    ex = nrel(got[7], ohdcg.m_irs(t["ref"], r128, 7, 1.0))
+    print(f"M_IRS bf16 vs rounding oracle: 1 iteration {e1:.2e}, 7 iterations {e7:.2e}; vs FP64 {ex:.2e}",
+          flush=True)
+    assert e1 < 2e-4
+    assert e7 < 2.0 ** -7
+    assert 2.0 ** -8 / 10 < ex < 2e-2
+
+
+def test_hdcg_solve_bf16_mirs_keeps_iterations():
+    """Table "sloppy": the solve with M_IRS on 16-bit fields reaches the same
+    FP64 residual with the complex64 run's A-DEF2 iteration count (within
+    two, or 10%)."""
+    name = "12^4xLs2-b4-n4"
+    banner(f"hdcg_solve irs_prec=bf16 {name}")
+    dims, Ls, block, nvec, eps, mass = GEOMS[name]
+    U = synth.gauge_field(dims, eps, 300)
+    raw = synth.gaussian_half_field(dims, Ls, 301, nrhs=nvec)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass)
+    h = hd.HDCG(op, block, raw)
+    ref = DWF(U, dims, Ls, 1.8, mass)
+    b = synth.gaussian_half_field(dims, Ls, 357)
+    its = {}
+    for prec in (hd.DWF_C64, hd.DWF_BF16):
+        h.set_params(irs_prec=prec)
+        x = op.new_field()
+        rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+        print(prec, st, flush=True)
+        assert rc == 0 and st["converged"] == 1
+        r = b - ref.H(op.to_canonical(x).cpu().numpy())
+        assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+        its[prec] = st["inner_iterations"]
+    assert abs(its[hd.DWF_BF16] - its[hd.DWF_C64]) <= max(2, 0.1 * its[hd.DWF_C64]), its
+    # invalid solve-phase parameters leave the handle as it was
+    for bad in (dict(irs_prec=hd.DWF_F16), dict(coarse_prec=hd.DWF_C128), dict(inner_tol=2.0)):
+        with pytest.raises(hd.HdcgError):
+            h.set_params(**bad)
+    # a 16-bit coarse matrix built on demand by hdcg_set_params
+    h.set_params(irs_prec=hd.DWF_C64, coarse_prec=hd.DWF_BF16)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    assert rc == 0 and st["converged"] == 1
+    h.close()
+    op.close()
+
+
 def test_hdcg_solve_small(two_level):
     t = two_level
     banner(f"hdcg_solve {t['name']}")
