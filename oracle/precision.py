@@ -43,6 +43,17 @@ def round_bf16(a):
     return np.ldexp(q, e - _SIG_BITS)
 
 
+def trunc_bf16(a):
+    """Each real and imaginary part of `a` (float32 values) cut to bfloat16 by
+    dropping the low 16 bits of its float32 word: the truncation of Sec. VI.E
+    (rounding toward zero)."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return trunc_bf16(a.real) + 1j * trunc_bf16(a.imag)
+    m, e = np.frexp(a.astype(np.float32).astype(np.float64))
+    return np.ldexp(np.trunc(np.ldexp(m, _SIG_BITS)), e - _SIG_BITS)
+
+
 def mpc_bf16(op, h):
     """M_pc h with the even half-field t and the result stored in 16 bits
     (returns the stored result and the unrounded one)."""
@@ -72,11 +83,14 @@ def _nrm(a):
     return float(np.vdot(a.ravel(), a.ravel()).real)
 
 
-def m_irs_bf16(op, b, niter, lam):
+def m_irs_bf16(op, b, niter, lam, trunc=False):
     """M_IRS(H, N, lambda) b (Sec. IV.C): exactly N CG iterations on
     H + lambda from zero, every vector stored in 16 bits.  The norms are
-    those of the values before they are stored; the scalars are FP64."""
-    r = round_bf16(b)
+    those of the values before they are stored; the scalars are FP64.
+    trunc: cut the CG's vectors by truncation (the paper's choice) instead of
+    rounding them (H keeps rounding)."""
+    rnd = trunc_bf16 if trunc else round_bf16
+    r = rnd(b)
     p = r.copy()
     x = np.zeros_like(r)
     rr = _nrm(r)
@@ -84,12 +98,12 @@ def m_irs_bf16(op, b, niter, lam):
     for _ in range(niter):
         w, pap = H_bf16(op, p)
         alpha = rr / (pap + lam * pp)
-        x = round_bf16(x + alpha * p)
+        x = rnd(x + alpha * p)
         r_new = r - alpha * (w + lam * p)
         rr_new = _nrm(r_new)
-        r = round_bf16(r_new)
+        r = rnd(r_new)
         p_new = r + (rr_new / rr) * p
         pp = _nrm(p_new)
-        p = round_bf16(p_new)
+        p = rnd(p_new)
         rr = rr_new
     return x

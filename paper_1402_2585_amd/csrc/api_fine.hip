@@ -461,8 +461,10 @@ int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_p
     HDCG_HIP(hipMemcpyAsync(dst, src, n * cbytes(src_prec), hipMemcpyDeviceToDevice, st));
     return DWF_OK;
   }
-  if (dst_prec == DWF_BF16) return launch_convert(static_cast<bf16c*>(dst), static_cast<const c64*>(src), n, st);
-  if (src_prec == DWF_BF16) return launch_convert(static_cast<c64*>(dst), static_cast<const bf16c*>(src), n, st);
+  if (dst_prec == DWF_BF16)
+    return launch_convert16(op, static_cast<bf16c*>(dst), static_cast<const c64*>(src), nrhs, st);
+  if (src_prec == DWF_BF16)
+    return launch_convert16(op, static_cast<c64*>(dst), static_cast<const bf16c*>(src), nrhs, st);
   if (dst_prec == DWF_C64)
     return launch_convert(static_cast<c64*>(dst), static_cast<const c128*>(src), n, st);
   return launch_convert(static_cast<c128*>(dst), static_cast<const c64*>(src), n, st);

@@ -101,9 +101,13 @@ int launch_xpay(dwf_op* op, cplx<R>* p, const cplx<R>* r, const double* num, con
 template <typename R>
 int launch_axpby(dwf_op* op, cplx<R>* y, const cplx<R>* x, double a, double b, size_t n,
                  hipStream_t stream);
-// dst = src between storage types (c128, c64, bf16c), rounded to nearest even
+// dst = src between c128 and c64 (n complex values), rounded to nearest even
 template <typename Td, typename Ts>
 int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream);
+// complex64 <-> 16-bit native fields (nrhs of them; the 16-bit native layout
+// keeps each site s-major), rounded to nearest even
+int launch_convert16(dwf_op* op, bf16c* dst, const c64* src, int nrhs, hipStream_t stream);
+int launch_convert16(dwf_op* op, c64* dst, const bf16c* src, int nrhs, hipStream_t stream);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
 void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)

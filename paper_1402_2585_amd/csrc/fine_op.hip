@@ -161,12 +161,80 @@ __device__ __forceinline__ void store_field(cplx<R>* p, cplx<R> v, bool nt) {
     *p = v;
   }
 }
-__device__ __forceinline__ void store_field(bf16c* p, cplx<float> v, bool nt) {
-  const unsigned w = (unsigned)f32_to_bf16(v.re) | ((unsigned)f32_to_bf16(v.im) << 16);
-  if (nt)
-    __builtin_nontemporal_store(w, reinterpret_cast<unsigned*>(p));
-  else
-    *reinterpret_cast<unsigned*>(p) = w;
+// 16-bit fields keep each site s-major, [s][spin*colour] (48 bytes per
+// (site, s)), where the wider types keep [spin*colour][s]: a lane, which owns
+// one s of one site, then moves its twelve values with three 16-byte
+// accesses instead of twelve 4-byte ones.
+template <typename T>
+constexpr bool kSMajor = std::is_same<T, bf16c>::value;
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ cplx<float> bf16_word(unsigned w) {
+  return cmk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+__device__ __forceinline__ unsigned bf16_pack(cplx<float> v) {
+  return (unsigned)f32_to_bf16(v.re) | ((unsigned)f32_to_bf16(v.im) << 16);
+}
+// the twelve values of one (site, s) row; p 16-byte aligned
+__device__ __forceinline__ void ld_row12(const bf16c* p, cplx<float> (&v)[12]) {
+  const u32x4* q = reinterpret_cast<const u32x4*>(p);
+  const u32x4 a = q[0], b = q[1], c = q[2];
+  v[0] = bf16_word(a.x), v[1] = bf16_word(a.y), v[2] = bf16_word(a.z), v[3] = bf16_word(a.w);
+  v[4] = bf16_word(b.x), v[5] = bf16_word(b.y), v[6] = bf16_word(b.z), v[7] = bf16_word(b.w);
+  v[8] = bf16_word(c.x), v[9] = bf16_word(c.y), v[10] = bf16_word(c.z), v[11] = bf16_word(c.w);
+}
+// six values (one chirality half of a row); p 8-byte aligned
+__device__ __forceinline__ void ld_half6(const bf16c* p, cplx<float>* v) {
+  const u32x2* q = reinterpret_cast<const u32x2*>(p);
+  const u32x2 a = q[0], b = q[1], c = q[2];
+  v[0] = bf16_word(a.x), v[1] = bf16_word(a.y), v[2] = bf16_word(b.x);
+  v[3] = bf16_word(b.y), v[4] = bf16_word(c.x), v[5] = bf16_word(c.y);
+}
+__device__ __forceinline__ void st_row12(bf16c* p, const cplx<float> (&v)[12], bool nt) {
+  u32x4* q = reinterpret_cast<u32x4*>(p);
+  u32x4 w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k].x = bf16_pack(v[4 * k]);
+    w[k].y = bf16_pack(v[4 * k + 1]);
+    w[k].z = bf16_pack(v[4 * k + 2]);
+    w[k].w = bf16_pack(v[4 * k + 3]);
+  }
+  if (nt) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(w[k], q + k);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[k] = w[k];
+  }
+}
+
+// complex64 [site][12][Ls] <-> 16-bit [site][Ls][12], one (site, s) row per
+// thread; rows = nrhs * Vh * Ls
+__global__ void to_bf16_kernel(bf16c* __restrict__ dst, const cplx<float>* __restrict__ src, size_t rows,
+                               int Ls) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t site = i / Ls;
+    const int s = (int)(i - site * Ls);
+    const cplx<float>* f = src + site * 12 * Ls + s;
+    cplx<float> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = f[c * Ls];
+    st_row12(dst + site * 12 * Ls + s * 12, v, false);
+  }
+}
+__global__ void from_bf16_kernel(cplx<float>* __restrict__ dst, const bf16c* __restrict__ src, size_t rows,
+                                 int Ls) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t site = i / Ls;
+    const int s = (int)(i - site * Ls);
+    cplx<float> v[12];
+    ld_row12(src + site * 12 * Ls + s * 12, v);
+    cplx<float>* f = dst + site * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) f[c * Ls] = v[c];
+  }
 }
 
 // acc += (1 + SG*gamma_mu) W psi from the projected half-spinor
@@ -369,9 +437,16 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
     }
     __syncthreads();
     if (active) {
-      T* o = out + (size_t)v * 12 * Ls + s;
+      if constexpr (kSMajor<T>) {
+        cplx<R> row[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) store_field(o + c * Ls, buf[(vloc * 12 + c) * ld + s], A.nt & 1);
+        for (int c = 0; c < 12; ++c) row[c] = buf[(vloc * 12 + c) * ld + s];
+        st_row12(out + (size_t)v * 12 * Ls + s * 12, row, A.nt & 1);
+      } else {
+        T* o = out + (size_t)v * 12 * Ls + s;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) store_field(o + c * Ls, buf[(vloc * 12 + c) * ld + s], A.nt & 1);
+      }
     }
   } else {
     // ---- M_5 c - 1/4 hop (or M_5^+ c - 1/4 hop^+) --------------------------
@@ -400,7 +475,28 @@ __device__ __forceinline__ void hop_epilogue(const cplx<R> (&acc)[12], bool acti
       }
     }
     double nrm = 0.0;
-    if (active) {
+    if constexpr (kSMajor<T>) {
+      if (active) {
+        const T* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
+        const R al = (R)A.alpha, be = (R)A.beta, m = (R)A.mass, q = (R)0.25;
+        const int s_dn = (s > 0) ? s - 1 : Ls - 1, s_up = (s < Ls - 1) ? s + 1 : 0;
+        const R f_dn = (s > 0) ? be : -m * be, f_up = (s < Ls - 1) ? be : -m * be;
+        // the P+ half (c < 6) couples to s-1 and the P- half to s+1 (swapped
+        // in the adjoint), as in the branch below
+        const int sa = DAG ? s_up : s_dn, sb = DAG ? s_dn : s_up;
+        const R fa = DAG ? f_up : f_dn, fb = DAG ? f_dn : f_up;
+        cplx<R> x[12], y[12], r[12];
+        ld_row12(cen + s * 12, x);
+        ld_half6(cen + sa * 12, y);
+        ld_half6(cen + sb * 12 + 6, y + 6);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          r[c] = al * x[c] + (c < 6 ? fa : fb) * y[c] - q * hop[c];
+          nrm += (double)r[c].re * (double)r[c].re + (double)r[c].im * (double)r[c].im;
+        }
+        st_row12(out + (size_t)v * 12 * Ls + s * 12, r, A.nt & 1);
+      }
+    } else if (active) {
       const T* cen = center + rhs * A.field + (size_t)v * 12 * Ls;
       T* o = out + (size_t)v * 12 * Ls + s;
       const R al = (R)A.alpha, be = (R)A.beta, m = (R)A.mass, q = (R)0.25;
@@ -472,9 +568,13 @@ __device__ __forceinline__ void load_dirs(cplx<typename St<T>::R> (&psi)[N][12],
                                           const int (&nb)[8], size_t col, int s, int Ls) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const T* p = in + (size_t)nb[D0 + k] * col + s;
+    if constexpr (kSMajor<T>) {
+      ld_row12(in + (size_t)nb[D0 + k] * col + s * 12, psi[k]);
+    } else {
+      const T* p = in + (size_t)nb[D0 + k] * col + s;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[k][c] = St<T>::ld(p + c * Ls);
+      for (int c = 0; c < 12; ++c) psi[k][c] = St<T>::ld(p + c * Ls);
+    }
   }
 }
 
@@ -490,11 +590,20 @@ __device__ __forceinline__ void load_dirs_c5(cplx<R> (&psi)[N][12], const T* __r
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const T* p = in + (size_t)nb[D0 + k] * col;
+    if constexpr (kSMajor<T>) {
+      cplx<R> x[12], y[12];
+      ld_row12(p + s * 12, x);
+      ld_half6(p + s_dn * 12, y);
+      ld_half6(p + s_up * 12 + 6, y + 6);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      const cplx<R> x = St<T>::ld(p + c * Ls + s);
-      const cplx<R> y = St<T>::ld(c < 6 ? p + c * Ls + s_dn : p + c * Ls + s_up);
-      psi[k][c] = b5 * x + (c < 6 ? w_dn : w_up) * y;
+      for (int c = 0; c < 12; ++c) psi[k][c] = b5 * x[c] + (c < 6 ? w_dn : w_up) * y[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const cplx<R> x = St<T>::ld(p + c * Ls + s);
+        const cplx<R> y = St<T>::ld(c < 6 ? p + c * Ls + s_dn : p + c * Ls + s_up);
+        psi[k][c] = b5 * x + (c < 6 ? w_dn : w_up) * y;
+      }
     }
   }
 }
@@ -824,6 +933,8 @@ template <typename R, typename T>
 int launch_mpc(dwf_op* op, T* out, const T* in, bool dagger, int nrhs, hipStream_t stream,
                double* norm_result) {
   const int prec = std::is_same<T, bf16c>::value ? DWF_BF16 : prec_of<R>();
+  if (kSMajor<T> && (!aligned16(out) || !aligned16(in)))
+    return fail(DWF_ERR_ARG, "16-bit fields must be 16-byte aligned");
   HDCG_TRY(ensure_tmp(op, prec, nrhs));
   T* te = op->tmp[tmp_index(prec)][0].as<T>();
   // stage 1: t_e = M_5^-1 Dh_eo in    (adjoint: M_5^-+ Dh^+_eo in)
@@ -898,6 +1009,24 @@ int launch_axpby(dwf_op*, cplx<R>* y, const cplx<R>* x, double a, double b, size
   return DWF_OK;
 }
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+int launch_convert16(dwf_op* op, bf16c* dst, const c64* src, int nrhs, hipStream_t stream) {
+  if (!aligned16(dst)) return fail(DWF_ERR_ARG, "16-bit fields must be 16-byte aligned");
+  const size_t rows = (size_t)nrhs * op->g.Vh * op->g.Ls;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(red_blocks(rows * 12)), dim3(256), 0, stream, dst, src, rows, op->g.Ls);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+int launch_convert16(dwf_op* op, c64* dst, const bf16c* src, int nrhs, hipStream_t stream) {
+  if (!aligned16(src)) return fail(DWF_ERR_ARG, "16-bit fields must be 16-byte aligned");
+  const size_t rows = (size_t)nrhs * op->g.Vh * op->g.Ls;
+  hipLaunchKernelGGL(from_bf16_kernel, dim3(red_blocks(rows * 12)), dim3(256), 0, stream, dst, src, rows,
+                     op->g.Ls);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
 template <typename Td, typename Ts>
 int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream) {
   hipLaunchKernelGGL((convert_kernel<Td, Ts>), dim3(red_blocks(n)), dim3(256), 0, stream, dst, src, n);
@@ -924,8 +1053,7 @@ template int launch_mpcdagmpc<float, bf16c>(dwf_op*, bf16c*, const bf16c*, int, 
 template int launch_norm2<float, bf16c>(dwf_op*, const bf16c*, int, double*, hipStream_t);
 template int launch_convert<c128, c64>(c128*, const c64*, size_t, hipStream_t);
 template int launch_convert<c64, c128>(c64*, const c128*, size_t, hipStream_t);
-template int launch_convert<bf16c, c64>(bf16c*, const c64*, size_t, hipStream_t);
-template int launch_convert<c64, bf16c>(c64*, const bf16c*, size_t, hipStream_t);
+
 
 // ------------------------------------------------------------ host setup ---
 int import_gauge(dwf_op* op, const void* gauge_c128, hipStream_t stream) {

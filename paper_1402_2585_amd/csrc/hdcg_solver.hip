@@ -169,7 +169,7 @@ int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixe
   double* pap = slot(h, S_PAP);
   double* pp = lam != 0.0 ? slot(h, S_PP) : nullptr;
   HDCG_TRY(b_zero(x, n * nr, st));
-  HDCG_TRY(launch_convert(r, b, n * nr, st));
+  HDCG_TRY(launch_convert16(op, r, b, nr, st));
   HDCG_HIP(hipMemcpyAsync(p, r, n * nr * sizeof(bf16c), hipMemcpyDeviceToDevice, st));
   HDCG_TRY(b_norm2(red, r, n, nr, rr[0], st));
   if (pp) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -180,7 +180,7 @@ int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixe
     HDCG_TRY(b_update(red, x, r, p, w, n, nr, cur, pap, pp, lam, nxt, st));
     HDCG_TRY(b_xpay(red, p, r, n, nr, nxt, cur, pp, st));
   }
-  return launch_convert(x_out, x, n * nr, st);
+  return launch_convert16(op, x_out, x, nr, st);
 }
 
 // M_IRS in the storage precision the parameters select

@@ -10,8 +10,10 @@
   m_irs_bf16 is its FP64 M_IRS (so no term of either is dropped);
 - with the rounding in place, the error of H_bf16 sits at the level one
   bfloat16 rounding per stored field gives (so the rounding does happen);
-- Table "sloppy": M_IRS in 16 bits leaves the A-DEF2 iteration count as in
-  FP64 (within one iteration) on a small two-level problem.
+- Table "sloppy": M_IRS in 16 bits, rounded or truncated as the paper does,
+  leaves the A-DEF2 iteration count as in FP64 (within one iteration) on a
+  small two-level problem;
+- truncation equals clearing the low 16 bits of the float32 word.
 """
 import numpy as np
 import pytest
@@ -63,6 +65,15 @@ def test_round_bf16_matches_bit_pattern_construction():
     assert np.array_equal(prc.round_bf16(got), got)
 
 
+def test_trunc_bf16_drops_low_bits():
+    rng = np.random.default_rng(6)
+    f = (rng.standard_normal(100000) * np.exp(rng.uniform(-20, 20, 100000))).astype(np.float32)
+    want = (f.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    got = prc.trunc_bf16(f.astype(np.float64))
+    assert np.array_equal(got, want)
+    assert np.all(np.abs(got) <= np.abs(f)) and np.abs(got - f).max() > 0
+
+
 @pytest.fixture(scope="module")
 def op_small():
     dims, Ls = (4, 4, 4, 8), 6
@@ -104,8 +115,12 @@ def test_sloppy_mirs_keeps_iteration_count():
     tl = hdcg.TwoLevel(op, phi, sob, C, crs.build_fourier(op, phi, sob, C), coarse_tol=0.04)
     b = synth.gaussian_half_field(dims, Ls, 80)
     its = {}
-    for name, fn in (("fp64", None), ("bf16", prc.m_irs_bf16)):
+
+    def truncating(op_, r_, n_, lam_):
+        return prc.m_irs_bf16(op_, r_, n_, lam_, trunc=True)
+
+    for name, fn in (("fp64", None), ("bf16", prc.m_irs_bf16), ("bf16-trunc", truncating)):
         x, it, rel = hdcg.gpcg(tl, b, n_irs=4, tol=1e-5, m_irs_fn=fn)
         assert rel <= 1e-5 and np.sqrt(norm2(b - op.H(x)) / norm2(b)) <= 2e-5
         its[name] = it
-    assert abs(its["bf16"] - its["fp64"]) <= 1, its
+    assert abs(its["bf16"] - its["fp64"]) <= 1 and abs(its["bf16-trunc"] - its["fp64"]) <= 1, its
