@@ -287,7 +287,8 @@ def main():
                    "lattice": list(dims), "Ls": Ls, "nrhs": 1},
         "gflops": round(fl / (ms128 * 1e-3) / 1e9, 1),
         "c64": {"gbs": round(gbs64, 1), "ms_per_application": round(ms64, 5),
-                "gflops": round(fl / (ms64 * 1e-3) / 1e9, 1), "frac_of_hbm_peak": round(gbs64 / HBM_PEAK_GBS, 3)},
+                "gflops": round(fl / (ms64 * 1e-3) / 1e9, 1), "frac_of_hbm_peak": round(gbs64 / HBM_PEAK_GBS, 3),
+                "traffic": traffic_from_profiles("c64")},
         "roofline": {
             "kernel": "hop_kernel (4 launches per application; per-launch average)",
             "bound": "hbm",
@@ -315,7 +316,8 @@ def main():
         by16 = algorithmic_bytes_H(dims, Ls, 1, 4, 8)
         out["bf16"] = {"gbs": round(by16 / (ms16 * 1e-3) / 1e9, 1), "ms_per_application": round(ms16, 5),
                        "speedup_vs_c64": round(ms64 / ms16, 3),
-                       "frac_of_hbm_peak": round(by16 / (ms16 * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+                       "frac_of_hbm_peak": round(by16 / (ms16 * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                       "traffic": traffic_from_profiles("bf16")}
         out["mobius"] = {"b5": 1.5, "c5": 0.5,
                          "c128": {"gbs": round(by128 / (msm * 1e-3) / 1e9, 1), "ms_per_application": round(msm, 5)},
                          "c64": {"gbs": round(by64 / (msm64 * 1e-3) / 1e9, 1), "ms_per_application": round(msm64, 5)}}

@@ -3,7 +3,7 @@
 // not depend on the link values), or runs a plain copy kernel of known size
 // to calibrate the FETCH_SIZE / WRITE_SIZE counters.
 //
-//   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64> <reps> [nrhs]
+//   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64|bf16> <reps> [nrhs]
 //   hdcg_prof copy|read <MiB> <reps> [grid]
 #include <hip/hip_runtime.h>
 
@@ -129,7 +129,7 @@ int main(int argc, char** argv) {
   if (argc < 9) return 2;
   int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
   const int Ls = std::atoi(argv[6]);
-  const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : DWF_C128;
+  const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : (!std::strcmp(argv[7], "bf16") ? DWF_BF16 : DWF_C128);
   const int reps = std::atoi(argv[8]);
   const int nrhs = argc > 9 ? std::atoi(argv[9]) : 1;
   const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
