@@ -168,6 +168,21 @@ int cg_solve(dwf_op_t op, void* x, const void* b, int nrhs, double tol, int maxi
 int cg_solve_mixed(dwf_op_t op, void* x, const void* b, int nrhs, double tol, double inner_tol, int maxiter,
                    struct dwf_solve_stats* st, void* stream);
 
+/* Multi-shift CG (Sec. IV.B: the rational filter of the subspace generation
+ * is one multi-shift solve): (H + shifts[j]) x_j = b for j < nshift (1..8)
+ * from the Krylov space of the smallest shift, shifts[0]; the other shifts'
+ * residuals are zeta_j r with zeta_j from the three-term recurrence of the
+ * CG coefficients.  All in complex128.  x: device, nshift * nrhs native
+ * complex128 fields, x[j][rhs], overwritten (the solve starts from zero);
+ * b: nrhs native complex128 fields; shifts: host.  Stops when the base
+ * system's recursive residual |r| <= tol |b| for every right-hand side (the
+ * other shifts are then closer still).  st (nullable): iterations, matmuls,
+ * and in true_residual the base system's last checked recursive relative
+ * residual.  Synchronises; DWF_NOT_CONVERGED at maxiter; DWF_ERR_ARG unless
+ * shifts[0] <= every shift, 1 <= nshift <= 8, tol > 0. */
+int dwf_multishift_cg(dwf_op_t op, void* x, const void* b, int nrhs, const double* shifts, int nshift,
+                      double tol, int maxiter, struct dwf_solve_stats* st, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Hierarchically deflated CG: blocked subspace (Sec. II), little Dirac
  * operator (Sec. V.A.1), the A-DEF2 solver (Sec. IV.E, Table "algos").     */
@@ -192,6 +207,17 @@ struct hdcg_params {
   int irs_prec;       /* storage of the M_IRS fields: DWF_C64 (default) or DWF_BF16 (16-bit
                          fields, FP32 arithmetic, FP64 norms; the one-GPU form of the
                          16-bit M_IRS communication of Sec. VI.E, Table "sloppy") */
+  int subspace_gen;   /* 0 (default): the given vectors, then n_ii inverse-iteration steps;
+                         1: first the fourth-order rational filter of Sec. IV.B (equation
+                         "ratfilt"), prod_j (H + rat_lo + j rat_eps)^-1, j = 0..3, by one
+                         complex128 multi-shift CG and the partial-fraction sum, each vector
+                         then normalised (inverse iteration follows when n_ii > 0) */
+  double rat_lo;      /* filter threshold lambda, default 3e-4 */
+  double rat_eps;     /* filter shift spacing epsilon, default 1e-4 (lambda / 3) */
+  double rat_tol;     /* multi-shift residual, default 1e-6 */
+  int rat_maxiter;    /* multi-shift iteration cap, default 10000 */
+  int wall_noise;     /* 1: keep only the physical wall components of the given vectors
+                         (P- at s = 0, P+ at s = Ls - 1, Sec. IV.B) before filtering */
 };
 
 struct hdcg_stats {

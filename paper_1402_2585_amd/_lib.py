@@ -44,7 +44,9 @@ class HdcgParams(C.Structure):
                 ("coarse_tol", C.c_double), ("coarse_maxiter", C.c_int), ("flexible", C.c_int),
                 ("inner_tol", C.c_double), ("inner_maxiter", C.c_int), ("outer_maxiter", C.c_int),
                 ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int),
-                ("irs_prec", C.c_int)]
+                ("irs_prec", C.c_int), ("subspace_gen", C.c_int), ("rat_lo", C.c_double),
+                ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
+                ("wall_noise", C.c_int)]
 
 
 class HdcgStats(C.Structure):
@@ -86,6 +88,7 @@ def load():
         "dwf_xpay": (i, [vp, vp, vp, dp, i, i, vp]),
         "cg_solve": (i, [vp, vp, vp, i, d, i, C.POINTER(SolveStats), vp]),
         "cg_solve_mixed": (i, [vp, vp, vp, i, d, d, i, C.POINTER(SolveStats), vp]),
+        "dwf_multishift_cg": (i, [vp, vp, vp, i, dp, i, d, i, C.POINTER(SolveStats), vp]),
         "dwf_last_error": (C.c_char_p, []),
         "hdcg_default_params": (None, [C.POINTER(HdcgParams)]),
         "hdcg_setup": (i, [C.POINTER(vp), vp, C.POINTER(C.c_int * 4), i, vp, C.POINTER(HdcgParams), vp]),
@@ -225,6 +228,14 @@ def cg_solve_mixed(op, x, b, nrhs=1, tol=1e-8, inner_tol=1e-5, maxiter=100000, s
     st = SolveStats()
     rc = _check(load().cg_solve_mixed(op, _ptr(x), _ptr(b), int(nrhs), float(tol), float(inner_tol), int(maxiter),
                                       C.byref(st), _stream(stream)), allow_soft=True)
+    return rc, st.as_dict()
+
+
+def dwf_multishift_cg(op, x, b, shifts, nrhs=1, tol=1e-10, maxiter=100000, stream=None):
+    st = SolveStats()
+    sh = _dbl(shifts, len(shifts))
+    rc = _check(load().dwf_multishift_cg(op, _ptr(x), _ptr(b), int(nrhs), sh, len(shifts), float(tol),
+                                         int(maxiter), C.byref(st), _stream(stream)), allow_soft=True)
     return rc, st.as_dict()
 
 

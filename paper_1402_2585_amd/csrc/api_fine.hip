@@ -379,7 +379,7 @@ int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, doubl
       rc = fail(DWF_ERR_HIP, "copy of the M_5^-1 table failed");
       break;
     }
-    if (hipHostMalloc((void**)&op->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&op->pinned, kPinnedDoubles * sizeof(double), hipHostMallocDefault) != hipSuccess) {
       op->pinned = nullptr;
       rc = fail(DWF_ERR_HIP, "pinned host allocation failed");
       break;
@@ -414,6 +414,7 @@ int dwf_destroy(dwf_op_t op) {
   op->red.partials.release();
   op->hop_part.release();
   for (auto& m : op->mgw) m.release();
+  for (auto& m : op->msw) m.release();
   op->red.counters.release();
   op->red.results.release();
   if (op->pinned) (void)hipHostFree(op->pinned);
@@ -468,6 +469,29 @@ int dwf_convert(dwf_op_t op, void* dst, int dst_prec, const void* src, int src_p
   if (dst_prec == DWF_C64)
     return launch_convert(static_cast<c64*>(dst), static_cast<const c128*>(src), n, st);
   return launch_convert(static_cast<c128*>(dst), static_cast<const c64*>(src), n, st);
+}
+
+int dwf_multishift_cg(dwf_op_t op, void* x, const void* b, int nrhs, const double* shifts, int nshift, double tol,
+                      int maxiter, struct dwf_solve_stats* st, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_nrhs(nrhs));
+  if (!x || !b || !shifts || x == b) return fail(DWF_ERR_ARG, "dwf_multishift_cg needs x, b (distinct) and shifts");
+  auto s = static_cast<hipStream_t>(stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  int it = 0;
+  double res = 0.0;
+  const int rc = multishift_cg(op, static_cast<c128*>(x), static_cast<const c128*>(b), nrhs, shifts, nshift, tol,
+                               maxiter, &it, &res, s);
+  if (rc < 0) return rc;
+  if (st) {
+    st->iterations = it;
+    st->restarts = 0;
+    st->converged = rc == DWF_OK;
+    st->true_residual = res;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st->matmuls = (double)it * nrhs;
+  }
+  return rc;
 }
 
 int mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int dagger, int nrhs, void* stream) {

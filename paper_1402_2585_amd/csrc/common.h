@@ -202,6 +202,7 @@ struct DevBuf {
 // output, the last workgroup to finish (ticket counter) sums the partials in
 // a fixed order and resets the counter.
 constexpr int kMaxPartials = 1 << 16;  // partial slots per reduced quantity
+constexpr int kPinnedDoubles = 1024;   // host pinned scalars of an operator handle
 constexpr int kRedThreads = 256;
 
 struct Reducer {

@@ -52,6 +52,7 @@ struct dwf_op {
   hdk::DevBuf tmp[3][3];          // [c128, c64, bf16][t_e, chi, s_e] work fields
   hdk::DevBuf cgw[4];             // CG work fields (c128): r, p, w, spare
   hdk::DevBuf mgw[5];             // mixed-precision CG work fields (c64): r, p, w, source, correction
+  hdk::DevBuf msw[4];             // multi-shift CG: p_j (c128), r, w, device scalars
   hdk::Reducer red;
   hdk::DevBuf hop_part;           // fused-norm partials of the hop stage: [rhs][workgroups]
   struct {
@@ -64,7 +65,7 @@ struct dwf_op {
     int phases = 4;               // neighbour-load phases per stage (2 or 4)
   } tune;
   hdk::DevBuf host_pinned_dummy;
-  double* pinned = nullptr;        // host pinned scalars
+  double* pinned = nullptr;        // host pinned scalars [kPinnedDoubles]
   int device = 0;
   size_t site_elems() const { return (size_t)12 * g.Ls; }
   size_t field_elems(int nrhs) const { return (size_t)nrhs * g.Vh * 12 * g.Ls; }
@@ -101,6 +102,19 @@ int launch_xpay(dwf_op* op, cplx<R>* p, const cplx<R>* r, const double* num, con
 template <typename R>
 int launch_axpby(dwf_op* op, cplx<R>* y, const cplx<R>* x, double a, double b, size_t n,
                  hipStream_t stream);
+// Multi-shift CG (complex128): (H + shifts[j]) x_j = b for j < ns (<= 8),
+// shifts[0] the smallest; x: [ns][nrhs] fields, overwritten (starts from 0).
+// Stops when |r| <= tol |b| for the base system of every right-hand side;
+// *iters = iterations run, *resid = max relative base residual (the value
+// checked last).  Synchronises; DWF_NOT_CONVERGED at maxiter.
+int multishift_cg(dwf_op* op, c128* x, const c128* b, int nrhs, const double* shifts, int ns, double tol,
+                  int maxiter, int* iters, double* resid, hipStream_t stream);
+// out = sum_j coef[j] x_j over nrhs fields (x: [ns][nrhs] fields)
+int multishift_combine(dwf_op* op, c128* out, const c128* x, int nrhs, const double* coef, int ns,
+                       hipStream_t stream);
+// keep only P- at s = 0 and P+ at s = Ls - 1 (the physical wall components)
+int wall_mask(dwf_op* op, c128* f, int nrhs, hipStream_t stream);
+
 // dst = src between c128 and c64 (n complex values), rounded to nearest even
 template <typename Td, typename Ts>
 int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream);

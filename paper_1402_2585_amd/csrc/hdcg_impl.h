@@ -59,6 +59,10 @@ struct hdcg {
     int build_batch = 8;
     int coarse_prec = DWF_C64;  // storage of A inside Q: C64 (VALU), BF16 / F16 (MFMA)
     int irs_prec = DWF_C64;     // storage of the M_IRS fields: C64 or BF16
+    int subspace_gen = 0;       // 1: rational filter (multi-shift) before inverse iteration
+    double rat_lo = 3e-4, rat_eps = 1e-4, rat_tol = 1e-6;
+    int rat_maxiter = 10000;
+    int wall_noise = 0;         // keep only the physical wall components of the noise
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;

@@ -403,6 +403,12 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->coarse_prec = DWF_C64;
   p->verbose = 0;
   p->irs_prec = DWF_C64;
+  p->subspace_gen = 0;
+  p->rat_lo = 3e-4;
+  p->rat_eps = 1e-4;
+  p->rat_tol = 1e-6;
+  p->rat_maxiter = 10000;
+  p->wall_noise = 0;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -450,6 +456,47 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   DevBuf work;  // canonical c128 copy of the vectors
   HDCG_TRY(work.ensure(fe * nv * sizeof(c128)));
   HDCG_HIP(hipMemcpyAsync(work.ptr, vectors, fe * nv * sizeof(c128), hipMemcpyDeviceToDevice, st));
+  if (h->prm.subspace_gen == 1) {
+    // rational filter, Sec. IV.B: prod_j (H + lo + j eps)^-1 eta as
+    // sum_j c_j (H + s_j)^-1 eta, c_j = prod_{i != j} 1 / (s_i - s_j), the
+    // shifted solutions from one multi-shift CG (groups of up to 8 vectors)
+    const int G = std::min(nv, 8);
+    double sh[4], cf[4];
+    for (int j = 0; j < 4; ++j) sh[j] = h->prm.rat_lo + j * h->prm.rat_eps;
+    for (int j = 0; j < 4; ++j) {
+      double d = 1.0;
+      for (int i = 0; i < 4; ++i)
+        if (i != j) d *= sh[i] - sh[j];
+      cf[j] = 1.0 / d;
+    }
+    DevBuf xs;
+    HDCG_TRY(xs.ensure(fe * 4 * G * sizeof(c128)));
+    HDCG_TRY(h->fw128[0].ensure(fe * G * sizeof(c128)));
+    HDCG_TRY(h->fw128[1].ensure(fe * G * sizeof(c128)));
+    c128* v128 = h->fw128[0].as<c128>();
+    c128* f128 = h->fw128[1].as<c128>();
+    double* nrm = slot(h, S_ORR);
+    for (int k0 = 0; k0 < nv; k0 += G) {
+      const int g = std::min(G, nv - k0);
+      c128* can = work.as<c128>() + (size_t)k0 * fe;
+      HDCG_TRY(dwf_import(op, v128, can, DWF_C128, g, st));
+      if (h->prm.wall_noise) HDCG_TRY(wall_mask(op, v128, g, st));
+      int it = 0;
+      double res = 0.0;
+      HDCG_TRY(multishift_cg(op, xs.as<c128>(), v128, g, sh, 4, h->prm.rat_tol, h->prm.rat_maxiter, &it, &res, st));
+      h->setup_matmuls += (long long)it * g;
+      HDCG_TRY(multishift_combine(op, f128, xs.as<c128>(), g, cf, 4, st));
+      HDCG_TRY(b_norm2<double>(red_of(op), f128, fe, g, nrm, st));
+      HDCG_TRY(b_scale_copy<double, double>(v128, f128, nrm, true, fe, g, st));  // normalise
+      HDCG_TRY(dwf_export(op, can, v128, DWF_C128, g, st));
+      if (h->prm.verbose) {
+        HDCG_HIP(hipStreamSynchronize(st));
+        std::fprintf(stderr, "[hdcg_setup] rational filter: vectors %d-%d done, %d multi-shift iterations (residual %.1e)\n",
+                     k0, k0 + g - 1, it, res);
+        std::fflush(stderr);
+      }
+    }
+  }
   if (h->prm.n_ii > 0) {
     const int G = std::min(nv, 8);
     HDCG_TRY(h->fw128[0].ensure(fe * G * sizeof(c128)));
@@ -624,12 +671,25 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.coarse_prec = p->coarse_prec;
     h->prm.verbose = p->verbose;
     h->prm.irs_prec = p->irs_prec;
+    h->prm.subspace_gen = p->subspace_gen;
+    h->prm.rat_lo = p->rat_lo;
+    h->prm.rat_eps = p->rat_eps;
+    h->prm.rat_tol = p->rat_tol;
+    h->prm.rat_maxiter = p->rat_maxiter;
+    h->prm.wall_noise = p->wall_noise;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
   if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec); rc < 0) {
     delete h;
     return rc;
+  }
+  if ((h->prm.subspace_gen != 0 && h->prm.subspace_gen != 1) ||
+      (h->prm.subspace_gen == 1 &&
+       !(h->prm.rat_lo > 0.0 && h->prm.rat_eps > 0.0 && h->prm.rat_tol > 0.0 && h->prm.rat_maxiter >= 1))) {
+    delete h;
+    return fail(DWF_ERR_ARG, "subspace_gen must be 0 or 1; the rational filter needs rat_lo, rat_eps, rat_tol > 0 "
+                             "and rat_maxiter >= 1");
   }
   if (hipHostMalloc((void**)&h->pinned, 64 * 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     h->pinned = nullptr;
