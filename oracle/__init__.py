@@ -17,4 +17,6 @@ coarse    little Dirac operator: brute force and the Fourier trick, coarse CG
 hdcg      Q, P_L, P_R, M_IRS, generalised PCG (A-DEF2, BNN), defect correction
 precision 16-bit (bfloat16) rounding; H and M_IRS with 16-bit field storage
 subspace  rational-filter subspace: multi-shift CG, partial fractions, wall noise
+ldop      second deflation level of the coarse operator: global vectors, the
+          pre-diagonalised third level, deflated CG
 """
