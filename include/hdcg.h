@@ -218,6 +218,8 @@ struct hdcg_params {
   int rat_maxiter;    /* multi-shift iteration cap, default 10000 */
   int wall_noise;     /* 1: keep only the physical wall components of the given vectors
                          (P- at s = 0, P+ at s = Ls - 1, Sec. IV.B) before filtering */
+  int ldop_defl;      /* 1 (default): once hdcg_ldop_setup has built the second deflation
+                         level, every coarse solve is deflated CG on it (Sec. V.B); 0: plain */
 };
 
 struct hdcg_stats {
@@ -285,9 +287,32 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
  * are native complex64 fields; asynchronous. */
 int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream);
 
+/* Second deflation level of the little Dirac operator (Sec. V.B, "Little
+ * Dirac operator deflation") and the pre-diagonalised third level.  Global
+ * coarse vectors, no further blocking: the Nvec free ones w_k[a][j] =
+ * delta_jk / sqrt(Nc), and n_extra more from noise_c128 (device, n_extra
+ * coarse vectors c[k][a][j] complex128 drawn by the caller), each taken
+ * through n_steps of v <- (A + shift)^-1 v / |v| (complex128 coarse CG to
+ * relative residual tol; the paper: three steps, 1e-7).  They are
+ * orthonormalised (Cholesky-QR twice, FP64), E = W^+ A W is diagonalised
+ * (E = U D U^+) and Z = W U, A Z are kept; every later coarse solve
+ * (hdcg_coarse_solve, the Q of hdcg_solve) is then deflated CG:
+ * x0 = Z D^-1 Z^+ b, search directions p = r + beta p - Z D^-1 (AZ)^+ r
+ * (params.ldop_defl = 0 turns it off).  Replaces an earlier second level.
+ * Synchronises.  DWF_ERR_ARG: n_extra < 0, Nvec + n_extra > 1024 or more than
+ * the coarse unknowns, tol <= 0, shift < 0; DWF_ERR_NUMERIC: dependent
+ * vectors or A not positive on them. */
+int hdcg_ldop_setup(hdcg_t h, int n_extra, const void* noise_c128, double shift, int n_steps, double tol,
+                    void* stream);
+/* The second level for parity checks: *n_global (host) = number of global
+ * vectors (0 before hdcg_ldop_setup); Z_c128 (device, nullable): the
+ * orthonormal eigenbasis Z[k][a][j] complex128 of E, ascending eigenvalue;
+ * D_host (host, nullable): the eigenvalues D.  Synchronises. */
+int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void* stream);
+
 /* Replace the solve-phase parameters of a built handle (n_irs, lambda_irs,
  * coarse_tol, coarse_maxiter, flexible, inner_tol, inner_maxiter,
- * outer_maxiter, coarse_prec, irs_prec); the setup-phase fields of *p are
+ * outer_maxiter, coarse_prec, irs_prec, ldop_defl); the setup-phase fields of *p are
  * ignored.  Builds the 16-bit copy of A when coarse_prec asks for one not yet
  * built.  Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle
  * is then unchanged). */

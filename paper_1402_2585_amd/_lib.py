@@ -46,7 +46,7 @@ class HdcgParams(C.Structure):
                 ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int),
                 ("irs_prec", C.c_int), ("subspace_gen", C.c_int), ("rat_lo", C.c_double),
                 ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
-                ("wall_noise", C.c_int)]
+                ("wall_noise", C.c_int), ("ldop_defl", C.c_int)]
 
 
 class HdcgStats(C.Structure):
@@ -100,6 +100,8 @@ def load():
         "hdcg_coarse_solve": (i, [vp, vp, vp, i, i, d, i, C.POINTER(C.c_int), vp]),
         "hdcg_mirs": (i, [vp, vp, vp, i, vp]),
         "hdcg_set_params": (i, [vp, C.POINTER(HdcgParams), vp]),
+        "hdcg_ldop_setup": (i, [vp, i, vp, d, i, d, vp]),
+        "hdcg_export_ldop": (i, [vp, C.POINTER(C.c_int), vp, dp, vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -298,6 +300,20 @@ def hdcg_mirs(h, out, inp, nrhs=1, stream=None):
 
 def hdcg_set_params(h, params, stream=None):
     _check(load().hdcg_set_params(h, C.byref(params), _stream(stream)))
+
+
+def hdcg_ldop_setup(h, n_extra, noise=None, shift=0.0, n_steps=3, tol=1e-7, stream=None):
+    _check(load().hdcg_ldop_setup(h, int(n_extra), _ptr(noise), float(shift), int(n_steps), float(tol),
+                                  _stream(stream)))
+
+
+def hdcg_export_ldop(h, Z=None, stream=None):
+    """Returns (n_global, D); fills Z (device complex128 [n][Nc][Nvec]) when given."""
+    n = C.c_int()
+    load().hdcg_export_ldop(h, C.byref(n), None, None, _stream(stream))
+    D = (C.c_double * max(n.value, 1))()
+    _check(load().hdcg_export_ldop(h, C.byref(n), _ptr(Z), D, _stream(stream)))
+    return n.value, np.array(D[:n.value])
 
 
 def hdcg_export_coarse(h, out, stream=None):

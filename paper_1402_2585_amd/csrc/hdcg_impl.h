@@ -12,6 +12,8 @@
 // consecutive threads on consecutive j.
 #pragma once
 
+#include <vector>
+
 #include "blas.h"
 #include "fine_op.h"
 
@@ -43,6 +45,14 @@ struct hdcg {
   hdk::DevBuf pcg_part;             // persistent coarse CG: per-workgroup partial sums
   hdk::DevBuf pcg_state;            // persistent coarse CG: grid barrier, status, iterations
   int persistent_coarse = 1;        // run the coarse CG as one persistent kernel when it applies
+  // second deflation level of the coarse operator (Sec. V.B): ng global
+  // vectors Z (orthonormal, E = Z^+ A Z = diag(D)) and A Z, complex128 and
+  // complex64, [ng][Nc * nvec]
+  int ng = 0;
+  hdk::DevBuf ldZ128, ldAZ128, ldZ64, ldAZ64;
+  hdk::DevBuf ldD;                  // double [ng]
+  hdk::DevBuf ldc;                  // coefficients [64][1024] complex128
+  std::vector<double> ldDh;         // D on the host
   double* pinned = nullptr;   // host pinned scalars [16][64]
   struct {
     int n_ii = 0;
@@ -63,6 +73,7 @@ struct hdcg {
     double rat_lo = 3e-4, rat_eps = 1e-4, rat_tol = 1e-6;
     int rat_maxiter = 10000;
     int wall_noise = 0;         // keep only the physical wall components of the noise
+    int ldop_defl = 1;          // deflate coarse solves with the second level once it is built
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;
@@ -100,5 +111,23 @@ int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, i
 // does not apply (more than 8 right-hand sides, unsuited nvec).
 int coarse_cg_persistent(hdcg* h, int mprec, cplx<float>* x, const cplx<float>* b, int nr, double tol,
                          int maxiter, int* iters, int* done, hipStream_t st);
+
+// complex128 CG on (A + shift) x = b from x = 0 (hdcg_solver.hip)
+int coarse_cg_shifted(hdcg* h, cplx<double>* x, const cplx<double>* b, int nr, double shift, double tol, int maxiter,
+                      int* iters, hipStream_t st);
+int ensure_at128_impl(hdcg* h, hipStream_t st);  // the complex128 transposed A for the mat-vec
+
+// second deflation level (ldop.hip): build Z, AZ, D from the free global
+// vectors and n_extra coarse noise vectors ([n_extra][Nc][nvec] complex128)
+// after n_steps of (A + shift)^-1 each (coarse CG to tol, at most maxiter)
+int ldop_build(hdcg* h, int n_extra, const cplx<double>* noise, double shift, int n_steps, double tol, int maxiter,
+               hipStream_t st);
+// c[rhs][k] = (V_k, r_rhs) / D_k into h->ldc
+template <typename R>
+int ldop_coef(hdcg* h, const cplx<R>* V, const cplx<R>* r, int nr, hipStream_t st);
+// out = (use_r ? r : 0) + (num ? num/den out : 0) + sign sum_k Z_k c[rhs][k]
+template <typename R>
+int ldop_apply(hdcg* h, cplx<R>* out, const cplx<R>* r, const double* num, const double* den, const cplx<R>* Z,
+               int nr, double sign, bool use_r, hipStream_t st);
 
 }  // namespace hdk

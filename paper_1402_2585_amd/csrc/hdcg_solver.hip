@@ -28,7 +28,7 @@ Red red_of(dwf_op* op) { return Red{op->red.partials.as<double>(), op->red.count
 // device scalar slots, 128 doubles each (room for 64 right-hand sides x 2)
 enum {
   S_RR0, S_RR1, S_PAP, S_PP,                       // fine CG
-  S_CRR0, S_CRR1, S_CPAP,                           // coarse CG
+  S_CRR0, S_CRR1, S_CPAP, S_CPP,                    // coarse CG
   S_ARR, S_APR, S_AWY, S_ARY0, S_ARY1, S_AINIT, S_APW,  // A-DEF2 (own slots: M_IRS runs inside)
   S_ORR, S_OBB,                                     // outer loop
   S_NSLOT
@@ -193,11 +193,16 @@ static int apply_mirs(hdcg* h, c64* z, const c64* r, int nr, int* it, hipStream_
 }
 
 // -------------------------------------------------------------- coarse CG --
+// CG on (A + shift) x = b from x = 0 (shift >= 0; the coarse operator in the
+// storage mprec selects for complex64).  With the second deflation level
+// built (and enabled, shift 0) it is deflated CG (Sec. V.B): x0 = Z D^-1 Z^+ b
+// and p = r + beta p - Z D^-1 (AZ)^+ r.  Stops at |r| <= tol |b|.
 template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
-              int maxiter, int* iters, hipStream_t st, int mprec = -1) {
+              int maxiter, int* iters, hipStream_t st, int mprec = -1, double shift = 0.0) {
+  const bool defl = h->ng > 0 && h->prm.ldop_defl != 0 && shift == 0.0;
   if constexpr (sizeof(R) == 4) {
-    if (h->persistent_coarse) {
+    if (h->persistent_coarse && !defl && shift == 0.0) {
       int done = 0;
       HDCG_TRY(coarse_cg_persistent(h, mprec == DWF_BF16 || mprec == DWF_F16 ? mprec : DWF_C64, x, b, nr, tol,
                                     maxiter, iters, &done, st));
@@ -212,11 +217,36 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
   const Red red = red_of(h->op);
   double* rr[2] = {slot(h, S_CRR0), slot(h, S_CRR1)};
   double* pap = slot(h, S_CPAP);
-  HDCG_TRY(b_zero<R>(x, n * nr, st));
-  HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
-  HDCG_HIP(hipMemcpyAsync(p, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
-  HDCG_TRY(b_norm2<R>(red, r, n, nr, rr[0], st));
+  double* pp = shift != 0.0 ? slot(h, S_CPP) : nullptr;
+  const cplx<R>* Z = nullptr;
+  const cplx<R>* AZ = nullptr;
+  if (defl) {
+    Z = reinterpret_cast<const cplx<R>*>(sizeof(R) == 8 ? h->ldZ128.ptr : h->ldZ64.ptr);
+    AZ = reinterpret_cast<const cplx<R>*>(sizeof(R) == 8 ? h->ldAZ128.ptr : h->ldAZ64.ptr);
+  }
+  auto matvec = [&](const cplx<R>* in, cplx<R>* out) -> int {
+    if constexpr (sizeof(R) == 4) {
+      if (mprec == DWF_BF16 || mprec == DWF_F16) return crs_apply_mfma(h, mprec, in, out, nr, st);
+    }
+    return crs_apply<R>(h, AT, in, out, nr, st);
+  };
+  HDCG_TRY(b_norm2<R>(red, b, n, nr, rr[0], st));
   HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 9, rr[0], nr * sizeof(double), hipMemcpyDeviceToHost, st));
+  HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  if (defl) {
+    // x0 = Z D^-1 Z^+ b ; r0 = b - A x0 ; p0 = r0 - Z D^-1 (AZ)^+ r0
+    HDCG_TRY(ldop_coef<R>(h, Z, b, nr, st));
+    HDCG_TRY(ldop_apply<R>(h, x, nullptr, nullptr, nullptr, Z, nr, 1.0, false, st));
+    HDCG_TRY(matvec(x, w));
+    HDCG_TRY(b_axpby<R>(r, w, -1.0, 1.0, n * nr, st));
+    HDCG_TRY(b_norm2<R>(red, r, n, nr, rr[0], st));
+    HDCG_TRY(ldop_coef<R>(h, AZ, r, nr, st));
+    HDCG_TRY(ldop_apply<R>(h, p, r, nullptr, nullptr, Z, nr, -1.0, true, st));
+  } else {
+    HDCG_TRY(b_zero<R>(x, n * nr, st));
+    HDCG_HIP(hipMemcpyAsync(p, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+    if (pp) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
   HDCG_HIP(hipStreamSynchronize(st));
   std::vector<double> bb(h->pinned + 64 * 9, h->pinned + 64 * 9 + nr);
   bool any = false;
@@ -229,17 +259,15 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
     while (!done && k < maxiter) {
       double* cur = rr[k & 1];
       double* nxt = rr[(k + 1) & 1];
-      if constexpr (sizeof(R) == 4) {
-        if (mprec == DWF_BF16 || mprec == DWF_F16)
-          HDCG_TRY(crs_apply_mfma(h, mprec, p, w, nr, st));
-        else
-          HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
-      } else {
-        HDCG_TRY(crs_apply<R>(h, AT, p, w, nr, st));
-      }
+      HDCG_TRY(matvec(p, w));
       HDCG_TRY(b_dot<R>(red, p, w, n, nr, pap, st));
-      HDCG_TRY(b_update<R>(red, x, r, p, w, n, nr, cur, false, pap, nullptr, 0.0, nxt, st, 2));
-      HDCG_TRY(b_xpay<R>(red, p, r, n, nr, nxt, false, cur, 1.0, nullptr, st));
+      HDCG_TRY(b_update<R>(red, x, r, p, w, n, nr, cur, false, pap, pp, shift, nxt, st, 2));
+      if (defl) {
+        HDCG_TRY(ldop_coef<R>(h, AZ, r, nr, st));
+        HDCG_TRY(ldop_apply<R>(h, p, r, nxt, cur, Z, nr, -1.0, true, st));
+      } else {
+        HDCG_TRY(b_xpay<R>(red, p, r, n, nr, nxt, false, cur, 1.0, pp, st));
+      }
       ++k;
       HDCG_TRY(ring.push(nxt, st));
       while (ring.checked < ring.queued && (ring.queued - ring.checked > 2 || k >= maxiter)) {
@@ -258,6 +286,17 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
     }
   }
   if (iters) *iters = k;
+  return DWF_OK;
+}
+
+int coarse_cg_shifted(hdcg* h, c128* x, const c128* b, int nr, double shift, double tol, int maxiter, int* iters,
+                      hipStream_t st) {
+  HDCG_TRY(ensure_at128_impl(h, st));
+  return coarse_cg<double>(h, h->AT128.as<c128>(), x, b, nr, tol, maxiter, iters, st, -1, shift);
+}
+
+int ensure_at128_impl(hdcg* h, hipStream_t st) {
+  if (h->AT128.bytes == 0) HDCG_TRY(crs_transpose(h, true, st));
   return DWF_OK;
 }
 
@@ -409,6 +448,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->rat_tol = 1e-6;
   p->rat_maxiter = 10000;
   p->wall_noise = 0;
+  p->ldop_defl = 1;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -436,6 +476,12 @@ int hdcg_destroy(hdcg_t h) {
   h->mf_f16.release();
   h->pcg_part.release();
   h->pcg_state.release();
+  h->ldZ128.release();
+  h->ldAZ128.release();
+  h->ldZ64.release();
+  h->ldAZ64.release();
+  h->ldD.release();
+  h->ldc.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return DWF_OK;
@@ -677,6 +723,7 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.rat_tol = p->rat_tol;
     h->prm.rat_maxiter = p->rat_maxiter;
     h->prm.wall_noise = p->wall_noise;
+    h->prm.ldop_defl = p->ldop_defl;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
@@ -774,10 +821,7 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
                             static_cast<c64*>(fine_out), nullptr, 1.0, fe, st);
 }
 
-static int ensure_at128(hdcg* h, hipStream_t st) {
-  if (h->AT128.bytes == 0) HDCG_TRY(crs_transpose(h, true, st));
-  return DWF_OK;
-}
+static int ensure_at128(hdcg* h, hipStream_t st) { return ensure_at128_impl(h, st); }
 
 int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream) {
   const bool m16 = prec == DWF_BF16 || prec == DWF_F16;
@@ -840,6 +884,29 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.outer_maxiter = p->outer_maxiter;
   h->prm.coarse_prec = p->coarse_prec;
   h->prm.irs_prec = p->irs_prec;
+  h->prm.ldop_defl = p->ldop_defl;
+  return DWF_OK;
+}
+
+int hdcg_ldop_setup(hdcg_t h, int n_extra, const void* noise_c128, double shift, int n_steps, double tol,
+                    void* stream) {
+  if (!h) return fail(DWF_ERR_ARG, "null handle");
+  return ldop_build(h, n_extra, static_cast<const c128*>(noise_c128), shift, n_steps, tol, 100000,
+                    static_cast<hipStream_t>(stream));
+}
+
+int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void* stream) {
+  if (!h) return fail(DWF_ERR_ARG, "null handle");
+  if (n_global) *n_global = h->ng;
+  if (h->ng == 0) return DWF_OK;
+  auto st = static_cast<hipStream_t>(stream);
+  if (Z_c128) {
+    HDCG_HIP(hipMemcpyAsync(Z_c128, h->ldZ128.ptr, sizeof(c128) * h->ng * h->Nc * h->nvec,
+                            hipMemcpyDeviceToDevice, st));
+    HDCG_HIP(hipStreamSynchronize(st));
+  }
+  if (D_host)
+    for (int i = 0; i < h->ng; ++i) D_host[i] = h->ldDh[i];
   return DWF_OK;
 }
 

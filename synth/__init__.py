@@ -95,3 +95,12 @@ def gaussian_half_field(dims, Ls: int, seed: int, nrhs: int | None = None) -> np
     re = g.standard_normal(shape)
     im = g.standard_normal(shape)
     return re + 1j * im
+
+
+def gaussian_coarse(Nc: int, nvec: int, seed: int, n: int) -> np.ndarray:
+    """n complex Gaussian coarse vectors c[k][a][j] (Nc sites, nvec
+    components), real and imaginary parts N(0, 1)."""
+    g = rng(seed)
+    re = g.standard_normal((n, Nc, nvec))
+    im = g.standard_normal((n, Nc, nvec))
+    return re + 1j * im

@@ -270,6 +270,84 @@ def test_hdcg_solve_bf16_mirs_keeps_iterations():
     op.close()
 
 
+def test_ldop_second_level_against_oracle(two_level):
+    """Second deflation level (Sec. V.B): the free vectors plus 6 coarse noise
+    vectors after 3 inverse-iteration steps, orthonormalised, E diagonalised.
+    Against the oracle on the same coarse noise and its own A: the
+    eigenvalues D (1e-8 relative: both iterate to 1e-12) and the projector
+    Z Z^+ on a random coarse vector (1e-7); then the deflated coarse solve
+    (complex128 to 1e-10 and complex64 to 1e-5) against a dense solve."""
+    from oracle import ldop as oldop
+
+    t = two_level
+    banner(f"ldop second level {t['name']}")
+    h, A, C = t["h"], t["A"], t["C"]
+    Nc, nvec = A.shape[0], A.shape[2]
+    noise = synth.gaussian_coarse(Nc, nvec, 360, 6)
+    hd.hdcg_ldop_setup(h.h, 6, torch.from_numpy(noise).to("cuda"), 0.0, 3, 1e-12)
+    try:
+        ng, D = hd.hdcg_export_ldop(h.h)
+        assert ng == nvec + 6
+        Zg = torch.empty((ng, Nc, nvec), dtype=torch.complex128, device="cuda")
+        hd.hdcg_export_ldop(h.h, Zg)
+        Zg = Zg.cpu().numpy().reshape(ng, -1)
+        Vi = oldop.inverse_iteration(A, C, noise, n_steps=3, shift=0.0, tol=1e-12)
+        W = oldop.orthonormal_basis(np.concatenate([oldop.free_global_vectors(Nc, nvec), Vi]))
+        Z, Dz, AZ = oldop.third_level(A, C, W)
+        print("D gpu", D[:4], "oracle", Dz[:4], flush=True)
+        assert np.abs(D - Dz).max() < 1e-8 * Dz.max()
+        v = np.random.default_rng(361).standard_normal(Nc * nvec) + 0j
+        Pg = Zg.T @ (Zg.conj() @ v)
+        Zo = Z.reshape(ng, -1)
+        Po = Zo.T @ (Zo.conj() @ v)
+        assert np.abs(Pg - Po).max() < 1e-7 * np.abs(Po).max()
+        b = synth.gaussian_coarse(Nc, nvec, 362, 1)[0]
+        xd = np.linalg.solve(ocrs.to_dense(A, C), b.ravel()).reshape(b.shape)
+        for prec, tol, bound in ((hd.DWF_C128, 1e-10, 1e-7), (hd.DWF_C64, 1e-5, 1e-3)):
+            x = h.new_coarse(prec)
+            rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b[None]).to(x.dtype).to("cuda").contiguous(), prec,
+                                          1, tol, 2000)
+            err = rel_err(x.cpu().numpy()[0], xd)
+            print(f"deflated coarse solve prec={prec}: {it} iterations, rel err {err:.2e}", flush=True)
+            assert rc == 0 and err < bound
+    finally:
+        h.set_params(ldop_defl=0)
+
+
+def test_ldop_deflation_cuts_coarse_iterations():
+    """On a subspace after inverse iteration (A then has the low modes the
+    second level is for), deflated coarse CG needs fewer iterations than
+    plain CG for the same solution, and HDCG with it reaches 1e-8."""
+    dims, Ls, block, nvec, eps, mass = GEOMS["12^4xLs2-b4-n4"]
+    banner("ldop deflation 12^4 x Ls2, n_ii = 2")
+    U = synth.gauge_field(dims, eps, 300)
+    raw = synth.gaussian_half_field(dims, Ls, 301, nrhs=nvec)
+    op = hd.FineOperator(U, dims, Ls, 1.8, mass)
+    h = hd.HDCG(op, block, raw, n_ii=2)
+    Nc = h.Nc
+    b = torch.from_numpy(synth.gaussian_coarse(Nc, nvec, 363, 1)).to("cuda")
+    x0 = h.new_coarse(hd.DWF_C128)
+    rc, it0 = hd.hdcg_coarse_solve(h.h, x0, b, hd.DWF_C128, 1, 1e-10, 5000)
+    hd.hdcg_ldop_setup(h.h, 24, torch.from_numpy(synth.gaussian_coarse(Nc, nvec, 364, 24)).to("cuda"), 0.0, 3, 1e-7)
+    x1 = h.new_coarse(hd.DWF_C128)
+    rc1, it1 = hd.hdcg_coarse_solve(h.h, x1, b, hd.DWF_C128, 1, 1e-10, 5000)
+    print(f"coarse CG iterations: plain {it0}, deflated {it1}", flush=True)
+    assert rc == 0 and rc1 == 0 and it1 < it0
+    assert rel_err(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-8
+    ref = DWF(U, dims, Ls, 1.8, mass)
+    bf = synth.gaussian_half_field(dims, Ls, 365)
+    x = op.new_field()
+    rcs, st = hd.hdcg_solve(h.h, x, op.to_native(bf), 1, 1e-8)
+    print(st, flush=True)
+    assert rcs == 0 and st["converged"] == 1
+    r = bf - ref.H(op.to_canonical(x).cpu().numpy())
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(bf, bf).real) <= 1e-8
+    with pytest.raises(hd.HdcgError):
+        hd.hdcg_ldop_setup(h.h, -1, None)
+    h.close()
+    op.close()
+
+
 def test_hdcg_solve_small(two_level):
     t = two_level
     banner(f"hdcg_solve {t['name']}")
