@@ -153,8 +153,9 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps each to
     1e-3, complex64 coarse operator and inner solver, FP64 defect correction)
     from the same seeded source, each to a 1e-8 FP64 true residual, on this
-    GPU; then the same HDCG with 16-bit M_IRS fields, and with the
-    rational-filter subspace in place of inverse iteration."""
+    GPU; then the same HDCG with 16-bit M_IRS fields, with the second
+    deflation level of the coarse operator, and with the rational-filter
+    subspace in place of inverse iteration."""
     import numpy as np
 
     import synth
@@ -207,6 +208,29 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
     rel_b = true_residual(x3)
+    # second deflation level of the coarse operator (Sec. V.B): the 24 free
+    # global vectors and 128 more after 3 inverse-iteration steps to 1e-7
+    n_extra = 128
+    noise = torch.from_numpy(synth.gaussian_coarse(h.Nc, w.nvec, w.coarse_seed, n_extra)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hd.hdcg_ldop_setup(h.h, n_extra, noise, 0.0, 3, 1e-7)
+    torch.cuda.synchronize()
+    t_ldop = time.perf_counter() - t0
+    del noise
+    ldop = {"global_vectors": w.nvec + n_extra, "setup_seconds": round(t_ldop, 3)}
+    for name, iprec in (("c64_mirs", hd.DWF_C64), ("bf16_mirs", hd.DWF_BF16)):
+        h.set_params(irs_prec=iprec, ldop_defl=1)
+        x5 = op.new_field(zero=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc5, st5 = hd.hdcg_solve(h.h, x5, b, 1, tol)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter() - t0
+        ldop[name] = {"seconds": round(t5, 4), "outer": st5["outer_iterations"], "inner": st5["inner_iterations"],
+                      "coarse_iterations": st5["coarse_iterations"], "true_residual": true_residual(x5),
+                      "status": rc5, "speedup_solve_vs_cg": round(t_cg / t5, 3)}
+        del x5
     h.close()
     # the subspace from the rational filter (Sec. IV.B: lambda = 3e-4,
     # eps = lambda / 3, multi-shift residual 1e-6, noise on the walls only)
@@ -243,6 +267,7 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
                            "speedup_vs_c64_mirs": round(t_h / t_b, 3),
                            "speedup_solve_vs_cg": round(t_cg / t_b, 3),
                            "speedup_solve_vs_mixed_cg": round(t_mixed / t_b, 3)},
+        "hdcg_ldop_deflation": ldop,
         "hdcg_rational_subspace": {"setup_seconds": round(t_setup_r, 3), "seconds": round(t_r, 4),
                                    "outer": st_r["outer_iterations"], "inner": st_r["inner_iterations"],
                                    "coarse_iterations": st_r["coarse_iterations"], "true_residual": rel_r,

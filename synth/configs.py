@@ -37,6 +37,11 @@ class Workload:
     def subspace_seed(self, k: int) -> int:
         return 1000 * self.cfg + 500 + k
 
+    @property
+    def coarse_seed(self) -> int:
+        """the coarse noise of the second deflation level"""
+        return 1000 * self.cfg + 900
+
 
 WORKLOADS = {
     1: Workload(1, "cg-fp64-4^4xLs8", (4, 4, 4, 4), 8, 1.8, 0.01, 0.5),
