@@ -509,6 +509,11 @@ int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int n
     }
     hipLaunchKernelGGL((k_capply<R, 1, 16>), dim3(h->Nc, 1), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in, out,
                        h->Nc, h->nvec, nr);
+  } else if (sizeof(R) == 8 && nr > 2) {
+    // complex128 with many right-hand sides (the second deflation level's
+    // setup): eight per pass over A, so A is read nr / 8 times
+    hipLaunchKernelGGL((k_capply<R, 8, 2>), dim3(h->Nc, (nr + 7) / 8), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in,
+                       out, h->Nc, h->nvec, nr);
   } else {
     constexpr int NR = sizeof(R) == 8 ? 2 : 4;
     hipLaunchKernelGGL((k_capply<R, NR, 8>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st, AT,

@@ -31,6 +31,13 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
     ap.add_argument("--irs", choices=["c64", "bf16"], default="c64", help="storage of the M_IRS fields")
+    ap.add_argument("--ldop", type=int, default=0,
+                    help="extra global coarse vectors of the second deflation level (0: none)")
+    ap.add_argument("--nrhs_solve", type=int, default=1, help="right-hand sides of the HDCG solve")
+    ap.add_argument("--variants", action="store_true",
+                    help="solve four times on one setup: as given, 16-bit M_IRS fields, and both again after "
+                         "building the second deflation level (--ldop vectors, default 128)")
+    ap.add_argument("--cg", action="store_true", help="also time the plain FP64 CG on the same source(s)")
     ap.add_argument("--n_ii", type=int, default=3)
     ap.add_argument("--tol_ii", type=float, default=1e-3)
     ap.add_argument("--maxiter_ii", type=int, default=500)
@@ -111,11 +118,72 @@ def run_hdcg(a, torch, synth):
     h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
                 irs_prec=iprec, verbose=1)
     print("setup done", flush=True)
-    x = op.new_field(zero=True)
-    rc, st = hd.hdcg_solve(h.h, x, b, 1, 1e-8)
-    print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs}: status {rc} {st}", flush=True)
+    if a.variants:
+        run_variants(a, torch, synth, hd, w, op, h, b)
+        h.close()
+        op.close()
+        return
+    if a.ldop > 0:
+        noise = torch.from_numpy(synth.gaussian_coarse(h.Nc, w.nvec, w.coarse_seed, a.ldop)).to("cuda")
+        hd.hdcg_ldop_setup(h.h, a.ldop, noise, 0.0, 3, 1e-7)
+        del noise
+        print(f"second deflation level: {w.nvec + a.ldop} global vectors", flush=True)
+    if a.nrhs_solve > 1:
+        bs = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(r))
+                                        for r in range(a.nrhs_solve)])).to("cuda")
+        b = op.to_native(bs)
+    x = op.new_field(zero=True, nrhs=a.nrhs_solve)
+    rc, st = hd.hdcg_solve(h.h, x, b, a.nrhs_solve, 1e-8)
+    print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs} ldop {a.ldop} nrhs {a.nrhs_solve}: "
+          f"status {rc} {st}", flush=True)
     h.close()
     op.close()
+
+
+def run_variants(a, torch, synth, hd, w, op, h, b):
+    import time
+
+    import numpy as np
+
+    nr = a.nrhs_solve
+    if nr > 1:
+        bs = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(r))
+                                        for r in range(nr)])).to("cuda")
+        b = op.to_native(bs)
+        del bs
+    if a.cg:
+        x = op.new_field(zero=True, nrhs=nr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(nr):
+            n1 = x.numel() // nr
+            rc, st = hd.cg_solve(op.h, x[r * n1:(r + 1) * n1], b[r * n1:(r + 1) * n1], 1, 1e-8, 50000)
+        torch.cuda.synchronize()
+        print(f"plain FP64 CG, {nr} right-hand side(s) one after another: {time.perf_counter() - t0:.3f} s", flush=True)
+        del x
+
+    def solve(name):
+        x = op.new_field(zero=True, nrhs=nr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = hd.hdcg_solve(h.h, x, b, nr, 1e-8)
+        torch.cuda.synchronize()
+        print(f"variant {name}: {time.perf_counter() - t0:.3f} s, status {rc} {st}", flush=True)
+
+    solve("as given")
+    h.set_params(irs_prec=hd.DWF_BF16)
+    solve("16-bit M_IRS fields")
+    n_extra = a.ldop if a.ldop > 0 else 128
+    noise = torch.from_numpy(synth.gaussian_coarse(h.Nc, w.nvec, w.coarse_seed, n_extra)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hd.hdcg_ldop_setup(h.h, n_extra, noise, 0.0, 3, 1e-7)
+    torch.cuda.synchronize()
+    print(f"second deflation level: {w.nvec + n_extra} global vectors, {time.perf_counter() - t0:.2f} s", flush=True)
+    del noise
+    solve("16-bit M_IRS fields + second level")
+    h.set_params(irs_prec=hd.DWF_C64)
+    solve("second level")
 
 
 def run_lanczos(a, torch, synth):
