@@ -433,6 +433,42 @@ def test_hdcg_inverse_iteration_and_multi_rhs():
     op.close()
 
 
+def test_hdcg_solve_ragged_groups_zero_source_and_16bit_mirs():
+    """Nine right-hand sides (a group of 8 and a ragged group of 1), one of
+    them zero (its solution must be exactly zero), with 16-bit M_IRS fields
+    and the second deflation level, every non-zero one to 1e-8."""
+    name = "12^4xLs2-b4-n4"
+    banner(f"hdcg nrhs=9 (one zero), bf16 M_IRS, second level {name}")
+    dims, Ls, block, nvec, raw, op, h, ref = _setup(name, n_ii=1)
+    hd.hdcg_ldop_setup(h.h, 8, torch.from_numpy(synth.gaussian_coarse(h.Nc, nvec, 366, 8)).to("cuda"), 0.0, 3, 1e-7)
+    h.set_params(irs_prec=hd.DWF_BF16)
+    b = synth.gaussian_half_field(dims, Ls, 367, nrhs=9)
+    b[4] = 0.0
+    x = op.new_field(nrhs=9)
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 9, 1e-8)
+    print(st, flush=True)
+    assert rc == 0 and st["converged"] == 1
+    xc = op.to_canonical(x, nrhs=9).cpu().numpy()
+    assert np.all(xc[4] == 0)
+    for i in (0, 3, 7, 8):
+        r = b[i] - ref.H(xc[i])
+        assert np.sqrt(np.vdot(r, r).real / np.vdot(b[i], b[i]).real) <= 1e-8, i
+    h.close()
+    op.close()
+
+
+def test_multishift_zero_source():
+    dims, Ls = (4, 4, 4, 4), 4
+    op = hd.FineOperator(synth.gauge_field(dims, 0.5, 368), dims, Ls, 1.8, 0.02)
+    b = op.new_field(nrhs=2, zero=True)
+    x = op.new_field(nrhs=4)
+    x.fill_(1.0)
+    rc, st = hd.dwf_multishift_cg(op.h, x, b, [0.1, 0.2], 2, tol=1e-10)
+    assert rc == 0 and st["iterations"] == 0
+    assert torch.count_nonzero(x).item() == 0
+    op.close()
+
+
 def test_setup_rejects_bad_blocks():
     banner("setup geometry errors")
     dims, Ls = (8, 8, 8, 8), 2
