@@ -219,8 +219,9 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     t_ldop = time.perf_counter() - t0
     del noise
     ldop = {"global_vectors": w.nvec + n_extra, "setup_seconds": round(t_ldop, 3)}
-    for name, iprec in (("c64_mirs", hd.DWF_C64), ("bf16_mirs", hd.DWF_BF16)):
-        h.set_params(irs_prec=iprec, ldop_defl=1)
+    for name, iprec, pprec in (("c64_mirs", hd.DWF_C64, hd.DWF_C64), ("bf16_mirs", hd.DWF_BF16, hd.DWF_C64),
+                               ("bf16_mirs_bf16_subspace", hd.DWF_BF16, hd.DWF_BF16)):
+        h.set_params(irs_prec=iprec, ldop_defl=1, phi_prec=pprec)
         x5 = op.new_field(zero=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

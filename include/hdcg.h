@@ -220,6 +220,9 @@ struct hdcg_params {
                          (P- at s = 0, P+ at s = Ls - 1, Sec. IV.B) before filtering */
   int ldop_defl;      /* 1 (default): once hdcg_ldop_setup has built the second deflation
                          level, every coarse solve is deflated CG on it (Sec. V.B); 0: plain */
+  int phi_prec;       /* storage of the subspace for the project / promote of the solve's Q:
+                         DWF_C64 (default) or DWF_BF16 (bf16 pairs rounded to nearest even
+                         from FP64, half the bytes; arithmetic and vectors complex64) */
 };
 
 struct hdcg_stats {
@@ -262,7 +265,9 @@ int hdcg_dims(hdcg_t h, int coarse_dims[4], int* ncoarse, int* nvec);
 
 /* c[rhs][a][k] = <phi^a_k, psi_rhs> (project, P^+) and psi = sum phi^a_k
  * c[a][k] (promote, P), Sec. II.  Fine fields native, coarse vectors
- * canonical, both in precision prec (C128 or C64); asynchronous. */
+ * canonical, both in precision prec (C128 or C64); prec DWF_BF16: the
+ * subspace in 16 bits (built on first use), vectors complex64, FP32
+ * arithmetic.  Asynchronous. */
 int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int nrhs, void* stream);
 int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream);
 
@@ -312,10 +317,11 @@ int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void
 
 /* Replace the solve-phase parameters of a built handle (n_irs, lambda_irs,
  * coarse_tol, coarse_maxiter, flexible, inner_tol, inner_maxiter,
- * outer_maxiter, coarse_prec, irs_prec, ldop_defl); the setup-phase fields of *p are
- * ignored.  Builds the 16-bit copy of A when coarse_prec asks for one not yet
- * built.  Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle
- * is then unchanged). */
+ * outer_maxiter, coarse_prec, irs_prec, ldop_defl, phi_prec); the
+ * setup-phase fields of *p are ignored.  Builds the 16-bit copies of A and
+ * of the subspace when coarse_prec or phi_prec asks for one not yet built.
+ * Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle is
+ * then unchanged). */
 int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream);
 
 /* Copies for parity checks: the little Dirac operator in the canonical layout

@@ -46,7 +46,7 @@ class HdcgParams(C.Structure):
                 ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int),
                 ("irs_prec", C.c_int), ("subspace_gen", C.c_int), ("rat_lo", C.c_double),
                 ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
-                ("wall_noise", C.c_int), ("ldop_defl", C.c_int)]
+                ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int)]
 
 
 class HdcgStats(C.Structure):

@@ -28,6 +28,7 @@ struct hdcg {
   hdk::DevBuf site_of;        // int [Nc][nsb]
   hdk::DevBuf nbr;            // int [Nc][81]
   hdk::DevBuf phi128, phi64;  // [Nc][nvec][nb]
+  hdk::DevBuf phi16;          // the same in 16 bits (bf16 pairs) when phi_prec asks for it
   hdk::DevBuf A128;           // [Nc][81][nvec][nvec]
   hdk::DevBuf AT64;           // [Nc][81][nvec][nvec] transposed per l
   hdk::DevBuf AT128;          // same layout in complex128 (parity / FP64 use)
@@ -74,6 +75,7 @@ struct hdcg {
     int rat_maxiter = 10000;
     int wall_noise = 0;         // keep only the physical wall components of the noise
     int ldop_defl = 1;          // deflate coarse solves with the second level once it is built
+    int phi_prec = DWF_C64;     // subspace storage for the solve's project / promote: C64 or BF16
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;
@@ -98,6 +100,12 @@ int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride,
 template <typename R>
 int blk_promote(hdcg* h, const cplx<R>* P, const cplx<R>* c, int nr, cplx<R>* fine_out,
                 const cplx<R>* base, double sign, size_t fstride, hipStream_t st);
+// the same two with the subspace stored in 16 bits (complex64 vectors)
+int blk_dot(hdcg* h, const bf16c* P, const cplx<float>* fine, size_t fstride, int nr, cplx<float>* out, size_t sr,
+            size_t sa, size_t sk, hipStream_t st);
+int blk_promote(hdcg* h, const bf16c* P, const cplx<float>* c, int nr, cplx<float>* fine_out,
+                const cplx<float>* base, double sign, size_t fstride, hipStream_t st);
+int blk_phi16(hdcg* h, hipStream_t st);        // phi16 = phi128 rounded to bf16 pairs
 int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
 template <typename R>
 int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);

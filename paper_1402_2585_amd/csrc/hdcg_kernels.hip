@@ -80,9 +80,10 @@ __global__ void k_phi_layout(cplx<R>* __restrict__ phi, const cplx<double>* __re
 }
 
 // out[r*sr + a*sa + k*sk] = ph[a] * sum_i conj(P[a][k][i]) Q(r, a, i)
-template <typename R, bool FINE>
+// P is stored as TP (cplx<R>, or bf16c with R = float); arithmetic in R.
+template <typename TP, bool FINE, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(kT)
-k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
+k_blkdot(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
          const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
          cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk,
          const cplx<double>* __restrict__ phase) {
@@ -91,7 +92,7 @@ k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fs
   const int a = blockIdx.x, k0 = blockIdx.y * 16, r0 = blockIdx.z * 16;
   const int t = threadIdx.x, tk = t >> 4, tr = t & 15;
   cplx<R> acc = cmk((R)0, (R)0);
-  const cplx<R>* Pa = P + (size_t)a * nvec * nb;
+  const TP* Pa = P + (size_t)a * nvec * nb;
   for (size_t i0 = 0; i0 < nb; i0 += 32) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -99,7 +100,7 @@ k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fs
       const int kk = e >> 5, ii = e & 31;
       const int k = k0 + kk;
       cplx<R> v = cmk((R)0, (R)0);
-      if (k < nvec) v = conj(Pa[(size_t)k * nb + i0 + ii]);
+      if (k < nvec) v = conj(St<TP>::ld(Pa + (size_t)k * nb + i0 + ii));
       Ps[kk][ii] = v;
       const int rr = e >> 5;  // 0..15
       const int r = r0 + rr;
@@ -130,43 +131,68 @@ k_blkdot(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fs
   }
 }
 
+// V consecutive subspace values (V = 4: one 16-byte load of bf16 pairs)
+template <typename TP, int V, typename R = typename St<TP>::R>
+__device__ __forceinline__ void ld_phi(const TP* p, cplx<R> (&o)[V]) {
+  if constexpr (V == 4 && sizeof(TP) == 4) {
+    const uint4 w = *reinterpret_cast<const uint4*>(p);
+    const unsigned u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[e] = cmk(__uint_as_float(u[e] << 16), __uint_as_float(u[e] & 0xffff0000u));
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e) o[e] = St<TP>::ld(p + e);
+  }
+}
+
 // Few right-hand sides: one workgroup per (vector k, block a) streams the
 // row P[a][k][:] once, lanes running over the 12 Ls contiguous components of
-// each site column; out[r*sr + a*sa + k*sk] = sum_i conj(P[a][k][i]) Q_r(site(a, i)).
-template <typename R, int NR>
+// each site column (V consecutive ones per lane); out[r*sr + a*sa + k*sk] =
+// sum_i conj(P[a][k][i]) Q_r(site(a, i)).  The workgroups of one block are
+// consecutive after the XCD remap, so the block's fine data is fetched into
+// one L2 for all its Nvec rows.
+template <typename TP, int NR, int V, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(256)
-k_project_small(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
+k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
                 const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
                 cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk) {
-  const int k = blockIdx.x, a = blockIdx.y;
-  const cplx<R>* Pk = P + ((size_t)a * nvec + k) * nb;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int k = wg % nvec, a = wg / nvec;
+  const TP* Pk = P + ((size_t)a * nvec + k) * nb;
   const int* so = site_of + (size_t)a * nsb;
   cplx<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
   // U sites at a time, their loads issued before the multiply-adds
-  constexpr int U = 8;
-  for (int q = threadIdx.x; q < col; q += blockDim.x) {
+  constexpr int U = NR * V > 4 ? 4 : 8;
+  for (int q = threadIdx.x * V; q < col; q += blockDim.x * V) {
     for (int j0 = 0; j0 < nsb; j0 += U) {
-      cplx<R> pv[U], qv[U][NR];
+      cplx<R> pv[U][V], qv[U][NR][V];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        pv[u] = cmk((R)0, (R)0);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) qv[u][r] = cmk((R)0, (R)0);
         const int j = j0 + u;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          pv[u][e] = cmk((R)0, (R)0);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) qv[u][r][e] = cmk((R)0, (R)0);
+        }
         if (j < nsb) {
-          pv[u] = Pk[(size_t)j * col + q];
+          ld_phi<TP, V>(Pk + (size_t)j * col + q, pv[u]);
           const size_t base = (size_t)so[j] * col + q;
 #pragma unroll
           for (int r = 0; r < NR; ++r)
-            if (r < nr) qv[u][r] = Q[r * fstride + base];
+            if (r < nr)
+#pragma unroll
+              for (int e = 0; e < V; ++e) qv[u][r][e] = Q[r * fstride + base + e];
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int r = 0; r < NR; ++r) cjmac(acc[r], pv[u], qv[u][r]);
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int e = 0; e < V; ++e) cjmac(acc[r], pv[u][e], qv[u][r][e]);
     }
   }
   __shared__ double red[2 * NR][4];
@@ -191,43 +217,58 @@ k_project_small(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ Q, si
   }
 }
 
-// fine_out[r][site(a, i)] = base + sign * sum_k P[a][k][i] c[r][a][k]
-template <typename R, int NR>
+// fine_out[r][site(a, i)] = base + sign * sum_k P[a][k][i] c[r][a][k], V
+// consecutive i per thread (they lie in one site column: 12 Ls % V == 0)
+template <typename TP, int NR, int V, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(kT)
-k_promote(const cplx<R>* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int Nc, int nvec,
+k_promote(const TP* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int Nc, int nvec,
           size_t nb, int nsb, int col, const int* __restrict__ site_of, cplx<R>* out,
           const cplx<R>* base, R sign, size_t fstride) {  // out may alias base (in place)
   __shared__ cplx<R> cs[NR * 64];
   const int a = blockIdx.y;
-  const size_t i = (size_t)blockIdx.x * kT + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * kT + threadIdx.x) * V;
   for (int e = threadIdx.x; e < nr * nvec; e += kT)
     cs[e] = c[((size_t)(e / nvec) * Nc + a) * nvec + e % nvec];
   __syncthreads();
   if (i >= nb) return;
-  cplx<R> acc[NR];
+  cplx<R> acc[NR][V];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
-  const cplx<R>* Pa = P + (size_t)a * nvec * nb + i;
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[r][e] = cmk((R)0, (R)0);
+  const TP* Pa = P + (size_t)a * nvec * nb + i;
   // U subspace vectors at a time, their loads issued before the multiply-adds
   constexpr int U = 8;
   for (int k0 = 0; k0 < nvec; k0 += U) {
-    cplx<R> pv[U];
+    cplx<R> pv[U][V];
 #pragma unroll
-    for (int u = 0; u < U; ++u) pv[u] = (k0 + u < nvec) ? Pa[(size_t)(k0 + u) * nb] : cmk((R)0, (R)0);
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < nvec) {
+        ld_phi<TP, V>(Pa + (size_t)(k0 + u) * nb, pv[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) pv[u][e] = cmk((R)0, (R)0);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (r < nr && k0 + u < nvec) cmac(acc[r], pv[u], cs[r * nvec + k0 + u]);
+        if (r < nr && k0 + u < nvec)
+#pragma unroll
+          for (int e = 0; e < V; ++e) cmac(acc[r][e], pv[u][e], cs[r * nvec + k0 + u]);
   }
   const int j = (int)(i / col), q = (int)(i - (size_t)j * col);
   const size_t addr = (size_t)site_of[(size_t)a * nsb + j] * col + q;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r < nr) {
-      cplx<R> o = sign * acc[r];
-      if (base) o = base[r * fstride + addr] + o;
-      out[r * fstride + addr] = o;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        cplx<R> o = sign * acc[r][e];
+        if (base) o = base[r * fstride + addr + e] + o;
+        out[r * fstride + addr + e] = o;
+      }
     }
   }
 }
@@ -423,57 +464,116 @@ int blk_phi_layout(hdcg* h, cplx<R>* phi, const cplx<double>* can, bool to_nativ
   return DWF_OK;
 }
 
-template <typename R>
-int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
-            int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
-            hipStream_t st) {
+template <typename TP, typename R = typename St<TP>::R>
+int blk_dot_t(hdcg* h, const TP* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
+              int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
+              hipStream_t st) {
   const int col = 12 * h->op->g.Ls;
   if (fine && !phase && nr <= 4) {
     // streaming kernel: P read once, few accumulators per lane
-    const int threads = ((std::min(col, 256) + 63) / 64) * 64;
-    dim3 g2(h->nvec, h->Nc);
+    constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
+    if (col % V) return fail(DWF_ERR_ARG, "project: 12 Ls must be a multiple of 4");
+    const int threads = ((std::min(col / V, 256) + 63) / 64) * 64;
+    dim3 g2(h->nvec * h->Nc);
     if (nr == 1)
-      hipLaunchKernelGGL((k_project_small<R, 1>), g2, dim3(threads), 0, st, P, fine, fstride,
+      hipLaunchKernelGGL((k_project_small<TP, 1, V>), g2, dim3(threads), 0, st, P, fine, fstride,
                          h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
     else
-      hipLaunchKernelGGL((k_project_small<R, 4>), g2, dim3(threads), 0, st, P, fine, fstride,
+      hipLaunchKernelGGL((k_project_small<TP, 4, V>), g2, dim3(threads), 0, st, P, fine, fstride,
                          h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
     HDCG_HIP(hipGetLastError());
     return DWF_OK;
   }
   dim3 grid(h->Nc, (h->nvec + 15) / 16, (nr + 15) / 16);
   if (fine)
-    hipLaunchKernelGGL((k_blkdot<R, true>), grid, dim3(kT), 0, st, P, fine, fstride,
+    hipLaunchKernelGGL((k_blkdot<TP, true>), grid, dim3(kT), 0, st, P, fine, fstride,
                        h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
   else
-    hipLaunchKernelGGL((k_blkdot<R, false>), grid, dim3(kT), 0, st, P, blockq, (size_t)0,
+    hipLaunchKernelGGL((k_blkdot<TP, false>), grid, dim3(kT), 0, st, P, blockq, (size_t)0,
                        h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }
 
-template <typename R>
-int blk_promote(hdcg* h, const cplx<R>* P, const cplx<R>* c, int nr, cplx<R>* out,
-                const cplx<R>* base, double sign, size_t fstride, hipStream_t st) {
+template <typename TP, typename R = typename St<TP>::R>
+int blk_promote_t(hdcg* h, const TP* P, const cplx<R>* c, int nr, cplx<R>* out,
+                  const cplx<R>* base, double sign, size_t fstride, hipStream_t st) {
   if (nr < 1 || h->nvec > 64) return fail(DWF_ERR_ARG, "promote: bad nr / nvec");
   const int col = 12 * h->op->g.Ls;
+  constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
+  if (col % V) return fail(DWF_ERR_ARG, "promote: 12 Ls must be a multiple of 4");
   for (int r0 = 0; r0 < nr; r0 += 16) {
     const int n = nr - r0 < 16 ? nr - r0 : 16;
     dim3 grid((unsigned)((h->nb + kT - 1) / kT), h->Nc);
+    dim3 gridv((unsigned)((h->nb / V + kT - 1) / kT), h->Nc);
     const cplx<R>* cc = c + (size_t)r0 * h->Nc * h->nvec;
     cplx<R>* o = out + (size_t)r0 * fstride;
     const cplx<R>* b = base ? base + (size_t)r0 * fstride : nullptr;
     if (n <= 1)
-      hipLaunchKernelGGL((k_promote<R, 1>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+      hipLaunchKernelGGL((k_promote<TP, 1, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
                          h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
     else if (n <= 4)
-      hipLaunchKernelGGL((k_promote<R, 4>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+      hipLaunchKernelGGL((k_promote<TP, 4, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
                          h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
     else
-      hipLaunchKernelGGL((k_promote<R, 16>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
+      hipLaunchKernelGGL((k_promote<TP, 16, 1>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
                          h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
     HDCG_HIP(hipGetLastError());
   }
+  return DWF_OK;
+}
+
+template <typename R>
+int blk_dot(hdcg* h, const cplx<R>* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
+            int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
+            hipStream_t st) {
+  return blk_dot_t(h, P, fine, fstride, blockq, nr, out, sr, sa, sk, phase, st);
+}
+template <typename R>
+int blk_promote(hdcg* h, const cplx<R>* P, const cplx<R>* c, int nr, cplx<R>* out,
+                const cplx<R>* base, double sign, size_t fstride, hipStream_t st) {
+  return blk_promote_t(h, P, c, nr, out, base, sign, fstride, st);
+}
+int blk_dot(hdcg* h, const bf16c* P, const c64* fine, size_t fstride, int nr, c64* out, size_t sr, size_t sa,
+            size_t sk, hipStream_t st) {
+  return blk_dot_t<bf16c, float>(h, P, fine, fstride, nullptr, nr, out, sr, sa, sk, nullptr, st);
+}
+int blk_promote(hdcg* h, const bf16c* P, const c64* c, int nr, c64* out, const c64* base, double sign,
+                size_t fstride, hipStream_t st) {
+  return blk_promote_t(h, P, c, nr, out, base, sign, fstride, st);
+}
+
+// The subspace in 16 bits: phi16 = phi128 rounded to the nearest bfloat16
+// pair (ties to even), directly from FP64 (no intermediate float rounding)
+__device__ __forceinline__ unsigned short f64_to_bf16(double d) {
+  const unsigned long long u = __double_as_longlong(d);
+  const unsigned sign = (unsigned)(u >> 63);
+  const int e = (int)((u >> 52) & 0x7ff) - 1023 + 127;
+  const unsigned long long m = u & ((1ull << 52) - 1);
+  if (e <= 0) return (unsigned short)(sign << 15);              // below the normal range: signed zero
+  if (e >= 255) return (unsigned short)((sign << 15) | 0x7f80u);  // above it: infinity
+  unsigned v = ((unsigned)e << 7) | (unsigned)(m >> 45);
+  const unsigned long long rem = m & ((1ull << 45) - 1), half = 1ull << 44;
+  if (rem > half || (rem == half && (v & 1u))) ++v;  // a carry moves into the exponent
+  return (unsigned short)((sign << 15) | v);
+}
+__global__ void k_phi_bf16(bf16c* __restrict__ out, const c128* __restrict__ in, size_t total) {
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT) {
+    const c128 v = in[i];
+    bf16c o;
+    o.re = f64_to_bf16(v.re);
+    o.im = f64_to_bf16(v.im);
+    out[i] = o;
+  }
+}
+int blk_phi16(hdcg* h, hipStream_t st) {
+  const size_t total = (size_t)h->Nc * h->nvec * h->nb;
+  HDCG_TRY(h->phi16.ensure(total * sizeof(bf16c)));
+  size_t nbk = (total + kT - 1) / kT;
+  if (nbk > 65536) nbk = 65536;
+  hipLaunchKernelGGL(k_phi_bf16, dim3((unsigned)nbk), dim3(kT), 0, st, h->phi16.as<bf16c>(), h->phi128.as<c128>(),
+                     total);
+  HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }
 

@@ -308,13 +308,20 @@ static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, do
   HDCG_TRY(h->cw[4].ensure(n * nr * sizeof(c128)));
   c64* cb = h->cw[3].as<c64>();
   c64* cx = h->cw[4].as<c64>();
-  HDCG_TRY(blk_dot<float>(h, h->phi64.as<c64>(), in, fine_elems(h), nullptr, nr, cb, n, h->nvec, 1,
-                          nullptr, st));
+  const bool p16 = h->prm.phi_prec == DWF_BF16;
+  if (p16)
+    HDCG_TRY(blk_dot(h, h->phi16.as<bf16c>(), in, fine_elems(h), nr, cb, n, h->nvec, 1, st));
+  else
+    HDCG_TRY(blk_dot<float>(h, h->phi64.as<c64>(), in, fine_elems(h), nullptr, nr, cb, n, h->nvec, 1,
+                            nullptr, st));
   int it = 0;
   HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter,
                             &it, st, h->prm.coarse_prec));
   if (citers) *citers += it;
-  HDCG_TRY(blk_promote<float>(h, h->phi64.as<c64>(), cx, nr, out, base, sign, fine_elems(h), st));
+  if (p16)
+    HDCG_TRY(blk_promote(h, h->phi16.as<bf16c>(), cx, nr, out, base, sign, fine_elems(h), st));
+  else
+    HDCG_TRY(blk_promote<float>(h, h->phi64.as<c64>(), cx, nr, out, base, sign, fine_elems(h), st));
   return DWF_OK;
 }
 
@@ -413,11 +420,13 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
 
 using namespace hdk;
 
-static int check_solve_params(int coarse_prec, int irs_prec) {
+static int check_solve_params(int coarse_prec, int irs_prec, int phi_prec) {
   if (coarse_prec != DWF_C64 && coarse_prec != DWF_BF16 && coarse_prec != DWF_F16)
     return fail(DWF_ERR_ARG, "coarse_prec must be DWF_C64, DWF_BF16 or DWF_F16");
   if (irs_prec != DWF_C64 && irs_prec != DWF_BF16)
     return fail(DWF_ERR_ARG, "irs_prec must be DWF_C64 or DWF_BF16");
+  if (phi_prec != DWF_C64 && phi_prec != DWF_BF16)
+    return fail(DWF_ERR_ARG, "phi_prec must be DWF_C64 or DWF_BF16");
   return DWF_OK;
 }
 
@@ -449,6 +458,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->rat_maxiter = 10000;
   p->wall_noise = 0;
   p->ldop_defl = 1;
+  p->phi_prec = DWF_C64;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -458,6 +468,7 @@ int hdcg_destroy(hdcg_t h) {
   h->nbr.release();
   h->phi128.release();
   h->phi64.release();
+  h->phi16.release();
   h->A128.release();
   h->AT64.release();
   h->AT128.release();
@@ -591,6 +602,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   if (flag) return fail(DWF_ERR_NUMERIC, "block Gram matrix not positive definite (subspace vectors dependent on a block)");
   HDCG_TRY(h->phi64.ensure(fe * nv * sizeof(c64)));
   HDCG_TRY(launch_convert(h->phi64.as<c64>(), h->phi128.as<c128>(), fe * nv, st));
+  if (h->prm.phi_prec == DWF_BF16) HDCG_TRY(blk_phi16(h, st));
 
   // ---- little Dirac operator by the Fourier trick (Sec. V.A.1) ---------
   const size_t n2 = (size_t)nv * nv;
@@ -724,10 +736,11 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.rat_maxiter = p->rat_maxiter;
     h->prm.wall_noise = p->wall_noise;
     h->prm.ldop_defl = p->ldop_defl;
+    h->prm.phi_prec = p->phi_prec;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
-  if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec); rc < 0) {
+  if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec, h->prm.phi_prec); rc < 0) {
     delete h;
     return rc;
   }
@@ -790,18 +803,30 @@ int hdcg_export_coarse(hdcg_t h, void* A_c128, void* stream) {
   return DWF_OK;
 }
 
-static int check_h(hdcg* h, int prec, int nrhs) {
+static int check_h(hdcg* h, int prec, int nrhs, bool allow16 = false) {
   if (!h) return fail(DWF_ERR_ARG, "null hdcg handle");
-  if (prec != DWF_C128 && prec != DWF_C64) return fail(DWF_ERR_ARG, "precision must be DWF_C128 or DWF_C64");
+  if (prec != DWF_C128 && prec != DWF_C64 && !(allow16 && prec == DWF_BF16))
+    return fail(DWF_ERR_ARG, allow16 ? "precision must be DWF_C128, DWF_C64 or DWF_BF16"
+                                     : "precision must be DWF_C128 or DWF_C64");
   if (nrhs < 1 || nrhs > 64) return fail(DWF_ERR_ARG, "nrhs must be in 1..64");
   return DWF_OK;
 }
 
+static int ensure_phi16(hdcg* h, hipStream_t st) {
+  if (h->phi16.bytes == 0) HDCG_TRY(blk_phi16(h, st));
+  return DWF_OK;
+}
+
 int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int nrhs, void* stream) {
-  HDCG_TRY(check_h(h, prec, nrhs));
+  HDCG_TRY(check_h(h, prec, nrhs, true));
   if (!coarse_out || !fine_in) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t n = (size_t)h->Nc * h->nvec, fe = h->op->field_elems(1);
+  if (prec == DWF_BF16) {
+    HDCG_TRY(ensure_phi16(h, st));
+    return blk_dot(h, h->phi16.as<bf16c>(), static_cast<const c64*>(fine_in), fe, nrhs, static_cast<c64*>(coarse_out),
+                   n, h->nvec, 1, st);
+  }
   if (prec == DWF_C128)
     return blk_dot<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(fine_in), fe, nullptr, nrhs,
                            static_cast<c128*>(coarse_out), n, h->nvec, 1, nullptr, st);
@@ -810,10 +835,15 @@ int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int 
 }
 
 int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream) {
-  HDCG_TRY(check_h(h, prec, nrhs));
+  HDCG_TRY(check_h(h, prec, nrhs, true));
   if (!coarse_in || !fine_out) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t fe = h->op->field_elems(1);
+  if (prec == DWF_BF16) {
+    HDCG_TRY(ensure_phi16(h, st));
+    return blk_promote(h, h->phi16.as<bf16c>(), static_cast<const c64*>(coarse_in), nrhs, static_cast<c64*>(fine_out),
+                       nullptr, 1.0, fe, st);
+  }
   if (prec == DWF_C128)
     return blk_promote<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(coarse_in), nrhs,
                                static_cast<c128*>(fine_out), nullptr, 1.0, fe, st);
@@ -866,13 +896,14 @@ int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
 
 int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   if (!h || !p) return fail(DWF_ERR_ARG, "null argument to hdcg_set_params");
-  HDCG_TRY(check_solve_params(p->coarse_prec, p->irs_prec));
+  HDCG_TRY(check_solve_params(p->coarse_prec, p->irs_prec, p->phi_prec));
   if (p->n_irs < 0 || p->coarse_maxiter < 1 || p->inner_maxiter < 1 || p->outer_maxiter < 1 ||
       !(p->coarse_tol > 0.0) || !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
     return fail(DWF_ERR_ARG, "hdcg_set_params: iteration caps must be positive, tolerances in (0, 1)");
   auto st = static_cast<hipStream_t>(stream);
   if (p->coarse_prec == DWF_BF16 && !h->mf_have_bf16) HDCG_TRY(crs_build_mfma(h, DWF_BF16, st));
   if (p->coarse_prec == DWF_F16 && !h->mf_have_f16) HDCG_TRY(crs_build_mfma(h, DWF_F16, st));
+  if (p->phi_prec == DWF_BF16) HDCG_TRY(ensure_phi16(h, st));
   HDCG_HIP(hipStreamSynchronize(st));
   h->prm.n_irs = p->n_irs;
   h->prm.lambda_irs = p->lambda_irs;
@@ -885,6 +916,7 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.coarse_prec = p->coarse_prec;
   h->prm.irs_prec = p->irs_prec;
   h->prm.ldop_defl = p->ldop_defl;
+  h->prm.phi_prec = p->phi_prec;
   return DWF_OK;
 }
 

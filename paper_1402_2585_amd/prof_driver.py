@@ -31,12 +31,14 @@ def main():
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
     ap.add_argument("--irs", choices=["c64", "bf16"], default="c64", help="storage of the M_IRS fields")
+    ap.add_argument("--phi", choices=["c64", "bf16"], default="c64", help="storage of the subspace in Q")
     ap.add_argument("--ldop", type=int, default=0,
                     help="extra global coarse vectors of the second deflation level (0: none)")
     ap.add_argument("--nrhs_solve", type=int, default=1, help="right-hand sides of the HDCG solve")
     ap.add_argument("--variants", action="store_true",
-                    help="solve four times on one setup: as given, 16-bit M_IRS fields, and both again after "
-                         "building the second deflation level (--ldop vectors, default 128)")
+                    help="solve five times on one setup: as given, 16-bit M_IRS fields, both again after "
+                         "building the second deflation level (--ldop vectors, default 128), and with the "
+                         "subspace of Q in 16 bits as well")
     ap.add_argument("--cg", action="store_true", help="also time the plain FP64 CG on the same source(s)")
     ap.add_argument("--n_ii", type=int, default=3)
     ap.add_argument("--tol_ii", type=float, default=1e-3)
@@ -115,8 +117,9 @@ def run_hdcg(a, torch, synth):
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
     b = op.to_native(bsrc)
     iprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.irs]
+    pprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.phi]
     h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
-                irs_prec=iprec, verbose=1)
+                irs_prec=iprec, phi_prec=pprec, verbose=1)
     print("setup done", flush=True)
     if a.variants:
         run_variants(a, torch, synth, hd, w, op, h, b)
@@ -134,7 +137,8 @@ def run_hdcg(a, torch, synth):
         b = op.to_native(bs)
     x = op.new_field(zero=True, nrhs=a.nrhs_solve)
     rc, st = hd.hdcg_solve(h.h, x, b, a.nrhs_solve, 1e-8)
-    print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs} ldop {a.ldop} nrhs {a.nrhs_solve}: "
+    print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs} subspace {a.phi} ldop {a.ldop} "
+          f"nrhs {a.nrhs_solve}: "
           f"status {rc} {st}", flush=True)
     h.close()
     op.close()
@@ -182,7 +186,9 @@ def run_variants(a, torch, synth, hd, w, op, h, b):
     print(f"second deflation level: {w.nvec + n_extra} global vectors, {time.perf_counter() - t0:.2f} s", flush=True)
     del noise
     solve("16-bit M_IRS fields + second level")
-    h.set_params(irs_prec=hd.DWF_C64)
+    h.set_params(phi_prec=hd.DWF_BF16)
+    solve("16-bit M_IRS fields + second level + 16-bit subspace in Q")
+    h.set_params(irs_prec=hd.DWF_C64, phi_prec=hd.DWF_C64)
     solve("second level")
 
 

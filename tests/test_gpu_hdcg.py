@@ -93,6 +93,31 @@ def test_project_promote(two_level):
         assert rel_err(op.to_canonical(fine, prec, 2).cpu().numpy(), want_p) < tol
 
 
+def test_project_promote_bf16_subspace(two_level):
+    """The subspace in 16 bits (bf16 pairs rounded to nearest even from
+    FP64): project and promote against the oracle's with the oracle's own
+    rounding of the same subspace (complex64 tolerance 2e-5), one and five
+    right-hand sides (the streaming and the tiled block-dot kernels)."""
+    from oracle import precision as prc
+
+    t = two_level
+    banner(f"project/promote bf16 subspace {t['name']}")
+    op, h = t["op"], t["h"]
+    phi16 = prc.round_bf16(t["phi"])
+    for nr in (1, 5):
+        v = synth.gaussian_half_field(t["dims"], t["Ls"], 370 + nr, nrhs=nr).astype(np.complex64)
+        c = h.new_coarse(hd.DWF_C64, nrhs=nr)
+        hd.hdcg_project(h.h, c, op.to_native(v, hd.DWF_C64), hd.DWF_BF16, nr)
+        want = oblk.project(phi16, t["sob"], v.astype(np.complex128).reshape((nr,) + v.shape[-4:]))
+        assert rel_err(c.cpu().numpy(), want) < 2e-5
+        cc = synth.gaussian_coarse(h.Nc, t["nvec"], 380 + nr, nr).astype(np.complex64)
+        f = op.new_field(hd.DWF_C64, nrhs=nr)
+        hd.hdcg_promote(h.h, f, torch.from_numpy(cc).to("cuda"), hd.DWF_BF16, nr)
+        got = op.to_canonical(f, hd.DWF_C64, nrhs=nr).cpu().numpy().reshape((nr,) + v.shape[-4:])
+        want = oblk.promote(phi16, t["sob"], cc.astype(np.complex128))
+        assert rel_err(got, want) < 2e-5
+
+
 def test_coarse_operator_fourier_vs_oracle_brute_force(two_level):
     t = two_level
     banner(f"coarse A {t['name']}")
@@ -266,6 +291,15 @@ def test_hdcg_solve_bf16_mirs_keeps_iterations():
     x = op.new_field()
     rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
     assert rc == 0 and st["converged"] == 1
+    # the subspace of Q in 16 bits, with 16-bit M_IRS fields
+    h.set_params(irs_prec=hd.DWF_BF16, phi_prec=hd.DWF_BF16)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    print("bf16 subspace + bf16 M_IRS", st, flush=True)
+    assert rc == 0 and st["converged"] == 1
+    r = b - ref.H(op.to_canonical(x).cpu().numpy())
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8
+    assert st["inner_iterations"] <= its[hd.DWF_C64] + max(2, 0.1 * its[hd.DWF_C64])
     h.close()
     op.close()
 
