@@ -82,7 +82,22 @@ __global__ void __launch_bounds__(kT) k_defl_coef(const cplx<R>* __restrict__ V,
   const cplx<R>* v = V + (size_t)k * N;
   const cplx<R>* x = r + (size_t)rhs * N;
   double re = 0.0, im = 0.0;
-  for (size_t n = threadIdx.x; n < N; n += kT) {
+  // four strided elements per trip, loads first
+  size_t n = threadIdx.x;
+  for (; n + 3 * kT < N; n += 4 * kT) {
+    cplx<R> a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = v[n + u * kT];
+      b[u] = x[n + u * kT];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      re += (double)a[u].re * b[u].re + (double)a[u].im * b[u].im;
+      im += (double)a[u].re * b[u].im - (double)a[u].im * b[u].re;
+    }
+  }
+  for (; n < N; n += kT) {
     const cplx<R> a = v[n], b = x[n];
     re += (double)a.re * b.re + (double)a.im * b.im;
     im += (double)a.re * b.im - (double)a.im * b.re;
@@ -93,19 +108,40 @@ __global__ void __launch_bounds__(kT) k_defl_coef(const cplx<R>* __restrict__ V,
   if (threadIdx.x == 0) c[(size_t)rhs * ng + k] = cmk(s[0] / D[k], s[1] / D[k]);
 }
 
-// out = (use_r ? r : 0) + (num ? num/den * out : 0) + sign * sum_k Z_k c[rhs][k]
+// out = (use_r ? r : 0) + (num ? num/den * out : 0) + sign * sum_k Z_k c[rhs][k].
+// A workgroup takes 64 elements; its four waves split the sum over k and
+// meet in LDS (more workgroups in flight and four times shorter load chains).
 constexpr int kMaxGlobal = 1024;
+constexpr int kDefE = 64;
 template <typename R>
 __global__ void __launch_bounds__(kT) k_defl_apply(cplx<R>* __restrict__ out, const cplx<R>* __restrict__ r,
                                                    const double* __restrict__ num, const double* __restrict__ den,
                                                    const cplx<R>* __restrict__ Z, const c128* __restrict__ c, int ng,
                                                    size_t N, double sign, int use_r) {
   __shared__ c128 cs[kMaxGlobal];
+  __shared__ double part[kT / kDefE][kDefE][2];
   const int rhs = blockIdx.y;
   for (int k = threadIdx.x; k < ng; k += kT) cs[k] = c[(size_t)rhs * ng + k];
   __syncthreads();
-  const size_t n = (size_t)blockIdx.x * kT + threadIdx.x;
-  if (n >= N) return;
+  const int el = threadIdx.x % kDefE, slice = threadIdx.x / kDefE;
+  constexpr int kSlices = kT / kDefE;
+  const size_t n = (size_t)blockIdx.x * kDefE + el;
+  double zr = 0.0, zi = 0.0;
+  if (n < N) {
+    for (int k = slice; k < ng; k += kSlices) {
+      const cplx<R> z = Z[(size_t)k * N + n];
+      zr += (double)z.re * cs[k].re - (double)z.im * cs[k].im;
+      zi += (double)z.re * cs[k].im + (double)z.im * cs[k].re;
+    }
+  }
+  part[slice][el][0] = zr;
+  part[slice][el][1] = zi;
+  __syncthreads();
+  if (slice != 0 || n >= N) return;
+  for (int q = 1; q < kSlices; ++q) {
+    zr += part[q][el][0];
+    zi += part[q][el][1];
+  }
   const size_t e = (size_t)rhs * N + n;
   double re = 0.0, im = 0.0;
   if (use_r) {
@@ -117,12 +153,6 @@ __global__ void __launch_bounds__(kT) k_defl_apply(cplx<R>* __restrict__ out, co
     const double beta = d != 0.0 ? num[rhs] / d : 0.0;
     re += beta * out[e].re;
     im += beta * out[e].im;
-  }
-  double zr = 0.0, zi = 0.0;
-  for (int k = 0; k < ng; ++k) {
-    const cplx<R> z = Z[(size_t)k * N + n];
-    zr += (double)z.re * cs[k].re - (double)z.im * cs[k].im;
-    zi += (double)z.re * cs[k].im + (double)z.im * cs[k].re;
   }
   out[e] = cmk((R)(re + sign * zr), (R)(im + sign * zi));
 }
@@ -259,7 +289,7 @@ template <typename R>
 int ldop_apply(hdcg* h, cplx<R>* out, const cplx<R>* r, const double* num, const double* den, const cplx<R>* Z,
                int nr, double sign, bool use_r, hipStream_t st) {
   const size_t N = (size_t)h->Nc * h->nvec;
-  hipLaunchKernelGGL((k_defl_apply<R>), dim3((unsigned)((N + kT - 1) / kT), nr), dim3(kT), 0, st, out, r, num, den, Z,
+  hipLaunchKernelGGL((k_defl_apply<R>), dim3((unsigned)((N + kDefE - 1) / kDefE), nr), dim3(kT), 0, st, out, r, num, den, Z,
                      h->ldc.as<c128>(), h->ng, N, sign, use_r ? 1 : 0);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
