@@ -37,11 +37,54 @@ __device__ __forceinline__ void coef(const double* num, bool cnum, const double*
   }
 }
 
+// Workgroup sums of one right-hand side's NQ quantities, reduced over the
+// grid inside the producing kernel: each workgroup stores its partials with
+// coherent device-scope stores, waits for them to complete and takes a
+// ticket; the workgroup that takes the last ticket sums every partial in a
+// fixed order (the result does not depend on which one it is), writes
+// res[NQ * rhs + q] and resets the ticket counter.  No workgroup waits for
+// another, and no cache maintenance is needed.
 template <int NQ>
-__device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, double*) {
+__device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, double* res) {
   __shared__ double lds[NQ * 16];
+  __shared__ int last;
+  constexpr int nslots = kMaxPartials / NQ;
+  double* part = red.partials + (size_t)rhs * kMaxPartials;
   block_sum<NQ>(v, lds);
-  store_partial<NQ>(v, red.partials + (size_t)rhs * kMaxPartials, kMaxPartials / NQ, blockIdx.x);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      __hip_atomic_store(part + q * nslots + blockIdx.x, v[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    const unsigned t = __hip_atomic_fetch_add(red.counters + rhs, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last = t == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  double s[NQ];
+  const int G = (int)gridDim.x, B = (int)blockDim.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    s[q] = 0.0;
+    // four partials per trip, loads first (the last workgroup's sum is on
+    // the kernel's critical path)
+    for (int i0 = threadIdx.x; i0 < G; i0 += 4 * B) {
+      double a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        a[u] = i0 + u * B < G ? __hip_atomic_load(part + q * nslots + i0 + u * B, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[q] += a[u];
+    }
+  }
+  block_sum<NQ>(s, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) res[NQ * rhs + q] = s[q];
+    __hip_atomic_store(red.counters + rhs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <int NQ>
@@ -264,14 +307,14 @@ int norm2_t(Red red, const T* x, size_t n, int nrhs, double* res, hipStream_t st
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
   hipLaunchKernelGGL((k_norm2<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, n, red, res);
   LAUNCH_CHECK();
-  return launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, res, st);
+  return DWF_OK;
 }
 template <typename T>
 int dot_t(Red red, const T* a, const T* b, size_t n, int nrhs, double* res, hipStream_t st) {
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
   hipLaunchKernelGGL((k_dot<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, a, b, n, red, res);
   LAUNCH_CHECK();
-  return launch_finalize(2, red.partials, kMaxPartials / 2, nblocks(n), nrhs, res, st);
+  return DWF_OK;
 }
 template <typename T>
 int update_t(Red red, T* x, T* r, const T* p, const T* w, size_t n, int nrhs, const double* num,
@@ -282,7 +325,7 @@ int update_t(Red red, T* x, T* r, const T* p, const T* w, size_t n, int nrhs, co
   hipLaunchKernelGGL((k_update<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
                      cnum, den, den2, lam, red, rr, dstr);
   LAUNCH_CHECK();
-  return rr ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, rr, st) : DWF_OK;
+  return DWF_OK;
 }
 template <typename T>
 int xpay_t(Red red, T* p, const T* y, size_t n, int nrhs, const double* num, bool cnum,
@@ -292,7 +335,7 @@ int xpay_t(Red red, T* p, const T* y, size_t n, int nrhs, const double* num, boo
   hipLaunchKernelGGL((k_xpay<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, p, y, n, num, cnum, den,
                      sign, red, pp, dstr);
   LAUNCH_CHECK();
-  return pp ? launch_finalize(1, red.partials, kMaxPartials, nblocks(n), nrhs, pp, st) : DWF_OK;
+  return DWF_OK;
 }
 template <typename T>
 int zero_t(T* y, size_t total, hipStream_t st) {
