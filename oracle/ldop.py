@@ -99,3 +99,110 @@ def deflated_cg(A, C, b, Z, D, AZ, tol=1e-8, maxiter=10000):
         rr = rr_new
         it += 1
     return x.reshape(b.shape), it, np.sqrt(rr) / bn
+
+
+# ---------------------------------------------------------------------------
+# The truncated operator and the ADEF1 coarse solver (Sec. V.B, "Truncated
+# little Dirac operator as preconditioner").  Q_trunc keeps the zero- and
+# one-hop terms of A (the site itself and its 8 axis neighbours; still
+# Hermitian) plus an infra-red shift; a Chebyshev polynomial of Q_trunc
+# approximating 1/x on [lo, hi] is the high-mode preconditioner M, and the
+# second level deflates the low modes: ADEF1, M_1 = M P_D + Q with
+# P_D = 1 - A Q, Q = Z D^-1 Z^+, A Z stored (no extra A application).
+
+def one_hop_points():
+    """Stencil indices l with sum_mu |delta_mu| <= 1 (l = 40 first)."""
+    offs = crs.stencil_offsets()
+    pts = [l for l in range(crs.NSTENCIL) if np.abs(offs[l]).sum() <= 1]
+    pts.remove(40)
+    return [40] + pts
+
+
+def truncate(A, shift=0.0):
+    """Q_trunc + shift in the 81-point storage (the dropped terms zero)."""
+    T = np.zeros_like(A)
+    for l in one_hop_points():
+        T[:, l] = A[:, l]
+    nvec = A.shape[2]
+    T[:, 40] += shift * np.eye(nvec)
+    return T
+
+
+def chebyshev_inverse(apply, r, lo, hi, order):
+    """y = p(M) r from the Chebyshev iteration for M y = r started at y = 0:
+    the residual r - M y is R_n(M) r with the scaled Chebyshev polynomial
+    R_n(x) = T_n((d - x)/c) / T_n(d/c), d = (hi + lo)/2, c = (hi - lo)/2,
+    n = order (n - 1 applications of M).  The three-term recurrence of T_n
+    gives, with sigma = d/c and omega_k = 2 sigma T_{k-1}(sigma)/T_k(sigma)
+    (omega_1 = 2, omega_{k+1} = 1/(1 - omega_k/(4 sigma^2))),
+        delta_1 = r/d,  delta_{k+1} = (omega_{k+1}/d) r_k + (omega_{k+1} - 1) delta_k,
+        y_k = delta_1 + ... + delta_k,  r_k = r_{k-1} - M delta_k."""
+    if order < 1:
+        raise ValueError("order must be at least 1")
+    d, c = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = d / c
+    delta = r / d
+    y = delta.copy()
+    res = r.copy()
+    omega = 2.0
+    for _ in range(1, order):
+        res = res - apply(delta)
+        omega = 1.0 / (1.0 - omega / (4.0 * sigma * sigma))
+        delta = (omega / d) * res + (omega - 1.0) * delta
+        y = y + delta
+    return y
+
+
+def coarse_coarse_inverse(Z, D):
+    """v -> Z D^-1 Z^+ v on flat vectors."""
+    Zf = _flat(Z)
+    return lambda v: Zf.T @ ((Zf.conj() @ v) / D)
+
+
+def adef1_preconditioner(Z, D, AZ, M):
+    """r -> M (r - A Z D^-1 Z^+ r) + Z D^-1 Z^+ r (M_1 = M P_D + Q with
+    P_D = 1 - A Q), on vectors of the coarse shape."""
+    Zf, AZf = _flat(Z), _flat(AZ)
+
+    def M1(r):
+        c = (Zf.conj() @ r.ravel()) / D
+        return (M((r.ravel() - AZf.T @ c).reshape(r.shape)).ravel() + Zf.T @ c).reshape(r.shape)
+    return M1
+
+
+def adef1_solve(A, C, b, Z, D, AZ, M, tol=1e-8, maxiter=10000):
+    """Flexible generalised PCG on A x = b with the ADEF1 preconditioner
+    y = M (r - AZ D^-1 Z^+ r) + Z D^-1 Z^+ r, from x0 = Z D^-1 Z^+ b;
+    alpha = (p, r)/(p, w), beta = -(w, y)/(p, w).  Stops at |r| <= tol |b|.
+    Returns (x, iterations, relative residual)."""
+    shape = b.shape
+    bf = b.ravel()
+
+    def apply(v):
+        return crs.apply(A, v.reshape(shape), C).ravel()
+
+    Q = coarse_coarse_inverse(Z, D)
+    M1_ = adef1_preconditioner(Z, D, AZ, M)
+
+    def M1(r):
+        return M1_(r.reshape(shape)).ravel()
+
+    x = Q(bf)
+    r = bf - apply(x)
+    bn = np.linalg.norm(bf)
+    y = M1(r)
+    p = y.copy()
+    it = 0
+    while np.linalg.norm(r) > tol * bn and it < maxiter:
+        w = apply(p)
+        pw = np.vdot(p, w)
+        alpha = np.vdot(p, r) / pw
+        x = x + alpha * p
+        r = r - alpha * w
+        it += 1
+        if np.linalg.norm(r) <= tol * bn:
+            break
+        y = M1(r)
+        beta = -np.vdot(w, y) / pw
+        p = y + beta * p
+    return x.reshape(shape), it, np.linalg.norm(r) / bn

@@ -136,3 +136,94 @@ def test_deflated_cg_with_free_and_inverse_iteration_vectors(small):
     assert rel <= 1e-10 and np.abs(x - xd).max() < 1e-7 * np.abs(xd).max()
     _, it_cg, _ = cg(lambda u: crs.apply(A, u, C), b, tol=1e-10)
     assert it < it_cg, (it, it_cg)
+
+
+def test_truncation_keeps_one_hop_terms():
+    A, C = _dense_case(68)
+    T = ldop.truncate(A, shift=0.3)
+    Dn, Dt = crs.to_dense(A, C), crs.to_dense(T, C)
+    assert np.abs(Dt - Dt.conj().T).max() < 1e-14
+    coords = crs.coarse_coords(C)
+    nvec = A.shape[2]
+    Cc = np.array(C)
+    for a in range(0, A.shape[0], 7):
+        for b in range(A.shape[0]):
+            d = np.abs(coords[a] - coords[b])
+            d = np.minimum(d, Cc - d).sum()  # taxicab hops on the torus
+            blk_t = Dt[a * nvec:(a + 1) * nvec, b * nvec:(b + 1) * nvec]
+            blk_a = Dn[a * nvec:(a + 1) * nvec, b * nvec:(b + 1) * nvec]
+            want = blk_a + (0.3 * np.eye(nvec) if a == b else 0) if d <= 1 else np.zeros_like(blk_a)
+            assert np.abs(blk_t - want).max() < 1e-14
+
+
+def test_chebyshev_residual_polynomial():
+    """On an eigenvector with eigenvalue x the iteration leaves
+    R_n(x) = T_n((d - x)/c) / T_n(d/c) times it as residual (the definition of
+    the Chebyshev iteration), T_n from numpy's Chebyshev series, for x inside
+    and outside [lo, hi] and for orders 1, 2 and 16."""
+    M, ev, Q = _hpd(30, 69, lo=0.05, hi=60.0)
+    lo, hi = 0.5, 45.0
+    d, c = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    for n in (1, 2, 16):
+        Tn = np.zeros(n + 1)
+        Tn[n] = 1.0
+        norm = np.polynomial.chebyshev.chebval(d / c, Tn)
+        for i in range(30):
+            v = Q[:, i]
+            y = ldop.chebyshev_inverse(lambda u: M @ u, v, lo, hi, n)
+            want = np.polynomial.chebyshev.chebval((d - ev[i]) / c, Tn) / norm
+            res = v - M @ y
+            assert np.abs(res - want * v).max() < 1e-10 * max(1.0, abs(want)), (n, ev[i], want)
+    # order 1 is the Jacobi-like step y = r / d
+    v = Q[:, 0]
+    assert np.allclose(ldop.chebyshev_inverse(lambda u: M @ u, v, lo, hi, 1), v / d, rtol=0, atol=1e-15)
+
+
+def _hpd(n, seed, lo=1e-3, hi=30.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    ev = np.exp(rng.uniform(np.log(lo), np.log(hi), n))
+    return Q @ np.diag(ev) @ Q.conj().T, ev, Q
+
+
+def test_adef1_solves_and_reduces_iterations(small):
+    op, phi, sob, C, A = small
+    Nc, nvec = A.shape[0], A.shape[2]
+    rng = np.random.default_rng(70)
+    V0 = rng.standard_normal((6, Nc, nvec)) + 1j * rng.standard_normal((6, Nc, nvec))
+    W = ldop.orthonormal_basis(np.concatenate([ldop.free_global_vectors(Nc, nvec),
+                                               ldop.inverse_iteration(A, C, V0, 3, 0.0, 1e-9)]))
+    Z, Dz, AZ = ldop.third_level(A, C, W)
+    T = ldop.truncate(A, shift=0.1)
+    ev = np.linalg.eigvalsh(crs.to_dense(A, C))
+    lo, hi = 0.5, 1.1 * ev[-1]
+
+    def M(r):
+        return ldop.chebyshev_inverse(lambda u: crs.apply(T, u, C), r, lo, hi, 8)
+
+    b = rng.standard_normal((Nc, nvec)) + 1j * rng.standard_normal((Nc, nvec))
+    x, it, rel = ldop.adef1_solve(A, C, b, Z, Dz, AZ, M, tol=1e-10)
+    xd = np.linalg.solve(crs.to_dense(A, C), b.ravel()).reshape(b.shape)
+    assert rel <= 1e-10 and np.abs(x - xd).max() < 1e-7 * np.abs(xd).max()
+    _, it_d, _ = ldop.deflated_cg(A, C, b, Z, Dz, AZ, tol=1e-10)
+    assert it < it_d, (it, it_d)
+
+
+def test_adef1_is_identity_on_the_deflation_space(small):
+    """M_1 A z = z for z in span(Z): Q A z = z because Z^+ A Z = D, and the
+    M term then acts on A z - A z = 0 (any M, here a plain scaling)."""
+    op, phi, sob, C, A = small
+    Nc, nvec = A.shape[0], A.shape[2]
+    W = ldop.orthonormal_basis(ldop.free_global_vectors(Nc, nvec))
+    Z, Dz, AZ = ldop.third_level(A, C, W)
+    M1 = ldop.adef1_preconditioner(Z, Dz, AZ, lambda r: 0.37 * r)
+    rng = np.random.default_rng(71)
+    coef = rng.standard_normal(len(Z)) + 1j * rng.standard_normal(len(Z))
+    z = np.einsum("k,k...->...", coef, Z)
+    out = M1(crs.apply(A, z, C))
+    assert np.abs(out - z).max() < 1e-11 * np.abs(z).max()
+    # and on a vector A-orthogonal to span(Z) it is M alone
+    v = rng.standard_normal((Nc, nvec)) + 1j * rng.standard_normal((Nc, nvec))
+    v = v - np.einsum("k,k...->...", (Z.reshape(len(Z), -1).conj() @ crs.apply(A, v, C).ravel()) / Dz, Z)
+    out = M1(crs.apply(A, v, C))
+    assert np.abs(out - 0.37 * crs.apply(A, v, C)).max() < 1e-11 * np.abs(v).max()
