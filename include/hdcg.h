@@ -223,6 +223,16 @@ struct hdcg_params {
   int phi_prec;       /* storage of the subspace for the project / promote of the solve's Q:
                          DWF_C64 (default) or DWF_BF16 (bf16 pairs rounded to nearest even
                          from FP64, half the bytes; arithmetic and vectors complex64) */
+  int ldop_m1;        /* 0 (default): deflated coarse solves are deflated CG; 1: ADEF1 with
+                         the Chebyshev approximate inverse of the truncated operator
+                         (Sec. V.B, "Truncated little Dirac operator as preconditioner";
+                         Table "optimised": LdopM1Chebyshev) */
+  double m1_lo;       /* Chebyshev interval low end, default 0.5 (Table "optimised") */
+  double m1_hi;       /* high end; 0 (default): 1.05 x a power-method estimate of the largest
+                         eigenvalue of Q_trunc + m1_shift (the paper's 45 fits its ensemble) */
+  int m1_order;       /* Chebyshev order n, default 16: residual polynomial of degree n,
+                         n - 1 applications of Q_trunc (1..256) */
+  double m1_shift;    /* infra-red shift added to Q_trunc, default 0 (>= 0) */
 };
 
 struct hdcg_stats {
@@ -317,12 +327,41 @@ int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void
 
 /* Replace the solve-phase parameters of a built handle (n_irs, lambda_irs,
  * coarse_tol, coarse_maxiter, flexible, inner_tol, inner_maxiter,
- * outer_maxiter, coarse_prec, irs_prec, ldop_defl, phi_prec); the
- * setup-phase fields of *p are ignored.  Builds the 16-bit copies of A and
- * of the subspace when coarse_prec or phi_prec asks for one not yet built.
+ * outer_maxiter, coarse_prec, irs_prec, ldop_defl, phi_prec and the m1_
+ * fields); the setup-phase fields of *p are ignored.  Builds the 16-bit
+ * copies of A and of the subspace when coarse_prec or phi_prec asks for one
+ * not yet built, and estimates the Chebyshev bound when ldop_m1 = 1 and
+ * m1_hi = 0.
  * Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle is
  * then unchanged). */
 int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream);
+
+/* The truncated little Dirac operator (Sec. V.B, "Truncated little Dirac
+ * operator as preconditioner"; Table "frobnorm"): out = (Q_trunc + m1_shift)
+ * in, Q_trunc keeping of A only the zero- and one-hop terms (the site and its
+ * eight axis neighbours; Hermitian).  in, out: device coarse vectors
+ * c[rhs][a][k], distinct, complex64 or complex128 by prec (DWF_C64 /
+ * DWF_C128), nrhs 1..64.  Builds Q_trunc (a ninth of the bytes of A) on first
+ * use and after a change of m1_shift.  Asynchronous. */
+int hdcg_trunc_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream);
+/* The Chebyshev interval [*lo, *hi] (host) the preconditioner uses: m1_lo,
+ * and m1_hi or, when m1_hi is 0, its estimate (taken once per m1_shift; the
+ * first call synchronises).  DWF_ERR_NUMERIC if the estimate is not above
+ * m1_lo. */
+int hdcg_m1_interval(hdcg_t h, double* lo, double* hi, void* stream);
+/* y = p(Q_trunc + m1_shift) r: m1_order steps of the Chebyshev iteration on
+ * [lo, hi] from y = 0 (residual T_n((d - x)/c) / T_n(d/c) r, d and c the
+ * interval's centre and half-width).  y, r: device coarse vectors as for
+ * hdcg_trunc_apply, distinct; r is not modified.  Asynchronous after the
+ * interval is known. */
+int hdcg_chebyshev(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream);
+/* y = M_1 r, the ADEF1 preconditioner of the coarse solve (Sec. V.B):
+ * p(Q_trunc + m1_shift) (r - A Z D^-1 Z^+ r) + Z D^-1 Z^+ r with the second
+ * level's Z, D and the stored A Z (no application of A).  Arguments as for
+ * hdcg_chebyshev; DWF_ERR_ARG before hdcg_ldop_setup.  With params.ldop_m1 =
+ * 1 every deflated coarse solve is flexible CG preconditioned by M_1 from
+ * x0 = Z D^-1 Z^+ b (alpha = (p, r)/(p, A p), beta = -(A p, y)/(p, A p)). */
+int hdcg_adef1_precondition(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream);
 
 /* Copies for parity checks: the little Dirac operator in the canonical layout
  * A[a][l][j][k] (device, Nc*81*nvec*nvec complex128), the orthonormalised

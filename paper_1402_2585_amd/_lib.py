@@ -46,7 +46,9 @@ class HdcgParams(C.Structure):
                 ("build_batch", C.c_int), ("coarse_prec", C.c_int), ("verbose", C.c_int),
                 ("irs_prec", C.c_int), ("subspace_gen", C.c_int), ("rat_lo", C.c_double),
                 ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
-                ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int)]
+                ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int),
+                ("ldop_m1", C.c_int), ("m1_lo", C.c_double), ("m1_hi", C.c_double), ("m1_order", C.c_int),
+                ("m1_shift", C.c_double)]
 
 
 class HdcgStats(C.Structure):
@@ -102,6 +104,10 @@ def load():
         "hdcg_set_params": (i, [vp, C.POINTER(HdcgParams), vp]),
         "hdcg_ldop_setup": (i, [vp, i, vp, d, i, d, vp]),
         "hdcg_export_ldop": (i, [vp, C.POINTER(C.c_int), vp, dp, vp]),
+        "hdcg_trunc_apply": (i, [vp, vp, vp, i, i, vp]),
+        "hdcg_m1_interval": (i, [vp, dp, dp, vp]),
+        "hdcg_chebyshev": (i, [vp, vp, vp, i, i, vp]),
+        "hdcg_adef1_precondition": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -314,6 +320,24 @@ def hdcg_export_ldop(h, Z=None, stream=None):
     D = (C.c_double * max(n.value, 1))()
     _check(load().hdcg_export_ldop(h, C.byref(n), _ptr(Z), D, _stream(stream)))
     return n.value, np.array(D[:n.value])
+
+
+def hdcg_trunc_apply(h, out, inp, prec, nrhs=1, stream=None):
+    _check(load().hdcg_trunc_apply(h, _ptr(out), _ptr(inp), int(prec), int(nrhs), _stream(stream)))
+
+
+def hdcg_m1_interval(h, stream=None):
+    lo, hi = C.c_double(), C.c_double()
+    _check(load().hdcg_m1_interval(h, C.byref(lo), C.byref(hi), _stream(stream)))
+    return lo.value, hi.value
+
+
+def hdcg_chebyshev(h, y, r, prec, nrhs=1, stream=None):
+    _check(load().hdcg_chebyshev(h, _ptr(y), _ptr(r), int(prec), int(nrhs), _stream(stream)))
+
+
+def hdcg_adef1_precondition(h, y, r, prec, nrhs=1, stream=None):
+    _check(load().hdcg_adef1_precondition(h, _ptr(y), _ptr(r), int(prec), int(nrhs), _stream(stream)))
 
 
 def hdcg_export_coarse(h, out, stream=None):

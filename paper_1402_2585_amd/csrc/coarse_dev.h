@@ -33,21 +33,23 @@ __device__ __forceinline__ void st_coherent(c64* p, c64 v) {
 // out[r][a][j] for r0 <= r < min(r0 + NR, nr).  `red` is kCT * NR complex
 // of LDS.  With STAGED (one right-hand side) `in` is instead the site's
 // operand already gathered into LDS: in[l * nvec + k] = c[nbr(a,l)][k].
-// Every thread of the workgroup must call it.
-template <typename R, int NR, int U, bool STAGED = false>
+// Every thread of the workgroup must call it.  NS is the number of stencil
+// points (the 81 of A, or the 9 of the one-hop truncation): AT holds NS
+// matrices per site and nbr NS neighbours per site.
+template <typename R, int NR, int U, bool STAGED = false, int NS = kStencil>
 __device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr,
                                             const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                             int a, int Nc, int nvec, int nr, int r0, cplx<R>* red) {
   static_assert(!STAGED || NR == 1, "a staged operand holds one right-hand side");
   const int parts = kCT / nvec;
   const int j = threadIdx.x % nvec, part = threadIdx.x / nvec;
-  const int K = kStencil * nvec;
+  const int K = NS * nvec;
   cplx<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
   if (part < parts) {
     const cplx<R>* Aa = AT + (size_t)a * K * nvec + j;
-    const int* nb = nbr + (size_t)a * kStencil;
+    const int* nb = nbr + (size_t)a * NS;
     for (int q0 = part; q0 < K; q0 += parts * U) {
       cplx<R> Av[U], xv[U][NR];
 #pragma unroll

@@ -34,7 +34,7 @@ struct hdcg {
   hdk::DevBuf AT128;          // same layout in complex128 (parity / FP64 use)
   hdk::DevBuf gram, rinv;     // [Nc][nvec][nvec] c128 Cholesky-QR work
   hdk::DevBuf flag;           // int error flag
-  hdk::DevBuf cw[6];          // coarse work vectors (c64/c128)
+  hdk::DevBuf cw[10];         // coarse work vectors (c64/c128); 6-9: truncated-operator preconditioner
   hdk::DevBuf fw64[12];       // fine c64 work fields: 0-7 solver, 8-10 fine CG
   hdk::DevBuf fw128[3];       // fine c128 work fields
   hdk::DevBuf fw16[4];        // fine 16-bit work fields of M_IRS: x, r, p, w
@@ -54,6 +54,12 @@ struct hdcg {
   hdk::DevBuf ldD;                  // double [ng]
   hdk::DevBuf ldc;                  // coefficients [64][1024] complex128
   std::vector<double> ldDh;         // D on the host
+  // the truncated operator Q_trunc + m1_shift (Sec. V.B): zero- and one-hop
+  // terms, TT[a][m][k][j] for the 9 points m, and their neighbour table
+  hdk::DevBuf TT64, TT128, nbr9;
+  double tt_shift64 = __builtin_nan(""), tt_shift128 = __builtin_nan("");  // shift TT was built with
+  double m1_hi_est = 0.0;           // estimated Chebyshev upper bound (m1_hi <= 0)
+  hdk::DevBuf ycw;                  // ADEF1 coarse solve: the preconditioned residual
   double* pinned = nullptr;   // host pinned scalars [16][64]
   struct {
     int n_ii = 0;
@@ -76,6 +82,10 @@ struct hdcg {
     int wall_noise = 0;         // keep only the physical wall components of the noise
     int ldop_defl = 1;          // deflate coarse solves with the second level once it is built
     int phi_prec = DWF_C64;     // subspace storage for the solve's project / promote: C64 or BF16
+    int ldop_m1 = 0;            // 1: deflated coarse solves run ADEF1 with Chebyshev(Q_trunc)
+    double m1_lo = 0.5, m1_hi = 0.0;  // Chebyshev interval (m1_hi <= 0: estimated)
+    int m1_order = 16;          // Chebyshev order (m1_order - 1 truncated mat-vecs)
+    double m1_shift = 0.0;      // infra-red shift added to Q_trunc
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;
@@ -130,6 +140,19 @@ int ensure_at128_impl(hdcg* h, hipStream_t st);  // the complex128 transposed A 
 // after n_steps of (A + shift)^-1 each (coarse CG to tol, at most maxiter)
 int ldop_build(hdcg* h, int n_extra, const cplx<double>* noise, double shift, int n_steps, double tol, int maxiter,
                hipStream_t st);
+// truncated operator and ADEF1 (trunc.hip): out = (Q_trunc + m1_shift) in;
+// y = p(Q_trunc + m1_shift) r (Chebyshev, m1_order, [m1_lo, m1_hi]);
+// y = M_1 r = p(.) (r - A Z D^-1 Z^+ r) + Z D^-1 Z^+ r; the interval in use
+template <typename R>
+int trunc_apply(hdcg* h, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);
+template <typename R>
+int m1_chebyshev(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
+template <typename R>
+int m1_adef1(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
+int m1_bounds(hdcg* h, double* lo, double* hi, hipStream_t st);
+int m1_check_params(int ldop_m1, double lo, double hi, int order, double shift);
+void trunc_invalidate(hdcg* h);  // after a change of m1_shift
+
 // c[rhs][k] = (V_k, r_rhs) / D_k into h->ldc
 template <typename R>
 int ldop_coef(hdcg* h, const cplx<R>* V, const cplx<R>* r, int nr, hipStream_t st);

@@ -28,7 +28,7 @@ Red red_of(dwf_op* op) { return Red{op->red.partials.as<double>(), op->red.count
 // device scalar slots, 128 doubles each (room for 64 right-hand sides x 2)
 enum {
   S_RR0, S_RR1, S_PAP, S_PP,                       // fine CG
-  S_CRR0, S_CRR1, S_CPAP, S_CPP,                    // coarse CG
+  S_CRR0, S_CRR1, S_CPAP, S_CPP, S_CPR, S_CWY,      // coarse CG, coarse ADEF1
   S_ARR, S_APR, S_AWY, S_ARY0, S_ARY1, S_AINIT, S_APW,  // A-DEF2 (own slots: M_IRS runs inside)
   S_ORR, S_OBB,                                     // outer loop
   S_NSLOT
@@ -192,6 +192,85 @@ static int apply_mirs(hdcg* h, c64* z, const c64* r, int nr, int* it, hipStream_
   return fine_cg(h, z, r, nr, h->prm.lambda_irs, h->prm.n_irs, 0.0, 0, it, st);
 }
 
+// ---------------------------------------------------------- coarse ADEF1 --
+// Flexible CG on A x = b preconditioned by ADEF1 with the Chebyshev
+// approximate inverse of the truncated operator (Sec. V.B, "Truncated little
+// Dirac operator as preconditioner"): x0 = Z D^-1 Z^+ b, y = M_1 r, p = y;
+// alpha = (p, r) / (p, A p); beta = -(A p, y) / (p, A p) (the new direction
+// A-orthogonal to the last; M_1 is not symmetric).  Stops at |r| <= tol |b|.
+template <typename R>
+int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol, int maxiter,
+                 int* iters, hipStream_t st, int mprec) {
+  const size_t n = (size_t)h->Nc * h->nvec;
+  for (int i = 0; i < 3; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
+  HDCG_TRY(h->ycw.ensure(n * nr * sizeof(c128)));
+  cplx<R>* r = h->cw[0].as<cplx<R>>();
+  cplx<R>* p = h->cw[1].as<cplx<R>>();
+  cplx<R>* w = h->cw[2].as<cplx<R>>();
+  cplx<R>* y = h->ycw.as<cplx<R>>();
+  const Red red = red_of(h->op);
+  double* rr[2] = {slot(h, S_CRR0), slot(h, S_CRR1)};
+  double* pw = slot(h, S_CPAP);
+  double* pr = slot(h, S_CPR);
+  double* wy = slot(h, S_CWY);
+  const cplx<R>* Z = reinterpret_cast<const cplx<R>*>(sizeof(R) == 8 ? h->ldZ128.ptr : h->ldZ64.ptr);
+  auto matvec = [&](const cplx<R>* in, cplx<R>* out) -> int {
+    if constexpr (sizeof(R) == 4) {
+      if (mprec == DWF_BF16 || mprec == DWF_F16) return crs_apply_mfma(h, mprec, in, out, nr, st);
+    }
+    return crs_apply<R>(h, AT, in, out, nr, st);
+  };
+  HDCG_TRY(b_norm2<R>(red, b, n, nr, rr[0], st));
+  HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 9, rr[0], nr * sizeof(double), hipMemcpyDeviceToHost, st));
+  HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  // x0 = Z D^-1 Z^+ b ; r0 = b - A x0 ; p0 = y0 = M_1 r0
+  HDCG_TRY(ldop_coef<R>(h, Z, b, nr, st));
+  HDCG_TRY(ldop_apply<R>(h, x, nullptr, nullptr, nullptr, Z, nr, 1.0, false, st));
+  HDCG_TRY(matvec(x, w));
+  HDCG_TRY(b_axpby<R>(r, w, -1.0, 1.0, n * nr, st));
+  HDCG_TRY(m1_adef1<R>(h, y, r, nr, st));
+  HDCG_HIP(hipMemcpyAsync(p, y, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  HDCG_HIP(hipStreamSynchronize(st));
+  std::vector<double> bb(h->pinned + 64 * 9, h->pinned + 64 * 9 + nr);
+  bool any = false;
+  for (double v : bb) any = any || v > 0.0;
+  int k = 0;
+  if (any) {
+    LagRing ring;
+    HDCG_TRY(ring.init(h->pinned, nr));
+    bool done = false;
+    while (!done && k < maxiter) {
+      double* nxt = rr[(k + 1) & 1];
+      HDCG_TRY(matvec(p, w));
+      HDCG_TRY(b_dot<R>(red, p, w, n, nr, pw, st));
+      HDCG_TRY(b_dot<R>(red, p, r, n, nr, pr, st));
+      HDCG_TRY(b_update<R>(red, x, r, p, w, n, nr, pr, true, pw, nullptr, 0.0, nxt, st, 2));
+      HDCG_TRY(m1_adef1<R>(h, y, r, nr, st));
+      HDCG_TRY(b_dot<R>(red, w, y, n, nr, wy, st));
+      HDCG_TRY(b_xpay<R>(red, p, y, n, nr, wy, true, pw, -1.0, nullptr, st, 2));
+      ++k;
+      HDCG_TRY(ring.push(nxt, st));
+      while (ring.checked < ring.queued && (ring.queued - ring.checked > 2 || k >= maxiter)) {
+        const double* v;
+        HDCG_TRY(ring.pop(&v));
+        bool conv = true;
+        for (int i = 0; i < nr; ++i) {
+          if (!std::isfinite(v[i])) return fail(DWF_ERR_NUMERIC, "coarse ADEF1 residual not finite");
+          if (v[i] > tol * tol * bb[i]) conv = false;
+        }
+        if (conv) {
+          done = true;
+          break;
+        }
+      }
+    }
+  } else {
+    HDCG_TRY(b_zero<R>(x, n * nr, st));
+  }
+  if (iters) *iters = k;
+  return DWF_OK;
+}
+
 // -------------------------------------------------------------- coarse CG --
 // CG on (A + shift) x = b from x = 0 (shift >= 0; the coarse operator in the
 // storage mprec selects for complex64).  With the second deflation level
@@ -201,6 +280,7 @@ template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
               int maxiter, int* iters, hipStream_t st, int mprec = -1, double shift = 0.0) {
   const bool defl = h->ng > 0 && h->prm.ldop_defl != 0 && shift == 0.0;
+  if (defl && h->prm.ldop_m1 == 1) return coarse_adef1<R>(h, AT, x, b, nr, tol, maxiter, iters, st, mprec);
   if constexpr (sizeof(R) == 4) {
     if (h->persistent_coarse && !defl && shift == 0.0) {
       int done = 0;
@@ -459,6 +539,11 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->wall_noise = 0;
   p->ldop_defl = 1;
   p->phi_prec = DWF_C64;
+  p->ldop_m1 = 0;
+  p->m1_lo = 0.5;
+  p->m1_hi = 0.0;
+  p->m1_order = 16;
+  p->m1_shift = 0.0;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -493,6 +578,10 @@ int hdcg_destroy(hdcg_t h) {
   h->ldAZ64.release();
   h->ldD.release();
   h->ldc.release();
+  h->TT64.release();
+  h->TT128.release();
+  h->nbr9.release();
+  h->ycw.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return DWF_OK;
@@ -737,10 +826,20 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.wall_noise = p->wall_noise;
     h->prm.ldop_defl = p->ldop_defl;
     h->prm.phi_prec = p->phi_prec;
+    h->prm.ldop_m1 = p->ldop_m1;
+    h->prm.m1_lo = p->m1_lo;
+    h->prm.m1_hi = p->m1_hi;
+    h->prm.m1_order = p->m1_order;
+    h->prm.m1_shift = p->m1_shift;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
   if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec, h->prm.phi_prec); rc < 0) {
+    delete h;
+    return rc;
+  }
+  if (const int rc = m1_check_params(h->prm.ldop_m1, h->prm.m1_lo, h->prm.m1_hi, h->prm.m1_order, h->prm.m1_shift);
+      rc < 0) {
     delete h;
     return rc;
   }
@@ -897,6 +996,7 @@ int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
 int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   if (!h || !p) return fail(DWF_ERR_ARG, "null argument to hdcg_set_params");
   HDCG_TRY(check_solve_params(p->coarse_prec, p->irs_prec, p->phi_prec));
+  HDCG_TRY(m1_check_params(p->ldop_m1, p->m1_lo, p->m1_hi, p->m1_order, p->m1_shift));
   if (p->n_irs < 0 || p->coarse_maxiter < 1 || p->inner_maxiter < 1 || p->outer_maxiter < 1 ||
       !(p->coarse_tol > 0.0) || !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
     return fail(DWF_ERR_ARG, "hdcg_set_params: iteration caps must be positive, tolerances in (0, 1)");
@@ -917,7 +1017,47 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.irs_prec = p->irs_prec;
   h->prm.ldop_defl = p->ldop_defl;
   h->prm.phi_prec = p->phi_prec;
+  if (p->m1_shift != h->prm.m1_shift) trunc_invalidate(h);
+  h->prm.ldop_m1 = p->ldop_m1;
+  h->prm.m1_lo = p->m1_lo;
+  h->prm.m1_hi = p->m1_hi;
+  h->prm.m1_order = p->m1_order;
+  h->prm.m1_shift = p->m1_shift;
+  // the estimated Chebyshev bound (m1_hi <= 0) is taken now, not inside a solve
+  if (h->prm.ldop_m1 == 1 && h->prm.m1_hi <= 0.0) {
+    double lo = 0, hi = 0;
+    HDCG_TRY(m1_bounds(h, &lo, &hi, st));
+  }
   return DWF_OK;
+}
+
+int hdcg_trunc_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!out || !in || out == in) return fail(DWF_ERR_ARG, "hdcg_trunc_apply needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128) return trunc_apply<double>(h, static_cast<const c128*>(in), static_cast<c128*>(out), nrhs, st);
+  return trunc_apply<float>(h, static_cast<const c64*>(in), static_cast<c64*>(out), nrhs, st);
+}
+
+int hdcg_m1_interval(hdcg_t h, double* lo, double* hi, void* stream) {
+  if (!h || !lo || !hi) return fail(DWF_ERR_ARG, "null argument to hdcg_m1_interval");
+  return m1_bounds(h, lo, hi, static_cast<hipStream_t>(stream));
+}
+
+int hdcg_chebyshev(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!y || !r || y == r) return fail(DWF_ERR_ARG, "hdcg_chebyshev needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128) return m1_chebyshev<double>(h, static_cast<c128*>(y), static_cast<const c128*>(r), nrhs, st);
+  return m1_chebyshev<float>(h, static_cast<c64*>(y), static_cast<const c64*>(r), nrhs, st);
+}
+
+int hdcg_adef1_precondition(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!y || !r || y == r) return fail(DWF_ERR_ARG, "hdcg_adef1_precondition needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128) return m1_adef1<double>(h, static_cast<c128*>(y), static_cast<const c128*>(r), nrhs, st);
+  return m1_adef1<float>(h, static_cast<c64*>(y), static_cast<const c64*>(r), nrhs, st);
 }
 
 int hdcg_ldop_setup(hdcg_t h, int n_extra, const void* noise_c128, double shift, int n_steps, double tol,

@@ -348,6 +348,96 @@ def test_ldop_second_level_against_oracle(two_level):
         h.set_params(ldop_defl=0)
 
 
+def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
+    """The truncated little Dirac operator and ADEF1 (Sec. V.B, "Truncated
+    little Dirac operator as preconditioner") against the oracle on its own
+    A: Q_trunc + 0.2 on three right-hand sides (complex128 1e-12, complex64
+    1e-5); the estimated Chebyshev bound against the largest eigenvalue of
+    the dense Q_trunc (from below, within 10%, times 1.05); with hi fixed by
+    the test to 1.1 x that eigenvalue, the Chebyshev inverse of orders 1, 5
+    and 16 (complex128 1e-10, complex64 1e-4) and M_1 on the second level
+    built from the same coarse noise (complex128 1e-6: the two Z agree to
+    about 1e-8); the ADEF1 coarse solve against a dense solve (complex128 to
+    1e-10: 1e-7; complex64 to 1e-5 on three right-hand sides: 1e-3), in no
+    more iterations than deflated CG; and a full solve with it to 1e-8."""
+    from oracle import ldop as oldop
+
+    t = two_level
+    banner(f"truncated operator / Chebyshev / ADEF1 {t['name']}")
+    h, A, C, op, ref = t["h"], t["A"], t["C"], t["op"], t["ref"]
+    Nc, nvec = A.shape[0], A.shape[2]
+    shift = 0.2
+    T = oldop.truncate(A, shift)
+    lmax = np.linalg.eigvalsh(ocrs.to_dense(T, C))[-1]
+    precs = ((hd.DWF_C128, torch.complex128), (hd.DWF_C64, torch.complex64))
+    try:
+        h.set_params(m1_shift=shift, m1_hi=0.0, m1_lo=0.5, m1_order=16)
+        v = synth.gaussian_coarse(Nc, nvec, 370, 3)
+        want = np.array([ocrs.apply(T, vi, C) for vi in v])
+        for (prec, dt), tol in zip(precs, (1e-12, 1e-5)):
+            out = h.new_coarse(prec, 3)
+            hd.hdcg_trunc_apply(h.h, out, torch.from_numpy(v).to(dt).to("cuda"), prec, 3)
+            err = rel_err(out.cpu().numpy(), want)
+            print(f"Q_trunc prec={prec}: rel err {err:.2e}", flush=True)
+            assert err < tol
+        lo, hi_est = hd.hdcg_m1_interval(h.h)
+        print(f"Chebyshev interval [{lo}, {hi_est:.4f}], lambda_max(Q_trunc) {lmax:.4f}", flush=True)
+        assert lo == 0.5 and 0.9 * lmax <= hi_est / 1.05 <= lmax * (1 + 1e-6)
+        hi = 1.1 * lmax
+        r = synth.gaussian_coarse(Nc, nvec, 371, 2)
+        for n in (1, 5, 16):
+            h.set_params(m1_hi=hi, m1_order=n)
+            want = np.array([oldop.chebyshev_inverse(lambda u: ocrs.apply(T, u, C), ri, lo, hi, n) for ri in r])
+            for (prec, dt), tol in zip(precs, (1e-10, 1e-4)):
+                y = h.new_coarse(prec, 2)
+                hd.hdcg_chebyshev(h.h, y, torch.from_numpy(r).to(dt).to("cuda"), prec, 2)
+                err = rel_err(y.cpu().numpy(), want)
+                print(f"Chebyshev order {n} prec={prec}: rel err {err:.2e}", flush=True)
+                assert err < tol
+        # M_1 on the second level built from the same noise
+        noise = synth.gaussian_coarse(Nc, nvec, 372, 6)
+        hd.hdcg_ldop_setup(h.h, 6, torch.from_numpy(noise).to("cuda"), 0.0, 3, 1e-12)
+        Vi = oldop.inverse_iteration(A, C, noise, n_steps=3, shift=0.0, tol=1e-12)
+        W = oldop.orthonormal_basis(np.concatenate([oldop.free_global_vectors(Nc, nvec), Vi]))
+        Z, Dz, AZ = oldop.third_level(A, C, W)
+        M = lambda u: oldop.chebyshev_inverse(lambda q: ocrs.apply(T, q, C), u, lo, hi, 16)
+        M1 = oldop.adef1_preconditioner(Z, Dz, AZ, M)
+        want = np.array([M1(ri) for ri in r])
+        y = h.new_coarse(hd.DWF_C128, 2)
+        hd.hdcg_adef1_precondition(h.h, y, torch.from_numpy(r).to("cuda"), hd.DWF_C128, 2)
+        err = rel_err(y.cpu().numpy(), want)
+        print(f"M_1 complex128: rel err {err:.2e}", flush=True)
+        assert err < 1e-6
+        # the ADEF1 coarse solve
+        b = synth.gaussian_coarse(Nc, nvec, 373, 3)
+        xd = np.array([np.linalg.solve(ocrs.to_dense(A, C), bi.ravel()).reshape(bi.shape) for bi in b])
+        h.set_params(ldop_defl=1, ldop_m1=0)
+        x = h.new_coarse(hd.DWF_C128)
+        rc, it_d = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b[:1]).to("cuda"), hd.DWF_C128, 1, 1e-10, 2000)
+        assert rc == 0
+        h.set_params(ldop_m1=1)
+        x = h.new_coarse(hd.DWF_C128)
+        rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b[:1]).to("cuda"), hd.DWF_C128, 1, 1e-10, 2000)
+        err = rel_err(x.cpu().numpy()[0], xd[0])
+        print(f"ADEF1 coarse solve complex128: {it} iterations (deflated CG {it_d}), rel err {err:.2e}", flush=True)
+        assert rc == 0 and err < 1e-7 and it <= it_d
+        x = h.new_coarse(hd.DWF_C64, 3)
+        rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to(torch.complex64).to("cuda"), hd.DWF_C64, 3,
+                                      1e-5, 2000)
+        err = rel_err(x.cpu().numpy(), xd)
+        print(f"ADEF1 coarse solve complex64, 3 rhs: {it} iterations, rel err {err:.2e}", flush=True)
+        assert rc == 0 and err < 1e-3
+        bf = synth.gaussian_half_field(t["dims"], t["Ls"], 374)
+        xf = op.new_field()
+        rcs, st = hd.hdcg_solve(h.h, xf, op.to_native(bf), 1, 1e-8)
+        print("hdcg_solve with ADEF1 coarse solves", st, flush=True)
+        assert rcs == 0 and st["converged"] == 1
+        rf = bf - ref.H(op.to_canonical(xf).cpu().numpy())
+        assert np.sqrt(np.vdot(rf, rf).real / np.vdot(bf, bf).real) <= 1e-8
+    finally:
+        h.set_params(ldop_m1=0, ldop_defl=0, m1_shift=0.0, m1_hi=0.0, m1_order=16)
+
+
 def test_ldop_deflation_cuts_coarse_iterations():
     """On a subspace after inverse iteration (A then has the low modes the
     second level is for), deflated coarse CG needs fewer iterations than
@@ -368,6 +458,14 @@ def test_ldop_deflation_cuts_coarse_iterations():
     print(f"coarse CG iterations: plain {it0}, deflated {it1}", flush=True)
     assert rc == 0 and rc1 == 0 and it1 < it0
     assert rel_err(x1.cpu().numpy(), x0.cpu().numpy()) < 1e-8
+    # ADEF1 with the Chebyshev inverse of Q_trunc (estimated interval)
+    h.set_params(ldop_m1=1)
+    lo, hi = hd.hdcg_m1_interval(h.h)
+    x2 = h.new_coarse(hd.DWF_C128)
+    rc2, it2 = hd.hdcg_coarse_solve(h.h, x2, b, hd.DWF_C128, 1, 1e-10, 5000)
+    print(f"ADEF1 coarse iterations {it2} on [{lo}, {hi:.3f}]", flush=True)
+    assert rc2 == 0 and rel_err(x2.cpu().numpy(), x0.cpu().numpy()) < 1e-8
+    h.set_params(ldop_m1=0)
     ref = DWF(U, dims, Ls, 1.8, mass)
     bf = synth.gaussian_half_field(dims, Ls, 365)
     x = op.new_field()
