@@ -71,6 +71,11 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_1402_2585_amd.build.build() first")
+    # PyTorch ships its own HIP runtime, which its libraries request under a
+    # name the dynamic loader does not match to the system runtime's soname.
+    # Loaded first, the library would bring in the system runtime and torch a
+    # second one; with torch loaded first the library binds to torch's copy.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i, d, sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
     dp = C.POINTER(C.c_double)

@@ -188,7 +188,13 @@ def run_variants(a, torch, synth, hd, w, op, h, b):
     solve("16-bit M_IRS fields + second level")
     h.set_params(phi_prec=hd.DWF_BF16)
     solve("16-bit M_IRS fields + second level + 16-bit subspace in Q")
-    h.set_params(irs_prec=hd.DWF_C64, phi_prec=hd.DWF_C64)
+    h.set_params(ldop_m1=1)
+    lo, hi = hd.hdcg_m1_interval(h.h)
+    print(f"ADEF1 Chebyshev interval [{lo}, {hi:.3f}]", flush=True)
+    for order in (16, 8):
+        h.set_params(m1_order=order)
+        solve(f"16-bit M_IRS fields + second level (ADEF1, Chebyshev order {order}) + 16-bit subspace in Q")
+    h.set_params(ldop_m1=0, m1_order=16, irs_prec=hd.DWF_C64, phi_prec=hd.DWF_C64)
     solve("second level")
 
 
