@@ -99,6 +99,51 @@ k_cheb_step(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const 
   }
 }
 
+// The same for one right-hand side with the operand at the nine points first
+// gathered into LDS (one coalesced pass), so the column loop streams only the
+// operator.
+constexpr int kStageNvec = 64;
+template <typename R, int U>
+__global__ void __launch_bounds__(kCT)
+k_cheb_step1(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const cplx<R>* __restrict__ dcur,
+             cplx<R>* __restrict__ dnext, cplx<R>* __restrict__ res, cplx<R>* __restrict__ y, cplx<R>* __restrict__ tw,
+             int Nc, int nvec, double ca, double cb) {
+  __shared__ cplx<R> red[kCT];
+  __shared__ cplx<R> s_in[kTS * kStageNvec];
+  const int a = blockIdx.x;
+  const int* nb = nbr9 + (size_t)a * kTS;
+  for (int e = threadIdx.x; e < kTS * nvec; e += kCT) {
+    const int m = e / nvec;
+    s_in[e] = dcur[(size_t)nb[m] * nvec + (e - m * nvec)];
+  }
+  __syncthreads();
+  capply_site<R, 1, U, true, kTS>(TT, nbr9, s_in, tw, a, Nc, nvec, 1, 0, red);
+  if (threadIdx.x >= nvec) return;
+  const size_t idx = (size_t)a * nvec + threadIdx.x;
+  const cplx<R> t = tw[idx], rv = res[idx], dv = s_in[threadIdx.x], yv = y[idx];  // point 0 is the site
+  const double rre = (double)rv.re - t.re, rim = (double)rv.im - t.im;
+  const double dre = ca * rre + cb * dv.re, dim = ca * rim + cb * dv.im;
+  res[idx] = cmk((R)rre, (R)rim);
+  dnext[idx] = cmk((R)dre, (R)dim);
+  y[idx] = cmk((R)(yv.re + dre), (R)(yv.im + dim));
+}
+
+template <typename R, int U>
+__global__ void __launch_bounds__(kCT)
+k_trunc_apply1(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const cplx<R>* __restrict__ in,
+               cplx<R>* __restrict__ out, int Nc, int nvec) {
+  __shared__ cplx<R> red[kCT];
+  __shared__ cplx<R> s_in[kTS * kStageNvec];
+  const int a = blockIdx.x;
+  const int* nb = nbr9 + (size_t)a * kTS;
+  for (int e = threadIdx.x; e < kTS * nvec; e += kCT) {
+    const int m = e / nvec;
+    s_in[e] = in[(size_t)nb[m] * nvec + (e - m * nvec)];
+  }
+  __syncthreads();
+  capply_site<R, 1, U, true, kTS>(TT, nbr9, s_in, out, a, Nc, nvec, 1, 0, red);
+}
+
 // d1 = u / d; y = d1 (acc = 0) or y += d1 (acc = 1)
 template <typename R>
 __global__ void k_cheb_first(cplx<R>* __restrict__ d1, cplx<R>* __restrict__ y, const cplx<R>* __restrict__ u,
@@ -152,6 +197,12 @@ constexpr int kMaxOrder = 256;
 
 template <typename R>
 int trunc_launch(hdcg* h, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st) {
+  if (nr == 1 && h->nvec <= kStageNvec) {
+    hipLaunchKernelGGL((k_trunc_apply1<R, 16>), dim3(h->Nc), dim3(kCT), 0, st, tt_buf<R>(h).template as<cplx<R>>(),
+                       h->nbr9.as<int>(), in, out, h->Nc, h->nvec);
+    HDCG_HIP(hipGetLastError());
+    return DWF_OK;
+  }
   constexpr int NR = sizeof(R) == 8 ? 2 : 4;
   hipLaunchKernelGGL((k_trunc_apply<R, NR, 8>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st,
                      tt_buf<R>(h).template as<cplx<R>>(), h->nbr9.as<int>(), in, out, h->Nc, h->nvec, nr);
@@ -175,6 +226,13 @@ int cheb_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, double lo, doubl
   double omega = 2.0;
   for (int k = 1; k < h->prm.m1_order; ++k) {
     omega = 1.0 / (1.0 - omega / (4.0 * sigma * sigma));
+    if (nr == 1 && h->nvec <= kStageNvec) {
+      hipLaunchKernelGGL((k_cheb_step1<R, 16>), dim3(h->Nc), dim3(kCT), 0, st, tt_buf<R>(h).template as<cplx<R>>(),
+                         h->nbr9.as<int>(), dl[(k - 1) & 1], dl[k & 1], u, y, tw, h->Nc, h->nvec, omega / d,
+                         omega - 1.0);
+      HDCG_HIP(hipGetLastError());
+      continue;
+    }
     hipLaunchKernelGGL((k_cheb_step<R, NR, 8>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st,
                        tt_buf<R>(h).template as<cplx<R>>(), h->nbr9.as<int>(), dl[(k - 1) & 1], dl[k & 1], u, y, tw,
                        h->Nc, h->nvec, nr, omega / d, omega - 1.0);

@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos"], default="H")
+    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos", "coarse"], default="H")
     ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
@@ -70,6 +70,9 @@ def main():
         return
     if a.what == "lanczos":
         run_lanczos(a, torch, synth)
+        return
+    if a.what == "coarse":
+        run_coarse(a, torch, synth)
         return
 
     dims = tuple(a.dims)
@@ -191,11 +194,51 @@ def run_variants(a, torch, synth, hd, w, op, h, b):
     h.set_params(ldop_m1=1)
     lo, hi = hd.hdcg_m1_interval(h.h)
     print(f"ADEF1 Chebyshev interval [{lo}, {hi:.3f}]", flush=True)
-    for order in (16, 8):
+    for order in (16, 8, 4):
         h.set_params(m1_order=order)
         solve(f"16-bit M_IRS fields + second level (ADEF1, Chebyshev order {order}) + 16-bit subspace in Q")
     h.set_params(ldop_m1=0, m1_order=16, irs_prec=hd.DWF_C64, phi_prec=hd.DWF_C64)
     solve("second level")
+
+
+def run_coarse(a, torch, synth):
+    """Times the coarse-grid kernels of a numbered workload (subspace: the
+    seeded vectors, orthonormalised, no inverse iteration): the little Dirac
+    operator mat-vec, its one-hop truncation and the Chebyshev inverse
+    (order 16 on [0.5, 45]), complex64, one right-hand side, --reps each."""
+    import time
+
+    import numpy as np
+
+    from synth.configs import WORKLOADS
+
+    w = WORKLOADS[a.workload]
+    U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
+    V = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k))
+                                   for k in range(w.nvec)])).to("cuda")
+    torch.cuda.synchronize()
+    import paper_1402_2585_amd as hd
+
+    op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
+    h = hd.HDCG(op, w.block, V, n_ii=0)
+    del V
+    h.set_params(m1_lo=0.5, m1_hi=45.0, m1_order=16)
+    x = torch.from_numpy(synth.gaussian_coarse(h.Nc, h.nvec, w.coarse_seed, 1)).to(torch.complex64).to("cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    print(f"coarse grid Nc {h.Nc} nvec {h.nvec}", flush=True)
+    for name, fn in (("A mat-vec", lambda: hd.coarse_apply(h.h, y, x, hd.DWF_C64)),
+                     ("Q_trunc mat-vec", lambda: hd.hdcg_trunc_apply(h.h, y, x, hd.DWF_C64)),
+                     ("Chebyshev order 16", lambda: hd.hdcg_chebyshev(h.h, y, x, hd.DWF_C64))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.reps):
+            fn()
+        torch.cuda.synchronize()
+        print(f"{name}: {(time.perf_counter() - t0) / a.reps * 1e3:.3f} ms", flush=True)
+    h.close()
+    op.close()
 
 
 def run_lanczos(a, torch, synth):

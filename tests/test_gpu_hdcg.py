@@ -351,11 +351,12 @@ def test_ldop_second_level_against_oracle(two_level):
 def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
     """The truncated little Dirac operator and ADEF1 (Sec. V.B, "Truncated
     little Dirac operator as preconditioner") against the oracle on its own
-    A: Q_trunc + 0.2 on three right-hand sides (complex128 1e-12, complex64
-    1e-5); the estimated Chebyshev bound against the largest eigenvalue of
+    A: Q_trunc + 0.2 on one and three right-hand sides (complex128 1e-12,
+    complex64 1e-5); the estimated Chebyshev bound against the largest eigenvalue of
     the dense Q_trunc (from below, within 10%, times 1.05); with hi fixed by
     the test to 1.1 x that eigenvalue, the Chebyshev inverse of orders 1, 5
-    and 16 (complex128 1e-10, complex64 1e-4) and M_1 on the second level
+    and 16 on one and two right-hand sides (complex128 1e-10, complex64 1e-4)
+    and M_1 on the second level
     built from the same coarse noise (complex128 1e-6: the two Z agree to
     about 1e-8); the ADEF1 coarse solve against a dense solve (complex128 to
     1e-10: 1e-7; complex64 to 1e-5 on three right-hand sides: 1e-3), in no
@@ -375,11 +376,12 @@ def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
         v = synth.gaussian_coarse(Nc, nvec, 370, 3)
         want = np.array([ocrs.apply(T, vi, C) for vi in v])
         for (prec, dt), tol in zip(precs, (1e-12, 1e-5)):
-            out = h.new_coarse(prec, 3)
-            hd.hdcg_trunc_apply(h.h, out, torch.from_numpy(v).to(dt).to("cuda"), prec, 3)
-            err = rel_err(out.cpu().numpy(), want)
-            print(f"Q_trunc prec={prec}: rel err {err:.2e}", flush=True)
-            assert err < tol
+            for nr in (1, 3):  # one right-hand side takes the LDS-staged kernel
+                out = h.new_coarse(prec, nr)
+                hd.hdcg_trunc_apply(h.h, out, torch.from_numpy(v[:nr]).to(dt).to("cuda"), prec, nr)
+                err = rel_err(out.cpu().numpy(), want[:nr])
+                print(f"Q_trunc prec={prec} nrhs={nr}: rel err {err:.2e}", flush=True)
+                assert err < tol
         lo, hi_est = hd.hdcg_m1_interval(h.h)
         print(f"Chebyshev interval [{lo}, {hi_est:.4f}], lambda_max(Q_trunc) {lmax:.4f}", flush=True)
         assert lo == 0.5 and 0.9 * lmax <= hi_est / 1.05 <= lmax * (1 + 1e-6)
@@ -389,11 +391,12 @@ def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
             h.set_params(m1_hi=hi, m1_order=n)
             want = np.array([oldop.chebyshev_inverse(lambda u: ocrs.apply(T, u, C), ri, lo, hi, n) for ri in r])
             for (prec, dt), tol in zip(precs, (1e-10, 1e-4)):
-                y = h.new_coarse(prec, 2)
-                hd.hdcg_chebyshev(h.h, y, torch.from_numpy(r).to(dt).to("cuda"), prec, 2)
-                err = rel_err(y.cpu().numpy(), want)
-                print(f"Chebyshev order {n} prec={prec}: rel err {err:.2e}", flush=True)
-                assert err < tol
+                for nr in (1, 2):
+                    y = h.new_coarse(prec, nr)
+                    hd.hdcg_chebyshev(h.h, y, torch.from_numpy(r[:nr]).to(dt).to("cuda"), prec, nr)
+                    err = rel_err(y.cpu().numpy(), want[:nr])
+                    print(f"Chebyshev order {n} prec={prec} nrhs={nr}: rel err {err:.2e}", flush=True)
+                    assert err < tol
         # M_1 on the second level built from the same noise
         noise = synth.gaussian_coarse(Nc, nvec, 372, 6)
         hd.hdcg_ldop_setup(h.h, 6, torch.from_numpy(noise).to("cuda"), 0.0, 3, 1e-12)
