@@ -219,9 +219,15 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     t_ldop = time.perf_counter() - t0
     del noise
     ldop = {"global_vectors": w.nvec + n_extra, "setup_seconds": round(t_ldop, 3)}
-    for name, iprec, pprec in (("c64_mirs", hd.DWF_C64, hd.DWF_C64), ("bf16_mirs", hd.DWF_BF16, hd.DWF_C64),
-                               ("bf16_mirs_bf16_subspace", hd.DWF_BF16, hd.DWF_BF16)):
-        h.set_params(irs_prec=iprec, ldop_defl=1, phi_prec=pprec)
+    # the last two: the coarse solves by ADEF1 with the Chebyshev inverse of
+    # the one-hop truncated operator (Sec. V.B; Table "optimised" uses order
+    # 16), interval [0.5, 1.05 x estimated largest eigenvalue]
+    for name, iprec, pprec, m1, order in (
+            ("c64_mirs", hd.DWF_C64, hd.DWF_C64, 0, 16), ("bf16_mirs", hd.DWF_BF16, hd.DWF_C64, 0, 16),
+            ("bf16_mirs_bf16_subspace", hd.DWF_BF16, hd.DWF_BF16, 0, 16),
+            ("bf16_mirs_bf16_subspace_adef1_cheb16", hd.DWF_BF16, hd.DWF_BF16, 1, 16),
+            ("bf16_mirs_bf16_subspace_adef1_cheb8", hd.DWF_BF16, hd.DWF_BF16, 1, 8)):
+        h.set_params(irs_prec=iprec, ldop_defl=1, phi_prec=pprec, ldop_m1=m1, m1_order=order)
         x5 = op.new_field(zero=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
