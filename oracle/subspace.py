@@ -25,6 +25,13 @@ wall_mask(h)                   keep only P- at s = 0 and P+ at s = Ls - 1
 multishift_cg(apply, b, ...)   CG for (A + s_j) x_j = b, all j from one Krylov space
 rational_filter(op, eta, ...)  the filter by one multi-shift solve and the sum
 rational_filter_product(...)   the filter as four successive shifted CG solves
+surface_truncate(V, depth)     remove the fifth-dimension interior of subspace vectors
+
+Surface truncation (the closing paragraph of the subsection): the filtered
+vectors are bound to the walls, so the interior slices depth <= s < Ls - depth
+of the subspace vectors may be set to zero, which cuts the bytes of the
+projection to and from the coarse problem by Ls / (2 depth); a depth with
+2 depth >= Ls keeps every slice.
 """
 from __future__ import annotations
 
@@ -136,3 +143,13 @@ def rational_filter_product(op, eta, lam=3e-4, eps=1e-4, tol=1e-12, wall=False):
     for s in shifts_of(lam, eps):
         v, _, _ = cg(lambda u, s=s: op.H(u) + s * u, v, tol=tol)
     return v
+
+
+def surface_truncate(V, depth):
+    """V (..., Ls, Vh, 4, 3) with the slices depth <= s < Ls - depth set to
+    zero (a copy; unchanged when 2 depth >= Ls)."""
+    out = np.array(V, copy=True)
+    Ls = out.shape[-4]
+    if 2 * depth < Ls:
+        out[..., depth:Ls - depth, :, :, :] = 0
+    return out

@@ -124,3 +124,33 @@ def test_filtered_vectors_are_low_modes():
         rq_eta = np.vdot(src, op.H(src)).real / np.vdot(src, src).real
         rq_phi = np.vdot(phi, op.H(phi)).real
         assert rq_phi < 1e-2 * rq_eta, (wall, rq_phi, rq_eta)
+
+
+def test_surface_truncation():
+    """Zero interior, untouched surface, identity when 2 depth >= Ls; the
+    block orthonormalisation of truncated vectors keeps the interior zero
+    (it only combines vectors within a block); and on the wall-noise
+    filtered vectors of a 4^4 x Ls12 operator most of the norm sits on the
+    two wall slices, the property the truncation relies on."""
+    from oracle import blocks as oblk
+    from oracle.dwf import DWF
+
+    dims, Ls = (4, 4, 4, 4), 12
+    V = synth.gaussian_half_field(dims, Ls, 420, nrhs=3)
+    T = sub.surface_truncate(V, 4)
+    assert np.array_equal(T[:, :4], V[:, :4]) and np.array_equal(T[:, Ls - 4:], V[:, Ls - 4:])
+    assert not T[:, 4:Ls - 4].any()
+    for d in (6, 7, 12):
+        assert np.array_equal(sub.surface_truncate(V, d), V)
+    Vb = synth.gaussian_half_field((8, 8, 8, 8), 10, 421, nrhs=3)
+    _, _, sob = oblk.block_map((8, 8, 8, 8), (4, 4, 4, 4))
+    phi = oblk.orthonormalise(sub.surface_truncate(Vb, 3), sob)
+    assert not phi[:, 3:7].any()
+    F = phi.reshape(3, -1)
+    G = F.conj() @ F.T  # all blocks summed: Nblocks x identity
+    assert np.abs(G - (2 ** 4) * np.eye(3)).max() < 1e-10
+    U = synth.gauge_field(dims, 0.5, 300)
+    op = DWF(U, dims, Ls, 1.8, 0.01)
+    phi, _ = sub.rational_filter(op, synth.gaussian_half_field(dims, Ls, 400), tol=1e-6, wall=True)
+    prof = np.array([np.vdot(phi[s].ravel(), phi[s].ravel()).real for s in range(Ls)])
+    assert prof[0] + prof[-1] > 0.5 * prof.sum()
