@@ -233,6 +233,11 @@ struct hdcg_params {
   int m1_order;       /* Chebyshev order n, default 16: residual polynomial of degree n,
                          n - 1 applications of Q_trunc (1..256) */
   double m1_shift;    /* infra-red shift added to Q_trunc, default 0 (>= 0) */
+  int surface_depth;  /* d > 0 with 2 d < Ls: the subspace keeps only the slices s < d and
+                         s >= Ls - d (Sec. IV.B, the interior of the wall-bound vectors
+                         removed before block orthonormalisation), and the solve's project /
+                         promote read a surface-only copy, Ls / (2 d) times fewer bytes;
+                         d must then be a multiple of 4.  0 (default) or 2 d >= Ls: all slices */
 };
 
 struct hdcg_stats {

@@ -48,7 +48,7 @@ class HdcgParams(C.Structure):
                 ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
                 ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int),
                 ("ldop_m1", C.c_int), ("m1_lo", C.c_double), ("m1_hi", C.c_double), ("m1_order", C.c_int),
-                ("m1_shift", C.c_double)]
+                ("m1_shift", C.c_double), ("surface_depth", C.c_int)]
 
 
 class HdcgStats(C.Structure):

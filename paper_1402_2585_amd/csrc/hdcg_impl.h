@@ -29,6 +29,8 @@ struct hdcg {
   hdk::DevBuf nbr;            // int [Nc][81]
   hdk::DevBuf phi128, phi64;  // [Nc][nvec][nb]
   hdk::DevBuf phi16;          // the same in 16 bits (bf16 pairs) when phi_prec asks for it
+  int sd = 0;                 // surface depth in force (0: every s slice of the subspace kept)
+  hdk::DevBuf phis64, phis16; // the solve's subspace, surface slices only (sd > 0): [Nc][nvec][nsb][12][2 sd]
   hdk::DevBuf A128;           // [Nc][81][nvec][nvec]
   hdk::DevBuf AT64;           // [Nc][81][nvec][nvec] transposed per l
   hdk::DevBuf AT128;          // same layout in complex128 (parity / FP64 use)
@@ -86,6 +88,7 @@ struct hdcg {
     double m1_lo = 0.5, m1_hi = 0.0;  // Chebyshev interval (m1_hi <= 0: estimated)
     int m1_order = 16;          // Chebyshev order (m1_order - 1 truncated mat-vecs)
     double m1_shift = 0.0;      // infra-red shift added to Q_trunc
+    int surface_depth = 0;      // > 0 and 2 depth < Ls: remove the subspace's fifth-dimension interior
     int verbose = 0;            // print setup progress to stderr
   } prm;
   double setup_seconds = 0.0;
@@ -117,6 +120,13 @@ int blk_promote(hdcg* h, const bf16c* P, const cplx<float>* c, int nr, cplx<floa
                 const cplx<float>* base, double sign, size_t fstride, hipStream_t st);
 int blk_phi16(hdcg* h, hipStream_t st);        // phi16 = phi128 rounded to bf16 pairs
 int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
+int blk_surface_zero(hdcg* h, hipStream_t st);  // zero phi128 at sd <= s < Ls - sd
+// the solve's project / promote (complex64 vectors) on the subspace copy
+// phi_prec selects (p16: bf16 pairs), surface slices only when sd > 0
+int solve_project(hdcg* h, bool p16, const cplx<float>* fine, size_t fstride, int nr, cplx<float>* out, size_t sr,
+                  size_t sa, size_t sk, hipStream_t st);
+int solve_promote(hdcg* h, bool p16, const cplx<float>* c, int nr, cplx<float>* out, const cplx<float>* base,
+                  double sign, size_t fstride, hipStream_t st);
 template <typename R>
 int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st);
 int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_t st);

@@ -79,12 +79,22 @@ __global__ void k_phi_layout(cplx<R>* __restrict__ phi, const cplx<double>* __re
   }
 }
 
+// Position in a fine site column (12 Ls: [spin-colour][s]) of entry q of a
+// subspace column that keeps only the surface slices (12 x 2 sd: s < sd, then
+// s >= Ls - sd); sd = 0: the full column, q itself.
+__device__ __forceinline__ int surf_q(int q, int Ls, int sd) {
+  if (sd == 0) return q;
+  const int w = 2 * sd, c = q / w, sp = q - c * w;
+  return c * Ls + (sp < sd ? sp : Ls - w + sp);
+}
+
 // out[r*sr + a*sa + k*sk] = ph[a] * sum_i conj(P[a][k][i]) Q(r, a, i)
 // P is stored as TP (cplx<R>, or bf16c with R = float); arithmetic in R.
+// P's site column has colP entries (col, or the surface-only 24 sd).
 template <typename TP, bool FINE, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(kT)
 k_blkdot(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
-         const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
+         const int* __restrict__ site_of, int nsb, int col, int colP, int Ls, int sd, size_t nb, int nvec, int nr,
          cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk,
          const cplx<double>* __restrict__ phase) {
   __shared__ cplx<R> Ps[16][33];
@@ -108,8 +118,8 @@ k_blkdot(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride
       if (r < nr) {
         const size_t i = i0 + ii;
         if (FINE) {
-          const int j = (int)(i / col), qq = (int)(i - (size_t)j * col);
-          q = Q[r * fstride + (size_t)site_of[(size_t)a * nsb + j] * col + qq];
+          const int j = (int)(i / colP), qq = (int)(i - (size_t)j * colP);
+          q = Q[r * fstride + (size_t)site_of[(size_t)a * nsb + j] * col + surf_q(qq, Ls, sd)];
         } else {
           q = Q[((size_t)a * nr + r) * nb + i];
         }
@@ -154,8 +164,8 @@ __device__ __forceinline__ void ld_phi(const TP* p, cplx<R> (&o)[V]) {
 template <typename TP, int NR, int V, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(256)
 k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
-                const int* __restrict__ site_of, int nsb, int col, size_t nb, int nvec, int nr,
-                cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk) {
+                const int* __restrict__ site_of, int nsb, int col, int colP, int Ls, int sd, size_t nb, int nvec,
+                int nr, cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk) {
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int k = wg % nvec, a = wg / nvec;
   const TP* Pk = P + ((size_t)a * nvec + k) * nb;
@@ -165,7 +175,8 @@ k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t 
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
   // U sites at a time, their loads issued before the multiply-adds
   constexpr int U = NR * V > 4 ? 4 : 8;
-  for (int q = threadIdx.x * V; q < col; q += blockDim.x * V) {
+  for (int q = threadIdx.x * V; q < colP; q += blockDim.x * V) {
+    const int qf = surf_q(q, Ls, sd);  // V consecutive entries stay in one run (sd % V == 0)
     for (int j0 = 0; j0 < nsb; j0 += U) {
       cplx<R> pv[U][V], qv[U][NR][V];
 #pragma unroll
@@ -178,8 +189,8 @@ k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t 
           for (int r = 0; r < NR; ++r) qv[u][r][e] = cmk((R)0, (R)0);
         }
         if (j < nsb) {
-          ld_phi<TP, V>(Pk + (size_t)j * col + q, pv[u]);
-          const size_t base = (size_t)so[j] * col + q;
+          ld_phi<TP, V>(Pk + (size_t)j * colP + q, pv[u]);
+          const size_t base = (size_t)so[j] * col + qf;
 #pragma unroll
           for (int r = 0; r < NR; ++r)
             if (r < nr)
@@ -222,7 +233,7 @@ k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t 
 template <typename TP, int NR, int V, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(kT)
 k_promote(const TP* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int Nc, int nvec,
-          size_t nb, int nsb, int col, const int* __restrict__ site_of, cplx<R>* out,
+          size_t nb, int nsb, int col, int colP, int Ls, int sd, const int* __restrict__ site_of, cplx<R>* out,
           const cplx<R>* base, R sign, size_t fstride) {  // out may alias base (in place)
   __shared__ cplx<R> cs[NR * 64];
   const int a = blockIdx.y;
@@ -258,8 +269,8 @@ k_promote(const TP* __restrict__ P, const cplx<R>* __restrict__ c, int nr, int N
 #pragma unroll
           for (int e = 0; e < V; ++e) cmac(acc[r][e], pv[u][e], cs[r * nvec + k0 + u]);
   }
-  const int j = (int)(i / col), q = (int)(i - (size_t)j * col);
-  const size_t addr = (size_t)site_of[(size_t)a * nsb + j] * col + q;
+  const int j = (int)(i / colP), q = (int)(i - (size_t)j * colP);
+  const size_t addr = (size_t)site_of[(size_t)a * nsb + j] * col + surf_q(q, Ls, sd);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r < nr) {
@@ -464,60 +475,89 @@ int blk_phi_layout(hdcg* h, cplx<R>* phi, const cplx<double>* can, bool to_nativ
   return DWF_OK;
 }
 
+// sd > 0: P holds only the surface slices (columns of 24 sd entries)
 template <typename TP, typename R = typename St<TP>::R>
 int blk_dot_t(hdcg* h, const TP* P, const cplx<R>* fine, size_t fstride, const cplx<R>* blockq,
               int nr, cplx<R>* out, size_t sr, size_t sa, size_t sk, const cplx<double>* phase,
-              hipStream_t st) {
-  const int col = 12 * h->op->g.Ls;
+              hipStream_t st, int sd = 0) {
+  const int Ls = h->op->g.Ls;
+  const int col = 12 * Ls;
+  const int colP = sd > 0 ? 24 * sd : col;
+  const size_t nbP = (size_t)h->nsb * colP;
+  if (sd > 0 && (!fine || phase)) return fail(DWF_ERR_ARG, "surface subspace: fine-field projection only");
   if (fine && !phase && nr <= 4) {
     // streaming kernel: P read once, few accumulators per lane
     constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
-    if (col % V) return fail(DWF_ERR_ARG, "project: 12 Ls must be a multiple of 4");
-    const int threads = ((std::min(col / V, 256) + 63) / 64) * 64;
+    if (col % V || sd % V) return fail(DWF_ERR_ARG, "project: 12 Ls and the surface depth must be multiples of 4");
+    const int threads = ((std::min(colP / V, 256) + 63) / 64) * 64;
     dim3 g2(h->nvec * h->Nc);
     if (nr == 1)
       hipLaunchKernelGGL((k_project_small<TP, 1, V>), g2, dim3(threads), 0, st, P, fine, fstride,
-                         h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
+                         h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk);
     else
       hipLaunchKernelGGL((k_project_small<TP, 4, V>), g2, dim3(threads), 0, st, P, fine, fstride,
-                         h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk);
+                         h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk);
     HDCG_HIP(hipGetLastError());
     return DWF_OK;
   }
   dim3 grid(h->Nc, (h->nvec + 15) / 16, (nr + 15) / 16);
   if (fine)
     hipLaunchKernelGGL((k_blkdot<TP, true>), grid, dim3(kT), 0, st, P, fine, fstride,
-                       h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
+                       h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk, phase);
   else
     hipLaunchKernelGGL((k_blkdot<TP, false>), grid, dim3(kT), 0, st, P, blockq, (size_t)0,
-                       h->site_of.as<int>(), h->nsb, col, h->nb, h->nvec, nr, out, sr, sa, sk, phase);
+                       h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk, phase);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }
 
+// fine_out = base + sign P c on the interior slices too when sd > 0: there
+// P is zero, so out = base (or 0 without base)
+template <typename R>
+__global__ void k_surface_rest(cplx<R>* out, const cplx<R>* base, size_t fe, size_t fstride, int nr, int Ls,
+                               int sd) {
+  const size_t total = fe * nr;
+  for (size_t idx = (size_t)blockIdx.x * kT + threadIdx.x; idx < total; idx += (size_t)gridDim.x * kT) {
+    const size_t r = idx / fe, i = idx - r * fe;
+    const int s = (int)(i % Ls);
+    if (s < sd || s >= Ls - sd) continue;
+    out[r * fstride + i] = base ? base[r * fstride + i] : cmk((R)0, (R)0);
+  }
+}
+
 template <typename TP, typename R = typename St<TP>::R>
 int blk_promote_t(hdcg* h, const TP* P, const cplx<R>* c, int nr, cplx<R>* out,
-                  const cplx<R>* base, double sign, size_t fstride, hipStream_t st) {
+                  const cplx<R>* base, double sign, size_t fstride, hipStream_t st, int sd = 0) {
   if (nr < 1 || h->nvec > 64) return fail(DWF_ERR_ARG, "promote: bad nr / nvec");
-  const int col = 12 * h->op->g.Ls;
+  const int Ls = h->op->g.Ls;
+  const int col = 12 * Ls;
+  const int colP = sd > 0 ? 24 * sd : col;
+  const size_t nbP = (size_t)h->nsb * colP;
   constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
-  if (col % V) return fail(DWF_ERR_ARG, "promote: 12 Ls must be a multiple of 4");
+  if (col % V || sd % V) return fail(DWF_ERR_ARG, "promote: 12 Ls and the surface depth must be multiples of 4");
+  if (sd > 0 && out != base) {
+    const size_t fe = h->op->field_elems(1);
+    size_t nbk = (fe * nr + kT - 1) / kT;
+    if (nbk > 65536) nbk = 65536;
+    hipLaunchKernelGGL((k_surface_rest<R>), dim3((unsigned)nbk), dim3(kT), 0, st, out, base, fe, fstride, nr, Ls, sd);
+    HDCG_HIP(hipGetLastError());
+  }
   for (int r0 = 0; r0 < nr; r0 += 16) {
     const int n = nr - r0 < 16 ? nr - r0 : 16;
-    dim3 grid((unsigned)((h->nb + kT - 1) / kT), h->Nc);
-    dim3 gridv((unsigned)((h->nb / V + kT - 1) / kT), h->Nc);
+    dim3 grid((unsigned)((nbP + kT - 1) / kT), h->Nc);
+    dim3 gridv((unsigned)((nbP / V + kT - 1) / kT), h->Nc);
     const cplx<R>* cc = c + (size_t)r0 * h->Nc * h->nvec;
     cplx<R>* o = out + (size_t)r0 * fstride;
     const cplx<R>* b = base ? base + (size_t)r0 * fstride : nullptr;
     if (n <= 1)
-      hipLaunchKernelGGL((k_promote<TP, 1, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
-                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+      hipLaunchKernelGGL((k_promote<TP, 1, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, nbP, h->nsb,
+                         col, colP, Ls, sd, h->site_of.as<int>(), o, b, (R)sign, fstride);
     else if (n <= 4)
-      hipLaunchKernelGGL((k_promote<TP, 4, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
-                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+      hipLaunchKernelGGL((k_promote<TP, 4, V>), gridv, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, nbP, h->nsb,
+                         col, colP, Ls, sd, h->site_of.as<int>(), o, b, (R)sign, fstride);
     else
-      hipLaunchKernelGGL((k_promote<TP, 16, 1>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, h->nb,
-                         h->nsb, col, h->site_of.as<int>(), o, b, (R)sign, fstride);
+      hipLaunchKernelGGL((k_promote<TP, 16, 1>), grid, dim3(kT), 0, st, P, cc, n, h->Nc, h->nvec, nbP, h->nsb,
+                         col, colP, Ls, sd, h->site_of.as<int>(), o, b, (R)sign, fstride);
     HDCG_HIP(hipGetLastError());
   }
   return DWF_OK;
@@ -575,6 +615,92 @@ int blk_phi16(hdcg* h, hipStream_t st) {
                      total);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
+}
+
+// Surface-depth truncation of the subspace (Sec. IV.B, closing paragraph of
+// the subspace-generation subsection): the interior slices sd <= s < Ls - sd
+// of phi128 are zeroed before the block orthonormalisation, and the solve's
+// complex64 / 16-bit copies keep only the 2 sd surface slices of each site
+// column ([a][k][j][spin-colour][s'], s' < sd: s = s', else s = Ls - 2 sd + s'),
+// so project and promote read Ls / (2 sd) times fewer subspace bytes.
+__global__ void k_surface_zero(c128* __restrict__ phi, size_t total, int Ls, int sd) {
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT) {
+    const int s = (int)(i % Ls);
+    if (s >= sd && s < Ls - sd) phi[i] = cmk(0.0, 0.0);
+  }
+}
+__global__ void k_phi_surface(c64* __restrict__ o64, bf16c* __restrict__ o16, const c128* __restrict__ in,
+                              size_t total, int Ls, int sd) {
+  const int w = 2 * sd;
+  for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < total; i += (size_t)gridDim.x * kT) {
+    const size_t row = i / w;
+    const int sp = (int)(i - row * w);
+    const c128 v = in[row * Ls + (sp < sd ? sp : Ls - w + sp)];
+    if (o64) o64[i] = cmk((float)v.re, (float)v.im);
+    if (o16) {
+      bf16c b;
+      b.re = f64_to_bf16(v.re);
+      b.im = f64_to_bf16(v.im);
+      o16[i] = b;
+    }
+  }
+}
+static unsigned grid_of(size_t total) {
+  const size_t nbk = (total + kT - 1) / kT;
+  return (unsigned)(nbk > 65536 ? 65536 : nbk);
+}
+int blk_surface_zero(hdcg* h, hipStream_t st) {
+  const size_t total = (size_t)h->Nc * h->nvec * h->nb;
+  hipLaunchKernelGGL(k_surface_zero, dim3(grid_of(total)), dim3(kT), 0, st, h->phi128.as<c128>(), total,
+                     h->op->g.Ls, h->sd);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+static int surface_copy(hdcg* h, bool sixteen, hipStream_t st) {
+  const size_t total = (size_t)h->Nc * h->nvec * h->nsb * 24 * h->sd;
+  DevBuf& b = sixteen ? h->phis16 : h->phis64;
+  HDCG_TRY(b.ensure(total * (sixteen ? sizeof(bf16c) : sizeof(c64))));
+  hipLaunchKernelGGL(k_phi_surface, dim3(grid_of(total)), dim3(kT), 0, st, sixteen ? nullptr : b.as<c64>(),
+                     sixteen ? b.as<bf16c>() : nullptr, h->phi128.as<c128>(), total, h->op->g.Ls, h->sd);
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+// The subspace copy the solve reads: 16-bit or complex64, surface-only when
+// sd > 0 (built on first use)
+int solve_project(hdcg* h, bool p16, const c64* fine, size_t fstride, int nr, c64* out, size_t sr, size_t sa,
+                  size_t sk, hipStream_t st) {
+  if (h->sd > 0) {
+    if (p16) {
+      if (h->phis16.bytes == 0) HDCG_TRY(surface_copy(h, true, st));
+      return blk_dot_t<bf16c, float>(h, h->phis16.as<bf16c>(), fine, fstride, nullptr, nr, out, sr, sa, sk, nullptr,
+                                     st, h->sd);
+    }
+    if (h->phis64.bytes == 0) HDCG_TRY(surface_copy(h, false, st));
+    return blk_dot_t<c64, float>(h, h->phis64.as<c64>(), fine, fstride, nullptr, nr, out, sr, sa, sk, nullptr, st,
+                                 h->sd);
+  }
+  if (p16) {
+    if (h->phi16.bytes == 0) HDCG_TRY(blk_phi16(h, st));
+    return blk_dot_t<bf16c, float>(h, h->phi16.as<bf16c>(), fine, fstride, nullptr, nr, out, sr, sa, sk, nullptr, st);
+  }
+  return blk_dot_t<c64, float>(h, h->phi64.as<c64>(), fine, fstride, nullptr, nr, out, sr, sa, sk, nullptr, st);
+}
+int solve_promote(hdcg* h, bool p16, const c64* c, int nr, c64* out, const c64* base, double sign, size_t fstride,
+                  hipStream_t st) {
+  if (h->sd > 0) {
+    if (p16) {
+      if (h->phis16.bytes == 0) HDCG_TRY(surface_copy(h, true, st));
+      return blk_promote_t(h, h->phis16.as<bf16c>(), c, nr, out, base, sign, fstride, st, h->sd);
+    }
+    if (h->phis64.bytes == 0) HDCG_TRY(surface_copy(h, false, st));
+    return blk_promote_t(h, h->phis64.as<c64>(), c, nr, out, base, sign, fstride, st, h->sd);
+  }
+  if (p16) {
+    if (h->phi16.bytes == 0) HDCG_TRY(blk_phi16(h, st));
+    return blk_promote_t(h, h->phi16.as<bf16c>(), c, nr, out, base, sign, fstride, st);
+  }
+  return blk_promote_t(h, h->phi64.as<c64>(), c, nr, out, base, sign, fstride, st);
 }
 
 int blk_cholqr_step(hdcg* h, hipStream_t st) {

@@ -389,19 +389,12 @@ static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, do
   c64* cb = h->cw[3].as<c64>();
   c64* cx = h->cw[4].as<c64>();
   const bool p16 = h->prm.phi_prec == DWF_BF16;
-  if (p16)
-    HDCG_TRY(blk_dot(h, h->phi16.as<bf16c>(), in, fine_elems(h), nr, cb, n, h->nvec, 1, st));
-  else
-    HDCG_TRY(blk_dot<float>(h, h->phi64.as<c64>(), in, fine_elems(h), nullptr, nr, cb, n, h->nvec, 1,
-                            nullptr, st));
+  HDCG_TRY(solve_project(h, p16, in, fine_elems(h), nr, cb, n, h->nvec, 1, st));
   int it = 0;
   HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter,
                             &it, st, h->prm.coarse_prec));
   if (citers) *citers += it;
-  if (p16)
-    HDCG_TRY(blk_promote(h, h->phi16.as<bf16c>(), cx, nr, out, base, sign, fine_elems(h), st));
-  else
-    HDCG_TRY(blk_promote<float>(h, h->phi64.as<c64>(), cx, nr, out, base, sign, fine_elems(h), st));
+  HDCG_TRY(solve_promote(h, p16, cx, nr, out, base, sign, fine_elems(h), st));
   return DWF_OK;
 }
 
@@ -544,6 +537,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->m1_hi = 0.0;
   p->m1_order = 16;
   p->m1_shift = 0.0;
+  p->surface_depth = 0;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -579,6 +573,8 @@ int hdcg_destroy(hdcg_t h) {
   h->ldD.release();
   h->ldc.release();
   h->TT64.release();
+  h->phis64.release();
+  h->phis16.release();
   h->TT128.release();
   h->nbr9.release();
   h->ycw.release();
@@ -680,6 +676,8 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   }
   HDCG_TRY(h->phi128.ensure(fe * nv * sizeof(c128)));
   HDCG_TRY(blk_phi_layout<double>(h, h->phi128.as<c128>(), work.as<c128>(), true, nv, st));
+  // surface-depth truncation (Sec. IV.B): the fifth-dimension interior removed
+  if (h->sd > 0) HDCG_TRY(blk_surface_zero(h, st));
   work.release();
 
   // ---- block orthonormalisation: Cholesky-QR, twice (FP64) -------------
@@ -691,7 +689,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   if (flag) return fail(DWF_ERR_NUMERIC, "block Gram matrix not positive definite (subspace vectors dependent on a block)");
   HDCG_TRY(h->phi64.ensure(fe * nv * sizeof(c64)));
   HDCG_TRY(launch_convert(h->phi64.as<c64>(), h->phi128.as<c128>(), fe * nv, st));
-  if (h->prm.phi_prec == DWF_BF16) HDCG_TRY(blk_phi16(h, st));
+  if (h->prm.phi_prec == DWF_BF16 && h->sd == 0) HDCG_TRY(blk_phi16(h, st));
 
   // ---- little Dirac operator by the Fourier trick (Sec. V.A.1) ---------
   const size_t n2 = (size_t)nv * nv;
@@ -831,6 +829,7 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.m1_hi = p->m1_hi;
     h->prm.m1_order = p->m1_order;
     h->prm.m1_shift = p->m1_shift;
+    h->prm.surface_depth = p->surface_depth;
   }
   // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
   if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
@@ -842,6 +841,14 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
       rc < 0) {
     delete h;
     return rc;
+  }
+  {
+    const int d = h->prm.surface_depth, Ls = op->g.Ls;
+    if (d < 0 || (d > 0 && 2 * d < Ls && d % 4 != 0)) {
+      delete h;
+      return fail(DWF_ERR_ARG, "surface_depth must be 0, a multiple of 4 below Ls / 2, or at least Ls / 2");
+    }
+    h->sd = d > 0 && 2 * d < Ls ? d : 0;
   }
   if ((h->prm.subspace_gen != 0 && h->prm.subspace_gen != 1) ||
       (h->prm.subspace_gen == 1 &&
@@ -921,16 +928,11 @@ int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int 
   if (!coarse_out || !fine_in) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t n = (size_t)h->Nc * h->nvec, fe = h->op->field_elems(1);
-  if (prec == DWF_BF16) {
-    HDCG_TRY(ensure_phi16(h, st));
-    return blk_dot(h, h->phi16.as<bf16c>(), static_cast<const c64*>(fine_in), fe, nrhs, static_cast<c64*>(coarse_out),
-                   n, h->nvec, 1, st);
-  }
   if (prec == DWF_C128)
     return blk_dot<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(fine_in), fe, nullptr, nrhs,
                            static_cast<c128*>(coarse_out), n, h->nvec, 1, nullptr, st);
-  return blk_dot<float>(h, h->phi64.as<c64>(), static_cast<const c64*>(fine_in), fe, nullptr, nrhs,
-                        static_cast<c64*>(coarse_out), n, h->nvec, 1, nullptr, st);
+  return solve_project(h, prec == DWF_BF16, static_cast<const c64*>(fine_in), fe, nrhs,
+                       static_cast<c64*>(coarse_out), n, h->nvec, 1, st);
 }
 
 int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream) {
@@ -938,16 +940,11 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
   if (!coarse_in || !fine_out) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t fe = h->op->field_elems(1);
-  if (prec == DWF_BF16) {
-    HDCG_TRY(ensure_phi16(h, st));
-    return blk_promote(h, h->phi16.as<bf16c>(), static_cast<const c64*>(coarse_in), nrhs, static_cast<c64*>(fine_out),
-                       nullptr, 1.0, fe, st);
-  }
   if (prec == DWF_C128)
     return blk_promote<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(coarse_in), nrhs,
                                static_cast<c128*>(fine_out), nullptr, 1.0, fe, st);
-  return blk_promote<float>(h, h->phi64.as<c64>(), static_cast<const c64*>(coarse_in), nrhs,
-                            static_cast<c64*>(fine_out), nullptr, 1.0, fe, st);
+  return solve_promote(h, prec == DWF_BF16, static_cast<const c64*>(coarse_in), nrhs, static_cast<c64*>(fine_out),
+                       nullptr, 1.0, fe, st);
 }
 
 static int ensure_at128(hdcg* h, hipStream_t st) { return ensure_at128_impl(h, st); }
@@ -1003,7 +1000,7 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   auto st = static_cast<hipStream_t>(stream);
   if (p->coarse_prec == DWF_BF16 && !h->mf_have_bf16) HDCG_TRY(crs_build_mfma(h, DWF_BF16, st));
   if (p->coarse_prec == DWF_F16 && !h->mf_have_f16) HDCG_TRY(crs_build_mfma(h, DWF_F16, st));
-  if (p->phi_prec == DWF_BF16) HDCG_TRY(ensure_phi16(h, st));
+  if (p->phi_prec == DWF_BF16 && h->sd == 0) HDCG_TRY(ensure_phi16(h, st));
   HDCG_HIP(hipStreamSynchronize(st));
   h->prm.n_irs = p->n_irs;
   h->prm.lambda_irs = p->lambda_irs;

@@ -40,6 +40,8 @@ def main():
                          "building the second deflation level (--ldop vectors, default 128), and with the "
                          "subspace of Q in 16 bits as well")
     ap.add_argument("--cg", action="store_true", help="also time the plain FP64 CG on the same source(s)")
+    ap.add_argument("--surface_depth", type=int, default=0,
+                    help="keep only the subspace's s < d and s >= Ls - d slices (0: all)")
     ap.add_argument("--n_ii", type=int, default=3)
     ap.add_argument("--tol_ii", type=float, default=1e-3)
     ap.add_argument("--maxiter_ii", type=int, default=500)
@@ -122,7 +124,7 @@ def run_hdcg(a, torch, synth):
     iprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.irs]
     pprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.phi]
     h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
-                irs_prec=iprec, phi_prec=pprec, verbose=1)
+                irs_prec=iprec, phi_prec=pprec, surface_depth=a.surface_depth, verbose=1)
     print("setup done", flush=True)
     if a.variants:
         run_variants(a, torch, synth, hd, w, op, h, b)
