@@ -35,6 +35,8 @@ def main():
     ap.add_argument("--ldop", type=int, default=0,
                     help="extra global coarse vectors of the second deflation level (0: none)")
     ap.add_argument("--nrhs_solve", type=int, default=1, help="right-hand sides of the HDCG solve")
+    ap.add_argument("--m1_order", type=int, default=0,
+                    help="with --ldop: coarse solves by ADEF1 with a Chebyshev inverse of this order (0: deflated CG)")
     ap.add_argument("--variants", action="store_true",
                     help="solve five times on one setup: as given, 16-bit M_IRS fields, both again after "
                          "building the second deflation level (--ldop vectors, default 128), and with the "
@@ -136,6 +138,10 @@ def run_hdcg(a, torch, synth):
         hd.hdcg_ldop_setup(h.h, a.ldop, noise, 0.0, 3, 1e-7)
         del noise
         print(f"second deflation level: {w.nvec + a.ldop} global vectors", flush=True)
+        if a.m1_order > 0:
+            h.set_params(ldop_m1=1, m1_order=a.m1_order)
+            lo, hi = hd.hdcg_m1_interval(h.h)
+            print(f"ADEF1, Chebyshev order {a.m1_order} on [{lo}, {hi:.3f}]", flush=True)
     if a.nrhs_solve > 1:
         bs = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(r))
                                         for r in range(a.nrhs_solve)])).to("cuda")
@@ -143,6 +149,7 @@ def run_hdcg(a, torch, synth):
     x = op.new_field(zero=True, nrhs=a.nrhs_solve)
     rc, st = hd.hdcg_solve(h.h, x, b, a.nrhs_solve, 1e-8)
     print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs} subspace {a.phi} ldop {a.ldop} "
+          f"m1_order {a.m1_order} surface_depth {a.surface_depth} "
           f"nrhs {a.nrhs_solve}: "
           f"status {rc} {st}", flush=True)
     h.close()
