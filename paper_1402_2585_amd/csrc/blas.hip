@@ -87,22 +87,35 @@ __device__ __forceinline__ void reduce_out(double (&v)[NQ], Red red, int rhs, do
   }
 }
 
+// Sum of the per-workgroup partials of a kernel that does not finish its own
+// reduction (the hop kernel's fused norm: one partial per workgroup, up to
+// ~10^5).  One 1024-thread workgroup per right-hand side; each lane keeps
+// eight independent accumulators so eight loads are in flight per trip
+// (fixed order: deterministic).
+constexpr int kFinT = 1024;
 template <int NQ>
-__global__ void __launch_bounds__(256) k_finalize(const double* __restrict__ partials, int nslots,
-                                                  int nblocks, size_t rstride, double* __restrict__ res) {
+__global__ void __launch_bounds__(kFinT) k_finalize(const double* __restrict__ partials, int nslots,
+                                                    int nblocks, size_t rstride, double* __restrict__ res) {
   const int rhs = blockIdx.x;
   const double* p = partials + (size_t)rhs * rstride;
-  __shared__ double lds[16];
+  __shared__ double lds[kFinT / 64];
   for (int q = 0; q < NQ; ++q) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += p[q * nslots + i];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    const double* pq = p + (size_t)q * nslots;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 7 * kFinT < nblocks; i += 8 * kFinT) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += pq[i + u * kFinT];
+    }
+    for (; i < nblocks; i += kFinT) s[0] += pq[i];
+    double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += lds[w];
-      res[NQ * rhs + q] = t;
+      double r = 0.0;
+      for (int w = 0; w < kFinT / 64; ++w) r += lds[w];
+      res[NQ * rhs + q] = r;
     }
     __syncthreads();
   }
@@ -294,9 +307,9 @@ int launch_finalize(int nq, const double* partials, int nslots, int nblocks, int
                     hipStream_t st, size_t rstride) {
   if (nblocks > nslots || (size_t)nq * nslots > rstride) return fail(DWF_ERR_ARG, "too many partial sums");
   if (nq == 1)
-    hipLaunchKernelGGL((k_finalize<1>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, rstride, res);
+    hipLaunchKernelGGL((k_finalize<1>), dim3(nrhs), dim3(kFinT), 0, st, partials, nslots, nblocks, rstride, res);
   else
-    hipLaunchKernelGGL((k_finalize<2>), dim3(nrhs), dim3(256), 0, st, partials, nslots, nblocks, rstride, res);
+    hipLaunchKernelGGL((k_finalize<2>), dim3(nrhs), dim3(kFinT), 0, st, partials, nslots, nblocks, rstride, res);
   LAUNCH_CHECK();
   return DWF_OK;
 }

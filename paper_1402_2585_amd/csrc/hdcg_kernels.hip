@@ -155,12 +155,11 @@ __device__ __forceinline__ void ld_phi(const TP* p, cplx<R> (&o)[V]) {
   }
 }
 
-// Few right-hand sides: one workgroup per (vector k, block a) streams the
-// row P[a][k][:] once, lanes running over the 12 Ls contiguous components of
-// each site column (V consecutive ones per lane); out[r*sr + a*sa + k*sk] =
-// sum_i conj(P[a][k][i]) Q_r(site(a, i)).  The workgroups of one block are
-// consecutive after the XCD remap, so the block's fine data is fetched into
-// one L2 for all its Nvec rows.
+// Few right-hand sides: one 128-thread workgroup per (vector k, block a)
+// streams the row P[a][k][:] once, lanes striding over its entries V at a
+// time; out[r*sr + a*sa + k*sk] = sum_i conj(P[a][k][i]) Q_r(site(a, i)).
+// The workgroups of one block are consecutive after the XCD remap, so the
+// block's fine data is fetched into one L2 for all its Nvec rows.
 template <typename TP, int NR, int V, typename R = typename St<TP>::R>
 __global__ void __launch_bounds__(256)
 k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
@@ -173,38 +172,42 @@ k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t 
   cplx<R> acc[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
-  // U sites at a time, their loads issued before the multiply-adds
+  // the row P[a][k][:] is one contiguous run of nsb colP entries: lanes
+  // stride over it V entries at a time (all lanes busy, loads coalesced),
+  // U of them in flight per lane before the multiply-adds; V consecutive
+  // entries stay in one site column and one surface run (colP % V == 0,
+  // sd % V == 0)
   constexpr int U = NR * V > 4 ? 4 : 8;
-  for (int q = threadIdx.x * V; q < colP; q += blockDim.x * V) {
-    const int qf = surf_q(q, Ls, sd);  // V consecutive entries stay in one run (sd % V == 0)
-    for (int j0 = 0; j0 < nsb; j0 += U) {
-      cplx<R> pv[U][V], qv[U][NR][V];
+  const int total = nsb * colP;
+  const int step = blockDim.x * V;
+  for (int e0 = threadIdx.x * V; e0 < total; e0 += step * U) {
+    cplx<R> pv[U][V], qv[U][NR][V];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j = j0 + u;
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * step;
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pv[u][e] = cmk((R)0, (R)0);
+      for (int x = 0; x < V; ++x) {
+        pv[u][x] = cmk((R)0, (R)0);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) qv[u][r][e] = cmk((R)0, (R)0);
-        }
-        if (j < nsb) {
-          ld_phi<TP, V>(Pk + (size_t)j * colP + q, pv[u]);
-          const size_t base = (size_t)so[j] * col + qf;
-#pragma unroll
-          for (int r = 0; r < NR; ++r)
-            if (r < nr)
-#pragma unroll
-              for (int e = 0; e < V; ++e) qv[u][r][e] = Q[r * fstride + base + e];
-        }
+        for (int r = 0; r < NR; ++r) qv[u][r][x] = cmk((R)0, (R)0);
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
+      if (e < total) {
+        const int j = e / colP, q = e - j * colP;
+        ld_phi<TP, V>(Pk + e, pv[u]);
+        const size_t base = (size_t)so[j] * col + surf_q(q, Ls, sd);
 #pragma unroll
         for (int r = 0; r < NR; ++r)
+          if (r < nr)
 #pragma unroll
-          for (int e = 0; e < V; ++e) cjmac(acc[r], pv[u][e], qv[u][r][e]);
+            for (int x = 0; x < V; ++x) qv[u][r][x] = Q[r * fstride + base + x];
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int x = 0; x < V; ++x) cjmac(acc[r], pv[u][x], qv[u][r][x]);
   }
   __shared__ double red[2 * NR][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -489,7 +492,7 @@ int blk_dot_t(hdcg* h, const TP* P, const cplx<R>* fine, size_t fstride, const c
     // streaming kernel: P read once, few accumulators per lane
     constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
     if (col % V || sd % V) return fail(DWF_ERR_ARG, "project: 12 Ls and the surface depth must be multiples of 4");
-    const int threads = ((std::min(colP / V, 256) + 63) / 64) * 64;
+    const int threads = 128;
     dim3 g2(h->nvec * h->Nc);
     if (nr == 1)
       hipLaunchKernelGGL((k_project_small<TP, 1, V>), g2, dim3(threads), 0, st, P, fine, fstride,
