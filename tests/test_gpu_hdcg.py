@@ -571,7 +571,8 @@ def test_hdcg_inverse_iteration_and_multi_rhs():
 def test_hdcg_solve_ragged_groups_zero_source_and_16bit_mirs():
     """Nine right-hand sides (a group of 8 and a ragged group of 1), one of
     them zero (its solution must be exactly zero), with 16-bit M_IRS fields
-    and the second deflation level, every non-zero one to 1e-8."""
+    and the second deflation level, every non-zero one to 1e-8; then again
+    with ADEF1 coarse solves on the BF16 coarse operator."""
     name = "12^4xLs2-b4-n4"
     banner(f"hdcg nrhs=9 (one zero), bf16 M_IRS, second level {name}")
     dims, Ls, block, nvec, raw, op, h, ref = _setup(name, n_ii=1)
@@ -586,6 +587,18 @@ def test_hdcg_solve_ragged_groups_zero_source_and_16bit_mirs():
     xc = op.to_canonical(x, nrhs=9).cpu().numpy()
     assert np.all(xc[4] == 0)
     for i in (0, 3, 7, 8):
+        r = b[i] - ref.H(xc[i])
+        assert np.sqrt(np.vdot(r, r).real / np.vdot(b[i], b[i]).real) <= 1e-8, i
+    # the same with ADEF1 coarse solves (Chebyshev order 8) on the BF16 MFMA
+    # coarse operator: a zero column inside a group of coarse right-hand sides
+    h.set_params(ldop_m1=1, m1_order=8, coarse_prec=hd.DWF_BF16)
+    x = op.new_field(nrhs=9)
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 9, 1e-8)
+    print("ADEF1, BF16 coarse", st, flush=True)
+    assert rc == 0 and st["converged"] == 1
+    xc = op.to_canonical(x, nrhs=9).cpu().numpy()
+    assert np.all(xc[4] == 0)
+    for i in (0, 5, 8):
         r = b[i] - ref.H(xc[i])
         assert np.sqrt(np.vdot(r, r).real / np.vdot(b[i], b[i]).real) <= 1e-8, i
     h.close()
