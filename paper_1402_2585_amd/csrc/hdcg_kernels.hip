@@ -155,45 +155,52 @@ __device__ __forceinline__ void ld_phi(const TP* p, cplx<R> (&o)[V]) {
   }
 }
 
-// Few right-hand sides: one 128-thread workgroup per (vector k, block a)
-// streams the row P[a][k][:] once, lanes striding over its entries V at a
-// time; out[r*sr + a*sa + k*sk] = sum_i conj(P[a][k][i]) Q_r(site(a, i)).
-// The workgroups of one block are consecutive after the XCD remap, so the
-// block's fine data is fetched into one L2 for all its Nvec rows.
-template <typename TP, int NR, int V, typename R = typename St<TP>::R>
-__global__ void __launch_bounds__(256)
+// Few right-hand sides: one 128-thread workgroup per (block a, group of KG
+// subspace vectors k0 .. k0 + KG - 1) streams the KG rows P[a][k][:] once,
+// lanes striding over the entries V at a time; each fine value loaded serves
+// all KG rows, so the block's fine data is read Nvec / KG times from L2
+// instead of Nvec times.  out[r*sr + a*sa + k*sk] =
+// sum_i conj(P[a][k][i]) Q_r(site(a, i)).  The workgroups of one block are
+// consecutive after the XCD remap, so its fine data stays in one L2.
+template <typename TP, int NR, int V, int KG, typename R = typename St<TP>::R>
+__global__ void __launch_bounds__(128)
 k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t fstride,
                 const int* __restrict__ site_of, int nsb, int col, int colP, int Ls, int sd, size_t nb, int nvec,
                 int nr, cplx<R>* __restrict__ out, size_t sr, size_t sa, size_t sk) {
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int k = wg % nvec, a = wg / nvec;
-  const TP* Pk = P + ((size_t)a * nvec + k) * nb;
+  const int ngrp = (nvec + KG - 1) / KG;
+  const int k0 = (wg % ngrp) * KG, a = wg / ngrp;
+  const TP* Pk = P + ((size_t)a * nvec + k0) * nb;
   const int* so = site_of + (size_t)a * nsb;
-  cplx<R> acc[NR];
+  cplx<R> acc[KG][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = cmk((R)0, (R)0);
-  // the row P[a][k][:] is one contiguous run of nsb colP entries: lanes
-  // stride over it V entries at a time (all lanes busy, loads coalesced),
-  // U of them in flight per lane before the multiply-adds; V consecutive
-  // entries stay in one site column and one surface run (colP % V == 0,
-  // sd % V == 0)
-  constexpr int U = NR * V > 4 ? 4 : 8;
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[g][r] = cmk((R)0, (R)0);
+  // each row P[a][k][:] is one contiguous run of nsb colP entries; V
+  // consecutive entries stay in one site column and one surface run
+  // (colP % V == 0, sd % V == 0); U strides' loads are issued before the
+  // multiply-adds
+  constexpr int U = V == 4 ? 1 : 4;
   const int total = nsb * colP;
   const int step = blockDim.x * V;
   for (int e0 = threadIdx.x * V; e0 < total; e0 += step * U) {
-    cplx<R> pv[U][V], qv[U][NR][V];
+    cplx<R> pv[U][KG][V], qv[U][NR][V];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * step;
 #pragma unroll
       for (int x = 0; x < V; ++x) {
-        pv[u][x] = cmk((R)0, (R)0);
+#pragma unroll
+        for (int g = 0; g < KG; ++g) pv[u][g][x] = cmk((R)0, (R)0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) qv[u][r][x] = cmk((R)0, (R)0);
       }
       if (e < total) {
         const int j = e / colP, q = e - j * colP;
-        ld_phi<TP, V>(Pk + e, pv[u]);
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+          if (k0 + g < nvec) ld_phi<TP, V>(Pk + (size_t)g * nb + e, pv[u][g]);
         const size_t base = (size_t)so[j] * col + surf_q(q, Ls, sd);
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -205,29 +212,32 @@ k_project_small(const TP* __restrict__ P, const cplx<R>* __restrict__ Q, size_t 
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
+      for (int g = 0; g < KG; ++g)
 #pragma unroll
-        for (int x = 0; x < V; ++x) cjmac(acc[r], pv[u][x], qv[u][r][x]);
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int x = 0; x < V; ++x) cjmac(acc[g][r], pv[u][g][x], qv[u][r][x]);
   }
-  __shared__ double red[2 * NR][4];
+  __shared__ double red[KG * NR][2][2];  // [(g, r)][re / im][wave]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double re = wave_sum((double)acc[r].re), im = wave_sum((double)acc[r].im);
-    if (lane == 0) {
-      red[2 * r][wave] = re;
-      red[2 * r + 1][wave] = im;
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double re = wave_sum((double)acc[g][r].re), im = wave_sum((double)acc[g][r].im);
+      if (lane == 0) {
+        red[g * NR + r][0][wave] = re;
+        red[g * NR + r][1][wave] = im;
+      }
     }
-  }
   __syncthreads();
-  if (threadIdx.x < nr && threadIdx.x < NR) {
-    const int r = threadIdx.x;
-    double re = 0.0, im = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      re += red[2 * r][w];
-      im += red[2 * r + 1][w];
+  if (threadIdx.x < KG * NR) {
+    const int g = threadIdx.x / NR, r = threadIdx.x - g * NR;
+    if (r < nr && k0 + g < nvec) {
+      const double re = red[threadIdx.x][0][0] + red[threadIdx.x][0][1];
+      const double im = red[threadIdx.x][1][0] + red[threadIdx.x][1][1];
+      out[r * sr + a * sa + (k0 + g) * sk] = cmk((R)re, (R)im);
     }
-    out[r * sr + a * sa + k * sk] = cmk((R)re, (R)im);
   }
 }
 
@@ -492,14 +502,18 @@ int blk_dot_t(hdcg* h, const TP* P, const cplx<R>* fine, size_t fstride, const c
     // streaming kernel: P read once, few accumulators per lane
     constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
     if (col % V || sd % V) return fail(DWF_ERR_ARG, "project: 12 Ls and the surface depth must be multiples of 4");
-    const int threads = 128;
-    dim3 g2(h->nvec * h->Nc);
-    if (nr == 1)
-      hipLaunchKernelGGL((k_project_small<TP, 1, V>), g2, dim3(threads), 0, st, P, fine, fstride,
+    // two waves per workgroup (the kernel's reduction assumes 128 threads)
+    if (nr == 1) {
+      constexpr int KG = 8;
+      dim3 g2(h->Nc * ((h->nvec + KG - 1) / KG));
+      hipLaunchKernelGGL((k_project_small<TP, 1, V, KG>), g2, dim3(128), 0, st, P, fine, fstride,
                          h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk);
-    else
-      hipLaunchKernelGGL((k_project_small<TP, 4, V>), g2, dim3(threads), 0, st, P, fine, fstride,
+    } else {
+      constexpr int KG = 2;
+      dim3 g2(h->Nc * ((h->nvec + KG - 1) / KG));
+      hipLaunchKernelGGL((k_project_small<TP, 4, V, KG>), g2, dim3(128), 0, st, P, fine, fstride,
                          h->site_of.as<int>(), h->nsb, col, colP, Ls, sd, nbP, h->nvec, nr, out, sr, sa, sk);
+    }
     HDCG_HIP(hipGetLastError());
     return DWF_OK;
   }
