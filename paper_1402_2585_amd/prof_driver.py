@@ -214,7 +214,8 @@ def run_coarse(a, torch, synth):
     """Times the coarse-grid kernels of a numbered workload (subspace: the
     seeded vectors, orthonormalised, no inverse iteration): the little Dirac
     operator mat-vec, its one-hop truncation and the Chebyshev inverse
-    (order 16 on [0.5, 45]), complex64, one right-hand side, --reps each."""
+    (order 16 on [0.5, 45]), and the project / promote of the solve's
+    subspace copies; complex64 vectors, one right-hand side, --reps each."""
     import time
 
     import numpy as np
@@ -236,9 +237,16 @@ def run_coarse(a, torch, synth):
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     print(f"coarse grid Nc {h.Nc} nvec {h.nvec}", flush=True)
+    f = torch.randn(op.new_field(hd.DWF_C64).numel(), dtype=torch.complex64, device="cuda")
+    g = torch.empty_like(f)
+    torch.cuda.synchronize()
     for name, fn in (("A mat-vec", lambda: hd.coarse_apply(h.h, y, x, hd.DWF_C64)),
                      ("Q_trunc mat-vec", lambda: hd.hdcg_trunc_apply(h.h, y, x, hd.DWF_C64)),
-                     ("Chebyshev order 16", lambda: hd.hdcg_chebyshev(h.h, y, x, hd.DWF_C64))):
+                     ("Chebyshev order 16", lambda: hd.hdcg_chebyshev(h.h, y, x, hd.DWF_C64)),
+                     ("project, complex64 subspace", lambda: hd.hdcg_project(h.h, y, f, hd.DWF_C64)),
+                     ("project, bf16 subspace", lambda: hd.hdcg_project(h.h, y, f, hd.DWF_BF16)),
+                     ("promote, complex64 subspace", lambda: hd.hdcg_promote(h.h, g, y, hd.DWF_C64)),
+                     ("promote, bf16 subspace", lambda: hd.hdcg_promote(h.h, g, y, hd.DWF_BF16))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
