@@ -55,6 +55,7 @@ struct hdcg {
   hdk::DevBuf ldZ128, ldAZ128, ldZ64, ldAZ64;
   hdk::DevBuf ldD;                  // double [ng]
   hdk::DevBuf ldc;                  // coefficients [64][1024] complex128
+  hdk::DevBuf ldpart;               // sliced partial sums of the coefficients [nr][ng][slices]
   std::vector<double> ldDh;         // D on the host
   // the truncated operator Q_trunc + m1_shift (Sec. V.B): zero- and one-hop
   // terms, TT[a][m][k][j] for the 9 points m, and their neighbour table

@@ -572,6 +572,7 @@ int hdcg_destroy(hdcg_t h) {
   h->ldAZ64.release();
   h->ldD.release();
   h->ldc.release();
+  h->ldpart.release();
   h->TT64.release();
   h->phis64.release();
   h->phis16.release();

@@ -73,18 +73,23 @@ __global__ void k_free_vectors(c128* __restrict__ W, int Nc, int nvec) {
   W[e] = cmk(j == k ? 1.0 / std::sqrt((double)Nc) : 0.0, 0.0);
 }
 
-// c[rhs][k] = (V_k, r_rhs) / D[k]; one workgroup per (k, rhs)
+// c[rhs][k] = (V_k, r_rhs) / D[k]; one workgroup per (k, slice, rhs).  With
+// one slice the workgroup writes c; with S slices (long vectors: a single
+// workgroup per k would leave most CUs idle) it writes its partial sum to
+// part[rhs][k][slice] and k_defl_coef_sum adds the S partials in order.
 template <typename R>
 __global__ void __launch_bounds__(kT) k_defl_coef(const cplx<R>* __restrict__ V, const cplx<R>* __restrict__ r,
                                                   const double* __restrict__ D, int ng, size_t N,
-                                                  c128* __restrict__ c) {
-  const int k = blockIdx.x, rhs = blockIdx.y;
+                                                  c128* __restrict__ c, c128* __restrict__ part) {
+  const int k = blockIdx.x, sl = blockIdx.y, S = gridDim.y, rhs = blockIdx.z;
+  const size_t chunk = (N + S - 1) / S;
+  const size_t n0 = (size_t)sl * chunk, n1 = n0 + chunk < N ? n0 + chunk : N;
   const cplx<R>* v = V + (size_t)k * N;
   const cplx<R>* x = r + (size_t)rhs * N;
   double re = 0.0, im = 0.0;
   // four strided elements per trip, loads first
-  size_t n = threadIdx.x;
-  for (; n + 3 * kT < N; n += 4 * kT) {
+  size_t n = n0 + threadIdx.x;
+  for (; n + 3 * kT < n1; n += 4 * kT) {
     cplx<R> a[4], b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -97,7 +102,7 @@ __global__ void __launch_bounds__(kT) k_defl_coef(const cplx<R>* __restrict__ V,
       im += (double)a[u].re * b[u].im - (double)a[u].im * b[u].re;
     }
   }
-  for (; n < N; n += kT) {
+  for (; n < n1; n += kT) {
     const cplx<R> a = v[n], b = x[n];
     re += (double)a.re * b.re + (double)a.im * b.im;
     im += (double)a.re * b.im - (double)a.im * b.re;
@@ -105,7 +110,24 @@ __global__ void __launch_bounds__(kT) k_defl_coef(const cplx<R>* __restrict__ V,
   double s[2] = {re, im};
   __shared__ double lds[32];
   block_sum<2>(s, lds);
-  if (threadIdx.x == 0) c[(size_t)rhs * ng + k] = cmk(s[0] / D[k], s[1] / D[k]);
+  if (threadIdx.x != 0) return;
+  if (S == 1)
+    c[(size_t)rhs * ng + k] = cmk(s[0] / D[k], s[1] / D[k]);
+  else
+    part[((size_t)rhs * ng + k) * S + sl] = cmk(s[0], s[1]);
+}
+
+__global__ void k_defl_coef_sum(const c128* __restrict__ part, const double* __restrict__ D, int ng, int S,
+                                c128* __restrict__ c) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x, rhs = blockIdx.y;
+  if (k >= ng) return;
+  const c128* p = part + ((size_t)rhs * ng + k) * S;
+  double re = 0.0, im = 0.0;
+  for (int sl = 0; sl < S; ++sl) {
+    re += p[sl].re;
+    im += p[sl].im;
+  }
+  c[(size_t)rhs * ng + k] = cmk(re / D[k], im / D[k]);
 }
 
 // out = (use_r ? r : 0) + (num ? num/den * out : 0) + sign * sum_k Z_k c[rhs][k].
@@ -279,9 +301,21 @@ int expand(const c128* X, const std::vector<cd>& M, int nx, int ny, size_t N, De
 template <typename R>
 int ldop_coef(hdcg* h, const cplx<R>* V, const cplx<R>* r, int nr, hipStream_t st) {
   const size_t N = (size_t)h->Nc * h->nvec;
-  hipLaunchKernelGGL((k_defl_coef<R>), dim3(h->ng, nr), dim3(kT), 0, st, V, r, h->ldD.as<double>(), h->ng, N,
-                     h->ldc.as<c128>());
+  // up to 16 slices per vector, each of at least 128 elements
+  const int S = (int)std::max<size_t>(1, std::min<size_t>(16, N / 128));
+  c128* part = nullptr;
+  if (S > 1) {
+    HDCG_TRY(h->ldpart.ensure(sizeof(c128) * (size_t)nr * h->ng * S));
+    part = h->ldpart.as<c128>();
+  }
+  hipLaunchKernelGGL((k_defl_coef<R>), dim3(h->ng, S, nr), dim3(kT), 0, st, V, r, h->ldD.as<double>(), h->ng, N,
+                     h->ldc.as<c128>(), part);
   HDCG_HIP(hipGetLastError());
+  if (S > 1) {
+    hipLaunchKernelGGL(k_defl_coef_sum, dim3((h->ng + 255) / 256, nr), dim3(256), 0, st, part, h->ldD.as<double>(),
+                       h->ng, S, h->ldc.as<c128>());
+    HDCG_HIP(hipGetLastError());
+  }
   return DWF_OK;
 }
 
