@@ -337,7 +337,8 @@ int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void
  * copies of A and of the subspace when coarse_prec or phi_prec asks for one
  * not yet built, and estimates the Chebyshev bound when ldop_m1 = 1 and
  * m1_hi = 0.
- * Synchronises `stream`.  DWF_ERR_ARG on an invalid field (the handle is
+ * Synchronises `stream`.  DWF_ERR_ARG on an invalid field, DWF_ERR_NUMERIC
+ * if the Chebyshev bound estimate is not above m1_lo (the parameters are
  * then unchanged). */
 int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream);
 

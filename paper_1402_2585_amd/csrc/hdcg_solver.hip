@@ -1003,6 +1003,7 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   if (p->coarse_prec == DWF_F16 && !h->mf_have_f16) HDCG_TRY(crs_build_mfma(h, DWF_F16, st));
   if (p->phi_prec == DWF_BF16 && h->sd == 0) HDCG_TRY(ensure_phi16(h, st));
   HDCG_HIP(hipStreamSynchronize(st));
+  const auto old = h->prm;
   h->prm.n_irs = p->n_irs;
   h->prm.lambda_irs = p->lambda_irs;
   h->prm.coarse_tol = p->coarse_tol;
@@ -1021,10 +1022,15 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.m1_hi = p->m1_hi;
   h->prm.m1_order = p->m1_order;
   h->prm.m1_shift = p->m1_shift;
-  // the estimated Chebyshev bound (m1_hi <= 0) is taken now, not inside a solve
+  // the estimated Chebyshev bound (m1_hi <= 0) is taken now, not inside a
+  // solve; if it fails the previous parameters are restored
   if (h->prm.ldop_m1 == 1 && h->prm.m1_hi <= 0.0) {
     double lo = 0, hi = 0;
-    HDCG_TRY(m1_bounds(h, &lo, &hi, st));
+    if (const int rc = m1_bounds(h, &lo, &hi, st); rc < 0) {
+      if (h->prm.m1_shift != old.m1_shift) trunc_invalidate(h);
+      h->prm = old;
+      return rc;
+    }
   }
   return DWF_OK;
 }

@@ -264,10 +264,11 @@ int m1_bounds(hdcg* h, double* lo, double* hi, hipStream_t st) {
   *lo = h->prm.m1_lo;
   if (h->prm.m1_hi > 0.0) {
     *hi = h->prm.m1_hi;
-    return DWF_OK;
+    return DWF_OK;  // m1_hi > m1_lo is checked with the parameters
   }
   if (h->m1_hi_est > 0.0) {
     *hi = h->m1_hi_est;
+    if (!(*hi > *lo)) return fail(DWF_ERR_NUMERIC, "Chebyshev upper bound estimate not above m1_lo");
     return DWF_OK;
   }
   HDCG_TRY(trunc_ensure<float>(h, st));
@@ -300,9 +301,10 @@ int m1_bounds(hdcg* h, double* lo, double* hi, hipStream_t st) {
   HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 15, sn, sizeof(double), hipMemcpyDeviceToHost, st));
   HDCG_HIP(hipStreamSynchronize(st));
   const double lam = std::sqrt(h->pinned[64 * 15]);
-  if (!std::isfinite(lam) || !(lam > *lo)) return fail(DWF_ERR_NUMERIC, "Chebyshev upper bound estimate not above m1_lo");
+  if (!std::isfinite(lam) || !(lam > 0.0)) return fail(DWF_ERR_NUMERIC, "Chebyshev upper bound estimate not positive");
   h->m1_hi_est = 1.05 * lam;
   *hi = h->m1_hi_est;
+  if (!(*hi > *lo)) return fail(DWF_ERR_NUMERIC, "Chebyshev upper bound estimate not above m1_lo");
   return DWF_OK;
 }
 

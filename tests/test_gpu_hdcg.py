@@ -385,6 +385,11 @@ def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
         lo, hi_est = hd.hdcg_m1_interval(h.h)
         print(f"Chebyshev interval [{lo}, {hi_est:.4f}], lambda_max(Q_trunc) {lmax:.4f}", flush=True)
         assert lo == 0.5 and 0.9 * lmax <= hi_est / 1.05 <= lmax * (1 + 1e-6)
+        # an interval whose low end lies above the estimated top is refused,
+        # and the parameters stay as they were
+        with pytest.raises(hd.HdcgError):
+            h.set_params(ldop_m1=1, m1_lo=2.0 * hi_est)
+        assert hd.hdcg_m1_interval(h.h) == (lo, hi_est) and h.params.ldop_m1 == 0
         hi = 1.1 * lmax
         r = synth.gaussian_coarse(Nc, nvec, 371, 2)
         for n in (1, 5, 16):
