@@ -31,8 +31,9 @@ __device__ __forceinline__ void st_coherent(c64* p, c64 v) {
 // with all their loads issued before the multiply-adds (the operator is read
 // once per mat-vec, so many loads must be in flight per wave).  Writes
 // out[r][a][j] for r0 <= r < min(r0 + NR, nr).  `red` is kCT * NR complex
-// of LDS.  With STAGED (one right-hand side) `in` is instead the site's
-// operand already gathered into LDS: in[l * nvec + k] = c[nbr(a,l)][k].
+// of LDS.  With STAGED `in` is instead the site's operand already gathered
+// into LDS for the NR right-hand sides r0 .. r0 + NR - 1:
+// in[r * NS * nvec + l * nvec + k] = c[r0 + r][nbr(a,l)][k].
 // Every thread of the workgroup must call it.  NS is the number of stencil
 // points (the 81 of A, or the 9 of the one-hop truncation): AT holds NS
 // matrices per site and nbr NS neighbours per site.
@@ -40,7 +41,6 @@ template <typename R, int NR, int U, bool STAGED = false, int NS = kStencil>
 __device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr,
                                             const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                             int a, int Nc, int nvec, int nr, int r0, cplx<R>* red) {
-  static_assert(!STAGED || NR == 1, "a staged operand holds one right-hand side");
   const int parts = kCT / nvec;
   const int j = threadIdx.x % nvec, part = threadIdx.x / nvec;
   const int K = NS * nvec;
@@ -61,7 +61,9 @@ __device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, cons
         if (q < K) {
           Av[u] = Aa[(size_t)q * nvec];
           if constexpr (STAGED) {
-            xv[u][0] = in[q];
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+              if (r0 + r < nr) xv[u][r] = in[r * K + q];
           } else {
             const int l = q / nvec, k = q - l * nvec;
             const size_t vo = (size_t)nb[l] * nvec + k;

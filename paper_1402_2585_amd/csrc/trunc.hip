@@ -99,33 +99,39 @@ k_cheb_step(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const 
   }
 }
 
-// The same for one right-hand side with the operand at the nine points first
-// gathered into LDS (one coalesced pass), so the column loop streams only the
-// operator.
+// The same with the nine-point operand of the workgroup's NR right-hand
+// sides first gathered into LDS (one coalesced pass), so the column loop
+// streams only the operator.
 constexpr int kStageNvec = 64;
-template <typename R, int U>
+template <typename R, int NR, int U>
 __global__ void __launch_bounds__(kCT)
-k_cheb_step1(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const cplx<R>* __restrict__ dcur,
-             cplx<R>* __restrict__ dnext, cplx<R>* __restrict__ res, cplx<R>* __restrict__ y, cplx<R>* __restrict__ tw,
-             int Nc, int nvec, double ca, double cb) {
-  __shared__ cplx<R> red[kCT];
-  __shared__ cplx<R> s_in[kTS * kStageNvec];
-  const int a = blockIdx.x;
+k_cheb_step_staged(const cplx<R>* __restrict__ TT, const int* __restrict__ nbr9, const cplx<R>* __restrict__ dcur,
+                   cplx<R>* __restrict__ dnext, cplx<R>* __restrict__ res, cplx<R>* __restrict__ y,
+                   cplx<R>* __restrict__ tw, int Nc, int nvec, int nr, double ca, double cb) {
+  __shared__ cplx<R> red[kCT * NR];
+  __shared__ cplx<R> s_in[NR * kTS * kStageNvec];
+  const int a = blockIdx.x, r0 = blockIdx.y * NR;
+  const int K = kTS * nvec;
   const int* nb = nbr9 + (size_t)a * kTS;
-  for (int e = threadIdx.x; e < kTS * nvec; e += kCT) {
-    const int m = e / nvec;
-    s_in[e] = dcur[(size_t)nb[m] * nvec + (e - m * nvec)];
+  for (int e = threadIdx.x; e < NR * K; e += kCT) {
+    const int r = e / K, rem = e - r * K, m = rem / nvec;
+    s_in[e] = r0 + r < nr ? dcur[((size_t)(r0 + r) * Nc + nb[m]) * nvec + (rem - m * nvec)] : cmk((R)0, (R)0);
   }
   __syncthreads();
-  capply_site<R, 1, U, true, kTS>(TT, nbr9, s_in, tw, a, Nc, nvec, 1, 0, red);
+  capply_site<R, NR, U, true, kTS>(TT, nbr9, s_in, tw, a, Nc, nvec, nr, r0, red);
   if (threadIdx.x >= nvec) return;
-  const size_t idx = (size_t)a * nvec + threadIdx.x;
-  const cplx<R> t = tw[idx], rv = res[idx], dv = s_in[threadIdx.x], yv = y[idx];  // point 0 is the site
-  const double rre = (double)rv.re - t.re, rim = (double)rv.im - t.im;
-  const double dre = ca * rre + cb * dv.re, dim = ca * rim + cb * dv.im;
-  res[idx] = cmk((R)rre, (R)rim);
-  dnext[idx] = cmk((R)dre, (R)dim);
-  y[idx] = cmk((R)(yv.re + dre), (R)(yv.im + dim));
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r0 + r >= nr) break;
+    const size_t idx = ((size_t)(r0 + r) * Nc + a) * nvec + threadIdx.x;
+    // point 0 of the staged operand is the site itself
+    const cplx<R> t = tw[idx], rv = res[idx], dv = s_in[r * K + threadIdx.x], yv = y[idx];
+    const double rre = (double)rv.re - t.re, rim = (double)rv.im - t.im;
+    const double dre = ca * rre + cb * dv.re, dim = ca * rim + cb * dv.im;
+    res[idx] = cmk((R)rre, (R)rim);
+    dnext[idx] = cmk((R)dre, (R)dim);
+    y[idx] = cmk((R)(yv.re + dre), (R)(yv.im + dim));
+  }
 }
 
 template <typename R, int U>
@@ -226,10 +232,15 @@ int cheb_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, double lo, doubl
   double omega = 2.0;
   for (int k = 1; k < h->prm.m1_order; ++k) {
     omega = 1.0 / (1.0 - omega / (4.0 * sigma * sigma));
-    if (nr == 1 && h->nvec <= kStageNvec) {
-      hipLaunchKernelGGL((k_cheb_step1<R, 16>), dim3(h->Nc), dim3(kCT), 0, st, tt_buf<R>(h).template as<cplx<R>>(),
-                         h->nbr9.as<int>(), dl[(k - 1) & 1], dl[k & 1], u, y, tw, h->Nc, h->nvec, omega / d,
-                         omega - 1.0);
+    if (h->nvec <= kStageNvec) {
+      const cplx<R>* TTp = tt_buf<R>(h).template as<cplx<R>>();
+      if (nr == 1)
+        hipLaunchKernelGGL((k_cheb_step_staged<R, 1, 16>), dim3(h->Nc, 1), dim3(kCT), 0, st, TTp, h->nbr9.as<int>(),
+                           dl[(k - 1) & 1], dl[k & 1], u, y, tw, h->Nc, h->nvec, nr, omega / d, omega - 1.0);
+      else
+        hipLaunchKernelGGL((k_cheb_step_staged<R, NR, 16 / NR>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st,
+                           TTp, h->nbr9.as<int>(), dl[(k - 1) & 1], dl[k & 1], u, y, tw, h->Nc, h->nvec, nr,
+                           omega / d, omega - 1.0);
       HDCG_HIP(hipGetLastError());
       continue;
     }
