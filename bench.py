@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the copy bandwidth and the 32^3x64 H")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver and its kernels run on one GPU; multi-GPU sharding is a design only, so --gpus must be 1"}))
         sys.exit(2)
 
     import torch
