@@ -227,3 +227,22 @@ def test_adef1_is_identity_on_the_deflation_space(small):
     v = v - np.einsum("k,k...->...", (Z.reshape(len(Z), -1).conj() @ crs.apply(A, v, C).ravel()) / Dz, Z)
     out = M1(crs.apply(A, v, C))
     assert np.abs(out - 0.37 * crs.apply(A, v, C)).max() < 1e-11 * np.abs(v).max()
+
+
+def test_chebyshev_minimax_on_the_paper_interval():
+    """With the paper's interval [0.5, 45] and order 16 (Table "optimised"),
+    the residual factor 1 - x p(x) of the Chebyshev iteration stays within
+    1 / T_16(d/c) on the whole interval and reaches it at the 17 Chebyshev
+    extrema x_j = d - c cos(j pi / 16) (the minimax property of T_n)."""
+    lo, hi, n = 0.5, 45.0, 16
+    d, c = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    bound = 1.0 / np.cosh(n * np.arccosh(d / c))
+    xs = np.concatenate([np.linspace(lo, hi, 997), d - c * np.cos(np.arange(n + 1) * np.pi / n)])
+    M = np.diag(xs)
+    v = np.ones(len(xs))
+    y = ldop.chebyshev_inverse(lambda u: M @ u, v, lo, hi, n)
+    res = v - xs * y
+    assert np.abs(res).max() <= bound * (1 + 1e-9)
+    ext = res[-(n + 1):]
+    assert np.allclose(np.abs(ext), bound, rtol=1e-7)
+    assert np.all(np.sign(ext[1:]) == -np.sign(ext[:-1]))  # equioscillation
