@@ -200,3 +200,39 @@ def test_hdcg_defect_correction_solves(small_two_level):
     x, outers, inner_its, rel = hdcg.defect_correction(tl, b, tol=1e-8, inner_tol=1e-5, n_irs=4)
     r = b - op.H(x)
     assert np.sqrt(norm2(r) / norm2(b)) <= 1e-8 and outers >= 1
+
+
+
+@pytest.mark.slow
+def test_standard_and_flexible_pcg_coincide_for_a_fixed_symmetric_preconditioner(small_two_level):
+    """Fig. "pcg_general" with its standard update (alpha = (r, y)/(p, w),
+    beta = (r', y')/(r, y)) and the flexible one (alpha = (p, r)/(p, w),
+    beta = -(w, y')/(p, w)) produce the same iterates in exact arithmetic
+    when M_1 is a fixed Hermitian positive operator: (p_k, r_k) = (y_k, r_k)
+    because r_k is orthogonal to p_{k-1}, and -(w_k, y_{k+1}) =
+    (r_{k+1} - r_k, y_{k+1}) / alpha_k with (r_k, y_{k+1}) = 0.  With an exact
+    Q, BNN's M_1 = P_R M P_L + Q is Hermitian for Hermitian M, and A-DEF2
+    iterates equal BNN's (Sec. IV.E.1).  M here is the linear Hermitian
+    positive polynomial 0.05 + 0.001 H in place of the (nonlinear) M_IRS."""
+    op, _, phi, sob, C, A = small_two_level
+    tl = hdcg.TwoLevel(op, phi, sob, C, A, coarse_tol=1e-13)
+    b = synth.gaussian_half_field(op.dims, op.Ls, 90)
+
+    def poly(o, r, n, lam):
+        return 0.05 * r + 0.001 * o.H(r)
+
+    runs = {}
+    for method, flex in (("bnn", True), ("bnn", False), ("adef2", False)):
+        its = []
+        hdcg.gpcg(tl, b, method=method, tol=1e-30, maxiter=4, flexible=flex, m_irs_fn=poly,
+                  x=tl.Q(b) if method == "bnn" else None,
+                  callback=lambda it, x, r, p: its.append((x.copy(), np.sqrt(norm2(r)))))
+        runs[method, flex] = its
+    assert len(runs["bnn", True]) == 4
+    for (xf, _), (xs, _) in zip(runs["bnn", True], runs["bnn", False]):
+        assert np.abs(xf - xs).max() <= 1e-8 * np.abs(xf).max()
+    for (xa, _), (xb, _) in zip(runs["adef2", False], runs["bnn", False]):
+        assert np.abs(xa - xb).max() <= 1e-8 * np.abs(xa).max()
+    # the iteration makes progress (a stalled update would also agree)
+    res = [r for _, r in runs["adef2", False]]
+    assert res[-1] < 0.5 * np.sqrt(norm2(b))
