@@ -375,6 +375,16 @@ int hdcg_adef1_precondition(hdcg_t h, void* y, const void* r, int prec, int nrhs
  * (host int arrays of V/2 entries indexed by cb: block index, rank in block). */
 int hdcg_export_coarse(hdcg_t h, void* A_c128, void* stream);
 int hdcg_export_subspace(hdcg_t h, void* phi_c128, void* stream);
+/* Replace the little Dirac operator of a built handle by a caller-given one
+ * in the same canonical layout A[a][l][j][k] (device, complex128, Nc*81*nvec*
+ * nvec entries; the caller keeps ownership), e.g. an operator reused from an
+ * earlier setup on the same subspace or a seeded test operator.  Every copy
+ * derived from A (the transposed complex64 / complex128 forms, the 16-bit
+ * MFMA storage and its scales, the truncated operator) is rebuilt; the second
+ * deflation level built on the old operator is dropped (hdcg_ldop_setup
+ * again to rebuild it).  The coarse solves assume A Hermitian positive
+ * definite.  Synchronises. */
+int hdcg_import_coarse(hdcg_t h, const void* A_c128, void* stream);
 int hdcg_export_block_map(hdcg_t h, int* block_of_site, int* index_in_block);
 
 /* Solve H x = b for nrhs right-hand sides to |b - H x| / |b| <= tol (FP64

@@ -114,6 +114,7 @@ def load():
         "hdcg_chebyshev": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_adef1_precondition": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
+        "hdcg_import_coarse": (i, [vp, vp, vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "hdcg_solve": (i, [vp, vp, vp, i, d, C.POINTER(HdcgStats), vp]),
@@ -347,6 +348,10 @@ def hdcg_adef1_precondition(h, y, r, prec, nrhs=1, stream=None):
 
 def hdcg_export_coarse(h, out, stream=None):
     _check(load().hdcg_export_coarse(h, _ptr(out), _stream(stream)))
+
+
+def hdcg_import_coarse(h, A, stream=None):
+    _check(load().hdcg_import_coarse(h, _ptr(A), _stream(stream)))
 
 
 def hdcg_export_subspace(h, out, stream=None):

@@ -910,6 +910,26 @@ int hdcg_export_coarse(hdcg_t h, void* A_c128, void* stream) {
   return DWF_OK;
 }
 
+int hdcg_import_coarse(hdcg_t h, const void* A_c128, void* stream) {
+  if (!h || !A_c128) return fail(DWF_ERR_ARG, "null argument");
+  auto st = static_cast<hipStream_t>(stream);
+  HDCG_HIP(hipMemcpyAsync(h->A128.ptr, A_c128, (size_t)h->Nc * kStencil * h->nvec * h->nvec * sizeof(c128),
+                          hipMemcpyDeviceToDevice, st));
+  // every copy derived from A is rebuilt now or on its next use
+  HDCG_TRY(crs_transpose(h, false, st));
+  if (h->AT128.bytes) HDCG_TRY(crs_transpose(h, true, st));
+  h->mf_smax.release();
+  h->mf_rho.release();
+  const int had_bf16 = h->mf_have_bf16, had_f16 = h->mf_have_f16;
+  h->mf_have_bf16 = h->mf_have_f16 = 0;
+  if (had_bf16) HDCG_TRY(crs_build_mfma(h, DWF_BF16, st));
+  if (had_f16) HDCG_TRY(crs_build_mfma(h, DWF_F16, st));
+  trunc_invalidate(h);
+  h->ng = 0;  // the second level was built on the old operator
+  HDCG_HIP(hipStreamSynchronize(st));
+  return DWF_OK;
+}
+
 static int check_h(hdcg* h, int prec, int nrhs, bool allow16 = false) {
   if (!h) return fail(DWF_ERR_ARG, "null hdcg handle");
   if (prec != DWF_C128 && prec != DWF_C64 && !(allow16 && prec == DWF_BF16))

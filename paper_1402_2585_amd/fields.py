@@ -1,10 +1,35 @@
 """Device-buffer helpers around an operator handle (allocation with PyTorch,
-layout conversion through the library)."""
+layout conversion through the library).
+
+Handles are released explicitly: close() on each object, or, for whatever is
+still open when the interpreter exits, one atexit handler that closes every
+HDCG handle and then every operator (an HDCG handle refers to its operator)
+while the HIP runtime is still fully up.  A finaliser that runs during
+interpreter shutdown does nothing, so no device memory is freed from a
+garbage-collection pass at exit."""
 from __future__ import annotations
+
+import atexit
+import sys
+import weakref
 
 import numpy as np
 
 from . import _lib as L
+
+_LIVE_HDCG = weakref.WeakSet()
+_LIVE_OPS = weakref.WeakSet()
+
+
+def close_all():
+    """Close every open HDCG handle, then every operator handle."""
+    for h in list(_LIVE_HDCG):
+        h.close()
+    for op in list(_LIVE_OPS):
+        op.close()
+
+
+atexit.register(close_all)
 
 # torch element type of a native field per precision; 16-bit fields are
 # bfloat16 tensors holding (re, im) pairs, two elements per complex value
@@ -32,13 +57,17 @@ class FineOperator:
         X, Y, Z, T = dims
         self.Vh = X * Y * Z * T // 2
         self.canonical_shape = (self.Ls, self.Vh, 4, 3)
+        _LIVE_OPS.add(self)
 
     def close(self):
         if self.h is not None:
             L.dwf_destroy(self.h)
             self.h = None
+        _LIVE_OPS.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -98,6 +127,7 @@ class HDCG:
         self.params = p
         self.h = L.hdcg_setup(op.h, block, self.nvec, v, p)
         self.coarse_dims, self.Nc, _ = L.hdcg_dims(self.h)
+        _LIVE_HDCG.add(self)
 
     def set_params(self, **changes):
         """Change solve-phase parameters (hdcg_set_params) of the built handle."""
@@ -115,8 +145,11 @@ class HDCG:
         if self.h is not None:
             L.hdcg_destroy(self.h)
             self.h = None
+        _LIVE_HDCG.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -104,3 +104,56 @@ def gaussian_coarse(Nc: int, nvec: int, seed: int, n: int) -> np.ndarray:
     re = g.standard_normal((n, Nc, nvec))
     im = g.standard_normal((n, Nc, nvec))
     return re + 1j * im
+
+
+def _coarse_index(C, c):
+    """Coarse lexicographic index of coordinates c (..., 4), x fastest, on the torus."""
+    c = np.mod(c, np.array(C))
+    return c[..., 0] + C[0] * (c[..., 1] + C[1] * (c[..., 2] + C[2] * c[..., 3]))
+
+
+def coarse_stencil_operator(C, nvec: int, seed: int, mass: float = 0.1, fill: float = 0.25) -> np.ndarray:
+    """A seeded Hermitian positive-definite block stencil in the layout of the
+    little Dirac operator, A[a][l][j][k] with l = sum_mu (delta_mu + 1) 3^mu
+    (delta_x fastest, l = 40 the site), A[a][l] = A[a + delta_l][80 - l]^+.
+
+    It is a lattice Laplacian whose hopping matrices on the eight axis
+    neighbours are a random pure gauge, U_mu(a) = g_a g_{a+mu}^+ with seeded
+    unitary g_a (so the lowest mode sits at mass), (8 + mass) on the
+    diagonal, plus a random Hermitian fill on all 81 stencil points whose
+    blocks have spectral norm fill * mass / 80 each: the spectrum lies in
+    [mass (1 - fill), 16 + mass (1 + fill)].  Coarse extents must be >= 3 so
+    the 81 offsets are distinct."""
+    C = tuple(int(c) for c in C)
+    assert min(C) >= 3
+    g = rng(seed)
+    nc = int(np.prod(C))
+    a = np.arange(nc)
+    coords = np.stack([a % C[0], (a // C[0]) % C[1], (a // (C[0] * C[1])) % C[2], a // (C[0] * C[1] * C[2])], 1)
+    offs = np.array([[(l // 3 ** mu) % 3 - 1 for mu in range(4)] for l in range(81)])
+    A = np.zeros((nc, 81, nvec, nvec), dtype=np.complex128)
+
+    def gauss(*shape):
+        return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+    def unitary():
+        q, r = np.linalg.qr(gauss(nvec, nvec))
+        return q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+
+    gsite = [unitary() for _ in range(nc)]
+
+    for l in range(41):  # one of each pair (l, 80 - l); l = 40 is the site itself
+        for site in range(nc):
+            B = gauss(nvec, nvec)
+            B *= fill * mass / 80 / np.linalg.norm(B, 2)
+            if l == 40:
+                B = 0.5 * (B + B.conj().T)
+            if l == 40:
+                A[site, 40] += B + (8.0 + mass) * np.eye(nvec)
+                continue
+            b = _coarse_index(C, coords[site] + offs[l])
+            if int(np.abs(offs[l]).sum()) == 1:  # minus the pure-gauge hop
+                B = B - gsite[site] @ gsite[b].conj().T
+            A[site, l] += B
+            A[b, 80 - l] += B.conj().T
+    return A
