@@ -100,6 +100,21 @@ int dwf_create_mobius(dwf_op_t* op, const int dims[4], int Ls, double M5, double
                       const void* gauge_c128, const double bc_phase[8], void* stream);
 int dwf_destroy(dwf_op_t op);
 
+/* Launch shape of the hop kernel (the workgroup tiling of the Wilson hop
+ * stages; the operator is the same for every shape, to rounding order):
+ * shape = {bx, by, bz, bt, remap, lds_kb, nt, morton, phases}.
+ *   bx..bt  site block of one workgroup in (x/2, y, z, t), powers of two
+ *           (all 0: consecutive checkerboard sites); a block that does not
+ *           divide the lattice or exceeds 256 threads falls back to 0;
+ *   remap   1: workgroups reordered so each XCD takes one contiguous range;
+ *   lds_kb  minimum LDS per workgroup in KiB (0..150; caps occupancy);
+ *   nt      1: non-temporal output stores;
+ *   morton  1: site blocks in Morton order (power-of-two block grids);
+ *   phases  2 or 4 neighbour-load phases per stage.
+ * The default, set by dwf_create, is {2, 2, 1, 1, 1, 0, 1, 1, 4}.  For
+ * launch-shape sweeps and their tests.  DWF_ERR_ARG on an invalid entry. */
+int dwf_set_hop_shape(dwf_op_t op, const int shape[9]);
+
 /* Bytes of one native half-field buffer holding nrhs right-hand sides
  * (prec DWF_C128, DWF_C64 or DWF_BF16). */
 int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes);
@@ -238,20 +253,40 @@ struct hdcg_params {
                          removed before block orthonormalisation), and the solve's project /
                          promote read a surface-only copy, Ls / (2 d) times fewer bytes;
                          d must then be a multiple of 4.  0 (default) or 2 d >= Ls: all slices */
+  int coarse_persistent; /* 1 (default): coarse CG of up to 16 right-hand sides with the complex64
+                            or 16-bit operator as one persistent kernel (per-right-hand-side
+                            convergence masks); 0: one launch per step (for comparisons) */
+  int graph;             /* 1 (default): when the coarse solve is the persistent kernel (no
+                            second level active), the preconditioner of every A-DEF2 iteration
+                            (M_IRS, H z - r, project, coarse solve, promote) is captured once per
+                            inner solve as a HIP graph and replayed; 0: launched one by one */
+  int phase_timing;      /* 1: hdcg_solve times its phases with HIP events (hdcg_stats t_*;
+                            disables the graph); 0 (default): no events */
 };
 
 struct hdcg_stats {
-  int outer_iterations;  /* FP64 defect-correction restarts */
-  int inner_iterations;  /* A-DEF2 iterations summed over restarts */
+  int outer_iterations;  /* FP64 defect-correction restarts (max over groups of RHS) */
+  int inner_iterations;  /* A-DEF2 iterations summed over restarts and groups */
   int coarse_solves;     /* applications of Q */
-  int coarse_iterations; /* coarse CG iterations summed */
+  int coarse_iterations; /* coarse CG iterations summed over solves (each solve: its longest RHS) */
   int converged;         /* 1 if |b - H x| / |b| <= tol for every RHS */
-  int pad;
+  int nrhs;              /* entries of the per-RHS arrays below */
   double true_residual;  /* max over RHS of the FP64 relative residual */
   double seconds;        /* solve wall time (setup excluded) */
   double setup_seconds;  /* wall time of hdcg_setup */
   double matmuls_fp64;   /* applications of H in complex128 (per RHS summed) */
   double matmuls_fp32;   /* applications of H in complex64 (per RHS summed) */
+  double matmuls_bf16;   /* applications of H on 16-bit fields (M_IRS with irs_prec = DWF_BF16) */
+  int group_size;        /* right-hand sides solved together (one batch shares every operator pass) */
+  int graph_replays;     /* preconditioner applications replayed from a captured graph */
+  /* Phase times in seconds, the categories of Fig. "pie" (filled when
+   * params.phase_timing = 1, else 0): H in FP64 (the outer residuals); H in
+   * complex64 and 16 bits (A-DEF2, M_IRS, the preconditioner's correction);
+   * the coarse solves inside Q (LdopInv); project and promote; linear
+   * combinations and reductions of fine vectors; precision conversions. */
+  double t_fine_dp, t_fine_sp, t_coarse, t_project_promote, t_linalg, t_convert;
+  long long coarse_iterations_rhs[64]; /* per RHS: coarse CG iterations summed over solves */
+  double true_residual_rhs[64];        /* per RHS: FP64 |b - H x| / |b| */
 };
 
 /* Fill *p with the defaults above. */
@@ -300,6 +335,16 @@ int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* 
  * Synchronises; DWF_NOT_CONVERGED at maxiter. */
 int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
                       int* iters, void* stream);
+
+/* The iterations each right-hand side of the last hdcg_coarse_solve ran
+ * before its residual reached tol (a zero right-hand side: 0), into the host
+ * array iters_rhs[nrhs]; nrhs must equal that call's.  Right-hand sides of
+ * one call run together (one mat-vec for all of them per iteration); with
+ * up to 16 of them and the complex64 or 16-bit operator the solve is one
+ * persistent kernel that masks each right-hand side off once it converges,
+ * so these counts differ from each other and from *iters (the longest). */
+int hdcg_coarse_iterations(hdcg_t h, int* iters_rhs, int nrhs);
+
 
 /* out = M_IRS in: exactly n_irs CG iterations on H + lambda_irs from zero
  * (Sec. IV.C) with the work fields stored as p->irs_prec selects (complex64,

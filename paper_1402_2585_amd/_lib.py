@@ -48,17 +48,25 @@ class HdcgParams(C.Structure):
                 ("rat_eps", C.c_double), ("rat_tol", C.c_double), ("rat_maxiter", C.c_int),
                 ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int),
                 ("ldop_m1", C.c_int), ("m1_lo", C.c_double), ("m1_hi", C.c_double), ("m1_order", C.c_int),
-                ("m1_shift", C.c_double), ("surface_depth", C.c_int)]
+                ("m1_shift", C.c_double), ("surface_depth", C.c_int), ("coarse_persistent", C.c_int),
+                ("graph", C.c_int), ("phase_timing", C.c_int)]
 
 
 class HdcgStats(C.Structure):
     _fields_ = [("outer_iterations", C.c_int), ("inner_iterations", C.c_int),
                 ("coarse_solves", C.c_int), ("coarse_iterations", C.c_int), ("converged", C.c_int),
-                ("pad", C.c_int), ("true_residual", C.c_double), ("seconds", C.c_double),
-                ("setup_seconds", C.c_double), ("matmuls_fp64", C.c_double), ("matmuls_fp32", C.c_double)]
+                ("nrhs", C.c_int), ("true_residual", C.c_double), ("seconds", C.c_double),
+                ("setup_seconds", C.c_double), ("matmuls_fp64", C.c_double), ("matmuls_fp32", C.c_double),
+                ("matmuls_bf16", C.c_double), ("group_size", C.c_int), ("graph_replays", C.c_int),
+                ("t_fine_dp", C.c_double), ("t_fine_sp", C.c_double), ("t_coarse", C.c_double),
+                ("t_project_promote", C.c_double), ("t_linalg", C.c_double), ("t_convert", C.c_double),
+                ("coarse_iterations_rhs", C.c_longlong * 64), ("true_residual_rhs", C.c_double * 64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.endswith("_rhs")}
+        d["coarse_iterations_rhs"] = list(self.coarse_iterations_rhs[:self.nrhs])
+        d["true_residual_rhs"] = list(self.true_residual_rhs[:self.nrhs])
+        return d
 
 
 _lib = None
@@ -83,6 +91,7 @@ def load():
         "dwf_create": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, vp, dp, vp]),
         "dwf_create_mobius": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, d, d, vp, dp, vp]),
         "dwf_destroy": (i, [vp]),
+        "dwf_set_hop_shape": (i, [vp, C.POINTER(C.c_int)]),
         "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
         "dwf_import": (i, [vp, vp, vp, i, i, vp]),
         "dwf_export": (i, [vp, vp, vp, i, i, vp]),
@@ -115,6 +124,7 @@ def load():
         "hdcg_adef1_precondition": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_import_coarse": (i, [vp, vp, vp]),
+        "hdcg_coarse_iterations": (i, [vp, C.POINTER(C.c_int), i]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "hdcg_solve": (i, [vp, vp, vp, i, d, C.POINTER(HdcgStats), vp]),
@@ -178,6 +188,12 @@ def dwf_create_mobius(gauge, dims, Ls, M5, mass, b5, c5, bc=(1, 1, 1, -1), strea
 
 def dwf_destroy(op):
     _check(load().dwf_destroy(op))
+
+
+def dwf_set_hop_shape(op, shape):
+    """shape: 9 ints (bx, by, bz, bt, remap, lds_kb, nt, morton, phases)."""
+    a = (C.c_int * 9)(*[int(v) for v in shape])
+    _check(load().dwf_set_hop_shape(op, a))
 
 
 def dwf_field_bytes(op, prec, nrhs=1):
@@ -304,6 +320,12 @@ def hdcg_coarse_solve(h, x, b, prec, nrhs=1, tol=1e-8, maxiter=10000, stream=Non
     rc = _check(load().hdcg_coarse_solve(h, _ptr(x), _ptr(b), int(prec), int(nrhs), float(tol), int(maxiter),
                                          C.byref(it), _stream(stream)), allow_soft=True)
     return rc, it.value
+
+
+def hdcg_coarse_iterations(h, nrhs):
+    a = (C.c_int * nrhs)()
+    _check(load().hdcg_coarse_iterations(h, a, int(nrhs)))
+    return list(a)
 
 
 def hdcg_mirs(h, out, inp, nrhs=1, stream=None):

@@ -351,20 +351,6 @@ int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, doubl
   const double den = alpha * (1.0 + mass * std::pow(kap, Ls));
   for (int n = 0; n < 64; ++n) op->f5.pw[n] = n < Ls ? std::pow(kap, n) / den : 0.0;
   (void)hipGetDevice(&op->device);
-  // hop launch shape: HDCG_HOP_TILE="bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]"
-  // overrides the default (bx = 0: consecutive sites)
-  if (const char* e = std::getenv("HDCG_HOP_TILE")) {
-    int b[9] = {0, 0, 0, 0, op->tune.remap, op->tune.lds_kb, op->tune.nt, op->tune.morton, op->tune.phases};
-    if (std::sscanf(e, "%d,%d,%d,%d,%d,%d,%d,%d,%d", &b[0], &b[1], &b[2], &b[3], &b[4], &b[5], &b[6], &b[7],
-                    &b[8]) >= 4) {
-      for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
-      op->tune.remap = b[4];
-      op->tune.lds_kb = b[5] < 0 ? 0 : (b[5] > 150 ? 150 : b[5]);
-      op->tune.nt = b[6] & 1;
-      op->tune.morton = b[7] != 0;
-      op->tune.phases = b[8] == 2 ? 2 : 4;
-    }
-  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = DWF_OK;
   do {
@@ -398,6 +384,24 @@ int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, doubl
     return rc;
   }
   *out = op;
+  return DWF_OK;
+}
+
+int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
+  if (!op || !shape) return fail(DWF_ERR_ARG, "null argument to dwf_set_hop_shape");
+  auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
+  const int* b = shape;
+  const bool linear = b[0] == 0 && b[1] == 0 && b[2] == 0 && b[3] == 0;
+  if (!linear && !(pow2(b[0]) && pow2(b[1]) && pow2(b[2]) && pow2(b[3])))
+    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: block extents must be powers of two (or all 0)");
+  if (b[5] < 0 || b[5] > 150 || (b[8] != 2 && b[8] != 4))
+    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: lds_kb must be in 0..150 and phases 2 or 4");
+  for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
+  op->tune.remap = b[4] != 0;
+  op->tune.lds_kb = b[5];
+  op->tune.nt = b[6] & 1;
+  op->tune.morton = b[7] != 0;
+  op->tune.phases = b[8];
   return DWF_OK;
 }
 

@@ -36,8 +36,10 @@ __device__ __forceinline__ void st_coherent(c64* p, c64 v) {
 // in[r * NS * nvec + l * nvec + k] = c[r0 + r][nbr(a,l)][k].
 // Every thread of the workgroup must call it.  NS is the number of stencil
 // points (the 81 of A, or the 9 of the one-hop truncation): AT holds NS
-// matrices per site and nbr NS neighbours per site.
-template <typename R, int NR, int U, bool STAGED = false, int NS = kStencil>
+// matrices per site and nbr NS neighbours per site.  COH (complex64 only):
+// the operand is read with coherent loads (written by other workgroups of a
+// running persistent kernel).
+template <typename R, int NR, int U, bool STAGED = false, int NS = kStencil, bool COH = false>
 __device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr,
                                             const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out,
                                             int a, int Nc, int nvec, int nr, int r0, cplx<R>* red) {
@@ -69,7 +71,12 @@ __device__ __forceinline__ void capply_site(const cplx<R>* __restrict__ AT, cons
             const size_t vo = (size_t)nb[l] * nvec + k;
 #pragma unroll
             for (int r = 0; r < NR; ++r)
-              if (r0 + r < nr) xv[u][r] = in[(size_t)(r0 + r) * Nc * nvec + vo];
+              if (r0 + r < nr) {
+                if constexpr (COH)
+                  xv[u][r] = ld_coherent(in + (size_t)(r0 + r) * Nc * nvec + vo);
+                else
+                  xv[u][r] = in[(size_t)(r0 + r) * Nc * nvec + vo];
+              }
           }
         }
       }
@@ -133,9 +140,10 @@ __device__ __forceinline__ unsigned short to16(float f) {
 // `red` is NW * MT * NT * 64 f32x4 of LDS.  Writes out[r][a][:] for the
 // nrhs right-hand sides of `in` (at most 16 when NT = 2, 8 when NT = 1).
 // With STAGED (one right-hand side) `in` is the site's operand gathered
-// into LDS: in[l * nvec + k] = c[nbr(a,l)][k].  Every thread of the
-// workgroup (NW * 64 threads) must call it.
-template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false>
+// into LDS: in[l * nvec + k] = c[nbr(a,l)][k].  COH: the operand is read
+// with coherent loads (persistent kernels).  Every thread of the workgroup
+// (NW * 64 threads) must call it.
+template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false, bool COH = false>
 __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restrict__ F,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ smax, const int* __restrict__ nbr,
@@ -188,7 +196,13 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
             float v[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const c64 x = STAGED ? in[rem + i] : in[co + i];
+              c64 x;
+              if constexpr (STAGED)
+                x = in[rem + i];
+              else if constexpr (COH)
+                x = ld_coherent(in + co + i);
+              else
+                x = in[co + i];
               // columns r:        part 0 -> Re c, part 1 -> -Im c
               // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
               v[i] = r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im));

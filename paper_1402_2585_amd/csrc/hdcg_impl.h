@@ -19,6 +19,28 @@
 
 constexpr int kStencil = 81;
 
+// Phases of a solve, the categories of Fig. "pie" (Sec. VI.B).
+enum { PH_FINE_DP, PH_FINE_SP, PH_COARSE, PH_PROJ, PH_LINALG, PH_CONVERT, PH_N };
+
+// Optional hipEvent timing of the phases on the solve's stream: each phase
+// section records an event pair; collect() (after a synchronisation of the
+// stream) adds the elapsed times per category and recycles the events.
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> cat;  // category of event pair i (events 2i, 2i + 1)
+  size_t used = 0;
+  double sec[PH_N] = {};
+  int begin(int c, hipStream_t st);  // index of the pair, -1 when off
+  void end(int idx, hipStream_t st);
+  int collect();
+  void reset() {
+    used = 0;
+    for (double& v : sec) v = 0.0;
+  }
+  ~PhaseTimer();
+};
+
 struct hdcg {
   dwf_op* op = nullptr;
   int B[4] = {0, 0, 0, 0};
@@ -94,6 +116,11 @@ struct hdcg {
   } prm;
   double setup_seconds = 0.0;
   long long setup_matmuls = 0;
+  int last_coarse_iters[64] = {};   // per right-hand side, the last hdcg_coarse_solve
+  int last_coarse_nrhs = 0;
+  PhaseTimer timer;                 // phase times of the solve (params.phase_timing)
+  int use_graph = 1;                // capture the preconditioner as a graph when it has no host step
+  hipStream_t cap_stream = nullptr; // stream the preconditioner is captured on (never run on)
 };
 
 namespace hdk {
@@ -136,10 +163,26 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st);
 int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
 
 // coarse CG from x = 0 on the complex64 (mprec = DWF_C64) or 16-bit MFMA
-// operator as one persistent kernel (coarse_cg.hip); *done = 0 when that form
-// does not apply (more than 8 right-hand sides, unsuited nvec).
+// operator as one persistent kernel (coarse_cg.hip), 1..16 right-hand sides
+// with per-right-hand-side convergence masks; *done = 0 when that form does
+// not apply (more than 16 right-hand sides, unsuited nvec).  iters_rhs
+// (nullable): the iterations each right-hand side ran before converging.
 int coarse_cg_persistent(hdcg* h, int mprec, cplx<float>* x, const cplx<float>* b, int nr, double tol,
-                         int maxiter, int* iters, int* done, hipStream_t st);
+                         int maxiter, int* iters, int* iters_rhs, int* done, hipStream_t st);
+// the same, enqueued only (no host synchronisation, so it may be captured
+// into a graph); its counts go to device totals.  *done = 0 when the form
+// does not apply or its work memory has not been sized by an earlier solve.
+int coarse_cg_persistent_deferred(hdcg* h, int mprec, cplx<float>* x, const cplx<float>* b, int nr, double tol,
+                                  int maxiter, int* done, hipStream_t st);
+int coarse_cg_clear_totals(hdcg* h, hipStream_t st);
+// work memory of a persistent solve (0: the form does not apply), and the
+// solve with its work memory supplied by the caller (allocates nothing)
+size_t coarse_cg_work_bytes(hdcg* h, int mprec, int nr);
+int coarse_cg_persistent_in(hdcg* h, void* work, int mprec, cplx<float>* x, const cplx<float>* b, int nr, double tol,
+                            int maxiter, int* iters, hipStream_t st);
+// the deferred solves' counts since the last clear: *solves, and added to
+// *iters and iters_rhs[0..nr); synchronises
+int coarse_cg_totals(hdcg* h, int nr, int* solves, long long* iters, long long* iters_rhs, hipStream_t st);
 
 // complex128 CG on (A + shift) x = b from x = 0 (hdcg_solver.hip)
 int coarse_cg_shifted(hdcg* h, cplx<double>* x, const cplx<double>* b, int nr, double shift, double tol, int maxiter,

@@ -37,6 +37,15 @@ inline double* slot(hdcg* h, int s) { return h->scal.as<double>() + 128 * s; }
 
 inline size_t fine_elems(hdcg* h) { return h->op->field_elems(1); }
 
+// RAII section of one phase category (no-op when phase timing is off)
+struct Phase {
+  hdcg* h;
+  hipStream_t st;
+  int idx;
+  Phase(hdcg* hh, int cat, hipStream_t s) : h(hh), st(s), idx(hh->timer.begin(cat, s)) {}
+  ~Phase() { h->timer.end(idx, st); }
+};
+
 // Host reads of device residual norms through a pinned ring: iteration k is
 // inspected once `lag` later iterations are queued, so the GPU never idles.
 struct LagRing {
@@ -72,6 +81,23 @@ struct LagRing {
     *vals = host + 64 * s;
     ++checked;
     return DWF_OK;
+  }
+};
+
+// Per right-hand side, the first checked iteration whose recursive
+// residual met the tolerance (0 for a zero right-hand side).
+struct ConvAt {
+  int at[64];
+  void init(const std::vector<double>& bb, int nr) {
+    for (int i = 0; i < nr; ++i) at[i] = bb[i] > 0.0 ? -1 : 0;
+  }
+  void note(const double* v, const std::vector<double>& bb, double tol, int nr, int iteration) {
+    for (int i = 0; i < nr; ++i)
+      if (at[i] < 0 && v[i] <= tol * tol * bb[i]) at[i] = iteration;
+  }
+  void out(int* iters_rhs, int nr, int k) const {
+    if (iters_rhs)
+      for (int i = 0; i < nr; ++i) iters_rhs[i] = at[i] >= 0 ? at[i] : k;
   }
 };
 
@@ -128,10 +154,16 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
   while (!done && k < limit) {
     double* cur = rr[k & 1];
     double* nxt = rr[(k + 1) & 1];
-    HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pap));
-    HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, cur, false, pap, lam != 0.0 ? pp : nullptr, lam,
-                             nxt, st));
-    HDCG_TRY(b_xpay<float>(red, p, r, n, nr, nxt, false, cur, 1.0, lam != 0.0 ? pp : nullptr, st));
+    {
+      Phase ph(h, PH_FINE_SP, st);
+      HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pap));
+    }
+    {
+      Phase ph(h, PH_LINALG, st);
+      HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, cur, false, pap, lam != 0.0 ? pp : nullptr, lam,
+                               nxt, st));
+      HDCG_TRY(b_xpay<float>(red, p, r, n, nr, nxt, false, cur, 1.0, lam != 0.0 ? pp : nullptr, st));
+    }
     ++k;
     if (fixed > 0) continue;
     HDCG_TRY(ring.push(nxt, st));
@@ -169,17 +201,25 @@ int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixe
   double* pap = slot(h, S_PAP);
   double* pp = lam != 0.0 ? slot(h, S_PP) : nullptr;
   HDCG_TRY(b_zero(x, n * nr, st));
-  HDCG_TRY(launch_convert16(op, r, b, nr, st));
+  {
+    Phase ph(h, PH_CONVERT, st);
+    HDCG_TRY(launch_convert16(op, r, b, nr, st));
+  }
   HDCG_HIP(hipMemcpyAsync(p, r, n * nr * sizeof(bf16c), hipMemcpyDeviceToDevice, st));
   HDCG_TRY(b_norm2(red, r, n, nr, rr[0], st));
   if (pp) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int k = 0; k < fixed; ++k) {
     double* cur = rr[k & 1];
     double* nxt = rr[(k + 1) & 1];
-    HDCG_TRY((launch_mpcdagmpc<float, bf16c>(op, w, p, nr, st, pap)));
+    {
+      Phase ph(h, PH_FINE_SP, st);
+      HDCG_TRY((launch_mpcdagmpc<float, bf16c>(op, w, p, nr, st, pap)));
+    }
+    Phase ph(h, PH_LINALG, st);
     HDCG_TRY(b_update(red, x, r, p, w, n, nr, cur, pap, pp, lam, nxt, st));
     HDCG_TRY(b_xpay(red, p, r, n, nr, nxt, cur, pp, st));
   }
+  Phase ph(h, PH_CONVERT, st);
   return launch_convert16(op, x_out, x, nr, st);
 }
 
@@ -200,7 +240,7 @@ static int apply_mirs(hdcg* h, c64* z, const c64* r, int nr, int* it, hipStream_
 // A-orthogonal to the last; M_1 is not symmetric).  Stops at |r| <= tol |b|.
 template <typename R>
 int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol, int maxiter,
-                 int* iters, hipStream_t st, int mprec) {
+                 int* iters, hipStream_t st, int mprec, int* iters_rhs = nullptr) {
   const size_t n = (size_t)h->Nc * h->nvec;
   for (int i = 0; i < 3; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
   HDCG_TRY(h->ycw.ensure(n * nr * sizeof(c128)));
@@ -235,6 +275,8 @@ int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int n
   bool any = false;
   for (double v : bb) any = any || v > 0.0;
   int k = 0;
+  ConvAt ca;
+  ca.init(bb, nr);
   if (any) {
     LagRing ring;
     HDCG_TRY(ring.init(h->pinned, nr));
@@ -258,6 +300,7 @@ int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int n
           if (!std::isfinite(v[i])) return fail(DWF_ERR_NUMERIC, "coarse ADEF1 residual not finite");
           if (v[i] > tol * tol * bb[i]) conv = false;
         }
+        ca.note(v, bb, tol, nr, ring.checked);
         if (conv) {
           done = true;
           break;
@@ -268,6 +311,7 @@ int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int n
     HDCG_TRY(b_zero<R>(x, n * nr, st));
   }
   if (iters) *iters = k;
+  ca.out(iters_rhs, nr, k);
   return DWF_OK;
 }
 
@@ -278,14 +322,15 @@ int coarse_adef1(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int n
 // and p = r + beta p - Z D^-1 (AZ)^+ r.  Stops at |r| <= tol |b|.
 template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
-              int maxiter, int* iters, hipStream_t st, int mprec = -1, double shift = 0.0) {
+              int maxiter, int* iters, hipStream_t st, int mprec = -1, double shift = 0.0, int* iters_rhs = nullptr) {
   const bool defl = h->ng > 0 && h->prm.ldop_defl != 0 && shift == 0.0;
-  if (defl && h->prm.ldop_m1 == 1) return coarse_adef1<R>(h, AT, x, b, nr, tol, maxiter, iters, st, mprec);
+  if (defl && h->prm.ldop_m1 == 1)
+    return coarse_adef1<R>(h, AT, x, b, nr, tol, maxiter, iters, st, mprec, iters_rhs);
   if constexpr (sizeof(R) == 4) {
     if (h->persistent_coarse && !defl && shift == 0.0) {
       int done = 0;
       HDCG_TRY(coarse_cg_persistent(h, mprec == DWF_BF16 || mprec == DWF_F16 ? mprec : DWF_C64, x, b, nr, tol,
-                                    maxiter, iters, &done, st));
+                                    maxiter, iters, iters_rhs, &done, st));
       if (done) return DWF_OK;
     }
   }
@@ -332,6 +377,8 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
   bool any = false;
   for (double v : bb) any = any || v > 0.0;
   int k = 0;
+  ConvAt ca;
+  ca.init(bb, nr);
   if (any) {
     LagRing ring;
     HDCG_TRY(ring.init(h->pinned, nr));
@@ -358,6 +405,7 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
           if (!std::isfinite(v[i])) return fail(DWF_ERR_NUMERIC, "coarse CG residual not finite");
           if (v[i] > tol * tol * bb[i]) conv = false;
         }
+        ca.note(v, bb, tol, nr, ring.checked);
         if (conv) {
           done = true;
           break;
@@ -366,6 +414,7 @@ int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, 
     }
   }
   if (iters) *iters = k;
+  ca.out(iters_rhs, nr, k);
   return DWF_OK;
 }
 
@@ -380,43 +429,123 @@ int ensure_at128_impl(hdcg* h, hipStream_t st) {
   return DWF_OK;
 }
 
-// Q v = P A^-1 P^+ v (complex64): out = base + sign * Q in
-static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, double sign,
-                   int* citers, hipStream_t st) {
+struct InnerStats {
+  int iterations = 0, coarse_solves = 0, coarse_iterations = 0, graph_replays = 0;
+  double matmuls32 = 0, matmuls16 = 0;
+  long long coarse_it_rhs[64] = {};
+};
+
+// Q v = P A^-1 P^+ v (complex64): out = base + sign * Q in.  deferred: the
+// coarse solve is the persistent kernel enqueued without reading its result
+// back (its counts go to the device totals), so that the whole application
+// can be captured into a graph.
+static int apply_Q(hdcg* h, c64* out, const c64* in, int nr, const c64* base, double sign, InnerStats* is,
+                   hipStream_t st, bool deferred = false) {
   const size_t n = (size_t)h->Nc * h->nvec;
   HDCG_TRY(h->cw[3].ensure(n * nr * sizeof(c128)));
   HDCG_TRY(h->cw[4].ensure(n * nr * sizeof(c128)));
   c64* cb = h->cw[3].as<c64>();
   c64* cx = h->cw[4].as<c64>();
   const bool p16 = h->prm.phi_prec == DWF_BF16;
-  HDCG_TRY(solve_project(h, p16, in, fine_elems(h), nr, cb, n, h->nvec, 1, st));
-  int it = 0;
-  HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter,
-                            &it, st, h->prm.coarse_prec));
-  if (citers) *citers += it;
+  {
+    Phase ph(h, PH_PROJ, st);
+    HDCG_TRY(solve_project(h, p16, in, fine_elems(h), nr, cb, n, h->nvec, 1, st));
+  }
+  {
+    Phase ph(h, PH_COARSE, st);
+    const int cp = h->prm.coarse_prec;
+    if (deferred) {
+      int done = 0;
+      HDCG_TRY(coarse_cg_persistent_deferred(h, cp == DWF_BF16 || cp == DWF_F16 ? cp : DWF_C64, cx, cb, nr,
+                                             h->prm.coarse_tol, h->prm.coarse_maxiter, &done, st));
+      if (!done) return fail(DWF_ERR_STATE, "deferred coarse solve not available");
+    } else {
+      int it = 0, itr[64];
+      HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), cx, cb, nr, h->prm.coarse_tol, h->prm.coarse_maxiter, &it, st,
+                                cp, 0.0, itr));
+      is->coarse_iterations += it;
+      for (int i = 0; i < nr; ++i) is->coarse_it_rhs[i] += itr[i];
+    }
+  }
+  Phase ph(h, PH_PROJ, st);
   HDCG_TRY(solve_promote(h, p16, cx, nr, out, base, sign, fine_elems(h), st));
   return DWF_OK;
 }
 
-struct InnerStats {
-  int iterations = 0, coarse_solves = 0, coarse_iterations = 0;
-  double matmuls32 = 0;
-};
-
 // y = M_1 r = P_R M_IRS r + Q r = z - Q (H z - r), z = M_IRS r.  z is
-// computed in y's storage and the correction subtracted in place.
-static int precondition(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, hipStream_t st) {
+// computed in y's storage and the correction subtracted in place.  No host
+// step when deferred (see apply_Q).
+static int precondition_body(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, hipStream_t st, bool deferred) {
   const size_t n = fine_elems(h);
   c64* z = y;
   c64* t = h->fw64[6].as<c64>();
   int it = 0;
   HDCG_TRY(apply_mirs(h, z, r, nr, &it, st));
-  is->matmuls32 += it * nr;
-  HDCG_TRY(launch_mpcdagmpc<float>(h->op, t, z, nr, st, nullptr));
+  {
+    Phase ph(h, PH_FINE_SP, st);
+    HDCG_TRY(launch_mpcdagmpc<float>(h->op, t, z, nr, st, nullptr));
+  }
+  {
+    Phase ph(h, PH_LINALG, st);
+    HDCG_TRY(b_axpby<float>(t, r, -1.0, 1.0, n * nr, st));  // t = H z - r
+  }
+  HDCG_TRY(apply_Q(h, y, t, nr, z, -1.0, is, st, deferred));
+  return DWF_OK;
+}
+
+static void count_precondition(hdcg* h, int nr, InnerStats* is) {
+  if (h->prm.irs_prec == DWF_BF16)
+    is->matmuls16 += (double)h->prm.n_irs * nr;
+  else
+    is->matmuls32 += (double)h->prm.n_irs * nr;
   is->matmuls32 += nr;
-  HDCG_TRY(b_axpby<float>(t, r, -1.0, 1.0, n * nr, st));  // t = H z - r
-  HDCG_TRY(apply_Q(h, y, t, nr, z, -1.0, &is->coarse_iterations, st));
   is->coarse_solves += 1;
+}
+
+// The preconditioner of one inner solve as a graph: every call after the
+// first (which runs eagerly and sizes every buffer) replays one capture of
+// the whole application, taken on a stream of the handle that never runs
+// work itself.  Applies when the coarse solve is the persistent kernel.
+struct PrecGraph {
+  hipGraphExec_t exec = nullptr;
+  bool warm = false, failed = false;
+  ~PrecGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+static bool graph_applies(hdcg* h, int nr) {
+  if (!h->use_graph || h->timer.on || !h->persistent_coarse) return false;
+  if (h->ng > 0 && h->prm.ldop_defl != 0) return false;
+  const int cp = h->prm.coarse_prec;
+  return coarse_cg_work_bytes(h, cp == DWF_BF16 || cp == DWF_F16 ? cp : DWF_C64, nr) > 0;
+}
+
+static int precondition(hdcg* h, c64* y, const c64* r, int nr, InnerStats* is, hipStream_t st, PrecGraph* g) {
+  count_precondition(h, nr, is);
+  if (!g || g->failed || !g->warm) {
+    if (g) g->warm = true;
+    return precondition_body(h, y, r, nr, is, st, false);
+  }
+  if (!g->exec) {
+    if (!h->cap_stream) HDCG_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HDCG_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = precondition_body(h, y, r, nr, is, h->cap_stream, true);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    hipError_t ei = hipErrorUnknown;
+    if (rc == DWF_OK && ec == hipSuccess && graph) ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != DWF_OK || ec != hipSuccess || ei != hipSuccess) {
+      // the capture did not work out: this inner solve runs eagerly
+      (void)hipGetLastError();
+      g->failed = true;
+      g->exec = nullptr;
+      return precondition_body(h, y, r, nr, is, st, false);
+    }
+  }
+  HDCG_HIP(hipGraphLaunch(g->exec, st));
+  is->graph_replays += 1;
   return DWF_OK;
 }
 
@@ -440,30 +569,48 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
   double* pw = slot(h, S_APW);
   double* init = slot(h, S_AINIT);
   const bool flex = h->prm.flexible != 0;
+  PrecGraph graph;
+  PrecGraph* g = graph_applies(h, nr) ? &graph : nullptr;
+  if (g) HDCG_TRY(coarse_cg_clear_totals(h, st));
   HDCG_TRY(b_norm2<float>(red, rin, n, nr, init, st));
   HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 10, init, nr * sizeof(double), hipMemcpyDeviceToHost, st));
   // x0 = Q rin ; r0 = rin - H x0
-  HDCG_TRY(apply_Q(h, x, rin, nr, nullptr, 1.0, &is->coarse_iterations, st));
+  HDCG_TRY(apply_Q(h, x, rin, nr, nullptr, 1.0, is, st));
   is->coarse_solves += 1;
-  HDCG_TRY(launch_mpcdagmpc<float>(op, w, x, nr, st, nullptr));
+  {
+    Phase ph(h, PH_FINE_SP, st);
+    HDCG_TRY(launch_mpcdagmpc<float>(op, w, x, nr, st, nullptr));
+  }
   is->matmuls32 += nr;
-  HDCG_HIP(hipMemcpyAsync(r, rin, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
-  HDCG_TRY(b_axpby<float>(r, w, -1.0, 1.0, n * nr, st));
-  HDCG_TRY(precondition(h, y, r, nr, is, st));
-  HDCG_HIP(hipMemcpyAsync(p, y, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
-  if (!flex) HDCG_TRY(b_dot<float>(red, r, y, n, nr, ry[0], st));
+  {
+    Phase ph(h, PH_LINALG, st);
+    HDCG_HIP(hipMemcpyAsync(r, rin, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+    HDCG_TRY(b_axpby<float>(r, w, -1.0, 1.0, n * nr, st));
+  }
+  HDCG_TRY(precondition(h, y, r, nr, is, st, g));
+  {
+    Phase ph(h, PH_LINALG, st);
+    HDCG_HIP(hipMemcpyAsync(p, y, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
+    if (!flex) HDCG_TRY(b_dot<float>(red, r, y, n, nr, ry[0], st));
+  }
   HDCG_HIP(hipStreamSynchronize(st));
   std::vector<double> r0(h->pinned + 64 * 10, h->pinned + 64 * 10 + nr);
   int k = 0;
   while (k < maxiter) {
     // w = H p, (p, w) = |M_pc p|^2 fused into the operator
-    HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pw));
+    {
+      Phase ph(h, PH_FINE_SP, st);
+      HDCG_TRY(launch_mpcdagmpc<float>(op, w, p, nr, st, pw));
+    }
     is->matmuls32 += nr;
-    if (flex) {
-      HDCG_TRY(b_dot<float>(red, p, r, n, nr, pr, st));  // alpha = (p, r) / (p, w)
-      HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, pr, true, pw, nullptr, 0.0, rr, st));
-    } else {
-      HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, ry[k & 1], true, pw, nullptr, 0.0, rr, st));
+    {
+      Phase ph(h, PH_LINALG, st);
+      if (flex) {
+        HDCG_TRY(b_dot<float>(red, p, r, n, nr, pr, st));  // alpha = (p, r) / (p, w)
+        HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, pr, true, pw, nullptr, 0.0, rr, st));
+      } else {
+        HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, ry[k & 1], true, pw, nullptr, 0.0, rr, st));
+      }
     }
     ++k;
     HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 11, rr, nr * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -475,7 +622,8 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
       if (v > tol * tol * r0[i]) conv = false;
     }
     if (conv) break;
-    HDCG_TRY(precondition(h, y, r, nr, is, st));
+    HDCG_TRY(precondition(h, y, r, nr, is, st, g));
+    Phase ph(h, PH_LINALG, st);
     if (flex) {
       HDCG_TRY(b_dot<float>(red, w, y, n, nr, wy, st));  // beta = -(w, y) / (p, w)
       HDCG_TRY(b_xpay<float>(red, p, y, n, nr, wy, true, pw, -1.0, nullptr, st));
@@ -486,6 +634,16 @@ static int adef2(hdcg* h, c64* x, const c64* rin, int nr, double tol, int maxite
     }
   }
   is->iterations += k;
+  if (g && graph.exec) {
+    // the replays' coarse solves left their counts on the device
+    long long its = 0;
+    HDCG_TRY(coarse_cg_totals(h, nr, nullptr, &its, is->coarse_it_rhs, st));
+    is->coarse_iterations += (int)its;
+  }
+  if (h->timer.on) {
+    HDCG_HIP(hipStreamSynchronize(st));
+    HDCG_TRY(h->timer.collect());
+  }
   return DWF_OK;
 }
 
@@ -538,6 +696,9 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->m1_order = 16;
   p->m1_shift = 0.0;
   p->surface_depth = 0;
+  p->coarse_persistent = 1;
+  p->graph = 1;
+  p->phase_timing = 0;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -580,6 +741,7 @@ int hdcg_destroy(hdcg_t h) {
   h->nbr9.release();
   h->ycw.release();
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return DWF_OK;
 }
@@ -831,9 +993,10 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.m1_order = p->m1_order;
     h->prm.m1_shift = p->m1_shift;
     h->prm.surface_depth = p->surface_depth;
+    h->persistent_coarse = p->coarse_persistent != 0;
+    h->use_graph = p->graph != 0;
+    h->timer.on = p->phase_timing != 0;
   }
-  // HDCG_COARSE_PERSISTENT=0 selects the launch-per-step coarse CG (comparisons)
-  if (const char* e = std::getenv("HDCG_COARSE_PERSISTENT")) h->persistent_coarse = std::atoi(e) != 0;
   if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec, h->prm.phi_prec); rc < 0) {
     delete h;
     return rc;
@@ -994,13 +1157,21 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
   {
     HDCG_TRY(ensure_at128(h, st));
     HDCG_TRY(coarse_cg<double>(h, h->AT128.as<c128>(), static_cast<c128*>(x), static_cast<const c128*>(b), nrhs,
-                               tol, maxiter, &it, st));
+                               tol, maxiter, &it, st, -1, 0.0, h->last_coarse_iters));
   } else
     HDCG_TRY(coarse_cg<float>(h, h->AT64.as<c64>(), static_cast<c64*>(x), static_cast<const c64*>(b), nrhs, tol,
-                              maxiter, &it, st, m16 ? prec : -1));
+                              maxiter, &it, st, m16 ? prec : -1, 0.0, h->last_coarse_iters));
+  h->last_coarse_nrhs = nrhs;
   HDCG_HIP(hipStreamSynchronize(st));
   if (iters) *iters = it;
   return it >= maxiter ? DWF_NOT_CONVERGED : DWF_OK;
+}
+
+int hdcg_coarse_iterations(hdcg_t h, int* iters_rhs, int nrhs) {
+  if (!h || !iters_rhs) return fail(DWF_ERR_ARG, "null argument");
+  if (nrhs != h->last_coarse_nrhs) return fail(DWF_ERR_ARG, "nrhs differs from the last hdcg_coarse_solve");
+  for (int i = 0; i < nrhs; ++i) iters_rhs[i] = h->last_coarse_iters[i];
+  return DWF_OK;
 }
 
 int hdcg_mirs(hdcg_t h, void* out, const void* in, int nrhs, void* stream) {
@@ -1042,6 +1213,9 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.m1_hi = p->m1_hi;
   h->prm.m1_order = p->m1_order;
   h->prm.m1_shift = p->m1_shift;
+  h->persistent_coarse = p->coarse_persistent != 0;
+  h->use_graph = p->graph != 0;
+  h->timer.on = p->phase_timing != 0;
   // the estimated Chebyshev bound (m1_hi <= 0) is taken now, not inside a
   // solve; if it fails the previous parameters are restored
   if (h->prm.ldop_m1 == 1 && h->prm.m1_hi <= 0.0) {
@@ -1108,7 +1282,7 @@ int hdcg_export_ldop(hdcg_t h, int* n_global, void* Z_c128, double* D_host, void
 
 // FP64 defect correction for one group of right-hand sides solved together.
 static int solve_group(hdcg* h, c128* x, const c128* b, int nrhs, double tol, InnerStats* is,
-                       int* outer_out, double* mm64_out, double* rel_out, hipStream_t st) {
+                       int* outer_out, double* mm64_out, double* rel_rhs, hipStream_t st) {
   dwf_op* op = h->op;
   const size_t fe = op->field_elems(1);
   constexpr int kOuterChunk = 4;  // FP64 residual computed a few right-hand sides at a time
@@ -1129,7 +1303,7 @@ static int solve_group(hdcg* h, c128* x, const c128* b, int nrhs, double tol, In
   HDCG_HIP(hipStreamSynchronize(st));
   std::vector<double> bb(h->pinned + 64 * 12, h->pinned + 64 * 12 + nrhs);
   int outer = 0;
-  double mm64 = 0, rel = 0;
+  double mm64 = 0;
   int status = DWF_OK;
   for (;;) {
     // r = b - H x in FP64
@@ -1137,19 +1311,27 @@ static int solve_group(hdcg* h, c128* x, const c128* b, int nrhs, double tol, In
     if (outer > 0) {
       for (int r0 = 0; r0 < nrhs; r0 += kOuterChunk) {
         const int nc = std::min(kOuterChunk, nrhs - r0);
-        HDCG_TRY(launch_mpcdagmpc<double>(op, w, x + (size_t)r0 * fe, nc, st, nullptr));
+        {
+          Phase ph(h, PH_FINE_DP, st);
+          HDCG_TRY(launch_mpcdagmpc<double>(op, w, x + (size_t)r0 * fe, nc, st, nullptr));
+        }
+        Phase ph(h, PH_LINALG, st);
         HDCG_TRY(b_axpby<double>(r + (size_t)r0 * fe, w, -1.0, 1.0, fe * nc, st));
       }
       mm64 += nrhs;
     }
-    HDCG_TRY(b_norm2<double>(red, r, fe, nrhs, orr, st));
+    {
+      Phase ph(h, PH_LINALG, st);
+      HDCG_TRY(b_norm2<double>(red, r, fe, nrhs, orr, st));
+    }
     HDCG_HIP(hipMemcpyAsync(h->pinned + 64 * 13, orr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     HDCG_HIP(hipStreamSynchronize(st));
-    rel = 0;
+    double rel = 0;
     for (int i = 0; i < nrhs; ++i) {
       const double v = h->pinned[64 * 13 + i];
       if (!std::isfinite(v)) return fail(DWF_ERR_NUMERIC, "outer residual not finite");
-      rel = std::max(rel, bb[i] > 0 ? std::sqrt(v / bb[i]) : 0.0);
+      rel_rhs[i] = bb[i] > 0 ? std::sqrt(v / bb[i]) : 0.0;
+      rel = std::max(rel, rel_rhs[i]);
     }
     if (rel <= tol) break;
     if (outer >= h->prm.outer_maxiter) {
@@ -1159,16 +1341,84 @@ static int solve_group(hdcg* h, c128* x, const c128* b, int nrhs, double tol, In
     // inner complex64 solve on the normalised residual, x += |r| e; the inner
     // target is only as tight as the remaining reduction needs (never below
     // the complex64 floor inner_tol)
-    HDCG_TRY(b_scale_copy<float, double>(r64, r, orr, true, fe, nrhs, st));
+    {
+      Phase ph(h, PH_CONVERT, st);
+      HDCG_TRY(b_scale_copy<float, double>(r64, r, orr, true, fe, nrhs, st));
+    }
     const double itol = std::max(h->prm.inner_tol, 0.5 * tol / rel);
     HDCG_TRY(adef2(h, e64, r64, nrhs, itol, h->prm.inner_maxiter, is, st));
-    HDCG_TRY(b_axpy_mixed<double, float>(x, e64, orr, fe, nrhs, st, true));
+    {
+      Phase ph(h, PH_CONVERT, st);
+      HDCG_TRY(b_axpy_mixed<double, float>(x, e64, orr, fe, nrhs, st, true));
+    }
     ++outer;
+  }
+  if (h->timer.on) {
+    HDCG_HIP(hipStreamSynchronize(st));
+    HDCG_TRY(h->timer.collect());
   }
   *outer_out = outer;
   *mm64_out += mm64;
-  *rel_out = rel;
   return status;
+}
+
+// Right-hand sides solved together: up to 16 (one batch shares every pass
+// over the operators, and the coarse solve of all of them is one persistent
+// kernel), fewer when the work fields of that many would not fit the free
+// device memory (about 13 complex64, 7 16-bit and 2 complex128 fine fields
+// per right-hand side, counting those already held for reuse).
+static int group_size(hdcg* h, int nrhs) {
+  const size_t fe = fine_elems(h);
+  const size_t per = fe * (13 * sizeof(c64) + 7 * sizeof(bf16c) + 2 * sizeof(c128));
+  size_t held = 0;
+  for (auto& b : h->fw64) held += b.bytes;
+  for (auto& b : h->fw16) held += b.bytes;
+  for (auto& b : h->fw128) held += b.bytes;
+  for (auto& a : h->op->tmp)
+    for (auto& b : a) held += b.bytes;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+  const size_t avail = free_b + held;
+  int g = std::min(16, nrhs);
+  while (g > 1 && per * (size_t)g + ((size_t)1 << 30) > avail) --g;
+  return g;
+}
+
+// ---------------------------------------------------------- phase timer --
+int PhaseTimer::begin(int c, hipStream_t st) {
+  if (!on) return -1;
+  if (2 * used + 2 > pool.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+  }
+  if (cat.size() <= used) cat.resize(used + 1);
+  const int idx = (int)used++;
+  cat[idx] = c;
+  if (hipEventRecord(pool[2 * idx], st) != hipSuccess) return -1;
+  return idx;
+}
+
+void PhaseTimer::end(int idx, hipStream_t st) {
+  if (idx >= 0) (void)hipEventRecord(pool[2 * idx + 1], st);
+}
+
+int PhaseTimer::collect() {
+  for (size_t i = 0; i < used; ++i) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pool[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]) != hipSuccess)
+      return fail(DWF_ERR_HIP, "phase timing event failed");
+    sec[cat[i]] += ms * 1e-3;
+  }
+  used = 0;
+  return DWF_OK;
+}
+
+PhaseTimer::~PhaseTimer() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
 int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol, struct hdcg_stats* stats,
@@ -1178,24 +1428,31 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
   auto st = static_cast<hipStream_t>(stream);
   const auto t0 = std::chrono::steady_clock::now();
   const size_t fe = h->op->field_elems(1);
-  // right-hand sides are solved together in groups of at most kGroup: they
-  // share every coarse solve, and the work memory stays bounded
-  constexpr int kGroup = 8;
+  const int kGroup = group_size(h, nrhs);
+  h->timer.reset();
   InnerStats is;
   int outer = 0, status = DWF_OK;
   double mm64 = 0, rel = 0;
+  double rel_rhs[64] = {};
   for (int g0 = 0; g0 < nrhs; g0 += kGroup) {
     const int ng = std::min(kGroup, nrhs - g0);
     int o = 0;
-    double rg = 0;
+    InnerStats gs;
     const int rc = solve_group(h, static_cast<c128*>(x_c128) + (size_t)g0 * fe,
-                               static_cast<const c128*>(b_c128) + (size_t)g0 * fe, ng, tol, &is, &o, &mm64,
-                               &rg, st);
+                               static_cast<const c128*>(b_c128) + (size_t)g0 * fe, ng, tol, &gs, &o, &mm64,
+                               rel_rhs + g0, st);
     if (rc < 0) return rc;
     if (rc == DWF_NOT_CONVERGED) status = DWF_NOT_CONVERGED;
     outer = std::max(outer, o);
-    rel = std::max(rel, rg);
+    is.iterations += gs.iterations;
+    is.coarse_solves += gs.coarse_solves;
+    is.coarse_iterations += gs.coarse_iterations;
+    is.graph_replays += gs.graph_replays;
+    is.matmuls32 += gs.matmuls32;
+    is.matmuls16 += gs.matmuls16;
+    for (int i = 0; i < ng; ++i) is.coarse_it_rhs[g0 + i] = gs.coarse_it_rhs[i];
   }
+  for (int i = 0; i < nrhs; ++i) rel = std::max(rel, rel_rhs[i]);
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->outer_iterations = outer;
@@ -1203,11 +1460,25 @@ int hdcg_solve(hdcg_t h, void* x_c128, const void* b_c128, int nrhs, double tol,
     stats->coarse_solves = is.coarse_solves;
     stats->coarse_iterations = is.coarse_iterations;
     stats->converged = status == DWF_OK;
+    stats->nrhs = nrhs;
     stats->true_residual = rel;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     stats->setup_seconds = h->setup_seconds;
     stats->matmuls_fp64 = mm64;
     stats->matmuls_fp32 = is.matmuls32;
+    stats->matmuls_bf16 = is.matmuls16;
+    stats->group_size = kGroup;
+    stats->graph_replays = is.graph_replays;
+    stats->t_fine_dp = h->timer.sec[PH_FINE_DP];
+    stats->t_fine_sp = h->timer.sec[PH_FINE_SP];
+    stats->t_coarse = h->timer.sec[PH_COARSE];
+    stats->t_project_promote = h->timer.sec[PH_PROJ];
+    stats->t_linalg = h->timer.sec[PH_LINALG];
+    stats->t_convert = h->timer.sec[PH_CONVERT];
+    for (int i = 0; i < nrhs; ++i) {
+      stats->coarse_iterations_rhs[i] = is.coarse_it_rhs[i];
+      stats->true_residual_rhs[i] = rel_rhs[i];
+    }
   }
   if (status == DWF_NOT_CONVERGED) set_error("hdcg_solve: outer iteration limit reached");
   return status;

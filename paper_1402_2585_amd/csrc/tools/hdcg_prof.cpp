@@ -83,7 +83,8 @@ int main(int argc, char** argv) {
     return 0;
   }
   if (!std::strcmp(argv[1], "sweep")) {
-    // hdcg_prof sweep X Y Z T Ls prec reps tile1 tile2 ...   (tile = "bx,by,bz,bt,remap")
+    // hdcg_prof sweep X Y Z T Ls prec reps shape1 shape2 ...
+    // (shape = "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]", see dwf_set_hop_shape)
     int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
     const int Ls = std::atoi(argv[6]);
     const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : DWF_C128;
@@ -99,9 +100,15 @@ int main(int argc, char** argv) {
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     for (int a = 9; a < argc; ++a) {
-      setenv("HDCG_HOP_TILE", argv[a], 1);
+      int shape[9] = {2, 2, 1, 1, 1, 0, 1, 1, 4};
+      if (std::sscanf(argv[a], "%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1], &shape[2], &shape[3], &shape[4],
+                      &shape[5], &shape[6], &shape[7], &shape[8]) < 4) {
+        std::fprintf(stderr, "bad shape %s\n", argv[a]);
+        return 2;
+      }
       dwf_op_t op;
       ACHECK(dwf_create(&op, dims, Ls, 1.8, 0.01, dU, nullptr, nullptr));
+      ACHECK(dwf_set_hop_shape(op, shape));
       size_t bytes = 0;
       ACHECK(dwf_field_bytes(op, prec, 1, &bytes));
       void *x, *y;

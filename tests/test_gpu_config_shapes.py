@@ -177,9 +177,10 @@ def test_coarse_kernels_on_seeded_operator(shape):
 
 
 def test_coarse_solves_on_seeded_operator(shape):
-    """Coarse CG (complex64 VALU and bf16 / fp16 MFMA storage, one right-hand
-    side in the persistent kernel and several at once) on a seeded operator,
-    against a dense solve.  The 16-bit runs use a better-conditioned operator
+    """Coarse CG (complex64 VALU and bf16 / fp16 MFMA storage) on a seeded
+    operator against a dense solve: one right-hand side, and 5 and 16 at once
+    in the batched persistent kernel, whose per-right-hand-side masks give
+    uneven iteration counts (a zero source takes none).  The 16-bit runs use a better-conditioned operator
     (mass 1, condition ~ 17) so that the rounding of A (relative 2^-9 for
     bf16) stays below the solve tolerance in the solution."""
     t = shape
@@ -192,14 +193,28 @@ def test_coarse_solves_on_seeded_operator(shape):
         for nr in (1, 5, 16):
             b = synth.gaussian_coarse(h.Nc, h.nvec, 451 + nr, nr)
             if nr == 16:
-                b[3] = 0.0  # a zero right-hand side inside the batch
-                b[7] *= 1e-3  # and one of a very different scale
+                # right-hand sides of different spectral content, so that their
+                # solves need different iteration counts: zero, a rescaled one,
+                # D^j v (high modes weighted up), a point source
+                b[3] = 0.0
+                b[7] *= 1e-3
+                for j, r in enumerate((10, 11, 12, 13), start=1):
+                    v = b[r].ravel()
+                    for _ in range(j):
+                        v = D @ v
+                    b[r] = v.reshape(b[r].shape)
+                b[14] = 0.0
+                b[14, 5, 2] = 1.0
             xw = np.linalg.solve(D, b.reshape(nr, -1).T).T
             for prec in precs:
                 x = torch.zeros((nr, h.Nc, h.nvec), dtype=torch.complex64, device="cuda")
                 rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to("cuda", torch.complex64), prec, nr, tol,
                                               5000)
                 assert rc == 0 and it > 0
+                its = hd.hdcg_coarse_iterations(h.h, nr)
+                assert max(its) == it, (its, it)  # one persistent solve: it runs until the last converges
+                if nr == 16:
+                    assert its[3] == 0 and len(set(its)) > 2, its  # the zero source, uneven counts
                 xg = x.cpu().numpy().reshape(nr, -1).astype(np.complex128)
                 for r in range(nr):
                     nb = np.linalg.norm(b[r])
@@ -209,7 +224,7 @@ def test_coarse_solves_on_seeded_operator(shape):
                     res = np.linalg.norm(b[r].ravel() - D @ xg[r]) / nb
                     err = np.linalg.norm(xg[r] - xw[r]) / np.linalg.norm(xw[r])
                     assert res < check and err < check * 20, (mass, prec, nr, r, res, err)
-                print(f"mass {mass} prec {prec} nrhs {nr}: {it} iterations", flush=True)
+                print(f"mass {mass} prec {prec} nrhs {nr}: {it} iterations, per RHS {its}", flush=True)
 
 
 # ------------------------------------------------------------ end to end --

@@ -247,28 +247,26 @@ def test_config2_full_size_H():
     op.close()
 
 
-# Launch shapes of the hop kernel (HDCG_HOP_TILE = "bx,by,bz,bt,remap,lds_kb,nt,
-# morton,phases", read when the operator is created): every ordering and
-# load-phase path must give the same operator as the oracle.
+# Launch shapes of the hop kernel (dwf_set_hop_shape: bx, by, bz, bt, remap,
+# lds_kb, nt, morton, phases): every ordering and load-phase path must give
+# the same operator as the oracle.
 SHAPES = {
     "default": None,
-    "linear": "0,0,0,0",
-    "two-phases": "2,2,1,1,1,0,1,1,2",
-    "lexicographic-2^4-plain-stores": "2,2,2,2,0,0,0,0,4",
-    "morton-1x2x2x1-no-remap": "1,2,2,1,0,0,1,1,4",
+    "linear": (0, 0, 0, 0, 1, 0, 1, 1, 4),
+    "two-phases": (2, 2, 1, 1, 1, 0, 1, 1, 2),
+    "lexicographic-2^4-plain-stores": (2, 2, 2, 2, 0, 0, 0, 0, 4),
+    "morton-1x2x2x1-no-remap": (1, 2, 2, 1, 0, 0, 1, 1, 4),
 }
 
 
 @pytest.mark.parametrize("shape", list(SHAPES))
-def test_hop_launch_shapes_ls16(shape, monkeypatch):
+def test_hop_launch_shapes_ls16(shape):
     banner(f"launch shape {shape}")
-    if SHAPES[shape] is None:
-        monkeypatch.delenv("HDCG_HOP_TILE", raising=False)
-    else:
-        monkeypatch.setenv("HDCG_HOP_TILE", SHAPES[shape])
     dims, Ls = (8, 8, 4, 8), 16
     U = synth.gauge_field(dims, 0.7, 150)
     op = hd.FineOperator(U, dims, Ls, 1.8, 0.02)
+    if SHAPES[shape] is not None:
+        hd.dwf_set_hop_shape(op.h, SHAPES[shape])
     ref = DWF(U, dims, Ls, 1.8, 0.02)
     b = synth.gaussian_half_field(dims, Ls, 151)
     want = ref.H(b)

@@ -178,20 +178,20 @@ def test_coarse_solve(two_level):
 
 
 @pytest.mark.parametrize("persistent", [True, False])
-def test_coarse_solve_c64_persistent_and_stepwise(two_level, persistent, monkeypatch):
-    """complex64 coarse CG for 1, 3 and 9 right-hand sides, as one persistent
-    kernel (up to 8 right-hand sides) and as one launch per step; every
-    solution checked against the oracle's dense coarse operator."""
+def test_coarse_solve_c64_persistent_and_stepwise(two_level, persistent):
+    """complex64 coarse CG for 1, 3, 9 and 16 right-hand sides, as one
+    persistent kernel (up to 16 right-hand sides, each masked off once it
+    converges) and as one launch per step; every solution checked against the
+    oracle's dense coarse operator."""
     t = two_level
     banner(f"coarse solve c64 persistent={persistent} {t['name']}")
     if persistent:
         h, own = t["h"], False
     else:
-        monkeypatch.setenv("HDCG_COARSE_PERSISTENT", "0")
         raw = synth.gaussian_half_field(t["dims"], t["Ls"], 301, nrhs=t["nvec"])
-        h, own = hd.HDCG(t["op"], t["block"], raw), True
+        h, own = hd.HDCG(t["op"], t["block"], raw, coarse_persistent=0), True
     D = ocrs.to_dense(t["A"], t["C"])
-    for nr in (1, 3, 9):
+    for nr in (1, 3, 9, 16):
         g = synth.rng(340 + nr)
         b = g.standard_normal((nr, h.Nc, h.nvec)) + 1j * g.standard_normal((nr, h.Nc, h.nvec))
         x = h.new_coarse(hd.DWF_C64, nr)
