@@ -345,6 +345,28 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
  * so these counts differ from each other and from *iters (the longest). */
 int hdcg_coarse_iterations(hdcg_t h, int* iters_rhs, int nrhs);
 
+/* hdcg_coarse_solve for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid it): the
+ * same persistent coarse CG, with its work memory (r, two search-direction
+ * buffers, A p, the per-workgroup partial sums and the grid-barrier state)
+ * carved from one static device array of 64 MiB that each device holds
+ * until the process ends, instead of the handle's buffers.  Calls no
+ * hipMalloc / hipFree.  The work memory, about 4 * 8 * Nc * nvec * nrhs
+ * bytes plus at most 1.1 MiB, must fit the array (the 24^3x48 grid with 4^4 blocks,
+ * Nc 2592, nvec 48, fits up to 16 right-hand sides); otherwise
+ * DWF_ERR_ARG.  prec DWF_C64, or DWF_BF16 / DWF_F16 once that 16-bit storage
+ * exists (built by an earlier call that allocates: hdcg_setup with
+ * coarse_prec, hdcg_set_params, coarse_apply); nrhs 1..16; nvec <= 64.
+ * DWF_ERR_STATE while the second deflation level is active (ldop_defl = 1
+ * after hdcg_ldop_setup): that solve is not covered.  Results equal those
+ * of hdcg_coarse_solve on the same handle and inputs (the same kernel and
+ * launch shape).  All calls on one device share the array and it keeps the
+ * last call's contents (every call re-initialises what it reads): calls
+ * that overlap in time on one device, from any handle or stream, race.
+ * Synchronises; DWF_NOT_CONVERGED at maxiter. */
+int hdcg_coarse_solve_noalloc(hdcg_t h, void* x, const void* b, int prec, int nrhs, double tol, int maxiter,
+                              int* iters, void* stream);
+
 
 /* out = M_IRS in: exactly n_irs CG iterations on H + lambda_irs from zero
  * (Sec. IV.C) with the work fields stored as p->irs_prec selects (complex64,

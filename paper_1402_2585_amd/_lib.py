@@ -125,6 +125,7 @@ def load():
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_import_coarse": (i, [vp, vp, vp]),
         "hdcg_coarse_iterations": (i, [vp, C.POINTER(C.c_int), i]),
+        "hdcg_coarse_solve_noalloc": (i, [vp, vp, vp, i, i, d, i, C.POINTER(C.c_int), vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "hdcg_solve": (i, [vp, vp, vp, i, d, C.POINTER(HdcgStats), vp]),
@@ -326,6 +327,13 @@ def hdcg_coarse_iterations(h, nrhs):
     a = (C.c_int * nrhs)()
     _check(load().hdcg_coarse_iterations(h, a, int(nrhs)))
     return list(a)
+
+
+def hdcg_coarse_solve_noalloc(h, x, b, prec, nrhs=1, tol=1e-8, maxiter=10000, stream=None):
+    it = C.c_int()
+    rc = _check(load().hdcg_coarse_solve_noalloc(h, _ptr(x), _ptr(b), int(prec), int(nrhs), float(tol), int(maxiter),
+                                                 C.byref(it), _stream(stream)), allow_soft=True)
+    return rc, it.value
 
 
 def hdcg_mirs(h, out, inp, nrhs=1, stream=None):
