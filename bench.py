@@ -1,7 +1,9 @@
 """Benchmark: M_pc^+ M_pc GB/s on one MI355X (16^4 x Ls16 domain-wall
 operator, FP64 complex), with the roofline of the hop kernel and the CPU
 oracle timed on a bounded sample; plus HDCG against plain FP64 CG time to a
-1e-8 residual on the 16^3x32 x Ls16 workload (skip with --no-hdcg).
+1e-8 residual on the 16^3x32 x Ls16 workload (skip with --no-hdcg) and on
+the 24^3x48 x Ls16 workload with one and with 16 right-hand sides (skip
+with --no-big).
 
 Prints ONE JSON line.  Inputs are seeded synthetic SU(3) gauge fields and
 Gaussian sources already resident in HBM when the timed region starts.
@@ -19,6 +21,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes_H(dims, Ls, nrhs, cbytes, gbytes=None):
@@ -195,9 +203,8 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     and HDCG (Nvec=24, 4^4 blocks, 3 inverse-iteration steps each to
     1e-3, complex64 coarse operator and inner solver, FP64 defect correction)
     from the same seeded source, each to a 1e-8 FP64 true residual, on this
-    GPU; then the same HDCG with 16-bit M_IRS fields, with the second
-    deflation level of the coarse operator, and with the rational-filter
-    subspace in place of inverse iteration."""
+    GPU; then the same HDCG with 16-bit M_IRS fields and with the second
+    deflation level of the coarse operator."""
     import numpy as np
 
     import synth
@@ -208,6 +215,7 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
     b = op.to_native(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(0)))
     x = op.new_field(zero=True)
+    log("16^3x32: FP64 CG")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc_cg, st_cg = hd.cg_solve(op.h, x, b, 1, tol, 50000)
@@ -226,6 +234,7 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     h = hd.HDCG(op, w.block, V, n_ii=3, tol_ii=1e-3, maxiter_ii=500)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    log(f"16^3x32 HDCG setup: {t_setup:.1f} s")
     x2 = op.new_field(zero=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -276,27 +285,12 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
         rc5, st5 = hd.hdcg_solve(h.h, x5, b, 1, tol)
         torch.cuda.synchronize()
         t5 = time.perf_counter() - t0
+        log(f"16^3x32 HDCG {name}: {t5:.3f} s")
         ldop[name] = {"seconds": round(t5, 4), "outer": st5["outer_iterations"], "inner": st5["inner_iterations"],
                       "coarse_iterations": st5["coarse_iterations"], "true_residual": true_residual(x5),
                       "status": rc5, "speedup_solve_vs_cg": round(t_cg / t5, 3)}
         del x5
     h.close()
-    # the subspace from the rational filter (Sec. IV.B: lambda = 3e-4,
-    # eps = lambda / 3, multi-shift residual 1e-6, noise on the walls only)
-    # in place of inverse iteration, same noise vectors
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hr = hd.HDCG(op, w.block, V, n_ii=0, subspace_gen=1, rat_lo=3e-4, rat_eps=1e-4, rat_tol=1e-6, wall_noise=1)
-    torch.cuda.synchronize()
-    t_setup_r = time.perf_counter() - t0
-    x4 = op.new_field(zero=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc_r, st_r = hd.hdcg_solve(hr.h, x4, b, 1, tol)
-    torch.cuda.synchronize()
-    t_r = time.perf_counter() - t0
-    rel_r = true_residual(x4)
-    hr.close()
     op.close()
     return {
         "workload": "16^3x32 x Ls16, M5=1.8, m=0.003, eps=0.7, Nvec=24, 4^4 blocks (coarse 4^3x8), "
@@ -317,13 +311,123 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
                            "speedup_solve_vs_cg": round(t_cg / t_b, 3),
                            "speedup_solve_vs_mixed_cg": round(t_mixed / t_b, 3)},
         "hdcg_ldop_deflation": ldop,
-        "hdcg_rational_subspace": {"setup_seconds": round(t_setup_r, 3), "seconds": round(t_r, 4),
-                                   "outer": st_r["outer_iterations"], "inner": st_r["inner_iterations"],
-                                   "coarse_iterations": st_r["coarse_iterations"], "true_residual": rel_r,
-                                   "status": rc_r, "speedup_solve_vs_cg": round(t_cg / t_r, 3)},
         "speedup_solve": round(t_cg / t_h, 3),
         "speedup_solve_vs_mixed_cg": round(t_mixed / t_h, 3),
         "break_even_rhs": (round(t_setup / (t_cg - t_h), 1) if t_cg > t_h else None),
+    }
+
+
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def hdcg_24(hd, torch, tol=1e-8):
+    """The 24^3x48 x Ls16, m = 0.001 workloads on one operator and one
+    subspace: config 4 (one right-hand side; Nvec = 48, 4^4 blocks, the
+    coarse operator in bf16 on MFMA with FP32 accumulation, FP64
+    orthonormalisation and true residual) and config 5 (16 right-hand sides
+    sharing the subspace, solved as one batch: per iteration one persistent
+    coarse-CG launch for all 16 with per-RHS masks, the preconditioner
+    replayed from a captured graph, autotuned MFMA tiles), each to a 1e-8
+    FP64 true residual, against plain FP64 CG on the same GPU from the same
+    sources (config 5: four batches of four) and, for config 4, the
+    mixed-precision CG.  The 48 starting vectors are drawn on the device
+    (Philox4x32-10, seed 4500; three inverse-iteration steps, complex64 CG to
+    1e-3, at most 100 iterations); M_IRS and the subspace copy inside Q are
+    stored in bf16; the FP64 subspace is released after setup (memory for
+    the 16-RHS batch).  Residuals are recomputed with the library's FP64 H
+    (the parity tests check such solutions against the oracle's H)."""
+    import numpy as np
+
+    import synth
+    from synth.configs import WORKLOADS
+
+    w4, w5 = WORKLOADS[4], WORKLOADS[5]
+    op = hd.FineOperator(synth.gauge_field(w4.dims, w4.eps, w4.gauge_seed), w4.dims, w4.Ls, w4.M5, w4.mass)
+    fe = op.Vh * w4.Ls * 12
+
+    def source(seed):
+        return torch.from_numpy(synth.gaussian_half_field(w4.dims, w4.Ls, seed)).to("cuda")
+
+    b4 = op.to_native(source(w4.source_seed(0)))
+    b5 = op.new_field(nrhs=w5.nrhs)
+    for r in range(w5.nrhs):
+        b5[r * fe:(r + 1) * fe] = op.to_native(source(w5.source_seed(r)))
+
+    def true_residuals(x, b, nr):
+        out = []
+        for r in range(nr):
+            xr, br = x[r * fe:(r + 1) * fe], b[r * fe:(r + 1) * fe]
+            res = op.H(xr)
+            hd.dwf_xpay(op.h, res, br, [-1.0], hd.DWF_C128)
+            out.append(float(np.sqrt(hd.dwf_norm2(op.h, res, hd.DWF_C128)[0] / hd.dwf_norm2(op.h, br, hd.DWF_C128)[0])))
+        return out
+
+    log("24^3x48: sources on the device")
+    x = op.new_field(zero=True)
+    t_cg4, (rc, st_cg4) = _timed(torch, lambda: hd.cg_solve(op.h, x, b4, 1, tol, 50000))
+    log(f"config 4 FP64 CG: {t_cg4:.2f} s")
+    x.zero_()
+    t_mx4, (rcm, st_mx4) = _timed(torch, lambda: hd.cg_solve_mixed(op.h, x, b4, 1, tol, 1e-5, 50000))
+    log(f"config 4 mixed CG: {t_mx4:.2f} s")
+    x5 = op.new_field(nrhs=w5.nrhs, zero=True)
+    t_cg5, its5, rel_cg5 = 0.0, 0, 0.0
+    for r0 in range(0, w5.nrhs, 4):
+        xs, bs = x5[r0 * fe:(r0 + 4) * fe], b5[r0 * fe:(r0 + 4) * fe]
+        dt, (rc5, st5) = _timed(torch, lambda: hd.cg_solve(op.h, xs, bs, 4, tol, 50000))
+        t_cg5 += dt
+        log(f"config 5 FP64 CG, right-hand sides {r0}-{r0 + 3}: {dt:.2f} s")
+        its5 = max(its5, st5["iterations"])
+        rel_cg5 = max(rel_cg5, st5["true_residual"])
+    hd.dwf_release_workspace(op.h)
+    t_setup, h = _timed(torch, lambda: hd.HDCG(op, w4.block, None, nvec=w4.nvec, seed=4500, n_ii=3, tol_ii=1e-3,
+                                               maxiter_ii=100, coarse_prec=hd.DWF_BF16, irs_prec=hd.DWF_BF16,
+                                               phi_prec=hd.DWF_BF16, keep_subspace_fp64=0))
+    log(f"24^3x48 HDCG setup: {t_setup:.1f} s")
+    x.zero_()
+    t_h4, (rch4, st_h4) = _timed(torch, lambda: hd.hdcg_solve(h.h, x, b4, 1, tol))
+    log(f"config 4 HDCG solve: {t_h4:.3f} s")
+    rel4 = true_residuals(x, b4, 1)[0]
+    x5.zero_()
+    t_h5, (rch5, st_h5) = _timed(torch, lambda: hd.hdcg_solve(h.h, x5, b5, w5.nrhs, tol))
+    log(f"config 5 HDCG solve (16 RHS): {t_h5:.3f} s")
+    rel5 = true_residuals(x5, b5, w5.nrhs)
+    tile1, _ = hd.hdcg_mfma_tile(h.h, hd.DWF_BF16, 1)
+    tile16, _ = hd.hdcg_mfma_tile(h.h, hd.DWF_BF16, 16)
+    h.close()
+    op.close()
+
+    def hstats(st):
+        return {k: st[k] for k in ("outer_iterations", "inner_iterations", "coarse_solves", "coarse_iterations",
+                                   "matmuls_fp64", "matmuls_fp32", "matmuls_bf16", "group_size", "graph_replays")}
+
+    return {
+        "workload": "24^3x48 x Ls16, M5=1.8, m=0.001, eps=0.7, Nvec=48, 4^4 blocks (coarse 6^3x12), inverse "
+                    "iteration 3 steps to 1e-3 (at most 100 its), bf16 MFMA coarse operator, bf16 M_IRS fields "
+                    "and subspace in Q",
+        "setup_seconds": round(t_setup, 2),
+        "mfma_tiles": {"nrhs_1": tile1, "nrhs_16": tile16},
+        "config4": {
+            "cg_fp64": {"seconds": round(t_cg4, 3), "iterations": st_cg4["iterations"],
+                        "true_residual": st_cg4["true_residual"], "status": rc},
+            "cg_mixed": {"seconds": round(t_mx4, 3), "iterations_c64": st_mx4["iterations"],
+                         "true_residual": st_mx4["true_residual"], "status": rcm},
+            "hdcg": dict(seconds=round(t_h4, 3), true_residual=rel4, status=rch4, **hstats(st_h4)),
+            "speedup_solve_vs_cg": round(t_cg4 / t_h4, 3),
+            "speedup_solve_vs_mixed_cg": round(t_mx4 / t_h4, 3),
+        },
+        "config5": {
+            "nrhs": w5.nrhs,
+            "cg_fp64": {"seconds": round(t_cg5, 3), "max_iterations": its5, "true_residual": rel_cg5},
+            "hdcg": dict(seconds=round(t_h5, 3), true_residual_max=max(rel5), status=rch5,
+                         coarse_iterations_rhs=st_h5["coarse_iterations_rhs"], **hstats(st_h5)),
+            "speedup_solve_vs_cg": round(t_cg5 / t_h5, 3),
+            "break_even_rhs": (round(t_setup / (t_cg5 - t_h5) * w5.nrhs, 1) if t_cg5 > t_h5 else None),
+        },
     }
 
 
@@ -335,6 +439,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-hdcg", action="store_true", help="skip HDCG vs CG at 16^3x32xLs16")
     ap.add_argument("--no-extra", action="store_true", help="skip the copy bandwidth and the 32^3x64 H")
+    ap.add_argument("--no-big", action="store_true", help="skip HDCG vs CG at 24^3x48xLs16 (1 and 16 RHS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver and its kernels run on one GPU; multi-GPU sharding is a design only, so --gpus must be 1"}))
@@ -353,6 +458,7 @@ def main():
     by64 = algorithmic_bytes_H(dims, Ls, 1, 8)
     fl = flops_H(dims, Ls, 1)
 
+    log("16^4: timing H")
     # timed region: `steps` applications of H in FP64 complex
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -400,6 +506,7 @@ def main():
                         "c128_gbs": round(by128 / (med128 * 1e-3) / 1e9, 1),
                         "c64_gbs": round(by64 / (med64 * 1e-3) / 1e9, 1)},
     }
+    log(f"H c128 {ms128:.4f} ms, c64 {ms64:.4f} ms")
     if not args.no_extra:
         # the Mobius kernel (b5 = 1.5, c5 = 0.5) on the same workload
         opm = hd.FineOperator(U, dims, Ls, 1.8, mass, b5=1.5, c5=0.5)
@@ -416,15 +523,19 @@ def main():
         out["mobius"] = {"b5": 1.5, "c5": 0.5,
                          "c128": {"gbs": round(by128 / (msm * 1e-3) / 1e9, 1), "ms_per_application": round(msm, 5)},
                          "c64": {"gbs": round(by64 / (msm64 * 1e-3) / 1e9, 1), "ms_per_application": round(msm64, 5)}}
+        log("copy bandwidth and 32^3x64")
         cb = copy_bandwidth(torch)
         out["roofline"]["copy_gbs_measured"] = round(cb, 1)
         out["roofline"]["frac_of_copy"] = round(gbs128 / cb, 4)
         out["mall_busting"] = mall_busting(hd, torch)
     if not args.no_hdcg:
         out["hdcg_vs_cg"] = hdcg_vs_cg(hd, torch)
+    if not args.no_big:
+        out["hdcg_vs_cg_24^3x48"] = hdcg_24(hd, torch)
     if not args.no_cpu:
         # the oracle forks its workers: release this process's device handles
         # first, and start no GPU work in the children
+        log("CPU oracle baseline")
         single, apps_per_s, workers, wall = cpu_baseline(dims, Ls, eps, mass)
         out["cpu_baseline"] = {
             "value": round(by128 * apps_per_s / 1e9, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",

@@ -115,6 +115,12 @@ int dwf_destroy(dwf_op_t op);
  * launch-shape sweeps and their tests.  DWF_ERR_ARG on an invalid entry. */
 int dwf_set_hop_shape(dwf_op_t op, const int shape[9]);
 
+/* Free the operator's work fields (the intermediate half-fields of M_pc
+ * and the fields of cg_solve, cg_solve_mixed and dwf_multishift_cg, sized
+ * for the largest right-hand-side count used so far); the next call that
+ * needs them allocates them again.  Synchronises the device. */
+int dwf_release_workspace(dwf_op_t op);
+
 /* Bytes of one native half-field buffer holding nrhs right-hand sides
  * (prec DWF_C128, DWF_C64 or DWF_BF16). */
 int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes);
@@ -262,6 +268,18 @@ struct hdcg_params {
                             inner solve as a HIP graph and replayed; 0: launched one by one */
   int phase_timing;      /* 1: hdcg_solve times its phases with HIP events (hdcg_stats t_*;
                             disables the graph); 0 (default): no events */
+  int mfma_tile;         /* -1 (default): the tile of the 16-bit MFMA mat-vec (MFMA form, waves,
+                            K steps in flight) is picked per shape by timing every candidate once
+                            per process (hdcg_mfma_tile reports it); 0..5: that candidate where
+                            the shape allows it (comparisons and tests) */
+  unsigned long long seed; /* hdcg_setup without vectors: seed of the Gaussian starting vectors
+                            it draws on the device (default 1; see hdcg_setup) */
+  int keep_subspace_fp64; /* 1 (default): the handle keeps the FP64 subspace after setup;
+                            0: hdcg_setup frees it once the solve's complex64 (and, as
+                            phi_prec / surface_depth ask, 16-bit or surface-only) copies exist,
+                            two thirds of the subspace memory (49 GB at 24^3 x 48 x 16, Nvec
+                            48); complex128 project / promote, hdcg_export_subspace and a later
+                            switch to a subspace copy not yet built then return DWF_ERR_STATE */
 };
 
 struct hdcg_stats {
@@ -297,7 +315,13 @@ void hdcg_default_params(struct hdcg_params* p);
  * least 3 blocks in every direction so the coarse stencil has 81 distinct
  * points); blocks span all of s.  vectors_c128: device, nvec canonical
  * complex128 half-fields Phi[k][s][cb][spin][colour] (the random starting
- * vectors; the caller draws them).  The library applies p->n_ii steps of
+ * vectors), or NULL: the library then draws them itself on the device from
+ * p->seed with the counter-based generator Philox4x32-10 (Salmon et al.,
+ * SC 2011; counter (i mod 2^32, i div 2^32, 0, 0), key (seed mod 2^32,
+ * seed div 2^32) for complex number i of the canonical array, two 53-bit
+ * uniforms u, v from the output word pairs (0, 1) and (2, 3), Box-Muller
+ * sqrt(-2 ln(1 - u)) (cos 2 pi v + i sin 2 pi v): real and imaginary parts
+ * N(0, 1)), reproducible on any host.  The library applies p->n_ii steps of
  * inverse iteration (complex64 CG, each vector renormalised), orthonormalises
  * the blocked vectors block by block (Cholesky-QR applied twice in FP64:
  * the unique QR with positive diagonal, as Gram-Schmidt gives), and computes
@@ -328,6 +352,22 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
  * complex64 vectors rounded to 16 bits, products accumulated in FP32 on MFMA
  * (vectors in/out complex64).  Asynchronous; out != in. */
 int coarse_apply(hdcg_t h, void* out, const void* in, int prec, int nrhs, void* stream);
+
+/* The tile of the 16-bit MFMA mat-vec (prec DWF_BF16 or DWF_F16) for
+ * nrhs_per_launch right-hand sides per launch (1..16; coarse_apply splits
+ * larger counts into launches of 16), as the project-written autotuner chose
+ * it: the first mat-vec of a shape (storage precision, Nc, nvec, right-hand
+ * sides per launch) times every tile allowed on the shape (one warm-up, best
+ * of three with HIP events) and keeps the fastest for the rest of the
+ * process, for every handle of that shape; a call under graph capture uses
+ * the cached tile or the default.  Tunes now, on zero operands, if that has
+ * not happened.  tile (host, 3 ints): K values per MFMA instruction (16, or
+ * 32 for gfx950's 16x16x32 bf16 / f16 forms), waves per workgroup (the K
+ * range split over them), K steps in flight per wave.  ms (host, nullable,
+ * *ntiles entries): the measured milliseconds of each candidate (-1: not
+ * allowed on the shape); ntiles (host, nullable): the number of candidates.
+ * Synchronises. */
+int hdcg_mfma_tile(hdcg_t h, int prec, int nrhs_per_launch, int tile[3], float* ms, int* ntiles, void* stream);
 
 /* CG on A x = b (A Hermitian positive definite, Sec. V.B) from x = 0 to
  * |r| <= tol |b| for every RHS, with the mat-vec of coarse_apply in precision

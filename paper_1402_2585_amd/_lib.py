@@ -49,7 +49,8 @@ class HdcgParams(C.Structure):
                 ("wall_noise", C.c_int), ("ldop_defl", C.c_int), ("phi_prec", C.c_int),
                 ("ldop_m1", C.c_int), ("m1_lo", C.c_double), ("m1_hi", C.c_double), ("m1_order", C.c_int),
                 ("m1_shift", C.c_double), ("surface_depth", C.c_int), ("coarse_persistent", C.c_int),
-                ("graph", C.c_int), ("phase_timing", C.c_int)]
+                ("graph", C.c_int), ("phase_timing", C.c_int), ("mfma_tile", C.c_int), ("seed", C.c_ulonglong),
+                ("keep_subspace_fp64", C.c_int)]
 
 
 class HdcgStats(C.Structure):
@@ -92,6 +93,7 @@ def load():
         "dwf_create_mobius": (i, [C.POINTER(vp), C.POINTER(C.c_int * 4), i, d, d, d, d, vp, dp, vp]),
         "dwf_destroy": (i, [vp]),
         "dwf_set_hop_shape": (i, [vp, C.POINTER(C.c_int)]),
+        "dwf_release_workspace": (i, [vp]),
         "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
         "dwf_import": (i, [vp, vp, vp, i, i, vp]),
         "dwf_export": (i, [vp, vp, vp, i, i, vp]),
@@ -125,6 +127,7 @@ def load():
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_import_coarse": (i, [vp, vp, vp]),
         "hdcg_coarse_iterations": (i, [vp, C.POINTER(C.c_int), i]),
+        "hdcg_mfma_tile": (i, [vp, i, i, C.POINTER(C.c_int), C.POINTER(C.c_float), C.POINTER(C.c_int), vp]),
         "hdcg_coarse_solve_noalloc": (i, [vp, vp, vp, i, i, d, i, C.POINTER(C.c_int), vp]),
         "hdcg_export_subspace": (i, [vp, vp, vp]),
         "hdcg_export_block_map": (i, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
@@ -189,6 +192,10 @@ def dwf_create_mobius(gauge, dims, Ls, M5, mass, b5, c5, bc=(1, 1, 1, -1), strea
 
 def dwf_destroy(op):
     _check(load().dwf_destroy(op))
+
+
+def dwf_release_workspace(op):
+    _check(load().dwf_release_workspace(op))
 
 
 def dwf_set_hop_shape(op, shape):
@@ -321,6 +328,16 @@ def hdcg_coarse_solve(h, x, b, prec, nrhs=1, tol=1e-8, maxiter=10000, stream=Non
     rc = _check(load().hdcg_coarse_solve(h, _ptr(x), _ptr(b), int(prec), int(nrhs), float(tol), int(maxiter),
                                          C.byref(it), _stream(stream)), allow_soft=True)
     return rc, it.value
+
+
+def hdcg_mfma_tile(h, prec, nrhs_per_launch, stream=None):
+    """(tile, ms): tile = (K per MFMA instruction, waves, K steps per wave);
+    ms = measured milliseconds of every candidate (-1: not allowed)."""
+    t = (C.c_int * 3)()
+    ms = (C.c_float * 32)()
+    n = C.c_int()
+    _check(load().hdcg_mfma_tile(h, int(prec), int(nrhs_per_launch), t, ms, C.byref(n), _stream(stream)))
+    return tuple(t), list(ms[:n.value])
 
 
 def hdcg_coarse_iterations(h, nrhs):

@@ -426,6 +426,17 @@ int dwf_destroy(dwf_op_t op) {
   return DWF_OK;
 }
 
+int dwf_release_workspace(dwf_op_t op) {
+  HDCG_TRY(check_op(op));
+  HDCG_HIP(hipDeviceSynchronize());
+  for (auto& a : op->tmp)
+    for (auto& b : a) b.release();
+  for (auto& b : op->cgw) b.release();
+  for (auto& m : op->mgw) m.release();
+  for (auto& m : op->msw) m.release();
+  return DWF_OK;
+}
+
 int dwf_field_bytes(dwf_op_t op, int prec, int nrhs, size_t* bytes) {
   HDCG_TRY(check_op(op));
   HDCG_TRY(check_prec16(prec));

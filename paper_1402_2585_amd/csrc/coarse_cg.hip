@@ -255,7 +255,8 @@ __device__ __forceinline__ void flag_error(PcgState* st, int accumulate) {
 // One right-hand side.  MODE 0: complex64 VALU operator; 1: bf16 MFMA;
 // 2: fp16 MFMA (MT M tiles).
 constexpr int kMaxNvec = 64;
-template <int MODE, int MT>
+// K32: the 16x16x32 MFMA form (nvec % 8 == 0), else 16x16x16.
+template <int MODE, int MT, bool K32>
 __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_cg(PcgArgs A) {
   constexpr int kRedBytes = MODE == 0 ? kCT * (int)sizeof(c64) : 8 * MT * 64 * (int)sizeof(f32x4);
   __shared__ __align__(16) unsigned char red_raw[kRedBytes];
@@ -327,9 +328,8 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k
       if constexpr (MODE == 0) {
         capply_site<float, 1, 12, true>(A.AT, A.nbr, s_in, A.w, a, Nc, nvec, 1, 0, reinterpret_cast<c64*>(red_raw));
       } else {
-        capply_site_mfma<MODE == 1, MT, 1, 8, (MT >= 3 ? 3 : 4), true>(A.F, A.rho, A.smax, A.nbr, s_in, A.w, a, Nc,
-                                                                       nvec, 1, A.ksteps,
-                                                                       reinterpret_cast<f32x4*>(red_raw));
+        capply_site_mfma<MODE == 1, MT, 1, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), true, false, K32>(
+            A.F, A.rho, A.smax, A.nbr, s_in, A.w, a, Nc, nvec, 1, A.ksteps, reinterpret_cast<f32x4*>(red_raw));
       }
       for (int e = tid; e < nvec; e += kCT) {
         const size_t idx = (size_t)a * nvec + e;
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k
 // Element slots: thread tid owns the elements e = tid and e = tid + kCT of
 // every site (e = rhs * nvec + j < nr * nvec <= 2 kCT), so each thread's
 // partial sums belong to two fixed right-hand sides.
-template <int MODE, int MT, int NT>
+template <int MODE, int MT, int NT, bool K32>
 __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_cg_mrhs(PcgArgs A) {
   constexpr int kRedBytes = MODE == 0 ? kCT * 4 * (int)sizeof(c64) : 8 * MT * NT * 64 * (int)sizeof(f32x4);
   __shared__ __align__(16) unsigned char red_raw[kRedBytes];
@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k
           capply_site<float, 4, 8, false, kStencil, true>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
                                                           reinterpret_cast<c64*>(red_raw));
       } else {
-        capply_site_mfma<MODE == 1, MT, NT, 8, (MT >= 3 ? 3 : 4), false, true>(
+        capply_site_mfma<MODE == 1, MT, NT, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), false, true, K32>(
             A.F, A.rho, A.smax, A.nbr, pk, A.w, a, Nc, nvec, nr, A.ksteps, reinterpret_cast<f32x4*>(red_raw));
       }
       const size_t so = (size_t)a * nvec;
@@ -542,66 +542,76 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k
   finish(A.st, k, nr, s_rr, s_it, A.accumulate);
 }
 
-// kernel of (single or batched, mode, M tiles, N tiles)
-template <int MODE, int MT, int NT, bool BATCH>
+// kernel of (single or batched, mode, M tiles, N tiles, MFMA form)
+template <int MODE, int MT, int NT, bool BATCH, bool K32>
 const void* kernel_of() {
   if constexpr (BATCH)
-    return reinterpret_cast<const void*>(&k_coarse_cg_mrhs<MODE, MT, NT>);
+    return reinterpret_cast<const void*>(&k_coarse_cg_mrhs<MODE, MT, NT, K32>);
   else
-    return reinterpret_cast<const void*>(&k_coarse_cg<MODE, MT>);
+    return reinterpret_cast<const void*>(&k_coarse_cg<MODE, MT, K32>);
 }
 
 // Workgroups of the kernel that can be resident at once, cached per kernel.
-template <int MODE, int MT, int NT, bool BATCH>
+template <int MODE, int MT, int NT, bool BATCH, bool K32>
 int max_grid(int* out) {
   static int cached = 0;
   if (!cached) {
     int dev = 0, cus = 0, per = 0;
     HDCG_HIP(hipGetDevice(&dev));
     HDCG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HDCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel_of<MODE, MT, NT, BATCH>(), kCT, 0));
+    HDCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel_of<MODE, MT, NT, BATCH, K32>(), kCT, 0));
     cached = per * cus;
   }
   *out = cached;
   return DWF_OK;
 }
 
-// The instantiation for the runtime (batch, mode, M tiles, N tiles): its
-// resident-grid size (query) or its launch.  The launch is an ordinary one
-// (it may then sit in a captured graph) with a grid no larger than what can
-// be resident at once; every workgroup then runs concurrently, and a
+// The instantiation for the runtime (batch, mode, M tiles, N tiles, form):
+// its resident-grid size (query) or its launch.  The launch is an ordinary
+// one (it may then sit in a captured graph) with a grid no larger than what
+// can be resident at once; every workgroup then runs concurrently, and a
 // barrier that still waited past its spin limit ends the solve with an
 // error instead of hanging.
-template <int MODE, int MT, int NT, bool BATCH>
+template <int MODE, int MT, int NT, bool BATCH, bool K32>
 int pcg_call(bool query, const PcgArgs* a, int G, int* gmax, hipStream_t st) {
-  if (query) return max_grid<MODE, MT, NT, BATCH>(gmax);
+  if (query) return max_grid<MODE, MT, NT, BATCH, K32>(gmax);
   if constexpr (BATCH)
-    hipLaunchKernelGGL((k_coarse_cg_mrhs<MODE, MT, NT>), dim3(G), dim3(kCT), 0, st, *a);
+    hipLaunchKernelGGL((k_coarse_cg_mrhs<MODE, MT, NT, K32>), dim3(G), dim3(kCT), 0, st, *a);
   else
-    hipLaunchKernelGGL((k_coarse_cg<MODE, MT>), dim3(G), dim3(kCT), 0, st, *a);
+    hipLaunchKernelGGL((k_coarse_cg<MODE, MT, K32>), dim3(G), dim3(kCT), 0, st, *a);
   HDCG_HIP(hipGetLastError());
   return DWF_OK;
 }
 
-template <int MODE, bool BATCH, int NT>
+template <int MODE, bool BATCH, int NT, bool K32>
 int pcg_mt(int mt, bool query, const PcgArgs* a, int G, int* gmax, hipStream_t st) {
   switch (mt) {
-    case 1: return pcg_call<MODE, 1, NT, BATCH>(query, a, G, gmax, st);
-    case 2: return pcg_call<MODE, 2, NT, BATCH>(query, a, G, gmax, st);
-    case 3: return pcg_call<MODE, 3, NT, BATCH>(query, a, G, gmax, st);
-    default: return pcg_call<MODE, 4, (NT > 1 && MODE != 0 ? 1 : NT), BATCH>(query, a, G, gmax, st);
+    case 1: return pcg_call<MODE, 1, NT, BATCH, K32>(query, a, G, gmax, st);
+    case 2: return pcg_call<MODE, 2, NT, BATCH, K32>(query, a, G, gmax, st);
+    case 3: return pcg_call<MODE, 3, NT, BATCH, K32>(query, a, G, gmax, st);
+    default: return pcg_call<MODE, 4, (NT > 1 && MODE != 0 ? 1 : NT), BATCH, K32>(query, a, G, gmax, st);
   }
 }
 
-int pcg_dispatch(int mode, int mt, int nr, bool query, const PcgArgs* a, int G, int* gmax, hipStream_t st) {
+template <int MODE, bool BATCH, int NT>
+int pcg_form(bool k32, int mt, bool query, const PcgArgs* a, int G, int* gmax, hipStream_t st) {
+  return k32 ? pcg_mt<MODE, BATCH, NT, true>(mt, query, a, G, gmax, st)
+             : pcg_mt<MODE, BATCH, NT, false>(mt, query, a, G, gmax, st);
+}
+
+// k32: the 16x16x32 MFMA form (16-bit modes with nvec % 8 == 0)
+int pcg_dispatch(int mode, int mt, bool k32, int nr, bool query, const PcgArgs* a, int G, int* gmax, hipStream_t st) {
   if (nr == 1) {
-    if (mode == 0) return pcg_call<0, 1, 1, false>(query, a, G, gmax, st);
-    return mode == 1 ? pcg_mt<1, false, 1>(mt, query, a, G, gmax, st) : pcg_mt<2, false, 1>(mt, query, a, G, gmax, st);
+    if (mode == 0) return pcg_call<0, 1, 1, false, false>(query, a, G, gmax, st);
+    return mode == 1 ? pcg_form<1, false, 1>(k32, mt, query, a, G, gmax, st)
+                     : pcg_form<2, false, 1>(k32, mt, query, a, G, gmax, st);
   }
-  if (mode == 0) return pcg_call<0, 1, 1, true>(query, a, G, gmax, st);
+  if (mode == 0) return pcg_call<0, 1, 1, true, false>(query, a, G, gmax, st);
   if (nr <= 8)
-    return mode == 1 ? pcg_mt<1, true, 1>(mt, query, a, G, gmax, st) : pcg_mt<2, true, 1>(mt, query, a, G, gmax, st);
-  return mode == 1 ? pcg_mt<1, true, 2>(mt, query, a, G, gmax, st) : pcg_mt<2, true, 2>(mt, query, a, G, gmax, st);
+    return mode == 1 ? pcg_form<1, true, 1>(k32, mt, query, a, G, gmax, st)
+                     : pcg_form<2, true, 1>(k32, mt, query, a, G, gmax, st);
+  return mode == 1 ? pcg_form<1, true, 2>(k32, mt, query, a, G, gmax, st)
+                   : pcg_form<2, true, 2>(k32, mt, query, a, G, gmax, st);
 }
 
 // ---------------------------------------------------------- workspace --
@@ -631,6 +641,11 @@ PcgWork carve(unsigned char* base, size_t n, int G) {
   return w;
 }
 
+// The 16x16x32 MFMA form for the 16-bit modes when nvec allows it (8 K
+// values of one stencil point per lane); the autotuner of the standalone
+// mat-vec picks this form on every workload shape measured.
+bool use_k32(int mode, int nvec) { return mode != 0 && nvec % 8 == 0; }
+
 // Shape of the launch for (mprec, nr): mode, M tiles and the grid; false
 // when the persistent form does not apply.
 bool plan(hdcg* h, int mprec, int nr, int* mode, int* mt, int* G) {
@@ -642,7 +657,7 @@ bool plan(hdcg* h, int mprec, int nr, int* mode, int* mt, int* G) {
   if (m16 && nr > 8 && *mt > 3) return false;  // the 2-tile-wide reduction of 4 M tiles exceeds LDS
   *mode = !m16 ? 0 : (mprec == DWF_BF16 ? 1 : 2);
   int gmax = 0;
-  if (pcg_dispatch(*mode, *mt, nr, true, nullptr, 0, &gmax, nullptr) < 0 || gmax < 1) return false;
+  if (pcg_dispatch(*mode, *mt, use_k32(*mode, nv), nr, true, nullptr, 0, &gmax, nullptr) < 0 || gmax < 1) return false;
   *G = std::min(std::min(h->Nc, gmax), kMaxGrid);
   return true;
 }
@@ -677,7 +692,7 @@ int launch_solve(hdcg* h, const PcgWork& wk, int mode, int mt, int G, int mprec,
   a.st = wk.st;
   hipLaunchKernelGGL(k_pcg_reset, dim3(1), dim3(256), 0, st, a.st, G);
   HDCG_HIP(hipGetLastError());
-  return pcg_dispatch(mode, mt, nr, false, &a, G, nullptr, st);
+  return pcg_dispatch(mode, mt, use_k32(mode, nv), nr, false, &a, G, nullptr, st);
 }
 
 // Read one solve's results back (synchronises).

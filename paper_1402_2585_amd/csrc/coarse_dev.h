@@ -6,6 +6,8 @@
 // Both forms take one coarse site a per 512-thread workgroup (8 waves).
 #pragma once
 
+#include <type_traits>
+
 #include "hdcg_impl.h"
 
 namespace hdk {
@@ -141,18 +143,29 @@ __device__ __forceinline__ unsigned short to16(float f) {
 // nrhs right-hand sides of `in` (at most 16 when NT = 2, 8 when NT = 1).
 // With STAGED (one right-hand side) `in` is the site's operand gathered
 // into LDS: in[l * nvec + k] = c[nbr(a,l)][k].  COH: the operand is read
-// with coherent loads (persistent kernels).  Every thread of the workgroup
+// with coherent loads (persistent kernels).  K32: gfx950's 16x16x32 MFMA
+// (8 K values per lane; the A fragment of one 32-wide step is two
+// consecutive 16-wide storage steps, one 16-byte load per lane; needs
+// nvec % 8 == 0), else the 16x16x16 form.  Every thread of the workgroup
 // (NW * 64 threads) must call it.
-template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false, bool COH = false>
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false, bool COH = false, bool K32 = false>
 __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restrict__ F,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ smax, const int* __restrict__ nbr,
                                                  const c64* __restrict__ in, c64* __restrict__ out, int a,
                                                  int Nc, int nvec, int nrhs, int ksteps, f32x4* red) {
+  using frag = std::conditional_t<K32, s16x8, s16x4>;
+  constexpr int KL = K32 ? 8 : 4;  // K values per lane and step
+  constexpr int KS = 4 * KL;       // K values per step
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ktot = 2 * kStencil * nvec;
   const int kn = kStencil * nvec;
   const int r16 = lane & 15, kg = lane >> 4;
+  const int nsteps = K32 ? (ksteps + 1) / 2 : ksteps;
   f32x4 acc[MT][NT];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -161,26 +174,28 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
   const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
   const int* nb = nbr + (size_t)a * kStencil;
   const float* rh = rho + (size_t)a * kStencil;
-  for (int s0 = wave * U; s0 < ksteps; s0 += NW * U) {
-    s16x4 af[U][MT];
-    s16x4 bf[U][NT];
+  // storage step and k group of this lane's A fragment at step S
+  const int sub = K32 ? (kg >> 1) : 0, kgs = K32 ? 2 * (kg & 1) : kg;
+  for (int s0 = wave * U; s0 < nsteps; s0 += NW * U) {
+    frag af[U][MT];
+    frag bf[U][NT];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int s = s0 + u;
+      const int s = (K32 ? 2 * (s0 + u) : s0 + u) + sub;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int m = mt * 16 + r16;
         af[u][mt] = (s < ksteps && m < nvec)
-                        ? *reinterpret_cast<const s16x4*>(Fa + (((size_t)s * nvec + m) * 4 + kg) * 4)
-                        : s16x4{0, 0, 0, 0};
+                        ? *reinterpret_cast<const frag*>(Fa + (((size_t)s * nvec + m) * 4 + kgs) * 4)
+                        : frag{};
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k0 = 16 * (s0 + u) + 4 * kg;
+      const int k0 = KS * (s0 + u) + KL * kg;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = s16x4{0, 0, 0, 0};
-      if (s0 + u < ksteps && k0 < ktot) {
+      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = frag{};
+      if (s0 + u < nsteps && k0 < ktot) {
         const int part = k0 / kn;
         const int rem = k0 - part * kn;
         const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
@@ -193,9 +208,9 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
             const bool imcol = g >= nrhs;
             const int rr = imcol ? g - nrhs : g;
             const size_t co = (size_t)rr * Nc * nvec + vo;
-            float v[4];
+            frag b;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < KL; ++i) {
               c64 x;
               if constexpr (STAGED)
                 x = in[rem + i];
@@ -205,13 +220,8 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
                 x = in[co + i];
               // columns r:        part 0 -> Re c, part 1 -> -Im c
               // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
-              v[i] = r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im));
+              b[i] = (short)to16<BF16>(r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im)));
             }
-            s16x4 b;
-            b.x = (short)to16<BF16>(v[0]);
-            b.y = (short)to16<BF16>(v[1]);
-            b.z = (short)to16<BF16>(v[2]);
-            b.w = (short)to16<BF16>(v[3]);
             bf[u][nt] = b;
           }
         }
@@ -223,12 +233,23 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          if (BF16)
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u][mt], bf[u][nt], acc[mt][nt], 0, 0, 0);
-          else
-            acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[u][mt]),
-                                                                __builtin_bit_cast(h16x4, bf[u][nt]),
-                                                                acc[mt][nt], 0, 0, 0);
+          if constexpr (K32) {
+            if constexpr (BF16)
+              acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[u][mt]),
+                                                                    __builtin_bit_cast(bf16x8, bf[u][nt]),
+                                                                    acc[mt][nt], 0, 0, 0);
+            else
+              acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h16x8, af[u][mt]),
+                                                                   __builtin_bit_cast(h16x8, bf[u][nt]),
+                                                                   acc[mt][nt], 0, 0, 0);
+          } else {
+            if constexpr (BF16)
+              acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[u][mt], bf[u][nt], acc[mt][nt], 0, 0, 0);
+            else
+              acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h16x4, af[u][mt]),
+                                                                  __builtin_bit_cast(h16x4, bf[u][nt]),
+                                                                  acc[mt][nt], 0, 0, 0);
+          }
         }
   }
 #pragma unroll

@@ -2,6 +2,11 @@
 // or fp16) and FP32 accumulation: per-matrix scales, fragment-ordered
 // storage and the standalone mat-vec launch.  The per-site GEMM itself
 // (operand layout, scaling) is capply_site_mfma in coarse_dev.h.
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "coarse_dev.h"
 
 namespace hdk {
@@ -71,18 +76,19 @@ __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho
   for (int i = 0; i < 4; ++i) o[i] = v4[i];
 }
 
-template <bool BF16, int MT, int NT, int NW, int U>
+template <bool BF16, int MT, int NT, int NW, int U, bool K32>
 __global__ void __launch_bounds__(NW * 64)
 k_capply_mfma(const unsigned short* __restrict__ F, const float* __restrict__ rho,
               const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
               c64* __restrict__ out, int Nc, int nvec, int nrhs, int ksteps) {
   __shared__ f32x4 red[NW * MT * NT * 64];
-  capply_site_mfma<BF16, MT, NT, NW, U>(F, rho, smax, nbr, in, out, blockIdx.x, Nc, nvec, nrhs, ksteps, red);
+  capply_site_mfma<BF16, MT, NT, NW, U, false, false, K32>(F, rho, smax, nbr, in, out, blockIdx.x, Nc, nvec, nrhs,
+                                                           ksteps, red);
 }
 
 // One right-hand side: the site's operand at its 81 neighbours is gathered
 // into LDS first (one coalesced pass).
-template <bool BF16, int MT>
+template <bool BF16, int MT, int U, bool K32>
 __global__ void __launch_bounds__(8 * 64)
 k_capply_mfma_staged(const unsigned short* __restrict__ F, const float* __restrict__ rho,
                      const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
@@ -96,40 +102,181 @@ k_capply_mfma_staged(const unsigned short* __restrict__ F, const float* __restri
     xin[e] = in[(size_t)nb[l] * nvec + (e - l * nvec)];
   }
   __syncthreads();
-  capply_site_mfma<BF16, MT, 1, 8, 4, true>(F, rho, smax, nbr, xin, out, a, Nc, nvec, 1, ksteps, red);
+  capply_site_mfma<BF16, MT, 1, 8, U, true, false, K32>(F, rho, smax, nbr, xin, out, a, Nc, nvec, 1, ksteps, red);
 }
 
-// 8 waves per workgroup while their LDS reduction buffers fit in 48 KiB
+// ---------------------------------------------------------- tile shapes --
+// The variants the autotuner chooses from: MFMA form (16x16x16, or gfx950's
+// 16x16x32 with 8 K values per lane), waves per workgroup (the K range is
+// split over them and reduced through LDS) and K steps per wave in flight.
+// The N tiles follow the right-hand sides (one 16-column tile for up to 8,
+// two for up to 16 per launch) and the M tiles nvec.
+struct Tile {
+  int k32, nw, u;
+};
+constexpr Tile kTiles[] = {{0, 8, 4}, {0, 4, 4}, {0, 8, 2}, {1, 8, 2}, {1, 4, 2}, {1, 8, 4}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+constexpr int kDefaultTile = 0;  // the 16x16x16 form, 8 waves, 4 steps
+
+bool tile_allowed(int t, int nvec, int mt, int nt, bool staged) {
+  const Tile& T = kTiles[t];
+  if (T.k32 && nvec % 8 != 0) return false;
+  if (staged) return T.nw == 8 && (T.k32 ? T.u == 2 : T.u == 4);
+  return (size_t)T.nw * mt * nt * 64 * sizeof(f32x4) <= 48 * 1024;
+}
+
+// the untuned choice: 8 waves while their LDS reduction buffers fit 48 KiB, else 4
+int default_tile(int nvec, int n) {
+  const int mt = (nvec + 15) / 16, nt = 2 * n <= 16 ? 1 : 2;
+  return tile_allowed(kDefaultTile, nvec, mt, nt, n == 1) ? kDefaultTile : 1;
+}
+
+template <bool BF16, int MT, int NT, int NW, int U, bool K32>
+void launch_plain(const unsigned short* F, const float* rho, const float* smax, const int* nbr, const c64* in, c64* out,
+                  int Nc, int nvec, int n, int ksteps, hipStream_t st) {
+  if constexpr ((size_t)NW * MT * NT * 64 * sizeof(f32x4) <= 48 * 1024)
+    hipLaunchKernelGGL((k_capply_mfma<BF16, MT, NT, NW, U, K32>), dim3(Nc), dim3(NW * 64), 0, st, F, rho, smax, nbr,
+                       in, out, Nc, nvec, n, ksteps);
+}
+
 template <bool BF16, int MT, int NT>
-void launch_tile(const unsigned short* F, const float* rho, const float* smax, const int* nbr,
-                 const c64* in, c64* out, int Nc, int nvec, int n, int ksteps, hipStream_t st) {
-  constexpr int U = 4;
-  if constexpr (MT * NT <= 6)
-    hipLaunchKernelGGL((k_capply_mfma<BF16, MT, NT, 8, U>), dim3(Nc), dim3(8 * 64), 0, st, F, rho, smax,
-                       nbr, in, out, Nc, nvec, n, ksteps);
-  else
-    hipLaunchKernelGGL((k_capply_mfma<BF16, MT, NT, 4, U>), dim3(Nc), dim3(4 * 64), 0, st, F, rho, smax,
-                       nbr, in, out, Nc, nvec, n, ksteps);
+void launch_tile(int t, const unsigned short* F, const float* rho, const float* smax, const int* nbr, const c64* in,
+                 c64* out, int Nc, int nvec, int n, int ksteps, hipStream_t st) {
+  switch (t) {
+    case 0: return launch_plain<BF16, MT, NT, 8, 4, false>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+    case 1: return launch_plain<BF16, MT, NT, 4, 4, false>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+    case 2: return launch_plain<BF16, MT, NT, 8, 2, false>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+    case 3: return launch_plain<BF16, MT, NT, 8, 2, true>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+    case 4: return launch_plain<BF16, MT, NT, 4, 2, true>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+    default: return launch_plain<BF16, MT, NT, 8, 4, true>(F, rho, smax, nbr, in, out, Nc, nvec, n, ksteps, st);
+  }
 }
 
+// One launch of tile t for right-hand sides [r0, r0 + n) (n <= 16).
 template <bool BF16, int MT>
-int launch_mt(hdcg* h, const unsigned short* F, const c64* in, c64* out, int nr, int ksteps,
-              hipStream_t st) {
+int launch_chunk(hdcg* h, int t, const unsigned short* F, const c64* in, c64* out, int n, int ksteps, hipStream_t st) {
   const float* rho = h->mf_rho.as<float>();
   const float* smax = h->mf_smax.as<float>();
+  const int* nbr = h->nbr.as<int>();
+  if (n == 1) {
+    if (kTiles[t].k32)
+      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT, 2, true>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho, smax,
+                         nbr, in, out, h->Nc, h->nvec, ksteps);
+    else
+      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT, 4, false>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho, smax,
+                         nbr, in, out, h->Nc, h->nvec, ksteps);
+  } else if (2 * n <= 16) {
+    launch_tile<BF16, MT, 1>(t, F, rho, smax, nbr, in, out, h->Nc, h->nvec, n, ksteps, st);
+  } else {
+    launch_tile<BF16, MT, 2>(t, F, rho, smax, nbr, in, out, h->Nc, h->nvec, n, ksteps, st);
+  }
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <bool BF16>
+int launch_all(hdcg* h, int t, const unsigned short* F, const c64* in, c64* out, int nr, int ksteps, hipStream_t st) {
+  const int mt = (h->nvec + 15) / 16;
   for (int r0 = 0; r0 < nr; r0 += 16) {
     const int n = nr - r0 < 16 ? nr - r0 : 16;
     const c64* i0 = in + (size_t)r0 * h->Nc * h->nvec;
     c64* o0 = out + (size_t)r0 * h->Nc * h->nvec;
-    if (n == 1)
-      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho, smax,
-                         h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, ksteps);
-    else if (2 * n <= 16)
-      launch_tile<BF16, MT, 1>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);
-    else
-      launch_tile<BF16, MT, 2>(F, rho, smax, h->nbr.as<int>(), i0, o0, h->Nc, h->nvec, n, ksteps, st);
-    HDCG_HIP(hipGetLastError());
+    switch (mt) {
+      case 1: HDCG_TRY((launch_chunk<BF16, 1>(h, t, F, i0, o0, n, ksteps, st))); break;
+      case 2: HDCG_TRY((launch_chunk<BF16, 2>(h, t, F, i0, o0, n, ksteps, st))); break;
+      case 3: HDCG_TRY((launch_chunk<BF16, 3>(h, t, F, i0, o0, n, ksteps, st))); break;
+      default: HDCG_TRY((launch_chunk<BF16, 4>(h, t, F, i0, o0, n, ksteps, st))); break;
+    }
   }
+  return DWF_OK;
+}
+
+// --------------------------------------------------------- the autotuner --
+// The tile of a shape (storage precision, Nc, nvec, right-hand sides per
+// launch) is chosen once per process by timing every allowed variant on the
+// caller's own operands (one warm-up launch, then the best of three timed
+// with HIP events) and kept in a cache shared by all handles.  Tuning needs
+// a host synchronisation, so a call made while its stream is being captured
+// into a graph uses the cached tile, or the default one if there is none.
+struct TuneKey {
+  int prec, Nc, nvec, n;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, Nc, nvec, n) < std::tie(o.prec, o.Nc, o.nvec, o.n);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+std::map<TuneKey, std::vector<float>> g_tune_ms;  // measured ms per tile (negative: not allowed)
+
+int tune(hdcg* h, int prec, const unsigned short* F, const c64* in, c64* out, int n, int ksteps, hipStream_t st,
+         int* best) {
+  const int mt = (h->nvec + 15) / 16, nt = 2 * n <= 16 ? 1 : 2;
+  std::vector<float> ms(kNumTiles, -1.f);
+  hipEvent_t e0, e1;
+  HDCG_HIP(hipEventCreate(&e0));
+  HDCG_HIP(hipEventCreate(&e1));
+  int rc = DWF_OK, bt = default_tile(h->nvec, n);
+  float bms = 0.f;
+  for (int t = 0; t < kNumTiles && rc == DWF_OK; ++t) {
+    if (!tile_allowed(t, h->nvec, mt, nt, n == 1)) continue;
+    if (n == 1) {  // the staged kernel has one variant per MFMA form
+      bool dup = false;
+      for (int q = 0; q < t; ++q)
+        if (ms[q] >= 0.f && kTiles[q].k32 == kTiles[t].k32) dup = true;
+      if (dup) continue;
+    }
+    auto run = [&]() {
+      return prec == DWF_BF16 ? launch_all<true>(h, t, F, in, out, n, ksteps, st)
+                              : launch_all<false>(h, t, F, in, out, n, ksteps, st);
+    };
+    rc = run();
+    float m = 1e30f;
+    for (int rep = 0; rep < 3 && rc == DWF_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = fail(DWF_ERR_HIP, "autotuner event failed");
+      if (rc == DWF_OK) rc = run();
+      if (rc == DWF_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = fail(DWF_ERR_HIP, "autotuner event failed");
+      float x = 0.f;
+      if (rc == DWF_OK && hipEventElapsedTime(&x, e0, e1) == hipSuccess) m = std::min(m, x);
+    }
+    ms[t] = m;
+    if (rc == DWF_OK && (bms == 0.f || m < bms)) {
+      bms = m;
+      bt = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HDCG_TRY(rc);
+  *best = bt;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_ms[TuneKey{prec, h->Nc, h->nvec, n}] = ms;
+  return DWF_OK;
+}
+
+int tile_for(hdcg* h, int prec, const unsigned short* F, const c64* in, c64* out, int n, int ksteps, hipStream_t st,
+             int* t) {
+  if (h->mfma_tile >= 0) {  // a fixed candidate (when allowed on the shape)
+    const int mt = (h->nvec + 15) / 16, nt = 2 * n <= 16 ? 1 : 2;
+    *t = h->mfma_tile < kNumTiles && tile_allowed(h->mfma_tile, h->nvec, mt, nt, n == 1) ? h->mfma_tile
+                                                                                         : default_tile(h->nvec, n);
+    return DWF_OK;
+  }
+  const TuneKey key{prec, h->Nc, h->nvec, n};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      *t = it->second;
+      return DWF_OK;
+    }
+  }
+  *t = default_tile(h->nvec, n);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return DWF_OK;
+  HDCG_TRY(tune(h, prec, F, in, out, n, ksteps, st, t));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = *t;
   return DWF_OK;
 }
 
@@ -172,16 +319,69 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
 int crs_apply_mfma(hdcg* h, int prec, const c64* in, c64* out, int nr, hipStream_t st) {
   if ((prec == DWF_BF16 && !h->mf_have_bf16) || (prec == DWF_F16 && !h->mf_have_f16))
     HDCG_TRY(crs_build_mfma(h, prec, st));
-  const int mtiles = (h->nvec + 15) / 16;
   const int ksteps = (2 * kStencil * h->nvec + 15) / 16;
   const unsigned short* F = (prec == DWF_BF16 ? h->mf_bf16 : h->mf_f16).as<unsigned short>();
-  const bool bf = prec == DWF_BF16;
-  switch (mtiles) {
-    case 1: return bf ? launch_mt<true, 1>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 1>(h, F, in, out, nr, ksteps, st);
-    case 2: return bf ? launch_mt<true, 2>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 2>(h, F, in, out, nr, ksteps, st);
-    case 3: return bf ? launch_mt<true, 3>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 3>(h, F, in, out, nr, ksteps, st);
-    default: return bf ? launch_mt<true, 4>(h, F, in, out, nr, ksteps, st) : launch_mt<false, 4>(h, F, in, out, nr, ksteps, st);
+  // one tile for the full 16-column launches, one for the last, smaller one
+  const int nfull = nr / 16, rest = nr % 16;
+  if (nfull > 0) {
+    int t = 0;
+    HDCG_TRY(tile_for(h, prec, F, in, out, 16, ksteps, st, &t));
+    for (int c = 0; c < nfull; ++c) {
+      const size_t off = (size_t)c * 16 * h->Nc * h->nvec;
+      HDCG_TRY(prec == DWF_BF16 ? launch_all<true>(h, t, F, in + off, out + off, 16, ksteps, st)
+                                : launch_all<false>(h, t, F, in + off, out + off, 16, ksteps, st));
+    }
   }
+  if (rest > 0) {
+    const size_t off = (size_t)nfull * 16 * h->Nc * h->nvec;
+    int t = 0;
+    HDCG_TRY(tile_for(h, prec, F, in + off, out + off, rest, ksteps, st, &t));
+    HDCG_TRY(prec == DWF_BF16 ? launch_all<true>(h, t, F, in + off, out + off, rest, ksteps, st)
+                              : launch_all<false>(h, t, F, in + off, out + off, rest, ksteps, st));
+  }
+  return DWF_OK;
+}
+
+// The tile the autotuner chose for (prec, n right-hand sides per launch) on
+// this handle's shape, tuning now on scratch operands if it has not run:
+// out[0..2] = {MFMA form (16 or 32 K per instruction), waves, K steps per
+// wave}; ms (nullable, kNumTiles entries) the measured times, -1 for tiles
+// not allowed on the shape.
+int crs_mfma_tile(hdcg* h, int prec, int n, int out[3], float* ms, int* ntiles, hipStream_t st) {
+  if (ntiles) *ntiles = kNumTiles;
+  if ((prec == DWF_BF16 && !h->mf_have_bf16) || (prec == DWF_F16 && !h->mf_have_f16))
+    HDCG_TRY(crs_build_mfma(h, prec, st));
+  const TuneKey key{prec, h->Nc, h->nvec, n};
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    have = g_tune.count(key) > 0;
+  }
+  if (!have) {
+    DevBuf a, b;
+    const size_t bytes = (size_t)n * h->Nc * h->nvec * sizeof(c64);
+    HDCG_TRY(a.ensure(bytes));
+    HDCG_TRY(b.ensure(bytes));
+    HDCG_HIP(hipMemsetAsync(a.ptr, 0, bytes, st));
+    int t = 0;
+    const int rc = tile_for(h, prec, (prec == DWF_BF16 ? h->mf_bf16 : h->mf_f16).as<unsigned short>(), a.as<c64>(),
+                            b.as<c64>(), n, (2 * kStencil * h->nvec + 15) / 16, st, &t);
+    HDCG_HIP(hipStreamSynchronize(st));
+    a.release();
+    b.release();
+    HDCG_TRY(rc);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  const int t = it != g_tune.end() ? it->second : default_tile(h->nvec, n);
+  out[0] = kTiles[t].k32 ? 32 : 16;
+  out[1] = kTiles[t].nw;
+  out[2] = kTiles[t].u;
+  if (ms) {
+    auto m = g_tune_ms.find(key);
+    for (int i = 0; i < kNumTiles; ++i) ms[i] = m != g_tune_ms.end() ? m->second[i] : -1.f;
+  }
+  return DWF_OK;
 }
 
 }  // namespace hdk

@@ -120,6 +120,9 @@ struct hdcg {
   int last_coarse_nrhs = 0;
   PhaseTimer timer;                 // phase times of the solve (params.phase_timing)
   int use_graph = 1;                // capture the preconditioner as a graph when it has no host step
+  int mfma_tile = -1;               // 16-bit mat-vec tile: -1 autotuned per shape, >= 0 a fixed candidate
+  unsigned long long seed = 1;      // seed of the starting vectors drawn when the caller gives none
+  int keep_phi128 = 1;              // keep the FP64 subspace after setup
   hipStream_t cap_stream = nullptr; // stream the preconditioner is captured on (never run on)
 };
 
@@ -149,6 +152,7 @@ int blk_promote(hdcg* h, const bf16c* P, const cplx<float>* c, int nr, cplx<floa
 int blk_phi16(hdcg* h, hipStream_t st);        // phi16 = phi128 rounded to bf16 pairs
 int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
 int blk_surface_zero(hdcg* h, hipStream_t st);  // zero phi128 at sd <= s < Ls - sd
+int blk_surface_copies(hdcg* h, bool p16, hipStream_t st);  // build the solve's surface-only copy (sd > 0)
 // the solve's project / promote (complex64 vectors) on the subspace copy
 // phi_prec selects (p16: bf16 pairs), surface slices only when sd > 0
 int solve_project(hdcg* h, bool p16, const cplx<float>* fine, size_t fstride, int nr, cplx<float>* out, size_t sr,
@@ -161,6 +165,8 @@ int crs_idft(hdcg* h, cplx<double>* Y, const cplx<double> finv[4][9], hipStream_
 int crs_transpose(hdcg* h, bool fp64, hipStream_t st);  // A128 -> AT128 (fp64) or AT64
 int crs_build_mfma(hdcg* h, int prec, hipStream_t st);
 int crs_apply_mfma(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
+// the autotuned tile for n right-hand sides per launch: {K per MFMA, waves, K steps per wave}
+int crs_mfma_tile(hdcg* h, int prec, int n, int out[3], float* ms, int* ntiles, hipStream_t st);
 
 // coarse CG from x = 0 on the complex64 (mprec = DWF_C64) or 16-bit MFMA
 // operator as one persistent kernel (coarse_cg.hip), 1..16 right-hand sides

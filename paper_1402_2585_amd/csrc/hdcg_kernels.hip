@@ -624,6 +624,7 @@ __global__ void k_phi_bf16(bf16c* __restrict__ out, const c128* __restrict__ in,
   }
 }
 int blk_phi16(hdcg* h, hipStream_t st) {
+  if (h->phi128.bytes == 0) return fail(DWF_ERR_STATE, "the FP64 subspace was released after setup");
   const size_t total = (size_t)h->Nc * h->nvec * h->nb;
   HDCG_TRY(h->phi16.ensure(total * sizeof(bf16c)));
   size_t nbk = (total + kT - 1) / kT;
@@ -674,12 +675,20 @@ int blk_surface_zero(hdcg* h, hipStream_t st) {
   return DWF_OK;
 }
 static int surface_copy(hdcg* h, bool sixteen, hipStream_t st) {
+  if (h->phi128.bytes == 0) return fail(DWF_ERR_STATE, "the FP64 subspace was released after setup");
   const size_t total = (size_t)h->Nc * h->nvec * h->nsb * 24 * h->sd;
   DevBuf& b = sixteen ? h->phis16 : h->phis64;
   HDCG_TRY(b.ensure(total * (sixteen ? sizeof(bf16c) : sizeof(c64))));
   hipLaunchKernelGGL(k_phi_surface, dim3(grid_of(total)), dim3(kT), 0, st, sixteen ? nullptr : b.as<c64>(),
                      sixteen ? b.as<bf16c>() : nullptr, h->phi128.as<c128>(), total, h->op->g.Ls, h->sd);
   HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+// The solve's surface-only subspace copy (sd > 0), built now if missing.
+int blk_surface_copies(hdcg* h, bool p16, hipStream_t st) {
+  if (h->sd == 0) return DWF_OK;
+  if ((p16 ? h->phis16 : h->phis64).bytes == 0) HDCG_TRY(surface_copy(h, p16, st));
   return DWF_OK;
 }
 

@@ -113,6 +113,39 @@ __global__ void k_probe(c128* __restrict__ c, const c128* __restrict__ z, int k0
   c[e] = (k == k0 + r) ? z[a] : cmk(0.0, 0.0);
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) from its published
+// definition: ten rounds of two 32x32 -> 64-bit products with the Weyl key
+// schedule.  Complex number i of the starting vectors takes the block with
+// counter (i lo, i hi, 0, 0) and key (seed lo, seed hi): two 53-bit uniforms
+// from the word pairs (0, 1) and (2, 3), then Box-Muller.
+__global__ void k_philox_gaussian(c128* __restrict__ out, size_t n, unsigned long long seed) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned c0 = (unsigned)i, c1 = (unsigned)((unsigned long long)i >> 32), c2 = 0u, c3 = 0u;
+  unsigned k0 = (unsigned)seed, k1 = (unsigned)(seed >> 32);
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0;
+    const unsigned long long p1 = (unsigned long long)0xCD9E8D57u * c2;
+    const unsigned n0 = (unsigned)(p1 >> 32) ^ c1 ^ k0, n1 = (unsigned)p1;
+    const unsigned n2 = (unsigned)(p0 >> 32) ^ c3 ^ k1, n3 = (unsigned)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  const double scale = 1.0 / 9007199254740992.0;  // 2^-53
+  const double u = (double)((((unsigned long long)c1 << 32) | c0) >> 11) * scale;
+  const double v = (double)((((unsigned long long)c3 << 32) | c2) >> 11) * scale;
+  const double rad = sqrt(-2.0 * log1p(-u));
+  double sv, cv;
+  sincos(2.0 * kPi * v, &sv, &cv);
+  out[i] = cmk(rad * cv, rad * sv);
+}
+
 int ensure_fine64(hdcg* h, int idx, int nr) {
   return h->fw64[idx].ensure(fine_elems(h) * nr * sizeof(c64));
 }
@@ -699,6 +732,9 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->coarse_persistent = 1;
   p->graph = 1;
   p->phase_timing = 0;
+  p->mfma_tile = -1;
+  p->seed = 1;
+  p->keep_subspace_fp64 = 1;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -760,7 +796,15 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   // ---- subspace: inverse iteration on the given starting vectors ---------
   DevBuf work;  // canonical c128 copy of the vectors
   HDCG_TRY(work.ensure(fe * nv * sizeof(c128)));
-  HDCG_HIP(hipMemcpyAsync(work.ptr, vectors, fe * nv * sizeof(c128), hipMemcpyDeviceToDevice, st));
+  if (vectors) {
+    HDCG_HIP(hipMemcpyAsync(work.ptr, vectors, fe * nv * sizeof(c128), hipMemcpyDeviceToDevice, st));
+  } else {
+    // no vectors given: seeded Gaussian starting vectors drawn on the device
+    const size_t n = fe * nv;
+    hipLaunchKernelGGL(k_philox_gaussian, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, work.as<c128>(), n,
+                       h->seed);
+    HDCG_HIP(hipGetLastError());
+  }
   if (h->prm.subspace_gen == 1) {
     // rational filter, Sec. IV.B: prod_j (H + lo + j eps)^-1 eta as
     // sum_j c_j (H + s_j)^-1 eta, c_j = prod_{i != j} 1 / (s_i - s_j), the
@@ -929,6 +973,13 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
   if (h->prm.coarse_prec == DWF_BF16 || h->prm.coarse_prec == DWF_F16)
     HDCG_TRY(crs_build_mfma(h, h->prm.coarse_prec, st));
   HDCG_HIP(hipStreamSynchronize(st));
+  // without keep_subspace_fp64 the FP64 subspace goes too, once the solve's
+  // copies (complex64, and 16-bit or surface-only as the parameters ask) exist
+  if (!h->keep_phi128) {
+    HDCG_TRY(blk_surface_copies(h, h->prm.phi_prec == DWF_BF16, st));
+    HDCG_HIP(hipStreamSynchronize(st));
+    h->phi128.release();
+  }
   // setup-only work memory goes back before the solve allocates its own
   for (int i = 0; i < 3; ++i) h->fw128[i].release();
   for (int i : {0, 1, 8, 9, 10}) h->fw64[i].release();
@@ -939,7 +990,7 @@ static int setup_impl(hdcg* h, const void* vectors, hipStream_t st) {
 
 int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const void* vectors_c128,
                const struct hdcg_params* p, void* stream) {
-  if (!out || !op || !block || !vectors_c128) return fail(DWF_ERR_ARG, "null argument to hdcg_setup");
+  if (!out || !op || !block) return fail(DWF_ERR_ARG, "null argument to hdcg_setup");
   *out = nullptr;
   if (nvec < 1 || nvec > 64) return fail(DWF_ERR_ARG, "nvec must be in 1..64");
   const int L[4] = {op->g.X, op->g.Y, op->g.Z, op->g.T};
@@ -993,9 +1044,12 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.m1_order = p->m1_order;
     h->prm.m1_shift = p->m1_shift;
     h->prm.surface_depth = p->surface_depth;
+    h->seed = p->seed;
+    h->keep_phi128 = p->keep_subspace_fp64 != 0;
     h->persistent_coarse = p->coarse_persistent != 0;
     h->use_graph = p->graph != 0;
     h->timer.on = p->phase_timing != 0;
+    h->mfma_tile = p->mfma_tile;
   }
   if (const int rc = check_solve_params(h->prm.coarse_prec, h->prm.irs_prec, h->prm.phi_prec); rc < 0) {
     delete h;
@@ -1062,6 +1116,7 @@ int hdcg_export_block_map(hdcg_t h, int* block_of_site, int* index_in_block) {
 
 int hdcg_export_subspace(hdcg_t h, void* phi_c128, void* stream) {
   if (!h || !phi_c128) return fail(DWF_ERR_ARG, "null argument");
+  if (h->phi128.bytes == 0) return fail(DWF_ERR_STATE, "the FP64 subspace was released after setup");
   return blk_phi_layout<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(phi_c128), false, h->nvec,
                                 static_cast<hipStream_t>(stream));
 }
@@ -1112,6 +1167,8 @@ int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int 
   if (!coarse_out || !fine_in) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t n = (size_t)h->Nc * h->nvec, fe = h->op->field_elems(1);
+  if (prec == DWF_C128 && h->phi128.bytes == 0)
+    return fail(DWF_ERR_STATE, "the FP64 subspace was released after setup");
   if (prec == DWF_C128)
     return blk_dot<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(fine_in), fe, nullptr, nrhs,
                            static_cast<c128*>(coarse_out), n, h->nvec, 1, nullptr, st);
@@ -1124,6 +1181,8 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
   if (!coarse_in || !fine_out) return fail(DWF_ERR_ARG, "null argument");
   auto st = static_cast<hipStream_t>(stream);
   const size_t fe = h->op->field_elems(1);
+  if (prec == DWF_C128 && h->phi128.bytes == 0)
+    return fail(DWF_ERR_STATE, "the FP64 subspace was released after setup");
   if (prec == DWF_C128)
     return blk_promote<double>(h, h->phi128.as<c128>(), static_cast<const c128*>(coarse_in), nrhs,
                                static_cast<c128*>(fine_out), nullptr, 1.0, fe, st);
@@ -1165,6 +1224,13 @@ int hdcg_coarse_solve(hdcg_t h, void* x, const void* b, int prec, int nrhs, doub
   HDCG_HIP(hipStreamSynchronize(st));
   if (iters) *iters = it;
   return it >= maxiter ? DWF_NOT_CONVERGED : DWF_OK;
+}
+
+int hdcg_mfma_tile(hdcg_t h, int prec, int nrhs_per_launch, int tile[3], float* ms, int* ntiles, void* stream) {
+  if (!h || !tile) return fail(DWF_ERR_ARG, "null argument");
+  if (prec != DWF_BF16 && prec != DWF_F16) return fail(DWF_ERR_ARG, "prec must be DWF_BF16 or DWF_F16");
+  if (nrhs_per_launch < 1 || nrhs_per_launch > 16) return fail(DWF_ERR_ARG, "nrhs_per_launch must be in 1..16");
+  return crs_mfma_tile(h, prec, nrhs_per_launch, tile, ms, ntiles, static_cast<hipStream_t>(stream));
 }
 
 int hdcg_coarse_iterations(hdcg_t h, int* iters_rhs, int nrhs) {
@@ -1216,6 +1282,7 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->persistent_coarse = p->coarse_persistent != 0;
   h->use_graph = p->graph != 0;
   h->timer.on = p->phase_timing != 0;
+  h->mfma_tile = p->mfma_tile;
   // the estimated Chebyshev bound (m1_hi <= 0) is taken now, not inside a
   // solve; if it fails the previous parameters are restored
   if (h->prm.ldop_m1 == 1 && h->prm.m1_hi <= 0.0) {

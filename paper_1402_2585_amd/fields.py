@@ -117,12 +117,19 @@ class FineOperator:
 class HDCG:
     """Owns one hdcg handle built on a FineOperator."""
 
-    def __init__(self, op: FineOperator, block, vectors, params=None, **overrides):
+    def __init__(self, op: FineOperator, block, vectors, params=None, nvec=None, **overrides):
+        """vectors: the nvec canonical starting vectors, or None with nvec
+        given: the library then draws them from params.seed (Philox4x32-10)."""
         torch = op.torch
         self.op = op
-        v = vectors if isinstance(vectors, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(vectors))
-        v = v.to(device="cuda", dtype=torch.complex128).contiguous()
-        self.nvec = v.shape[0]
+        if vectors is None:
+            if not nvec:
+                raise ValueError("nvec is needed when no vectors are given")
+            v, self.nvec = None, int(nvec)
+        else:
+            v = vectors if isinstance(vectors, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(vectors))
+            v = v.to(device="cuda", dtype=torch.complex128).contiguous()
+            self.nvec = v.shape[0]
         p = params if params is not None else L.hdcg_default_params(**overrides)
         self.params = p
         self.h = L.hdcg_setup(op.h, block, self.nvec, v, p)

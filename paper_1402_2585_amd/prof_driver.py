@@ -3,6 +3,7 @@
   python3 -m paper_1402_2585_amd.prof_driver --what H --prec c128 --reps 5
   python3 -m paper_1402_2585_amd.prof_driver --what copy --mib 1024 --reps 5
   python3 -m paper_1402_2585_amd.prof_driver --what hdcg --workload 3 --coarse c64
+  python3 -m paper_1402_2585_amd.prof_driver --what mfma --workload 4 --Ls 1 --reps 20
 
 `H` applies M_pc^+ M_pc to a seeded source on the 16^4 x Ls16 workload (or
 --dims/--Ls); `copy` runs a plain device-to-device copy kernel of known size,
@@ -26,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos", "coarse"], default="H")
+    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos", "coarse", "mfma"], default="H")
     ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
@@ -77,6 +78,9 @@ def main():
         return
     if a.what == "coarse":
         run_coarse(a, torch, synth)
+        return
+    if a.what == "mfma":
+        run_mfma(a, torch, synth)
         return
 
     dims = tuple(a.dims)
@@ -254,6 +258,50 @@ def run_coarse(a, torch, synth):
             fn()
         torch.cuda.synchronize()
         print(f"{name}: {(time.perf_counter() - t0) / a.reps * 1e3:.3f} ms", flush=True)
+    h.close()
+    op.close()
+
+
+def run_mfma(a, torch, synth):
+    """The 16-bit MFMA mat-vec of the little Dirac operator on the coarse grid
+    of a numbered workload (Nc, Nvec as there; the fine lattice keeps the
+    workload's 4D extents with Ls = --Ls, which does not change the coarse
+    shape), on a random operator imported into the handle: for bf16 and fp16
+    storage and 1, 8 and 16 right-hand sides, the autotuned tile and the time
+    of every candidate, and the matrix bytes per launch over the time."""
+    import time
+
+    from synth.configs import WORKLOADS
+
+    import paper_1402_2585_amd as hd
+
+    w = WORKLOADS[a.workload]
+    U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
+    op = hd.FineOperator(U, w.dims, a.Ls, w.M5, w.mass)
+    h = hd.HDCG(op, w.block, None, nvec=w.nvec, seed=w.subspace_seed(0))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn((h.Nc, 81, h.nvec, h.nvec), dtype=torch.complex128, device="cuda", generator=g)
+    hd.hdcg_import_coarse(h.h, A)
+    del A
+    kst = (2 * 81 * h.nvec + 15) // 16
+    mbytes = h.Nc * kst * h.nvec * 16 * 2  # fragment-ordered 16-bit storage
+    print(f"coarse grid Nc {h.Nc} nvec {h.nvec}: 16-bit matrix {mbytes / 1e9:.3f} GB", flush=True)
+    for prec, pname in ((hd.DWF_BF16, "bf16"), (hd.DWF_F16, "fp16")):
+        for nr in (1, 8, 16):
+            x = torch.randn((nr, h.Nc, h.nvec), dtype=torch.complex64, device="cuda", generator=g)
+            y = torch.empty_like(x)
+            tile, ms = hd.hdcg_mfma_tile(h.h, prec, nr)
+            hd.coarse_apply(h.h, y, x, prec, nr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.reps):
+                hd.coarse_apply(h.h, y, x, prec, nr)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / a.reps
+            vb = 2 * h.Nc * h.nvec * nr * 8
+            flops = 8 * h.Nc * 81 * h.nvec * h.nvec * nr
+            print(f"{pname} nrhs {nr}: tile {tile} {dt * 1e3:.4f} ms, {(mbytes + vb) / dt / 1e9:.1f} GB/s, "
+                  f"{flops / dt / 1e12:.2f} TFLOP/s; candidates ms {[round(m, 4) for m in ms]}", flush=True)
     h.close()
     op.close()
 

@@ -157,3 +157,55 @@ def coarse_stencil_operator(C, nvec: int, seed: int, mass: float = 0.1, fill: fl
             A[site, l] += B
             A[b, 80 - l] += B.conj().T
     return A
+
+
+# Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+# easy as 1, 2, 3", SC 2011): the counter-based generator the library uses
+# to draw subspace starting vectors on the device when the caller passes
+# none.  Written here from the published definition for the tests that
+# reproduce those vectors.
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key):
+    """ctr: uint64 array (..., 4) of 32-bit words; key: two 32-bit words.
+    Returns the four 32-bit output words (..., 4) as uint64."""
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) & _MASK32 for i in range(4)]
+    k0, k1 = np.uint64(key[0]) & _MASK32, np.uint64(key[1]) & _MASK32
+    m0, m1 = np.uint64(_PHILOX_M[0]), np.uint64(_PHILOX_M[1])
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + np.uint64(_PHILOX_W[0])) & _MASK32
+            k1 = (k1 + np.uint64(_PHILOX_W[1])) & _MASK32
+        p0 = m0 * c[0]  # 64-bit products of 32-bit words cannot overflow
+        p1 = m1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return np.stack(c, axis=-1)
+
+
+def philox_gaussian(n: int, seed: int, offset: int = 0) -> np.ndarray:
+    """n complex Gaussian numbers (real and imaginary parts N(0, 1)), number
+    i from the Philox4x32-10 block with counter (i lo, i hi, 0, 0) and key
+    (seed lo, seed hi), i = offset .. offset + n - 1: two 53-bit uniforms u, v
+    from the word pairs (0, 1) and (2, 3), then Box-Muller,
+    sqrt(-2 ln(1 - u)) * (cos 2 pi v, sin 2 pi v)."""
+    i = np.arange(offset, offset + n, dtype=np.uint64)
+    ctr = np.stack([i & _MASK32, i >> np.uint64(32), np.zeros_like(i), np.zeros_like(i)], axis=-1)
+    w = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+    scale = 2.0 ** -53
+    u = (((w[:, 1] << np.uint64(32)) | w[:, 0]) >> np.uint64(11)).astype(np.float64) * scale
+    v = (((w[:, 3] << np.uint64(32)) | w[:, 2]) >> np.uint64(11)).astype(np.float64) * scale
+    r = np.sqrt(-2.0 * np.log1p(-u))
+    return r * np.cos(2.0 * np.pi * v) + 1j * r * np.sin(2.0 * np.pi * v)
+
+
+def philox_subspace(dims, Ls: int, nvec: int, seed: int) -> np.ndarray:
+    """The nvec starting vectors the library draws for hdcg_setup without
+    given vectors: canonical Phi[k][s][cb][spin][colour], complex number i of
+    the whole array from philox_gaussian."""
+    shape = half_field_shape(dims, Ls, nvec)
+    return philox_gaussian(int(np.prod(shape)), seed).reshape(shape)

@@ -57,6 +57,19 @@ def test_param_struct_layout_matches_the_library():
                 inner_tol=1e-5, inner_maxiter=500, outer_maxiter=50, build_batch=8, coarse_prec=hd.DWF_C64,
                 verbose=0, irs_prec=hd.DWF_C64, subspace_gen=0, rat_lo=3e-4, rat_eps=1e-4, rat_tol=1e-6,
                 rat_maxiter=10000, wall_noise=0, ldop_defl=1, phi_prec=hd.DWF_C64, ldop_m1=0, m1_lo=0.5,
-                m1_hi=0.0, m1_order=16, m1_shift=0.0, surface_depth=0)
+                m1_hi=0.0, m1_order=16, m1_shift=0.0, surface_depth=0, coarse_persistent=1, graph=1,
+                phase_timing=0, mfma_tile=-1, seed=1, keep_subspace_fp64=1)
     got = {k: getattr(p, k) for k in want}
     assert got == want
+
+
+def test_stats_struct_size_matches_the_header():
+    """The ctypes mirror of struct hdcg_stats has the header's layout: fixed
+    fields, six phase times, then the two 64-entry per-RHS arrays."""
+    import ctypes as C
+
+    import paper_1402_2585_amd as hd
+    from paper_1402_2585_amd._lib import HdcgStats
+
+    assert C.sizeof(HdcgStats) == 6 * 4 + 6 * 8 + 2 * 4 + 6 * 8 + 64 * 8 + 64 * 8
+    assert HdcgStats.coarse_iterations_rhs.offset % 8 == 0 and hd.HdcgError is not None

@@ -101,3 +101,37 @@ def test_batch_of_16_with_zero_source_and_stats(setup):
     for r in (0, 15):
         res = b[r] - ref.H(xc[r])
         assert np.sqrt(np.vdot(res, res).real / np.vdot(b[r], b[r]).real) <= 1e-8 * (1 + 1e-3)
+
+
+def test_setup_without_vectors_draws_philox_starting_vectors():
+    """hdcg_setup with no vectors draws them on the device from the seed
+    (Philox4x32-10, Box-Muller); synth.philox_subspace draws the same numbers
+    on the host from the generator's published definition, so the
+    orthonormalised subspace equals the oracle's orthonormalisation of those
+    (1e-12), and a solve on it converges."""
+    from oracle import blocks as oblk
+
+    dims, Ls, nvec, seed = (12, 12, 12, 12), 2, 4, 77
+    banner("hdcg_setup with vectors drawn on the device")
+    U = synth.gauge_field(dims, 0.5, 490)
+    op = hd.FineOperator(U, dims, Ls, 1.8, 0.05)
+    h = hd.HDCG(op, BLOCK, None, nvec=nvec, seed=seed)
+    raw = synth.philox_subspace(dims, Ls, nvec, seed)
+    _, _, sob = oblk.block_map(dims, BLOCK)
+    want = oblk.orthonormalise(raw, sob)
+    got = h.subspace().cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"subspace from the device generator: rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+    h2 = hd.HDCG(op, BLOCK, None, nvec=nvec, seed=seed + 1)
+    assert np.abs(h2.subspace().cpu().numpy() - got).max() > 0.5 * np.abs(got).max()  # another seed, other vectors
+    h2.close()
+    ref = DWF(U, dims, Ls, 1.8, 0.05)
+    b = synth.gaussian_half_field(dims, Ls, 491)
+    x = op.new_field()
+    rc, st = hd.hdcg_solve(h.h, x, op.to_native(b), 1, 1e-8)
+    assert rc == 0
+    r = b - ref.H(op.to_canonical(x).cpu().numpy())
+    assert np.sqrt(np.vdot(r, r).real / np.vdot(b, b).real) <= 1e-8 * (1 + 1e-3)
+    h.close()
+    op.close()

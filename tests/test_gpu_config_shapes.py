@@ -176,6 +176,36 @@ def test_coarse_kernels_on_seeded_operator(shape):
             assert err < tol, (nr, prec)
 
 
+def test_mfma_tile_candidates_and_autotuner(shape):
+    """Every tile the autotuner chooses from (16x16x16 and gfx950 16x16x32
+    MFMA forms, 4 or 8 waves, 2 or 4 K steps in flight) gives the oracle's
+    mat-vec to the 16-bit tolerance for 1, 3 and 16 right-hand sides; the
+    autotuner's pick is one of them and its timings are reported."""
+    t = shape
+    banner(f"MFMA tile candidates {t['name']}")
+    h = t["h"]
+    A = synth.coarse_stencil_operator(t["C"], h.nvec, 445)
+    hd.hdcg_import_coarse(h.h, torch.from_numpy(A).to("cuda"))
+    for nr in (1, 3, 16):
+        c = synth.gaussian_coarse(h.Nc, h.nvec, 446 + nr, nr)
+        want = ocrs.apply(A, c, t["C"])
+        inp = torch.from_numpy(c).to("cuda", torch.complex64).contiguous()
+        for prec, tol in ((hd.DWF_BF16, 1e-2), (hd.DWF_F16, 2e-3)):
+            for cand in range(6):
+                h.set_params(mfma_tile=cand)
+                out = torch.zeros_like(inp)
+                hd.coarse_apply(h.h, out, inp, prec, nr)
+                err = rel_err(out.cpu().numpy(), want)
+                assert err < tol, (nr, prec, cand, err)
+            h.set_params(mfma_tile=-1)
+            tile, ms = hd.hdcg_mfma_tile(h.h, prec, nr)
+            assert tile[0] in (16, 32) and tile[1] in (4, 8) and tile[2] in (2, 4)
+            assert len(ms) == 6 and min(m for m in ms if m >= 0) > 0
+            if h.nvec % 8 == 0:
+                assert all(m > 0 for m in ms[3:5]) or nr == 1  # the 16x16x32 candidates were timed
+            print(f"nrhs {nr} prec {prec}: tile {tile}, ms {[round(m, 4) for m in ms]}", flush=True)
+
+
 def test_coarse_solves_on_seeded_operator(shape):
     """Coarse CG (complex64 VALU and bf16 / fp16 MFMA storage) on a seeded
     operator against a dense solve: one right-hand side, and 5 and 16 at once
