@@ -111,9 +111,23 @@ int dwf_destroy(dwf_op_t op);
  *   nt      1: non-temporal output stores;
  *   morton  1: site blocks in Morton order (power-of-two block grids);
  *   phases  2 or 4 neighbour-load phases per stage.
- * The default, set by dwf_create, is {2, 2, 1, 1, 1, 0, 1, 1, 4}.  For
- * launch-shape sweeps and their tests.  DWF_ERR_ARG on an invalid entry. */
+ * By default the block and remap entries are chosen by the library's
+ * autotuner: the first application of H for a field storage (complex128,
+ * complex64, 16-bit) and for one or several right-hand sides times each
+ * candidate block / order on that call's own operands (one warm-up, best of
+ * three with HIP events; skipped while the stream is being captured) and
+ * keeps the fastest for the operator; the other entries are
+ * {lds_kb 0, nt 1, morton 1, phases 4}.  This call fixes a shape instead
+ * (launch-shape sweeps and their tests); shape[0] = -1 returns to the
+ * autotuned shapes.  DWF_ERR_ARG on an invalid entry. */
 int dwf_set_hop_shape(dwf_op_t op, const int shape[9]);
+
+/* The hop launch shape in use for (prec DWF_C128 / DWF_C64 / DWF_BF16,
+ * nrhs = 1 or more): shape[9] as dwf_set_hop_shape takes it; ms (nullable,
+ * *ncand entries) the autotuner's milliseconds per H of each candidate, -1
+ * before it has run.  Returns 1 (and the current shape) when the autotuner
+ * has not run yet for that storage and count. */
+int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, int* ncand);
 
 /* Free the operator's work fields (the intermediate half-fields of M_pc
  * and the fields of cg_solve, cg_solve_mixed and dwf_multishift_cg, sized

@@ -94,6 +94,7 @@ def load():
         "dwf_destroy": (i, [vp]),
         "dwf_set_hop_shape": (i, [vp, C.POINTER(C.c_int)]),
         "dwf_release_workspace": (i, [vp]),
+        "dwf_get_hop_shape": (i, [vp, i, i, C.POINTER(C.c_int), C.POINTER(C.c_float), C.POINTER(C.c_int)]),
         "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
         "dwf_import": (i, [vp, vp, vp, i, i, vp]),
         "dwf_export": (i, [vp, vp, vp, i, i, vp]),
@@ -192,6 +193,15 @@ def dwf_create_mobius(gauge, dims, Ls, M5, mass, b5, c5, bc=(1, 1, 1, -1), strea
 
 def dwf_destroy(op):
     _check(load().dwf_destroy(op))
+
+
+def dwf_get_hop_shape(op, prec, nrhs=1):
+    """(shape (9 ints), ms per candidate (-1: not tuned yet), tuned flag)."""
+    sh = (C.c_int * 9)()
+    ms = (C.c_float * 16)()
+    n = C.c_int()
+    rc = _check(load().dwf_get_hop_shape(op, int(prec), int(nrhs), sh, ms, C.byref(n)), allow_soft=True)
+    return tuple(sh), list(ms[:n.value]), rc == 0
 
 
 def dwf_release_workspace(op):

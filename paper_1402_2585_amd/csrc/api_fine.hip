@@ -389,6 +389,10 @@ int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, doubl
 
 int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
   if (!op || !shape) return fail(DWF_ERR_ARG, "null argument to dwf_set_hop_shape");
+  if (shape[0] == -1) {  // back to the autotuned shapes
+    op->hop_autotune = 1;
+    return DWF_OK;
+  }
   auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
   const int* b = shape;
   const bool linear = b[0] == 0 && b[1] == 0 && b[2] == 0 && b[3] == 0;
@@ -402,7 +406,30 @@ int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
   op->tune.nt = b[6] & 1;
   op->tune.morton = b[7] != 0;
   op->tune.phases = b[8];
+  op->hop_autotune = 0;
   return DWF_OK;
+}
+
+int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, int* ncand) {
+  if (!op || !shape || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_get_hop_shape");
+  if (prec != DWF_C128 && prec != DWF_C64 && prec != DWF_BF16) return fail(DWF_ERR_ARG, "bad precision");
+  const int pi = prec == DWF_C128 ? 0 : (prec == DWF_BF16 ? 2 : 1), ri = nrhs > 1;
+  const int c = op->hop_choice[pi][ri];
+  const int n = hop_shape_candidates();
+  if (ncand) *ncand = n;
+  if (ms)
+    for (int i = 0; i < n; ++i) ms[i] = c >= 0 ? op->hop_ms[pi][ri][i] : -1.f;
+  if (op->hop_autotune && c >= 0) {
+    hop_shape_of(c, shape);
+  } else {
+    for (int i = 0; i < 4; ++i) shape[i] = op->tune.block[i];
+    shape[4] = op->tune.remap;
+  }
+  shape[5] = op->tune.lds_kb;
+  shape[6] = op->tune.nt;
+  shape[7] = op->tune.morton;
+  shape[8] = op->tune.phases;
+  return op->hop_autotune && c < 0 ? 1 : DWF_OK;
 }
 
 int dwf_destroy(dwf_op_t op) {

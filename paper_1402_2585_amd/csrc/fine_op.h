@@ -64,6 +64,12 @@ struct dwf_op {
     int morton = 1;               // Morton order of the site blocks (power-of-two block grids)
     int phases = 4;               // neighbour-load phases per stage (2 or 4)
   } tune;
+  // launch-shape autotuner: the candidate chosen per (field storage c128 /
+  // c64 / 16-bit, one / several right-hand sides), -1 before it has run;
+  // off after dwf_set_hop_shape fixes a shape
+  int hop_autotune = 1;
+  int hop_choice[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+  float hop_ms[3][2][8] = {};  // measured ms per H of each candidate
   hdk::DevBuf host_pinned_dummy;
   double* pinned = nullptr;        // host pinned scalars [kPinnedDoubles]
   int device = 0;
@@ -122,6 +128,11 @@ int launch_convert(Td* dst, const Ts* src, size_t n, hipStream_t stream);
 // keeps each site s-major), rounded to nearest even
 int launch_convert16(dwf_op* op, bf16c* dst, const c64* src, int nrhs, hipStream_t stream);
 int launch_convert16(dwf_op* op, c64* dst, const bf16c* src, int nrhs, hipStream_t stream);
+
+// the hop launch-shape candidates of the autotuner: their number, and
+// candidate c as {bx, by, bz, bt, remap}
+int hop_shape_candidates();
+void hop_shape_of(int c, int shape[5]);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
 void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)

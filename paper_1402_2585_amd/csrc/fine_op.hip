@@ -944,14 +944,94 @@ int launch_mpc(dwf_op* op, T* out, const T* in, bool dagger, int nrhs, hipStream
   return DWF_OK;
 }
 
+// ------------------------------------------------ launch-shape autotuner --
+// Candidate launch shapes of the hop stages: the workgroup's site block in
+// (x/2, y, z, t) and whether workgroups are reordered XCD-contiguously.  Which
+// is fastest depends on the lattice (how the block grid divides over the 8
+// XCDs and their L2 caches) and on the bytes per site; on 16^4 x 16 the
+// 2x2x1x1 XCD-contiguous Morton order wins, on 24^3 x 48 x 16 (a block grid
+// that is not a power of two) other shapes do.
+struct HopShape {
+  int block[4];
+  int remap;
+};
+constexpr HopShape kHopShapes[] = {{{2, 2, 1, 1}, 1}, {{2, 2, 1, 1}, 0}, {{2, 2, 2, 2}, 1},
+                                   {{2, 2, 2, 2}, 0}, {{4, 2, 1, 1}, 1}, {{1, 2, 2, 1}, 1}};
+constexpr int kNumHopShapes = sizeof(kHopShapes) / sizeof(kHopShapes[0]);
+
+int hop_shape_candidates() { return kNumHopShapes; }
+void hop_shape_of(int c, int shape[5]) {
+  for (int i = 0; i < 4; ++i) shape[i] = kHopShapes[c].block[i];
+  shape[4] = kHopShapes[c].remap;
+}
+
+static void apply_shape(dwf_op* op, int c) {
+  for (int i = 0; i < 4; ++i) op->tune.block[i] = kHopShapes[c].block[i];
+  op->tune.remap = kHopShapes[c].remap;
+}
+
 template <typename R, typename T>
-int launch_mpcdagmpc(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t stream, double* pap_result) {
+static int apply_mpcdagmpc(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t stream, double* pap_result) {
   const int prec = std::is_same<T, bf16c>::value ? DWF_BF16 : prec_of<R>();
   HDCG_TRY(ensure_tmp(op, prec, nrhs));
   T* chi = op->tmp[tmp_index(prec)][1].as<T>();
   HDCG_TRY((launch_mpc<R, T>(op, chi, in, false, nrhs, stream, pap_result)));
   HDCG_TRY((launch_mpc<R, T>(op, out, chi, true, nrhs, stream, nullptr)));
   return DWF_OK;
+}
+
+// The shape for (storage, right-hand sides): tuned on this call's own
+// operands the first time (one warm-up and the best of three applications of
+// H per candidate, timed with HIP events on the stream), unless the stream is
+// being captured into a graph (then the default until a later call tunes).
+template <typename R, typename T>
+static int select_shape(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t st) {
+  if (!op->hop_autotune) return DWF_OK;
+  const int pi = tmp_index(std::is_same<T, bf16c>::value ? DWF_BF16 : prec_of<R>()), ri = nrhs > 1;
+  int& choice = op->hop_choice[pi][ri];
+  if (choice < 0) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      apply_shape(op, 0);
+      return DWF_OK;
+    }
+    hipEvent_t e0, e1;
+    HDCG_HIP(hipEventCreate(&e0));
+    HDCG_HIP(hipEventCreate(&e1));
+    int rc = DWF_OK, best = 0;
+    float bms = 0.f;
+    for (int c = 0; c < kNumHopShapes && rc == DWF_OK; ++c) {
+      apply_shape(op, c);
+      rc = apply_mpcdagmpc<R, T>(op, out, in, nrhs, st, nullptr);
+      float m = 1e30f;
+      for (int rep = 0; rep < 3 && rc == DWF_OK; ++rep) {
+        float x = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(DWF_ERR_HIP, "hop autotuner event failed");
+        if (rc == DWF_OK) rc = apply_mpcdagmpc<R, T>(op, out, in, nrhs, st, nullptr);
+        if (rc == DWF_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&x, e0, e1) != hipSuccess))
+          rc = fail(DWF_ERR_HIP, "hop autotuner event failed");
+        m = std::min(m, x);
+      }
+      op->hop_ms[pi][ri][c] = m;
+      if (rc == DWF_OK && (c == 0 || m < bms)) {
+        bms = m;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HDCG_TRY(rc);
+    choice = best;
+  }
+  apply_shape(op, choice);
+  return DWF_OK;
+}
+
+template <typename R, typename T>
+int launch_mpcdagmpc(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t stream, double* pap_result) {
+  HDCG_TRY((select_shape<R, T>(op, out, in, nrhs, stream)));
+  return apply_mpcdagmpc<R, T>(op, out, in, nrhs, stream, pap_result);
 }
 
 template <typename R, typename T>

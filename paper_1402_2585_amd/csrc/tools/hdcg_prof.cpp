@@ -3,7 +3,7 @@
 // not depend on the link values), or runs a plain copy kernel of known size
 // to calibrate the FETCH_SIZE / WRITE_SIZE counters.
 //
-//   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64|bf16> <reps> [nrhs]
+//   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64|bf16> <reps> [nrhs] [shape]
 //   hdcg_prof copy|read <MiB> <reps> [grid]
 #include <hip/hip_runtime.h>
 
@@ -139,6 +139,10 @@ int main(int argc, char** argv) {
   const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : (!std::strcmp(argv[7], "bf16") ? DWF_BF16 : DWF_C128);
   const int reps = std::atoi(argv[8]);
   const int nrhs = argc > 9 ? std::atoi(argv[9]) : 1;
+  // optional fixed launch shape "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]" (else autotuned)
+  int shape[9] = {2, 2, 1, 1, 1, 0, 1, 1, 4};
+  const bool fixed = argc > 10 && std::sscanf(argv[10], "%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1], &shape[2],
+                                               &shape[3], &shape[4], &shape[5], &shape[6], &shape[7], &shape[8]) >= 4;
   const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
   std::vector<double> U(V * 4 * 9 * 2, 0.0);
   for (size_t l = 0; l < V * 4; ++l)
@@ -148,6 +152,7 @@ int main(int argc, char** argv) {
   CHECK(hipMemcpy(dU, U.data(), U.size() * sizeof(double), hipMemcpyHostToDevice));
   dwf_op_t op;
   ACHECK(dwf_create(&op, dims, Ls, 1.8, 0.01, dU, nullptr, nullptr));
+  if (fixed) ACHECK(dwf_set_hop_shape(op, shape));
   size_t bytes = 0;
   ACHECK(dwf_field_bytes(op, prec, nrhs, &bytes));
   void *x, *y;

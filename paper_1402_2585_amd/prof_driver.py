@@ -45,6 +45,10 @@ def main():
     ap.add_argument("--cg", action="store_true", help="also time the plain FP64 CG on the same source(s)")
     ap.add_argument("--surface_depth", type=int, default=0,
                     help="keep only the subspace's s < d and s >= Ls - d slices (0: all)")
+    ap.add_argument("--seeded", action="store_true",
+                    help="the subspace starting vectors drawn by the library (Philox, seed 1000 cfg + 500)")
+    ap.add_argument("--phase_timing", action="store_true", help="report the solve's phase times (Fig. pie)")
+    ap.add_argument("--no_graph", action="store_true", help="launch the preconditioner kernel by kernel")
     ap.add_argument("--n_ii", type=int, default=3)
     ap.add_argument("--tol_ii", type=float, default=1e-3)
     ap.add_argument("--maxiter_ii", type=int, default=500)
@@ -116,8 +120,8 @@ def run_hdcg(a, torch, synth):
     w = WORKLOADS[a.workload]
     # every torch operation on the inputs happens before the library's first launch
     U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
-    V = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k))
-                                   for k in range(w.nvec)])).to("cuda")
+    V = None if a.seeded else torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k))
+                                                         for k in range(w.nvec)])).to("cuda")
     bsrc = torch.from_numpy(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(0))).to("cuda")
     torch.cuda.synchronize()
     print("inputs on device", flush=True)
@@ -129,8 +133,11 @@ def run_hdcg(a, torch, synth):
     b = op.to_native(bsrc)
     iprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.irs]
     pprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.phi]
-    h = hd.HDCG(op, w.block, V, n_ii=a.n_ii, tol_ii=a.tol_ii, maxiter_ii=a.maxiter_ii, coarse_prec=cprec,
-                irs_prec=iprec, phi_prec=pprec, surface_depth=a.surface_depth, verbose=1)
+    h = hd.HDCG(op, w.block, V, nvec=w.nvec, seed=w.subspace_seed(0), n_ii=a.n_ii, tol_ii=a.tol_ii,
+                maxiter_ii=a.maxiter_ii, coarse_prec=cprec, irs_prec=iprec, phi_prec=pprec,
+                surface_depth=a.surface_depth, verbose=1, keep_subspace_fp64=0 if a.seeded else 1,
+                phase_timing=1 if a.phase_timing else 0, graph=0 if a.no_graph else 1)
+    del V
     print("setup done", flush=True)
     if a.variants:
         run_variants(a, torch, synth, hd, w, op, h, b)
@@ -147,9 +154,11 @@ def run_hdcg(a, torch, synth):
             lo, hi = hd.hdcg_m1_interval(h.h)
             print(f"ADEF1, Chebyshev order {a.m1_order} on [{lo}, {hi:.3f}]", flush=True)
     if a.nrhs_solve > 1:
-        bs = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(r))
-                                        for r in range(a.nrhs_solve)])).to("cuda")
-        b = op.to_native(bs)
+        b = op.new_field(nrhs=a.nrhs_solve)
+        n1 = b.numel() // a.nrhs_solve
+        for r in range(a.nrhs_solve):
+            src = torch.from_numpy(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(r))).to("cuda")
+            b[r * n1:(r + 1) * n1] = op.to_native(src)
     x = op.new_field(zero=True, nrhs=a.nrhs_solve)
     rc, st = hd.hdcg_solve(h.h, x, b, a.nrhs_solve, 1e-8)
     print(f"hdcg workload {a.workload} coarse {a.coarse} M_IRS fields {a.irs} subspace {a.phi} ldop {a.ldop} "
