@@ -109,15 +109,24 @@ int dwf_destroy(dwf_op_t op);
  *   remap   1: workgroups reordered so each XCD takes one contiguous range;
  *   lds_kb  minimum LDS per workgroup in KiB (0..150; caps occupancy);
  *   nt      1: non-temporal output stores;
- *   morton  1: site blocks in Morton order (power-of-two block grids);
- *   phases  2 or 4 neighbour-load phases per stage.
- * By default the block and remap entries are chosen by the library's
+ *   morton  block order: 0 lexicographic; 1 Morton (power-of-two block
+ *           grids, else lexicographic); 2 the block grid bisected into eight
+ *           compact regions, one per XCD, Morton order inside each (any
+ *           block grid; remap ignored); 3 the same regions taken t-plane by
+ *           t-plane; 4 regions cut in x, y, z only (each spans all of t),
+ *           all XCDs marching through t together, Morton order within each
+ *           plane.  Orders 2-4 read a table that the library builds
+ *           on the first launch outside graph capture (host memory and
+ *           4 bytes of device memory per workgroup, kept until dwf_destroy);
+ *   phases  2 or 4 neighbour-load phases per stage (0: 4 for complex128,
+ *           2 for complex64 and 16-bit fields).
+ * By default the block, remap and order entries are chosen by the library's
  * autotuner: the first application of H for a field storage (complex128,
  * complex64, 16-bit) and for one or several right-hand sides times each
  * candidate block / order on that call's own operands (one warm-up, best of
  * three with HIP events; skipped while the stream is being captured) and
  * keeps the fastest for the operator; the other entries are
- * {lds_kb 0, nt 1, morton 1, phases 4}.  This call fixes a shape instead
+ * {lds_kb 0, nt 0, phases 0}.  This call fixes a shape instead
  * (launch-shape sweeps and their tests); shape[0] = -1 returns to the
  * autotuned shapes.  DWF_ERR_ARG on an invalid entry. */
 int dwf_set_hop_shape(dwf_op_t op, const int shape[9]);

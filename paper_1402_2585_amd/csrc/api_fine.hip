@@ -398,13 +398,13 @@ int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
   const bool linear = b[0] == 0 && b[1] == 0 && b[2] == 0 && b[3] == 0;
   if (!linear && !(pow2(b[0]) && pow2(b[1]) && pow2(b[2]) && pow2(b[3])))
     return fail(DWF_ERR_ARG, "dwf_set_hop_shape: block extents must be powers of two (or all 0)");
-  if (b[5] < 0 || b[5] > 150 || (b[8] != 2 && b[8] != 4))
-    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: lds_kb must be in 0..150 and phases 2 or 4");
+  if (b[5] < 0 || b[5] > 150 || (b[8] != 0 && b[8] != 2 && b[8] != 4) || b[7] < 0 || b[7] > 4)
+    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: lds_kb must be in 0..150, order 0..4 and phases 0, 2 or 4");
   for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
   op->tune.remap = b[4] != 0;
   op->tune.lds_kb = b[5];
   op->tune.nt = b[6] & 1;
-  op->tune.morton = b[7] != 0;
+  op->tune.morton = b[7];
   op->tune.phases = b[8];
   op->hop_autotune = 0;
   return DWF_OK;
@@ -419,15 +419,13 @@ int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, 
   if (ncand) *ncand = n;
   if (ms)
     for (int i = 0; i < n; ++i) ms[i] = c >= 0 ? op->hop_ms[pi][ri][i] : -1.f;
-  if (op->hop_autotune && c >= 0) {
-    hop_shape_of(c, shape);
-  } else {
-    for (int i = 0; i < 4; ++i) shape[i] = op->tune.block[i];
-    shape[4] = op->tune.remap;
-  }
+  int cand[6];
+  if (op->hop_autotune && c >= 0) hop_shape_of(c, cand);
+  for (int i = 0; i < 4; ++i) shape[i] = op->hop_autotune && c >= 0 ? cand[i] : op->tune.block[i];
+  shape[4] = op->hop_autotune && c >= 0 ? cand[4] : op->tune.remap;
   shape[5] = op->tune.lds_kb;
   shape[6] = op->tune.nt;
-  shape[7] = op->tune.morton;
+  shape[7] = op->hop_autotune && c >= 0 ? cand[5] : op->tune.morton;
   shape[8] = op->tune.phases;
   return op->hop_autotune && c < 0 ? 1 : DWF_OK;
 }
@@ -444,6 +442,7 @@ int dwf_destroy(dwf_op_t op) {
   for (auto& b : op->cgw) b.release();
   op->red.partials.release();
   op->hop_part.release();
+  for (auto& kv : op->hop_tables) kv.second.dev.release();
   for (auto& m : op->mgw) m.release();
   for (auto& m : op->msw) m.release();
   op->red.counters.release();

@@ -126,9 +126,7 @@ typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)f);  // round to nearest even (v_cvt_pk_bf16_f32)
 }
 __device__ __forceinline__ unsigned short f2h(float f) {
   _Float16 h = (_Float16)f;

@@ -115,13 +115,26 @@ __host__ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   __builtin_memcpy(&f, &u, 4);
   return f;
 }
-// round to nearest even; a NaN may come out as an infinity (still
-// non-finite, which is all the solvers test for)
+// round to nearest even: on the device gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32); on the host the same rounding in integer arithmetic
+// (a NaN may come out as an infinity there, still non-finite)
 __host__ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
+#else
   unsigned u;
   __builtin_memcpy(&u, &f, 4);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
+#endif
+}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+// (re, im) rounded to nearest even and packed re | im << 16: one
+// v_cvt_pk_bf16_f32
+__device__ __forceinline__ unsigned f32x2_to_bf16x2(float re, float im) {
+  const f32x2_t v = {re, im};
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_t));
 }
 
 // Storage traits: St<T>::R is the arithmetic type of a field stored as T;
@@ -148,10 +161,7 @@ struct St<bf16c> {
     return cmk(bf16_to_f32(v.re), bf16_to_f32(v.im));
   }
   __device__ __forceinline__ static void st(bf16c* p, cplx<float> v) {
-    bf16c o;
-    o.re = f32_to_bf16(v.re);
-    o.im = f32_to_bf16(v.im);
-    *p = o;
+    *reinterpret_cast<unsigned*>(p) = f32x2_to_bf16x2(v.re, v.im);
   }
 };
 

@@ -13,6 +13,10 @@
 // stage reads the eight links of its output site contiguously.
 #pragma once
 
+#include <array>
+#include <map>
+#include <vector>
+
 #include "common.h"
 
 namespace hdk {
@@ -56,20 +60,31 @@ struct dwf_op {
   hdk::Reducer red;
   hdk::DevBuf hop_part;           // fused-norm partials of the hop stage: [rhs][workgroups]
   struct {
-    // hop launch shape (measured best on MI355X at 16^4 and 24^3x48, Ls = 16)
+    // hop launch shape (measured best on MI355X at 16^4 and 24^3x48, Ls = 16;
+    // block, remap and order are the autotuner's)
     int block[4] = {2, 2, 1, 1};  // workgroup site block in (x/2, y, z, t), powers of two; 0 = linear
     int remap = 1;                // XCD-contiguous workgroup order
     int lds_kb = 0;               // minimum LDS per workgroup (caps occupancy)
-    int nt = 1;                   // non-temporal output stores
-    int morton = 1;               // Morton order of the site blocks (power-of-two block grids)
-    int phases = 4;               // neighbour-load phases per stage (2 or 4)
+    int nt = 0;                   // non-temporal output stores
+    int morton = 1;               // block order: 0 lexicographic, 1 Morton (power-of-two block
+                                  // grids), 2-4 per-XCD regions from a table
+    int phases = 0;               // neighbour-load phases per stage (2 or 4; 0: 4 for complex128,
+                                  // 2 for the FP32 kernels, whose spinors take half the registers)
   } tune;
   // launch-shape autotuner: the candidate chosen per (field storage c128 /
   // c64 / 16-bit, one / several right-hand sides), -1 before it has run;
   // off after dwf_set_hop_shape fixes a shape
   int hop_autotune = 1;
   int hop_choice[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
-  float hop_ms[3][2][8] = {};  // measured ms per H of each candidate
+  float hop_ms[3][2][16] = {};  // measured ms per H of each candidate
+  // workgroup -> site-block tables of the region orders, one per
+  // (bx, by, bz, bt, order); built on first use outside graph capture, kept
+  // until the operator is destroyed (a launch in flight may still read one)
+  struct OrderTable {
+    std::vector<int> host;
+    hdk::DevBuf dev;
+  };
+  std::map<std::array<int, 5>, OrderTable> hop_tables;
   hdk::DevBuf host_pinned_dummy;
   double* pinned = nullptr;        // host pinned scalars [kPinnedDoubles]
   int device = 0;
@@ -130,9 +145,9 @@ int launch_convert16(dwf_op* op, bf16c* dst, const c64* src, int nrhs, hipStream
 int launch_convert16(dwf_op* op, c64* dst, const bf16c* src, int nrhs, hipStream_t stream);
 
 // the hop launch-shape candidates of the autotuner: their number, and
-// candidate c as {bx, by, bz, bt, remap}
+// candidate c as {bx, by, bz, bt, remap, order}
 int hop_shape_candidates();
-void hop_shape_of(int c, int shape[5]);
+void hop_shape_of(int c, int shape[6]);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
 void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)

@@ -174,7 +174,7 @@ __device__ __forceinline__ cplx<float> bf16_word(unsigned w) {
   return cmk(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
 }
 __device__ __forceinline__ unsigned bf16_pack(cplx<float> v) {
-  return (unsigned)f32_to_bf16(v.re) | ((unsigned)f32_to_bf16(v.im) << 16);
+  return f32x2_to_bf16x2(v.re, v.im);
 }
 // the twelve values of one (site, s) row; p 16-byte aligned
 __device__ __forceinline__ void ld_row12(const bf16c* p, cplx<float> (&v)[12]) {
@@ -307,6 +307,7 @@ struct HopArgs {
   int nt;             // non-temporal output stores
   int morton;         // Morton (bit-interleaved) order of the block grid (power-of-two grids)
   int nbt;            // block-grid extent in t
+  const int* order;   // nullable: block of workgroup blockIdx.x, packed gx | gy << 8 | gz << 16 | gt << 24
   size_t field;       // complex elements per rhs
   // fifth dimension: M_5 = alpha + beta K, recurrence of M_5^-1 y_s = ia x_s + kap y_{s-1},
   // Mobius C_5 = b5 + c5 K (K: P+ from s-1, P- from s+1, -mass at the wrap)
@@ -320,7 +321,13 @@ struct HopArgs {
 // Block coordinates of workgroup wg in the block grid (lexicographic or
 // Morton order); uniform across the workgroup.
 __device__ __forceinline__ void hop_block(const HopArgs& A, int wg, int& gx, int& gy, int& gz, int& gt) {
-  if (A.morton) {
+  if (A.order) {
+    const int q = A.order[wg];
+    gx = q & 255;
+    gy = (q >> 8) & 255;
+    gz = (q >> 16) & 255;
+    gt = (q >> 24) & 255;
+  } else if (A.morton) {
     // de-interleave the bits of wg over the four block-grid dimensions
     gx = gy = gz = gt = 0;
     int bit = 0, px = 0, py = 0, pz = 0, pt = 0;
@@ -631,7 +638,8 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Geom& g = A.g;
   const int Ls = LS > 0 ? LS : g.Ls;  // compile-time when LS > 0: immediate load offsets
-  const int wg = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  // a table order already places each workgroup on its XCD's region
+  const int wg = (A.remap && !A.order) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
   const int vloc = tid / Ls, s = tid - vloc * Ls;
@@ -643,9 +651,21 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
   out += rhs * A.field;
 
   cplx<R>* links = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][kLinkLd]
+  // The site's 72 link entries, entry e by thread s = e mod Ls.  With Ls
+  // fixed at compile time every load is issued before the first neighbour
+  // loads and written to LDS after them, so the wave waits for memory once
+  // instead of once per entry.
+  constexpr int NL = LS > 0 ? (72 + LS - 1) / LS : 1;
+  cplx<R> lk[NL];
   if (active) {
     const cplx<R>* G = gauge + (size_t)v * 72;
-    for (int e = s; e < 72; e += Ls) links[vloc * kLinkLd + e] = G[e];
+    if constexpr (LS > 0) {
+      // (the last entries of the short threads re-read entry 71: no branch)
+#pragma unroll
+      for (int k = 0; k < NL; ++k) lk[k] = G[min(s + k * LS, 71)];
+    } else {
+      for (int e = s; e < 72; e += Ls) links[vloc * kLinkLd + e] = G[e];
+    }
   }
 
   constexpr int ND = 8 / NPH;
@@ -661,6 +681,11 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
       load_dirs_c5<T, 0, ND>(psi, in, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
     else
       load_dirs<T, 0, ND>(psi, in, nb, col, s, Ls);
+    if constexpr (LS > 0) {
+#pragma unroll
+      for (int k = 0; k < NL; ++k)
+        if (s + k * LS < 72) links[vloc * kLinkLd + s + k * LS] = lk[k];
+    }
   }
   __syncthreads();  // links in LDS
 
@@ -836,6 +861,107 @@ static void launch_hop(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, 
   }
 }
 
+// ------------------------------------------------- region block orders --
+// Orders 2-4 place the site blocks with a table instead of an index
+// formula, so that they work on block grids of any extents (Morton's bit
+// interleaving needs powers of two).  The block grid is bisected three times
+// into eight compact regions, one per XCD (each cut halves the region's
+// longest extent in lattice sites), so each XCD's L2 serves one region and
+// its halo; within a region the blocks run in Morton order of the region's
+// power-of-two bounding grid with the blocks outside skipped (order 2), or
+// t-plane by t-plane with Morton order inside each plane (order 3).  Order 4
+// cuts only x, y and z, so every region spans all of t and the eight XCDs
+// march through t together, plane by plane: a plane's t +- 1 neighbours are
+// the planes the same XCD has just read or reads next.
+// Workgroup b runs on XCD b mod 8 as the (b / 8)-th of that XCD's, so it
+// takes the entry of the concatenated region list that the XCD-contiguous
+// remap gives it.
+static void morton_box(const int lo[4], const int len[4], int dims, std::vector<int>& out) {
+  int bits[4] = {0, 0, 0, 0}, total = 0;
+  for (int d = 0; d < dims; ++d) {
+    while ((1 << bits[d]) < len[d]) ++bits[d];
+    total += bits[d];
+  }
+  for (long long code = 0; code < (1LL << total); ++code) {
+    int c[4] = {0, 0, 0, 0}, used[4] = {0, 0, 0, 0}, bit = 0;
+    while (bit < total)
+      for (int d = 0; d < dims && bit < total; ++d)
+        if (used[d] < bits[d]) c[d] |= (int)((code >> bit++) & 1) << used[d]++;
+    bool inside = true;
+    for (int d = 0; d < dims; ++d) inside = inside && c[d] < len[d];
+    if (!inside) continue;
+    int q = 0;
+    for (int d = 0; d < dims; ++d) q |= (lo[d] + c[d]) << (8 * d);
+    out.push_back(q);
+  }
+}
+
+static void region_blocks(int lo[4], int len[4], const int site_ext[4], int parts, int kind, std::vector<int>& out) {
+  if (parts > 1) {
+    int d = -1;
+    long best = 0;
+    for (int k = kind == 4 ? 2 : 3; k >= 0; --k)
+      if (len[k] >= 2 && (long)len[k] * site_ext[k] > best) {
+        best = (long)len[k] * site_ext[k];
+        d = k;
+      }
+    if (d >= 0) {
+      int lo2[4], len2[4];
+      for (int k = 0; k < 4; ++k) lo2[k] = lo[k], len2[k] = len[k];
+      len2[d] = len[d] / 2;
+      region_blocks(lo2, len2, site_ext, parts / 2, kind, out);
+      lo2[d] = lo[d] + len[d] / 2;
+      len2[d] = len[d] - len[d] / 2;
+      region_blocks(lo2, len2, site_ext, parts / 2, kind, out);
+      return;
+    }
+  }
+  if (kind == 2) {
+    morton_box(lo, len, 4, out);
+  } else {
+    for (int t = 0; t < len[3]; ++t) {
+      const size_t at = out.size();
+      morton_box(lo, len, 3, out);
+      for (size_t i = at; i < out.size(); ++i) out[i] |= (lo[3] + t) << 24;
+    }
+  }
+}
+
+// The table for the current block shape and order (2, 3 or 4) on `stream`,
+// built on first use; nullptr when the stream is being captured and the
+// table does not exist yet (the launch then uses the index-formula order).
+static const int* hop_order_table(dwf_op* op, const HopArgs& A, int kind, hipStream_t stream, int* rc) {
+  *rc = DWF_OK;
+  const std::array<int, 5> key = {A.bx, A.by, A.bz, A.bt, kind};
+  auto it = op->hop_tables.find(key);
+  if (it != op->hop_tables.end()) return it->second.dev.as<int>();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  dwf_op::OrderTable& t = op->hop_tables[key];
+  const int nb[4] = {A.nbx, A.nby, A.nbz, A.nbt};
+  const int site_ext[4] = {2 * A.bx, A.by, A.bz, A.bt};
+  int lo[4] = {0, 0, 0, 0}, len[4] = {nb[0], nb[1], nb[2], nb[3]};
+  std::vector<int> list;
+  list.reserve((size_t)nb[0] * nb[1] * nb[2] * nb[3]);
+  region_blocks(lo, len, site_ext, 8, kind, list);
+  const int n = (int)list.size();
+  t.host.resize(n);
+  const int q = n >> 3, r = n & 7;
+  for (int b = 0; b < n; ++b) {  // the device's xcd_remap, on the host
+    const int x = b & 7, k = b >> 3;
+    t.host[b] = list[(x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k];
+  }
+  *rc = t.dev.ensure(sizeof(int) * (size_t)n);
+  if (*rc == DWF_OK && hipMemcpyAsync(t.dev.ptr, t.host.data(), sizeof(int) * (size_t)n, hipMemcpyHostToDevice,
+                                      stream) != hipSuccess)
+    *rc = fail(DWF_ERR_HIP, "hop order table upload failed");
+  if (*rc != DWF_OK) {
+    op->hop_tables.erase(key);
+    return nullptr;
+  }
+  return t.dev.as<int>();
+}
+
 template <typename R, typename T = cplx<R>>
 static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
                       bool dagger, int epi, int out_parity, int nrhs, hipStream_t stream,
@@ -853,6 +979,7 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
   A.nt = op->tune.nt;
   A.morton = 0;
   A.nbt = 1;
+  A.order = nullptr;
   {
     const int* b = op->tune.block;
     auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
@@ -871,7 +998,13 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
       A.lbx = __builtin_ctz(b[0]);
       A.lby = __builtin_ctz(b[1]);
       A.lbz = __builtin_ctz(b[2]);
-      A.morton = op->tune.morton && pow2(A.nbx) && pow2(A.nby) && pow2(A.nbz) && pow2(A.nbt);
+      const bool p2 = pow2(A.nbx) && pow2(A.nby) && pow2(A.nbz) && pow2(A.nbt);
+      A.morton = op->tune.morton != 0 && p2;
+      if (op->tune.morton >= 2 && A.nbx <= 256 && A.nby <= 256 && A.nbz <= 256 && A.nbt <= 128) {
+        int rc = DWF_OK;
+        A.order = hop_order_table(op, A, op->tune.morton, stream, &rc);
+        HDCG_TRY(rc);
+      }
     }
   }
   A.field = (size_t)g.Vh * 12 * g.Ls;
@@ -907,7 +1040,8 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
   if ((size_t)op->tune.lds_kb * 1024 > lds) lds = (size_t)op->tune.lds_kb * 1024;
   // directions whose neighbour loads are in flight together: 8 / phases
   // (the Mobius kernels are built for four phases only)
-  const bool two = op->tune.phases == 4 || mob;
+  const int phases = op->tune.phases > 0 ? op->tune.phases : (sizeof(R) == 8 ? 4 : 2);
+  const bool two = phases == 4 || mob;
   if (mob) {
     if (g.Ls == 16)
       launch_hop<R, 4, 16, true, T>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
@@ -954,20 +1088,27 @@ int launch_mpc(dwf_op* op, T* out, const T* in, bool dagger, int nrhs, hipStream
 struct HopShape {
   int block[4];
   int remap;
+  int order;  // 1 Morton (index formula), 2-4 region tables
 };
-constexpr HopShape kHopShapes[] = {{{2, 2, 1, 1}, 1}, {{2, 2, 1, 1}, 0}, {{2, 2, 2, 2}, 1},
-                                   {{2, 2, 2, 2}, 0}, {{4, 2, 1, 1}, 1}, {{1, 2, 2, 1}, 1}};
+constexpr HopShape kHopShapes[] = {{{2, 2, 1, 1}, 1, 1}, {{2, 2, 1, 1}, 0, 1}, {{2, 2, 2, 2}, 1, 1},
+                                   {{2, 2, 2, 2}, 0, 1}, {{4, 2, 1, 1}, 1, 1}, {{1, 2, 2, 1}, 1, 1},
+                                   {{2, 2, 1, 1}, 1, 2}, {{1, 2, 2, 1}, 1, 2}, {{2, 2, 1, 1}, 1, 3},
+                                   {{2, 2, 2, 2}, 1, 2}, {{2, 2, 1, 1}, 1, 4}, {{1, 2, 2, 1}, 1, 4},
+                                   {{2, 2, 2, 2}, 1, 4}};
 constexpr int kNumHopShapes = sizeof(kHopShapes) / sizeof(kHopShapes[0]);
+static_assert(kNumHopShapes <= 16, "hop_ms holds 16 candidates");
 
 int hop_shape_candidates() { return kNumHopShapes; }
-void hop_shape_of(int c, int shape[5]) {
+void hop_shape_of(int c, int shape[6]) {
   for (int i = 0; i < 4; ++i) shape[i] = kHopShapes[c].block[i];
   shape[4] = kHopShapes[c].remap;
+  shape[5] = kHopShapes[c].order;
 }
 
 static void apply_shape(dwf_op* op, int c) {
   for (int i = 0; i < 4; ++i) op->tune.block[i] = kHopShapes[c].block[i];
   op->tune.remap = kHopShapes[c].remap;
+  op->tune.morton = kHopShapes[c].order;
 }
 
 template <typename R, typename T>

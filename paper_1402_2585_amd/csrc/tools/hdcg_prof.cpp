@@ -4,7 +4,7 @@
 // to calibrate the FETCH_SIZE / WRITE_SIZE counters.
 //
 //   hdcg_prof H <X> <Y> <Z> <T> <Ls> <c128|c64|bf16> <reps> [nrhs] [shape]
-//   hdcg_prof copy|read <MiB> <reps> [grid]
+//   hdcg_prof copy|copy4|read <MiB> <reps> [grid]
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -36,6 +36,25 @@ __global__ void copy_kernel(const double4* __restrict__ x, double4* __restrict__
     y[i] = x[i];
 }
 
+// copy with four 32-byte loads in flight per thread before the stores, and
+// non-temporal stores (n a multiple of 4 * grid * block is not required)
+__global__ void copy4_kernel(const double4* __restrict__ x, double4* __restrict__ y, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    double4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = x[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      typedef double d4 __attribute__((ext_vector_type(4)));
+      const d4 w = {v[k].x, v[k].y, v[k].z, v[k].w};
+      __builtin_nontemporal_store(w, reinterpret_cast<d4*>(y + i + k * stride));
+    }
+  }
+  for (; i < n; i += stride) y[i] = x[i];
+}
+
 // streaming read: one partial sum per thread (n / (grid * block) loads each)
 __global__ void read_kernel(const double4* __restrict__ x, double* __restrict__ y, size_t n) {
   double s = 0.0;
@@ -48,9 +67,10 @@ __global__ void read_kernel(const double4* __restrict__ x, double* __restrict__ 
 
 int main(int argc, char** argv) {
   if (argc < 2) return 2;
-  if (!std::strcmp(argv[1], "copy") || !std::strcmp(argv[1], "read")) {
-    // hdcg_prof copy|read <MiB> <reps> [grid]: plain copy (or streaming read) of MiB
-    const bool rd = !std::strcmp(argv[1], "read");
+  if (!std::strcmp(argv[1], "copy") || !std::strcmp(argv[1], "read") || !std::strcmp(argv[1], "copy4")) {
+    // hdcg_prof copy|copy4|read <MiB> <reps> [grid]: plain copy (copy4: four
+    // loads in flight per thread, non-temporal stores) or streaming read of MiB
+    const bool rd = !std::strcmp(argv[1], "read"), c4 = !std::strcmp(argv[1], "copy4");
     const size_t mib = argc > 2 ? std::atol(argv[2]) : 1024;
     const int reps = argc > 3 ? std::atoi(argv[3]) : 3;
     const int grid = argc > 4 ? std::atoi(argv[4]) : 4096;
@@ -68,6 +88,8 @@ int main(int argc, char** argv) {
     for (int r = 0; r < reps; ++r) {
       if (rd)
         hipLaunchKernelGGL(read_kernel, dim3(grid), dim3(256), 0, 0, x, part, n);
+      else if (c4)
+        hipLaunchKernelGGL(copy4_kernel, dim3(grid), dim3(256), 0, 0, x, y, n);
       else
         hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, 0, x, y, n);
     }
@@ -78,16 +100,16 @@ int main(int argc, char** argv) {
     CHECK(hipEventElapsedTime(&ms, e0, e1));
     const double bytes = (double)n * 32 * (rd ? 1 : 2);
     std::printf("%s %zu MiB x %d grid %d (bytes per launch read %zu write %zu)  %.4f ms/launch  %.1f GB/s\n",
-                rd ? "read" : "copy", mib, reps, grid, n * 32, rd ? (size_t)0 : n * 32, ms / reps,
+                argv[1], mib, reps, grid, n * 32, rd ? (size_t)0 : n * 32, ms / reps,
                 bytes / (ms / reps * 1e-3) / 1e9);
     return 0;
   }
   if (!std::strcmp(argv[1], "sweep")) {
-    // hdcg_prof sweep X Y Z T Ls prec reps shape1 shape2 ...
+    // hdcg_prof sweep X Y Z T Ls prec(c128|c64|bf16) reps shape1 shape2 ...
     // (shape = "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]", see dwf_set_hop_shape)
     int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
     const int Ls = std::atoi(argv[6]);
-    const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : DWF_C128;
+    const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : (!std::strcmp(argv[7], "bf16") ? DWF_BF16 : DWF_C128);
     const int reps = std::atoi(argv[8]);
     const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
     std::vector<double> U(V * 4 * 9 * 2, 0.0);
@@ -122,8 +144,11 @@ int main(int argc, char** argv) {
       CHECK(hipEventSynchronize(e1));
       float ms = 0;
       CHECK(hipEventElapsedTime(&ms, e0, e1));
-      const double half = (double)V / 2 * Ls * 12, cb = prec == DWF_C64 ? 8 : 16;
-      const double by = (10 * half + 4.0 * V * 36) * cb;
+      // field bytes per complex (16-bit fields: 4) and link bytes per complex
+      // (complex64 links with 16-bit fields)
+      const double half = (double)V / 2 * Ls * 12;
+      const double cb = prec == DWF_C128 ? 16 : (prec == DWF_C64 ? 8 : 4), gb = prec == DWF_C128 ? 16 : 8;
+      const double by = 10 * half * cb + 4.0 * V * 36 * gb;
       std::printf("tile %-14s %s %dx%dx%dx%d Ls=%d  %.4f ms/H  %.1f GB/s\n", argv[a], argv[7], dims[0], dims[1],
                   dims[2], dims[3], Ls, ms / reps, by / (ms / reps * 1e-3) / 1e9);
       std::fflush(stdout);

@@ -256,6 +256,8 @@ SHAPES = {
     "two-phases": (2, 2, 1, 1, 1, 0, 1, 1, 2),
     "lexicographic-2^4-plain-stores": (2, 2, 2, 2, 0, 0, 0, 0, 4),
     "morton-1x2x2x1-no-remap": (1, 2, 2, 1, 0, 0, 1, 1, 4),
+    "regions-morton-2x2x1x1": (2, 2, 1, 1, 1, 0, 1, 2, 4),
+    "regions-planes-2^4": (2, 2, 2, 2, 1, 0, 1, 3, 4),
 }
 
 
@@ -275,6 +277,37 @@ def test_hop_launch_shapes_ls16(shape):
     got64 = op.to_canonical(op.H(op.to_native(b, hd.DWF_C64), hd.DWF_C64), hd.DWF_C64).cpu().numpy()
     assert rel_err(got64, want) < 5e-6
     op.close()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("block", [(2, 2, 1, 1), (1, 2, 2, 1)])
+def test_hop_region_orders_on_a_block_grid_of_odd_extents(order, block):
+    """The table orders (eight per-XCD regions by bisection, Morton or
+    t-planes inside) on a lattice whose block grid is not a power of two
+    (3 x 3 x 4 x 6 blocks of 2x2x1x1, 6 x 3 x 2 x 6 of 1x2x2x1; regions of
+    unequal size): every site is computed once, with the arithmetic of every
+    other order, so H matches the oracle (complex128) and equals, bit for bit,
+    the lexicographic order's H in complex128, complex64 and 16-bit storage."""
+    dims, Ls = (12, 6, 4, 6), 16
+    banner(f"region order {order} block {block} on {dims} x Ls{Ls}")
+    U = synth.gauge_field(dims, 0.7, 152)
+    op = hd.FineOperator(U, dims, Ls, 1.8, 0.02)
+    lex = hd.FineOperator(U, dims, Ls, 1.8, 0.02)
+    hd.dwf_set_hop_shape(op.h, tuple(block) + (1, 0, 1, order, 4))
+    hd.dwf_set_hop_shape(lex.h, tuple(block) + (0, 0, 1, 0, 4))
+    assert hd.dwf_get_hop_shape(op.h, hd.DWF_C128)[0][7] == order
+    b = synth.gaussian_half_field(dims, Ls, 153)
+    want = DWF(U, dims, Ls, 1.8, 0.02).H(b)
+    x = op.to_native(b)
+    got = op.H(x)
+    assert rel_err(op.to_canonical(got).cpu().numpy(), want) < 1e-12
+    assert torch.equal(got, lex.H(x))
+    x64 = op.to_native(b, hd.DWF_C64)
+    assert torch.equal(op.H(x64, hd.DWF_C64), lex.H(x64, hd.DWF_C64))
+    x16, _ = _bf16_input(op, b)
+    assert torch.equal(op.H(x16, hd.DWF_BF16), lex.H(x16, hd.DWF_BF16))
+    op.close()
+    lex.close()
 
 
 # Mobius (Cayley-form) kernel: (b5, c5) other than Shamir's (1, 0)
