@@ -270,12 +270,15 @@ struct hdcg_params {
   int ldop_m1;        /* 0 (default): deflated coarse solves are deflated CG; 1: ADEF1 with
                          the Chebyshev approximate inverse of the truncated operator
                          (Sec. V.B, "Truncated little Dirac operator as preconditioner";
-                         Table "optimised": LdopM1Chebyshev) */
+                         Table "optimised": LdopM1Chebyshev); 2: ADEF1 with the paper's
+                         alternative, M_IRS(Q_trunc), m1_order CG iterations on
+                         Q_trunc + m1_shift (the infra-red shift) from zero */
   double m1_lo;       /* Chebyshev interval low end, default 0.5 (Table "optimised") */
   double m1_hi;       /* high end; 0 (default): 1.05 x a power-method estimate of the largest
                          eigenvalue of Q_trunc + m1_shift (the paper's 45 fits its ensemble) */
   int m1_order;       /* Chebyshev order n, default 16: residual polynomial of degree n,
-                         n - 1 applications of Q_trunc (1..256) */
+                         n - 1 applications of Q_trunc (1..256); with ldop_m1 = 2 the
+                         number of CG iterations (n applications) */
   double m1_shift;    /* infra-red shift added to Q_trunc, default 0 (>= 0) */
   int surface_depth;  /* d > 0 with 2 d < Ls: the subspace keeps only the slices s < d and
                          s >= Ls - d (Sec. IV.B, the interior of the wall-bound vectors
@@ -491,12 +494,21 @@ int hdcg_m1_interval(hdcg_t h, double* lo, double* hi, void* stream);
  * hdcg_trunc_apply, distinct; r is not modified.  Asynchronous after the
  * interval is known. */
 int hdcg_chebyshev(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream);
+/* y = M_IRS(Q_trunc + m1_shift, m1_order) r (Sec. V.B, closing paragraph of
+ * "Truncated little Dirac operator as preconditioner", with the infra-red
+ * shifted CG of Sec. IV.C): exactly m1_order CG iterations on
+ * (Q_trunc + m1_shift) y = r from y = 0, each right-hand side with its own
+ * coefficients (a zero r gives y = 0).  Arguments as for hdcg_chebyshev;
+ * asynchronous. */
+int hdcg_trunc_cg(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream);
 /* y = M_1 r, the ADEF1 preconditioner of the coarse solve (Sec. V.B):
  * p(Q_trunc + m1_shift) (r - A Z D^-1 Z^+ r) + Z D^-1 Z^+ r with the second
  * level's Z, D and the stored A Z (no application of A).  Arguments as for
- * hdcg_chebyshev; DWF_ERR_ARG before hdcg_ldop_setup.  With params.ldop_m1 =
- * 1 every deflated coarse solve is flexible CG preconditioned by M_1 from
- * x0 = Z D^-1 Z^+ b (alpha = (p, r)/(p, A p), beta = -(A p, y)/(p, A p)). */
+ * hdcg_chebyshev; DWF_ERR_ARG before hdcg_ldop_setup.  p(.) is the
+ * Chebyshev polynomial, or with params.ldop_m1 = 2 the CG of hdcg_trunc_cg.
+ * With params.ldop_m1 = 1 or 2 every deflated coarse solve is flexible CG
+ * preconditioned by M_1 from x0 = Z D^-1 Z^+ b (alpha = (p, r)/(p, A p),
+ * beta = -(A p, y)/(p, A p)). */
 int hdcg_adef1_precondition(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream);
 
 /* Copies for parity checks: the little Dirac operator in the canonical layout

@@ -28,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import coarse as crs
-from .cg import cg
+from .cg import cg, cg_fixed
 
 
 def _flat(V):
@@ -151,6 +151,15 @@ def chebyshev_inverse(apply, r, lo, hi, order):
         delta = (omega / d) * res + (omega - 1.0) * delta
         y = y + delta
     return y
+
+
+def trunc_cg(T, C, r, order):
+    """M_IRS(Q_trunc) r: `order` CG iterations on the shifted truncated
+    operator T (truncate(A, shift)) from zero, the fixed-order CG the paper
+    offers in place of the Chebyshev polynomial (Sec. V.B, closing paragraph
+    of "Truncated little Dirac operator as preconditioner"; the infra-red
+    shifted CG of Sec. IV.C)."""
+    return cg_fixed(lambda u: crs.apply(T, u, C), r, order)
 
 
 def coarse_coarse_inverse(Z, D):

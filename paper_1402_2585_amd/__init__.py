@@ -14,7 +14,7 @@ from ._lib import (  # noqa: F401
     coarse_apply, hdcg_coarse_solve, hdcg_coarse_iterations, hdcg_mfma_tile, hdcg_coarse_solve_noalloc, hdcg_default_params, hdcg_destroy, hdcg_dims, hdcg_export_block_map,
     hdcg_export_coarse, hdcg_import_coarse, hdcg_export_ldop, hdcg_export_subspace, hdcg_ldop_setup, hdcg_mirs, hdcg_project,
     hdcg_promote, hdcg_set_params, hdcg_setup,
-    hdcg_solve, hdcg_trunc_apply, hdcg_m1_interval, hdcg_chebyshev, hdcg_adef1_precondition,
+    hdcg_solve, hdcg_trunc_apply, hdcg_m1_interval, hdcg_chebyshev, hdcg_trunc_cg, hdcg_adef1_precondition,
 )
 from .fields import HDCG, FineOperator  # noqa: F401
 

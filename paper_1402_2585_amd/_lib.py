@@ -124,6 +124,7 @@ def load():
         "hdcg_trunc_apply": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_m1_interval": (i, [vp, dp, dp, vp]),
         "hdcg_chebyshev": (i, [vp, vp, vp, i, i, vp]),
+        "hdcg_trunc_cg": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_adef1_precondition": (i, [vp, vp, vp, i, i, vp]),
         "hdcg_export_coarse": (i, [vp, vp, vp]),
         "hdcg_import_coarse": (i, [vp, vp, vp]),
@@ -397,6 +398,10 @@ def hdcg_m1_interval(h, stream=None):
 
 def hdcg_chebyshev(h, y, r, prec, nrhs=1, stream=None):
     _check(load().hdcg_chebyshev(h, _ptr(y), _ptr(r), int(prec), int(nrhs), _stream(stream)))
+
+
+def hdcg_trunc_cg(h, y, r, prec, nrhs=1, stream=None):
+    _check(load().hdcg_trunc_cg(h, _ptr(y), _ptr(r), int(prec), int(nrhs), _stream(stream)))
 
 
 def hdcg_adef1_precondition(h, y, r, prec, nrhs=1, stream=None):

@@ -209,6 +209,9 @@ template <typename R>
 int m1_chebyshev(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
 template <typename R>
 int m1_adef1(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
+// y = M_IRS(Q_trunc + m1_shift, m1_order) r: m1_order CG iterations from 0
+template <typename R>
+int m1_trunc_cg(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
 int m1_bounds(hdcg* h, double* lo, double* hi, hipStream_t st);
 int m1_check_params(int ldop_m1, double lo, double hi, int order, double shift);
 void trunc_invalidate(hdcg* h);  // after a change of m1_shift

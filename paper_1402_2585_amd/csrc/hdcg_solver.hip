@@ -357,7 +357,7 @@ template <typename R>
 int coarse_cg(hdcg* h, const cplx<R>* AT, cplx<R>* x, const cplx<R>* b, int nr, double tol,
               int maxiter, int* iters, hipStream_t st, int mprec = -1, double shift = 0.0, int* iters_rhs = nullptr) {
   const bool defl = h->ng > 0 && h->prm.ldop_defl != 0 && shift == 0.0;
-  if (defl && h->prm.ldop_m1 == 1)
+  if (defl && h->prm.ldop_m1 >= 1)
     return coarse_adef1<R>(h, AT, x, b, nr, tol, maxiter, iters, st, mprec, iters_rhs);
   if constexpr (sizeof(R) == 4) {
     if (h->persistent_coarse && !defl && shift == 0.0) {
@@ -1315,6 +1315,14 @@ int hdcg_chebyshev(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* s
   auto st = static_cast<hipStream_t>(stream);
   if (prec == DWF_C128) return m1_chebyshev<double>(h, static_cast<c128*>(y), static_cast<const c128*>(r), nrhs, st);
   return m1_chebyshev<float>(h, static_cast<c64*>(y), static_cast<const c64*>(r), nrhs, st);
+}
+
+int hdcg_trunc_cg(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_h(h, prec, nrhs));
+  if (!y || !r || y == r) return fail(DWF_ERR_ARG, "hdcg_trunc_cg needs distinct in/out buffers");
+  auto st = static_cast<hipStream_t>(stream);
+  if (prec == DWF_C128) return m1_trunc_cg<double>(h, static_cast<c128*>(y), static_cast<const c128*>(r), nrhs, st);
+  return m1_trunc_cg<float>(h, static_cast<c64*>(y), static_cast<const c64*>(r), nrhs, st);
 }
 
 int hdcg_adef1_precondition(hdcg_t h, void* y, const void* r, int prec, int nrhs, void* stream) {

@@ -10,7 +10,7 @@
 // of the bytes of A.  It is stored like AT64 / AT128, transposed per stencil
 // point, TT[a][m][k][j] = A[a][l_m][j][k] (+ shift delta_jk at m = 0).
 //
-// The high-mode preconditioner is the Chebyshev iteration for
+// The high-mode preconditioner M is the Chebyshev iteration for
 // (Q_trunc + shift) y = u from y = 0 with the spectrum taken in [lo, hi]:
 // the residual is R_n(x) u, R_n(x) = T_n((d - x)/c) / T_n(d/c),
 // d = (hi + lo)/2, c = (hi - lo)/2.  With sigma = d/c and
@@ -21,9 +21,13 @@
 // for a site and the three site-local updates (delta ping-pongs between two
 // buffers because neighbours read delta_k).
 //
+// or, the paper's alternative, M_IRS(Q_trunc): a fixed number of CG
+// iterations on (Q_trunc + shift) y = u from y = 0.
+//
 // ADEF1 (the second level, Z orthonormal with Z^+ A Z = diag(D), A Z stored):
 //     M_1 r = M (r - A Z D^-1 Z^+ r) + Z D^-1 Z^+ r
 // needs no application of the untruncated A.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -252,6 +256,38 @@ int cheb_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, double lo, doubl
   return DWF_OK;
 }
 
+// y = (acc ? y : 0) + x_n, x_n the n-th iterate (n = m1_order) of CG on
+// (Q_trunc + shift) x = u from x = 0: the infra-red shifted preconditioner
+// M_IRS(Q_trunc, n, shift) of Sec. IV.C on the truncated operator (the
+// paper's alternative to the Chebyshev polynomial).  Every step runs for
+// every right-hand side with its own alpha and beta in device memory (a zero
+// residual gives zero coefficients), so nothing waits for the host.  u is
+// overwritten (it ends as the CG residual).
+template <typename R>
+int mirs_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, hipStream_t st) {
+  const size_t n = (size_t)h->Nc * h->nvec;
+  for (int i = 6; i < 8; ++i) HDCG_TRY(h->cw[i].ensure(n * nr * sizeof(c128)));
+  HDCG_TRY(h->cw[8].ensure(std::max<size_t>(n * nr * sizeof(c128), 4 * 64 * sizeof(double))));
+  cplx<R>* p = h->cw[6].as<cplx<R>>();
+  cplx<R>* w = h->cw[7].as<cplx<R>>();
+  double* sc = h->cw[8].as<double>();
+  double* rr[2] = {sc, sc + 64};
+  double* pw = sc + 128;  // complex (p, w) per right-hand side
+  const Red red{h->op->red.partials.as<double>(), h->op->red.counters.as<unsigned>()};
+  if (!acc) HDCG_TRY(b_zero<R>(y, n * nr, st));
+  HDCG_TRY(b_norm2<R>(red, u, n, nr, rr[0], st));
+  HDCG_HIP(hipMemcpyAsync(p, u, n * nr * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  for (int k = 0; k < h->prm.m1_order; ++k) {
+    HDCG_TRY(trunc_launch<R>(h, p, w, nr, st));
+    HDCG_TRY(b_dot<R>(red, p, w, n, nr, pw, st));
+    // y += alpha p, u -= alpha w, alpha = |u|^2 / (p, w); then p = u + beta p
+    HDCG_TRY(b_update<R>(red, y, u, p, w, n, nr, rr[k & 1], false, pw, nullptr, 0.0, rr[(k + 1) & 1], st, 2));
+    if (k + 1 < h->prm.m1_order)
+      HDCG_TRY(b_xpay<R>(red, p, u, n, nr, rr[(k + 1) & 1], false, rr[k & 1], 1.0, nullptr, st));
+  }
+  return DWF_OK;
+}
+
 }  // namespace
 
 void trunc_invalidate(hdcg* h) {
@@ -332,10 +368,22 @@ int m1_chebyshev(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st) 
 }
 
 template <typename R>
+int m1_trunc_cg(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st) {
+  HDCG_TRY(trunc_ensure<R>(h, st));
+  const size_t n = (size_t)h->Nc * h->nvec * nr;
+  HDCG_TRY(h->cw[9].ensure(n * sizeof(c128)));
+  cplx<R>* u = h->cw[9].as<cplx<R>>();
+  HDCG_HIP(hipMemcpyAsync(u, r, n * sizeof(cplx<R>), hipMemcpyDeviceToDevice, st));
+  return mirs_run<R>(h, y, u, nr, false, st);
+}
+
+// M is the Chebyshev polynomial (ldop_m1 = 1) or M_IRS(Q_trunc) (ldop_m1 = 2)
+template <typename R>
 int m1_adef1(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st) {
   if (h->ng == 0) return fail(DWF_ERR_ARG, "ADEF1 needs the second deflation level (hdcg_ldop_setup)");
+  const bool cg = h->prm.ldop_m1 == 2;
   double lo = 0, hi = 0;
-  HDCG_TRY(m1_bounds(h, &lo, &hi, st));
+  if (!cg) HDCG_TRY(m1_bounds(h, &lo, &hi, st));
   HDCG_TRY(trunc_ensure<R>(h, st));
   const size_t n = (size_t)h->Nc * h->nvec * nr;
   HDCG_TRY(h->cw[9].ensure(n * sizeof(c128)));
@@ -346,13 +394,13 @@ int m1_adef1(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st) {
   HDCG_TRY(ldop_coef<R>(h, Z, r, nr, st));
   HDCG_TRY(ldop_apply<R>(h, u, r, nullptr, nullptr, AZ, nr, -1.0, true, st));
   HDCG_TRY(ldop_apply<R>(h, y, nullptr, nullptr, nullptr, Z, nr, 1.0, false, st));
-  return cheb_run<R>(h, y, u, nr, true, lo, hi, st);
+  return cg ? mirs_run<R>(h, y, u, nr, true, st) : cheb_run<R>(h, y, u, nr, true, lo, hi, st);
 }
 
 int m1_check_params(int ldop_m1, double lo, double hi, int order, double shift) {
-  if (ldop_m1 != 0 && ldop_m1 != 1) return fail(DWF_ERR_ARG, "ldop_m1 must be 0 or 1");
+  if (ldop_m1 < 0 || ldop_m1 > 2) return fail(DWF_ERR_ARG, "ldop_m1 must be 0, 1 or 2");
   if (!(lo > 0.0) || !(hi == 0.0 || hi > lo) || order < 1 || order > kMaxOrder || !(shift >= 0.0))
-    return fail(DWF_ERR_ARG, "Chebyshev preconditioner: need m1_lo > 0, m1_hi = 0 or > m1_lo, "
+    return fail(DWF_ERR_ARG, "truncated-operator preconditioner: need m1_lo > 0, m1_hi = 0 or > m1_lo, "
                              "1 <= m1_order <= 256, m1_shift >= 0");
   return DWF_OK;
 }
@@ -361,6 +409,8 @@ template int trunc_apply<float>(hdcg*, const c64*, c64*, int, hipStream_t);
 template int trunc_apply<double>(hdcg*, const c128*, c128*, int, hipStream_t);
 template int m1_chebyshev<float>(hdcg*, c64*, const c64*, int, hipStream_t);
 template int m1_chebyshev<double>(hdcg*, c128*, const c128*, int, hipStream_t);
+template int m1_trunc_cg<float>(hdcg*, c64*, const c64*, int, hipStream_t);
+template int m1_trunc_cg<double>(hdcg*, c128*, const c128*, int, hipStream_t);
 template int m1_adef1<float>(hdcg*, c64*, const c64*, int, hipStream_t);
 template int m1_adef1<double>(hdcg*, c128*, const c128*, int, hipStream_t);
 

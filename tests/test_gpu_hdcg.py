@@ -446,6 +446,86 @@ def test_truncated_operator_chebyshev_adef1_against_oracle(two_level):
         h.set_params(ldop_m1=0, ldop_defl=0, m1_shift=0.0, m1_hi=0.0, m1_order=16)
 
 
+def test_truncated_cg_mirs_and_adef1_against_oracle(two_level):
+    """M_IRS(Q_trunc), the paper's fixed-order CG alternative to the
+    Chebyshev polynomial (Sec. V.B, closing paragraph of "Truncated little
+    Dirac operator as preconditioner"): hdcg_trunc_cg against the oracle's
+    trunc_cg for 1, 4 and 12 iterations on one and three right-hand sides,
+    one of them zero (complex128 1e-10, complex64 1e-4; the zero one stays
+    exactly zero); M_1 with ldop_m1 = 2 against the oracle's ADEF1
+    preconditioner with that M (complex128 1e-6: the two second levels agree
+    to about 1e-8); the ADEF1 coarse solve with it against a dense solve
+    (complex128 to 1e-10: 1e-7; complex64 on three right-hand sides: 1e-3);
+    and a full solve with it to 1e-8 under the oracle's H."""
+    from oracle import ldop as oldop
+
+    t = two_level
+    banner(f"truncated CG (M_IRS(Q_trunc)) / ADEF1 {t['name']}")
+    h, A, C, op, ref = t["h"], t["A"], t["C"], t["op"], t["ref"]
+    Nc, nvec = A.shape[0], A.shape[2]
+    shift = 0.2
+    T = oldop.truncate(A, shift)
+    precs = ((hd.DWF_C128, torch.complex128, 1e-10), (hd.DWF_C64, torch.complex64, 1e-4))
+    try:
+        r = synth.gaussian_coarse(Nc, nvec, 380, 3)
+        r[1] = 0.0
+        for n in (1, 4, 12):
+            h.set_params(m1_shift=shift, m1_order=n)
+            want = np.array([oldop.trunc_cg(T, C, ri, n) for ri in r])
+            for prec, dt, tol in precs:
+                for nr in (1, 3):
+                    y = h.new_coarse(prec, nr)
+                    hd.hdcg_trunc_cg(h.h, y, torch.from_numpy(r[:nr]).to(dt).to("cuda"), prec, nr)
+                    got = y.cpu().numpy()
+                    err = rel_err(got, want[:nr])
+                    print(f"truncated CG {n} iterations prec={prec} nrhs={nr}: rel err {err:.2e}", flush=True)
+                    assert err < tol
+                    if nr == 3:
+                        assert np.abs(got[1]).max() == 0.0
+        noise = synth.gaussian_coarse(Nc, nvec, 372, 6)
+        hd.hdcg_ldop_setup(h.h, 6, torch.from_numpy(noise).to("cuda"), 0.0, 3, 1e-12)
+        Vi = oldop.inverse_iteration(A, C, noise, n_steps=3, shift=0.0, tol=1e-12)
+        W = oldop.orthonormal_basis(np.concatenate([oldop.free_global_vectors(Nc, nvec), Vi]))
+        Z, Dz, AZ = oldop.third_level(A, C, W)
+        h.set_params(ldop_m1=2, m1_order=8)
+        M1 = oldop.adef1_preconditioner(Z, Dz, AZ, lambda u: oldop.trunc_cg(T, C, u, 8))
+        r2 = synth.gaussian_coarse(Nc, nvec, 381, 2)
+        want = np.array([M1(ri) for ri in r2])
+        y = h.new_coarse(hd.DWF_C128, 2)
+        hd.hdcg_adef1_precondition(h.h, y, torch.from_numpy(r2).to("cuda"), hd.DWF_C128, 2)
+        err = rel_err(y.cpu().numpy(), want)
+        print(f"M_1 with the truncated CG, complex128: rel err {err:.2e}", flush=True)
+        assert err < 1e-6
+        b = synth.gaussian_coarse(Nc, nvec, 382, 3)
+        xd = np.array([np.linalg.solve(ocrs.to_dense(A, C), bi.ravel()).reshape(bi.shape) for bi in b])
+        h.set_params(ldop_defl=1, ldop_m1=0)
+        x = h.new_coarse(hd.DWF_C128)
+        rc, it_d = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b[:1]).to("cuda"), hd.DWF_C128, 1, 1e-10, 2000)
+        assert rc == 0
+        h.set_params(ldop_m1=2)
+        x = h.new_coarse(hd.DWF_C128)
+        rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b[:1]).to("cuda"), hd.DWF_C128, 1, 1e-10, 2000)
+        err = rel_err(x.cpu().numpy()[0], xd[0])
+        print(f"ADEF1(M_IRS(Q_trunc)) coarse solve complex128: {it} iterations (deflated CG {it_d}), "
+              f"rel err {err:.2e}", flush=True)
+        assert rc == 0 and err < 1e-7 and it <= it_d
+        x = h.new_coarse(hd.DWF_C64, 3)
+        rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to(torch.complex64).to("cuda"), hd.DWF_C64, 3,
+                                      1e-5, 2000)
+        err = rel_err(x.cpu().numpy(), xd)
+        print(f"ADEF1(M_IRS(Q_trunc)) coarse solve complex64, 3 rhs: {it} iterations, rel err {err:.2e}", flush=True)
+        assert rc == 0 and err < 1e-3
+        bf = synth.gaussian_half_field(t["dims"], t["Ls"], 383)
+        xf = op.new_field()
+        rcs, st = hd.hdcg_solve(h.h, xf, op.to_native(bf), 1, 1e-8)
+        print("hdcg_solve with ADEF1(M_IRS(Q_trunc)) coarse solves", st, flush=True)
+        assert rcs == 0 and st["converged"] == 1
+        rf = bf - ref.H(op.to_canonical(xf).cpu().numpy())
+        assert np.sqrt(np.vdot(rf, rf).real / np.vdot(bf, bf).real) <= 1e-8
+    finally:
+        h.set_params(ldop_m1=0, ldop_defl=0, m1_shift=0.0, m1_hi=0.0, m1_order=16)
+
+
 def test_ldop_deflation_cuts_coarse_iterations():
     """On a subspace after inverse iteration (A then has the low modes the
     second level is for), deflated coarse CG needs fewer iterations than

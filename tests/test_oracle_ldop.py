@@ -209,6 +209,50 @@ def test_adef1_solves_and_reduces_iterations(small):
     assert it < it_d, (it, it_d)
 
 
+def test_trunc_cg_is_the_fixed_order_cg_on_q_trunc():
+    """M_IRS(Q_trunc) (Sec. V.B, with the shifted CG of Sec. IV.C): one
+    iteration is the steepest-descent step (r, r) / (r, T r) r; enough
+    iterations reach the dense solve of Q_trunc + shift; on an eigenvector of
+    T the first iteration is already its exact inverse; zero stays zero."""
+    A, C = _dense_case(72)
+    T = ldop.truncate(A, shift=0.5)
+    Dt = crs.to_dense(T, C)
+    ev, U = np.linalg.eigh(Dt)
+    assert ev[0] > 0
+    rng = np.random.default_rng(73)
+    r = rng.standard_normal((A.shape[0], A.shape[2])) + 1j * rng.standard_normal((A.shape[0], A.shape[2]))
+    Tr = crs.apply(T, r, C)
+    y1 = ldop.trunc_cg(T, C, r, 1)
+    want = (np.vdot(r, r) / np.vdot(r, Tr)).real * r
+    assert np.abs(y1 - want).max() < 1e-13 * np.abs(want).max()
+    yn = ldop.trunc_cg(T, C, r, 300)
+    xd = np.linalg.solve(Dt, r.ravel()).reshape(r.shape)
+    assert np.abs(yn - xd).max() < 1e-10 * np.abs(xd).max()
+    v = U[:, 5].reshape(r.shape)
+    assert np.abs(ldop.trunc_cg(T, C, v, 1) - v / ev[5]).max() < 1e-12 * np.abs(v).max() / ev[5]
+    assert np.abs(ldop.trunc_cg(T, C, np.zeros_like(r), 4)).max() == 0.0
+
+
+def test_adef1_with_the_truncated_cg_solves_and_reduces_iterations(small):
+    """ADEF1 with M = M_IRS(Q_trunc) (8 CG iterations on Q_trunc + 0.1) in
+    place of the Chebyshev polynomial: the flexible coarse solve reaches the
+    dense solution, in fewer iterations than deflated CG."""
+    op, phi, sob, C, A = small
+    Nc, nvec = A.shape[0], A.shape[2]
+    rng = np.random.default_rng(74)
+    V0 = rng.standard_normal((6, Nc, nvec)) + 1j * rng.standard_normal((6, Nc, nvec))
+    W = ldop.orthonormal_basis(np.concatenate([ldop.free_global_vectors(Nc, nvec),
+                                               ldop.inverse_iteration(A, C, V0, 3, 0.0, 1e-9)]))
+    Z, Dz, AZ = ldop.third_level(A, C, W)
+    T = ldop.truncate(A, shift=0.1)
+    b = rng.standard_normal((Nc, nvec)) + 1j * rng.standard_normal((Nc, nvec))
+    x, it, rel = ldop.adef1_solve(A, C, b, Z, Dz, AZ, lambda r: ldop.trunc_cg(T, C, r, 8), tol=1e-10)
+    xd = np.linalg.solve(crs.to_dense(A, C), b.ravel()).reshape(b.shape)
+    assert rel <= 1e-10 and np.abs(x - xd).max() < 1e-7 * np.abs(xd).max()
+    _, it_d, _ = ldop.deflated_cg(A, C, b, Z, Dz, AZ, tol=1e-10)
+    assert it < it_d, (it, it_d)
+
+
 def test_adef1_is_identity_on_the_deflation_space(small):
     """M_1 A z = z for z in span(Z): Q A z = z because Z^+ A Z = D, and the
     M term then acts on A z - A z = 0 (any M, here a plain scaling)."""
