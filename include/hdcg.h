@@ -306,6 +306,12 @@ struct hdcg_params {
                             two thirds of the subspace memory (49 GB at 24^3 x 48 x 16, Nvec
                             48); complex128 project / promote, hdcg_export_subspace and a later
                             switch to a subspace copy not yet built then return DWF_ERR_STATE */
+  int m1_prec;           /* storage of Q_trunc for the complex64 coarse solves and for
+                            hdcg_trunc_apply / hdcg_chebyshev / hdcg_trunc_cg with DWF_C64:
+                            DWF_C64 (default), or DWF_BF16 / DWF_F16: the nine matrices per
+                            site in the 16-bit MFMA storage of coarse_prec (per-matrix scales,
+                            FP32 accumulation; nvec a multiple of 4, at most 64), a quarter of
+                            the complex64 bytes.  The complex128 forms keep complex128 */
 };
 
 struct hdcg_stats {

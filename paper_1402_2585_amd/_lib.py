@@ -50,7 +50,7 @@ class HdcgParams(C.Structure):
                 ("ldop_m1", C.c_int), ("m1_lo", C.c_double), ("m1_hi", C.c_double), ("m1_order", C.c_int),
                 ("m1_shift", C.c_double), ("surface_depth", C.c_int), ("coarse_persistent", C.c_int),
                 ("graph", C.c_int), ("phase_timing", C.c_int), ("mfma_tile", C.c_int), ("seed", C.c_ulonglong),
-                ("keep_subspace_fp64", C.c_int)]
+                ("keep_subspace_fp64", C.c_int), ("m1_prec", C.c_int)]
 
 
 class HdcgStats(C.Structure):

@@ -14,6 +14,17 @@ namespace hdk {
 
 constexpr int kCT = 512;  // threads per coarse-site workgroup
 
+// The one-hop truncation of the stencil (Sec. V.B): kOneHop points, point m
+// at stencil index l = sum_mu (d_mu + 1) 3^mu; m = 0 the site, m = 2 mu + 1
+// and 2 mu + 2 the neighbours at -1 and +1 in direction mu.
+constexpr int kOneHop = 9;
+__host__ __device__ inline int one_hop_l(int m) {
+  if (m == 0) return 40;
+  const int mu = (m - 1) >> 1;
+  const int p3 = mu == 0 ? 1 : mu == 1 ? 3 : mu == 2 ? 9 : 27;
+  return (m & 1) ? 40 - p3 : 40 + p3;
+}
+
 // Loads and stores of complex64 values that other workgroups of a running
 // persistent kernel write or read: relaxed device-scope atomics, coherent
 // across the XCDs' L2 caches without whole-cache write-back or invalidation.
@@ -144,13 +155,15 @@ __device__ __forceinline__ unsigned short to16(float f) {
 // with coherent loads (persistent kernels).  K32: gfx950's 16x16x32 MFMA
 // (8 K values per lane; the A fragment of one 32-wide step is two
 // consecutive 16-wide storage steps, one 16-byte load per lane; needs
-// nvec % 8 == 0), else the 16x16x16 form.  Every thread of the workgroup
-// (NW * 64 threads) must call it.
+// nvec % 8 == 0), else the 16x16x16 form.  NS: stencil points (the 81 of A,
+// or the 9 of the one-hop truncation; F, rho and nbr then hold NS per site).
+// Every thread of the workgroup (NW * 64 threads) must call it.
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false, bool COH = false, bool K32 = false>
+template <bool BF16, int MT, int NT, int NW, int U, bool STAGED = false, bool COH = false, bool K32 = false,
+          int NS = kStencil>
 __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restrict__ F,
                                                  const float* __restrict__ rho,
                                                  const float* __restrict__ smax, const int* __restrict__ nbr,
@@ -160,8 +173,8 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
   constexpr int KL = K32 ? 8 : 4;  // K values per lane and step
   constexpr int KS = 4 * KL;       // K values per step
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ktot = 2 * kStencil * nvec;
-  const int kn = kStencil * nvec;
+  const int ktot = 2 * NS * nvec;
+  const int kn = NS * nvec;
   const int r16 = lane & 15, kg = lane >> 4;
   const int nsteps = K32 ? (ksteps + 1) / 2 : ksteps;
   f32x4 acc[MT][NT];
@@ -170,8 +183,8 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
-  const int* nb = nbr + (size_t)a * kStencil;
-  const float* rh = rho + (size_t)a * kStencil;
+  const int* nb = nbr + (size_t)a * NS;
+  const float* rh = rho + (size_t)a * NS;
   // storage step and k group of this lane's A fragment at step S
   const int sub = K32 ? (kg >> 1) : 0, kgs = K32 ? 2 * (kg & 1) : kg;
   for (int s0 = wave * U; s0 < nsteps; s0 += NW * U) {

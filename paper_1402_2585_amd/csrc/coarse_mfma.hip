@@ -2,6 +2,8 @@
 // or fp16) and FP32 accumulation: per-matrix scales, fragment-ordered
 // storage and the standalone mat-vec launch.  The per-site GEMM itself
 // (operand layout, scaling) is capply_site_mfma in coarse_dev.h.
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -32,20 +34,23 @@ __global__ void k_scales(const c128* __restrict__ A, float* __restrict__ s, int 
   if (threadIdx.x == 0) s[al] = red[0];
 }
 
-// rho[a][l] = s_al / smax_a (in place), smax[a]
+// rho[a][l] = s_al / smax_a (in place), smax[a]; NS matrices per site
+template <int NS>
 __global__ void k_rho(float* __restrict__ s, float* __restrict__ smax, int Nc) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= Nc) return;
   float m = 0.f;
-  for (int l = 0; l < kStencil; ++l) m = fmaxf(m, s[a * kStencil + l]);
+  for (int l = 0; l < NS; ++l) m = fmaxf(m, s[a * NS + l]);
   smax[a] = m;
-  for (int l = 0; l < kStencil; ++l) {
-    const float v = s[a * kStencil + l];
-    s[a * kStencil + l] = m > 0.f ? v / m : 0.f;
+  for (int l = 0; l < NS; ++l) {
+    const float v = s[a * NS + l];
+    s[a * NS + l] = m > 0.f ? v / m : 0.f;
   }
 }
 
-template <bool BF16>
+// A: [Nc][NS][nvec][nvec] row-major matrices (NS = 81: the little Dirac
+// operator; NS = 9: its one-hop truncation)
+template <bool BF16, int NS>
 __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho,
                        const float* __restrict__ smax, unsigned short* __restrict__ F, int Nc,
                        int nvec, int ksteps) {
@@ -57,17 +62,17 @@ __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho
   const size_t as = e / (4 * (size_t)nvec);
   const int s = (int)(as % ksteps);
   const int a = (int)(as / ksteps);
-  const int ktot = 2 * kStencil * nvec;
+  const int ktot = 2 * NS * nvec;
   unsigned short v4[4];
   for (int i = 0; i < 4; ++i) {
     const int kap = 16 * s + 4 * kg + i;
     float v = 0.f;
     if (kap < ktot) {
-      const int part = kap / (kStencil * nvec);
-      const int rem = kap - part * kStencil * nvec;
+      const int part = kap / (NS * nvec);
+      const int rem = kap - part * NS * nvec;
       const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
-      const float sal = rho[a * kStencil + l] * smax[a];
-      const c128 x = A[(((size_t)a * kStencil + l) * nvec + m) * nvec + k];
+      const float sal = rho[a * NS + l] * smax[a];
+      const c128 x = A[(((size_t)a * NS + l) * nvec + m) * nvec + k];
       v = sal > 0.f ? (float)((part == 0 ? x.re : x.im) / sal) : 0.f;
     }
     v4[i] = to16<BF16>(v);
@@ -76,33 +81,34 @@ __global__ void k_frag(const c128* __restrict__ A, const float* __restrict__ rho
   for (int i = 0; i < 4; ++i) o[i] = v4[i];
 }
 
-template <bool BF16, int MT, int NT, int NW, int U, bool K32>
+template <bool BF16, int MT, int NT, int NW, int U, bool K32, int NS = kStencil>
 __global__ void __launch_bounds__(NW * 64)
 k_capply_mfma(const unsigned short* __restrict__ F, const float* __restrict__ rho,
               const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
               c64* __restrict__ out, int Nc, int nvec, int nrhs, int ksteps) {
   __shared__ f32x4 red[NW * MT * NT * 64];
-  capply_site_mfma<BF16, MT, NT, NW, U, false, false, K32>(F, rho, smax, nbr, in, out, blockIdx.x, Nc, nvec, nrhs,
-                                                           ksteps, red);
+  capply_site_mfma<BF16, MT, NT, NW, U, false, false, K32, NS>(F, rho, smax, nbr, in, out, blockIdx.x, Nc, nvec,
+                                                               nrhs, ksteps, red);
 }
 
-// One right-hand side: the site's operand at its 81 neighbours is gathered
+// One right-hand side: the site's operand at its NS neighbours is gathered
 // into LDS first (one coalesced pass).
-template <bool BF16, int MT, int U, bool K32>
+template <bool BF16, int MT, int U, bool K32, int NS = kStencil>
 __global__ void __launch_bounds__(8 * 64)
 k_capply_mfma_staged(const unsigned short* __restrict__ F, const float* __restrict__ rho,
                      const float* __restrict__ smax, const int* __restrict__ nbr, const c64* __restrict__ in,
                      c64* __restrict__ out, int Nc, int nvec, int ksteps) {
   __shared__ f32x4 red[8 * MT * 64];
-  __shared__ c64 xin[kStencil * 64];
+  __shared__ c64 xin[NS * 64];
   const int a = blockIdx.x;
-  const int* nb = nbr + (size_t)a * kStencil;
-  for (int e = threadIdx.x; e < kStencil * nvec; e += 8 * 64) {
+  const int* nb = nbr + (size_t)a * NS;
+  for (int e = threadIdx.x; e < NS * nvec; e += 8 * 64) {
     const int l = e / nvec;
     xin[e] = in[(size_t)nb[l] * nvec + (e - l * nvec)];
   }
   __syncthreads();
-  capply_site_mfma<BF16, MT, 1, 8, U, true, false, K32>(F, rho, smax, nbr, xin, out, a, Nc, nvec, 1, ksteps, red);
+  capply_site_mfma<BF16, MT, 1, 8, U, true, false, K32, NS>(F, rho, smax, nbr, xin, out, a, Nc, nvec, 1, ksteps,
+                                                            red);
 }
 
 // ---------------------------------------------------------- tile shapes --
@@ -293,7 +299,7 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
     hipLaunchKernelGGL(k_scales, dim3(h->Nc * kStencil), dim3(256), 0, st, h->A128.as<c128>(),
                        h->mf_rho.as<float>(), nv * nv);
     HDCG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rho, dim3((h->Nc + 127) / 128), dim3(128), 0, st, h->mf_rho.as<float>(),
+    hipLaunchKernelGGL(k_rho<kStencil>, dim3((h->Nc + 127) / 128), dim3(128), 0, st, h->mf_rho.as<float>(),
                        h->mf_smax.as<float>(), h->Nc);
     HDCG_HIP(hipGetLastError());
   }
@@ -301,11 +307,11 @@ int crs_build_mfma(hdcg* h, int prec, hipStream_t st) {
   const size_t total = (size_t)h->Nc * ksteps * nv * 4;  // (a, s, m, kg), 4 values each
   HDCG_TRY(F.ensure(total * 4 * sizeof(unsigned short)));
   if (prec == DWF_BF16)
-    hipLaunchKernelGGL((k_frag<true>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_frag<true, kStencil>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
                        F.as<unsigned short>(), h->Nc, nv, ksteps);
   else
-    hipLaunchKernelGGL((k_frag<false>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_frag<false, kStencil>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        h->A128.as<c128>(), h->mf_rho.as<float>(), h->mf_smax.as<float>(),
                        F.as<unsigned short>(), h->Nc, nv, ksteps);
   HDCG_HIP(hipGetLastError());
@@ -340,6 +346,138 @@ int crs_apply_mfma(hdcg* h, int prec, const c64* in, c64* out, int nr, hipStream
                               : launch_all<false>(h, t, F, in + off, out + off, rest, ksteps, st));
   }
   return DWF_OK;
+}
+
+// ------------------------------------------- 16-bit truncated operator --
+// Q_trunc + shift (the zero- and one-hop matrices of A, Sec. V.B) in the same
+// 16-bit fragment storage as A, with its own per-matrix scales: nine matrices
+// per site instead of 81.  Built from A128 through a temporary complex128
+// copy of the nine matrices; applied with a fixed tile (the gfx950 16x16x32
+// form when nvec % 8 == 0, eight waves; one right-hand side through the
+// LDS-staged kernel).
+
+namespace {
+
+constexpr int kTS9 = kOneHop;
+
+__global__ void k_q9(c128* __restrict__ Q, const c128* __restrict__ A, int Nc, int nvec, double shift) {
+  const size_t total = (size_t)Nc * kTS9 * nvec * nvec;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx % nvec);
+    const int j = (int)((idx / nvec) % nvec);
+    const size_t am = idx / ((size_t)nvec * nvec);
+    const int m = (int)(am % kTS9);
+    const size_t a = am / kTS9;
+    c128 v = A[((a * kStencil + one_hop_l(m)) * nvec + j) * nvec + k];
+    if (m == 0 && j == k) v.re += shift;
+    Q[idx] = v;
+  }
+}
+
+template <bool BF16, int MT>
+int trunc16_chunk(hdcg* h, const unsigned short* F, const c64* in, c64* out, int n, int ksteps, hipStream_t st) {
+  const float* rho = h->tq_rho.as<float>();
+  const float* smax = h->tq_smax.as<float>();
+  const int* nbr = h->nbr9.as<int>();
+  const bool k32 = h->nvec % 8 == 0;
+  if (n == 1) {
+    if (k32)
+      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT, 2, true, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho,
+                         smax, nbr, in, out, h->Nc, h->nvec, ksteps);
+    else
+      hipLaunchKernelGGL((k_capply_mfma_staged<BF16, MT, 4, false, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho,
+                         smax, nbr, in, out, h->Nc, h->nvec, ksteps);
+  } else if (2 * n <= 16) {
+    if (k32)
+      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 1, 8, 2, true, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho,
+                         smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+    else
+      hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 1, 8, 4, false, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho,
+                         smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+  } else {
+    // two 16-column tiles: the LDS reduction buffer of 8 waves is 8 * MT * 2
+    // * 1 KiB, within 48 KiB for MT <= 3; 4 waves for MT = 4
+    if constexpr (MT <= 3) {
+      if (k32)
+        hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2, 8, 2, true, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F, rho,
+                           smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+      else
+        hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2, 8, 4, false, kTS9>), dim3(h->Nc), dim3(8 * 64), 0, st, F,
+                           rho, smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+    } else {
+      if (k32)
+        hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2, 4, 2, true, kTS9>), dim3(h->Nc), dim3(4 * 64), 0, st, F, rho,
+                           smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+      else
+        hipLaunchKernelGGL((k_capply_mfma<BF16, MT, 2, 4, 4, false, kTS9>), dim3(h->Nc), dim3(4 * 64), 0, st, F,
+                           rho, smax, nbr, in, out, h->Nc, h->nvec, n, ksteps);
+    }
+  }
+  HDCG_HIP(hipGetLastError());
+  return DWF_OK;
+}
+
+template <bool BF16>
+int trunc16_all(hdcg* h, const unsigned short* F, const c64* in, c64* out, int nr, hipStream_t st) {
+  const int ksteps = (2 * kTS9 * h->nvec + 15) / 16;
+  const int mt = (h->nvec + 15) / 16;
+  for (int r0 = 0; r0 < nr; r0 += 16) {
+    const int n = nr - r0 < 16 ? nr - r0 : 16;
+    const size_t off = (size_t)r0 * h->Nc * h->nvec;
+    switch (mt) {
+      case 1: HDCG_TRY((trunc16_chunk<BF16, 1>(h, F, in + off, out + off, n, ksteps, st))); break;
+      case 2: HDCG_TRY((trunc16_chunk<BF16, 2>(h, F, in + off, out + off, n, ksteps, st))); break;
+      case 3: HDCG_TRY((trunc16_chunk<BF16, 3>(h, F, in + off, out + off, n, ksteps, st))); break;
+      default: HDCG_TRY((trunc16_chunk<BF16, 4>(h, F, in + off, out + off, n, ksteps, st))); break;
+    }
+  }
+  return DWF_OK;
+}
+
+}  // namespace
+
+int trunc16_build(hdcg* h, int prec, double shift, hipStream_t st) {
+  const int nv = h->nvec;
+  if (nv % 4 != 0 || nv > 64)
+    return fail(DWF_ERR_ARG, "16-bit truncated operator needs nvec a multiple of 4 and <= 64");
+  if (h->A128.bytes == 0) return fail(DWF_ERR_ARG, "the truncated operator needs the little Dirac operator");
+  if (h->nbr9.bytes == 0) return fail(DWF_ERR_STATE, "one-hop neighbour table not built");
+  const size_t nmat = (size_t)h->Nc * kTS9;
+  DevBuf q;
+  HDCG_TRY(q.ensure(sizeof(c128) * nmat * nv * nv));
+  const size_t tot = nmat * nv * nv;
+  hipLaunchKernelGGL(k_q9, dim3((unsigned)std::min<size_t>((tot + 255) / 256, 65536)), dim3(256), 0, st, q.as<c128>(),
+                     h->A128.as<c128>(), h->Nc, nv, shift);
+  HDCG_HIP(hipGetLastError());
+  HDCG_TRY(h->tq_rho.ensure(sizeof(float) * nmat));
+  HDCG_TRY(h->tq_smax.ensure(sizeof(float) * h->Nc));
+  hipLaunchKernelGGL(k_scales, dim3((unsigned)nmat), dim3(256), 0, st, q.as<c128>(), h->tq_rho.as<float>(), nv * nv);
+  HDCG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_rho<kTS9>, dim3((h->Nc + 127) / 128), dim3(128), 0, st, h->tq_rho.as<float>(),
+                     h->tq_smax.as<float>(), h->Nc);
+  HDCG_HIP(hipGetLastError());
+  const int ksteps = (2 * kTS9 * nv + 15) / 16;
+  const size_t total = (size_t)h->Nc * ksteps * nv * 4;
+  DevBuf& F = prec == DWF_BF16 ? h->tq_bf16 : h->tq_f16;
+  HDCG_TRY(F.ensure(total * 4 * sizeof(unsigned short)));
+  if (prec == DWF_BF16)
+    hipLaunchKernelGGL((k_frag<true, kTS9>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q.as<c128>(),
+                       h->tq_rho.as<float>(), h->tq_smax.as<float>(), F.as<unsigned short>(), h->Nc, nv, ksteps);
+  else
+    hipLaunchKernelGGL((k_frag<false, kTS9>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, q.as<c128>(),
+                       h->tq_rho.as<float>(), h->tq_smax.as<float>(), F.as<unsigned short>(), h->Nc, nv, ksteps);
+  HDCG_HIP(hipGetLastError());
+  HDCG_HIP(hipStreamSynchronize(st));  // before the temporary copy is freed
+  q.release();
+  (prec == DWF_BF16 ? h->tq_shift_bf16 : h->tq_shift_f16) = shift;
+  // the scales are shared by the two 16-bit forms: the other one is stale now
+  (prec == DWF_BF16 ? h->tq_shift_f16 : h->tq_shift_bf16) = std::nan("");
+  return DWF_OK;
+}
+
+int trunc16_apply(hdcg* h, int prec, const c64* in, c64* out, int nr, hipStream_t st) {
+  const unsigned short* F = (prec == DWF_BF16 ? h->tq_bf16 : h->tq_f16).as<unsigned short>();
+  return prec == DWF_BF16 ? trunc16_all<true>(h, F, in, out, nr, st) : trunc16_all<false>(h, F, in, out, nr, st);
 }
 
 // The tile the autotuner chose for (prec, n right-hand sides per launch) on

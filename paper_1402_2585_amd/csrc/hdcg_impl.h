@@ -83,6 +83,9 @@ struct hdcg {
   // terms, TT[a][m][k][j] for the 9 points m, and their neighbour table
   hdk::DevBuf TT64, TT128, nbr9;
   double tt_shift64 = __builtin_nan(""), tt_shift128 = __builtin_nan("");  // shift TT was built with
+  // Q_trunc + m1_shift in the 16-bit MFMA storage (m1_prec BF16 / F16): scales and fragments
+  hdk::DevBuf tq_rho, tq_smax, tq_bf16, tq_f16;
+  double tq_shift_bf16 = __builtin_nan(""), tq_shift_f16 = __builtin_nan("");
   double m1_hi_est = 0.0;           // estimated Chebyshev upper bound (m1_hi <= 0)
   hdk::DevBuf ycw;                  // ADEF1 coarse solve: the preconditioned residual
   double* pinned = nullptr;   // host pinned scalars [16][64]
@@ -111,6 +114,7 @@ struct hdcg {
     double m1_lo = 0.5, m1_hi = 0.0;  // Chebyshev interval (m1_hi <= 0: estimated)
     int m1_order = 16;          // Chebyshev order (m1_order - 1 truncated mat-vecs)
     double m1_shift = 0.0;      // infra-red shift added to Q_trunc
+    int m1_prec = DWF_C64;      // Q_trunc storage for complex64 solves: C64, or BF16 / F16 (MFMA)
     int surface_depth = 0;      // > 0 and 2 depth < Ls: remove the subspace's fifth-dimension interior
     int verbose = 0;            // print setup progress to stderr
   } prm;
@@ -215,6 +219,10 @@ int m1_trunc_cg(hdcg* h, cplx<R>* y, const cplx<R>* r, int nr, hipStream_t st);
 int m1_bounds(hdcg* h, double* lo, double* hi, hipStream_t st);
 int m1_check_params(int ldop_m1, double lo, double hi, int order, double shift);
 void trunc_invalidate(hdcg* h);  // after a change of m1_shift
+// Q_trunc + shift in 16-bit MFMA storage (coarse_mfma.hip; needs nbr9), and
+// out = (Q_trunc + shift) in with it (complex64 vectors, 1..64 right-hand sides)
+int trunc16_build(hdcg* h, int prec, double shift, hipStream_t st);
+int trunc16_apply(hdcg* h, int prec, const cplx<float>* in, cplx<float>* out, int nr, hipStream_t st);
 
 // c[rhs][k] = (V_k, r_rhs) / D_k into h->ldc
 template <typename R>

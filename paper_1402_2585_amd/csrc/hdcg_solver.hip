@@ -25,6 +25,15 @@ constexpr double kPi = 3.14159265358979323846;
 
 Red red_of(dwf_op* op) { return Red{op->red.partials.as<double>(), op->red.counters.as<unsigned>()}; }
 
+// m1_prec: complex64, or 16-bit MFMA storage where nvec allows it
+int check_m1_prec(int prec, int nvec) {
+  if (prec == DWF_C64) return DWF_OK;
+  if (prec != DWF_BF16 && prec != DWF_F16) return fail(DWF_ERR_ARG, "m1_prec must be DWF_C64, DWF_BF16 or DWF_F16");
+  if (nvec % 4 != 0 || nvec > 64)
+    return fail(DWF_ERR_ARG, "a 16-bit truncated operator needs nvec a multiple of 4 and at most 64");
+  return DWF_OK;
+}
+
 // device scalar slots, 128 doubles each (room for 64 right-hand sides x 2)
 enum {
   S_RR0, S_RR1, S_PAP, S_PP,                       // fine CG
@@ -735,6 +744,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->mfma_tile = -1;
   p->seed = 1;
   p->keep_subspace_fp64 = 1;
+  p->m1_prec = DWF_C64;
 }
 
 int hdcg_destroy(hdcg_t h) {
@@ -1043,6 +1053,7 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
     h->prm.m1_hi = p->m1_hi;
     h->prm.m1_order = p->m1_order;
     h->prm.m1_shift = p->m1_shift;
+    h->prm.m1_prec = p->m1_prec;
     h->prm.surface_depth = p->surface_depth;
     h->seed = p->seed;
     h->keep_phi128 = p->keep_subspace_fp64 != 0;
@@ -1057,6 +1068,10 @@ int hdcg_setup(hdcg_t* out, dwf_op_t op, const int block[4], int nvec, const voi
   }
   if (const int rc = m1_check_params(h->prm.ldop_m1, h->prm.m1_lo, h->prm.m1_hi, h->prm.m1_order, h->prm.m1_shift);
       rc < 0) {
+    delete h;
+    return rc;
+  }
+  if (const int rc = check_m1_prec(h->prm.m1_prec, h->nvec); rc < 0) {
     delete h;
     return rc;
   }
@@ -1252,6 +1267,7 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   if (!h || !p) return fail(DWF_ERR_ARG, "null argument to hdcg_set_params");
   HDCG_TRY(check_solve_params(p->coarse_prec, p->irs_prec, p->phi_prec));
   HDCG_TRY(m1_check_params(p->ldop_m1, p->m1_lo, p->m1_hi, p->m1_order, p->m1_shift));
+  HDCG_TRY(check_m1_prec(p->m1_prec, h->nvec));
   if (p->n_irs < 0 || p->coarse_maxiter < 1 || p->inner_maxiter < 1 || p->outer_maxiter < 1 ||
       !(p->coarse_tol > 0.0) || !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
     return fail(DWF_ERR_ARG, "hdcg_set_params: iteration caps must be positive, tolerances in (0, 1)");
@@ -1274,6 +1290,8 @@ int hdcg_set_params(hdcg_t h, const struct hdcg_params* p, void* stream) {
   h->prm.ldop_defl = p->ldop_defl;
   h->prm.phi_prec = p->phi_prec;
   if (p->m1_shift != h->prm.m1_shift) trunc_invalidate(h);
+  if (p->m1_prec != h->prm.m1_prec) h->m1_hi_est = 0.0;  // estimated on the other storage
+  h->prm.m1_prec = p->m1_prec;
   h->prm.ldop_m1 = p->ldop_m1;
   h->prm.m1_lo = p->m1_lo;
   h->prm.m1_hi = p->m1_hi;

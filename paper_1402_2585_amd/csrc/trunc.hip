@@ -37,16 +37,7 @@ namespace hdk {
 
 namespace {
 
-constexpr int kTS = 9;  // one-hop stencil points
-
-// stencil index l = sum_mu (d_mu + 1) 3^mu of point m: m = 0 the site,
-// m = 2 mu + 1 and 2 mu + 2 the neighbours at -1 and +1 in direction mu
-__host__ __device__ inline int one_hop_l(int m) {
-  if (m == 0) return 40;
-  const int mu = (m - 1) >> 1;
-  const int p3 = mu == 0 ? 1 : mu == 1 ? 3 : mu == 2 ? 9 : 27;
-  return (m & 1) ? 40 - p3 : 40 + p3;
-}
+constexpr int kTS = kOneHop;
 
 template <typename R>
 __global__ void k_trunc_build(cplx<R>* __restrict__ TT, const c128* __restrict__ A, int Nc, int nvec, double shift) {
@@ -171,6 +162,22 @@ __global__ void k_cheb_first(cplx<R>* __restrict__ d1, cplx<R>* __restrict__ y, 
   }
 }
 
+// res -= tw, dnext = ca res + cb dcur, y += dnext (the updates of
+// k_cheb_step after a separate mat-vec tw = Q_trunc dcur)
+template <typename R>
+__global__ void k_cheb_update(const cplx<R>* __restrict__ tw, cplx<R>* __restrict__ res,
+                              const cplx<R>* __restrict__ dcur, cplx<R>* __restrict__ dnext, cplx<R>* __restrict__ y,
+                              size_t total, double ca, double cb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const cplx<R> t = tw[i], rv = res[i], dv = dcur[i], yv = y[i];
+  const double rre = (double)rv.re - t.re, rim = (double)rv.im - t.im;
+  const double dre = ca * rre + cb * dv.re, dim = ca * rim + cb * dv.im;
+  res[i] = cmk((R)rre, (R)rim);
+  dnext[i] = cmk((R)dre, (R)dim);
+  y[i] = cmk((R)(yv.re + dre), (R)(yv.im + dim));
+}
+
 template <typename R>
 DevBuf& tt_buf(hdcg* h) {
   return sizeof(R) == 8 ? h->TT128 : h->TT64;
@@ -181,11 +188,15 @@ double& tt_shift(hdcg* h) {
 }
 
 // TT (in R) and the neighbour table for the current shift
+// the 16-bit storage of Q_trunc in use for complex64 vectors (0: complex64)
+template <typename R>
+int trunc16_prec(hdcg* h) {
+  return sizeof(R) == 4 && (h->prm.m1_prec == DWF_BF16 || h->prm.m1_prec == DWF_F16) ? h->prm.m1_prec : 0;
+}
+
 template <typename R>
 int trunc_ensure(hdcg* h, hipStream_t st) {
   const double shift = h->prm.m1_shift;
-  DevBuf& TT = tt_buf<R>(h);
-  if (TT.bytes != 0 && tt_shift<R>(h) == shift) return DWF_OK;
   if (h->A128.bytes == 0) return fail(DWF_ERR_ARG, "the truncated operator needs the little Dirac operator");
   if (h->nbr9.bytes == 0) {
     HDCG_TRY(h->nbr9.ensure(sizeof(int) * (size_t)h->Nc * kTS));
@@ -193,6 +204,12 @@ int trunc_ensure(hdcg* h, hipStream_t st) {
     hipLaunchKernelGGL(k_nbr9, dim3((n + 255) / 256), dim3(256), 0, st, h->nbr9.as<int>(), h->nbr.as<int>(), h->Nc);
     HDCG_HIP(hipGetLastError());
   }
+  if (const int p16 = trunc16_prec<R>(h)) {
+    if ((p16 == DWF_BF16 ? h->tq_shift_bf16 : h->tq_shift_f16) == shift) return DWF_OK;
+    return trunc16_build(h, p16, shift, st);
+  }
+  DevBuf& TT = tt_buf<R>(h);
+  if (TT.bytes != 0 && tt_shift<R>(h) == shift) return DWF_OK;
   const size_t total = (size_t)h->Nc * kTS * h->nvec * h->nvec;
   HDCG_TRY(TT.ensure(sizeof(cplx<R>) * total));
   const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 65536);
@@ -207,6 +224,9 @@ constexpr int kMaxOrder = 256;
 
 template <typename R>
 int trunc_launch(hdcg* h, const cplx<R>* in, cplx<R>* out, int nr, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    if (const int p16 = trunc16_prec<R>(h)) return trunc16_apply(h, p16, in, out, nr, st);
+  }
   if (nr == 1 && h->nvec <= kStageNvec) {
     hipLaunchKernelGGL((k_trunc_apply1<R, 16>), dim3(h->Nc), dim3(kCT), 0, st, tt_buf<R>(h).template as<cplx<R>>(),
                        h->nbr9.as<int>(), in, out, h->Nc, h->nvec);
@@ -236,6 +256,13 @@ int cheb_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, double lo, doubl
   double omega = 2.0;
   for (int k = 1; k < h->prm.m1_order; ++k) {
     omega = 1.0 / (1.0 - omega / (4.0 * sigma * sigma));
+    if (trunc16_prec<R>(h)) {  // the 16-bit mat-vec, then the site-local updates
+      HDCG_TRY(trunc_launch<R>(h, dl[(k - 1) & 1], tw, nr, st));
+      hipLaunchKernelGGL((k_cheb_update<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tw, u, dl[(k - 1) & 1],
+                         dl[k & 1], y, n, omega / d, omega - 1.0);
+      HDCG_HIP(hipGetLastError());
+      continue;
+    }
     if (h->nvec <= kStageNvec) {
       const cplx<R>* TTp = tt_buf<R>(h).template as<cplx<R>>();
       if (nr == 1)
@@ -292,6 +319,7 @@ int mirs_run(hdcg* h, cplx<R>* y, cplx<R>* u, int nr, bool acc, hipStream_t st) 
 
 void trunc_invalidate(hdcg* h) {
   h->tt_shift64 = h->tt_shift128 = std::nan("");
+  h->tq_shift_bf16 = h->tq_shift_f16 = std::nan("");
   h->m1_hi_est = 0.0;
 }
 

@@ -58,7 +58,7 @@ def test_param_struct_layout_matches_the_library():
                 verbose=0, irs_prec=hd.DWF_C64, subspace_gen=0, rat_lo=3e-4, rat_eps=1e-4, rat_tol=1e-6,
                 rat_maxiter=10000, wall_noise=0, ldop_defl=1, phi_prec=hd.DWF_C64, ldop_m1=0, m1_lo=0.5,
                 m1_hi=0.0, m1_order=16, m1_shift=0.0, surface_depth=0, coarse_persistent=1, graph=1,
-                phase_timing=0, mfma_tile=-1, seed=1, keep_subspace_fp64=1)
+                phase_timing=0, mfma_tile=-1, seed=1, keep_subspace_fp64=1, m1_prec=hd.DWF_C64)
     got = {k: getattr(p, k) for k in want}
     assert got == want
 

@@ -206,6 +206,59 @@ def test_mfma_tile_candidates_and_autotuner(shape):
             print(f"nrhs {nr} prec {prec}: tile {tile}, ms {[round(m, 4) for m in ms]}", flush=True)
 
 
+def test_truncated_operator_16bit_on_seeded_operator(shape):
+    """Q_trunc + 0.3 (Sec. V.B) in complex64 and in the 16-bit MFMA storage
+    (m1_prec bf16 / fp16: nine matrices per site, per-matrix scales) on 1, 3
+    and 16 right-hand sides against the oracle's truncated operator
+    (complex64 2e-5, bf16 1e-2, fp16 2e-3, as the 81-point mat-vec); the
+    Chebyshev polynomial of order 6 on [0.5, Gershgorin bound] and 6
+    iterations of the truncated CG with each storage against the oracle's
+    (complex64 1e-4, bf16 3e-2, fp16 5e-3)."""
+    from oracle import ldop as oldop
+
+    t = shape
+    banner(f"16-bit truncated operator {t['name']}")
+    h = t["h"]
+    A = synth.coarse_stencil_operator(t["C"], h.nvec, 450)
+    hd.hdcg_import_coarse(h.h, torch.from_numpy(A).to("cuda"))
+    shift = 0.3
+    T = oldop.truncate(A, shift)
+    # an upper bound of the spectrum of the Hermitian T: the largest absolute row sum
+    rows = np.zeros((h.Nc, h.nvec))
+    for l in oldop.one_hop_points():
+        rows += np.abs(T[:, l]).sum(axis=2)
+    hi = float(rows.max())
+    tols = {hd.DWF_C64: (2e-5, 1e-4), hd.DWF_BF16: (1e-2, 3e-2), hd.DWF_F16: (2e-3, 5e-3)}
+    try:
+        for mp, (tol_mv, tol_pre) in tols.items():
+            h.set_params(m1_prec=mp, m1_shift=shift, m1_lo=0.5, m1_hi=hi, m1_order=6)
+            for nr in (1, 3, 16):
+                c = synth.gaussian_coarse(h.Nc, h.nvec, 451 + nr, nr)
+                want = ocrs.apply(T, c, t["C"])
+                inp = torch.from_numpy(c).to("cuda", torch.complex64).contiguous()
+                out = torch.zeros_like(inp)
+                hd.hdcg_trunc_apply(h.h, out, inp, hd.DWF_C64, nr)
+                err = rel_err(out.cpu().numpy(), want)
+                print(f"Q_trunc m1_prec {mp} nrhs {nr}: rel err {err:.2e}", flush=True)
+                assert err < tol_mv, (mp, nr)
+            r = synth.gaussian_coarse(h.Nc, h.nvec, 460, 3)
+            inp = torch.from_numpy(r).to("cuda", torch.complex64).contiguous()
+            want = np.array([oldop.chebyshev_inverse(lambda u: ocrs.apply(T, u, t["C"]), ri, 0.5, hi, 6) for ri in r])
+            y = torch.zeros_like(inp)
+            hd.hdcg_chebyshev(h.h, y, inp, hd.DWF_C64, 3)
+            err = rel_err(y.cpu().numpy(), want)
+            print(f"Chebyshev order 6, m1_prec {mp}: rel err {err:.2e}", flush=True)
+            assert err < tol_pre, mp
+            want = np.array([oldop.trunc_cg(T, t["C"], ri, 6) for ri in r])
+            y = torch.zeros_like(inp)
+            hd.hdcg_trunc_cg(h.h, y, inp, hd.DWF_C64, 3)
+            err = rel_err(y.cpu().numpy(), want)
+            print(f"truncated CG 6 iterations, m1_prec {mp}: rel err {err:.2e}", flush=True)
+            assert err < tol_pre, mp
+    finally:
+        h.set_params(m1_prec=hd.DWF_C64, m1_shift=0.0, m1_hi=0.0, m1_order=16)
+
+
 def test_coarse_solves_on_seeded_operator(shape):
     """Coarse CG (complex64 VALU and bf16 / fp16 MFMA storage) on a seeded
     operator against a dense solve: one right-hand side, and 5 and 16 at once

@@ -522,8 +522,29 @@ def test_truncated_cg_mirs_and_adef1_against_oracle(two_level):
         assert rcs == 0 and st["converged"] == 1
         rf = bf - ref.H(op.to_canonical(xf).cpu().numpy())
         assert np.sqrt(np.vdot(rf, rf).real / np.vdot(bf, bf).real) <= 1e-8
+        if nvec % 4 == 0:
+            # the 16-bit Q_trunc in both preconditioners: the flexible coarse
+            # solve still reaches the dense solution, and a solve with 16-bit A
+            # and 16-bit Q_trunc reaches 1e-8 under the oracle's H
+            for m1 in (1, 2):
+                h.set_params(ldop_m1=m1, m1_prec=hd.DWF_BF16, m1_hi=0.0)
+                x = h.new_coarse(hd.DWF_C64, 3)
+                rc, it = hd.hdcg_coarse_solve(h.h, x, torch.from_numpy(b).to(torch.complex64).to("cuda"), hd.DWF_C64,
+                                              3, 1e-5, 2000)
+                err = rel_err(x.cpu().numpy(), xd)
+                print(f"ADEF1 (ldop_m1 {m1}) with bf16 Q_trunc, complex64, 3 rhs: {it} iterations, rel err {err:.2e}",
+                      flush=True)
+                assert rc == 0 and err < 1e-3
+            h.set_params(coarse_prec=hd.DWF_BF16)
+            xf = op.new_field()
+            rcs, st = hd.hdcg_solve(h.h, xf, op.to_native(bf), 1, 1e-8)
+            print("hdcg_solve, bf16 A and bf16 Q_trunc", st, flush=True)
+            assert rcs == 0 and st["converged"] == 1
+            rf = bf - ref.H(op.to_canonical(xf).cpu().numpy())
+            assert np.sqrt(np.vdot(rf, rf).real / np.vdot(bf, bf).real) <= 1e-8
     finally:
-        h.set_params(ldop_m1=0, ldop_defl=0, m1_shift=0.0, m1_hi=0.0, m1_order=16)
+        h.set_params(ldop_m1=0, ldop_defl=0, m1_shift=0.0, m1_hi=0.0, m1_order=16, m1_prec=hd.DWF_C64,
+                     coarse_prec=hd.DWF_C64)
 
 
 def test_ldop_deflation_cuts_coarse_iterations():
