@@ -273,12 +273,17 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     # the last two: the coarse solves by ADEF1 with the Chebyshev inverse of
     # the one-hop truncated operator (Sec. V.B; Table "optimised" uses order
     # 16), interval [0.5, 1.05 x estimated largest eigenvalue]
-    for name, iprec, pprec, m1, order in (
-            ("c64_mirs", hd.DWF_C64, hd.DWF_C64, 0, 16), ("bf16_mirs", hd.DWF_BF16, hd.DWF_C64, 0, 16),
-            ("bf16_mirs_bf16_subspace", hd.DWF_BF16, hd.DWF_BF16, 0, 16),
-            ("bf16_mirs_bf16_subspace_adef1_cheb16", hd.DWF_BF16, hd.DWF_BF16, 1, 16),
-            ("bf16_mirs_bf16_subspace_adef1_cheb8", hd.DWF_BF16, hd.DWF_BF16, 1, 8)):
-        h.set_params(irs_prec=iprec, ldop_defl=1, phi_prec=pprec, ldop_m1=m1, m1_order=order)
+    # (ldop_m1 = 2: M_IRS(Q_trunc), 8 CG iterations; m1_prec: storage of Q_trunc)
+    for name, iprec, pprec, m1, order, m1p in (
+            ("c64_mirs", hd.DWF_C64, hd.DWF_C64, 0, 16, hd.DWF_C64),
+            ("bf16_mirs", hd.DWF_BF16, hd.DWF_C64, 0, 16, hd.DWF_C64),
+            ("bf16_mirs_bf16_subspace", hd.DWF_BF16, hd.DWF_BF16, 0, 16, hd.DWF_C64),
+            ("bf16_mirs_bf16_subspace_adef1_cheb16", hd.DWF_BF16, hd.DWF_BF16, 1, 16, hd.DWF_C64),
+            ("bf16_mirs_bf16_subspace_adef1_cheb8", hd.DWF_BF16, hd.DWF_BF16, 1, 8, hd.DWF_C64),
+            ("bf16_mirs_bf16_subspace_adef1_cheb8_bf16_qtrunc", hd.DWF_BF16, hd.DWF_BF16, 1, 8, hd.DWF_BF16),
+            ("bf16_mirs_bf16_subspace_adef1_trunc_cg8", hd.DWF_BF16, hd.DWF_BF16, 2, 8, hd.DWF_C64),
+            ("bf16_mirs_bf16_subspace_adef1_trunc_cg8_bf16_qtrunc", hd.DWF_BF16, hd.DWF_BF16, 2, 8, hd.DWF_BF16)):
+        h.set_params(irs_prec=iprec, ldop_defl=1, phi_prec=pprec, ldop_m1=m1, m1_order=order, m1_prec=m1p)
         x5 = op.new_field(zero=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

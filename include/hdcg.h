@@ -102,7 +102,7 @@ int dwf_destroy(dwf_op_t op);
 
 /* Launch shape of the hop kernel (the workgroup tiling of the Wilson hop
  * stages; the operator is the same for every shape, to rounding order):
- * shape = {bx, by, bz, bt, remap, lds_kb, nt, morton, phases}.
+ * shape = {bx, by, bz, bt, remap, lds_kb, nt, morton, phases, rg}.
  *   bx..bt  site block of one workgroup in (x/2, y, z, t), powers of two
  *           (all 0: consecutive checkerboard sites); a block that does not
  *           divide the lattice or exceeds 256 threads falls back to 0;
@@ -119,8 +119,11 @@ int dwf_destroy(dwf_op_t op);
  *           on the first launch outside graph capture (host memory and
  *           4 bytes of device memory per workgroup, kept until dwf_destroy);
  *   phases  2 or 4 neighbour-load phases per stage (0: 4 for complex128,
- *           2 for complex64 and 16-bit fields).
- * By default the block, remap and order entries are chosen by the library's
+ *           2 for complex64 and 16-bit fields);
+ *   rg      right-hand sides one workgroup applies the stage to, one after
+ *           another on the links it staged once (1..64; a call with fewer
+ *           right-hand sides uses that many).
+ * By default the block, remap, order and rg entries are chosen by the library's
  * autotuner: the first application of H for a field storage (complex128,
  * complex64, 16-bit) and for one or several right-hand sides times each
  * candidate block / order on that call's own operands (one warm-up, best of
@@ -129,14 +132,14 @@ int dwf_destroy(dwf_op_t op);
  * {lds_kb 0, nt 0, phases 0}.  This call fixes a shape instead
  * (launch-shape sweeps and their tests); shape[0] = -1 returns to the
  * autotuned shapes.  DWF_ERR_ARG on an invalid entry. */
-int dwf_set_hop_shape(dwf_op_t op, const int shape[9]);
+int dwf_set_hop_shape(dwf_op_t op, const int shape[10]);
 
 /* The hop launch shape in use for (prec DWF_C128 / DWF_C64 / DWF_BF16,
- * nrhs = 1 or more): shape[9] as dwf_set_hop_shape takes it; ms (nullable,
+ * nrhs = 1 or more): shape[10] as dwf_set_hop_shape takes it; ms (nullable,
  * *ncand entries) the autotuner's milliseconds per H of each candidate, -1
  * before it has run.  Returns 1 (and the current shape) when the autotuner
  * has not run yet for that storage and count. */
-int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, int* ncand);
+int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[10], float* ms, int* ncand);
 
 /* Free the operator's work fields (the intermediate half-fields of M_pc
  * and the fields of cg_solve, cg_solve_mixed and dwf_multishift_cg, sized

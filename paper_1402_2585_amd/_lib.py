@@ -197,9 +197,9 @@ def dwf_destroy(op):
 
 
 def dwf_get_hop_shape(op, prec, nrhs=1):
-    """(shape (9 ints), ms per candidate (-1: not tuned yet), tuned flag)."""
-    sh = (C.c_int * 9)()
-    ms = (C.c_float * 16)()
+    """(shape (10 ints), ms per candidate (-1: not tuned or not tried), tuned flag)."""
+    sh = (C.c_int * 10)()
+    ms = (C.c_float * 32)()
     n = C.c_int()
     rc = _check(load().dwf_get_hop_shape(op, int(prec), int(nrhs), sh, ms, C.byref(n)), allow_soft=True)
     return tuple(sh), list(ms[:n.value]), rc == 0
@@ -210,8 +210,10 @@ def dwf_release_workspace(op):
 
 
 def dwf_set_hop_shape(op, shape):
-    """shape: 9 ints (bx, by, bz, bt, remap, lds_kb, nt, morton, phases)."""
-    a = (C.c_int * 9)(*[int(v) for v in shape])
+    """shape: 10 ints (bx, by, bz, bt, remap, lds_kb, nt, morton, phases, rg);
+    9 take rg = 1."""
+    v = [int(x) for x in shape] + ([1] if len(shape) == 9 else [])
+    a = (C.c_int * 10)(*v)
     _check(load().dwf_set_hop_shape(op, a))
 
 

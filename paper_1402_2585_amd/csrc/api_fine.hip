@@ -387,7 +387,7 @@ int dwf_create_mobius(dwf_op_t* out, const int dims[4], int Ls, double M5, doubl
   return DWF_OK;
 }
 
-int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
+int dwf_set_hop_shape(dwf_op_t op, const int shape[10]) {
   if (!op || !shape) return fail(DWF_ERR_ARG, "null argument to dwf_set_hop_shape");
   if (shape[0] == -1) {  // back to the autotuned shapes
     op->hop_autotune = 1;
@@ -398,19 +398,21 @@ int dwf_set_hop_shape(dwf_op_t op, const int shape[9]) {
   const bool linear = b[0] == 0 && b[1] == 0 && b[2] == 0 && b[3] == 0;
   if (!linear && !(pow2(b[0]) && pow2(b[1]) && pow2(b[2]) && pow2(b[3])))
     return fail(DWF_ERR_ARG, "dwf_set_hop_shape: block extents must be powers of two (or all 0)");
-  if (b[5] < 0 || b[5] > 150 || (b[8] != 0 && b[8] != 2 && b[8] != 4) || b[7] < 0 || b[7] > 4)
-    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: lds_kb must be in 0..150, order 0..4 and phases 0, 2 or 4");
+  if (b[5] < 0 || b[5] > 150 || (b[8] != 0 && b[8] != 2 && b[8] != 4) || b[7] < 0 || b[7] > 4 || b[9] < 1 || b[9] > 64)
+    return fail(DWF_ERR_ARG, "dwf_set_hop_shape: lds_kb must be in 0..150, order 0..4, phases 0, 2 or 4 and "
+                             "rhs per workgroup 1..64");
   for (int i = 0; i < 4; ++i) op->tune.block[i] = b[i];
   op->tune.remap = b[4] != 0;
   op->tune.lds_kb = b[5];
   op->tune.nt = b[6] & 1;
   op->tune.morton = b[7];
   op->tune.phases = b[8];
+  op->tune.rg = b[9];
   op->hop_autotune = 0;
   return DWF_OK;
 }
 
-int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, int* ncand) {
+int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[10], float* ms, int* ncand) {
   if (!op || !shape || nrhs < 1) return fail(DWF_ERR_ARG, "bad arguments to dwf_get_hop_shape");
   if (prec != DWF_C128 && prec != DWF_C64 && prec != DWF_BF16) return fail(DWF_ERR_ARG, "bad precision");
   const int pi = prec == DWF_C128 ? 0 : (prec == DWF_BF16 ? 2 : 1), ri = nrhs > 1;
@@ -419,14 +421,16 @@ int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[9], float* ms, 
   if (ncand) *ncand = n;
   if (ms)
     for (int i = 0; i < n; ++i) ms[i] = c >= 0 ? op->hop_ms[pi][ri][i] : -1.f;
-  int cand[6];
-  if (op->hop_autotune && c >= 0) hop_shape_of(c, cand);
-  for (int i = 0; i < 4; ++i) shape[i] = op->hop_autotune && c >= 0 ? cand[i] : op->tune.block[i];
-  shape[4] = op->hop_autotune && c >= 0 ? cand[4] : op->tune.remap;
+  int cand[7];
+  const bool tuned = op->hop_autotune && c >= 0;
+  if (tuned) hop_shape_of(c, cand);
+  for (int i = 0; i < 4; ++i) shape[i] = tuned ? cand[i] : op->tune.block[i];
+  shape[4] = tuned ? cand[4] : op->tune.remap;
   shape[5] = op->tune.lds_kb;
   shape[6] = op->tune.nt;
-  shape[7] = op->hop_autotune && c >= 0 ? cand[5] : op->tune.morton;
+  shape[7] = tuned ? cand[5] : op->tune.morton;
   shape[8] = op->tune.phases;
+  shape[9] = tuned ? cand[6] : op->tune.rg;
   return op->hop_autotune && c < 0 ? 1 : DWF_OK;
 }
 

@@ -70,13 +70,14 @@ struct dwf_op {
                                   // grids), 2-4 per-XCD regions from a table
     int phases = 0;               // neighbour-load phases per stage (2 or 4; 0: 4 for complex128,
                                   // 2 for the FP32 kernels, whose spinors take half the registers)
+    int rg = 1;                   // right-hand sides per workgroup (sharing the links staged in LDS)
   } tune;
   // launch-shape autotuner: the candidate chosen per (field storage c128 /
   // c64 / 16-bit, one / several right-hand sides), -1 before it has run;
   // off after dwf_set_hop_shape fixes a shape
   int hop_autotune = 1;
   int hop_choice[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
-  float hop_ms[3][2][16] = {};  // measured ms per H of each candidate
+  float hop_ms[3][2][24] = {};  // measured ms per H of each candidate (-1: not tried)
   // workgroup -> site-block tables of the region orders, one per
   // (bx, by, bz, bt, order); built on first use outside graph capture, kept
   // until the operator is destroyed (a launch in flight may still read one)
@@ -145,9 +146,9 @@ int launch_convert16(dwf_op* op, bf16c* dst, const c64* src, int nrhs, hipStream
 int launch_convert16(dwf_op* op, c64* dst, const bf16c* src, int nrhs, hipStream_t stream);
 
 // the hop launch-shape candidates of the autotuner: their number, and
-// candidate c as {bx, by, bz, bt, remap, order}
+// candidate c as {bx, by, bz, bt, remap, order, rhs per workgroup}
 int hop_shape_candidates();
-void hop_shape_of(int c, int shape[6]);
+void hop_shape_of(int c, int shape[7]);
 
 int ensure_tmp(dwf_op* op, int prec, int nrhs);
 void release_tmp(dwf_op* op);  // drop the operator's work fields (regrown on demand)

@@ -308,6 +308,9 @@ struct HopArgs {
   int morton;         // Morton (bit-interleaved) order of the block grid (power-of-two grids)
   int nbt;            // block-grid extent in t
   const int* order;   // nullable: block of workgroup blockIdx.x, packed gx | gy << 8 | gz << 16 | gt << 24
+  int rg;             // right-hand sides per workgroup (blockIdx.y takes rg of the nrhs)
+  int nrhs;
+  int epi_off;        // byte offset of the epilogue's LDS buffer (0: it reuses the link rows)
   size_t field;       // complex elements per rhs
   // fifth dimension: M_5 = alpha + beta K, recurrence of M_5^-1 y_s = ia x_s + kap y_{s-1},
   // Mobius C_5 = b5 + c5 K (K: P+ from s-1, P- from s+1, -mass at the wrap)
@@ -640,25 +643,30 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
   const int Ls = LS > 0 ? LS : g.Ls;  // compile-time when LS > 0: immediate load offsets
   // a table order already places each workgroup on its XCD's region
   const int wg = (A.remap && !A.order) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int rhs = blockIdx.y;
+  const int rhs0 = blockIdx.y * A.rg;
+  const int nr = min(A.rg, A.nrhs - rhs0);
   const int tid = threadIdx.x;
   const int vloc = tid / Ls, s = tid - vloc * Ls;
   Site c;
   const int v = hop_site(A, wg, vloc, c);
   const bool active = (vloc < A.spw) && (v < g.Vh);
 
-  in += rhs * A.field;
-  out += rhs * A.field;
-
   cplx<R>* links = reinterpret_cast<cplx<R>*>(smem_raw);  // [spw][kLinkLd]
-  // The site's 72 link entries, entry e by thread s = e mod Ls.  With Ls
-  // fixed at compile time every load is issued before the first neighbour
-  // loads and written to LDS after them, so the wave waits for memory once
-  // instead of once per entry.
+  constexpr int ND = 8 / NPH;
+  constexpr int SF = DAG ? 1 : -1;
   constexpr int NL = LS > 0 ? (72 + LS - 1) / LS : 1;
-  cplx<R> lk[NL];
+  const size_t col = (size_t)12 * Ls;
+  // Mobius: the first stage of M_pc hops C_5 in (C_5 on the neighbours' columns)
+  constexpr bool C5IN = MOB && !DAG && EPI == EPI_INV;
+  int nb[8];
+  cplx<R> psi[ND][12];
+  // The site's 72 link entries, entry e by thread s = e mod Ls.  With Ls
+  // fixed at compile time they are loaded before the first right-hand
+  // side's first-phase neighbour loads are issued and written to LDS after
+  // them, so the wave waits for memory once instead of once per entry.
   if (active) {
     const cplx<R>* G = gauge + (size_t)v * 72;
+    cplx<R> lk[NL];
     if constexpr (LS > 0) {
       // (the last entries of the short threads re-read entry 71: no branch)
 #pragma unroll
@@ -666,58 +674,64 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
     } else {
       for (int e = s; e < 72; e += Ls) links[vloc * kLinkLd + e] = G[e];
     }
-  }
-
-  constexpr int ND = 8 / NPH;
-  constexpr int SF = DAG ? 1 : -1;
-  const size_t col = (size_t)12 * Ls;
-  int nb[8];
-  cplx<R> psi[ND][12];
-  // Mobius: the first stage of M_pc hops C_5 in (C_5 on the neighbours' columns)
-  constexpr bool C5IN = MOB && !DAG && EPI == EPI_INV;
-  if (active) {
     hop_neighbours(g, c, nb);
     if (C5IN)
-      load_dirs_c5<T, 0, ND>(psi, in, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
+      load_dirs_c5<T, 0, ND>(psi, in + rhs0 * A.field, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
     else
-      load_dirs<T, 0, ND>(psi, in, nb, col, s, Ls);
+      load_dirs<T, 0, ND>(psi, in + rhs0 * A.field, nb, col, s, Ls);
     if constexpr (LS > 0) {
 #pragma unroll
       for (int k = 0; k < NL; ++k)
         if (s + k * LS < 72) links[vloc * kLinkLd + s + k * LS] = lk[k];
     }
   }
-  __syncthreads();  // links in LDS
+  // The workgroup's right-hand sides one after another, all on the links
+  // staged once (with several, the epilogue has an LDS buffer of its own).
+  for (int rr = 0; rr < nr; ++rr) {
+    const int rhs = rhs0 + rr;
+    const T* __restrict__ inr = in + rhs * A.field;
+    T* __restrict__ outr = out + rhs * A.field;
+    if (rr > 0 && active) {
+      if (C5IN)
+        load_dirs_c5<T, 0, ND>(psi, inr, nb, col, s, Ls, (R)A.b5, (R)A.c5, (R)A.mass);
+      else
+        load_dirs<T, 0, ND>(psi, inr, nb, col, s, Ls);
+    }
+    __syncthreads();  // links in LDS
 
-  cplx<R> acc[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = cmk((R)0, (R)0);
-  if (active) {
-    const cplx<R>* L = links + vloc * kLinkLd;
-    apply_dirs<R, 0, ND, SF>(acc, psi, L);
-    const R b5 = (R)A.b5, c5 = (R)A.c5, mm = (R)A.mass;
-    if (NPH >= 2) {
-      if (C5IN)
-        load_dirs_c5<T, ND % 8, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
-      else
-        load_dirs<T, ND % 8, ND>(psi, in, nb, col, s, Ls);
-      apply_dirs<R, ND % 8, ND, SF>(acc, psi, L);
+    cplx<R> acc[12];
+  #pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cmk((R)0, (R)0);
+    if (active) {
+      const cplx<R>* L = links + vloc * kLinkLd;
+      apply_dirs<R, 0, ND, SF>(acc, psi, L);
+      const R b5 = (R)A.b5, c5 = (R)A.c5, mm = (R)A.mass;
+      if (NPH >= 2) {
+        if (C5IN)
+          load_dirs_c5<T, ND % 8, ND>(psi, inr, nb, col, s, Ls, b5, c5, mm);
+        else
+          load_dirs<T, ND % 8, ND>(psi, inr, nb, col, s, Ls);
+        apply_dirs<R, ND % 8, ND, SF>(acc, psi, L);
+      }
+      if (NPH == 4) {
+        if (C5IN)
+          load_dirs_c5<T, 4, ND>(psi, inr, nb, col, s, Ls, b5, c5, mm);
+        else
+          load_dirs<T, 4, ND>(psi, inr, nb, col, s, Ls);
+        apply_dirs<R, 4, ND, SF>(acc, psi, L);
+        if (C5IN)
+          load_dirs_c5<T, 6, ND>(psi, inr, nb, col, s, Ls, b5, c5, mm);
+        else
+          load_dirs<T, 6, ND>(psi, inr, nb, col, s, Ls);
+        apply_dirs<R, 6, ND, SF>(acc, psi, L);
+      }
     }
-    if (NPH == 4) {
-      if (C5IN)
-        load_dirs_c5<T, 4, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
-      else
-        load_dirs<T, 4, ND>(psi, in, nb, col, s, Ls);
-      apply_dirs<R, 4, ND, SF>(acc, psi, L);
-      if (C5IN)
-        load_dirs_c5<T, 6, ND>(psi, in, nb, col, s, Ls, b5, c5, mm);
-      else
-        load_dirs<T, 6, ND>(psi, in, nb, col, s, Ls);
-      apply_dirs<R, 6, ND, SF>(acc, psi, L);
-    }
+    // the epilogue's LDS buffer reuses the link rows (one right-hand side per
+    // workgroup) or the previous right-hand side's buffer
+    if (EPI == EPI_INV || (MOB && DAG)) __syncthreads();
+    hop_epilogue<R, DAG, EPI, LS, MOB, T>(acc, active, vloc, s, v, wg, rhs, outr, center, pw, A,
+                                          smem_raw + A.epi_off);
   }
-  if (EPI == EPI_INV || (MOB && DAG)) __syncthreads();  // the epilogue's LDS buffer reuses the link rows
-  hop_epilogue<R, DAG, EPI, LS, MOB, T>(acc, active, vloc, s, v, wg, rhs, out, center, pw, A, smem_raw);
 }
 
 // ------------------------------------------------------------------ BLAS ---
@@ -980,6 +994,8 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
   A.morton = 0;
   A.nbt = 1;
   A.order = nullptr;
+  A.nrhs = nrhs;
+  A.rg = std::max(1, std::min(op->tune.rg, nrhs));
   {
     const int* b = op->tune.block;
     auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };
@@ -1033,9 +1049,17 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
   const cplx<R>* G = reinterpret_cast<const cplx<R>*>(dbl ? op->gauge128.ptr : op->gauge64.ptr) +
                      (size_t)out_parity * g.Vh * 72;
   const R* pw = reinterpret_cast<const R*>(dbl ? op->pw128.ptr : op->pw64.ptr);
-  dim3 grid(nwg, nrhs), block(threads);
-  size_t lds = (epi == EPI_INV || (mob && dagger)) ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
-  lds = std::max(lds, (size_t)A.spw * kLinkLd * sizeof(cplx<R>));
+  dim3 grid(nwg, (nrhs + A.rg - 1) / A.rg), block(threads);
+  const size_t epi_lds = (epi == EPI_INV || (mob && dagger)) ? (size_t)A.spw * 12 * (g.Ls + 1) * sizeof(cplx<R>) : 0;
+  const size_t link_lds = (size_t)A.spw * kLinkLd * sizeof(cplx<R>);
+  size_t lds;
+  if (A.rg > 1 && epi_lds > 0) {  // separate regions: the links stay for the next right-hand side
+    A.epi_off = (int)((link_lds + 15) / 16 * 16);
+    lds = A.epi_off + epi_lds;
+  } else {
+    A.epi_off = 0;
+    lds = std::max(epi_lds, link_lds);
+  }
   // optional LDS request that caps the resident workgroups per CU
   if ((size_t)op->tune.lds_kb * 1024 > lds) lds = (size_t)op->tune.lds_kb * 1024;
   // directions whose neighbour loads are in flight together: 8 / phases
@@ -1089,26 +1113,30 @@ struct HopShape {
   int block[4];
   int remap;
   int order;  // 1 Morton (index formula), 2-4 region tables
+  int rg;     // right-hand sides per workgroup (candidates with rg > 1 are tried only for several)
 };
-constexpr HopShape kHopShapes[] = {{{2, 2, 1, 1}, 1, 1}, {{2, 2, 1, 1}, 0, 1}, {{2, 2, 2, 2}, 1, 1},
-                                   {{2, 2, 2, 2}, 0, 1}, {{4, 2, 1, 1}, 1, 1}, {{1, 2, 2, 1}, 1, 1},
-                                   {{2, 2, 1, 1}, 1, 2}, {{1, 2, 2, 1}, 1, 2}, {{2, 2, 1, 1}, 1, 3},
-                                   {{2, 2, 2, 2}, 1, 2}, {{2, 2, 1, 1}, 1, 4}, {{1, 2, 2, 1}, 1, 4},
-                                   {{2, 2, 2, 2}, 1, 4}};
+constexpr HopShape kHopShapes[] = {
+    {{2, 2, 1, 1}, 1, 1, 1},  {{2, 2, 1, 1}, 0, 1, 1},  {{2, 2, 2, 2}, 1, 1, 1}, {{2, 2, 2, 2}, 0, 1, 1},
+    {{4, 2, 1, 1}, 1, 1, 1},  {{1, 2, 2, 1}, 1, 1, 1},  {{2, 2, 1, 1}, 1, 2, 1}, {{1, 2, 2, 1}, 1, 2, 1},
+    {{2, 2, 1, 1}, 1, 3, 1},  {{2, 2, 2, 2}, 1, 2, 1},  {{2, 2, 1, 1}, 1, 4, 1}, {{1, 2, 2, 1}, 1, 4, 1},
+    {{2, 2, 2, 2}, 1, 4, 1},  {{2, 2, 1, 1}, 1, 4, 16}, {{2, 2, 1, 1}, 1, 1, 16}, {{1, 2, 2, 1}, 1, 4, 16},
+    {{2, 2, 1, 1}, 0, 0, 16}, {{2, 2, 1, 1}, 1, 4, 4}};
 constexpr int kNumHopShapes = sizeof(kHopShapes) / sizeof(kHopShapes[0]);
-static_assert(kNumHopShapes <= 16, "hop_ms holds 16 candidates");
+static_assert(kNumHopShapes <= 24, "hop_ms holds 24 candidates");
 
 int hop_shape_candidates() { return kNumHopShapes; }
-void hop_shape_of(int c, int shape[6]) {
+void hop_shape_of(int c, int shape[7]) {
   for (int i = 0; i < 4; ++i) shape[i] = kHopShapes[c].block[i];
   shape[4] = kHopShapes[c].remap;
   shape[5] = kHopShapes[c].order;
+  shape[6] = kHopShapes[c].rg;
 }
 
 static void apply_shape(dwf_op* op, int c) {
   for (int i = 0; i < 4; ++i) op->tune.block[i] = kHopShapes[c].block[i];
   op->tune.remap = kHopShapes[c].remap;
   op->tune.morton = kHopShapes[c].order;
+  op->tune.rg = kHopShapes[c].rg;
 }
 
 template <typename R, typename T>
@@ -1142,6 +1170,8 @@ static int select_shape(dwf_op* op, T* out, const T* in, int nrhs, hipStream_t s
     int rc = DWF_OK, best = 0;
     float bms = 0.f;
     for (int c = 0; c < kNumHopShapes && rc == DWF_OK; ++c) {
+      op->hop_ms[pi][ri][c] = -1.f;
+      if (kHopShapes[c].rg > 1 && nrhs == 1) continue;  // the same as its one-RHS form
       apply_shape(op, c);
       rc = apply_mpcdagmpc<R, T>(op, out, in, nrhs, st, nullptr);
       float m = 1e30f;

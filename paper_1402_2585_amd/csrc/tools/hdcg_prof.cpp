@@ -106,7 +106,7 @@ int main(int argc, char** argv) {
   }
   if (!std::strcmp(argv[1], "sweep")) {
     // hdcg_prof sweep X Y Z T Ls prec(c128|c64|bf16) reps shape1 shape2 ...
-    // (shape = "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]", see dwf_set_hop_shape)
+    // (shape = "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases,rg]", see dwf_set_hop_shape)
     int dims[4] = {std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5])};
     const int Ls = std::atoi(argv[6]);
     const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : (!std::strcmp(argv[7], "bf16") ? DWF_BF16 : DWF_C128);
@@ -122,9 +122,9 @@ int main(int argc, char** argv) {
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     for (int a = 9; a < argc; ++a) {
-      int shape[9] = {2, 2, 1, 1, 1, 0, 1, 1, 4};
-      if (std::sscanf(argv[a], "%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1], &shape[2], &shape[3], &shape[4],
-                      &shape[5], &shape[6], &shape[7], &shape[8]) < 4) {
+      int shape[10] = {2, 2, 1, 1, 1, 0, 0, 1, 0, 1};
+      if (std::sscanf(argv[a], "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1], &shape[2], &shape[3], &shape[4],
+                      &shape[5], &shape[6], &shape[7], &shape[8], &shape[9]) < 4) {
         std::fprintf(stderr, "bad shape %s\n", argv[a]);
         return 2;
       }
@@ -164,10 +164,11 @@ int main(int argc, char** argv) {
   const int prec = !std::strcmp(argv[7], "c64") ? DWF_C64 : (!std::strcmp(argv[7], "bf16") ? DWF_BF16 : DWF_C128);
   const int reps = std::atoi(argv[8]);
   const int nrhs = argc > 9 ? std::atoi(argv[9]) : 1;
-  // optional fixed launch shape "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases]" (else autotuned)
-  int shape[9] = {2, 2, 1, 1, 1, 0, 1, 1, 4};
-  const bool fixed = argc > 10 && std::sscanf(argv[10], "%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1], &shape[2],
-                                               &shape[3], &shape[4], &shape[5], &shape[6], &shape[7], &shape[8]) >= 4;
+  // optional fixed launch shape "bx,by,bz,bt[,remap,lds_kb,nt,morton,phases,rg]" (else autotuned)
+  int shape[10] = {2, 2, 1, 1, 1, 0, 0, 1, 0, 1};
+  const bool fixed = argc > 10 && std::sscanf(argv[10], "%d,%d,%d,%d,%d,%d,%d,%d,%d,%d", &shape[0], &shape[1],
+                                               &shape[2], &shape[3], &shape[4], &shape[5], &shape[6], &shape[7],
+                                               &shape[8], &shape[9]) >= 4;
   const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
   std::vector<double> U(V * 4 * 9 * 2, 0.0);
   for (size_t l = 0; l < V * 4; ++l)

@@ -5,6 +5,14 @@ notes under profiles/.
   python3 paper_1402_2585_amd/prof_summary.py trace <run_results.db> [--match S] [--grid N]
   python3 paper_1402_2585_amd/prof_summary.py pmc <run_results.db> [--match S] [--grid N]
   python3 paper_1402_2585_amd/prof_summary.py hop-json <dir> --out profiles/hop_kernel_16^4xLs16_pmc.json
+  python3 paper_1402_2585_amd/prof_summary.py solve <run_results.db> [--top N]
+
+`solve` summarises the solve phase of a traced `prof_driver.py --what hdcg`
+run: the dispatches after the last kernel that only the setup launches (the
+Gram, Cholesky, inverse-DFT, probe and second-level build kernels), their
+span from first start to last end, the time kernels were busy (the union of
+the dispatch intervals), and per kernel the workgroups x grid.y, calls, total
+and average time, largest total first.
 
 `trace` prints, per kernel name (optionally only names containing S and
 dispatches whose grid has N work-items in x), the dispatch count and the
@@ -94,6 +102,42 @@ def hop_json(dirs, out_path, root):
     return out
 
 
+SETUP_KERNELS = ("k_chol_inv", "k_gs_apply", "k_idft_dim", "k_probe", "k_philox_gaussian", "k_blockmap",
+                 "k_transpose", "k_phi_layout", "k_phi_bf16", "k_phi_surface", "k_free_vectors", "k_surface_zero",
+                 "k_gram", "k_expand", "k_frag", "k_scales", "k_rho")
+
+
+def solve_rows(db, setup_kernels=SETUP_KERNELS):
+    c = sqlite3.connect(db)
+    rows = list(c.execute("select name, start, end, grid_x, grid_y, workgroup_x from kernels order by start"))
+    last = -1
+    for i, (name, *_rest) in enumerate(rows):
+        if any(k in name for k in setup_kernels):
+            last = i
+    sol = rows[last + 1:]
+    if not sol:
+        return None
+    span = (max(r[2] for r in sol) - min(r[1] for r in sol)) / 1e6
+    busy, cur_s, cur_e = 0, None, None
+    for _, st, en, *_r in sol:
+        if cur_e is None or st > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+    busy += cur_e - cur_s
+    per = defaultdict(list)
+    shape = {}
+    for name, st, en, gx, gy, wx in sol:
+        per[name].append((en - st) / 1e3)
+        shape[name] = (gx // max(wx, 1), gy)
+    table = sorted(({"kernel": k, "workgroups": shape[k][0], "grid_y": shape[k][1], "calls": len(v),
+                     "total_ms": sum(v) / 1e3, "avg_us": sum(v) / len(v)} for k, v in per.items()),
+                   key=lambda r: -r["total_ms"])
+    return {"span_ms": span, "busy_ms": busy / 1e6, "dispatches": len(sol), "kernels": table}
+
+
 def short(name, n=110):
     name = name.replace("hdk::", "").replace("(anonymous namespace)::", "")
     i = name.find("(")
@@ -104,14 +148,29 @@ def short(name, n=110):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["trace", "pmc", "hop-json"])
+    ap.add_argument("what", choices=["trace", "pmc", "hop-json", "solve"])
     ap.add_argument("db", help="result database, or for hop-json the directory holding the runs "
                                "fetch_<tag>/, write_<tag>/ (tag c128, c64, bf16, copy), each with run_results.db")
     ap.add_argument("--out", default=None, help="hop-json: output path")
     ap.add_argument("--match", default=None)
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--json", action="store_true")
+    ap.add_argument("--top", type=int, default=25, help="solve: kernels listed")
     a = ap.parse_args()
+    if a.what == "solve":
+        r = solve_rows(a.db)
+        if r is None:
+            raise SystemExit("no dispatches after the setup")
+        if a.json:
+            print(json.dumps(r, indent=1))
+            return
+        print(f"Solve phase (after the setup's last kernel): span {r['span_ms']:.1f} ms, kernels busy "
+              f"{r['busy_ms']:.1f} ms, {r['dispatches']} dispatches.\n")
+        print("| kernel | workgroups x grid.y | calls | total ms | avg us |\n|---|---|---|---|---|")
+        for k in r["kernels"][:a.top]:
+            print(f"| `{short(k['kernel'])}` | {k['workgroups']} x {k['grid_y']} | {k['calls']} | "
+                  f"{k['total_ms']:.2f} | {k['avg_us']:.1f} |")
+        return
     if a.what == "hop-json":
         import os
 

@@ -310,6 +310,58 @@ def test_hop_region_orders_on_a_block_grid_of_odd_extents(order, block):
     lex.close()
 
 
+@pytest.mark.parametrize("mobius", [False, True])
+def test_hop_several_rhs_per_workgroup_bitwise(mobius):
+    """rg > 1: one workgroup applies a stage to several right-hand sides one
+    after another on the links it staged once.  H on 5 right-hand sides
+    (groups of 4 and 1, and of 5 with rg = 16) equals, bit for bit, the one
+    right-hand side per workgroup form in complex128, complex64 and 16-bit
+    storage (Shamir and Mobius: the adjoint Mobius stage has an LDS buffer of
+    its own then); M_IRS on 3 right-hand sides, whose CG takes (p, H p) from
+    the fused norms of the same stages, gives the same result in complex64
+    and 16-bit fields."""
+    dims, Ls, nr = (8, 8, 4, 8), 16, 5
+    banner(f"several RHS per workgroup, mobius={mobius}")
+    U = synth.gauge_field(dims, 0.7, 154)
+    kw = dict(b5=1.5, c5=0.5) if mobius else {}
+    ops = {rg: hd.FineOperator(U, dims, Ls, 1.8, 0.02, **kw) for rg in (1, 4, 16)}
+    for rg, o in ops.items():
+        hd.dwf_set_hop_shape(o.h, (2, 2, 1, 1, 1, 0, 0, 4, 0, rg))
+    b = synth.gaussian_half_field(dims, Ls, 155, nrhs=nr)
+    op1 = ops[1]
+    want = DWF(U, dims, Ls, 1.8, 0.02, **({"b": 1.5, "c": 0.5} if mobius else {})).H(b[2])
+    for prec in (hd.DWF_C128, hd.DWF_C64, hd.DWF_BF16):
+        x = _bf16_input(op1, b)[0] if prec == hd.DWF_BF16 else op1.to_native(b, prec)
+        ref = op1.H(x, prec, nrhs=nr)
+        for rg in (4, 16):
+            assert torch.equal(ops[rg].H(x, prec, nrhs=nr), ref), (prec, rg)
+        if prec == hd.DWF_C128:
+            got = op1.to_canonical(ref, nrhs=nr).cpu().numpy()[2]
+            assert rel_err(got, want) < 1e-12
+    for o in ops.values():
+        o.close()
+    # M_IRS on 3 right-hand sides (its CG takes (p, H p) from the fused norm
+    # of the stages), complex64 and 16-bit fields
+    dims = (12, 12, 12, 12)
+    U = synth.gauge_field(dims, 0.7, 156)
+    raw = synth.gaussian_half_field(dims, Ls, 157, nrhs=4)
+    r = synth.gaussian_half_field(dims, Ls, 158, nrhs=3)
+    outs = {}
+    for rg in (1, 4):
+        o = hd.FineOperator(U, dims, Ls, 1.8, 0.02, **kw)
+        hd.dwf_set_hop_shape(o.h, (2, 2, 1, 1, 1, 0, 0, 4, 0, rg))
+        h = hd.HDCG(o, (4, 4, 4, 4), raw)
+        for iprec in (hd.DWF_C64, hd.DWF_BF16):
+            h.set_params(irs_prec=iprec)
+            z = o.new_field(hd.DWF_C64, 3, zero=True)
+            hd.hdcg_mirs(h.h, z, o.to_native(r, hd.DWF_C64), 3)
+            outs[(rg, iprec)] = z
+        h.close()
+        o.close()
+    for iprec in (hd.DWF_C64, hd.DWF_BF16):
+        assert torch.equal(outs[(1, iprec)], outs[(4, iprec)]), iprec
+
+
 # Mobius (Cayley-form) kernel: (b5, c5) other than Shamir's (1, 0)
 MOBIUS = {
     "4^4xLs8-b1.5-c0.5": ((4, 4, 4, 4), 8, 1.5, 0.5, 0.02, (1, 1, 1, -1)),
