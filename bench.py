@@ -214,6 +214,7 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     U = synth.gauge_field(w.dims, w.eps, w.gauge_seed)
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
     b = op.to_native(synth.gaussian_half_field(w.dims, w.Ls, w.source_seed(0)))
+    tune_hop(hd, op, (1, 8))
     x = op.new_field(zero=True)
     log("16^3x32: FP64 CG")
     torch.cuda.synchronize()
@@ -322,6 +323,16 @@ def hdcg_vs_cg(hd, torch, tol=1e-8):
     }
 
 
+def tune_hop(hd, op, counts):
+    """Run the hop launch-shape autotuner for every field storage and the
+    given right-hand-side counts before anything is timed (its trials are a
+    one-time cost per operator, as a serving process would pay at start)."""
+    for n in counts:
+        for prec in (hd.DWF_C128, hd.DWF_C64, hd.DWF_BF16):
+            hd.dwf_tune_hop(op.h, prec, n)
+    hd.dwf_release_workspace(op.h)
+
+
 def _timed(torch, fn):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -372,7 +383,8 @@ def hdcg_24(hd, torch, tol=1e-8):
             out.append(float(np.sqrt(hd.dwf_norm2(op.h, res, hd.DWF_C128)[0] / hd.dwf_norm2(op.h, br, hd.DWF_C128)[0])))
         return out
 
-    log("24^3x48: sources on the device")
+    tune_hop(hd, op, (1, w5.nrhs))
+    log("24^3x48: sources on the device, hop shapes tuned")
     x = op.new_field(zero=True)
     t_cg4, (rc, st_cg4) = _timed(torch, lambda: hd.cg_solve(op.h, x, b4, 1, tol, 50000))
     log(f"config 4 FP64 CG: {t_cg4:.2f} s")

@@ -141,6 +141,15 @@ int dwf_set_hop_shape(dwf_op_t op, const int shape[10]);
  * has not run yet for that storage and count. */
 int dwf_get_hop_shape(dwf_op_t op, int prec, int nrhs, int shape[10], float* ms, int* ncand);
 
+/* Run the hop launch-shape autotuner now for (prec DWF_C128 / DWF_C64 /
+ * DWF_BF16, one or several right-hand sides; nrhs sizes its trial fields)
+ * on zero fields the call allocates and frees (2 x nrhs fields, plus the
+ * operator's work fields), so that a later timed application does not pay
+ * the trials.  Nothing happens when that slot is tuned already or a fixed
+ * shape is set.  Synchronises.  DWF_ERR_OOM when the trial fields do not
+ * fit. */
+int dwf_tune_hop(dwf_op_t op, int prec, int nrhs, void* stream);
+
 /* Free the operator's work fields (the intermediate half-fields of M_pc
  * and the fields of cg_solve, cg_solve_mixed and dwf_multishift_cg, sized
  * for the largest right-hand-side count used so far); the next call that

@@ -8,7 +8,7 @@ fallback.
 """
 from ._lib import (  # noqa: F401
     DWF_BF16, DWF_C64, DWF_C128, DWF_F16, DWF_NOT_CONVERGED, DWF_OK, HdcgError, cg_solve, cg_solve_mixed,
-    dwf_cg_update, dwf_convert, dwf_create, dwf_create_mobius, dwf_destroy, dwf_set_hop_shape, dwf_get_hop_shape, dwf_release_workspace, dwf_dot, dwf_export, dwf_field_bytes,
+    dwf_cg_update, dwf_convert, dwf_create, dwf_create_mobius, dwf_destroy, dwf_set_hop_shape, dwf_get_hop_shape, dwf_tune_hop, dwf_release_workspace, dwf_dot, dwf_export, dwf_field_bytes,
     dwf_multishift_cg,
     dwf_import, dwf_last_error, dwf_norm2, dwf_xpay, load, mpc_apply, mpc_dag_mpc_apply,
     coarse_apply, hdcg_coarse_solve, hdcg_coarse_iterations, hdcg_mfma_tile, hdcg_coarse_solve_noalloc, hdcg_default_params, hdcg_destroy, hdcg_dims, hdcg_export_block_map,

@@ -94,6 +94,7 @@ def load():
         "dwf_destroy": (i, [vp]),
         "dwf_set_hop_shape": (i, [vp, C.POINTER(C.c_int)]),
         "dwf_release_workspace": (i, [vp]),
+        "dwf_tune_hop": (i, [vp, i, i, vp]),
         "dwf_get_hop_shape": (i, [vp, i, i, C.POINTER(C.c_int), C.POINTER(C.c_float), C.POINTER(C.c_int)]),
         "dwf_field_bytes": (i, [vp, i, i, C.POINTER(sz)]),
         "dwf_import": (i, [vp, vp, vp, i, i, vp]),
@@ -203,6 +204,10 @@ def dwf_get_hop_shape(op, prec, nrhs=1):
     n = C.c_int()
     rc = _check(load().dwf_get_hop_shape(op, int(prec), int(nrhs), sh, ms, C.byref(n)), allow_soft=True)
     return tuple(sh), list(ms[:n.value]), rc == 0
+
+
+def dwf_tune_hop(op, prec, nrhs=1, stream=None):
+    _check(load().dwf_tune_hop(op, int(prec), int(nrhs), _stream(stream)))
 
 
 def dwf_release_workspace(op):

@@ -567,6 +567,25 @@ int mpc_dag_mpc_apply(dwf_op_t op, void* out, const void* in, int prec, int nrhs
   return launch_mpcdagmpc<float>(op, static_cast<c64*>(out), static_cast<const c64*>(in), nrhs, st, nullptr);
 }
 
+int dwf_tune_hop(dwf_op_t op, int prec, int nrhs, void* stream) {
+  HDCG_TRY(check_op(op));
+  HDCG_TRY(check_prec16(prec));
+  HDCG_TRY(check_nrhs(nrhs));
+  auto st = static_cast<hipStream_t>(stream);
+  const int pi = prec == DWF_C128 ? 0 : (prec == DWF_BF16 ? 2 : 1);
+  if (!op->hop_autotune || op->hop_choice[pi][nrhs > 1] >= 0) return DWF_OK;
+  const size_t bytes = op->field_elems(nrhs) * cbytes(prec);
+  DevBuf a, b;
+  HDCG_TRY(a.ensure(bytes));
+  HDCG_TRY(b.ensure(bytes));
+  int rc = hipMemsetAsync(a.ptr, 0, bytes, st) == hipSuccess ? DWF_OK : fail(DWF_ERR_HIP, "dwf_tune_hop: memset failed");
+  if (rc == DWF_OK) rc = mpc_dag_mpc_apply(op, b.ptr, a.ptr, prec, nrhs, stream);
+  if (rc == DWF_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(DWF_ERR_HIP, "dwf_tune_hop: sync failed");
+  a.release();
+  b.release();
+  return rc;
+}
+
 static int fetch(dwf_op* op, double* host, const double* dev, int n, hipStream_t st) {
   HDCG_HIP(hipMemcpyAsync(op->pinned, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
   HDCG_HIP(hipStreamSynchronize(st));

@@ -634,7 +634,7 @@ __device__ __forceinline__ void apply_dirs(cplx<R> (&acc)[12], const cplx<R> (&p
 // NPH = number of load phases (2: four directions in flight at a time; 4:
 // two).  LS > 0 fixes Ls at compile time.  Dynamic LDS:
 // max(spw * kLinkLd, spw * 12 * (Ls + 1)) complex.
-template <typename R, bool DAG, int EPI, int NPH, int LS, bool MOB, typename T>
+template <typename R, bool DAG, int EPI, int NPH, int LS, bool MOB, typename T, bool MR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
 hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ center,
            const cplx<R>* __restrict__ gauge, const R* __restrict__ pw, HopArgs A) {
@@ -644,7 +644,10 @@ hop_kernel(T* __restrict__ out, const T* __restrict__ in, const T* __restrict__ 
   // a table order already places each workgroup on its XCD's region
   const int wg = (A.remap && !A.order) ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int rhs0 = blockIdx.y * A.rg;
-  const int nr = min(A.rg, A.nrhs - rhs0);
+  // MR: several right-hand sides per workgroup (a separate instantiation,
+  // so that the one-RHS kernel keeps the register footprint of straight-line
+  // code)
+  const int nr = MR ? min(A.rg, A.nrhs - rhs0) : 1;
   const int tid = threadIdx.x;
   const int vloc = tid / Ls, s = tid - vloc * Ls;
   Site c;
@@ -859,20 +862,36 @@ int ensure_tmp(dwf_op* op, int prec, int nrhs) {
   return DWF_OK;
 }
 
+template <typename R, int NPH, int LS, bool MOB, typename T, bool MR>
+static void launch_hop_mr(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
+                          T* out, const T* in, const T* center, const cplx<R>* G, const R* pw, const HopArgs& A) {
+  if (epi == EPI_INV) {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS, MOB, T, MR>), grid, block, lds, stream, out, in, center,
+                         G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS, MOB, T, MR>), grid, block, lds, stream, out, in,
+                         center, G, pw, A);
+  } else {
+    if (dagger)
+      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS, MOB, T, MR>), grid, block, lds, stream, out, in, center,
+                         G, pw, A);
+    else
+      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS, MOB, T, MR>), grid, block, lds, stream, out, in,
+                         center, G, pw, A);
+  }
+}
+
+// several right-hand sides per workgroup are built for the compile-time Ls
+// = 16 kernels only (the launch keeps A.rg = 1 otherwise)
 template <typename R, int NPH, int LS, bool MOB, typename T>
 static void launch_hop(bool dagger, int epi, dim3 grid, dim3 block, size_t lds, hipStream_t stream,
                        T* out, const T* in, const T* center, const cplx<R>* G, const R* pw, const HopArgs& A) {
-  if (epi == EPI_INV) {
-    if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_INV, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
-    else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_INV, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
-  } else {
-    if (dagger)
-      hipLaunchKernelGGL((hop_kernel<R, true, EPI_SUB, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
-    else
-      hipLaunchKernelGGL((hop_kernel<R, false, EPI_SUB, NPH, LS, MOB, T>), grid, block, lds, stream, out, in, center, G, pw, A);
+  if constexpr (LS == 16) {
+    if (A.rg > 1)
+      return launch_hop_mr<R, NPH, LS, MOB, T, true>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
   }
+  launch_hop_mr<R, NPH, LS, MOB, T, false>(dagger, epi, grid, block, lds, stream, out, in, center, G, pw, A);
 }
 
 // ------------------------------------------------- region block orders --
@@ -995,7 +1014,7 @@ static int hop_launch(dwf_op* op, T* out, const T* in, const T* center,
   A.nbt = 1;
   A.order = nullptr;
   A.nrhs = nrhs;
-  A.rg = std::max(1, std::min(op->tune.rg, nrhs));
+  A.rg = g.Ls == 16 ? std::max(1, std::min(op->tune.rg, nrhs)) : 1;
   {
     const int* b = op->tune.block;
     auto pow2 = [](int n) { return n > 0 && (n & (n - 1)) == 0; };

@@ -131,6 +131,12 @@ def run_hdcg(a, torch, synth):
     cprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16, "f16": hd.DWF_F16}[a.coarse]
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
     b = op.to_native(bsrc)
+    # the hop autotuner's trials before the setup, so that a traced solve
+    # phase holds only the solve's own launches
+    for n in sorted({1, 8, a.nrhs_solve}):
+        for p in (hd.DWF_C128, hd.DWF_C64, hd.DWF_BF16):
+            hd.dwf_tune_hop(op.h, p, n)
+    hd.dwf_release_workspace(op.h)
     iprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.irs]
     pprec = {"c64": hd.DWF_C64, "bf16": hd.DWF_BF16}[a.phi]
     h = hd.HDCG(op, w.block, V, nvec=w.nvec, seed=w.subspace_seed(0), n_ii=a.n_ii, tol_ii=a.tol_ii,

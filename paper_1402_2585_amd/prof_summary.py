@@ -4,7 +4,7 @@ notes under profiles/.
 
   python3 paper_1402_2585_amd/prof_summary.py trace <run_results.db> [--match S] [--grid N]
   python3 paper_1402_2585_amd/prof_summary.py pmc <run_results.db> [--match S] [--grid N]
-  python3 paper_1402_2585_amd/prof_summary.py hop-json <dir> --out profiles/hop_kernel_16^4xLs16_pmc.json
+  python3 paper_1402_2585_amd/prof_summary.py hop-json <dir> --out profiles/hop_kernel_16^4xLs16_pmc.json [--shapes S]
   python3 paper_1402_2585_amd/prof_summary.py solve <run_results.db> [--top N]
 
 `solve` summarises the solve phase of a traced `prof_driver.py --what hdcg`
@@ -60,7 +60,7 @@ def pmc_rows(db, match=None, grid=None):
     return out
 
 
-def hop_json(dirs, out_path, root):
+def hop_json(dirs, out_path, root, shapes=None):
     """The hop kernel's HBM traffic per launch on 16^4 x Ls16 from the
     FETCH_SIZE / WRITE_SIZE runs (dirs: {tag: (fetch_db, write_db)} for
     c128, c64, bf16 and the copy-kernel calibration 'copy'), scaled by what
@@ -82,13 +82,17 @@ def hop_json(dirs, out_path, root):
     V, Ls = 16 ** 4, 16
     half = V // 2 * Ls * 12
     out = {"source_hash": h.hexdigest()[:16],
-           "workload": "H = M_pc^+ M_pc on 16^4 x Ls16, 1 RHS (the launch shape the autotuner picks there)",
+           "workload": "H = M_pc^+ M_pc on 16^4 x Ls16, 1 RHS",
+           "launch_shapes": shapes or {},
            "calibration": {"fetch_scale": fscale, "write_scale": wscale,
                            "copy_kernel": "hdcg_prof copy 1024 3: 1 GiB read + 1 GiB write per launch"}}
     for tag, cb, gb in (("c128", 16, 16), ("c64", 8, 8), ("bf16", 4, 8)):
         fetch_db, write_db = dirs[tag]
-        f_inv = [r["avg"] for r in pmc_rows(fetch_db, "hop_kernel") if r["counter"] == "FETCH_SIZE" and ", 0, 4," in r["kernel"]]
-        f_sub = [r["avg"] for r in pmc_rows(fetch_db, "hop_kernel") if r["counter"] == "FETCH_SIZE" and ", 1, 4," in r["kernel"]]
+        def epi(name):  # the third template argument of hop_kernel<R, DAG, EPI, NPH, LS, MOB, T>
+            return name[name.index("hop_kernel<") + len("hop_kernel<"):].split(",")[2].strip()
+
+        f_inv = [r["avg"] for r in pmc_rows(fetch_db, "hop_kernel") if r["counter"] == "FETCH_SIZE" and epi(r["kernel"]) == "0"]
+        f_sub = [r["avg"] for r in pmc_rows(fetch_db, "hop_kernel") if r["counter"] == "FETCH_SIZE" and epi(r["kernel"]) == "1"]
         w = [r["avg"] for r in pmc_rows(write_db, "hop_kernel") if r["counter"] == "WRITE_SIZE"]
         fi, fs, ww = sum(f_inv) / len(f_inv), sum(f_sub) / len(f_sub), sum(w) / len(w)
         per_launch = ((fi + fs) / 2 * fscale + ww * wscale) * 1024.0
@@ -152,6 +156,8 @@ def main():
     ap.add_argument("db", help="result database, or for hop-json the directory holding the runs "
                                "fetch_<tag>/, write_<tag>/ (tag c128, c64, bf16, copy), each with run_results.db")
     ap.add_argument("--out", default=None, help="hop-json: output path")
+    ap.add_argument("--shapes", default=None,
+                    help="hop-json: the launch shapes the runs used, e.g. 'c128=2,2,1,1,1,0,0,4,0,1;c64=...'")
     ap.add_argument("--match", default=None)
     ap.add_argument("--grid", type=int, default=None)
     ap.add_argument("--json", action="store_true")
@@ -177,7 +183,8 @@ def main():
         d = {t: (os.path.join(a.db, f"fetch_{t}", "run_results.db"), os.path.join(a.db, f"write_{t}", "run_results.db"))
              for t in ("c128", "c64", "bf16", "copy")}
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        print(json.dumps(hop_json(d, a.out, root), indent=1))
+        shapes = dict(kv.split("=", 1) for kv in a.shapes.split(";")) if a.shapes else None
+        print(json.dumps(hop_json(d, a.out, root, shapes), indent=1))
         return
     rows = (trace_rows if a.what == "trace" else pmc_rows)(a.db, a.match, a.grid)
     if a.json:

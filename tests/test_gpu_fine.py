@@ -310,6 +310,29 @@ def test_hop_region_orders_on_a_block_grid_of_odd_extents(order, block):
     lex.close()
 
 
+def test_dwf_tune_hop_runs_the_autotuner_once():
+    """dwf_tune_hop tunes one (storage, one / several RHS) slot on scratch
+    fields: afterwards dwf_get_hop_shape reports it tuned, every candidate
+    tried has a positive time (the several-RHS candidates only for the
+    several-RHS slot), and H with the chosen shape matches the oracle."""
+    dims, Ls = (8, 8, 4, 8), 16
+    banner("dwf_tune_hop")
+    U = synth.gauge_field(dims, 0.7, 159)
+    op = hd.FineOperator(U, dims, Ls, 1.8, 0.02)
+    assert not hd.dwf_get_hop_shape(op.h, hd.DWF_C64, 1)[2]
+    for n in (1, 3):
+        hd.dwf_tune_hop(op.h, hd.DWF_C64, n)
+        shape, ms, tuned = hd.dwf_get_hop_shape(op.h, hd.DWF_C64, n)
+        print(n, shape, [round(m, 4) for m in ms], flush=True)
+        assert tuned and len(ms) >= 13 and all(m > 0 for m in ms[:13])
+        assert all((m > 0) == (n > 1) for m in ms[13:])
+    assert not hd.dwf_get_hop_shape(op.h, hd.DWF_BF16, 1)[2]
+    b = synth.gaussian_half_field(dims, Ls, 160)
+    got = op.to_canonical(op.H(op.to_native(b, hd.DWF_C64), hd.DWF_C64), hd.DWF_C64).cpu().numpy()
+    assert rel_err(got, DWF(U, dims, Ls, 1.8, 0.02).H(b)) < 5e-6
+    op.close()
+
+
 @pytest.mark.parametrize("mobius", [False, True])
 def test_hop_several_rhs_per_workgroup_bitwise(mobius):
     """rg > 1: one workgroup applies a stage to several right-hand sides one
