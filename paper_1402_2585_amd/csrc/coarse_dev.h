@@ -37,6 +37,25 @@ __device__ __forceinline__ void st_coherent(c64* p, c64 v) {
   __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// KL consecutive complex64 values at byte offset `off` of the buffer `rs`,
+// two per 16-byte load, with the same agent-scope coherence as ld_coherent
+// (the loads carry the sc1 cache-policy bit that a relaxed agent-scope
+// atomic load carries on gfx950: cache policy 16); half the load
+// instructions of KL 8-byte atomic loads.
+typedef unsigned u32x4_coh __attribute__((ext_vector_type(4)));
+template <int KL>
+__device__ __forceinline__ void ld_coherent_run(__amdgpu_buffer_rsrc_t rs, unsigned off, c64 (&x)[KL]) {
+#pragma unroll
+  for (int q = 0; q < KL / 2; ++q) {
+    const u32x4_coh v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16u * q), 0, 16);
+    x[2 * q] = cmk(__uint_as_float(v.x), __uint_as_float(v.y));
+    x[2 * q + 1] = cmk(__uint_as_float(v.z), __uint_as_float(v.w));
+  }
+}
+// a raw buffer resource over `bytes` bytes at p (word 3 as for every gfx9 buffer)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coherent_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
 
 // ---------------------------------------------------- complex64/128 VALU --
 // AT[a][l][k][j] (transposed per stencil point).  Thread (part, j) sums the
@@ -185,6 +204,9 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
   const unsigned short* Fa = F + (size_t)a * ksteps * nvec * 16;
   const int* nb = nbr + (size_t)a * NS;
   const float* rh = rho + (size_t)a * NS;
+  // COH: the operand of all nrhs right-hand sides as one buffer resource
+  // (offsets stay below 2 GiB: nrhs <= 16 columns of Nc * nvec values)
+  const __amdgpu_buffer_rsrc_t rs = coherent_rsrc(in, COH ? (unsigned)((size_t)nrhs * Nc * nvec * sizeof(c64)) : 0u);
   // storage step and k group of this lane's A fragment at step S
   const int sub = K32 ? (kg >> 1) : 0, kgs = K32 ? 2 * (kg & 1) : kg;
   for (int s0 = wave * U; s0 < nsteps; s0 += NW * U) {
@@ -220,15 +242,16 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
             const int rr = imcol ? g - nrhs : g;
             const size_t co = (size_t)rr * Nc * nvec + vo;
             frag b;
+            c64 xs[KL];
+            if constexpr (COH) {
+              ld_coherent_run<KL>(rs, (unsigned)(co * sizeof(c64)), xs);
+            } else {
+#pragma unroll
+              for (int i = 0; i < KL; ++i) xs[i] = STAGED ? in[rem + i] : in[co + i];
+            }
 #pragma unroll
             for (int i = 0; i < KL; ++i) {
-              c64 x;
-              if constexpr (STAGED)
-                x = in[rem + i];
-              else if constexpr (COH)
-                x = ld_coherent(in + co + i);
-              else
-                x = in[co + i];
+              const c64 x = xs[i];
               // columns r:        part 0 -> Re c, part 1 -> -Im c
               // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
               b[i] = (short)to16<BF16>(r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im)));
