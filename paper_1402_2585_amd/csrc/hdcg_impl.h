@@ -153,6 +153,13 @@ int blk_dot(hdcg* h, const bf16c* P, const cplx<float>* fine, size_t fstride, in
             size_t sa, size_t sk, hipStream_t st);
 int blk_promote(hdcg* h, const bf16c* P, const cplx<float>* c, int nr, cplx<float>* fine_out,
                 const cplx<float>* base, double sign, size_t fstride, hipStream_t st);
+// the same two on MFMA for several right-hand sides (blk_mfma.hip): 16-byte
+// aligned subspace and fields, full site columns (sd == 0), nvec <= 64
+bool blk_mfma_applies(hdcg* h, const void* P, const void* field, size_t fstride, int sd);
+int blk_project_mfma(hdcg* h, const bf16c* P, const cplx<float>* fine, size_t fstride, int nr, cplx<float>* out,
+                     size_t sr, size_t sa, size_t sk, hipStream_t st);
+int blk_promote_mfma(hdcg* h, const bf16c* P, const cplx<float>* c, int nr, cplx<float>* fine_out,
+                     const cplx<float>* base, double sign, size_t fstride, hipStream_t st);
 int blk_phi16(hdcg* h, hipStream_t st);        // phi16 = phi128 rounded to bf16 pairs
 int blk_cholqr_step(hdcg* h, hipStream_t st);  // one Cholesky-QR pass on phi128
 int blk_surface_zero(hdcg* h, hipStream_t st);  // zero phi128 at sd <= s < Ls - sd

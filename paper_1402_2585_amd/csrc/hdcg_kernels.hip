@@ -10,6 +10,10 @@ namespace hdk {
 namespace {
 
 constexpr int kT = 256;
+// right-hand-side counts from which the 16-bit-subspace project / promote
+// run on MFMA
+constexpr int kProjectMfmaRhs = 2;
+constexpr int kPromoteMfmaRhs = 2;
 
 __global__ void k_blockmap(int* __restrict__ site_of, Geom g, int4 B, int4 C, int nsb, int total) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -498,6 +502,10 @@ int blk_dot_t(hdcg* h, const TP* P, const cplx<R>* fine, size_t fstride, const c
   const int colP = sd > 0 ? 24 * sd : col;
   const size_t nbP = (size_t)h->nsb * colP;
   if (sd > 0 && (!fine || phase)) return fail(DWF_ERR_ARG, "surface subspace: fine-field projection only");
+  if constexpr (std::is_same_v<TP, bf16c>) {
+    if (fine && !phase && nr >= kProjectMfmaRhs && blk_mfma_applies(h, P, fine, fstride, sd))
+      return blk_project_mfma(h, P, fine, fstride, nr, out, sr, sa, sk, st);
+  }
   if (fine && !phase && nr <= 4) {
     // streaming kernel: P read once, few accumulators per lane
     constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
@@ -552,6 +560,11 @@ int blk_promote_t(hdcg* h, const TP* P, const cplx<R>* c, int nr, cplx<R>* out,
   const size_t nbP = (size_t)h->nsb * colP;
   constexpr int V = sizeof(TP) == 4 ? 4 : 1;  // 16-byte loads of the 16-bit subspace
   if (col % V || sd % V) return fail(DWF_ERR_ARG, "promote: 12 Ls and the surface depth must be multiples of 4");
+  if constexpr (std::is_same_v<TP, bf16c>) {
+    if (nr >= kPromoteMfmaRhs && blk_mfma_applies(h, P, out, fstride, sd) &&
+        (!base || (reinterpret_cast<uintptr_t>(base) & 15u) == 0))
+      return blk_promote_mfma(h, P, c, nr, out, base, sign, fstride, st);
+  }
   if (sd > 0 && out != base) {
     const size_t fe = h->op->field_elems(1);
     size_t nbk = (fe * nr + kT - 1) / kT;

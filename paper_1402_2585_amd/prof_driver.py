@@ -231,41 +231,45 @@ def run_variants(a, torch, synth, hd, w, op, h, b):
 
 def run_coarse(a, torch, synth):
     """Times the coarse-grid kernels of a numbered workload (subspace: the
-    seeded vectors, orthonormalised, no inverse iteration): the little Dirac
-    operator mat-vec, its one-hop truncation and the Chebyshev inverse
-    (order 16 on [0.5, 45]), and the project / promote of the solve's
-    subspace copies; complex64 vectors, one right-hand side, --reps each."""
+    starting vectors drawn on the device from the workload's seed,
+    orthonormalised, no inverse iteration): the little Dirac operator
+    mat-vec, its one-hop truncation and the Chebyshev inverse (order 16 on
+    [0.5, 45]) on one right-hand side, and the project / promote of the
+    solve's subspace copies on one and on --nrhs_solve right-hand sides;
+    complex64 vectors, --reps each."""
     import time
-
-    import numpy as np
 
     from synth.configs import WORKLOADS
 
     w = WORKLOADS[a.workload]
     U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
-    V = torch.from_numpy(np.stack([synth.gaussian_half_field(w.dims, w.Ls, w.subspace_seed(k))
-                                   for k in range(w.nvec)])).to("cuda")
     torch.cuda.synchronize()
     import paper_1402_2585_amd as hd
 
     op = hd.FineOperator(U, w.dims, w.Ls, w.M5, w.mass)
-    h = hd.HDCG(op, w.block, V, n_ii=0)
-    del V
+    del U
+    # both subspace copies (complex64, bf16) are built before the FP64 one is released
+    h = hd.HDCG(op, w.block, None, nvec=w.nvec, seed=w.subspace_seed(0), n_ii=0, keep_subspace_fp64=0,
+                phi_prec=hd.DWF_BF16)
     h.set_params(m1_lo=0.5, m1_hi=45.0, m1_order=16)
     x = torch.from_numpy(synth.gaussian_coarse(h.Nc, h.nvec, w.coarse_seed, 1)).to(torch.complex64).to("cuda")
     y = torch.empty_like(x)
     torch.cuda.synchronize()
     print(f"coarse grid Nc {h.Nc} nvec {h.nvec}", flush=True)
-    f = torch.randn(op.new_field(hd.DWF_C64).numel(), dtype=torch.complex64, device="cuda")
+    nr = max(1, a.nrhs_solve)
+    f = torch.randn(nr * op.new_field(hd.DWF_C64).numel(), dtype=torch.complex64, device="cuda")
     g = torch.empty_like(f)
+    ym = torch.randn(nr * h.Nc * h.nvec, dtype=torch.complex64, device="cuda")
     torch.cuda.synchronize()
-    for name, fn in (("A mat-vec", lambda: hd.coarse_apply(h.h, y, x, hd.DWF_C64)),
-                     ("Q_trunc mat-vec", lambda: hd.hdcg_trunc_apply(h.h, y, x, hd.DWF_C64)),
-                     ("Chebyshev order 16", lambda: hd.hdcg_chebyshev(h.h, y, x, hd.DWF_C64)),
-                     ("project, complex64 subspace", lambda: hd.hdcg_project(h.h, y, f, hd.DWF_C64)),
-                     ("project, bf16 subspace", lambda: hd.hdcg_project(h.h, y, f, hd.DWF_BF16)),
-                     ("promote, complex64 subspace", lambda: hd.hdcg_promote(h.h, g, y, hd.DWF_C64)),
-                     ("promote, bf16 subspace", lambda: hd.hdcg_promote(h.h, g, y, hd.DWF_BF16))):
+    cases = [("A mat-vec", lambda: hd.coarse_apply(h.h, y, x, hd.DWF_C64)),
+             ("Q_trunc mat-vec", lambda: hd.hdcg_trunc_apply(h.h, y, x, hd.DWF_C64)),
+             ("Chebyshev order 16", lambda: hd.hdcg_chebyshev(h.h, y, x, hd.DWF_C64))]
+    for n in sorted({1, nr}):
+        cases += [(f"project, complex64 subspace, {n} RHS", lambda n=n: hd.hdcg_project(h.h, ym, f, hd.DWF_C64, n)),
+                  (f"project, bf16 subspace, {n} RHS", lambda n=n: hd.hdcg_project(h.h, ym, f, hd.DWF_BF16, n)),
+                  (f"promote, complex64 subspace, {n} RHS", lambda n=n: hd.hdcg_promote(h.h, g, ym, hd.DWF_C64, n)),
+                  (f"promote, bf16 subspace, {n} RHS", lambda n=n: hd.hdcg_promote(h.h, g, ym, hd.DWF_BF16, n))]
+    for name, fn in cases:
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -153,6 +153,37 @@ def test_project_promote_on_sampled_blocks(shape):
             assert rel_err(got_f, want_f) < tol, (prec, b)
 
 
+def test_project_promote_many_rhs_bf16(shape):
+    """The 16-bit-subspace project and promote for 17 right-hand sides (the
+    MFMA kernels: one full group of 16 and a ragged group of one; promote
+    with two 8-RHS column tiles) against the oracle on the sampled blocks,
+    to the complex64 tolerance: the kernels carry the complex64 operand as
+    three bf16 terms, exact to 2^-24, so only the summation order differs
+    from an FP32 computation."""
+    t = shape
+    banner(f"project / promote, 17 RHS, bf16 subspace {t['name']}")
+    op, h, sob, phi = t["op"], t["h"], t["sob"], t["phi"]
+    nr = 17
+    psi = synth.gaussian_half_field(t["dims"], t["Ls"], 470, nrhs=nr).astype(np.complex64)
+    c = synth.gaussian_coarse(h.Nc, h.nvec, 471, nr).astype(np.complex64)
+    phi16 = oprc.round_bf16(phi)
+    out = h.new_coarse(hd.DWF_C64, nr)
+    hd.hdcg_project(h.h, out, op.to_native(psi, hd.DWF_C64), hd.DWF_BF16, nr)
+    got = out.cpu().numpy()
+    fine = op.new_field(hd.DWF_C64, nr)
+    hd.hdcg_promote(h.h, fine, torch.from_numpy(c).to("cuda"), hd.DWF_BF16, nr)
+    fc = op.to_canonical(fine, hd.DWF_C64, nr)
+    for b in t["blocks"]:
+        pb = oblk.block_view(phi16, sob, b)  # (nvec, n_b)
+        want_c = np.einsum("ji,ri->rj", pb.conj(), oblk.block_view(psi.astype(np.complex128), sob, b))
+        err_c = rel_err(got[:, b], want_c)
+        want_f = np.einsum("ji,rj->ri", pb, c[:, b].astype(np.complex128))
+        got_f = fc[:, :, torch.from_numpy(sob[b]).to("cuda")].cpu().numpy().reshape(nr, -1)
+        err_f = rel_err(got_f, want_f)
+        print(f"block {b}: project {err_c:.2e}, promote {err_f:.2e}", flush=True)
+        assert err_c < 2e-5 and err_f < 2e-5, b
+
+
 def test_coarse_kernels_on_seeded_operator(shape):
     """coarse_apply (complex128, complex64, bf16 and fp16 MFMA with 1, 3 and
     16 right-hand sides) on a seeded Hermitian positive-definite stencil
