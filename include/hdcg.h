@@ -256,7 +256,9 @@ struct hdcg_params {
   double inner_tol;   /* relative residual of each complex64 A-DEF2 inner solve, default 1e-5 */
   int inner_maxiter;  /* inner iteration cap */
   int outer_maxiter;  /* FP64 defect-correction restarts cap */
-  int build_batch;    /* probe vectors per H application batch in the coarse build */
+  int build_batch;    /* probe vectors per H application batch in the coarse build
+                         (default 16, at most 16; two complex128 fields per probe
+                         vector are held during the build) */
   int coarse_prec;    /* storage of A inside Q: DWF_C64 (VALU, default), DWF_BF16 or DWF_F16
                          (MFMA with FP32 accumulation, per-matrix scales; nvec % 4 == 0) */
   int verbose;        /* 1: hdcg_setup prints stage progress to stderr */

@@ -189,6 +189,7 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
                                                  const c64* __restrict__ in, c64* __restrict__ out, int a,
                                                  int Nc, int nvec, int nrhs, int ksteps, f32x4* red) {
   using frag = std::conditional_t<K32, s16x8, s16x4>;
+  static_assert(!STAGED || NT == 1, "the LDS-staged operand serves one right-hand side");
   constexpr int KL = K32 ? 8 : 4;  // K values per lane and step
   constexpr int KS = 4 * KL;       // K values per step
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -209,6 +210,13 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
   const __amdgpu_buffer_rsrc_t rs = coherent_rsrc(in, COH ? (unsigned)((size_t)nrhs * Nc * nvec * sizeof(c64)) : 0u);
   // storage step and k group of this lane's A fragment at step S
   const int sub = K32 ? (kg >> 1) : 0, kgs = K32 ? 2 * (kg & 1) : kg;
+  // the right-hand side of this lane's B columns: with NT = 2 (9-16 RHS)
+  // lane r16 takes RHS r16, its Re column in tile 0 and its Im column in
+  // tile 1; with NT = 1 (1-8 RHS) columns 0 .. nrhs-1 are the Re columns and
+  // nrhs .. 2 nrhs-1 the Im columns
+  const int rr = NT == 2 ? r16 : (r16 < nrhs ? r16 : r16 - nrhs);
+  const bool cok = NT == 2 ? r16 < nrhs : r16 < 2 * nrhs;
+  const bool im1 = NT == 1 && r16 >= nrhs;
   for (int s0 = wave * U; s0 < nsteps; s0 += NW * U) {
     frag af[U][MT];
     frag bf[U][NT];
@@ -223,43 +231,68 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
                         : frag{};
       }
     }
+    if constexpr (STAGED) {
+      // one right-hand side, operand in LDS: each step's run converted as read
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k0 = KS * (s0 + u) + KL * kg;
+      for (int u = 0; u < U; ++u) {
+        const int k0 = KS * (s0 + u) + KL * kg;
+        bf[u][0] = frag{};
+        if (cok && s0 + u < nsteps && k0 < ktot) {
+          const int part = k0 / kn;
+          const int rem = k0 - part * kn;
+          const float r = rh[rem / nvec];
+          frag b;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) bf[u][nt] = frag{};
-      if (s0 + u < nsteps && k0 < ktot) {
-        const int part = k0 / kn;
-        const int rem = k0 - part * kn;
-        const int l = rem / nvec, k = rem - (rem / nvec) * nvec;
-        const float r = rh[l];
-        const size_t vo = (size_t)nb[l] * nvec + k;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int g = nt * 16 + r16;
-          if (g < 2 * nrhs) {
-            const bool imcol = g >= nrhs;
-            const int rr = imcol ? g - nrhs : g;
-            const size_t co = (size_t)rr * Nc * nvec + vo;
-            frag b;
-            c64 xs[KL];
-            if constexpr (COH) {
-              ld_coherent_run<KL>(rs, (unsigned)(co * sizeof(c64)), xs);
-            } else {
-#pragma unroll
-              for (int i = 0; i < KL; ++i) xs[i] = STAGED ? in[rem + i] : in[co + i];
-            }
-#pragma unroll
-            for (int i = 0; i < KL; ++i) {
-              const c64 x = xs[i];
-              // columns r:        part 0 -> Re c, part 1 -> -Im c
-              // columns nrhs + r: part 0 -> Im c, part 1 ->  Re c
-              b[i] = (short)to16<BF16>(r * (imcol ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im)));
-            }
-            bf[u][nt] = b;
+          for (int i = 0; i < KL; ++i) {
+            const c64 x = in[rem + i];
+            b[i] = (short)to16<BF16>(r * (im1 ? (part == 0 ? x.im : x.re) : (part == 0 ? x.re : -x.im)));
           }
+          bf[u][0] = b;
         }
       }
+    } else {
+      // the operand runs of all U steps are loaded before any is converted
+      // (addresses clamped to valid ones, invalid lanes zeroed afterwards), one
+      // run per lane and step: its right-hand side feeds both of its columns
+      c64 xs[U][KL];
+      float rsc[U];
+      int prt[U];
+      bool okv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k0 = KS * (s0 + u) + KL * kg;
+        const bool ok = cok && s0 + u < nsteps && k0 < ktot;
+        const int kk = ok ? k0 : 0;
+        const int part = kk / kn;
+        const int rem = kk - part * kn;
+        const int l = rem / nvec, k = rem - l * nvec;
+        okv[u] = ok;
+        prt[u] = part;
+        rsc[u] = rh[l];
+        const size_t co = (size_t)(ok ? rr : 0) * Nc * nvec + (size_t)nb[l] * nvec + k;
+        if constexpr (COH) {
+          ld_coherent_run<KL>(rs, (unsigned)(co * sizeof(c64)), xs[u]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < KL; ++i) xs[u][i] = in[co + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bool imcol = NT == 2 ? nt == 1 : im1;
+          frag b;
+#pragma unroll
+          for (int i = 0; i < KL; ++i) {
+            const c64 x = xs[u][i];
+            // Re columns: part 0 -> Re c, part 1 -> -Im c
+            // Im columns: part 0 -> Im c, part 1 ->  Re c
+            const float v = rsc[u] * (imcol ? (prt[u] == 0 ? x.im : x.re) : (prt[u] == 0 ? x.re : -x.im));
+            b[i] = okv[u] ? (short)to16<BF16>(v) : (short)0;
+          }
+          bf[u][nt] = b;
+        }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -298,11 +331,11 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
     f32x4 v = red[tile * 64 + ln];
 #pragma unroll
     for (int w = 1; w < NW; ++w) v += red[(w * MT * NT + tile) * 64 + ln];
-    // lane ln holds D[m = 4 (ln / 16) + i][n = ln % 16]
-    const int g = nt * 16 + (ln & 15);
-    if (g >= 2 * nrhs) continue;
-    const bool imcol = g >= nrhs;
-    const int rr = imcol ? g - nrhs : g;
+    // lane ln holds D[m = 4 (ln / 16) + i][n = ln % 16]; columns as loaded
+    const int n = ln & 15;
+    if (NT == 2 ? n >= nrhs : n >= 2 * nrhs) continue;
+    const bool imcol = NT == 2 ? nt == 1 : n >= nrhs;
+    const int rr = NT == 2 ? n : (imcol ? n - nrhs : n);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = mt * 16 + 4 * (ln >> 4) + i;

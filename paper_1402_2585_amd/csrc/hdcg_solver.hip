@@ -720,7 +720,7 @@ void hdcg_default_params(struct hdcg_params* p) {
   p->inner_tol = 1e-5;
   p->inner_maxiter = 500;
   p->outer_maxiter = 50;
-  p->build_batch = 8;
+  p->build_batch = 16;
   p->coarse_prec = DWF_C64;
   p->verbose = 0;
   p->irs_prec = DWF_C64;

@@ -54,7 +54,7 @@ def test_param_struct_layout_matches_the_library():
 
     p = hd.hdcg_default_params()
     want = dict(n_ii=0, maxiter_ii=500, n_irs=7, lambda_irs=1.0, coarse_tol=0.04, coarse_maxiter=2000, flexible=1,
-                inner_tol=1e-5, inner_maxiter=500, outer_maxiter=50, build_batch=8, coarse_prec=hd.DWF_C64,
+                inner_tol=1e-5, inner_maxiter=500, outer_maxiter=50, build_batch=16, coarse_prec=hd.DWF_C64,
                 verbose=0, irs_prec=hd.DWF_C64, subspace_gen=0, rat_lo=3e-4, rat_eps=1e-4, rat_tol=1e-6,
                 rat_maxiter=10000, wall_noise=0, ldop_defl=1, phi_prec=hd.DWF_C64, ldop_m1=0, m1_lo=0.5,
                 m1_hi=0.0, m1_order=16, m1_shift=0.0, surface_depth=0, coarse_persistent=1, graph=1,
