@@ -25,10 +25,13 @@ int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, doubl
 // den read with stride dstr, e.g. 2 for the real parts of dot results; a zero
 // denominator gives a zero coefficient)
 // x += alpha p ; r -= alpha (w + lam p) ; rr[rhs] = |r|^2 (if rr)
+// mode bits: kUpdX0, x is zero (not read: x = alpha p); kUpdXOnly, only x
+// is updated (r, w, rr untouched: the last step of a fixed-count CG)
+constexpr int kUpdX0 = 1, kUpdXOnly = 2;
 template <typename R>
 int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w, size_t n,
              int nrhs, const double* num, bool cnum, const double* den, const double* den2,
-             double lam, double* rr, hipStream_t st, int dstr = 1);
+             double lam, double* rr, hipStream_t st, int dstr = 1, int mode = 0);
 // beta = sign * num / den (num complex when cnum) ; p = y + beta p ;
 // pp[rhs] = |p|^2 (if pp)
 template <typename R>
@@ -55,7 +58,15 @@ int b_zero(cplx<R>* y, size_t total, hipStream_t st);
 int b_norm2(Red red, const bf16c* x, size_t n, int nrhs, double* res, hipStream_t st);
 int b_update(Red red, bf16c* x, bf16c* r, const bf16c* p, const bf16c* w, size_t n, int nrhs,
              const double* num, const double* den, const double* den2, double lam, double* rr,
-             hipStream_t st);
+             hipStream_t st, int mode = 0);
+// fixed-count CG on 16-bit fields: r = p = 16-bit b (complex64 [site][12][Ls]
+// to the 16-bit [site][Ls][12] layout), rr = |r|^2 of the stored values; and
+// its last step x_out (complex64 layout) = 16-bit(x + alpha p), x == nullptr
+// meaning zero, alpha = num / (den + lam den2)
+int b_mirs16_init(Red red, bf16c* r, bf16c* p, const c64* b, size_t n, int nrhs, int Ls, double* rr,
+                  hipStream_t st);
+int b_mirs16_last(c64* x_out, const bf16c* x, const bf16c* p, size_t n, int nrhs, int Ls, const double* num,
+                  const double* den, const double* den2, double lam, hipStream_t st);
 int b_xpay(Red red, bf16c* p, const bf16c* y, size_t n, int nrhs, const double* num,
            const double* den, double* pp, hipStream_t st);
 int b_zero(bf16c* y, size_t total, hipStream_t st);

@@ -185,11 +185,12 @@ __global__ void __launch_bounds__(kT) k_dot(const T* __restrict__ a, const T* __
   reduce_out<2>(v, red, rhs, res);
 }
 
-template <typename T>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kT)
 k_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ w,
          size_t n, const double* num, bool cnum, const double* den, const double* den2, double lam,
          Red red, double* rr, int dstr) {
+  constexpr bool X0 = MODE & kUpdX0, XONLY = MODE & kUpdXOnly;
   using R = typename St<T>::R;
   const int rhs = blockIdx.y;
   const size_t off = rhs * n;
@@ -206,20 +207,29 @@ k_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T*
   for (size_t g = (size_t)blockIdx.x * kT + threadIdx.x; g < n / V; g += (size_t)gridDim.x * kT) {
     cplx<R> pv[V], wv[V], xv[V], rv[V];
     Vec<T>::ld(p, g, pv);
-    Vec<T>::ld(w, g, wv);
-    Vec<T>::ld(x, g, xv);
-    Vec<T>::ld(r, g, rv);
+    if constexpr (!XONLY) {
+      Vec<T>::ld(w, g, wv);
+      Vec<T>::ld(r, g, rv);
+    }
+    if constexpr (X0) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) xv[k] = cmk((R)0, (R)0);
+    } else {
+      Vec<T>::ld(x, g, xv);
+    }
 #pragma unroll
     for (int k = 0; k < V; ++k) {
-      if (den2) wv[k] = wv[k] + l * pv[k];
       xv[k] = xv[k] + a * pv[k];
-      rv[k] = rv[k] - a * wv[k];
-      acc += nrm(rv[k]);
+      if constexpr (!XONLY) {
+        if (den2) wv[k] = wv[k] + l * pv[k];
+        rv[k] = rv[k] - a * wv[k];
+        acc += nrm(rv[k]);
+      }
     }
     Vec<T>::st(x, g, xv);
-    Vec<T>::st(r, g, rv);
+    if constexpr (!XONLY) Vec<T>::st(r, g, rv);
   }
-  if (rr) {
+  if (!XONLY && rr) {
     double v[1] = {acc};
     reduce_out<1>(v, red, rhs, rr);
   }
@@ -253,6 +263,69 @@ k_xpay(T* __restrict__ p, const T* __restrict__ y, size_t n, const double* num, 
   if (pp) {
     double v[1] = {acc};
     reduce_out<1>(v, red, rhs, pp);
+  }
+}
+
+// Fixed-count CG on 16-bit fields (M_IRS), first step: r = p = bf16(b) for
+// b complex64 [site][12][Ls] and r, p 16-bit [site][Ls][12] (rounded to
+// nearest even as every 16-bit store), and rr[rhs] = |r|^2 of the rounded
+// values.  One (site, s) row of 12 values per thread; rows per RHS.
+__global__ void __launch_bounds__(kT)
+k_mirs16_init(bf16c* __restrict__ r, bf16c* __restrict__ p, const c64* __restrict__ b, size_t rows, int Ls,
+              Red red, double* rr) {
+  const int rhs = blockIdx.y;
+  const size_t off = (size_t)rhs * rows * 12;
+  double acc = 0.0;
+  for (size_t row = (size_t)blockIdx.x * kT + threadIdx.x; row < rows; row += (size_t)gridDim.x * kT) {
+    const size_t site = row / Ls;
+    const int s = (int)(row - site * Ls);
+    const c64* f = b + off + site * 12 * Ls + s;
+    bf16c4 q[3];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      St<bf16c>::st(&q[c >> 2].v[c & 3], f[c * Ls]);
+      acc += nrm(St<bf16c>::ld(&q[c >> 2].v[c & 3]));
+    }
+    const size_t o = (off + site * 12 * Ls + (size_t)s * 12) / 4;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      reinterpret_cast<bf16c4*>(r)[o + k] = q[k];
+      reinterpret_cast<bf16c4*>(p)[o + k] = q[k];
+    }
+  }
+  double v[1] = {acc};
+  reduce_out<1>(v, red, rhs, rr);
+}
+
+// Its last step: only x is still needed, x_out = x + alpha p rounded to 16
+// bits as the stored x would be, written in complex64 [site][12][Ls]
+// (x == nullptr: x = 0); alpha as in k_update.
+__global__ void __launch_bounds__(kT)
+k_mirs16_last(c64* __restrict__ xo, const bf16c* __restrict__ x, const bf16c* __restrict__ p, size_t rows,
+              int Ls, const double* num, const double* den, const double* den2, double lam) {
+  const int rhs = blockIdx.y;
+  const size_t off = (size_t)rhs * rows * 12;
+  double are, aim;
+  coef(num, false, den, den2, lam, rhs, are, aim, 1);
+  const cplx<float> a = cmk((float)are, (float)aim);
+  for (size_t row = (size_t)blockIdx.x * kT + threadIdx.x; row < rows; row += (size_t)gridDim.x * kT) {
+    const size_t site = row / Ls;
+    const int s = (int)(row - site * Ls);
+    const size_t o = (off + site * 12 * Ls + (size_t)s * 12) / 4;
+    c64* f = xo + off + site * 12 * Ls + s;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const bf16c4 pq = reinterpret_cast<const bf16c4*>(p)[o + k];
+      bf16c4 xq;
+      if (x) xq = reinterpret_cast<const bf16c4*>(x)[o + k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const cplx<float> xv = x ? St<bf16c>::ld(&xq.v[e]) : cmk(0.f, 0.f);
+        bf16c t;
+        St<bf16c>::st(&t, xv + a * St<bf16c>::ld(&pq.v[e]));
+        f[(4 * k + e) * Ls] = St<bf16c>::ld(&t);
+      }
+    }
   }
 }
 
@@ -332,11 +405,21 @@ int dot_t(Red red, const T* a, const T* b, size_t n, int nrhs, double* res, hipS
 template <typename T>
 int update_t(Red red, T* x, T* r, const T* p, const T* w, size_t n, int nrhs, const double* num,
              bool cnum, const double* den, const double* den2, double lam, double* rr,
-             hipStream_t st, int dstr) {
+             hipStream_t st, int dstr, int mode) {
   if (n % Vec<T>::V) return fail(DWF_ERR_ARG, "16-bit fields need a multiple of 4 complex values");
   if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
-  hipLaunchKernelGGL((k_update<T>), dim3(nblocks(n), nrhs), dim3(kT), 0, st, x, r, p, w, n, num,
-                     cnum, den, den2, lam, red, rr, dstr);
+  if (mode < 0 || mode > (kUpdX0 | kUpdXOnly)) return fail(DWF_ERR_ARG, "update: bad mode");
+  const dim3 grid(nblocks(n), nrhs);
+#define HDCG_UPDATE(M)                                                                                      \
+  hipLaunchKernelGGL((k_update<T, M>), grid, dim3(kT), 0, st, x, r, p, w, n, num, cnum, den, den2, lam, red, \
+                     rr, dstr)
+  switch (mode) {
+    case 0: HDCG_UPDATE(0); break;
+    case kUpdX0: HDCG_UPDATE(kUpdX0); break;
+    case kUpdXOnly: HDCG_UPDATE(kUpdXOnly); break;
+    default: HDCG_UPDATE(kUpdX0 | kUpdXOnly); break;
+  }
+#undef HDCG_UPDATE
   LAUNCH_CHECK();
   return DWF_OK;
 }
@@ -370,8 +453,8 @@ int b_dot(Red red, const cplx<R>* a, const cplx<R>* b, size_t n, int nrhs, doubl
 template <typename R>
 int b_update(Red red, cplx<R>* x, cplx<R>* r, const cplx<R>* p, const cplx<R>* w, size_t n,
              int nrhs, const double* num, bool cnum, const double* den, const double* den2,
-             double lam, double* rr, hipStream_t st, int dstr) {
-  return update_t(red, x, r, p, w, n, nrhs, num, cnum, den, den2, lam, rr, st, dstr);
+             double lam, double* rr, hipStream_t st, int dstr, int mode) {
+  return update_t(red, x, r, p, w, n, nrhs, num, cnum, den, den2, lam, rr, st, dstr, mode);
 }
 template <typename R>
 int b_xpay(Red red, cplx<R>* p, const cplx<R>* y, size_t n, int nrhs, const double* num, bool cnum,
@@ -383,8 +466,24 @@ int b_norm2(Red red, const bf16c* x, size_t n, int nrhs, double* res, hipStream_
 }
 int b_update(Red red, bf16c* x, bf16c* r, const bf16c* p, const bf16c* w, size_t n, int nrhs,
              const double* num, const double* den, const double* den2, double lam, double* rr,
-             hipStream_t st) {
-  return update_t(red, x, r, p, w, n, nrhs, num, false, den, den2, lam, rr, st, 1);
+             hipStream_t st, int mode) {
+  return update_t(red, x, r, p, w, n, nrhs, num, false, den, den2, lam, rr, st, 1, mode);
+}
+int b_mirs16_init(Red red, bf16c* r, bf16c* p, const c64* b, size_t n, int nrhs, int Ls, double* rr,
+                  hipStream_t st) {
+  if (n % 12 || (n / 12) % Ls) return fail(DWF_ERR_ARG, "M_IRS: field size not a whole number of site rows");
+  if (nrhs > 64) return fail(DWF_ERR_ARG, "nrhs > 64");
+  hipLaunchKernelGGL(k_mirs16_init, dim3(nblocks(n), nrhs), dim3(kT), 0, st, r, p, b, n / 12, Ls, red, rr);
+  LAUNCH_CHECK();
+  return DWF_OK;
+}
+int b_mirs16_last(c64* x_out, const bf16c* x, const bf16c* p, size_t n, int nrhs, int Ls, const double* num,
+                  const double* den, const double* den2, double lam, hipStream_t st) {
+  if (n % 12 || (n / 12) % Ls) return fail(DWF_ERR_ARG, "M_IRS: field size not a whole number of site rows");
+  hipLaunchKernelGGL(k_mirs16_last, dim3(nblocks(n), nrhs), dim3(kT), 0, st, x_out, x, p, n / 12, Ls, num, den,
+                     den2, lam);
+  LAUNCH_CHECK();
+  return DWF_OK;
 }
 int b_xpay(Red red, bf16c* p, const bf16c* y, size_t n, int nrhs, const double* num,
            const double* den, double* pp, hipStream_t st) {
@@ -422,7 +521,7 @@ int b_zero(cplx<R>* y, size_t total, hipStream_t st) {
   template int b_dot<R>(Red, const cplx<R>*, const cplx<R>*, size_t, int, double*, hipStream_t); \
   template int b_update<R>(Red, cplx<R>*, cplx<R>*, const cplx<R>*, const cplx<R>*, size_t, int, \
                            const double*, bool, const double*, const double*, double, double*,   \
-                           hipStream_t, int);                                                     \
+                           hipStream_t, int, int);                                                \
   template int b_xpay<R>(Red, cplx<R>*, const cplx<R>*, size_t, int, const double*, bool,        \
                          const double*, double, double*, hipStream_t, int);                       \
   template int b_axpby<R>(cplx<R>*, const cplx<R>*, double, double, size_t, hipStream_t);        \

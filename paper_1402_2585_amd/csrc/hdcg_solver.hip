@@ -177,7 +177,9 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
   double* rr[2] = {slot(h, S_RR0), slot(h, S_RR1)};
   double* pap = slot(h, S_PAP);
   double* pp = slot(h, S_PP);
-  HDCG_TRY(b_zero<float>(x, n * nr, st));
+  // a fixed count writes x in its first step (x = alpha p) and skips the r,
+  // p and norm work of its last one, whose results nothing reads
+  if (fixed <= 0) HDCG_TRY(b_zero<float>(x, n * nr, st));
   HDCG_HIP(hipMemcpyAsync(r, b, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
   HDCG_HIP(hipMemcpyAsync(p, b, n * nr * sizeof(c64), hipMemcpyDeviceToDevice, st));
   HDCG_TRY(b_norm2<float>(red, r, n, nr, rr[0], st));
@@ -202,9 +204,11 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
     }
     {
       Phase ph(h, PH_LINALG, st);
+      const bool last = fixed > 0 && k == fixed - 1;
+      const int mode = (fixed > 0 && k == 0 ? kUpdX0 : 0) | (last ? kUpdXOnly : 0);
       HDCG_TRY(b_update<float>(red, x, r, p, w, n, nr, cur, false, pap, lam != 0.0 ? pp : nullptr, lam,
-                               nxt, st));
-      HDCG_TRY(b_xpay<float>(red, p, r, n, nr, nxt, false, cur, 1.0, lam != 0.0 ? pp : nullptr, st));
+                               last ? nullptr : nxt, st, 1, mode));
+      if (!last) HDCG_TRY(b_xpay<float>(red, p, r, n, nr, nxt, false, cur, 1.0, lam != 0.0 ? pp : nullptr, st));
     }
     ++k;
     if (fixed > 0) continue;
@@ -233,6 +237,7 @@ int fine_cg(hdcg* h, c64* x, const c64* b, int nr, double lam, int fixed, double
 int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixed, hipStream_t st) {
   dwf_op* op = h->op;
   const size_t n = fine_elems(h);
+  if (fixed <= 0) return b_zero<float>(x_out, n * nr, st);
   for (int i = 0; i < 4; ++i) HDCG_TRY(h->fw16[i].ensure(n * nr * sizeof(bf16c)));
   bf16c* x = h->fw16[0].as<bf16c>();
   bf16c* r = h->fw16[1].as<bf16c>();
@@ -242,13 +247,11 @@ int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixe
   double* rr[2] = {slot(h, S_RR0), slot(h, S_RR1)};
   double* pap = slot(h, S_PAP);
   double* pp = lam != 0.0 ? slot(h, S_PP) : nullptr;
-  HDCG_TRY(b_zero(x, n * nr, st));
   {
+    // r = p = b in 16 bits, |r|^2; x is first written by the first step
     Phase ph(h, PH_CONVERT, st);
-    HDCG_TRY(launch_convert16(op, r, b, nr, st));
+    HDCG_TRY(b_mirs16_init(red, r, p, b, n, nr, op->g.Ls, rr[0], st));
   }
-  HDCG_HIP(hipMemcpyAsync(p, r, n * nr * sizeof(bf16c), hipMemcpyDeviceToDevice, st));
-  HDCG_TRY(b_norm2(red, r, n, nr, rr[0], st));
   if (pp) HDCG_HIP(hipMemcpyAsync(pp, rr[0], nr * sizeof(double), hipMemcpyDeviceToDevice, st));
   for (int k = 0; k < fixed; ++k) {
     double* cur = rr[k & 1];
@@ -258,11 +261,15 @@ int fine_cg_bf16(hdcg* h, c64* x_out, const c64* b, int nr, double lam, int fixe
       HDCG_TRY((launch_mpcdagmpc<float, bf16c>(op, w, p, nr, st, pap)));
     }
     Phase ph(h, PH_LINALG, st);
-    HDCG_TRY(b_update(red, x, r, p, w, n, nr, cur, pap, pp, lam, nxt, st));
-    HDCG_TRY(b_xpay(red, p, r, n, nr, nxt, cur, pp, st));
+    if (k == fixed - 1) {
+      // the last step: x_out = x + alpha p, rounded as the stored x would be
+      HDCG_TRY(b_mirs16_last(x_out, k == 0 ? nullptr : x, p, n, nr, op->g.Ls, cur, pap, pp, lam, st));
+    } else {
+      HDCG_TRY(b_update(red, x, r, p, w, n, nr, cur, pap, pp, lam, nxt, st, k == 0 ? kUpdX0 : 0));
+      HDCG_TRY(b_xpay(red, p, r, n, nr, nxt, cur, pp, st));
+    }
   }
-  Phase ph(h, PH_CONVERT, st);
-  return launch_convert16(op, x_out, x, nr, st);
+  return DWF_OK;
 }
 
 // M_IRS in the storage precision the parameters select
