@@ -387,7 +387,10 @@ int hdcg_dims(hdcg_t h, int coarse_dims[4], int* ncoarse, int* nvec);
  * c[a][k] (promote, P), Sec. II.  Fine fields native, coarse vectors
  * canonical, both in precision prec (C128 or C64); prec DWF_BF16: the
  * subspace in 16 bits (built on first use), vectors complex64, FP32
- * arithmetic.  Asynchronous. */
+ * arithmetic (from 2 right-hand sides on the bf16 MFMA, the complex64
+ * values entering as three bf16 terms, so that every product is the FP32
+ * one; fields and subspace 16-byte aligned for that form, else the VALU
+ * kernels run).  Asynchronous. */
 int hdcg_project(hdcg_t h, void* coarse_out, const void* fine_in, int prec, int nrhs, void* stream);
 int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int nrhs, void* stream);
 
