@@ -375,12 +375,16 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // Several right-hand sides (2 <= nr <= 16; NT = 1 for nr <= 8, 2 above).
+// Complex64 (MODE 0): NT = 1, 2, 4 for nr <= 4, 8, 16, and the VALU mat-vec
+// takes 4 NT right-hand sides per pass over the operator (one pass).
 // Element slots: thread tid owns the elements e = tid and e = tid + kCT of
 // every site (e = rhs * nvec + j < nr * nvec <= 2 kCT), so each thread's
 // partial sums belong to two fixed right-hand sides.
 template <int MODE, int MT, int NT, bool K32>
 __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_cg_mrhs(PcgArgs A) {
-  constexpr int kRedBytes = MODE == 0 ? kCT * 4 * (int)sizeof(c64) : 8 * MT * NT * 64 * (int)sizeof(f32x4);
+  constexpr int NR0 = 4 * NT;                        // MODE 0: right-hand sides per pass
+  constexpr int U0 = NR0 >= 16 ? 2 : (NR0 >= 8 ? 4 : 8);  // and columns in flight
+  constexpr int kRedBytes = MODE == 0 ? kCT * NR0 * (int)sizeof(c64) : 8 * MT * NT * 64 * (int)sizeof(f32x4);
   __shared__ __align__(16) unsigned char red_raw[kRedBytes];
   __shared__ double s_tmp[2 * kCT];
   __shared__ double s_rr[kMaxR], s_bb[kMaxR], s_sum[kMaxR], s_alpha[kMaxR];
@@ -454,9 +458,9 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k
     acc0 = acc1 = 0.0;
     for (int a = wg; a < Nc; a += G) {
       if constexpr (MODE == 0) {
-        for (int r0 = 0; r0 < nr; r0 += 4)
-          capply_site<float, 4, 8, false, kStencil, true>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
-                                                          reinterpret_cast<c64*>(red_raw));
+        for (int r0 = 0; r0 < nr; r0 += NR0)
+          capply_site<float, NR0, U0, false, kStencil, true>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
+                                                             reinterpret_cast<c64*>(red_raw));
       } else {
         capply_site_mfma<MODE == 1, MT, NT, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), false, true, K32>(
             A.F, A.rho, A.smax, A.nbr, pk, A.w, a, Nc, nvec, nr, A.ksteps, reinterpret_cast<f32x4*>(red_raw));
@@ -606,7 +610,11 @@ int pcg_dispatch(int mode, int mt, bool k32, int nr, bool query, const PcgArgs* 
     return mode == 1 ? pcg_form<1, false, 1>(k32, mt, query, a, G, gmax, st)
                      : pcg_form<2, false, 1>(k32, mt, query, a, G, gmax, st);
   }
-  if (mode == 0) return pcg_call<0, 1, 1, true, false>(query, a, G, gmax, st);
+  if (mode == 0) {
+    if (nr <= 4) return pcg_call<0, 1, 1, true, false>(query, a, G, gmax, st);
+    if (nr <= 8) return pcg_call<0, 1, 2, true, false>(query, a, G, gmax, st);
+    return pcg_call<0, 1, 4, true, false>(query, a, G, gmax, st);
+  }
   if (nr <= 8)
     return mode == 1 ? pcg_form<1, true, 1>(k32, mt, query, a, G, gmax, st)
                      : pcg_form<2, true, 1>(k32, mt, query, a, G, gmax, st);

@@ -779,6 +779,13 @@ int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int n
     // setup): eight per pass over A, so A is read nr / 8 times
     hipLaunchKernelGGL((k_capply<R, 8, 2>), dim3(h->Nc, (nr + 7) / 8), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in,
                        out, h->Nc, h->nvec, nr);
+  } else if (sizeof(R) == 4 && nr > 8) {
+    // complex64, 9-16 right-hand sides: all of them per pass over A
+    hipLaunchKernelGGL((k_capply<R, 16, 2>), dim3(h->Nc, (nr + 15) / 16), dim3(kCT), 0, st, AT, h->nbr.as<int>(),
+                       in, out, h->Nc, h->nvec, nr);
+  } else if (sizeof(R) == 4 && nr > 4) {
+    hipLaunchKernelGGL((k_capply<R, 8, 4>), dim3(h->Nc, (nr + 7) / 8), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in,
+                       out, h->Nc, h->nvec, nr);
   } else {
     constexpr int NR = sizeof(R) == 8 ? 2 : 4;
     hipLaunchKernelGGL((k_capply<R, NR, 8>), dim3(h->Nc, (nr + NR - 1) / NR), dim3(kCT), 0, st, AT,
