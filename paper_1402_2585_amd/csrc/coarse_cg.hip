@@ -455,14 +455,18 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k
     c64* pn = (k & 1) ? A.p0 : A.p1;
 
     // ---- phase A: w = A p_k for all right-hand sides, partial <p_k, w>
+    // (p_k, published by coherent stores before the barrier, is gathered
+    // through the caches after an agent-scope acquire, which drops this
+    // XCD's stale lines, so that its 81-fold reuse across the sites hits L2)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     acc0 = acc1 = 0.0;
     for (int a = wg; a < Nc; a += G) {
       if constexpr (MODE == 0) {
         for (int r0 = 0; r0 < nr; r0 += NR0)
-          capply_site<float, NR0, U0, false, kStencil, true>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
-                                                             reinterpret_cast<c64*>(red_raw));
+          capply_site<float, NR0, U0, false, kStencil, false>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
+                                                              reinterpret_cast<c64*>(red_raw));
       } else {
-        capply_site_mfma<MODE == 1, MT, NT, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), false, true, K32>(
+        capply_site_mfma<MODE == 1, MT, NT, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), false, false, K32>(
             A.F, A.rho, A.smax, A.nbr, pk, A.w, a, Nc, nvec, nr, A.ksteps, reinterpret_cast<f32x4*>(red_raw));
       }
       const size_t so = (size_t)a * nvec;
