@@ -207,16 +207,24 @@ def test_coarse_solve_c64_persistent_and_stepwise(two_level, persistent):
 
 
 def test_mirs(two_level):
+    """M_IRS in complex64 against the oracle for 7 iterations (the first
+    step writes x, the last one updates only x) and for 1 (both at once)."""
     t = two_level
     banner(f"M_IRS {t['name']}")
     op, h = t["op"], t["h"]
     r = synth.gaussian_half_field(t["dims"], t["Ls"], 340)
-    want = ohdcg.m_irs(t["ref"], r, 7, 1.0)
-    out = op.new_field(hd.DWF_C64)
-    hd.hdcg_mirs(h.h, out, op.to_native(r, hd.DWF_C64))
-    err = rel_err(op.to_canonical(out, hd.DWF_C64).cpu().numpy(), want)
-    print(f"M_IRS c64 rel err {err:.2e}", flush=True)
-    assert err < 2e-5
+    try:
+        for n in (7, 1):
+            h.set_params(n_irs=n)
+            want = ohdcg.m_irs(t["ref"], r, n, 1.0)
+            out = op.new_field(hd.DWF_C64)
+            out.fill_(1.0)  # whatever x held before: the first step overwrites it
+            hd.hdcg_mirs(h.h, out, op.to_native(r, hd.DWF_C64))
+            err = rel_err(op.to_canonical(out, hd.DWF_C64).cpu().numpy(), want)
+            print(f"M_IRS c64, {n} iterations: rel err {err:.2e}", flush=True)
+            assert err < 2e-5, n
+    finally:
+        h.set_params(n_irs=7)
 
 
 def test_mirs_bf16_fields(two_level):
