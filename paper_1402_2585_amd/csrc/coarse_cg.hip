@@ -375,8 +375,10 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // Several right-hand sides (2 <= nr <= 16; NT = 1 for nr <= 8, 2 above).
-// Complex64 (MODE 0): NT = 1, 2, 4 for nr <= 4, 8, 16, and the VALU mat-vec
-// takes 4 NT right-hand sides per pass over the operator (one pass).
+// Complex64 on the FP32 MFMA (MODE 3, nvec % 4 == 0): NT and MT as for the
+// 16-bit modes.  Complex64 on the VALU (MODE 0, any other nvec): NT = 1, 2,
+// 4 for nr <= 4, 8, 16, and the mat-vec takes 4 NT right-hand sides per
+// pass over the operator (one pass).
 // Element slots: thread tid owns the elements e = tid and e = tid + kCT of
 // every site (e = rhs * nvec + j < nr * nvec <= 2 kCT), so each thread's
 // partial sums belong to two fixed right-hand sides.
@@ -465,6 +467,9 @@ __global__ void __launch_bounds__(kCT) __attribute__((amdgpu_waves_per_eu(2))) k
         for (int r0 = 0; r0 < nr; r0 += NR0)
           capply_site<float, NR0, U0, false, kStencil, false>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr, r0,
                                                               reinterpret_cast<c64*>(red_raw));
+      } else if constexpr (MODE == 3) {
+        capply_site_cmfma<float, MT, NT, 8, 2>(A.AT, A.nbr, pk, A.w, a, Nc, nvec, nr,
+                                                reinterpret_cast<f32x4*>(red_raw));
       } else {
         capply_site_mfma<MODE == 1, MT, NT, 8, (K32 ? 2 : (MT >= 3 ? 3 : 4)), false, false, K32>(
             A.F, A.rho, A.smax, A.nbr, pk, A.w, a, Nc, nvec, nr, A.ksteps, reinterpret_cast<f32x4*>(red_raw));
@@ -614,6 +619,8 @@ int pcg_dispatch(int mode, int mt, bool k32, int nr, bool query, const PcgArgs* 
     return mode == 1 ? pcg_form<1, false, 1>(k32, mt, query, a, G, gmax, st)
                      : pcg_form<2, false, 1>(k32, mt, query, a, G, gmax, st);
   }
+  if (mode == 3) return nr <= 8 ? pcg_mt<3, true, 1, false>(mt, query, a, G, gmax, st)
+                                 : pcg_mt<3, true, 2, false>(mt, query, a, G, gmax, st);
   if (mode == 0) {
     if (nr <= 4) return pcg_call<0, 1, 1, true, false>(query, a, G, gmax, st);
     if (nr <= 8) return pcg_call<0, 1, 2, true, false>(query, a, G, gmax, st);
@@ -656,7 +663,7 @@ PcgWork carve(unsigned char* base, size_t n, int G) {
 // The 16x16x32 MFMA form for the 16-bit modes when nvec allows it (8 K
 // values of one stencil point per lane); the autotuner of the standalone
 // mat-vec picks this form on every workload shape measured.
-bool use_k32(int mode, int nvec) { return mode != 0 && nvec % 8 == 0; }
+bool use_k32(int mode, int nvec) { return (mode == 1 || mode == 2) && nvec % 8 == 0; }
 
 // Shape of the launch for (mprec, nr): mode, M tiles and the grid; false
 // when the persistent form does not apply.
@@ -668,6 +675,9 @@ bool plan(hdcg* h, int mprec, int nr, int* mode, int* mt, int* G) {
   *mt = (nv + 15) / 16;
   if (m16 && nr > 8 && *mt > 3) return false;  // the 2-tile-wide reduction of 4 M tiles exceeds LDS
   *mode = !m16 ? 0 : (mprec == DWF_BF16 ? 1 : 2);
+  // complex64 with several right-hand sides: the FP32 MFMA form where its
+  // column runs and LDS reduction fit
+  if (!m16 && nr > 1 && nv % 4 == 0 && nv <= 64 && (nr <= 8 || *mt <= 3)) *mode = 3;
   int gmax = 0;
   if (pcg_dispatch(*mode, *mt, use_k32(*mode, nv), nr, true, nullptr, 0, &gmax, nullptr) < 0 || gmax < 1) return false;
   *G = std::min(std::min(h->Nc, gmax), kMaxGrid);
@@ -678,7 +688,7 @@ bool plan(hdcg* h, int mprec, int nr, int* mode, int* mt, int* G) {
 int launch_solve(hdcg* h, const PcgWork& wk, int mode, int mt, int G, int mprec, c64* x, const c64* b, int nr,
                  double tol, int maxiter, hipStream_t st, int accumulate = 0) {
   const int nv = h->nvec;
-  const bool m16 = mode != 0;
+  const bool m16 = mode == 1 || mode == 2;
   PcgArgs a;
   a.Nc = h->Nc;
   a.nvec = nv;

@@ -347,4 +347,128 @@ __device__ __forceinline__ void capply_site_mfma(const unsigned short* __restric
   __syncthreads();  // `red` may be reused by the caller
 }
 
+// ------------------------------- complex64 / complex128 on the MFMA --
+// The real GEMM of the 16-bit form (Re and Im columns per right-hand side,
+// K = (part, l, k)), on the complex operator in the VALU form's storage
+// AT[a][l][k][j] and gfx950's FP32 16x16x4 MFMA (complex64) or FP64 16x16x4
+// MFMA (complex128): no scales and no rounding of either operand,
+// accumulation in the storage precision as in the VALU form.  The complex
+// columns q = (l, k) of the site go in groups of 16: MFMA step i of a group
+// takes column q = q0 + 4 kg + i in lane group kg, where lane (m, kg)
+// supplies A[a][l][mt * 16 + m][k] (Re for part 0, Im for part 1) and lane
+// (kg, n) its right-hand side's operand value c[nbr(a,l)][k]; a lane's four
+// operand values are then one contiguous run (nvec % 4 == 0, so a run never
+// crosses a stencil point), and its A values four rows of AT.  Columns of
+// the N tiles as in capply_site_mfma (NT = 1: nrhs <= 8; NT = 2: nrhs <=
+// 16).  The FP32 form holds D[4 (lane / 16) + i][lane % 16] in its i-th
+// accumulator value, the FP64 form D[lane / 16 + 4 i][lane % 16].  `red` is
+// NW * MT * NT * 64 accumulators of LDS.  The operand is read through the
+// caches (a persistent caller acquires first).  Every thread of the
+// workgroup (NW * 64 threads) must call it.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R>
+using macc_t = std::conditional_t<sizeof(R) == 4, f32x4, f64x4>;
+
+template <typename R>
+__device__ __forceinline__ macc_t<R> mfma_4(R a, R b, macc_t<R> c) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename R, int MT, int NT, int NW, int U, int NS = kStencil>
+__device__ __forceinline__ void capply_site_cmfma(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr,
+                                                  const cplx<R>* __restrict__ in, cplx<R>* __restrict__ out, int a,
+                                                  int Nc, int nvec, int nrhs, macc_t<R>* red) {
+  using acc_t = macc_t<R>;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r16 = lane & 15, kg = lane >> 4;
+  const int K = NS * nvec;
+  const int ngroups = (K + 15) / 16;
+  acc_t acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  const cplx<R>* Aa = AT + (size_t)a * K * nvec;
+  const int* nb = nbr + (size_t)a * NS;
+  const int rr = NT == 2 ? r16 : (r16 < nrhs ? r16 : r16 - nrhs);
+  const bool cok = NT == 2 ? r16 < nrhs : r16 < 2 * nrhs;
+  const bool im1 = NT == 1 && r16 >= nrhs;
+  const size_t rbase = (size_t)(cok ? rr : 0) * Nc * nvec;
+  for (int g0 = wave * U; g0 < ngroups; g0 += NW * U) {
+    cplx<R> av[U][4][MT];
+    cplx<R> xv[U][4];
+    bool okv[U];
+    // all loads of the U groups before any MFMA (addresses clamped to valid
+    // ones; lanes past the end of K contribute zeros)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = 16 * (g0 + u) + 4 * kg;
+      const bool okq = g0 + u < ngroups && q < K;
+      const int qc = okq ? q : 0;
+      okv[u] = okq;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int m = mt * 16 + r16;
+          av[u][i][mt] = Aa[(size_t)(qc + i) * nvec + (m < nvec ? m : 0)];
+        }
+      const int l = qc / nvec, k = qc - l * nvec;
+      const cplx<R>* xp = in + rbase + (size_t)nb[l] * nvec + k;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) xv[u][i] = xp[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // Re columns: part 0 -> Re c, part 1 -> -Im c; Im columns: part 0 ->
+        // Im c, part 1 -> Re c (invalid lanes: zero operand)
+        const cplx<R> x = okv[u] && cok ? xv[u][i] : cmk((R)0, (R)0);
+        R b0[NT], b1[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bool imcol = NT == 2 ? nt == 1 : im1;
+          b0[nt] = imcol ? x.im : x.re;
+          b1[nt] = imcol ? x.re : -x.im;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const cplx<R> A = av[u][i][mt];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_4<R>(A.re, b0[nt], acc[mt][nt]);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_4<R>(A.im, b1[nt], acc[mt][nt]);
+        }
+      }
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) red[(wave * MT * NT + mt * NT + nt) * 64 + lane] = acc[mt][nt];
+  __syncthreads();
+  for (int q = threadIdx.x; q < MT * NT * 64; q += NW * 64) {
+    const int tile = q >> 6, ln = q & 63;
+    const int mt = tile / NT, nt = tile - mt * NT;
+    acc_t v = red[tile * 64 + ln];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[(w * MT * NT + tile) * 64 + ln];
+    const int n = ln & 15;
+    if (NT == 2 ? n >= nrhs : n >= 2 * nrhs) continue;
+    const bool imcol = NT == 2 ? nt == 1 : n >= nrhs;
+    const int rn = NT == 2 ? n : (imcol ? n - nrhs : n);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mt * 16 + (sizeof(R) == 4 ? 4 * (ln >> 4) + i : (ln >> 4) + 4 * i);
+      if (m >= nvec) continue;
+      R* o = reinterpret_cast<R*>(out + ((size_t)rn * Nc + a) * nvec + m);
+      o[imcol ? 1 : 0] = v[i];
+    }
+  }
+  __syncthreads();  // `red` may be reused by the caller
+}
+
 }  // namespace hdk

@@ -462,6 +462,38 @@ k_capply_staged(const c64* __restrict__ AT, const int* __restrict__ nbr, const c
   capply_site<float, 1, U, true>(AT, nbr, xin, out, a, Nc, nvec, 1, 0, red);
 }
 
+// Complex64 / complex128 with several right-hand sides on the FP32 / FP64
+// MFMA: up to 16 per launch row (blockIdx.y takes the right-hand sides
+// 16 y .. 16 y + 15).
+template <typename R, int MT, int NT, int NW, int U>
+__global__ void __launch_bounds__(NW * 64)
+k_capply_cmfma(const cplx<R>* __restrict__ AT, const int* __restrict__ nbr, const cplx<R>* __restrict__ in,
+               cplx<R>* __restrict__ out, int Nc, int nvec, int nr) {
+  __shared__ macc_t<R> red[NW * MT * NT * 64];
+  const int r0 = 16 * blockIdx.y;
+  const size_t off = (size_t)r0 * Nc * nvec;
+  capply_site_cmfma<R, MT, NT, NW, U>(AT, nbr, in + off, out + off, blockIdx.x, Nc, nvec, min(16, nr - r0), red);
+}
+
+template <typename R, int MT, int NT>
+void launch_cmfma(const cplx<R>* AT, const int* nbr, const cplx<R>* in, cplx<R>* out, int Nc, int nvec, int nr,
+                  hipStream_t st) {
+  // eight waves while their LDS reduction buffers fit 48 KiB, else four or two
+  constexpr size_t kTile = 64 * sizeof(macc_t<R>);
+  constexpr int NW = 8 * MT * NT * kTile <= 48 * 1024 ? 8 : (4 * MT * NT * kTile <= 48 * 1024 ? 4 : 2);
+  hipLaunchKernelGGL((k_capply_cmfma<R, MT, NT, NW, 2>), dim3(Nc, (nr + 15) / 16), dim3(NW * 64), 0, st, AT, nbr, in,
+                     out, Nc, nvec, nr);
+}
+
+template <typename R, int MT>
+void launch_cmfma_nt(const cplx<R>* AT, const int* nbr, const cplx<R>* in, cplx<R>* out, int Nc, int nvec, int nr,
+                     hipStream_t st) {
+  if (nr > 8)
+    launch_cmfma<R, MT, 2>(AT, nbr, in, out, Nc, nvec, nr, st);
+  else
+    launch_cmfma<R, MT, 1>(AT, nbr, in, out, Nc, nvec, nr, st);
+}
+
 }  // namespace
 
 // ================================================================= host ===
@@ -774,6 +806,16 @@ int crs_apply(hdcg* h, const cplx<R>* AT, const cplx<R>* in, cplx<R>* out, int n
     }
     hipLaunchKernelGGL((k_capply<R, 1, 16>), dim3(h->Nc, 1), dim3(kCT), 0, st, AT, h->nbr.as<int>(), in, out,
                        h->Nc, h->nvec, nr);
+  } else if (h->nvec % 4 == 0 && h->nvec <= 64) {
+    // several right-hand sides: the FP32 (complex64) or FP64 (complex128)
+    // MFMA form, all of up to 16 per pass over A
+    const int* nbr = h->nbr.as<int>();
+    switch ((h->nvec + 15) / 16) {
+      case 1: launch_cmfma_nt<R, 1>(AT, nbr, in, out, h->Nc, h->nvec, nr, st); break;
+      case 2: launch_cmfma_nt<R, 2>(AT, nbr, in, out, h->Nc, h->nvec, nr, st); break;
+      case 3: launch_cmfma_nt<R, 3>(AT, nbr, in, out, h->Nc, h->nvec, nr, st); break;
+      default: launch_cmfma_nt<R, 4>(AT, nbr, in, out, h->Nc, h->nvec, nr, st); break;
+    }
   } else if (sizeof(R) == 8 && nr > 2) {
     // complex128 with many right-hand sides (the second deflation level's
     // setup): eight per pass over A, so A is read nr / 8 times

@@ -354,8 +354,9 @@ int ldop_build(hdcg* h, int n_extra, const c128* noise, double shift, int n_step
   if (n_extra > 0) {
     c128* X = Wp + N * nv;
     HDCG_HIP(hipMemcpyAsync(X, noise, sizeof(c128) * N * n_extra, hipMemcpyDeviceToDevice, st));
-    // shifted inverse iteration, groups of up to 8 share one coarse CG
-    const int G = 8;
+    // shifted inverse iteration, groups of up to 16 share one coarse CG
+    // (its mat-vec reads A once per 16 right-hand sides)
+    const int G = 16;
     HDCG_TRY(tmp.ensure(sizeof(c128) * N * G));
     double* nrm = nullptr;
     HDCG_TRY(h->ldc.ensure(sizeof(c128) * 64 * kMaxGlobal));

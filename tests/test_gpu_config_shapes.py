@@ -185,8 +185,10 @@ def test_project_promote_many_rhs_bf16(shape):
 
 
 def test_coarse_kernels_on_seeded_operator(shape):
-    """coarse_apply (complex128, complex64, bf16 and fp16 MFMA with 1, 3 and
-    16 right-hand sides) on a seeded Hermitian positive-definite stencil
+    """coarse_apply (complex128, complex64 on the VALU for one right-hand side
+    and on the FP32 MFMA for several, bf16 and fp16 MFMA; 1, 3, 9, 16 and 17
+    right-hand sides: one and two N tiles, full and partial, and a second
+    launch row of 16) on a seeded Hermitian positive-definite stencil
     operator imported into the handle, against the oracle's mat-vec."""
     t = shape
     banner(f"coarse apply on seeded operator {t['name']}")
@@ -194,7 +196,7 @@ def test_coarse_kernels_on_seeded_operator(shape):
     A = synth.coarse_stencil_operator(t["C"], h.nvec, 440)
     hd.hdcg_import_coarse(h.h, torch.from_numpy(A).to("cuda"))
     assert rel_err(h.coarse_matrix().cpu().numpy(), A) == 0.0
-    for nr in (1, 3, 16):
+    for nr in (1, 3, 9, 16, 17):
         c = synth.gaussian_coarse(h.Nc, h.nvec, 441 + nr, nr)
         want = ocrs.apply(A, c, t["C"])
         for prec, tol in ((hd.DWF_C128, 1e-12), (hd.DWF_C64, 2e-5), (hd.DWF_BF16, 1e-2), (hd.DWF_F16, 2e-3)):
