@@ -4,6 +4,7 @@
   python3 -m paper_1402_2585_amd.prof_driver --what copy --mib 1024 --reps 5
   python3 -m paper_1402_2585_amd.prof_driver --what hdcg --workload 3 --coarse c64
   python3 -m paper_1402_2585_amd.prof_driver --what mfma --workload 4 --Ls 1 --reps 20
+  python3 -m paper_1402_2585_amd.prof_driver --what coarse_cg --workload 4 --Ls 1 --reps 10
 
 `H` applies M_pc^+ M_pc to a seeded source on the 16^4 x Ls16 workload (or
 --dims/--Ls); `copy` runs a plain device-to-device copy kernel of known size,
@@ -13,7 +14,10 @@ byte actually moved); `hdcg` sets up HDCG on a numbered synthetic workload
 solve to a 1e-8 FP64 true residual, printing the solver statistics;
 `lanczos` estimates the extreme eigenvalues of H on a numbered workload (the
 conditioning that sets the plain-CG iteration count) from --steps Lanczos
-steps with full reorthogonalisation, H applied by the library in FP64.
+steps with full reorthogonalisation, H applied by the library in FP64;
+`coarse_cg` times the coarse mat-vec in every storage and the persistent
+coarse CG per iteration for 1-16 right-hand sides on a seeded Hermitian,
+diagonally dominant stencil operator with the workload's coarse shape.
 """
 from __future__ import annotations
 
@@ -27,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos", "coarse", "mfma"], default="H")
+    ap.add_argument("--what", choices=["H", "copy", "hdcg", "lanczos", "coarse", "mfma", "coarse_cg"], default="H")
     ap.add_argument("--steps", type=int, default=80)
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--coarse", choices=["c64", "bf16", "f16"], default="c64")
@@ -85,6 +89,9 @@ def main():
         return
     if a.what == "mfma":
         run_mfma(a, torch, synth)
+        return
+    if a.what == "coarse_cg":
+        run_coarse_cg(a, torch, synth)
         return
 
     dims = tuple(a.dims)
@@ -321,6 +328,81 @@ def run_mfma(a, torch, synth):
             flops = 8 * h.Nc * 81 * h.nvec * h.nvec * nr
             print(f"{pname} nrhs {nr}: tile {tile} {dt * 1e3:.4f} ms, {(mbytes + vb) / dt / 1e9:.1f} GB/s, "
                   f"{flops / dt / 1e12:.2f} TFLOP/s; candidates ms {[round(m, 4) for m in ms]}", flush=True)
+    h.close()
+    op.close()
+
+
+def run_coarse_cg(a, torch, synth):
+    """The coarse mat-vec and the persistent coarse CG on the coarse grid of a
+    numbered workload (the fine lattice with Ls = --Ls, which does not change
+    the coarse shape), on a seeded Hermitian, diagonally dominant stencil
+    operator built on the device and imported into the handle: the
+    standalone mat-vec for complex128, complex64 and bf16 storage and 1, 8
+    and 16 right-hand sides (--reps each), and the persistent CG's time per
+    iteration for complex64 and bf16 and 1, 2, 8 and 16 right-hand sides, as
+    the difference of fixed-count solves of 12 and 4 iterations over 8
+    (tolerance 1e-30, so every right-hand side runs to the cap)."""
+    import time
+
+    from synth.configs import WORKLOADS
+
+    import paper_1402_2585_amd as hd
+
+    w = WORKLOADS[a.workload]
+    U = torch.from_numpy(synth.gauge_field(w.dims, w.eps, w.gauge_seed)).to("cuda")
+    op = hd.FineOperator(U, w.dims, a.Ls, w.M5, w.mass)
+    h = hd.HDCG(op, w.block, None, nvec=w.nvec, seed=w.subspace_seed(0), n_ii=0)
+    # A[a][l] = B_l(a) for the 40 stencil points before the site, A[a + d_l][80 - l]
+    # = B_l(a)^+ (Hermitian), 8 on the site's diagonal: diagonally dominant
+    C = [w.dims[i] // w.block[i] for i in range(4)]
+    nc, nv = h.Nc, h.nvec
+    g = torch.Generator(device="cuda").manual_seed(460)
+    ai = torch.arange(nc, device="cuda")
+    co = torch.stack([ai % C[0], (ai // C[0]) % C[1], (ai // (C[0] * C[1])) % C[2], ai // (C[0] * C[1] * C[2])], 1)
+    A = torch.zeros((nc, 81, nv, nv), dtype=torch.complex128, device="cuda")
+    for l in range(40):
+        off = torch.tensor([(l // 3 ** mu) % 3 - 1 for mu in range(4)], device="cuda")
+        c2 = (co + off) % torch.tensor(C, device="cuda")
+        nb = c2[:, 0] + C[0] * (c2[:, 1] + C[1] * (c2[:, 2] + C[2] * c2[:, 3]))
+        B = 1e-3 * torch.randn((nc, nv, nv), dtype=torch.complex128, device="cuda", generator=g)
+        A[:, l] = B
+        A[nb, 80 - l] = B.conj().transpose(1, 2)
+    A[:, 40] = 8.0 * torch.eye(nv, dtype=torch.complex128, device="cuda")
+    hd.hdcg_import_coarse(h.h, A)
+    del A
+    abytes = {hd.DWF_C128: 16, hd.DWF_C64: 8, hd.DWF_BF16: 4}
+    names = {hd.DWF_C128: "complex128", hd.DWF_C64: "complex64", hd.DWF_BF16: "bf16"}
+    print(f"coarse grid Nc {h.Nc} nvec {h.nvec}", flush=True)
+    for prec in (hd.DWF_C128, hd.DWF_C64, hd.DWF_BF16):
+        vt = torch.complex128 if prec == hd.DWF_C128 else torch.complex64
+        for nr in (1, 8, 16):
+            x = torch.randn((nr, h.Nc, h.nvec), dtype=vt, device="cuda", generator=g)
+            y = torch.empty_like(x)
+            hd.coarse_apply(h.h, y, x, prec, nr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.reps):
+                hd.coarse_apply(h.h, y, x, prec, nr)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / a.reps
+            mb = h.Nc * 81 * h.nvec * h.nvec * abytes[prec]
+            print(f"mat-vec {names[prec]} nrhs {nr}: {dt * 1e3:.3f} ms, matrix {mb / dt / 1e9:.0f} GB/s", flush=True)
+    for prec in (hd.DWF_C64, hd.DWF_BF16):
+        h.set_params(coarse_prec=prec)
+        for nr in (1, 2, 8, 16):
+            b = torch.randn((nr, h.Nc, h.nvec), dtype=torch.complex64, device="cuda", generator=g)
+            x = torch.zeros_like(b)
+            hd.hdcg_coarse_solve(h.h, x, b, prec, nr, 1e-30, 4)
+            ts = {}
+            for mi in (4, 12):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, it = hd.hdcg_coarse_solve(h.h, x, b, prec, nr, 1e-30, mi)
+                torch.cuda.synchronize()
+                ts[mi] = time.perf_counter() - t0
+                assert it == mi, (rc, it, mi)
+            print(f"persistent coarse CG {names[prec]} nrhs {nr}: {(ts[12] - ts[4]) / 8 * 1e3:.3f} ms per iteration",
+                  flush=True)
     h.close()
     op.close()
 
