@@ -259,7 +259,8 @@ struct hdcg_params {
   int build_batch;    /* probe vectors per H application batch in the coarse build
                          (default 16, at most 16; two complex128 fields per probe
                          vector are held during the build) */
-  int coarse_prec;    /* storage of A inside Q: DWF_C64 (VALU, default), DWF_BF16 or DWF_F16
+  int coarse_prec;    /* storage of A inside Q: DWF_C64 (default; VALU for one right-hand
+                         side, FP32 MFMA for several when nvec % 4 == 0), DWF_BF16 or DWF_F16
                          (MFMA with FP32 accumulation, per-matrix scales; nvec % 4 == 0) */
   int verbose;        /* 1: hdcg_setup prints stage progress to stderr */
   int irs_prec;       /* storage of the M_IRS fields: DWF_C64 (default) or DWF_BF16 (16-bit
@@ -396,7 +397,9 @@ int hdcg_promote(hdcg_t h, void* fine_out, const void* coarse_in, int prec, int 
 
 /* out[rhs][a][j] = sum_l sum_k A[a][l][j][k] in[rhs][a + delta_l][k]:
  * the 81-point block stencil of the little Dirac operator (Sec. V.A);
- * prec C128 or C64 (VALU, vectors in that precision), or BF16 / F16: the
+ * prec C128 or C64 (vectors in that precision; one right-hand side on the
+ * VALU, several, when nvec % 4 == 0, on the FP64 / FP32 16x16x4 MFMA with
+ * neither operand rounded, up to 16 per pass over A), or BF16 / F16: the
  * matrix stored in 16 bits with one scale per stencil matrix A[a][l], the
  * complex64 vectors rounded to 16 bits, products accumulated in FP32 on MFMA
  * (vectors in/out complex64).  Asynchronous; out != in. */
