@@ -3,7 +3,8 @@
 //
 // (A c)[r][a][j] = sum_l sum_k A[a][l][j][k] c[r][nbr(a,l)][k]   (Sec. V.A)
 //
-// Both forms take one coarse site a per 512-thread workgroup (8 waves).
+// Every form takes one coarse site a per workgroup: 512 threads for the VALU
+// form, NW waves for the MFMA forms.
 #pragma once
 
 #include <type_traits>
